@@ -1,0 +1,957 @@
+/*
+ * dbs_oracle.c -- plain FP64 CPU oracle of one PISO step of the two-phase
+ * micro-continuum Darcy-Brinkman-Stokes (DBS) method of Carrillo, Bourg and
+ * Soulaine (arXiv:2003.08374).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only tests, the smoke check and the benchmark's
+ * CPU-baseline leg may load this library.  It shares no code with the HIP
+ * product library and is written as a face-list finite-volume code: every
+ * face is visited once, its flux is added to the owner and subtracted from
+ * the neighbour.  Single thread, scalar loops, built with -O2
+ * -ffp-contract=off.
+ *
+ * What it computes, in the order of the paper's solution algorithm (Sec. 3.2):
+ *   1. explicit saturation transport, Eq. (phaseEq) as restated in
+ *      Eq. (two-phase-microcontinuum): Van Leer high-order convection and a
+ *      flux-corrected-transport (Zalesak) limiter (Sec. 3.1, 3.2).  The
+ *      relative flux phi*alpha_l*alpha_g*v_r uses the closures summarised in
+ *      Sec. 2.3: interface compression in clear regions and Eq. (vr_porous)
+ *      in porous regions;
+ *   2. property update from the new saturation: App. A relative permeability
+ *      and capillary pressure, mu = alpha mu_l + (1-alpha) mu_g (Eq. Fc context),
+ *      rho = alpha rho_l + (1-alpha) rho_g and the porous capillary force of
+ *      App. B;
+ *   3. momentum predictor, Eq. (semi_discretised_bis), with the Darcy drag
+ *      coefficient mu k^-1 = k0^-1 (k_rl/mu_l + k_rg/mu_g)^-1 (Sec. 2.3 summary);
+ *   4. n_corr pressure correctors, Eqs. (corrected_velocity) and
+ *      (pressure_predictor), solved in the p_rgh = p - rho g.x form.
+ *
+ * Readings taken where the paper is silent, garbled or inconsistent:
+ *   R1  compression velocity sign: +grad(alpha)/|grad(alpha)| (Sec. 2.3 summary),
+ *       face-local |v| = |F_f|/A_f, upwinded alpha*(1-alpha) product;
+ *   R2  drag coefficient in the k_rl/mu_l + k_rg/mu_g form (Sec. 2.3 summary);
+ *       the form printed beside Eq. (single-field-kr) is read as a typo;
+ *   R3  one density rho = alpha rho_l + (1-alpha) rho_g everywhere and the
+ *       porous capillary force of App. B:
+ *       F_c = (f_l - alpha)[(rho_l - rho_g) g + grad p_c] - p_c grad alpha,
+ *       f_l = M_l/(M_l + M_g); F_c = 0 in clear cells (sigma = 0);
+ *   R4  the 1/phi factors of the momentum PDE are kept on the time and
+ *       convection terms (convective flux divided by the face porosity);
+ *   R5  irreducible saturations 0, alpha_pc,max = 1 unless given; the
+ *       normalised p_c saturation is clamped to [eps_pc, 1] (Brooks-Corey) or
+ *       [eps_pc, 1 - eps_pc] (Van Genuchten) and dp_c/dalpha = 0 where clamped;
+ *   R6  a cell is porous iff k0^-1 > 0; a face is porous iff either side is;
+ *       face permeability is the harmonic mean 2/(k^-1_P + k^-1_N);
+ *       p_c = 0 and f_l - alpha = 0 in clear cells;
+ *   R7  porous relative flux phi a a_g v_r with the 1/alpha factors multiplied
+ *       out: G_f = a_g,f u_l - a_f u_g, u_l = -M_l,f (dn p_l - rho_l g_n) A_f,
+ *       u_g = -M_g,f (dn p_g - rho_g g_n) A_f, p_l = p - a_g p_c, p_g = p + a p_c,
+ *       which expands to the bracket of Eq. (vr_porous); a_f arithmetic face
+ *       mean; M_i,f = k0_f k_ri/mu_i of the cell upstream of phase i's
+ *       potential (phase-potential upwinding); p = p_rgh + rho g.x of the
+ *       previous step;
+ *   R8  MULES limiter: Zalesak bounds from the face neighbours and inflow
+ *       boundary values clipped to [0, 1], then mules_iter limiter iterations
+ *       in which a cell's room to rise (fall) is its bound margin plus the
+ *       limited antidiffusive flux leaving (entering) it; face factors never
+ *       grow between iterations;
+ *   R9  Van Leer ratio r = (a_U - a_UU)/(a_D - a_U); beyond a boundary a_UU = a_U;
+ *   R10 momentum convection upwind; viscous term implicit mu_f grad(U) plus an
+ *       explicit div(mu grad(U)^T) from U^n (switchable);
+ *   R11 momentum predictor solved with a fixed number of Jacobi sweeps;
+ *   R12 no Rhie-Chow / ddt flux correction; Cartesian reconstruct
+ *       R(q)_x = (q_west + q_east)/(2 A_x); no body force on boundary faces;
+ *       fixed-flux faces carry the p_rgh gradient that reproduces their
+ *       prescribed flux in the correctors, and the opposite face's force
+ *       density in the predictor;
+ *   R13 boundary conditions: inlet = fixed U, alpha and flux (zero normal
+ *       gradient of p_rgh); outlet = fixed static p (p_rgh_b = p_b - rho_P g.x_b),
+ *       zero-gradient U, alpha zero-gradient on outflow and the given value on
+ *       backflow; wall = no-slip, zero flux, zero-gradient alpha; empty = 2D;
+ *   R14 closed domains: zero-mean p_rgh;
+ *   R15 the pressure solve ends at ||b - A x||_2 <= tol ||b||_2.
+ */
+#include "dbs_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------ mesh */
+
+typedef struct {
+  int axis;
+  int own, nbr;      /* cell on the minus / plus side, -1 outside the domain */
+  int own2, nbr2;    /* cell beyond own (minus side) / beyond nbr (plus side) */
+  int bnd;           /* domain face 0..5, -1 for interior faces */
+  int kind;          /* boundary kind, -1 for interior faces */
+  double area, dist; /* area; centre-to-centre or centre-to-face distance */
+  double xf[3];      /* face centre */
+} face_t;
+
+typedef struct {
+  const dbso_case *cs;
+  int n[3], nc, nf, nfa[3];
+  double h[3], V;
+  face_t *f;
+  int *cf; /* six face ids per cell: x-, x+, y-, y+, z-, z+ */
+} mesh_t;
+
+static double clampd(double x, double lo, double hi) {
+  return x < lo ? lo : (x > hi ? hi : x);
+}
+static double maxd(double a, double b) { return a > b ? a : b; }
+static double mind(double a, double b) { return a < b ? a : b; }
+
+static int cell_id(const mesh_t *m, int i, int j, int k) {
+  return i + m->n[0] * (j + m->n[1] * k);
+}
+
+static void cell_centre(const mesh_t *m, int c, double x[3]) {
+  int i = c % m->n[0];
+  int j = (c / m->n[0]) % m->n[1];
+  int k = c / (m->n[0] * m->n[1]);
+  x[0] = (i + 0.5) * m->h[0];
+  x[1] = (j + 0.5) * m->h[1];
+  x[2] = (k + 0.5) * m->h[2];
+}
+
+static int validate_case(const dbso_case *cs) {
+  int n[3] = {cs->nx, cs->ny, cs->nz};
+  double h[3] = {cs->hx, cs->hy, cs->hz};
+  for (int a = 0; a < 3; a++) {
+    if (n[a] < 1 || !(h[a] > 0.0)) return -1;
+    int e0 = cs->bc_kind[2 * a] == DBSO_EMPTY, e1 = cs->bc_kind[2 * a + 1] == DBSO_EMPTY;
+    if (e0 != e1) return -1;
+    if (e0 && n[a] != 1) return -1;
+  }
+  for (int b = 0; b < 6; b++)
+    if (cs->bc_kind[b] < DBSO_WALL || cs->bc_kind[b] > DBSO_EMPTY) return -1;
+  if (!(cs->dt > 0.0) || cs->n_corr < 1 || cs->n_corr > 16 || cs->mom_sweeps < 0)
+    return -1;
+  return 0;
+}
+
+static int build_mesh(const dbso_case *cs, mesh_t *m) {
+  memset(m, 0, sizeof(*m));
+  if (validate_case(cs)) return -1;
+  m->cs = cs;
+  m->n[0] = cs->nx; m->n[1] = cs->ny; m->n[2] = cs->nz;
+  m->h[0] = cs->hx; m->h[1] = cs->hy; m->h[2] = cs->hz;
+  m->V = cs->hx * cs->hy * cs->hz;
+  m->nc = cs->nx * cs->ny * cs->nz;
+  m->nfa[0] = (cs->nx + 1) * cs->ny * cs->nz;
+  m->nfa[1] = cs->nx * (cs->ny + 1) * cs->nz;
+  m->nfa[2] = cs->nx * cs->ny * (cs->nz + 1);
+  m->nf = m->nfa[0] + m->nfa[1] + m->nfa[2];
+  m->f = (face_t *)calloc((size_t)m->nf, sizeof(face_t));
+  m->cf = (int *)calloc((size_t)m->nc * 6, sizeof(int));
+  if (!m->f || !m->cf) return -2;
+  int stride[3] = {1, m->n[0], m->n[0] * m->n[1]};
+  int id = 0;
+  for (int a = 0; a < 3; a++) {
+    int fn[3] = {m->n[0], m->n[1], m->n[2]};
+    fn[a] += 1;
+    for (int k = 0; k < fn[2]; k++)
+      for (int j = 0; j < fn[1]; j++)
+        for (int i = 0; i < fn[0]; i++) {
+          int idx[3] = {i, j, k};
+          int s = idx[a];
+          face_t *F = &m->f[id];
+          F->axis = a;
+          int lo[3] = {i, j, k};
+          lo[a] = s - 1;
+          F->own = s - 1 >= 0 ? cell_id(m, lo[0], lo[1], lo[2]) : -1;
+          F->nbr = s < m->n[a] ? cell_id(m, i, j, k) : -1;
+          F->own2 = s - 2 >= 0 ? F->own - stride[a] : -1;
+          F->nbr2 = s + 1 < m->n[a] ? F->nbr + stride[a] : -1;
+          F->bnd = s == 0 ? 2 * a : (s == m->n[a] ? 2 * a + 1 : -1);
+          F->kind = F->bnd >= 0 ? cs->bc_kind[F->bnd] : -1;
+          F->area = m->V / m->h[a];
+          F->dist = F->bnd >= 0 ? 0.5 * m->h[a] : m->h[a];
+          for (int b = 0; b < 3; b++)
+            F->xf[b] = b == a ? s * m->h[a] : (idx[b] + 0.5) * m->h[b];
+          if (F->own >= 0) m->cf[F->own * 6 + 2 * a + 1] = id;
+          if (F->nbr >= 0) m->cf[F->nbr * 6 + 2 * a] = id;
+          id++;
+        }
+  }
+  return 0;
+}
+
+static void free_mesh(mesh_t *m) {
+  free(m->f);
+  free(m->cf);
+}
+
+/* inside cell and outward sign of a boundary face */
+static int bnd_cell(const face_t *F, double *so) {
+  if (F->bnd & 1) { *so = 1.0; return F->own; }
+  *so = -1.0;
+  return F->nbr;
+}
+
+/* ------------------------------------------------------------- closures */
+
+/* App. A: relative permeability (A.1) and capillary pressure (A.2). */
+void dbso_closures(const dbso_case *cs, double alpha, double *krl, double *krg,
+                   double *pc, double *dpc) {
+  double ae = clampd((alpha - cs->s_lirr) / (1.0 - cs->s_girr - cs->s_lirr), 0.0, 1.0);
+  double m = cs->kr_m;
+  if (cs->kr_model == DBSO_BROOKS_COREY) {
+    *krl = pow(ae, m);
+    *krg = pow(1.0 - ae, m);
+  } else {
+    double t = pow(ae, 1.0 / m);
+    double u = 1.0 - pow(1.0 - t, m);
+    *krl = sqrt(ae) * u * u;
+    *krg = sqrt(1.0 - ae) * pow(1.0 - t, 2.0 * m);
+  }
+  double span = cs->a_pcmax - cs->a_pcirr;
+  double s = (alpha - cs->a_pcirr) / span;
+  double eps = cs->eps_pc;
+  double top = cs->pc_model == DBSO_BROOKS_COREY ? 1.0 : 1.0 - eps;
+  int clamped = s < eps || s > top;
+  s = clampd(s, eps, top);
+  if (cs->pc_model == DBSO_BROOKS_COREY) {
+    double beta = cs->pc_exp;
+    *pc = cs->pc0 * pow(s, -beta);
+    *dpc = clamped ? 0.0 : -beta * cs->pc0 * pow(s, -beta - 1.0) / span;
+  } else {
+    double mv = cs->pc_exp;
+    double t = pow(s, -1.0 / mv) - 1.0;
+    *pc = cs->pc0 * pow(t, 1.0 - mv);
+    *dpc = clamped ? 0.0
+                   : cs->pc0 * (1.0 - mv) * pow(t, -mv) * (-1.0 / mv) *
+                         pow(s, -1.0 / mv - 1.0) / span;
+  }
+}
+
+typedef struct {
+  double ml, mg; /* k_ri / mu_i */
+  double pc;     /* capillary pressure, 0 in clear cells (R6) */
+  double cf;     /* f_l - alpha in porous cells, 0 in clear cells (R3) */
+  double K;      /* Darcy drag coefficient mu k^-1 (R2) */
+  double rho, mu;
+} props_t;
+
+static void cell_props(const dbso_case *cs, double a, double kinv, props_t *p) {
+  double krl, krg, pc, dpc;
+  dbso_closures(cs, a, &krl, &krg, &pc, &dpc);
+  p->ml = krl / cs->mu_l;
+  p->mg = krg / cs->mu_g;
+  double mt = p->ml + p->mg;
+  int porous = kinv > 0.0;
+  p->pc = porous ? pc : 0.0;
+  p->cf = porous ? p->ml / mt - a : 0.0;
+  p->K = porous ? kinv / mt : 0.0;
+  p->rho = a * cs->rho_l + (1.0 - a) * cs->rho_g;
+  p->mu = a * cs->mu_l + (1.0 - a) * cs->mu_g;
+}
+
+/* alpha on a boundary face (R13) given the face flux along +axis */
+static double bnd_alpha(const dbso_case *cs, const face_t *F, const double *alpha,
+                        double flux) {
+  double so;
+  int c = bnd_cell(F, &so);
+  if (F->kind == DBSO_INLET) return cs->bc_alpha[F->bnd];
+  if (F->kind == DBSO_OUTLET && so * flux < 0.0) return cs->bc_alpha[F->bnd];
+  return alpha[c];
+}
+
+/* ---------------------------------------------------- 1. alpha transport */
+
+static void alpha_stage(const mesh_t *m, const double *phi, const double *kinv,
+                        const double *alpha, const double *F, const double *prgh,
+                        double *alpha_new, double *alphaPhi, double *rhoPhi,
+                        dbso_trace *tr) {
+  const dbso_case *cs = m->cs;
+  int nc = m->nc, nf = m->nf;
+  double V = m->V, dt = cs->dt;
+  props_t *pr = (props_t *)malloc(sizeof(props_t) * nc);
+  double *p = (double *)malloc(sizeof(double) * nc);
+  double *grad = (double *)calloc((size_t)nc * 3, sizeof(double));
+  double *FL = (double *)calloc((size_t)nf, sizeof(double));
+  double *A = (double *)calloc((size_t)nf, sizeof(double));
+  double *Rp = (double *)malloc(sizeof(double) * nc);
+  double *Rm = (double *)malloc(sizeof(double) * nc);
+
+  for (int c = 0; c < nc; c++) {
+    double x[3];
+    cell_props(cs, alpha[c], kinv[c], &pr[c]);
+    cell_centre(m, c, x);
+    p[c] = prgh[c] + pr[c].rho * (cs->g[0] * x[0] + cs->g[1] * x[1] + cs->g[2] * x[2]);
+  }
+  /* Gauss cell gradient of alpha (face values: mean inside, boundary value) */
+  for (int f = 0; f < nf; f++) {
+    const face_t *Fc = &m->f[f];
+    if (Fc->kind == DBSO_EMPTY) continue;
+    double af = Fc->bnd < 0 ? 0.5 * (alpha[Fc->own] + alpha[Fc->nbr])
+                            : bnd_alpha(cs, Fc, alpha, F[f]);
+    if (Fc->own >= 0) grad[Fc->own * 3 + Fc->axis] += af * Fc->area / V;
+    if (Fc->nbr >= 0) grad[Fc->nbr * 3 + Fc->axis] -= af * Fc->area / V;
+  }
+  double dN = 1e-8 / cbrt(V);
+
+  /* face fluxes: low order, high order, relative flux, antidiffusive part */
+  for (int f = 0; f < nf; f++) {
+    const face_t *Fc = &m->f[f];
+    if (Fc->kind == DBSO_EMPTY) continue;
+    double Ff = F[f];
+    if (Fc->bnd >= 0) {
+      FL[f] = Ff * bnd_alpha(cs, Fc, alpha, Ff);
+      A[f] = 0.0;
+      continue;
+    }
+    int o = Fc->own, n = Fc->nbr;
+    int up = Ff >= 0.0 ? o : n, dn = Ff >= 0.0 ? n : o;
+    int uu = Ff >= 0.0 ? Fc->own2 : Fc->nbr2;
+    double aU = alpha[up], aD = alpha[dn], aUU = uu >= 0 ? alpha[uu] : aU;
+    FL[f] = Ff * aU;
+    double avl = aU;
+    if (aD != aU) {
+      double r = (aU - aUU) / (aD - aU);
+      double psi = (r + fabs(r)) / (1.0 + fabs(r));
+      avl = aU + 0.5 * psi * (aD - aU);
+    }
+    double G;
+    if (kinv[o] == 0.0 && kinv[n] == 0.0) {
+      /* clear face: interface compression (R1) */
+      double gf[3], mag = 0.0;
+      for (int b = 0; b < 3; b++) {
+        gf[b] = 0.5 * (grad[o * 3 + b] + grad[n * 3 + b]);
+        mag += gf[b] * gf[b];
+      }
+      mag = sqrt(mag);
+      double nfa = gf[Fc->axis] / (mag + dN);
+      double Fr = cs->c_alpha * fabs(Ff) * nfa;
+      G = Fr >= 0.0 ? Fr * alpha[o] * (1.0 - alpha[n]) : Fr * alpha[n] * (1.0 - alpha[o]);
+    } else {
+      /* porous face: Eq. (vr_porous) times phi alpha_l alpha_g (R7), written
+         as alpha_g u_l - alpha u_g with the two phase Darcy fluxes of the
+         pressure-gradient relations of Sec. 2.3; each phase's mobility is
+         taken from the upstream cell of that phase's potential */
+      double k0f = 2.0 / (kinv[o] + kinv[n]);
+      double af = 0.5 * (alpha[o] + alpha[n]), agf = 1.0 - af;
+      double d = Fc->dist;
+      double ge = cs->g[Fc->axis];
+      double dp = (p[n] - p[o]) / d;
+      double dpl = dp - ((1.0 - alpha[n]) * pr[n].pc - (1.0 - alpha[o]) * pr[o].pc) / d -
+                   cs->rho_l * ge;
+      double dpg = dp + (alpha[n] * pr[n].pc - alpha[o] * pr[o].pc) / d - cs->rho_g * ge;
+      double ml = dpl < 0.0 ? pr[o].ml : pr[n].ml;
+      double mg = dpg < 0.0 ? pr[o].mg : pr[n].mg;
+      double ul = -k0f * ml * dpl * Fc->area;
+      double ug = -k0f * mg * dpg * Fc->area;
+      G = agf * ul - af * ug;
+    }
+    A[f] = Ff * avl + G - FL[f];
+  }
+
+  /* MULES limiter (R8): Zalesak bounds, then limiter iterations in which the
+     room left in a cell counts the already-limited counter-fluxes */
+  double *Qp = (double *)malloc(sizeof(double) * nc), *Qm = (double *)malloc(sizeof(double) * nc);
+  double *Pin = (double *)malloc(sizeof(double) * nc), *Pout = (double *)malloc(sizeof(double) * nc);
+  double *lam = (double *)malloc(sizeof(double) * nf);
+  for (int c = 0; c < nc; c++) {
+    double vol = phi[c] * V / dt;
+    double outL = 0.0, amax = alpha[c], amin = alpha[c], pin = 0.0, pout = 0.0;
+    for (int s = 0; s < 6; s++) {
+      int f = m->cf[c * 6 + s];
+      const face_t *Fc = &m->f[f];
+      if (Fc->kind == DBSO_EMPTY) continue;
+      double so = (s & 1) ? 1.0 : -1.0;
+      outL += so * FL[f];
+      if (Fc->bnd < 0) {
+        int nb = (s & 1) ? Fc->nbr : Fc->own;
+        amax = maxd(amax, alpha[nb]);
+        amin = mind(amin, alpha[nb]);
+      } else if (so * F[f] < 0.0) {
+        double ab = bnd_alpha(cs, Fc, alpha, F[f]);
+        amax = maxd(amax, ab);
+        amin = mind(amin, ab);
+      }
+      pin += maxd(0.0, -so * A[f]);
+      pout += maxd(0.0, so * A[f]);
+    }
+    amax = mind(1.0, amax);
+    amin = maxd(0.0, amin);
+    double aL = alpha[c] - outL / vol;
+    Qp[c] = vol * maxd(0.0, amax - aL);
+    Qm[c] = vol * maxd(0.0, aL - amin);
+    Pin[c] = pin;
+    Pout[c] = pout;
+  }
+  for (int f = 0; f < nf; f++) lam[f] = m->f[f].bnd < 0 ? 1.0 : 0.0;
+  for (int it = 0; it < cs->mules_iter; it++) {
+    for (int c = 0; c < nc; c++) {
+      double lout = 0.0, lin = 0.0;
+      for (int s = 0; s < 6; s++) {
+        int f = m->cf[c * 6 + s];
+        if (m->f[f].kind == DBSO_EMPTY) continue;
+        double so = (s & 1) ? 1.0 : -1.0;
+        lout += lam[f] * maxd(0.0, so * A[f]);
+        lin += lam[f] * maxd(0.0, -so * A[f]);
+      }
+      Rp[c] = Pin[c] > 0.0 ? clampd((Qp[c] + lout) / Pin[c], 0.0, 1.0) : 1.0;
+      Rm[c] = Pout[c] > 0.0 ? clampd((Qm[c] + lin) / Pout[c], 0.0, 1.0) : 1.0;
+    }
+    for (int f = 0; f < nf; f++) {
+      const face_t *Fc = &m->f[f];
+      if (Fc->bnd >= 0) continue;
+      double l = A[f] >= 0.0 ? mind(Rm[Fc->own], Rp[Fc->nbr]) : mind(Rp[Fc->own], Rm[Fc->nbr]);
+      lam[f] = mind(lam[f], l);
+    }
+  }
+  for (int f = 0; f < nf; f++) {
+    const face_t *Fc = &m->f[f];
+    if (Fc->kind == DBSO_EMPTY) { alphaPhi[f] = 0.0; rhoPhi[f] = 0.0; continue; }
+    alphaPhi[f] = FL[f] + lam[f] * A[f];
+    rhoPhi[f] = (cs->rho_l - cs->rho_g) * alphaPhi[f] + cs->rho_g * F[f];
+  }
+  free(Qp); free(Qm); free(Pin); free(Pout); free(lam);
+  /* forward Euler on d(phi alpha)/dt with static phi */
+  for (int c = 0; c < nc; c++) {
+    double out = 0.0;
+    for (int s = 0; s < 6; s++) {
+      int f = m->cf[c * 6 + s];
+      if (m->f[f].kind == DBSO_EMPTY) continue;
+      out += ((s & 1) ? 1.0 : -1.0) * alphaPhi[f];
+    }
+    alpha_new[c] = alpha[c] - dt * out / (phi[c] * V);
+  }
+  if (tr) {
+    if (tr->A) memcpy(tr->A, A, sizeof(double) * nf);
+    if (tr->Rp) memcpy(tr->Rp, Rp, sizeof(double) * nc);
+    if (tr->Rm) memcpy(tr->Rm, Rm, sizeof(double) * nc);
+    if (tr->alphaPhi) memcpy(tr->alphaPhi, alphaPhi, sizeof(double) * nf);
+    if (tr->alpha_new) memcpy(tr->alpha_new, alpha_new, sizeof(double) * nc);
+  }
+  free(pr); free(p); free(grad); free(FL); free(A); free(Rp); free(Rm);
+}
+
+/* ------------------------------------------------------- 3.-4. momentum */
+
+typedef struct {
+  double *aP;        /* diagonal per unit volume */
+  double *aON, *aNO; /* per face: owner-row coefficient of U_nbr, nbr-row of U_own */
+  double *Sh;        /* explicit source, 3 x nc (component-major) */
+} momeq_t;
+
+static double dot3(const double *a, const double *b) {
+  return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+}
+
+/* face force q_f = [F_c - (g.x_f) dn(rho) - dn(p_rgh)] A_f along +axis on
+   interior and outlet faces (R3, R12).  Fixed-flux faces (walls, inlets) are
+   filled by fixed_flux_forces. */
+static double face_body_force(const mesh_t *m, const props_t *pr, const double *alpha, int f);
+
+static void face_forces(const mesh_t *m, const props_t *pr, const double *alpha,
+                        const double *prgh, double *q) {
+  const dbso_case *cs = m->cs;
+  for (int f = 0; f < m->nf; f++) {
+    const face_t *Fc = &m->f[f];
+    q[f] = 0.0;
+    if (Fc->kind == DBSO_EMPTY) continue;
+    if (Fc->bnd >= 0) {
+      if (Fc->kind != DBSO_OUTLET) continue;
+      double so;
+      int c = bnd_cell(Fc, &so);
+      double pb = cs->bc_p[Fc->bnd] - pr[c].rho * dot3(cs->g, Fc->xf);
+      double sn = so > 0.0 ? (pb - prgh[c]) / Fc->dist : (prgh[c] - pb) / Fc->dist;
+      q[f] = -sn * Fc->area;
+      continue;
+    }
+    q[f] = (face_body_force(m, pr, alpha, f) - (prgh[Fc->nbr] - prgh[Fc->own]) / Fc->dist) *
+           Fc->area;
+  }
+}
+
+/* Fixed-flux faces (R12): in a corrector (HbyA != NULL) the boundary normal
+   gradient of p_rgh is the one that makes the corrected flux equal the
+   prescribed flux, so q_b = (F_b - HbyA_n A) / rAU_P; in the predictor the
+   force density is extrapolated from the opposite face of the same cell. */
+static void fixed_flux_forces(const mesh_t *m, const double *HbyA, const double *rAU,
+                              double *q) {
+  const dbso_case *cs = m->cs;
+  for (int f = 0; f < m->nf; f++) {
+    const face_t *Fc = &m->f[f];
+    if (Fc->bnd < 0 || (Fc->kind != DBSO_WALL && Fc->kind != DBSO_INLET)) continue;
+    double so;
+    int c = bnd_cell(Fc, &so);
+    int a = Fc->axis;
+    if (HbyA) {
+      double Fb = Fc->kind == DBSO_INLET ? cs->bc_U[Fc->bnd][a] * Fc->area : 0.0;
+      q[f] = (Fb - HbyA[a * m->nc + c] * Fc->area) / rAU[c];
+    } else {
+      int opp = m->cf[c * 6 + 2 * a + (so > 0.0 ? 0 : 1)];
+      const face_t *Fo = &m->f[opp];
+      q[f] = (Fo->bnd >= 0 && Fo->kind != DBSO_OUTLET) ? 0.0 : q[opp];
+    }
+  }
+}
+
+/* capillary + gravity part of the face force only (phig / rAU_f / A_f) */
+static double face_body_force(const mesh_t *m, const props_t *pr, const double *alpha, int f) {
+  const dbso_case *cs = m->cs;
+  const face_t *Fc = &m->f[f];
+  int o = Fc->own, n = Fc->nbr;
+  double d = Fc->dist;
+  double cff = 0.5 * (pr[o].cf + pr[n].cf), pcf = 0.5 * (pr[o].pc + pr[n].pc);
+  double Fcap = cff * ((cs->rho_l - cs->rho_g) * cs->g[Fc->axis] + (pr[n].pc - pr[o].pc) / d) -
+                pcf * (alpha[n] - alpha[o]) / d;
+  return Fcap - dot3(cs->g, Fc->xf) * (pr[n].rho - pr[o].rho) / d;
+}
+
+/* R(q)_P along each non-empty axis */
+static void reconstruct(const mesh_t *m, const double *q, double *R) {
+  for (int c = 0; c < m->nc; c++)
+    for (int a = 0; a < 3; a++) {
+      int fm = m->cf[c * 6 + 2 * a], fp = m->cf[c * 6 + 2 * a + 1];
+      if (m->f[fm].kind == DBSO_EMPTY) { R[a * m->nc + c] = 0.0; continue; }
+      R[a * m->nc + c] = (q[fm] + q[fp]) / (2.0 * m->f[fm].area);
+    }
+}
+
+/* sum over neighbours of a_N U_N for component d */
+static double nb_sum(const mesh_t *m, const momeq_t *eq, const double *U, int c) {
+  double s = 0.0;
+  for (int k = 0; k < 6; k++) {
+    int f = m->cf[c * 6 + k];
+    const face_t *Fc = &m->f[f];
+    if (Fc->bnd >= 0) continue;
+    if (k & 1) s += eq->aON[f] * U[Fc->nbr];
+    else s += eq->aNO[f] * U[Fc->own];
+  }
+  return s;
+}
+
+static void momentum_assemble(const mesh_t *m, const double *phi, const props_t *po,
+                              const props_t *pn, const double *alpha_new,
+                              const double *U, const double *rhoPhi, const double *F,
+                              momeq_t *eq) {
+  const dbso_case *cs = m->cs;
+  int nc = m->nc, nf = m->nf;
+  double V = m->V, dt = cs->dt;
+  for (int c = 0; c < nc; c++) {
+    eq->aP[c] = pn[c].rho / (phi[c] * dt) + pn[c].K;
+    for (int d = 0; d < 3; d++) eq->Sh[d * nc + c] = po[c].rho * U[d * nc + c] / (phi[c] * dt);
+  }
+  for (int f = 0; f < nf; f++) {
+    const face_t *Fc = &m->f[f];
+    eq->aON[f] = eq->aNO[f] = 0.0;
+    if (Fc->kind == DBSO_EMPTY) continue;
+    double rp = rhoPhi[f];
+    if (Fc->bnd < 0) {
+      int o = Fc->own, n = Fc->nbr;
+      double phf = 0.5 * (phi[o] + phi[n]);
+      double vis = 0.5 * (pn[o].mu + pn[n].mu) * Fc->area / (Fc->dist * V);
+      eq->aP[o] += maxd(rp, 0.0) / (phf * phi[o] * V) + vis;
+      eq->aON[f] = maxd(-rp, 0.0) / (phf * phi[o] * V) + vis;
+      eq->aP[n] += maxd(-rp, 0.0) / (phf * phi[n] * V) + vis;
+      eq->aNO[f] = maxd(rp, 0.0) / (phf * phi[n] * V) + vis;
+      continue;
+    }
+    double so;
+    int c = bnd_cell(Fc, &so);
+    double out = so * rp;
+    double conv = 1.0 / (phi[c] * phi[c] * V);
+    if (Fc->kind == DBSO_WALL) {
+      eq->aP[c] += pn[c].mu * Fc->area / (Fc->dist * V);
+    } else if (Fc->kind == DBSO_INLET) {
+      const double *Ub = cs->bc_U[Fc->bnd];
+      double ab = cs->bc_alpha[Fc->bnd];
+      double vis = (ab * cs->mu_l + (1.0 - ab) * cs->mu_g) * Fc->area / (Fc->dist * V);
+      if (out >= 0.0) eq->aP[c] += out * conv;
+      else
+        for (int d = 0; d < 3; d++) eq->Sh[d * nc + c] += -out * Ub[d] * conv;
+      eq->aP[c] += vis;
+      for (int d = 0; d < 3; d++) eq->Sh[d * nc + c] += vis * Ub[d];
+    } else if (Fc->kind == DBSO_OUTLET) {
+      eq->aP[c] += out * conv;
+    }
+  }
+  if (cs->transpose_visc) {
+    /* explicit div(mu grad(U)^T) from U^n (R10); gradU[c][i][d] = dU_d/dx_i */
+    double *gU = (double *)calloc((size_t)nc * 9, sizeof(double));
+    for (int f = 0; f < nf; f++) {
+      const face_t *Fc = &m->f[f];
+      if (Fc->kind == DBSO_EMPTY) continue;
+      double Uf[3];
+      if (Fc->bnd < 0) {
+        for (int d = 0; d < 3; d++) Uf[d] = 0.5 * (U[d * nc + Fc->own] + U[d * nc + Fc->nbr]);
+      } else {
+        double so;
+        int c = bnd_cell(Fc, &so);
+        for (int d = 0; d < 3; d++)
+          Uf[d] = Fc->kind == DBSO_WALL ? 0.0
+                  : Fc->kind == DBSO_INLET ? cs->bc_U[Fc->bnd][d] : U[d * nc + c];
+      }
+      for (int d = 0; d < 3; d++) {
+        if (Fc->own >= 0) gU[Fc->own * 9 + Fc->axis * 3 + d] += Uf[d] * Fc->area / V;
+        if (Fc->nbr >= 0) gU[Fc->nbr * 9 + Fc->axis * 3 + d] -= Uf[d] * Fc->area / V;
+      }
+    }
+    for (int f = 0; f < nf; f++) {
+      const face_t *Fc = &m->f[f];
+      if (Fc->kind == DBSO_EMPTY) continue;
+      int a = Fc->axis;
+      for (int i = 0; i < 3; i++) {
+        double gfi, muf;
+        if (Fc->bnd < 0) {
+          gfi = 0.5 * (gU[Fc->own * 9 + i * 3 + a] + gU[Fc->nbr * 9 + i * 3 + a]);
+          muf = 0.5 * (pn[Fc->own].mu + pn[Fc->nbr].mu);
+          double t = muf * Fc->area * gfi / V;
+          eq->Sh[i * nc + Fc->own] += t;
+          eq->Sh[i * nc + Fc->nbr] -= t;
+        } else {
+          double so;
+          int c = bnd_cell(Fc, &so);
+          gfi = gU[c * 9 + i * 3 + a];
+          if (Fc->kind == DBSO_INLET) {
+            double ab = cs->bc_alpha[Fc->bnd];
+            muf = ab * cs->mu_l + (1.0 - ab) * cs->mu_g;
+          } else {
+            muf = pn[c].mu;
+          }
+          eq->Sh[i * nc + c] += so * muf * Fc->area * gfi / V;
+        }
+      }
+    }
+    free(gU);
+  }
+  (void)alpha_new;
+  (void)F;
+}
+
+/* ---------------------------------------------------- pressure operator */
+
+/* per-face coefficient of the SPD pressure operator (interior and outlet faces) */
+static void pressure_coeffs(const mesh_t *m, const double *rAU, double *T) {
+  for (int f = 0; f < m->nf; f++) {
+    const face_t *Fc = &m->f[f];
+    T[f] = 0.0;
+    if (Fc->bnd < 0) {
+      T[f] = 0.5 * (rAU[Fc->own] + rAU[Fc->nbr]) * Fc->area / Fc->dist;
+    } else if (Fc->kind == DBSO_OUTLET) {
+      double so;
+      int c = bnd_cell(Fc, &so);
+      T[f] = rAU[c] * Fc->area / Fc->dist;
+    }
+  }
+}
+
+static void apply_op(const mesh_t *m, const double *T, const double *x, double *y) {
+  for (int c = 0; c < m->nc; c++) y[c] = 0.0;
+  for (int f = 0; f < m->nf; f++) {
+    const face_t *Fc = &m->f[f];
+    if (T[f] == 0.0) continue;
+    if (Fc->bnd < 0) {
+      double t = T[f] * (x[Fc->own] - x[Fc->nbr]);
+      y[Fc->own] += t;
+      y[Fc->nbr] -= t;
+    } else {
+      double so;
+      int c = bnd_cell(Fc, &so);
+      y[c] += T[f] * x[c];
+    }
+  }
+}
+
+static int has_outlet(const dbso_case *cs) {
+  for (int b = 0; b < 6; b++)
+    if (cs->bc_kind[b] == DBSO_OUTLET) return 1;
+  return 0;
+}
+
+static double vdot(int n, const double *a, const double *b) {
+  double s = 0.0;
+  for (int i = 0; i < n; i++) s += a[i] * b[i];
+  return s;
+}
+
+static void remove_mean(int n, double *v) {
+  double s = 0.0;
+  for (int i = 0; i < n; i++) s += v[i];
+  s /= n;
+  for (int i = 0; i < n; i++) v[i] -= s;
+}
+
+/* Jacobi-preconditioned CG for A x = b (R14, R15) */
+static int pcg(const mesh_t *m, const double *T, const double *b_in, double *x,
+               double tol, int maxit, int *iters, double *relres) {
+  int n = m->nc, closed = !has_outlet(m->cs);
+  double *b = (double *)malloc(sizeof(double) * n);
+  double *r = (double *)malloc(sizeof(double) * n);
+  double *z = (double *)malloc(sizeof(double) * n);
+  double *p = (double *)malloc(sizeof(double) * n);
+  double *q = (double *)malloc(sizeof(double) * n);
+  double *dg = (double *)calloc((size_t)n, sizeof(double));
+  memcpy(b, b_in, sizeof(double) * n);
+  if (closed) remove_mean(n, b);
+  for (int f = 0; f < m->nf; f++) {
+    const face_t *Fc = &m->f[f];
+    if (T[f] == 0.0) continue;
+    if (Fc->bnd < 0) { dg[Fc->own] += T[f]; dg[Fc->nbr] += T[f]; }
+    else { double so; dg[bnd_cell(Fc, &so)] += T[f]; }
+  }
+  apply_op(m, T, x, q);
+  for (int i = 0; i < n; i++) r[i] = b[i] - q[i];
+  if (closed) remove_mean(n, r);
+  double nb = sqrt(vdot(n, b, b)), nr = sqrt(vdot(n, r, r));
+  double norm = nb > 0.0 ? nb : nr;
+  int it = 0, rc = 0;
+  if (norm > 0.0 && nr > tol * norm) {
+    for (int i = 0; i < n; i++) { z[i] = dg[i] > 0.0 ? r[i] / dg[i] : 0.0; p[i] = z[i]; }
+    double rz = vdot(n, r, z);
+    for (;;) {
+      if (it >= maxit) { rc = -4; break; }
+      apply_op(m, T, p, q);
+      double pq = vdot(n, p, q);
+      if (pq <= 0.0) { rc = nr <= tol * norm ? 0 : -4; break; }
+      double al = rz / pq;
+      for (int i = 0; i < n; i++) { x[i] += al * p[i]; r[i] -= al * q[i]; }
+      it++;
+      nr = sqrt(vdot(n, r, r));
+      if (nr <= tol * norm) break;
+      for (int i = 0; i < n; i++) z[i] = dg[i] > 0.0 ? r[i] / dg[i] : 0.0;
+      double rz1 = vdot(n, r, z);
+      double be = rz1 / rz;
+      rz = rz1;
+      for (int i = 0; i < n; i++) p[i] = z[i] + be * p[i];
+    }
+  }
+  if (closed) remove_mean(n, x);
+  /* report the true residual */
+  apply_op(m, T, x, q);
+  for (int i = 0; i < n; i++) r[i] = b[i] - q[i];
+  if (closed) remove_mean(n, r);
+  if (iters) *iters = it;
+  if (relres) *relres = norm > 0.0 ? sqrt(vdot(n, r, r)) / norm : 0.0;
+  free(b); free(r); free(z); free(p); free(q); free(dg);
+  return rc;
+}
+
+/* --------------------------------------------------------------- driver */
+
+int dbso_init_flux(const dbso_case *cs, const double *Ux, const double *Uy,
+                   const double *Uz, double *Fx, double *Fy, double *Fz) {
+  mesh_t m;
+  if (build_mesh(cs, &m)) { free_mesh(&m); return -1; }
+  const double *U[3] = {Ux, Uy, Uz};
+  double *Fo[3] = {Fx, Fy, Fz};
+  int off = 0;
+  for (int a = 0; a < 3; a++) {
+    for (int l = 0; l < m.nfa[a]; l++) {
+      const face_t *Fc = &m.f[off + l];
+      double v = 0.0;
+      if (Fc->bnd < 0) {
+        v = 0.5 * (U[a][Fc->own] + U[a][Fc->nbr]) * Fc->area;
+      } else if (Fc->kind == DBSO_INLET) {
+        v = cs->bc_U[Fc->bnd][a] * Fc->area;
+      } else if (Fc->kind == DBSO_OUTLET) {
+        double so;
+        v = U[a][bnd_cell(Fc, &so)] * Fc->area;
+      }
+      Fo[a][l] = v;
+    }
+    off += m.nfa[a];
+  }
+  free_mesh(&m);
+  return 0;
+}
+
+int dbso_pressure_apply(const dbso_case *cs, const double *rAU, const double *x,
+                        double *y) {
+  mesh_t m;
+  if (build_mesh(cs, &m)) { free_mesh(&m); return -1; }
+  double *T = (double *)malloc(sizeof(double) * m.nf);
+  pressure_coeffs(&m, rAU, T);
+  apply_op(&m, T, x, y);
+  free(T);
+  free_mesh(&m);
+  return 0;
+}
+
+int dbso_pressure_solve(const dbso_case *cs, const double *rAU, const double *b,
+                        double *x, double tol, int maxit, int *iters, double *relres) {
+  mesh_t m;
+  if (build_mesh(cs, &m)) { free_mesh(&m); return -1; }
+  double *T = (double *)malloc(sizeof(double) * m.nf);
+  pressure_coeffs(&m, rAU, T);
+  int rc = pcg(&m, T, b, x, tol, maxit, iters, relres);
+  free(T);
+  free_mesh(&m);
+  return rc;
+}
+
+int dbso_step(const dbso_case *cs, const double *phi, const double *kinv,
+              double *alpha, double *Ux, double *Uy, double *Uz, double *p_rgh,
+              double *p_out, double *Fx, double *Fy, double *Fz, int nsteps,
+              dbso_info *info, dbso_trace *trace) {
+  mesh_t m;
+  int rc = build_mesh(cs, &m);
+  if (rc) { free_mesh(&m); return rc; }
+  int nc = m.nc, nf = m.nf;
+  for (int c = 0; c < nc; c++)
+    if (!(phi[c] > 0.0 && phi[c] <= 1.0) || !(kinv[c] >= 0.0)) { free_mesh(&m); return -1; }
+  double V = m.V;
+  double *F = (double *)malloc(sizeof(double) * nf);
+  double *U = (double *)malloc(sizeof(double) * 3 * nc);
+  double *U2 = (double *)malloc(sizeof(double) * 3 * nc);
+  double *an = (double *)malloc(sizeof(double) * nc);
+  double *aPhi = (double *)malloc(sizeof(double) * nf);
+  double *rPhi = (double *)malloc(sizeof(double) * nf);
+  double *q = (double *)malloc(sizeof(double) * nf);
+  double *R = (double *)malloc(sizeof(double) * 3 * nc);
+  double *B = (double *)malloc(sizeof(double) * 3 * nc);
+  double *rAU = (double *)malloc(sizeof(double) * nc);
+  double *HbyA = (double *)malloc(sizeof(double) * 3 * nc);
+  double *phiH = (double *)malloc(sizeof(double) * nf);
+  double *T = (double *)malloc(sizeof(double) * nf);
+  double *b = (double *)malloc(sizeof(double) * nc);
+  props_t *po = (props_t *)malloc(sizeof(props_t) * nc);
+  props_t *pn = (props_t *)malloc(sizeof(props_t) * nc);
+  momeq_t eq;
+  eq.aP = (double *)malloc(sizeof(double) * nc);
+  eq.aON = (double *)malloc(sizeof(double) * nf);
+  eq.aNO = (double *)malloc(sizeof(double) * nf);
+  eq.Sh = (double *)malloc(sizeof(double) * 3 * nc);
+  memcpy(F, Fx, sizeof(double) * m.nfa[0]);
+  memcpy(F + m.nfa[0], Fy, sizeof(double) * m.nfa[1]);
+  memcpy(F + m.nfa[0] + m.nfa[1], Fz, sizeof(double) * m.nfa[2]);
+  memcpy(U, Ux, sizeof(double) * nc);
+  memcpy(U + nc, Uy, sizeof(double) * nc);
+  memcpy(U + 2 * nc, Uz, sizeof(double) * nc);
+  if (info) memset(info, 0, sizeof(*info));
+
+  for (int step = 0; step < nsteps && rc == 0; step++) {
+    dbso_trace *tr = step == 0 ? trace : NULL;
+    /* 1. saturation */
+    for (int c = 0; c < nc; c++) cell_props(cs, alpha[c], kinv[c], &po[c]);
+    alpha_stage(&m, phi, kinv, alpha, F, p_rgh, an, aPhi, rPhi, tr);
+    /* 2. properties at alpha^{n+1} */
+    for (int c = 0; c < nc; c++) cell_props(cs, an[c], kinv[c], &pn[c]);
+    /* 3. momentum predictor */
+    momentum_assemble(&m, phi, po, pn, an, U, rPhi, F, &eq);
+    face_forces(&m, pn, an, p_rgh, q);
+    fixed_flux_forces(&m, NULL, NULL, q);
+    reconstruct(&m, q, R);
+    for (int i = 0; i < 3 * nc; i++) B[i] = eq.Sh[i] + R[i];
+    for (int s = 0; s < cs->mom_sweeps; s++) {
+      for (int d = 0; d < 3; d++)
+        for (int c = 0; c < nc; c++)
+          U2[d * nc + c] = (nb_sum(&m, &eq, U + d * nc, c) + B[d * nc + c]) / eq.aP[c];
+      memcpy(U, U2, sizeof(double) * 3 * nc);
+    }
+    if (tr) {
+      if (tr->Shat) memcpy(tr->Shat, eq.Sh, sizeof(double) * 3 * nc);
+      if (tr->Ustar) memcpy(tr->Ustar, U, sizeof(double) * 3 * nc);
+    }
+    /* 4. PISO correctors */
+    for (int c = 0; c < nc; c++) rAU[c] = 1.0 / eq.aP[c];
+    pressure_coeffs(&m, rAU, T);
+    for (int corr = 0; corr < cs->n_corr; corr++) {
+      for (int d = 0; d < 3; d++)
+        for (int c = 0; c < nc; c++)
+          HbyA[d * nc + c] = rAU[c] * (nb_sum(&m, &eq, U + d * nc, c) + eq.Sh[d * nc + c]);
+      for (int f = 0; f < nf; f++) {
+        const face_t *Fc = &m.f[f];
+        int a = Fc->axis;
+        phiH[f] = 0.0;
+        if (Fc->kind == DBSO_EMPTY || Fc->kind == DBSO_WALL) continue;
+        if (Fc->bnd < 0) {
+          int o = Fc->own, n = Fc->nbr;
+          double rAUf = 0.5 * (rAU[o] + rAU[n]);
+          phiH[f] = 0.5 * (HbyA[a * nc + o] + HbyA[a * nc + n]) * Fc->area +
+                    rAUf * face_body_force(&m, pn, an, f) * Fc->area;
+        } else if (Fc->kind == DBSO_INLET) {
+          phiH[f] = cs->bc_U[Fc->bnd][a] * Fc->area;
+        } else {
+          double so;
+          phiH[f] = HbyA[a * nc + bnd_cell(Fc, &so)] * Fc->area;
+        }
+      }
+      for (int c = 0; c < nc; c++) {
+        double div = 0.0, dir = 0.0;
+        for (int s = 0; s < 6; s++) {
+          int f = m.cf[c * 6 + s];
+          const face_t *Fc = &m.f[f];
+          div += ((s & 1) ? 1.0 : -1.0) * phiH[f];
+          if (Fc->kind == DBSO_OUTLET) {
+            double pb = cs->bc_p[Fc->bnd] - pn[c].rho * dot3(cs->g, Fc->xf);
+            dir += T[f] * pb;
+          }
+        }
+        b[c] = -div + dir;
+      }
+      if (tr && corr == 0) {
+        if (tr->rAU) memcpy(tr->rAU, rAU, sizeof(double) * nc);
+        if (tr->HbyA) memcpy(tr->HbyA, HbyA, sizeof(double) * 3 * nc);
+        if (tr->phiHbyA) memcpy(tr->phiHbyA, phiH, sizeof(double) * nf);
+        if (tr->b) memcpy(tr->b, b, sizeof(double) * nc);
+      }
+      int its = 0;
+      double rr = 0.0;
+      int src = pcg(&m, T, b, p_rgh, cs->p_tol, cs->p_maxit, &its, &rr);
+      if (info && corr < 16) { info->p_iters[corr] = its; info->p_relres[corr] = rr; }
+      if (src) rc = src;
+      /* flux and velocity correction */
+      for (int f = 0; f < nf; f++) {
+        const face_t *Fc = &m.f[f];
+        F[f] = phiH[f];
+        if (Fc->bnd < 0) {
+          F[f] -= T[f] * (p_rgh[Fc->nbr] - p_rgh[Fc->own]);
+        } else if (Fc->kind == DBSO_OUTLET) {
+          double so;
+          int c = bnd_cell(Fc, &so);
+          double pb = cs->bc_p[Fc->bnd] - pn[c].rho * dot3(cs->g, Fc->xf);
+          F[f] -= so > 0.0 ? T[f] * (pb - p_rgh[c]) : T[f] * (p_rgh[c] - pb);
+        }
+      }
+      face_forces(&m, pn, an, p_rgh, q);
+      fixed_flux_forces(&m, HbyA, rAU, q);
+      reconstruct(&m, q, R);
+      for (int d = 0; d < 3; d++)
+        for (int c = 0; c < nc; c++)
+          U[d * nc + c] = HbyA[d * nc + c] + rAU[c] * R[d * nc + c];
+    }
+    memcpy(alpha, an, sizeof(double) * nc);
+  }
+
+  /* outputs */
+  memcpy(Ux, U, sizeof(double) * nc);
+  memcpy(Uy, U + nc, sizeof(double) * nc);
+  memcpy(Uz, U + 2 * nc, sizeof(double) * nc);
+  memcpy(Fx, F, sizeof(double) * m.nfa[0]);
+  memcpy(Fy, F + m.nfa[0], sizeof(double) * m.nfa[1]);
+  memcpy(Fz, F + m.nfa[0] + m.nfa[1], sizeof(double) * m.nfa[2]);
+  if (p_out) {
+    for (int c = 0; c < nc; c++) {
+      double x[3];
+      cell_centre(&m, c, x);
+      double rho = alpha[c] * cs->rho_l + (1.0 - alpha[c]) * cs->rho_g;
+      p_out[c] = p_rgh[c] + rho * dot3(cs->g, x);
+    }
+  }
+  if (info) {
+    info->alpha_min = 1e300;
+    info->alpha_max = -1e300;
+    info->phase_volume = 0.0;
+    info->max_div = 0.0;
+    for (int c = 0; c < nc; c++) {
+      info->alpha_min = mind(info->alpha_min, alpha[c]);
+      info->alpha_max = maxd(info->alpha_max, alpha[c]);
+      info->phase_volume += phi[c] * alpha[c] * V;
+      double div = 0.0;
+      for (int s = 0; s < 6; s++) div += ((s & 1) ? 1.0 : -1.0) * F[m.cf[c * 6 + s]];
+      info->max_div = maxd(info->max_div, fabs(div));
+    }
+  }
+  free(F); free(U); free(U2); free(an); free(aPhi); free(rPhi); free(q); free(R);
+  free(B); free(rAU); free(HbyA); free(phiH); free(T); free(b); free(po); free(pn);
+  free(eq.aP); free(eq.aON); free(eq.aNO); free(eq.Sh);
+  free_mesh(&m);
+  return rc;
+}

@@ -1,0 +1,110 @@
+/*
+ * Plain FP64 CPU oracle for one PISO time step of the two-phase
+ * micro-continuum Darcy-Brinkman-Stokes method (Carrillo, Bourg & Soulaine,
+ * "A micro-continuum framework for multiphase flow in porous media",
+ * arXiv:2003.08374) on a uniform Cartesian mesh.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing on the product path may include, link,
+ * load or call this code: only the tests, the smoke check and the benchmark's
+ * CPU-baseline leg use it.  It shares no source with the HIP library.
+ *
+ * Conventions (all readings are listed in the oracle source header):
+ *   - cells (i,j,k), linear index c = i + nx*(j + ny*k), x fastest;
+ *   - face arrays: Fx has (nx+1)*ny*nz entries, index i + (nx+1)*(j + ny*k);
+ *     Fy nx*(ny+1)*nz, index i + nx*(j + (ny+1)*k); Fz nx*ny*(nz+1),
+ *     index i + nx*(j + ny*k); face values are oriented along +axis;
+ *   - domain faces are numbered 0:x-, 1:x+, 2:y-, 3:y+, 4:z-, 5:z+.
+ */
+#ifndef DBS_ORACLE_H
+#define DBS_ORACLE_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { DBSO_WALL = 0, DBSO_INLET = 1, DBSO_OUTLET = 2, DBSO_EMPTY = 3 };
+enum { DBSO_BROOKS_COREY = 0, DBSO_VAN_GENUCHTEN = 1 };
+
+typedef struct {
+  int nx, ny, nz;
+  double hx, hy, hz;
+  /* fluids: l = wetting (alpha), g = non-wetting */
+  double rho_l, rho_g, mu_l, mu_g;
+  double g[3];
+  double c_alpha;           /* interface compression coefficient */
+  int kr_model;             /* DBSO_BROOKS_COREY or DBSO_VAN_GENUCHTEN */
+  double kr_m;              /* exponent m of the relative permeability model */
+  int pc_model;             /* DBSO_BROOKS_COREY or DBSO_VAN_GENUCHTEN */
+  double pc0;               /* entry capillary pressure p_c0 [Pa] */
+  double pc_exp;            /* beta (Brooks-Corey) or m (Van Genuchten) */
+  double s_lirr, s_girr;    /* irreducible saturations of the k_r model */
+  double a_pcirr, a_pcmax;  /* saturation range of the p_c model */
+  double eps_pc;            /* clamp of the normalised p_c saturation */
+  int bc_kind[6];
+  double bc_U[6][3];        /* inlet velocity */
+  double bc_alpha[6];       /* inlet alpha; outlet backflow alpha */
+  double bc_p[6];           /* outlet static pressure p */
+  double dt;
+  int n_corr;               /* PISO correctors */
+  int mom_sweeps;           /* Jacobi sweeps of the momentum predictor */
+  int transpose_visc;       /* include div(mu grad(U)^T) */
+  int mules_iter;           /* MULES limiter iterations */
+  double p_tol;             /* relative residual of the pressure solve */
+  int p_maxit;
+} dbso_case;
+
+typedef struct {
+  int p_iters[16];          /* pressure iterations per corrector (last step) */
+  double p_relres[16];
+  double alpha_min, alpha_max;
+  double phase_volume;      /* sum phi*alpha*V after the last step */
+  double max_div;           /* max |sum_out F| over cells after the last step */
+} dbso_info;
+
+/* Optional intermediate arrays of the first step (any pointer may be NULL).
+   Face arrays use the concatenated x|y|z face order. */
+typedef struct {
+  double *A;                /* MULES antidiffusive flux, faces */
+  double *Rp, *Rm;          /* Zalesak limiter R+ / R-, cells */
+  double *alphaPhi;         /* limited alpha flux, faces */
+  double *alpha_new;        /* cells */
+  double *rAU;              /* 1/a_P of the momentum equation, cells */
+  double *Shat;             /* explicit momentum source, 3 x cells */
+  double *Ustar;            /* predicted velocity, 3 x cells */
+  double *HbyA;             /* first corrector, 3 x cells */
+  double *phiHbyA;          /* first corrector, faces */
+  double *b;                /* first corrector pressure right-hand side */
+} dbso_trace;
+
+/* Relative permeabilities, capillary pressure and dp_c/dalpha at one
+   saturation (paper App. A). */
+void dbso_closures(const dbso_case *cs, double alpha, double *krl, double *krg,
+                   double *pc, double *dpc);
+
+/* Face fluxes F = (linear interpolate U) . S; boundary faces take the
+   inlet velocity, zero at walls, the cell velocity at outlets. */
+int dbso_init_flux(const dbso_case *cs, const double *Ux, const double *Uy,
+                   const double *Uz, double *Fx, double *Fy, double *Fz);
+
+/* Advance nsteps PISO steps in place.  p (out) may be NULL.  Returns 0, or a
+   negative code: -1 bad input, -4 pressure solve did not converge. */
+int dbso_step(const dbso_case *cs, const double *phi, const double *kinv,
+              double *alpha, double *Ux, double *Uy, double *Uz, double *p_rgh,
+              double *p, double *Fx, double *Fy, double *Fz, int nsteps,
+              dbso_info *info, dbso_trace *trace);
+
+/* y = A x for the pressure operator built from rAU and the case's boundary
+   conditions (SPD form: -laplacian(rAU_f) with Dirichlet outlet faces). */
+int dbso_pressure_apply(const dbso_case *cs, const double *rAU, const double *x,
+                        double *y);
+
+/* Solve A x = b (x holds the initial guess on entry).  Jacobi-preconditioned
+   conjugate gradients to ||b - A x|| <= tol ||b||. */
+int dbso_pressure_solve(const dbso_case *cs, const double *rAU, const double *b,
+                        double *x, double tol, int maxit, int *iters,
+                        double *relres);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,244 @@
+"""Seeded synthetic workloads shaped after the paper's cases.
+
+This module only builds inputs: meshes, fluid and model constants, boundary
+conditions and seeded porosity / permeability / initial fields.  It holds
+none of the method's arithmetic and imports neither the HIP binding nor the
+oracle, so both sides can take their inputs from it.
+
+Fluid properties follow the paper's Table 1 (water, air, oil) with the
+viscosity overrides of the benchmark workloads (air 1.8e-5 Pa s, oil
+5e-3 Pa s); model constants follow Table 2 unless a workload fixes others.
+The paper's own case geometries exist only as figures, so the 3D fractured
+media below are synthetic stand-ins for its fractured-matrix application
+(Sec. 5.2): log-normal permeability with an 8-cell correlation length,
+uniform porosity, and planar solid-free fractures.
+"""
+from __future__ import annotations
+
+import dataclasses
+from dataclasses import dataclass, field
+
+import numpy as np
+
+WATER = {"rho": 1000.0, "mu": 1e-3}
+AIR = {"rho": 1.0, "mu": 1.8e-5}
+OIL = {"rho": 800.0, "mu": 5e-3}
+GRAVITY = 9.81
+
+
+def fluids(l, g):
+    return {"rho_l": l["rho"], "mu_l": l["mu"], "rho_g": g["rho"], "mu_g": g["mu"]}
+
+
+def wall():
+    return {"kind": "wall"}
+
+
+def empty():
+    return {"kind": "empty"}
+
+
+def inlet(U, alpha):
+    return {"kind": "inlet", "U": tuple(float(u) for u in U), "alpha": float(alpha)}
+
+
+def outlet(p=0.0, backflow_alpha=0.0):
+    return {"kind": "outlet", "p": float(p), "alpha": float(backflow_alpha)}
+
+
+@dataclass
+class Case:
+    """One single-domain problem: mesh, physics, boundaries, controls, fields.
+
+    Arrays are float64 with shape (nz, ny, nx) (x fastest in memory); U has
+    shape (3, nz, ny, nx).  ``bc`` lists the six domain faces in the order
+    x-, x+, y-, y+, z-, z+.
+    """
+    name: str
+    shape: tuple
+    h: tuple
+    fluids: dict
+    g: tuple
+    bc: list
+    phi: np.ndarray
+    kinv: np.ndarray
+    alpha: np.ndarray
+    U: np.ndarray
+    p_rgh: np.ndarray
+    F: tuple | None = None
+    c_alpha: float = 1.0
+    kr: dict = field(default_factory=lambda: {"model": "brooks_corey", "m": 2.0})
+    pc: dict = field(default_factory=lambda: {"model": "brooks_corey", "pc0": 1e3, "exp": 0.5})
+    dt: float = 1e-5
+    n_corr: int = 2
+    mom_sweeps: int = 3
+    transpose_visc: bool = True
+    mules_iter: int = 3
+    p_tol: float = 1e-13
+    p_maxit: int = 2000
+    precision: str = "fp64"
+    steps: int = 1
+
+    @property
+    def ncells(self) -> int:
+        return int(np.prod(self.shape))
+
+    def replace(self, **kw) -> "Case":
+        return dataclasses.replace(self, **kw)
+
+
+def _zeros(shape):
+    nx, ny, nz = shape
+    return np.zeros((nz, ny, nx))
+
+
+def _blank_state(shape):
+    nx, ny, nz = shape
+    return _zeros(shape), np.zeros((3, nz, ny, nx)), _zeros(shape)
+
+
+# --------------------------------------------------------------- 2D layered
+
+
+def layered_2d(n=64, h=1e-3, dt=1e-5, U_in=1e-3, steps=20, name="layered_2d_64"):
+    """2D n x n, lower half porous (phi 0.5, k 1e-12 m^2), upper half clear.
+
+    Water (wetting) enters over the full height of the left side into air;
+    fixed-pressure outlet on the right, walls top and bottom, gravity -y.
+    Brooks-Corey k_r (m = 2) and p_c (entry 1e3 Pa, beta 0.5).
+    """
+    shape = (n, n, 1)
+    phi = np.ones((1, n, n))
+    kinv = np.zeros((1, n, n))
+    phi[:, : n // 2, :] = 0.5
+    kinv[:, : n // 2, :] = 1e12
+    alpha, U, prgh = _blank_state(shape)
+    bc = [inlet((U_in, 0, 0), 1.0), outlet(0.0, 0.0), wall(), wall(), empty(), empty()]
+    return Case(name=name, shape=shape, h=(h, h, h), fluids=fluids(WATER, AIR),
+                g=(0.0, -GRAVITY, 0.0), bc=bc, phi=phi, kinv=kinv, alpha=alpha, U=U,
+                p_rgh=prgh, dt=dt, steps=steps,
+                kr={"model": "brooks_corey", "m": 2.0},
+                pc={"model": "brooks_corey", "pc0": 1e3, "exp": 0.5})
+
+
+def layered_2d_stress(n=64):
+    """Limiter-stress variant: 100x the inlet speed and dt (Courant ~0.1-0.2)."""
+    return layered_2d(n=n, dt=1e-3, U_in=0.1, name=f"layered_2d_{n}_stress")
+
+
+# ------------------------------------------------------ 3D fractured matrix
+
+
+def gaussian_field(shape, seed, corr_cells=8.0):
+    """White noise N(0,1) smoothed by a periodic Gaussian kernel of standard
+    deviation corr_cells (FFT), then standardised to mean 0 and std 1."""
+    nx, ny, nz = shape
+    rng = np.random.default_rng(seed)
+    w = rng.standard_normal((nz, ny, nx))
+    kz = np.fft.fftfreq(nz)[:, None, None]
+    ky = np.fft.fftfreq(ny)[None, :, None]
+    kx = np.fft.fftfreq(nx)[None, None, :]
+    s = corr_cells
+    filt = np.exp(-2.0 * (np.pi * s) ** 2 * (kx ** 2 + ky ** 2 + kz ** 2))
+    f = np.real(np.fft.ifftn(np.fft.fftn(w) * filt))
+    sd = f.std()
+    return (f - f.mean()) / (sd if sd > 0 else 1.0)
+
+
+def porous_matrix(shape, seed_k, seed_phi, log10k_mean=-13.0, log10k_sigma=0.5,
+                  phi_range=(0.2, 0.4), corr_cells=8.0):
+    g = gaussian_field(shape, seed_k, corr_cells)
+    k = 10.0 ** (log10k_mean + log10k_sigma * g)
+    rng = np.random.default_rng(seed_phi)
+    nx, ny, nz = shape
+    phi = rng.uniform(phi_range[0], phi_range[1], size=(nz, ny, nx))
+    return phi, 1.0 / k
+
+
+def _cell_centres(shape, h):
+    nx, ny, nz = shape
+    z, y, x = np.meshgrid((np.arange(nz) + 0.5) * h[2], (np.arange(ny) + 0.5) * h[1],
+                          (np.arange(nx) + 0.5) * h[0], indexing="ij")
+    return x, y, z
+
+
+def slab_fracture_mask(shape, h, half_width_cells=4):
+    """Solid-free slab |y - L_y/2| < half_width, spanning x and z."""
+    x, y, z = _cell_centres(shape, h)
+    Ly = shape[1] * h[1]
+    return np.abs(y - 0.5 * Ly) < half_width_cells * h[1]
+
+
+def random_plane_fractures(shape, h, n_frac, seed, half_width_cells=4):
+    """n_frac planes: normals uniform on the sphere, centres uniform in the
+    middle half of the box; cells within half_width of a plane are clear."""
+    rng = np.random.default_rng(seed)
+    x, y, z = _cell_centres(shape, h)
+    L = np.array([shape[0] * h[0], shape[1] * h[1], shape[2] * h[2]])
+    mask = np.zeros(x.shape, dtype=bool)
+    for _ in range(n_frac):
+        nrm = rng.standard_normal(3)
+        nrm /= np.linalg.norm(nrm)
+        c = rng.uniform(0.25, 0.75, size=3) * L
+        d = nrm[0] * (x - c[0]) + nrm[1] * (y - c[1]) + nrm[2] * (z - c[2])
+        mask |= np.abs(d) < half_width_cells * h[0]
+    return mask
+
+
+def fractured_3d(n=128, h=1e-4, dt=1e-5, seed_k=1, seed_phi=2, fractures="slab",
+                 frac_seed=5, n_frac=3, steps=100, U_in=1e-3, name=None, shape=None):
+    """3D fractured microporous matrix: water displacing oil.
+
+    log10 k = -13 + 0.5 g (g: 8-cell-correlated Gaussian field), phi ~ U[0.2,0.4];
+    fractures (phi = 1, k^-1 = 0) 8 cells wide: one slab normal to y, or
+    ``n_frac`` random planes.  Inlet on x- (U_in, alpha = 1), outlet on x+,
+    walls elsewhere, gravity -y; constitutive models as the 2D layered case.
+    """
+    shape = tuple(shape) if shape is not None else (n, n, n)
+    hh = (h, h, h)
+    phi, kinv = porous_matrix(shape, seed_k, seed_phi)
+    if fractures == "slab":
+        m = slab_fracture_mask(shape, hh)
+    elif fractures == "planes":
+        m = random_plane_fractures(shape, hh, n_frac, frac_seed)
+    else:
+        m = np.zeros(phi.shape, dtype=bool)
+    phi[m] = 1.0
+    kinv[m] = 0.0
+    alpha, U, prgh = _blank_state(shape)
+    bc = [inlet((U_in, 0, 0), 1.0), outlet(0.0, 0.0), wall(), wall(), wall(), wall()]
+    nm = name or f"fractured_3d_{shape[0]}x{shape[1]}x{shape[2]}_{fractures}"
+    return Case(name=nm, shape=shape, h=hh, fluids=fluids(WATER, OIL),
+                g=(0.0, -GRAVITY, 0.0), bc=bc, phi=phi, kinv=kinv, alpha=alpha, U=U,
+                p_rgh=prgh, dt=dt, steps=steps,
+                kr={"model": "brooks_corey", "m": 2.0},
+                pc={"model": "brooks_corey", "pc0": 1e3, "exp": 0.5})
+
+
+def fractured_128():
+    """128^3, one slab fracture, k seed 1, phi seed 2, 100 steps."""
+    return fractured_3d(n=128, seed_k=1, seed_phi=2, fractures="slab", steps=100,
+                        name="fractured_3d_128_slab")
+
+
+def fractured_256(precision="mixed", p_tol=1e-8):
+    """256^3, three random planar fractures (seed 5), k seed 3, phi seed 4."""
+    c = fractured_3d(n=256, seed_k=3, seed_phi=4, fractures="planes", frac_seed=5,
+                     n_frac=3, steps=12, name="fractured_3d_256_planes")
+    return c.replace(precision=precision, p_tol=p_tol)
+
+
+def batch_sizes(n_samples=512, seed=6, lo=32, hi=96):
+    rng = np.random.default_rng(seed)
+    return rng.integers(lo, hi + 1, size=n_samples)
+
+
+def batch_cases(n_samples=512, seed=6, lo=32, hi=96, precision="fp64", p_tol=1e-13):
+    """Independent cubic porous samples of edge U{lo..hi}; sample s has k seed
+    1000+s and phi seed 2000+s, no fracture."""
+    out = []
+    for s, n in enumerate(batch_sizes(n_samples, seed, lo, hi)):
+        c = fractured_3d(n=int(n), seed_k=1000 + s, seed_phi=2000 + s, fractures=None,
+                         steps=12, name=f"sample_{s}_{n}")
+        out.append(c.replace(precision=precision, p_tol=p_tol))
+    return out
