@@ -1,0 +1,179 @@
+/*
+ * dbs.h -- C ABI of the MI355X (gfx950) implementation of one PISO time step
+ * of the two-phase micro-continuum Darcy-Brinkman-Stokes method of Carrillo,
+ * Bourg and Soulaine (arXiv:2003.08374).
+ *
+ * The problem follows the paper's summary of the model, Eq.
+ * (two-phase-microcontinuum) in Sec. 2.2: the saturation alpha (wetting
+ * phase), the single-field (superficial) velocity U, the pressure p (solved
+ * as p_rgh = p - rho g.x), the porosity phi and the permeability k go in;
+ * advanced fields come out.  One call of dbs_step advances dt with the
+ * sequence of Sec. 3.2: MULES saturation transport with the relative flux of
+ * Sec. 2.3, property update (App. A closures, App. B capillary force),
+ * momentum predictor with the Darcy drag of Eq. (single-field-kr) in its
+ * Sec. 2.3 summary form, and n_corr pressure correctors (Eqs.
+ * (corrected_velocity), (pressure_predictor)) whose pressure equation is
+ * solved by conjugate gradients preconditioned with a geometric multigrid
+ * V-cycle.
+ *
+ * Mesh: uniform Cartesian nx*ny*nz, cell-centred.  Cell arrays hold nx*ny*nz
+ * doubles, index i + nx*(j + ny*k).  Face arrays are concatenated x|y|z:
+ * (nx+1)*ny*nz x-faces (index i + (nx+1)*(j + ny*k)), then nx*(ny+1)*nz
+ * y-faces (index i + nx*(j + (ny+1)*k)), then nx*ny*(nz+1) z-faces (index
+ * i + nx*(j + ny*k)); a face value is a volumetric flux [m^3/s] oriented
+ * along +axis.  Vector cell fields (U) are component-major: Ux | Uy | Uz.
+ * Domain faces: 0 x-, 1 x+, 2 y-, 3 y+, 4 z-, 5 z+.
+ *
+ * Ownership: the caller owns every host buffer; calls copy in or out and
+ * never keep caller pointers.  The library owns its device state from
+ * dbs_create to dbs_destroy.  The *_dev calls borrow caller device buffers
+ * only for the duration of the call.
+ *
+ * Errors: every int-returning call returns DBS_OK (0) or a negative DBS_E*
+ * code and records a message readable with dbs_last_error.  No C++
+ * exception crosses this boundary.  A handle is not thread-safe: calls on
+ * one handle must not overlap.
+ */
+#ifndef DBS_H
+#define DBS_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DBS_OK 0
+#define DBS_EINVAL (-1)   /* invalid argument or input field */
+#define DBS_ENOMEM (-2)   /* device allocation failed */
+#define DBS_EHIP (-3)     /* HIP runtime error */
+#define DBS_ENOCONV (-4)  /* pressure solve hit p_maxit; state = last iterate */
+#define DBS_ENAN (-5)     /* non-finite value in the state after a step */
+#define DBS_ECOURANT (-6) /* Courant number above max_courant; step not taken */
+#define DBS_EBOUNDS (-7)  /* alpha left [-bounds_tol, 1 + bounds_tol] */
+
+enum { DBS_BC_WALL = 0, DBS_BC_INLET = 1, DBS_BC_OUTLET = 2, DBS_BC_EMPTY = 3 };
+enum { DBS_BROOKS_COREY = 0, DBS_VAN_GENUCHTEN = 1 };
+enum { DBS_FP64 = 0, DBS_MIXED = 1 };
+
+typedef struct {
+  int nx, ny, nz;       /* cells per axis; nz = 1 with EMPTY z faces is 2D */
+  double dx, dy, dz;    /* cell size [m] */
+} dbs_grid;
+
+typedef struct {
+  double rho_l, rho_g;  /* densities of the wetting (alpha) and other phase */
+  double mu_l, mu_g;    /* viscosities [Pa s] */
+  double g[3];          /* gravity [m/s^2] */
+  double c_alpha;       /* interface compression coefficient (Sec. 2.3) */
+  int kr_model;         /* DBS_BROOKS_COREY or DBS_VAN_GENUCHTEN (App. A.1) */
+  double kr_m;          /* exponent m */
+  double s_lirr, s_girr;/* irreducible saturations */
+  int pc_model;         /* DBS_BROOKS_COREY or DBS_VAN_GENUCHTEN (App. A.2) */
+  double pc0;           /* entry capillary pressure [Pa] */
+  double pc_exp;        /* beta (Brooks-Corey) or m (Van Genuchten) */
+  double a_pcirr, a_pcmax; /* saturation range of the p_c model */
+  double eps_pc;        /* clamp of the normalised p_c saturation (>0) */
+} dbs_physics;
+
+typedef struct {
+  int kind;             /* DBS_BC_* */
+  double U[3];          /* inlet velocity */
+  double alpha;         /* inlet alpha; outlet backflow alpha */
+  double p;             /* outlet static pressure p [Pa] */
+} dbs_bc;
+
+typedef struct {
+  double dt;            /* time step [s] */
+  int n_corr;           /* PISO correctors (>= 1, the paper uses >= 2) */
+  int mom_sweeps;       /* Jacobi sweeps of the momentum predictor */
+  int transpose_visc;   /* 1: add div(mu grad(U)^T) explicitly */
+  int mules_iter;       /* MULES limiter iterations (>= 1) */
+  double p_tol;         /* pressure solve: ||b - A x||_2 <= p_tol ||b||_2 */
+  int p_maxit;          /* PCG iteration limit */
+  int precision;        /* DBS_FP64, or DBS_MIXED: FP32 multigrid inside FP64 PCG */
+  int mg_pre, mg_post;  /* red-black Gauss-Seidel sweeps per level (0: default 2) */
+  double max_courant;   /* > 0: refuse a step whose Courant number exceeds it */
+  double bounds_tol;    /* > 0: report DBS_EBOUNDS when alpha leaves the band */
+} dbs_controls;
+
+typedef struct {
+  long long steps;      /* steps taken since creation */
+  int p_iters[16];      /* PCG iterations per corrector of the last step */
+  double p_relres[16];  /* final relative residual per corrector */
+  int mg_levels;        /* multigrid levels */
+  double alpha_min, alpha_max;
+  double phase_volume;  /* sum phi alpha V */
+  double max_courant;   /* at the start of the last step */
+} dbs_stats;
+
+typedef struct dbs_handle dbs_handle;
+
+/* Validate the problem and allocate device state on the current HIP device.
+   All inputs are copied.  Fails with DBS_EINVAL for non-positive sizes, an
+   unpaired or misplaced EMPTY face, unknown models or non-positive dt. */
+int dbs_create(const dbs_grid *grid, const dbs_physics *phys, const dbs_bc bc[6],
+               const dbs_controls *ctl, dbs_handle **out);
+
+/* Porosity phi in (0, 1] and inverse permeability k0^-1 >= 0 [m^-2]
+   (0 marks a solid-free cell), host cell arrays (Sec. 2.2 porosity field).
+   DBS_EINVAL if a value is out of range or not finite. */
+int dbs_set_static(dbs_handle *h, const double *phi, const double *kinv);
+
+/* Host cell arrays alpha, U (3 x cells), p_rgh and the face flux F (or NULL:
+   F = linearly interpolated U . S with boundary values).  Resets the
+   derived fields (closures) from alpha. */
+int dbs_set_state(dbs_handle *h, const double *alpha, const double *U,
+                  const double *p_rgh, const double *F);
+
+/* Advance nsteps time steps (Sec. 3.2 sequence).  Synchronises the
+   library stream before returning. */
+int dbs_step(dbs_handle *h, int nsteps);
+
+/* Copy the state to host arrays; any pointer may be NULL.  p = p_rgh +
+   rho g.x (cell centres measured from the minimum corner). */
+int dbs_get_state(dbs_handle *h, double *alpha, double *U, double *p_rgh, double *p,
+                  double *F);
+
+/* Device-pointer forms: the same layouts in device memory, copied on
+   `stream` (a hipStream_t, NULL = the library stream) and synchronised. */
+int dbs_set_state_dev(dbs_handle *h, const double *alpha, const double *U,
+                      const double *p_rgh, const double *F, void *stream);
+int dbs_get_state_dev(dbs_handle *h, double *alpha, double *U, double *p_rgh, double *p,
+                      double *F, void *stream);
+
+/* Run subsequent work on a caller stream (hipStream_t; NULL restores the
+   library's own stream, created with default priority). */
+int dbs_set_stream(dbs_handle *h, void *stream);
+
+int dbs_get_stats(dbs_handle *h, dbs_stats *out);
+const char *dbs_last_error(const dbs_handle *h);
+void dbs_destroy(dbs_handle *h);
+
+/* Kernel timing with HIP events on the library stream.  mask selects kernel
+   classes (bit i = class i, see dbs_kernel_name); 0 turns timing off.
+   dbs_kernel_time returns the launches and the summed milliseconds of one
+   class since the last reset. */
+int dbs_set_profiling(dbs_handle *h, unsigned long long mask);
+int dbs_kernel_time(dbs_handle *h, int cls, long long *launches, double *ms);
+const char *dbs_kernel_name(int cls);
+int dbs_kernel_classes(void);
+void dbs_reset_profiling(dbs_handle *h);
+
+/* Tests only.  Solve the p_rgh pressure equation of this handle's mesh and
+   boundary conditions, -div(rAU_f grad x) with outlet faces as Dirichlet
+   faces (the operator of Eq. (pressure_predictor)), for host arrays rAU and
+   b; x holds the initial guess and receives the solution. */
+int dbs_debug_pressure_solve(dbs_handle *h, const double *rAU, const double *b, double *x,
+                             int *iters, double *relres);
+
+/* Tests only.  Run one step and copy intermediate fields to host arrays
+   (any pointer may be NULL): the MULES antidiffusive flux A (faces), 1/a_P
+   (cells), momentum source Shat and predicted U (3 x cells), and from the
+   first corrector HbyA (3 x cells), phiHbyA (faces) and the pressure
+   right-hand side b (cells). */
+int dbs_debug_step_trace(dbs_handle *h, double *A, double *rAU, double *Shat, double *Ustar,
+                         double *HbyA, double *phiHbyA, double *b);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DBS_H */

@@ -1,0 +1,178 @@
+// Internal device-side definitions shared by the HIP translation units.
+//
+// Layout: structure-of-arrays FP64 fields, x fastest (c = i + nx*(j + ny*k)).
+// Face arrays keep (n+1) entries along their own axis; a face value is
+// oriented along +axis.  Kernels run one thread per cell on 64 x 4 blocks
+// (one wavefront per 64-cell x-row segment, coalesced 512-byte loads).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+namespace dbs {
+
+enum { BC_WALL = 0, BC_INLET = 1, BC_OUTLET = 2, BC_EMPTY = 3 };
+enum { M_BROOKS_COREY = 0, M_VAN_GENUCHTEN = 1 };
+
+constexpr int BX = 64;
+constexpr int BY = 4;
+constexpr int NTHREADS = BX * BY;
+
+struct Phys {
+  double rho_l, rho_g, mu_l, mu_g;
+  double g[3];
+  double c_alpha;
+  int kr_model;
+  double kr_m, inv_kr_m, s_lirr, inv_span_kr;
+  int pc_model;
+  double pc0, pc_exp, a_pcirr, inv_span_pc, eps_pc;
+};
+
+struct Geom {
+  int n[3];
+  int nc;
+  int fo[3];        // offsets of the x|y|z face blocks in a concatenated face array
+  int nf;           // total faces
+  double h[3], ih[3], area[3], V, iV;
+  double dt;
+  int bck[6];
+  double bcU[6][3];
+  double bca[6];
+  double bcp[6];
+  int has_outlet;
+  double dN;        // interface-normal regularisation 1e-8 / V^(1/3)
+};
+
+// ---------------------------------------------------------------- indexing
+
+__device__ __forceinline__ int cidx(const Geom &G, int i, int j, int k) {
+  return i + G.n[0] * (j + G.n[1] * k);
+}
+
+// face on the minus side of cell coordinate (i,j,k) along axis a (the
+// coordinate along a may equal n[a]: the last face)
+__device__ __forceinline__ int fidx(const Geom &G, int a, int i, int j, int k) {
+  if (a == 0) return G.fo[0] + i + (G.n[0] + 1) * (j + G.n[1] * k);
+  if (a == 1) return G.fo[1] + i + G.n[0] * (j + (G.n[1] + 1) * k);
+  return G.fo[2] + i + G.n[0] * (j + G.n[1] * k);
+}
+
+__device__ __forceinline__ int stride_of(const Geom &G, int a) {
+  return a == 0 ? 1 : (a == 1 ? G.n[0] : G.n[0] * G.n[1]);
+}
+
+struct Cell {
+  int i, j, k, c;
+  int co[3];
+};
+
+__device__ __forceinline__ bool cell_from_thread(const Geom &G, Cell &P) {
+  P.i = blockIdx.x * BX + threadIdx.x;
+  P.j = blockIdx.y * BY + threadIdx.y;
+  P.k = blockIdx.z;
+  if (P.i >= G.n[0] || P.j >= G.n[1]) return false;
+  P.co[0] = P.i; P.co[1] = P.j; P.co[2] = P.k;
+  P.c = cidx(G, P.i, P.j, P.k);
+  return true;
+}
+
+// face index of side s (0 = minus, 1 = plus) of cell P along axis a
+__device__ __forceinline__ int face_of(const Geom &G, const Cell &P, int a, int s) {
+  int ii = P.i + (a == 0 ? s : 0), jj = P.j + (a == 1 ? s : 0), kk = P.k + (a == 2 ? s : 0);
+  return fidx(G, a, ii, jj, kk);
+}
+
+// is side s of cell P along axis a a domain boundary face?
+__device__ __forceinline__ bool on_boundary(const Geom &G, const Cell &P, int a, int s) {
+  return s == 0 ? P.co[a] == 0 : P.co[a] == G.n[a] - 1;
+}
+
+__device__ __forceinline__ double gdotx_cell(const Geom &G, const Phys &Ph, const Cell &P) {
+  return Ph.g[0] * (P.i + 0.5) * G.h[0] + Ph.g[1] * (P.j + 0.5) * G.h[1] +
+         Ph.g[2] * (P.k + 0.5) * G.h[2];
+}
+
+// g . x at the centre of side s of cell P along axis a
+__device__ __forceinline__ double gdotx_face(const Geom &G, const Phys &Ph, const Cell &P, int a,
+                                             int s) {
+  double x[3] = {(P.i + 0.5) * G.h[0], (P.j + 0.5) * G.h[1], (P.k + 0.5) * G.h[2]};
+  x[a] = (P.co[a] + s) * G.h[a];
+  return Ph.g[0] * x[0] + Ph.g[1] * x[1] + Ph.g[2] * x[2];
+}
+
+// ---------------------------------------------------------------- physics
+
+__device__ __forceinline__ double rho_of(const Phys &Ph, double a) {
+  return a * Ph.rho_l + (1.0 - a) * Ph.rho_g;
+}
+__device__ __forceinline__ double mu_of(const Phys &Ph, double a) {
+  return a * Ph.mu_l + (1.0 - a) * Ph.mu_g;
+}
+
+__device__ __forceinline__ double clamp01(double x, double lo, double hi) {
+  return fmin(fmax(x, lo), hi);
+}
+
+// App. A.1 relative permeabilities divided by the viscosities (mobility per
+// unit permeability) and App. A.2 capillary pressure of one cell.
+__device__ inline void closures(const Phys &Ph, double a, double &ml, double &mg, double &pc) {
+  double ae = clamp01((a - Ph.s_lirr) * Ph.inv_span_kr, 0.0, 1.0);
+  double krl, krg;
+  if (Ph.kr_model == M_BROOKS_COREY) {
+    krl = pow(ae, Ph.kr_m);
+    krg = pow(1.0 - ae, Ph.kr_m);
+  } else {
+    double t = pow(ae, Ph.inv_kr_m);
+    double u = 1.0 - pow(1.0 - t, Ph.kr_m);
+    krl = sqrt(ae) * u * u;
+    krg = sqrt(1.0 - ae) * pow(1.0 - t, 2.0 * Ph.kr_m);
+  }
+  ml = krl / Ph.mu_l;
+  mg = krg / Ph.mu_g;
+  double s = (a - Ph.a_pcirr) * Ph.inv_span_pc;
+  if (Ph.pc_model == M_BROOKS_COREY) {
+    s = clamp01(s, Ph.eps_pc, 1.0);
+    pc = Ph.pc0 * pow(s, -Ph.pc_exp);
+  } else {
+    s = clamp01(s, Ph.eps_pc, 1.0 - Ph.eps_pc);
+    pc = Ph.pc0 * pow(pow(s, -1.0 / Ph.pc_exp) - 1.0, 1.0 - Ph.pc_exp);
+  }
+}
+
+// boundary alpha (inlet value; outlet backflow value; else the cell value)
+__device__ __forceinline__ double bnd_alpha(const Geom &G, int b, double a_cell, double Fb) {
+  int kind = G.bck[b];
+  double so = (b & 1) ? 1.0 : -1.0;
+  if (kind == BC_INLET) return G.bca[b];
+  if (kind == BC_OUTLET && so * Fb < 0.0) return G.bca[b];
+  return a_cell;
+}
+
+// ---------------------------------------------------------- reductions
+
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+__device__ __forceinline__ double wave_min(double v) {
+  for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// block-wide sum over NTHREADS threads (4 wavefronts); result valid in thread 0
+__device__ __forceinline__ double block_sum(double v, double *lds) {
+  v = wave_sum(v);
+  int t = threadIdx.x + BX * threadIdx.y;
+  int w = t >> 6;
+  if ((t & 63) == 0) lds[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (t == 0)
+    for (int q = 0; q < NTHREADS / 64; q++) s += lds[q];
+  return s;
+}
+
+}  // namespace dbs

@@ -1,0 +1,321 @@
+// Saturation transport: Eq. (phaseEq) of Sec. 2.2 advanced explicitly with a
+// Van Leer convection flux, the relative flux phi*alpha_l*alpha_g*v_r of the
+// Sec. 2.3 summary (interface compression in clear regions, Eq. (vr_porous)
+// in porous regions) and the MULES flux limiter (Sec. 3.2).
+//
+// Five passes over the cells (plus two per extra limiter iteration):
+//   alpha_face     antidiffusive face flux A = F*alpha_VL + G - F*alpha_upwind
+//   alpha_bounds   local extrema, low-order provisional alpha, Q+-, P+-
+//   alpha_R        cell limiter factors R+- (counts limited counter-fluxes)
+//   alpha_lambda   face limiter = min over the two cells, never increasing
+//   alpha_update   limited flux, alpha^{n+1}, mass flux rhoPhi, closures
+// Every face is owned by the cell on its plus side (plus the last face of
+// each row, owned by the last cell), so all writes are race-free.
+#include "dbs_internal.h"
+
+namespace dbs {
+
+struct AlphaArgs {
+  const double *__restrict__ alpha, *__restrict__ F, *__restrict__ phi, *__restrict__ kinv;
+  const double *__restrict__ prgh, *__restrict__ ml, *__restrict__ mg, *__restrict__ pc;
+};
+
+__device__ inline Cell shifted(const Geom &G, const Cell &P, int a, int d) {
+  Cell Q = P;
+  Q.co[a] += d;
+  Q.i = Q.co[0]; Q.j = Q.co[1]; Q.k = Q.co[2];
+  Q.c = P.c + d * stride_of(G, a);
+  return Q;
+}
+
+// Gauss gradient of alpha in cell P: face values are the mean with the
+// neighbour, or the boundary alpha; empty axes contribute nothing.
+__device__ inline void grad_alpha(const Geom &G, const AlphaArgs &X, const Cell &P, double g[3]) {
+  double aP = X.alpha[P.c];
+  for (int a = 0; a < 3; a++) {
+    if (G.n[a] == 1 && G.bck[2 * a] == BC_EMPTY) { g[a] = 0.0; continue; }
+    double fv[2];
+    for (int s = 0; s < 2; s++) {
+      if (on_boundary(G, P, a, s))
+        fv[s] = bnd_alpha(G, 2 * a + s, aP, X.F[face_of(G, P, a, s)]);
+      else
+        fv[s] = 0.5 * (aP + X.alpha[P.c + (s ? 1 : -1) * stride_of(G, a)]);
+    }
+    g[a] = (fv[1] - fv[0]) * G.ih[a];
+  }
+}
+
+// Antidiffusive flux of the interior face on the minus side of cell N along a.
+__device__ inline double face_antidiffusive(const Geom &G, const Phys &Ph, const AlphaArgs &X,
+                                            const Cell &N, int a, int f) {
+  const int sa = stride_of(G, a);
+  const int o = N.c - sa, n = N.c;
+  const double Ff = X.F[f];
+  const double ao = X.alpha[o], an = X.alpha[n];
+  const bool fwd = Ff >= 0.0;
+  const double aU = fwd ? ao : an, aD = fwd ? an : ao;
+  double aUU = aU;
+  if (fwd) {
+    if (N.co[a] >= 2) aUU = X.alpha[o - sa];
+  } else {
+    if (N.co[a] + 1 < G.n[a]) aUU = X.alpha[n + sa];
+  }
+  const double FL = Ff * aU;
+  double avl = aU;
+  if (aD != aU) {
+    double r = (aU - aUU) / (aD - aU);
+    double psi = (r + fabs(r)) / (1.0 + fabs(r));
+    avl = aU + 0.5 * psi * (aD - aU);
+  }
+  double Gr;
+  const double ko = X.kinv[o], kn = X.kinv[n];
+  if (ko == 0.0 && kn == 0.0) {
+    // clear face: compression flux along +grad(alpha), face-local |v|
+    double go[3], gn[3];
+    Cell O = shifted(G, N, a, -1);
+    grad_alpha(G, X, O, go);
+    grad_alpha(G, X, N, gn);
+    double gf[3], mag2 = 0.0;
+    for (int b = 0; b < 3; b++) {
+      gf[b] = 0.5 * (go[b] + gn[b]);
+      mag2 += gf[b] * gf[b];
+    }
+    double nfa = gf[a] / (sqrt(mag2) + G.dN);
+    double Fr = Ph.c_alpha * fabs(Ff) * nfa;
+    Gr = Fr >= 0.0 ? Fr * ao * (1.0 - an) : Fr * an * (1.0 - ao);
+  } else {
+    // porous face: alpha_g u_l - alpha u_g with phase-upwinded mobilities
+    Cell O = shifted(G, N, a, -1);
+    const double k0f = 2.0 / (ko + kn);
+    const double af = 0.5 * (ao + an), agf = 1.0 - af;
+    const double ga = Ph.g[a];
+    const double po = X.prgh[o] + rho_of(Ph, ao) * gdotx_cell(G, Ph, O);
+    const double pn = X.prgh[n] + rho_of(Ph, an) * gdotx_cell(G, Ph, N);
+    const double pco = X.pc[o], pcn = X.pc[n];
+    const double dp = (pn - po) * G.ih[a];
+    const double dpl = dp - ((1.0 - an) * pcn - (1.0 - ao) * pco) * G.ih[a] - Ph.rho_l * ga;
+    const double dpg = dp + (an * pcn - ao * pco) * G.ih[a] - Ph.rho_g * ga;
+    const double mlf = dpl < 0.0 ? X.ml[o] : X.ml[n];
+    const double mgf = dpg < 0.0 ? X.mg[o] : X.mg[n];
+    const double ul = -k0f * mlf * dpl * G.area[a];
+    const double ug = -k0f * mgf * dpg * G.area[a];
+    Gr = agf * ul - af * ug;
+  }
+  return Ff * avl + Gr - FL;
+}
+
+__global__ void __launch_bounds__(NTHREADS) k_alpha_face(Geom G, Phys Ph, AlphaArgs X,
+                                                         double *__restrict__ A) {
+  Cell P;
+  if (!cell_from_thread(G, P)) return;
+  for (int a = 0; a < 3; a++) {
+    int f = face_of(G, P, a, 0);
+    A[f] = on_boundary(G, P, a, 0) ? 0.0 : face_antidiffusive(G, Ph, X, P, a, f);
+    if (P.co[a] == G.n[a] - 1) A[face_of(G, P, a, 1)] = 0.0;
+  }
+}
+
+// low-order (upwind) flux of side s of cell P along a, oriented along +axis
+__device__ __forceinline__ double low_order_flux(const Geom &G, const double *__restrict__ alpha,
+                                                 const double *__restrict__ F, const Cell &P,
+                                                 int a, int s, int f, bool bnd) {
+  double Ff = F[f];
+  if (bnd) return Ff * bnd_alpha(G, 2 * a + s, alpha[P.c], Ff);
+  int nb = P.c + (s ? 1 : -1) * stride_of(G, a);
+  int own = s ? P.c : nb, nbr = s ? nb : P.c;
+  return Ff * (Ff >= 0.0 ? alpha[own] : alpha[nbr]);
+}
+
+__global__ void __launch_bounds__(NTHREADS) k_alpha_bounds(
+    Geom G, const double *__restrict__ alpha, const double *__restrict__ F,
+    const double *__restrict__ phi, const double *__restrict__ A, double *__restrict__ Qp,
+    double *__restrict__ Qm, double *__restrict__ Pin, double *__restrict__ Pout) {
+  Cell P;
+  if (!cell_from_thread(G, P)) return;
+  const double aP = alpha[P.c];
+  double outL = 0.0, amax = aP, amin = aP, pin = 0.0, pout = 0.0;
+  for (int a = 0; a < 3; a++) {
+    if (G.n[a] == 1 && G.bck[2 * a] == BC_EMPTY) continue;
+    for (int s = 0; s < 2; s++) {
+      const double so = s ? 1.0 : -1.0;
+      const int f = face_of(G, P, a, s);
+      const bool bnd = on_boundary(G, P, a, s);
+      outL += so * low_order_flux(G, alpha, F, P, a, s, f, bnd);
+      if (!bnd) {
+        double an = alpha[P.c + (s ? 1 : -1) * stride_of(G, a)];
+        amax = fmax(amax, an);
+        amin = fmin(amin, an);
+      } else if (so * F[f] < 0.0) {
+        double ab = bnd_alpha(G, 2 * a + s, aP, F[f]);
+        amax = fmax(amax, ab);
+        amin = fmin(amin, ab);
+      }
+      const double Af = A[f];
+      pin += fmax(0.0, -so * Af);
+      pout += fmax(0.0, so * Af);
+    }
+  }
+  amax = fmin(1.0, amax);
+  amin = fmax(0.0, amin);
+  const double vol = phi[P.c] * G.V / G.dt;
+  const double aL = aP - outL / vol;
+  Qp[P.c] = vol * fmax(0.0, amax - aL);
+  Qm[P.c] = vol * fmax(0.0, aL - amin);
+  Pin[P.c] = pin;
+  Pout[P.c] = pout;
+}
+
+__global__ void __launch_bounds__(NTHREADS) k_alpha_R(
+    Geom G, const double *__restrict__ A, const double *__restrict__ lam, int first,
+    const double *__restrict__ Qp, const double *__restrict__ Qm, const double *__restrict__ Pin,
+    const double *__restrict__ Pout, double *__restrict__ Rp, double *__restrict__ Rm) {
+  Cell P;
+  if (!cell_from_thread(G, P)) return;
+  double lout = 0.0, lin = 0.0;
+  for (int a = 0; a < 3; a++) {
+    if (G.n[a] == 1 && G.bck[2 * a] == BC_EMPTY) continue;
+    for (int s = 0; s < 2; s++) {
+      if (on_boundary(G, P, a, s)) continue;  // A = 0 on boundary faces
+      const double so = s ? 1.0 : -1.0;
+      const int f = face_of(G, P, a, s);
+      const double l = first ? 1.0 : lam[f];
+      const double Af = A[f];
+      lout += l * fmax(0.0, so * Af);
+      lin += l * fmax(0.0, -so * Af);
+    }
+  }
+  const double pin = Pin[P.c], pout = Pout[P.c];
+  Rp[P.c] = pin > 0.0 ? clamp01((Qp[P.c] + lout) / pin, 0.0, 1.0) : 1.0;
+  Rm[P.c] = pout > 0.0 ? clamp01((Qm[P.c] + lin) / pout, 0.0, 1.0) : 1.0;
+}
+
+__global__ void __launch_bounds__(NTHREADS) k_alpha_lambda(Geom G, const double *__restrict__ A,
+                                                           const double *__restrict__ Rp,
+                                                           const double *__restrict__ Rm,
+                                                           int first, double *__restrict__ lam) {
+  Cell P;
+  if (!cell_from_thread(G, P)) return;
+  for (int a = 0; a < 3; a++) {
+    const int f = face_of(G, P, a, 0);
+    if (on_boundary(G, P, a, 0)) {
+      lam[f] = 0.0;
+    } else {
+      const int o = P.c - stride_of(G, a), n = P.c;
+      const double l = A[f] >= 0.0 ? fmin(Rm[o], Rp[n]) : fmin(Rp[o], Rm[n]);
+      lam[f] = first ? l : fmin(lam[f], l);
+    }
+    if (P.co[a] == G.n[a] - 1) lam[face_of(G, P, a, 1)] = 0.0;
+  }
+}
+
+__global__ void __launch_bounds__(NTHREADS) k_alpha_update(
+    Geom G, Phys Ph, const double *__restrict__ alpha, const double *__restrict__ F,
+    const double *__restrict__ phi, const double *__restrict__ kinv, const double *__restrict__ A,
+    const double *__restrict__ lam, double *__restrict__ alpha_new, double *__restrict__ rhoPhi,
+    double *__restrict__ ml, double *__restrict__ mg, double *__restrict__ pc) {
+  Cell P;
+  if (!cell_from_thread(G, P)) return;
+  double out = 0.0;
+  const double drho = Ph.rho_l - Ph.rho_g;
+  for (int a = 0; a < 3; a++) {
+    const bool empty = G.n[a] == 1 && G.bck[2 * a] == BC_EMPTY;
+    for (int s = 0; s < 2; s++) {
+      const int f = face_of(G, P, a, s);
+      if (empty) {
+        if (s == 0 || P.co[a] == G.n[a] - 1) rhoPhi[f] = 0.0;
+        continue;
+      }
+      const bool bnd = on_boundary(G, P, a, s);
+      const double FL = low_order_flux(G, alpha, F, P, a, s, f, bnd);
+      const double ap = bnd ? FL : fma(lam[f], A[f], FL);
+      out += s ? ap : -ap;
+      if (s == 0 || bnd) rhoPhi[f] = drho * ap + Ph.rho_g * F[f];
+    }
+  }
+  const double an = alpha[P.c] - G.dt * out / (phi[P.c] * G.V);
+  alpha_new[P.c] = an;
+  double l, g, p;
+  closures(Ph, an, l, g, p);
+  ml[P.c] = l;
+  mg[P.c] = g;
+  pc[P.c] = kinv[P.c] > 0.0 ? p : 0.0;
+}
+
+__global__ void __launch_bounds__(NTHREADS) k_closures(Geom G, Phys Ph,
+                                                       const double *__restrict__ alpha,
+                                                       const double *__restrict__ kinv,
+                                                       double *__restrict__ ml,
+                                                       double *__restrict__ mg,
+                                                       double *__restrict__ pc) {
+  Cell P;
+  if (!cell_from_thread(G, P)) return;
+  double l, g, p;
+  closures(Ph, alpha[P.c], l, g, p);
+  ml[P.c] = l;
+  mg[P.c] = g;
+  pc[P.c] = kinv[P.c] > 0.0 ? p : 0.0;
+}
+
+// F = (linearly interpolated U) . S, boundary: inlet velocity, 0 at walls,
+// the cell velocity at outlets.
+__global__ void __launch_bounds__(NTHREADS) k_init_flux(Geom G, const double *__restrict__ U,
+                                                        double *__restrict__ F) {
+  Cell P;
+  if (!cell_from_thread(G, P)) return;
+  for (int a = 0; a < 3; a++) {
+    const double *Ua = U + (size_t)a * G.nc;
+    for (int s = 0; s < 2; s++) {
+      const bool bnd = on_boundary(G, P, a, s);
+      if (s == 1 && !bnd) continue;
+      const int f = face_of(G, P, a, s);
+      double v = 0.0;
+      if (!bnd) {
+        v = 0.5 * (Ua[P.c - stride_of(G, a)] + Ua[P.c]) * G.area[a];
+      } else {
+        int kind = G.bck[2 * a + s];
+        if (kind == BC_INLET) v = G.bcU[2 * a + s][a] * G.area[a];
+        else if (kind == BC_OUTLET) v = Ua[P.c] * G.area[a];
+      }
+      F[f] = v;
+    }
+  }
+}
+
+void alpha_stage(Handle *h) {
+  const Geom &G = h->G;
+  dim3 blk(BX, BY);
+  AlphaArgs X{h->alpha, h->F, h->phi, h->kinv, h->prgh, h->ml, h->mg, h->pc};
+  DBS_LAUNCH(h, KC_ALPHA_FACE, k_alpha_face, h->grid, blk, G, h->P, X, h->A);
+  DBS_LAUNCH(h, KC_ALPHA_BOUNDS, k_alpha_bounds, h->grid, blk, G, (const double *)h->alpha,
+             (const double *)h->F, (const double *)h->phi, (const double *)h->A, h->Qp, h->Qm,
+             h->Pin, h->Pout);
+  for (int it = 0; it < h->ctl.mules_iter; it++) {
+    int first = it == 0;
+    DBS_LAUNCH(h, KC_ALPHA_LIMIT, k_alpha_R, h->grid, blk, G, (const double *)h->A,
+               (const double *)h->lam, first, (const double *)h->Qp, (const double *)h->Qm,
+               (const double *)h->Pin, (const double *)h->Pout, h->Rp, h->Rm);
+    DBS_LAUNCH(h, KC_ALPHA_LIMIT, k_alpha_lambda, h->grid, blk, G, (const double *)h->A,
+               (const double *)h->Rp, (const double *)h->Rm, first, h->lam);
+  }
+  // alpha^{n+1} goes to the spare buffer; the old one stays for rho^n
+  DBS_LAUNCH(h, KC_ALPHA_UPDATE, k_alpha_update, h->grid, blk, G, h->P,
+             (const double *)h->alpha, (const double *)h->F, (const double *)h->phi,
+             (const double *)h->kinv, (const double *)h->A, (const double *)h->lam,
+             h->alpha_old, h->rhoPhi, h->ml, h->mg, h->pc);
+  double *t = h->alpha;
+  h->alpha = h->alpha_old;
+  h->alpha_old = t;
+}
+
+void update_closures(Handle *h) {
+  dim3 blk(BX, BY);
+  DBS_LAUNCH(h, KC_MISC, k_closures, h->grid, blk, h->G, h->P, (const double *)h->alpha,
+             (const double *)h->kinv, h->ml, h->mg, h->pc);
+}
+
+void init_flux(Handle *h) {
+  dim3 blk(BX, BY);
+  DBS_LAUNCH(h, KC_MISC, k_init_flux, h->grid, blk, h->G, (const double *)h->U, h->F);
+}
+
+}  // namespace dbs

@@ -1,0 +1,370 @@
+// Momentum predictor and PISO correctors (Sec. 3.2, Eqs. (semi_discretised_bis),
+// (corrected_velocity), (pressure_predictor)) in the p_rgh = p - rho g.x form.
+//
+// Per unit volume, cell P (1/phi factors of the inertial terms kept):
+//   a_P = rho^{n+1}/(phi dt) + K + sum_f [max(out_f,0)/(phi_f phi V) + mu_f A/(h V)]
+//   a_N = max(-out_f,0)/(phi_f phi V) + mu_f A/(h V)       (upwind convection)
+//   S   = rho^n U^n/(phi dt) + div(mu grad(U)^T)|_{U^n} + boundary sources
+// with K = k0^-1 / (k_rl/mu_l + k_rg/mu_g) the Darcy drag (Sec. 2.3 summary),
+// out_f the outward mass flux rhoPhi.  Face forces
+//   q_f = [F_c,f - (g.x_f) dn(rho) - dn(p_rgh)] A_f,
+//   F_c = (f_l - alpha)[(rho_l - rho_g) g + grad p_c] - p_c grad alpha   (App. B)
+// are reconstructed to cells as R(q)_x = (q_west + q_east)/(2 A_x).
+// Neighbour coefficients are never stored: every kernel rebuilds them from
+// rhoPhi, alpha (viscosity) and phi, which costs fewer bytes than 7 arrays.
+#include "dbs_internal.h"
+
+namespace dbs {
+
+struct MomArgs {
+  const double *__restrict__ alpha;      // alpha^{n+1}
+  const double *__restrict__ alpha_old;  // alpha^n
+  const double *__restrict__ rhoPhi;
+  const double *__restrict__ phi, *__restrict__ kinv;
+  const double *__restrict__ ml, *__restrict__ mg, *__restrict__ pc;
+  const double *__restrict__ prgh;
+  const double *__restrict__ rAU;
+};
+
+__device__ __forceinline__ bool empty_axis(const Geom &G, int a) {
+  return G.n[a] == 1 && G.bck[2 * a] == BC_EMPTY;
+}
+
+__device__ __forceinline__ int nbr_of(const Geom &G, const Cell &P, int a, int s) {
+  return P.c + (s ? 1 : -1) * stride_of(G, a);
+}
+
+// f_l - alpha in porous cells, 0 in clear cells
+__device__ __forceinline__ double cap_coef(const MomArgs &M, int c) {
+  if (M.kinv[c] <= 0.0) return 0.0;
+  double l = M.ml[c], g = M.mg[c];
+  return l / (l + g) - M.alpha[c];
+}
+
+// body force per unit volume on the interior face between own (minus side)
+// and nbr (plus side) along a: F_c - (g.x_f) dn(rho)
+__device__ inline double face_body(const Geom &G, const Phys &Ph, const MomArgs &M, int own,
+                                   int nbr, int a, double gxf) {
+  const double ih = G.ih[a];
+  const double ao = M.alpha[own], an = M.alpha[nbr];
+  const double cf = 0.5 * (cap_coef(M, own) + cap_coef(M, nbr));
+  const double pco = M.pc[own], pcn = M.pc[nbr];
+  const double pcf = 0.5 * (pco + pcn);
+  const double Fcap =
+      cf * ((Ph.rho_l - Ph.rho_g) * Ph.g[a] + (pcn - pco) * ih) - pcf * (an - ao) * ih;
+  return Fcap - gxf * (rho_of(Ph, an) - rho_of(Ph, ao)) * ih;
+}
+
+// q on side s of P along a for interior and outlet faces (fixed-flux faces
+// are handled by the caller); p_rgh from `prgh`
+__device__ inline double face_force(const Geom &G, const Phys &Ph, const MomArgs &M,
+                                    const double *__restrict__ prgh, const Cell &P, int a,
+                                    int s) {
+  const double gxf = gdotx_face(G, Ph, P, a, s);
+  if (on_boundary(G, P, a, s)) {
+    // outlet: fixed static pressure, p_rgh_b = p_b - rho_P g.x_b
+    const double pb = G.bcp[2 * a + s] - rho_of(Ph, M.alpha[P.c]) * gxf;
+    const double sn = s ? (pb - prgh[P.c]) * 2.0 * G.ih[a] : (prgh[P.c] - pb) * 2.0 * G.ih[a];
+    return -sn * G.area[a];
+  }
+  const int nb = nbr_of(G, P, a, s);
+  const int own = s ? P.c : nb, nbr = s ? nb : P.c;
+  return (face_body(G, Ph, M, own, nbr, a, gxf) - (prgh[nbr] - prgh[own]) * G.ih[a]) *
+         G.area[a];
+}
+
+__device__ __forceinline__ bool fixed_flux(const Geom &G, int b) {
+  return G.bck[b] == BC_WALL || G.bck[b] == BC_INLET;
+}
+
+// R(q)_a of cell P.  hbya == nullptr: predictor (a fixed-flux face copies the
+// opposite face's force); otherwise corrector (a fixed-flux face carries the
+// p_rgh gradient that reproduces its prescribed flux).
+__device__ inline double reconstruct_axis(const Geom &G, const Phys &Ph, const MomArgs &M,
+                                          const double *__restrict__ prgh,
+                                          const double *__restrict__ hbya, const Cell &P,
+                                          int a) {
+  if (empty_axis(G, a)) return 0.0;
+  double q[2];
+  bool ff[2];
+  for (int s = 0; s < 2; s++) {
+    ff[s] = on_boundary(G, P, a, s) && fixed_flux(G, 2 * a + s);
+    if (!ff[s]) q[s] = face_force(G, Ph, M, prgh, P, a, s);
+  }
+  for (int s = 0; s < 2; s++) {
+    if (!ff[s]) continue;
+    if (hbya) {
+      const int b = 2 * a + s;
+      const double Fb = G.bck[b] == BC_INLET ? G.bcU[b][a] * G.area[a] : 0.0;
+      q[s] = (Fb - hbya[(size_t)a * G.nc + P.c] * G.area[a]) / M.rAU[P.c];
+    } else {
+      q[s] = ff[1 - s] ? 0.0 : q[1 - s];
+    }
+  }
+  return (q[0] + q[1]) / (2.0 * G.area[a]);
+}
+
+// momentum coefficient of side s of P along a
+struct FaceCoef {
+  double aN;      // neighbour coefficient (interior faces)
+  double diag;    // contribution to a_P
+  double src;     // multiplies the boundary velocity (inlet/wall sources)
+  int nb;         // neighbour cell or -1
+};
+
+__device__ inline FaceCoef mom_face(const Geom &G, const Phys &Ph, const MomArgs &M,
+                                    const Cell &P, int a, int s) {
+  FaceCoef r{0.0, 0.0, 0.0, -1};
+  const int f = face_of(G, P, a, s);
+  const double rp = M.rhoPhi[f];
+  const double out = s ? rp : -rp;
+  const double phP = M.phi[P.c];
+  if (!on_boundary(G, P, a, s)) {
+    const int nb = nbr_of(G, P, a, s);
+    const double phf = 0.5 * (phP + M.phi[nb]);
+    const double vis =
+        0.5 * (mu_of(Ph, M.alpha[P.c]) + mu_of(Ph, M.alpha[nb])) * G.area[a] * G.ih[a] * G.iV;
+    const double conv = 1.0 / (phf * phP * G.V);
+    r.diag = fmax(out, 0.0) * conv + vis;
+    r.aN = fmax(-out, 0.0) * conv + vis;
+    r.nb = nb;
+    return r;
+  }
+  const int b = 2 * a + s;
+  const double conv = 1.0 / (phP * phP * G.V);
+  const double d2 = 2.0 * G.ih[a];  // 1 / (h/2)
+  if (G.bck[b] == BC_WALL) {
+    r.diag = mu_of(Ph, M.alpha[P.c]) * G.area[a] * d2 * G.iV;
+  } else if (G.bck[b] == BC_INLET) {
+    const double vis = mu_of(Ph, G.bca[b]) * G.area[a] * d2 * G.iV;
+    if (out >= 0.0) r.diag = out * conv;
+    else r.src = -out * conv;
+    r.diag += vis;
+    r.src += vis;
+  } else if (G.bck[b] == BC_OUTLET) {
+    r.diag = out * conv;
+  }
+  return r;
+}
+
+// dU_comp/dx_axis at cell Q (Gauss; boundary: wall 0, inlet U_b, outlet U_Q)
+__device__ inline double dU(const Geom &G, const double *__restrict__ U, int Qc, const int Qco[3],
+                            int comp, int axis) {
+  if (empty_axis(G, axis)) return 0.0;
+  const double *Uc = U + (size_t)comp * G.nc;
+  const double uq = Uc[Qc];
+  double fv[2];
+  for (int s = 0; s < 2; s++) {
+    const bool bnd = s ? Qco[axis] == G.n[axis] - 1 : Qco[axis] == 0;
+    if (bnd) {
+      const int b = 2 * axis + s;
+      fv[s] = G.bck[b] == BC_WALL ? 0.0 : (G.bck[b] == BC_INLET ? G.bcU[b][comp] : uq);
+    } else {
+      fv[s] = 0.5 * (uq + Uc[Qc + (s ? 1 : -1) * stride_of(G, axis)]);
+    }
+  }
+  return (fv[1] - fv[0]) * G.ih[axis];
+}
+
+__global__ void __launch_bounds__(NTHREADS) k_mom_assemble(Geom G, Phys Ph, MomArgs M,
+                                                           const double *__restrict__ U,
+                                                           int transpose,
+                                                           double *__restrict__ rAU,
+                                                           double *__restrict__ Sh,
+                                                           double *__restrict__ B) {
+  Cell P;
+  if (!cell_from_thread(G, P)) return;
+  const int c = P.c;
+  const double phP = M.phi[c];
+  const double an = M.alpha[c];
+  const double mt = M.ml[c] + M.mg[c];
+  const double K = M.kinv[c] > 0.0 ? M.kinv[c] / mt : 0.0;
+  double aP = rho_of(Ph, an) / (phP * G.dt) + K;
+  const double rho_o = rho_of(Ph, M.alpha_old[c]);
+  double S[3];
+  for (int d = 0; d < 3; d++) S[d] = rho_o * U[(size_t)d * G.nc + c] / (phP * G.dt);
+  for (int a = 0; a < 3; a++) {
+    if (empty_axis(G, a)) continue;
+    for (int s = 0; s < 2; s++) {
+      FaceCoef fc = mom_face(G, Ph, M, P, a, s);
+      aP += fc.diag;
+      if (fc.src != 0.0) {
+        const double *Ub = G.bcU[2 * a + s];
+        for (int d = 0; d < 3; d++) S[d] += fc.src * Ub[d];
+      }
+    }
+  }
+  if (transpose) {
+    // explicit div(mu grad(U)^T): face flux mu_f A dU_a/dx_i, outward sign
+    for (int a = 0; a < 3; a++) {
+      if (empty_axis(G, a)) continue;
+      for (int s = 0; s < 2; s++) {
+        const double sg = s ? 1.0 : -1.0;
+        double muf;
+        double gN[3] = {0.0, 0.0, 0.0};
+        const bool bnd = on_boundary(G, P, a, s);
+        if (!bnd) {
+          const int nb = nbr_of(G, P, a, s);
+          int nco[3] = {P.co[0], P.co[1], P.co[2]};
+          nco[a] += s ? 1 : -1;
+          muf = 0.5 * (mu_of(Ph, an) + mu_of(Ph, M.alpha[nb]));
+          for (int i = 0; i < 3; i++) gN[i] = dU(G, U, nb, nco, a, i);
+        } else {
+          const int b = 2 * a + s;
+          muf = G.bck[b] == BC_INLET ? mu_of(Ph, G.bca[b]) : mu_of(Ph, an);
+        }
+        for (int i = 0; i < 3; i++) {
+          const double gP = dU(G, U, c, P.co, a, i);
+          const double gf = bnd ? gP : 0.5 * (gP + gN[i]);
+          S[i] += sg * muf * G.area[a] * gf * G.iV;
+        }
+      }
+    }
+  }
+  const double r = 1.0 / aP;
+  rAU[c] = r;
+  for (int d = 0; d < 3; d++) {
+    Sh[(size_t)d * G.nc + c] = S[d];
+    B[(size_t)d * G.nc + c] =
+        S[d] + reconstruct_axis(G, Ph, M, M.prgh, nullptr, P, d);
+  }
+}
+
+// Uout = rAU (sum_N a_N Uin_N + src): one Jacobi sweep (src = S + R(q)) or
+// HbyA (src = S)
+__global__ void __launch_bounds__(NTHREADS) k_mom_offdiag(Geom G, Phys Ph, MomArgs M,
+                                                          const double *__restrict__ Uin,
+                                                          const double *__restrict__ src,
+                                                          double *__restrict__ Uout) {
+  Cell P;
+  if (!cell_from_thread(G, P)) return;
+  const int c = P.c;
+  double acc[3] = {src[c], src[(size_t)G.nc + c], src[2 * (size_t)G.nc + c]};
+  for (int a = 0; a < 3; a++) {
+    if (empty_axis(G, a)) continue;
+    for (int s = 0; s < 2; s++) {
+      if (on_boundary(G, P, a, s)) continue;
+      FaceCoef fc = mom_face(G, Ph, M, P, a, s);
+      for (int d = 0; d < 3; d++) acc[d] += fc.aN * Uin[(size_t)d * G.nc + fc.nb];
+    }
+  }
+  const double r = M.rAU[c];
+  for (int d = 0; d < 3; d++) Uout[(size_t)d * G.nc + c] = r * acc[d];
+}
+
+// phiHbyA on the cell's faces and the pressure right-hand side
+// b = -sum_out phiHbyA + sum_outlet T_b p_rgh_b
+__device__ inline double phi_hbya(const Geom &G, const Phys &Ph, const MomArgs &M,
+                                  const double *__restrict__ H, const Cell &P, int a, int s) {
+  if (on_boundary(G, P, a, s)) {
+    const int b = 2 * a + s;
+    if (G.bck[b] == BC_INLET) return G.bcU[b][a] * G.area[a];
+    if (G.bck[b] == BC_OUTLET) return H[(size_t)a * G.nc + P.c] * G.area[a];
+    return 0.0;
+  }
+  const int nb = nbr_of(G, P, a, s);
+  const int own = s ? P.c : nb, nbr = s ? nb : P.c;
+  const double *Ha = H + (size_t)a * G.nc;
+  const double rAUf = 0.5 * (M.rAU[own] + M.rAU[nbr]);
+  const double gxf = gdotx_face(G, Ph, P, a, s);
+  return 0.5 * (Ha[own] + Ha[nbr]) * G.area[a] +
+         rAUf * face_body(G, Ph, M, own, nbr, a, gxf) * G.area[a];
+}
+
+__global__ void __launch_bounds__(NTHREADS) k_phihbya(Geom G, Phys Ph, MomArgs M,
+                                                      const double *__restrict__ H,
+                                                      double *__restrict__ phiH,
+                                                      double *__restrict__ rhs) {
+  Cell P;
+  if (!cell_from_thread(G, P)) return;
+  double div = 0.0, dir = 0.0;
+  for (int a = 0; a < 3; a++) {
+    const bool empty = empty_axis(G, a);
+    for (int s = 0; s < 2; s++) {
+      const int f = face_of(G, P, a, s);
+      const bool bnd = on_boundary(G, P, a, s);
+      const double v = empty ? 0.0 : phi_hbya(G, Ph, M, H, P, a, s);
+      if (s == 0 || bnd) phiH[f] = v;
+      div += s ? v : -v;
+      if (bnd && !empty && G.bck[2 * a + s] == BC_OUTLET) {
+        const double pb = G.bcp[2 * a + s] -
+                          rho_of(Ph, M.alpha[P.c]) * gdotx_face(G, Ph, P, a, s);
+        dir += M.rAU[P.c] * G.area[a] * 2.0 * G.ih[a] * pb;
+      }
+    }
+  }
+  rhs[P.c] = -div + dir;
+}
+
+// flux and velocity correction; last corrector also writes p = p_rgh + rho g.x
+__global__ void __launch_bounds__(NTHREADS) k_correct(Geom G, Phys Ph, MomArgs M,
+                                                      const double *__restrict__ H,
+                                                      const double *__restrict__ phiH,
+                                                      double *__restrict__ F,
+                                                      double *__restrict__ U,
+                                                      double *__restrict__ p, int last) {
+  Cell P;
+  if (!cell_from_thread(G, P)) return;
+  const int c = P.c;
+  const double *prgh = M.prgh;
+  for (int a = 0; a < 3; a++) {
+    for (int s = 0; s < 2; s++) {
+      const bool bnd = on_boundary(G, P, a, s);
+      if (s == 1 && !bnd) continue;
+      const int f = face_of(G, P, a, s);
+      double v = phiH[f];
+      if (!bnd) {
+        const int own = c - stride_of(G, a);
+        const double T = 0.5 * (M.rAU[own] + M.rAU[c]) * G.area[a] * G.ih[a];
+        v -= T * (prgh[c] - prgh[own]);
+      } else if (G.bck[2 * a + s] == BC_OUTLET) {
+        const double pb = G.bcp[2 * a + s] - rho_of(Ph, M.alpha[c]) * gdotx_face(G, Ph, P, a, s);
+        const double Tb = M.rAU[c] * G.area[a] * 2.0 * G.ih[a];
+        v -= s ? Tb * (pb - prgh[c]) : Tb * (prgh[c] - pb);
+      }
+      F[f] = v;
+    }
+  }
+  const double r = M.rAU[c];
+  for (int d = 0; d < 3; d++)
+    U[(size_t)d * G.nc + c] =
+        H[(size_t)d * G.nc + c] + r * reconstruct_axis(G, Ph, M, prgh, H, P, d);
+  if (last) p[c] = prgh[c] + rho_of(Ph, M.alpha[c]) * gdotx_cell(G, Ph, P);
+}
+
+static MomArgs mom_args(Handle *h) {
+  return MomArgs{h->alpha, h->alpha_old, h->rhoPhi, h->phi, h->kinv, h->ml,
+                 h->mg,    h->pc,        h->prgh,   h->rAU};
+}
+
+void momentum_predictor(Handle *h) {
+  dim3 blk(BX, BY);
+  MomArgs M = mom_args(h);
+  DBS_LAUNCH(h, KC_MOM_ASSEMBLE, k_mom_assemble, h->grid, blk, h->G, h->P, M,
+             (const double *)h->U, h->ctl.transpose_visc, h->rAU, h->Sh, h->B);
+  for (int s = 0; s < h->ctl.mom_sweeps; s++) {
+    DBS_LAUNCH(h, KC_MOM_OFFDIAG, k_mom_offdiag, h->grid, blk, h->G, h->P, M,
+               (const double *)h->U, (const double *)h->B, h->U2);
+    double *t = h->U;
+    h->U = h->U2;
+    h->U2 = t;
+  }
+}
+
+void corrector_assemble(Handle *h) {
+  dim3 blk(BX, BY);
+  MomArgs M = mom_args(h);
+  DBS_LAUNCH(h, KC_MOM_OFFDIAG, k_mom_offdiag, h->grid, blk, h->G, h->P, M,
+             (const double *)h->U, (const double *)h->Sh, h->HbyA);
+  DBS_LAUNCH(h, KC_PHIHBYA, k_phihbya, h->grid, blk, h->G, h->P, M, (const double *)h->HbyA,
+             h->phiH, h->rhs);
+}
+
+void corrector_update(Handle *h, bool last) {
+  dim3 blk(BX, BY);
+  MomArgs M = mom_args(h);
+  DBS_LAUNCH(h, KC_CORRECT, k_correct, h->grid, blk, h->G, h->P, M, (const double *)h->HbyA,
+             (const double *)h->phiH, h->F, h->U, h->p, (int)last);
+}
+
+}  // namespace dbs

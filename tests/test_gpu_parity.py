@@ -1,0 +1,178 @@
+"""GPU parity of the HIP path against the CPU oracle (run on an MI355X).
+
+Bar (FP64): relative L2 <= 1e-10 on p_rgh and U, max-abs <= 1e-10 on alpha,
+both sides solving the pressure equation to a relative residual of 1e-13 or
+tighter.  All GPU work goes through the C ABI (libdbs.so).
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle as O
+import pin_cases as PC
+from paper_2003_08374_amd import workloads as W
+from parity_util import compare_states, max_abs, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    torch.cuda.set_device(0)
+    O.build(force=False)
+
+
+def _dbs():
+    from paper_2003_08374_amd import dbs
+    return dbs
+
+
+def _run_both(case, nsteps, gpu_tol=1e-13, oracle_tol=1e-14, **kw):
+    dbs = _dbs()
+    st0 = O.initial_state(case)
+    ref, rinfo = O.step(case.replace(p_tol=oracle_tol, p_maxit=200000), st0, nsteps)
+    with dbs.Solver(case.replace(p_tol=gpu_tol), **kw) as s:
+        s.step(nsteps)
+        out = s.state()
+        stats = s.stats()
+    return out, ref, stats, rinfo
+
+
+# ------------------------------------------------------------- pressure solve
+
+
+@pytest.mark.parametrize("shape,closed", [((37, 29, 1), False), ((19, 14, 11), False),
+                                          ((16, 12, 10), True)])
+def test_pressure_solve_matches_oracle(shape, closed):
+    """PCG + GMG V-cycle vs the oracle's Jacobi-CG on the same operator:
+    ragged (odd) sizes, 2D and 3D, open and closed domains."""
+    dbs = _dbs()
+    nx, ny, nz = shape
+    c = PC.random_3d(shape, seed=5) if nz > 1 else W.layered_2d(n=4).replace(
+        shape=shape, phi=np.ones((1, ny, nx)), kinv=np.zeros((1, ny, nx)),
+        alpha=np.zeros((1, ny, nx)), U=np.zeros((3, 1, ny, nx)), p_rgh=np.zeros((1, ny, nx)))
+    if closed:
+        c = c.replace(bc=[W.wall()] * 6)
+    rng = np.random.default_rng(11)
+    n = nx * ny * nz
+    rAU = 10 ** rng.uniform(-9, -5, n)
+    b = rng.standard_normal(n) * 1e-6
+    if closed:
+        b -= b.mean()
+    xo, it_o, rr_o = O.pressure_solve(c, rAU, b, tol=1e-15)
+    with dbs.Solver(c.replace(p_tol=1e-14)) as s:
+        xg, it_g, rr_g = s.pressure_solve(rAU, b)
+    print(shape, closed, "oracle its", it_o, "gpu its", it_g, "gpu relres", rr_g)
+    assert rr_g <= 1e-14  # true residual b - A x
+    assert rel_l2(xg, xo) <= 1e-10
+    assert it_g < it_o  # the V-cycle preconditioner is doing real work
+
+
+# ----------------------------------------------------------- stage by stage
+
+
+def test_first_step_intermediates_match_oracle():
+    """One step of the 2D layered case: antidiffusive fluxes, momentum
+    diagonal and source, predicted U, HbyA, phiHbyA and the pressure RHS."""
+    dbs = _dbs()
+    case = W.layered_2d(n=24).replace(p_tol=1e-14)
+    # a state with motion everywhere: advance the oracle a few steps first
+    st, _ = O.step(case, O.initial_state(case), 3)
+    _, _, tr = O.step(case, st, 1, trace=True)
+    with dbs.Solver(case, state=st) as s:
+        g = s.trace_step()
+    for k in ("A", "rAU", "Shat", "Ustar", "HbyA", "phiHbyA", "b"):
+        e = rel_l2(g[k], tr[k])
+        print(k, e)
+        assert e <= 1e-12, (k, e)
+
+
+# ------------------------------------------------------------ full steps
+
+
+def test_layered_2d_20_steps():
+    """2D 64x64 layered porous/clear case, 20 steps (dt 1e-5)."""
+    case = W.layered_2d(n=64)
+    out, ref, st, _ = _run_both(case, 20)
+    compare_states(out, ref, label="layered_2d_64")
+    assert st["alpha_min"] >= -1e-12 and st["alpha_max"] <= 1 + 1e-12
+
+
+def test_layered_2d_stress_steps():
+    """Limiter-stress variant (Courant ~0.1): MULES branches are exercised."""
+    case = W.layered_2d_stress(n=32)
+    out, ref, st, _ = _run_both(case, 6)
+    compare_states(out, ref, tol_alpha=1e-9, tol_l2=1e-9, label="layered_2d_32_stress")
+
+
+def test_fractured_3d_small():
+    """3D fractured matrix generator at 24^3 (slab fracture), 5 steps."""
+    case = W.fractured_3d(n=24, fractures="slab", steps=5)
+    out, ref, st, _ = _run_both(case, 5)
+    compare_states(out, ref, label="fractured_3d_24")
+
+
+def test_fractured_3d_planes_ragged():
+    """Odd sizes (ragged coarsening), random planar fractures, 3 steps."""
+    case = W.fractured_3d(shape=(21, 18, 15), fractures="planes", n_frac=2, steps=3)
+    out, ref, st, _ = _run_both(case, 3)
+    compare_states(out, ref, label="fractured_3d_21x18x15")
+
+
+def test_random_3d_all_terms():
+    """Random porous/clear cells, random velocity and saturation, VG k_r and
+    BC p_c: every face type and closure branch, 1 step."""
+    case = PC.random_3d((9, 7, 6), seed=4)
+    out, ref, st, _ = _run_both(case, 1)
+    compare_states(out, ref, tol_alpha=1e-12, label="random3d")
+
+
+def test_closed_box_conservation_on_gpu():
+    nx, ny, h = 20, 20, 1e-3
+    rng = np.random.default_rng(7)
+    alpha = np.zeros((1, ny, nx))
+    alpha[:, 11:17, 5:15] = 1.0
+    alpha[:, 2:6, :] = rng.uniform(0, 1, (1, 4, nx))
+    phi = np.ones((1, ny, nx))
+    kinv = np.zeros((1, ny, nx))
+    phi[:, :9, :] = 0.4
+    kinv[:, :9, :] = 1e11
+    c = PC.closed_box_2d(nx, ny, h, W.fluids(W.WATER, W.AIR), phi=phi, kinv=kinv, alpha=alpha,
+                         dt=5e-5).replace(pc={"model": "brooks_corey", "pc0": 100.0, "exp": 0.5})
+    out, ref, st, _ = _run_both(c, 5)
+    compare_states(out, ref, tol_l2=1e-9, tol_alpha=1e-10, label="closed_box")
+    vol0 = float((phi.ravel() * alpha.ravel()).sum() * h ** 3)
+    assert st["phase_volume"] == pytest.approx(vol0, rel=1e-13)
+
+
+def test_gravity_drainage_plateau_on_gpu():
+    """Sec. 4.1.2 gravity front on the GPU path: plateau at 0.467."""
+    n, L = 100, 2.0
+    fl = W.fluids(W.WATER, PC.AIR_T1)
+    c = PC.column_1d(n, L / n, axis=1, alpha0=0.0, U_in=0.0, kinv=1e11, phi=0.5,
+                     g=(0.0, -9.81, 0.0), fl=fl, kr={"model": "brooks_corey", "m": 3.0},
+                     pc={"model": "brooks_corey", "pc0": 0.0, "exp": 0.5}, dt=20.0,
+                     bc_lo=W.outlet(0.0, 0.0), bc_hi=W.inlet((0.0, -1e-5, 0.0), 1.0))
+    dbs = _dbs()
+    with dbs.Solver(c.replace(p_tol=1e-12)) as s:
+        s.step(1500)
+        a = s.state()["alpha"]
+    assert abs(np.median(a[-40:-5]) - 0.467) < 0.01
+
+
+def test_error_paths():
+    dbs = _dbs()
+    case = W.layered_2d(n=16)
+    bad = case.replace(phi=np.zeros_like(case.phi))
+    with pytest.raises(dbs.DBSError) as e:
+        dbs.Solver(bad)
+    assert e.value.code == dbs.EINVAL
+    with dbs.Solver(case.replace(p_maxit=1, p_tol=1e-15)) as s:
+        assert s.step(2, check=False) == dbs.ENOCONV
+    with dbs.Solver(W.layered_2d_stress(n=16), max_courant=1e-9) as s:
+        s.step(1, check=False)
+        assert s.step(1, check=False) == dbs.ECOURANT
