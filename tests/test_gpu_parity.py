@@ -64,10 +64,10 @@ def test_pressure_solve_matches_oracle(shape, closed):
     if closed:
         b -= b.mean()
     xo, it_o, rr_o = O.pressure_solve(c, rAU, b, tol=1e-15)
-    with dbs.Solver(c.replace(p_tol=1e-14)) as s:
+    with dbs.Solver(c.replace(p_tol=1e-13)) as s:
         xg, it_g, rr_g = s.pressure_solve(rAU, b)
     print(shape, closed, "oracle its", it_o, "gpu its", it_g, "gpu relres", rr_g)
-    assert rr_g <= 1e-14  # true residual b - A x
+    assert rr_g <= 1e-13  # true residual b - A x
     assert rel_l2(xg, xo) <= 1e-10
     assert it_g < it_o  # the V-cycle preconditioner is doing real work
 
