@@ -69,22 +69,21 @@ __global__ void __launch_bounds__(NTHREADS) k_stats(Geom G, const double *__rest
                                                     const double *__restrict__ F,
                                                     double *__restrict__ part, int nb) {
   __shared__ double lds[5][NTHREADS / 64];
-  Cell P;
   double amin = 1e300, amax = -1e300, vol = 0.0, co = 0.0, bad = 0.0;
-  if (cell_from_thread(G, P)) {
+  FOR_CELLS(G, P) {
     const double a = alpha[P.c];
-    amin = a;
-    amax = a;
-    vol = phi[P.c] * a * G.V;
+    amin = fmin(amin, a);
+    amax = fmax(amax, a);
+    vol += phi[P.c] * a * G.V;
     double out = 0.0;
     for (int ax = 0; ax < 3; ax++) {
       const double fm = F[face_of(G, P, ax, 0)], fp = F[face_of(G, P, ax, 1)];
       out += fmax(fp, 0.0) + fmax(-fm, 0.0);
     }
-    co = G.dt * out / (phi[P.c] * G.V);
+    co = fmax(co, G.dt * out / (phi[P.c] * G.V));
     bool ok = isfinite(a) && isfinite(prgh[P.c]);
     for (int d = 0; d < 3; d++) ok = ok && isfinite(U[(size_t)d * G.nc + P.c]);
-    bad = ok ? 0.0 : 1.0;
+    bad += ok ? 0.0 : 1.0;
   }
   amin = wave_min(amin);
   amax = wave_max(amax);
@@ -103,8 +102,7 @@ __global__ void __launch_bounds__(NTHREADS) k_stats(Geom G, const double *__rest
       r[0] = fmin(r[0], lds[0][w]); r[1] = fmax(r[1], lds[1][w]); r[2] += lds[2][w];
       r[3] = fmax(r[3], lds[3][w]); r[4] += lds[4][w];
     }
-    const int bid = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
-    for (int q = 0; q < 5; q++) part[q * nb + bid] = r[q];
+    for (int q = 0; q < 5; q++) part[q * nb + blockIdx.x] = r[q];
   }
 }
 
@@ -282,8 +280,8 @@ int dbs_create(const dbs_grid *grid, const dbs_physics *phys, const dbs_bc bc[6]
     return rc;
   }
   h->stream = h->own_stream;
-  h->grid = dim3((G.n[0] + BX - 1) / BX, (G.n[1] + BY - 1) / BY, G.n[2]);
-  h->nblocks = (int)(h->grid.x * h->grid.y * h->grid.z);
+  h->nblocks = cell_blocks(G);
+  h->grid = dim3(h->nblocks);
   const size_t nc = G.nc, nf = G.nf;
   rc = DBS_OK;
   h->phi = dmalloc(h, nc, rc); h->kinv = dmalloc(h, nc, rc);
@@ -292,6 +290,7 @@ int dbs_create(const dbs_grid *grid, const dbs_physics *phys, const dbs_bc bc[6]
   h->prgh = dmalloc(h, nc, rc); h->p = dmalloc(h, nc, rc);
   h->F = dmalloc(h, nf, rc);
   h->ml = dmalloc(h, nc, rc); h->mg = dmalloc(h, nc, rc); h->pc = dmalloc(h, nc, rc);
+  h->cf = dmalloc(h, nc, rc);
   h->A = dmalloc(h, nf, rc); h->lam = dmalloc(h, nf, rc); h->rhoPhi = dmalloc(h, nf, rc);
   h->Qp = dmalloc(h, nc > 5 * (size_t)h->nblocks ? nc : 5 * (size_t)h->nblocks, rc);
   h->Qm = dmalloc(h, nc, rc); h->Pin = dmalloc(h, nc, rc); h->Pout = dmalloc(h, nc, rc);
@@ -464,6 +463,7 @@ static int one_step(Handle *h, TraceOut *tr) {
 
 static int finish_steps(Handle *h, int rc) {
   int e = hip_check(h, hipStreamSynchronize(h->stream), "step");
+  if (!e) e = hip_check(h, hipGetLastError(), "kernel launch");
   if (e) return e;
   prof_collect(h);
   double s[5];
@@ -538,6 +538,7 @@ int dbs_debug_pressure_solve(dbs_handle *H, const double *rAU, const double *b, 
   int src = pressure_solve(h, h->rAU, h->rhs, h->Rp, iters, relres);
   rc = hip_check(h, hipMemcpyAsync(x, h->Rp, nc * 8, hipMemcpyDeviceToHost, h->stream), "copy");
   if (!rc) rc = hip_check(h, hipStreamSynchronize(h->stream), "solve");
+  if (!rc) rc = hip_check(h, hipGetLastError(), "kernel launch");
   prof_collect(h);
   if (rc) return rc;
   if (src) return fail(h, src, "pressure solve did not converge");

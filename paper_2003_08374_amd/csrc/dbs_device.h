@@ -65,15 +65,36 @@ struct Cell {
   int co[3];
 };
 
-__device__ __forceinline__ bool cell_from_thread(const Geom &G, Cell &P) {
-  P.i = blockIdx.x * BX + threadIdx.x;
-  P.j = blockIdx.y * BY + threadIdx.y;
-  P.k = blockIdx.z;
-  if (P.i >= G.n[0] || P.j >= G.n[1]) return false;
+// Per-cell kernels run one cell per thread on a 1-D grid of 64x4 blocks.
+// Blocks are renumbered so that each of the 8 XCDs receives a contiguous run
+// (a slab of planes): the y and z neighbours of a tile then sit in the same
+// L2.  (Walking several planes per thread was tried: the heavy per-cell
+// kernels then hold more registers and lose occupancy.)
+__host__ __device__ inline int cell_blocks(const Geom &G) {
+  return ((G.n[0] + BX - 1) / BX) * ((G.n[1] + BY - 1) / BY) * G.n[2];
+}
+
+__device__ __forceinline__ bool cell_of_thread(const Geom &G, Cell &P) {
+  const int nbx = (G.n[0] + BX - 1) / BX, nby = (G.n[1] + BY - 1) / BY;
+  const int nb = nbx * nby * G.n[2];
+  const int b = blockIdx.x;
+  const int full = nb & ~7;
+  int L = b;
+  if (b < full) L = (b & 7) * (full >> 3) + (b >> 3);
+  const int bx = L % nbx;
+  L /= nbx;
+  P.i = bx * BX + threadIdx.x;
+  P.j = (L % nby) * BY + threadIdx.y;
+  P.k = L / nby;
   P.co[0] = P.i; P.co[1] = P.j; P.co[2] = P.k;
   P.c = cidx(G, P.i, P.j, P.k);
-  return true;
+  return P.i < G.n[0] && P.j < G.n[1];
 }
+
+// body executed for this thread's cell
+#define FOR_CELLS(G, P) \
+  Cell P;               \
+  if (cell_of_thread(G, P))
 
 // face index of side s (0 = minus, 1 = plus) of cell P along axis a
 __device__ __forceinline__ int face_of(const Geom &G, const Cell &P, int a, int s) {

@@ -56,6 +56,7 @@ struct Handle {
   double *F = nullptr;                 // faces
   // closures of the current alpha: k_rl/mu_l, k_rg/mu_g, p_c (0 in clear cells)
   double *ml = nullptr, *mg = nullptr, *pc = nullptr;
+  double *cf = nullptr;  // f_l - alpha in porous cells, 0 in clear cells
   // transport work arrays
   double *A = nullptr, *lam = nullptr, *rhoPhi = nullptr;  // faces
   double *Qp = nullptr, *Qm = nullptr, *Pin = nullptr, *Pout = nullptr, *Rp = nullptr,
@@ -68,10 +69,15 @@ struct Handle {
   double *r = nullptr, *z = nullptr, *pv = nullptr, *q = nullptr;
   float *rf = nullptr;  // FP32 residual (mixed precision)
   float *zoldf = nullptr;  // previous preconditioned residual (flexible CG)
+  float *zf2 = nullptr;    // second fine correction buffer (FP32 V-cycle)
+  double *z2 = nullptr;    // second fine correction buffer (FP64 V-cycle)
   double *partials = nullptr;  // per-block partial sums
   double *scal = nullptr;      // device scalars
   double *hscal = nullptr;     // pinned host mirror
   std::vector<Level> lv;
+  void *lvshape = nullptr;  // launch shapes per level (owned by k_pressure.hip)
+  int bottom = 0;           // first level cycled by one work-group
+  int red_blocks = 0;       // blocks of the fine-level reduction kernels
   int mg_pre = 2, mg_post = 2, coarse_sweeps = 16;
 
   dbs_stats st;

@@ -106,12 +106,12 @@ __device__ inline double face_antidiffusive(const Geom &G, const Phys &Ph, const
 
 __global__ void __launch_bounds__(NTHREADS) k_alpha_face(Geom G, Phys Ph, AlphaArgs X,
                                                          double *__restrict__ A) {
-  Cell P;
-  if (!cell_from_thread(G, P)) return;
+  FOR_CELLS(G, P) {
   for (int a = 0; a < 3; a++) {
     int f = face_of(G, P, a, 0);
     A[f] = on_boundary(G, P, a, 0) ? 0.0 : face_antidiffusive(G, Ph, X, P, a, f);
     if (P.co[a] == G.n[a] - 1) A[face_of(G, P, a, 1)] = 0.0;
+  }
   }
 }
 
@@ -130,8 +130,7 @@ __global__ void __launch_bounds__(NTHREADS) k_alpha_bounds(
     Geom G, const double *__restrict__ alpha, const double *__restrict__ F,
     const double *__restrict__ phi, const double *__restrict__ A, double *__restrict__ Qp,
     double *__restrict__ Qm, double *__restrict__ Pin, double *__restrict__ Pout) {
-  Cell P;
-  if (!cell_from_thread(G, P)) return;
+  FOR_CELLS(G, P) {
   const double aP = alpha[P.c];
   double outL = 0.0, amax = aP, amin = aP, pin = 0.0, pout = 0.0;
   for (int a = 0; a < 3; a++) {
@@ -163,14 +162,14 @@ __global__ void __launch_bounds__(NTHREADS) k_alpha_bounds(
   Qm[P.c] = vol * fmax(0.0, aL - amin);
   Pin[P.c] = pin;
   Pout[P.c] = pout;
+  }
 }
 
 __global__ void __launch_bounds__(NTHREADS) k_alpha_R(
     Geom G, const double *__restrict__ A, const double *__restrict__ lam, int first,
     const double *__restrict__ Qp, const double *__restrict__ Qm, const double *__restrict__ Pin,
     const double *__restrict__ Pout, double *__restrict__ Rp, double *__restrict__ Rm) {
-  Cell P;
-  if (!cell_from_thread(G, P)) return;
+  FOR_CELLS(G, P) {
   double lout = 0.0, lin = 0.0;
   for (int a = 0; a < 3; a++) {
     if (G.n[a] == 1 && G.bck[2 * a] == BC_EMPTY) continue;
@@ -187,14 +186,14 @@ __global__ void __launch_bounds__(NTHREADS) k_alpha_R(
   const double pin = Pin[P.c], pout = Pout[P.c];
   Rp[P.c] = pin > 0.0 ? clamp01((Qp[P.c] + lout) / pin, 0.0, 1.0) : 1.0;
   Rm[P.c] = pout > 0.0 ? clamp01((Qm[P.c] + lin) / pout, 0.0, 1.0) : 1.0;
+  }
 }
 
 __global__ void __launch_bounds__(NTHREADS) k_alpha_lambda(Geom G, const double *__restrict__ A,
                                                            const double *__restrict__ Rp,
                                                            const double *__restrict__ Rm,
                                                            int first, double *__restrict__ lam) {
-  Cell P;
-  if (!cell_from_thread(G, P)) return;
+  FOR_CELLS(G, P) {
   for (int a = 0; a < 3; a++) {
     const int f = face_of(G, P, a, 0);
     if (on_boundary(G, P, a, 0)) {
@@ -206,15 +205,16 @@ __global__ void __launch_bounds__(NTHREADS) k_alpha_lambda(Geom G, const double 
     }
     if (P.co[a] == G.n[a] - 1) lam[face_of(G, P, a, 1)] = 0.0;
   }
+  }
 }
 
 __global__ void __launch_bounds__(NTHREADS) k_alpha_update(
     Geom G, Phys Ph, const double *__restrict__ alpha, const double *__restrict__ F,
     const double *__restrict__ phi, const double *__restrict__ kinv, const double *__restrict__ A,
     const double *__restrict__ lam, double *__restrict__ alpha_new, double *__restrict__ rhoPhi,
-    double *__restrict__ ml, double *__restrict__ mg, double *__restrict__ pc) {
-  Cell P;
-  if (!cell_from_thread(G, P)) return;
+    double *__restrict__ ml, double *__restrict__ mg, double *__restrict__ pc,
+    double *__restrict__ cf) {
+  FOR_CELLS(G, P) {
   double out = 0.0;
   const double drho = Ph.rho_l - Ph.rho_g;
   for (int a = 0; a < 3; a++) {
@@ -238,7 +238,10 @@ __global__ void __launch_bounds__(NTHREADS) k_alpha_update(
   closures(Ph, an, l, g, p);
   ml[P.c] = l;
   mg[P.c] = g;
-  pc[P.c] = kinv[P.c] > 0.0 ? p : 0.0;
+  const bool porous = kinv[P.c] > 0.0;
+  pc[P.c] = porous ? p : 0.0;
+  cf[P.c] = porous ? l / (l + g) - an : 0.0;
+  }
 }
 
 __global__ void __launch_bounds__(NTHREADS) k_closures(Geom G, Phys Ph,
@@ -246,22 +249,25 @@ __global__ void __launch_bounds__(NTHREADS) k_closures(Geom G, Phys Ph,
                                                        const double *__restrict__ kinv,
                                                        double *__restrict__ ml,
                                                        double *__restrict__ mg,
-                                                       double *__restrict__ pc) {
-  Cell P;
-  if (!cell_from_thread(G, P)) return;
+                                                       double *__restrict__ pc,
+                                                       double *__restrict__ cf) {
+  FOR_CELLS(G, P) {
   double l, g, p;
-  closures(Ph, alpha[P.c], l, g, p);
+  const double a = alpha[P.c];
+  closures(Ph, a, l, g, p);
   ml[P.c] = l;
   mg[P.c] = g;
-  pc[P.c] = kinv[P.c] > 0.0 ? p : 0.0;
+  const bool porous = kinv[P.c] > 0.0;
+  pc[P.c] = porous ? p : 0.0;
+  cf[P.c] = porous ? l / (l + g) - a : 0.0;
+  }
 }
 
 // F = (linearly interpolated U) . S, boundary: inlet velocity, 0 at walls,
 // the cell velocity at outlets.
 __global__ void __launch_bounds__(NTHREADS) k_init_flux(Geom G, const double *__restrict__ U,
                                                         double *__restrict__ F) {
-  Cell P;
-  if (!cell_from_thread(G, P)) return;
+  FOR_CELLS(G, P) {
   for (int a = 0; a < 3; a++) {
     const double *Ua = U + (size_t)a * G.nc;
     for (int s = 0; s < 2; s++) {
@@ -278,6 +284,7 @@ __global__ void __launch_bounds__(NTHREADS) k_init_flux(Geom G, const double *__
       }
       F[f] = v;
     }
+  }
   }
 }
 
@@ -301,7 +308,7 @@ void alpha_stage(Handle *h) {
   DBS_LAUNCH(h, KC_ALPHA_UPDATE, k_alpha_update, h->grid, blk, G, h->P,
              (const double *)h->alpha, (const double *)h->F, (const double *)h->phi,
              (const double *)h->kinv, (const double *)h->A, (const double *)h->lam,
-             h->alpha_old, h->rhoPhi, h->ml, h->mg, h->pc);
+             h->alpha_old, h->rhoPhi, h->ml, h->mg, h->pc, h->cf);
   double *t = h->alpha;
   h->alpha = h->alpha_old;
   h->alpha_old = t;
@@ -310,7 +317,7 @@ void alpha_stage(Handle *h) {
 void update_closures(Handle *h) {
   dim3 blk(BX, BY);
   DBS_LAUNCH(h, KC_MISC, k_closures, h->grid, blk, h->G, h->P, (const double *)h->alpha,
-             (const double *)h->kinv, h->ml, h->mg, h->pc);
+             (const double *)h->kinv, h->ml, h->mg, h->pc, h->cf);
 }
 
 void init_flux(Handle *h) {

@@ -22,6 +22,7 @@ struct MomArgs {
   const double *__restrict__ rhoPhi;
   const double *__restrict__ phi, *__restrict__ kinv;
   const double *__restrict__ ml, *__restrict__ mg, *__restrict__ pc;
+  const double *__restrict__ cf;  // f_l - alpha (porous), 0 (clear)
   const double *__restrict__ prgh;
   const double *__restrict__ rAU;
 };
@@ -35,11 +36,7 @@ __device__ __forceinline__ int nbr_of(const Geom &G, const Cell &P, int a, int s
 }
 
 // f_l - alpha in porous cells, 0 in clear cells
-__device__ __forceinline__ double cap_coef(const MomArgs &M, int c) {
-  if (M.kinv[c] <= 0.0) return 0.0;
-  double l = M.ml[c], g = M.mg[c];
-  return l / (l + g) - M.alpha[c];
-}
+__device__ __forceinline__ double cap_coef(const MomArgs &M, int c) { return M.cf[c]; }
 
 // body force per unit volume on the interior face between own (minus side)
 // and nbr (plus side) along a: F_c - (g.x_f) dn(rho)
@@ -172,8 +169,7 @@ __global__ void __launch_bounds__(NTHREADS) k_mom_assemble(Geom G, Phys Ph, MomA
                                                            double *__restrict__ rAU,
                                                            double *__restrict__ Sh,
                                                            double *__restrict__ B) {
-  Cell P;
-  if (!cell_from_thread(G, P)) return;
+  FOR_CELLS(G, P) {
   const int c = P.c;
   const double phP = M.phi[c];
   const double an = M.alpha[c];
@@ -228,6 +224,7 @@ __global__ void __launch_bounds__(NTHREADS) k_mom_assemble(Geom G, Phys Ph, MomA
     B[(size_t)d * G.nc + c] =
         S[d] + reconstruct_axis(G, Ph, M, M.prgh, nullptr, P, d);
   }
+  }
 }
 
 // Uout = rAU (sum_N a_N Uin_N + src): one Jacobi sweep (src = S + R(q)) or
@@ -236,8 +233,7 @@ __global__ void __launch_bounds__(NTHREADS) k_mom_offdiag(Geom G, Phys Ph, MomAr
                                                           const double *__restrict__ Uin,
                                                           const double *__restrict__ src,
                                                           double *__restrict__ Uout) {
-  Cell P;
-  if (!cell_from_thread(G, P)) return;
+  FOR_CELLS(G, P) {
   const int c = P.c;
   double acc[3] = {src[c], src[(size_t)G.nc + c], src[2 * (size_t)G.nc + c]};
   for (int a = 0; a < 3; a++) {
@@ -250,6 +246,7 @@ __global__ void __launch_bounds__(NTHREADS) k_mom_offdiag(Geom G, Phys Ph, MomAr
   }
   const double r = M.rAU[c];
   for (int d = 0; d < 3; d++) Uout[(size_t)d * G.nc + c] = r * acc[d];
+  }
 }
 
 // phiHbyA on the cell's faces and the pressure right-hand side
@@ -275,8 +272,7 @@ __global__ void __launch_bounds__(NTHREADS) k_phihbya(Geom G, Phys Ph, MomArgs M
                                                       const double *__restrict__ H,
                                                       double *__restrict__ phiH,
                                                       double *__restrict__ rhs) {
-  Cell P;
-  if (!cell_from_thread(G, P)) return;
+  FOR_CELLS(G, P) {
   double div = 0.0, dir = 0.0;
   for (int a = 0; a < 3; a++) {
     const bool empty = empty_axis(G, a);
@@ -294,6 +290,7 @@ __global__ void __launch_bounds__(NTHREADS) k_phihbya(Geom G, Phys Ph, MomArgs M
     }
   }
   rhs[P.c] = -div + dir;
+  }
 }
 
 // flux and velocity correction; last corrector also writes p = p_rgh + rho g.x
@@ -303,8 +300,7 @@ __global__ void __launch_bounds__(NTHREADS) k_correct(Geom G, Phys Ph, MomArgs M
                                                       double *__restrict__ F,
                                                       double *__restrict__ U,
                                                       double *__restrict__ p, int last) {
-  Cell P;
-  if (!cell_from_thread(G, P)) return;
+  FOR_CELLS(G, P) {
   const int c = P.c;
   const double *prgh = M.prgh;
   for (int a = 0; a < 3; a++) {
@@ -330,11 +326,12 @@ __global__ void __launch_bounds__(NTHREADS) k_correct(Geom G, Phys Ph, MomArgs M
     U[(size_t)d * G.nc + c] =
         H[(size_t)d * G.nc + c] + r * reconstruct_axis(G, Ph, M, prgh, H, P, d);
   if (last) p[c] = prgh[c] + rho_of(Ph, M.alpha[c]) * gdotx_cell(G, Ph, P);
+  }
 }
 
 static MomArgs mom_args(Handle *h) {
   return MomArgs{h->alpha, h->alpha_old, h->rhoPhi, h->phi, h->kinv, h->ml,
-                 h->mg,    h->pc,        h->prgh,   h->rAU};
+                 h->mg,    h->pc,        h->cf,     h->prgh, h->rAU};
 }
 
 void momentum_predictor(Handle *h) {

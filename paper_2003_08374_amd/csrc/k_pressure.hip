@@ -7,18 +7,25 @@
 //
 // Hierarchy: cell-centred 2x2x2 aggregation (ceil(n/2) per axis, ragged odd
 // edges).  The fine operator is never stored: kernels rebuild T_f from rAU
-// (8 B per cell instead of 32).  Coarse operators store the +x/+y/+z face
-// coefficient of each cell, the outlet part of the diagonal and the diagonal;
-// a coarse face coefficient is half the sum of the fine ones it covers (the
-// h-doubling of a rediscretised operator).  Smoother: red-black Gauss-Seidel,
-// red then black on the way down and black then red on the way up, so the
-// V-cycle is a symmetric preconditioner.  Restriction sums the 8 children's
-// residuals (transpose of piecewise-constant prolongation).
+// (one array instead of four).  Coarse operators store the +x/+y/+z face
+// coefficient of each cell and the diagonal; a coarse face coefficient is
+// half the sum of the fine ones it covers (the h-doubling of a rediscretised
+// operator).  Smoother: red-black Gauss-Seidel, red then black on the way
+// down and black then red on the way up, so the V-cycle is a symmetric
+// preconditioner.  Restriction sums the 8 children's residuals (transpose of
+// piecewise-constant prolongation).  Levels of at most BOTTOM_CELLS cells are
+// cycled by one work-group in a single launch.
 //
 // Mixed precision (DBS_MIXED): the V-cycle runs in FP32 (rAU, coefficients,
 // residual, correction); the CG vectors, dot products and the convergence
 // test stay FP64; CG becomes flexible (Polak-Ribiere beta) and the true FP64
 // residual b - A x replaces the recursive one every few iterations.
+//
+// Launch shape: 1-D grids of 64x4 work-groups; each thread walks KZ planes
+// of one (x, y) column.  Smoothers give each thread a pair of x-adjacent
+// cells, one of each colour, so no lane idles in a half sweep.  Blocks are
+// renumbered so that each of the 8 XCDs receives a contiguous run of blocks
+// (a z-slab), keeping the y and z neighbours of a tile in the same L2.
 //
 // Reductions are deterministic: each block writes one partial sum, a single
 // block adds the partials in a fixed order.
@@ -30,151 +37,273 @@ namespace dbs {
 
 enum { S_RZ = 0, S_PQ, S_RR, S_ALPHA, S_BETA, S_RZNEW, S_RZOLD, S_BB, S_SUM, S_NSCAL };
 
-__device__ __forceinline__ bool red(int i, int j, int k) { return ((i + j + k) & 1) == 0; }
+constexpr int KZ = 8;              // planes per thread column
+constexpr int BOTTOM_LDS = 144000;  // bytes of LDS for the single work-group bottom
+constexpr int MAXLV = 16;
 
-// ----------------------------------------------------------- fine level (0)
+// ------------------------------------------------------------ launch shape
 
-template <typename R>
-struct Row0 {
-  R D, T[6];
-  int nb[6];
+struct ZG {
+  int nbx, nby, nbz;  // blocks per axis
+  int kz;             // planes per thread
+  int pair;           // 1: two x-cells per thread
 };
 
-// row of the fine operator, rebuilt from rAU
-template <typename R>
-__device__ __forceinline__ void row0(const Geom &G, const R *__restrict__ rAU, const Cell &P,
-                                     Row0<R> &w) {
-  const R rP = rAU[P.c];
-  R D = 0;
-  for (int a = 0; a < 3; a++) {
-    const R ca = (R)(G.area[a] * G.ih[a]);
-    for (int s = 0; s < 2; s++) {
-      const int q = 2 * a + s;
-      if (on_boundary(G, P, a, s)) {
-        w.nb[q] = -1;
-        w.T[q] = 0;
-        if (G.bck[q] == BC_OUTLET) D += rP * ca * (R)2;
-      } else {
-        const int nb = P.c + (s ? 1 : -1) * stride_of(G, a);
-        w.nb[q] = nb;
-        w.T[q] = (R)0.5 * (rP + rAU[nb]) * ca;
-        D += w.T[q];
-      }
-    }
-  }
-  w.D = D;
+__host__ __device__ inline int zg_blocks(const ZG &z) { return z.nbx * z.nby * z.nbz; }
+
+// planes per thread: as many as KZ while the launch keeps >= MIN_BLOCKS blocks
+constexpr int MIN_BLOCKS = 2048;
+static ZG make_zg(int n0, int n1, int n2, bool pair) {
+  ZG z;
+  const int cx = pair ? 2 * BX : BX;
+  z.nbx = (n0 + cx - 1) / cx;
+  z.nby = (n1 + BY - 1) / BY;
+  z.kz = 1;
+  while (z.kz < KZ && (long long)z.nbx * z.nby * ((n2 + 2 * z.kz - 1) / (2 * z.kz)) >= MIN_BLOCKS)
+    z.kz *= 2;
+  z.nbz = (n2 + z.kz - 1) / z.kz;
+  z.pair = pair;
+  return z;
 }
 
+// column owned by this thread: x index (first of the pair), y index, plane range
+__device__ __forceinline__ bool column(const ZG &z, int n0, int n1, int n2, int &i, int &j,
+                                       int &k0, int &k1) {
+  const int nb = zg_blocks(z);
+  const int b = blockIdx.x;
+  const int full = nb & ~7;
+  int L = b;
+  if (b < full) L = (b & 7) * (full >> 3) + (b >> 3);  // XCD-contiguous runs
+  const int bx = L % z.nbx;
+  L /= z.nbx;
+  const int by = L % z.nby;
+  const int bz = L / z.nby;
+  i = (bx * BX + threadIdx.x) * (z.pair ? 2 : 1);
+  j = by * BY + threadIdx.y;
+  k0 = bz * z.kz;
+  k1 = min(k0 + z.kz, n2);
+  return i < n0 && j < n1;
+}
+
+// ------------------------------------------------------------------ operator
+
+template <typename R>
+struct Op {
+  int n0, n1, n2;
+  int matfree;           // 1: coefficients rebuilt from rAU (fine level)
+  const R *rAU;
+  R c[3];                // area / h per axis
+  R ob[6];               // outlet diagonal factor per domain face (2 c or 0)
+  const R *Tx, *Ty, *Tz, *D;  // stored operator (coarse levels)
+};
+
+// diagonal and the six neighbour coefficients of cell (i,j,k); neighbour
+// order -x,+x,-y,+y,-z,+z; 0 where there is no neighbour
+template <typename R>
+__device__ __forceinline__ void op_row(const Op<R> &L, int i, int j, int k, int c, R &D,
+                                       R T[6]) {
+  const int sy = L.n0, sz = L.n0 * L.n1;
+  if (L.matfree) {
+    const R r = L.rAU[c];
+    const R h = (R)0.5;
+    T[0] = i > 0 ? h * (r + L.rAU[c - 1]) * L.c[0] : (R)0;
+    T[1] = i + 1 < L.n0 ? h * (r + L.rAU[c + 1]) * L.c[0] : (R)0;
+    T[2] = j > 0 ? h * (r + L.rAU[c - sy]) * L.c[1] : (R)0;
+    T[3] = j + 1 < L.n1 ? h * (r + L.rAU[c + sy]) * L.c[1] : (R)0;
+    T[4] = k > 0 ? h * (r + L.rAU[c - sz]) * L.c[2] : (R)0;
+    T[5] = k + 1 < L.n2 ? h * (r + L.rAU[c + sz]) * L.c[2] : (R)0;
+    R db = (i == 0 ? L.ob[0] : (R)0) + (i + 1 == L.n0 ? L.ob[1] : (R)0) +
+           (j == 0 ? L.ob[2] : (R)0) + (j + 1 == L.n1 ? L.ob[3] : (R)0) +
+           (k == 0 ? L.ob[4] : (R)0) + (k + 1 == L.n2 ? L.ob[5] : (R)0);
+    D = T[0] + T[1] + T[2] + T[3] + T[4] + T[5] + r * db;
+  } else {
+    T[0] = i > 0 ? L.Tx[c - 1] : (R)0;
+    T[1] = i + 1 < L.n0 ? L.Tx[c] : (R)0;
+    T[2] = j > 0 ? L.Ty[c - sy] : (R)0;
+    T[3] = j + 1 < L.n1 ? L.Ty[c] : (R)0;
+    T[4] = k > 0 ? L.Tz[c - sz] : (R)0;
+    T[5] = k + 1 < L.n2 ? L.Tz[c] : (R)0;
+    D = L.D[c];
+  }
+}
+
+// outlet (Dirichlet) part of the fine-level diagonal
+template <typename R>
+__device__ __forceinline__ R op_outlet(const Op<R> &L, int i, int j, int k, int c) {
+  const R db = (i == 0 ? L.ob[0] : (R)0) + (i + 1 == L.n0 ? L.ob[1] : (R)0) +
+               (j == 0 ? L.ob[2] : (R)0) + (j + 1 == L.n1 ? L.ob[3] : (R)0) +
+               (k == 0 ? L.ob[4] : (R)0) + (k + 1 == L.n2 ? L.ob[5] : (R)0);
+  return L.rAU[c] * db;
+}
+
+// sum of T_N x_N; a zero coefficient marks a missing neighbour
 template <typename R, typename X>
-__device__ __forceinline__ R offsum(const Row0<R> &w, const X *__restrict__ x) {
+__device__ __forceinline__ R op_off(const Op<R> &L, int c, const R T[6],
+                                    const X *__restrict__ x) {
+  const int sy = L.n0, sz = L.n0 * L.n1;
   R s = 0;
-  for (int q = 0; q < 6; q++)
-    if (w.nb[q] >= 0) s += w.T[q] * (R)x[w.nb[q]];
+  if (T[0] != (R)0) s += T[0] * (R)x[c - 1];
+  if (T[1] != (R)0) s += T[1] * (R)x[c + 1];
+  if (T[2] != (R)0) s += T[2] * (R)x[c - sy];
+  if (T[3] != (R)0) s += T[3] * (R)x[c + sy];
+  if (T[4] != (R)0) s += T[4] * (R)x[c - sz];
+  if (T[5] != (R)0) s += T[5] * (R)x[c + sz];
   return s;
 }
 
-// q = A p, partial sum of p.q
-__global__ void __launch_bounds__(NTHREADS) k_spmv0_dot(Geom G, const double *__restrict__ rAU,
-                                                        const double *__restrict__ p,
-                                                        double *__restrict__ q,
-                                                        double *__restrict__ partials) {
-  __shared__ double lds[NTHREADS / 64];
-  Cell P;
-  double v = 0.0;
-  if (cell_from_thread(G, P)) {
-    Row0<double> w;
-    row0(G, rAU, P, w);
-    const double pp = p[P.c];
-    const double y = w.D * pp - offsum(w, p);
-    q[P.c] = y;
-    v = pp * y;
-  }
+__device__ __forceinline__ void put_partial(double v, double *lds, double *partials, int slot0) {
   double s = block_sum(v, lds);
-  if (threadIdx.x == 0 && threadIdx.y == 0)
-    partials[blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z)] = s;
+  if (threadIdx.x == 0 && threadIdx.y == 0) partials[slot0 + blockIdx.x] = s;
 }
 
-// r = b - A x, partial sum of r.r and of b.b
-__global__ void __launch_bounds__(NTHREADS) k_resid0(Geom G, const double *__restrict__ rAU,
-                                                     const double *__restrict__ b,
-                                                     const double *__restrict__ x,
-                                                     double *__restrict__ r,
-                                                     double *__restrict__ partials, int nb2) {
+// ------------------------------------------------------------- CG kernels
+
+// q = A p, partial sum of p.q
+__global__ void __launch_bounds__(NTHREADS) k_spmv_dot(Op<double> L, ZG z,
+                                                       const double *__restrict__ p,
+                                                       double *__restrict__ q,
+                                                       double *__restrict__ partials) {
   __shared__ double lds[NTHREADS / 64];
-  Cell P;
-  double v = 0.0, vb = 0.0;
-  if (cell_from_thread(G, P)) {
-    Row0<double> w;
-    row0(G, rAU, P, w);
-    const double rr = b[P.c] - (w.D * x[P.c] - offsum(w, x));
-    r[P.c] = rr;
-    v = rr * rr;
-    vb = b[P.c] * b[P.c];
+  int i, j, k0, k1;
+  double v = 0.0;
+  if (column(z, L.n0, L.n1, L.n2, i, j, k0, k1)) {
+    int c = i + L.n0 * (j + L.n1 * k0);
+    for (int k = k0; k < k1; k++, c += L.n0 * L.n1) {
+      double D, T[6];
+      op_row(L, i, j, k, c, D, T);
+      const double pp = p[c];
+      const double y = D * pp - op_off(L, c, T, p);
+      q[c] = y;
+      v += pp * y;
+    }
   }
-  const int bid = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
-  double s = block_sum(v, lds);
-  if (threadIdx.x == 0 && threadIdx.y == 0) partials[bid] = s;
+  put_partial(v, lds, partials, 0);
+}
+
+// r = b - A x, partial sums of r.r and b.b
+__global__ void __launch_bounds__(NTHREADS) k_resid_dot(Op<double> L, ZG z,
+                                                        const double *__restrict__ b,
+                                                        const double *__restrict__ x,
+                                                        double *__restrict__ r,
+                                                        double *__restrict__ partials) {
+  __shared__ double lds[NTHREADS / 64];
+  int i, j, k0, k1;
+  double v = 0.0, vb = 0.0;
+  if (column(z, L.n0, L.n1, L.n2, i, j, k0, k1)) {
+    int c = i + L.n0 * (j + L.n1 * k0);
+    for (int k = k0; k < k1; k++, c += L.n0 * L.n1) {
+      double D, T[6];
+      op_row(L, i, j, k, c, D, T);
+      const double bb = b[c];
+      const double rr = bb - (D * x[c] - op_off(L, c, T, x));
+      r[c] = rr;
+      v += rr * rr;
+      vb += bb * bb;
+    }
+  }
+  put_partial(v, lds, partials, 0);
   __syncthreads();
-  s = block_sum(vb, lds);
-  if (threadIdx.x == 0 && threadIdx.y == 0) partials[nb2 + bid] = s;
+  put_partial(vb, lds, partials, zg_blocks(z));
 }
 
 // x += alpha p, r -= alpha q, partial sum of r.r
-__global__ void __launch_bounds__(NTHREADS) k_axpy_dot(Geom G, const double *__restrict__ scal,
+__global__ void __launch_bounds__(NTHREADS) k_axpy_dot(int n0, int n1, int n2, ZG z,
+                                                       const double *__restrict__ scal,
                                                        const double *__restrict__ p,
                                                        const double *__restrict__ q,
                                                        double *__restrict__ x,
                                                        double *__restrict__ r,
                                                        double *__restrict__ partials) {
   __shared__ double lds[NTHREADS / 64];
-  Cell P;
+  int i, j, k0, k1;
   double v = 0.0;
-  if (cell_from_thread(G, P)) {
+  if (column(z, n0, n1, n2, i, j, k0, k1)) {
     const double al = scal[S_ALPHA];
-    x[P.c] = fma(al, p[P.c], x[P.c]);
-    const double rr = fma(-al, q[P.c], r[P.c]);
-    r[P.c] = rr;
-    v = rr * rr;
+    int c = i + n0 * (j + n1 * k0);
+    for (int k = k0; k < k1; k++, c += n0 * n1) {
+      x[c] = fma(al, p[c], x[c]);
+      const double rr = fma(-al, q[c], r[c]);
+      r[c] = rr;
+      v += rr * rr;
+    }
   }
-  double s = block_sum(v, lds);
-  if (threadIdx.x == 0 && threadIdx.y == 0)
-    partials[blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z)] = s;
+  put_partial(v, lds, partials, 0);
 }
 
-// partial sums of r.z and (flexible) r.zold
+// partial sums of a.z and (flexible) a.zold
 template <typename Z>
-__global__ void __launch_bounds__(NTHREADS) k_dot_rz(Geom G, const double *__restrict__ r,
-                                                     const Z *__restrict__ z,
-                                                     const Z *__restrict__ zold,
-                                                     double *__restrict__ partials, int nb2) {
+__global__ void __launch_bounds__(NTHREADS) k_dot2(int n0, int n1, int n2, ZG z,
+                                                   const double *__restrict__ a,
+                                                   const Z *__restrict__ zz,
+                                                   const Z *__restrict__ zold,
+                                                   double *__restrict__ partials) {
   __shared__ double lds[NTHREADS / 64];
-  Cell P;
+  int i, j, k0, k1;
   double v = 0.0, vo = 0.0;
-  if (cell_from_thread(G, P)) {
-    v = r[P.c] * (double)z[P.c];
-    if (zold) vo = r[P.c] * (double)zold[P.c];
+  if (column(z, n0, n1, n2, i, j, k0, k1)) {
+    int c = i + n0 * (j + n1 * k0);
+    for (int k = k0; k < k1; k++, c += n0 * n1) {
+      const double ac = a[c];
+      v += ac * (double)zz[c];
+      if (zold) vo += ac * (double)zold[c];
+    }
   }
-  const int bid = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
-  double s = block_sum(v, lds);
-  if (threadIdx.x == 0 && threadIdx.y == 0) partials[bid] = s;
+  put_partial(v, lds, partials, 0);
   if (zold) {
     __syncthreads();
-    s = block_sum(vo, lds);
-    if (threadIdx.x == 0 && threadIdx.y == 0) partials[nb2 + bid] = s;
+    put_partial(vo, lds, partials, zg_blocks(z));
   }
 }
 
 // p = z + beta p (first: p = z); flexible CG keeps zold = z
 template <typename Z>
-__global__ void __launch_bounds__(NTHREADS) k_xpby(Geom G, const double *__restrict__ scal,
-                                                   const Z *__restrict__ z,
+__global__ void __launch_bounds__(NTHREADS) k_xpby(int n0, int n1, int n2, ZG z,
+                                                   const double *__restrict__ scal,
+                                                   const Z *__restrict__ zz,
                                                    double *__restrict__ p, int first,
                                                    Z *__restrict__ zold) {
-  Cell P;
-  if (!cell_from_thread(G, P)) return;
-  const double zz = (double)z[P.c];
-  p[P.c] = first ? zz : fma(scal[S_BETA], p[P.c], zz);
-  if (zold) zold[P.c] = z[P.c];
+  int i, j, k0, k1;
+  if (!column(z, n0, n1, n2, i, j, k0, k1)) return;
+  const double be = first ? 0.0 : scal[S_BETA];
+  int c = i + n0 * (j + n1 * k0);
+  for (int k = k0; k < k1; k++, c += n0 * n1) {
+    const Z zc = zz[c];
+    p[c] = first ? (double)zc : fma(be, p[c], (double)zc);
+    if (zold) zold[c] = zc;
+  }
+}
+
+template <typename R>
+__global__ void __launch_bounds__(NTHREADS) k_cast(int n0, int n1, int n2, ZG z,
+                                                   const double *__restrict__ in,
+                                                   R *__restrict__ out) {
+  int i, j, k0, k1;
+  if (!column(z, n0, n1, n2, i, j, k0, k1)) return;
+  int c = i + n0 * (j + n1 * k0);
+  for (int k = k0; k < k1; k++, c += n0 * n1) out[c] = (R)in[c];
+}
+
+__global__ void __launch_bounds__(NTHREADS) k_sum(int n0, int n1, int n2, ZG z,
+                                                  const double *__restrict__ x,
+                                                  double *__restrict__ partials) {
+  __shared__ double lds[NTHREADS / 64];
+  int i, j, k0, k1;
+  double v = 0.0;
+  if (column(z, n0, n1, n2, i, j, k0, k1)) {
+    int c = i + n0 * (j + n1 * k0);
+    for (int k = k0; k < k1; k++, c += n0 * n1) v += x[c];
+  }
+  put_partial(v, lds, partials, 0);
+}
+
+__global__ void __launch_bounds__(NTHREADS) k_sub_mean(int n0, int n1, int n2, ZG z,
+                                                       const double *__restrict__ scal,
+                                                       double *__restrict__ x) {
+  int i, j, k0, k1;
+  if (!column(z, n0, n1, n2, i, j, k0, k1)) return;
+  const double m = scal[S_SUM] / ((double)n0 * n1 * n2);
+  int c = i + n0 * (j + n1 * k0);
+  for (int k = k0; k < k1; k++, c += n0 * n1) x[c] -= m;
 }
 
 enum { FIN_STORE = 0, FIN_ALPHA = 1, FIN_BETA = 2, FIN_BETA_FLEX = 3 };
@@ -186,16 +315,24 @@ __global__ void __launch_bounds__(1024) k_finalize(const double *__restrict__ pa
                                                    int slot2, int op) {
   __shared__ double lds[16];
   const int t = threadIdx.x;
-  for (int h = 0; h < (two ? 2 : 1); h++) {
-    double v = 0.0;
-    for (int i = t; i < n; i += 1024) v += partials[h * n + i];
+  for (int hh = 0; hh < (two ? 2 : 1); hh++) {
+    double v0 = 0.0, v1 = 0.0, v2 = 0.0, v3 = 0.0;
+    int i = t;
+    for (; i + 3 * 1024 < n; i += 4 * 1024) {
+      v0 += partials[hh * n + i];
+      v1 += partials[hh * n + i + 1024];
+      v2 += partials[hh * n + i + 2048];
+      v3 += partials[hh * n + i + 3072];
+    }
+    for (; i < n; i += 1024) v0 += partials[hh * n + i];
+    double v = (v0 + v1) + (v2 + v3);
     v = wave_sum(v);
     if ((t & 63) == 0) lds[t >> 6] = v;
     __syncthreads();
     if (t == 0) {
       double s = 0.0;
       for (int w = 0; w < 16; w++) s += lds[w];
-      scal[h ? slot2 : slot] = s;
+      scal[hh ? slot2 : slot] = s;
     }
     __syncthreads();
   }
@@ -211,271 +348,604 @@ __global__ void __launch_bounds__(1024) k_finalize(const double *__restrict__ pa
   }
 }
 
-// partial sums of x (mean removal in closed domains)
-__global__ void __launch_bounds__(NTHREADS) k_sum(Geom G, const double *__restrict__ x,
-                                                  double *__restrict__ partials) {
-  __shared__ double lds[NTHREADS / 64];
-  Cell P;
-  double v = 0.0;
-  if (cell_from_thread(G, P)) v = x[P.c];
-  double s = block_sum(v, lds);
-  if (threadIdx.x == 0 && threadIdx.y == 0)
-    partials[blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z)] = s;
-}
+// ------------------------------------------------------ multigrid kernels
 
-__global__ void __launch_bounds__(NTHREADS) k_sub_mean(Geom G, const double *__restrict__ scal,
-                                                       double *__restrict__ x) {
-  Cell P;
-  if (!cell_from_thread(G, P)) return;
-  x[P.c] -= scal[S_SUM] / (double)G.nc;
-}
-
-template <typename R>
-__global__ void __launch_bounds__(NTHREADS) k_cast(Geom G, const double *__restrict__ in,
-                                                   R *__restrict__ out) {
-  Cell P;
-  if (!cell_from_thread(G, P)) return;
-  out[P.c] = (R)in[P.c];
-}
-
-// red-black Gauss-Seidel half sweep on the fine level; zero_init: x = b/D on
-// this colour and 0 on the other (first half sweep from a zero guess)
+// red-black Gauss-Seidel half sweep of colour `color` (0 = red: i+j+k even).
+// Each thread owns the x-pair (i, i+1) and updates the one of this colour in
+// every plane.  zero_init: x = b/D on this colour and 0 on the other.
 template <typename R, typename B>
-__global__ void __launch_bounds__(NTHREADS) k_smooth0(Geom G, const R *__restrict__ rAU,
-                                                      const B *__restrict__ b,
-                                                      R *__restrict__ x, int color,
-                                                      int zero_init) {
-  Cell P;
-  if (!cell_from_thread(G, P)) return;
-  const bool mine = red(P.i, P.j, P.k) == (color == 0);
-  if (zero_init) {
-    if (!mine) { x[P.c] = 0; return; }
-    Row0<R> w;
-    row0(G, rAU, P, w);
-    x[P.c] = w.D > 0 ? (R)b[P.c] / w.D : (R)0;
-    return;
+__global__ void __launch_bounds__(NTHREADS) k_smooth(Op<R> L, ZG z, const B *__restrict__ b,
+                                                     R *__restrict__ x, int color,
+                                                     int zero_init) {
+  int i0, j, k0, k1;
+  if (!column(z, L.n0, L.n1, L.n2, i0, j, k0, k1)) return;
+  const int sz = L.n0 * L.n1;
+  int base = i0 + L.n0 * (j + L.n1 * k0);
+  for (int k = k0; k < k1; k++, base += sz) {
+    const int off = ((j + k) & 1) == color ? 0 : 1;  // i0 is even
+    const int i = i0 + off;
+    if (zero_init && i0 + 1 - off < L.n0) x[base + 1 - off] = (R)0;
+    if (i >= L.n0) continue;
+    const int c = base + off;
+    R D, T[6];
+    op_row(L, i, j, k, c, D, T);
+    if (zero_init)
+      x[c] = D > (R)0 ? (R)b[c] / D : (R)0;
+    else
+      x[c] = D > (R)0 ? ((R)b[c] + op_off(L, c, T, x)) / D : (R)0;
   }
-  if (!mine) return;
-  Row0<R> w;
-  row0(G, rAU, P, w);
-  x[P.c] = w.D > 0 ? ((R)b[P.c] + offsum(w, x)) / w.D : (R)0;
 }
 
 // coarse right-hand side: sum over the 8 children of the fine residual
 template <typename R, typename B>
-__global__ void __launch_bounds__(NTHREADS) k_restrict0(Geom G, int cn0, int cn1, int cn2,
-                                                        const R *__restrict__ rAU,
-                                                        const B *__restrict__ b,
-                                                        const R *__restrict__ x,
-                                                        R *__restrict__ bc) {
-  const int I = blockIdx.x * BX + threadIdx.x, J = blockIdx.y * BY + threadIdx.y,
-            K = blockIdx.z;
-  if (I >= cn0 || J >= cn1) return;
-  R s = 0;
-  for (int dk = 0; dk < 2; dk++)
-    for (int dj = 0; dj < 2; dj++)
-      for (int di = 0; di < 2; di++) {
-        Cell P;
-        P.i = 2 * I + di; P.j = 2 * J + dj; P.k = 2 * K + dk;
-        if (P.i >= G.n[0] || P.j >= G.n[1] || P.k >= G.n[2]) continue;
-        P.co[0] = P.i; P.co[1] = P.j; P.co[2] = P.k;
-        P.c = cidx(G, P.i, P.j, P.k);
-        Row0<R> w;
-        row0(G, rAU, P, w);
-        s += (R)b[P.c] - (w.D * x[P.c] - offsum(w, x));
+__global__ void __launch_bounds__(NTHREADS) k_restrict(Op<R> L, ZG zc, int cn0, int cn1, int cn2,
+                                                       const B *__restrict__ b,
+                                                       const R *__restrict__ x,
+                                                       R *__restrict__ bc) {
+  int I, J, K0, K1;
+  if (!column(zc, cn0, cn1, cn2, I, J, K0, K1)) return;
+  for (int K = K0; K < K1; K++) {
+    R s = 0;
+    for (int dk = 0; dk < 2; dk++) {
+      const int k = 2 * K + dk;
+      if (k >= L.n2) continue;
+      for (int dj = 0; dj < 2; dj++) {
+        const int j = 2 * J + dj;
+        if (j >= L.n1) continue;
+        for (int di = 0; di < 2; di++) {
+          const int i = 2 * I + di;
+          if (i >= L.n0) continue;
+          const int c = i + L.n0 * (j + L.n1 * k);
+          R D, T[6];
+          op_row(L, i, j, k, c, D, T);
+          s += (R)b[c] - (D * x[c] - op_off(L, c, T, x));
+        }
       }
-  bc[I + cn0 * (J + cn1 * K)] = s;
-}
-
-// ---------------------------------------------------------- coarse levels
-
-template <typename R>
-struct LV {
-  int n0, n1, n2;
-  const R *Tx, *Ty, *Tz, *D;
-};
-
-template <typename R>
-__device__ __forceinline__ R coarse_off(const LV<R> &L, int i, int j, int k, int c,
-                                        const R *__restrict__ x) {
-  R s = 0;
-  const int sy = L.n0, sz = L.n0 * L.n1;
-  if (i + 1 < L.n0) s += L.Tx[c] * x[c + 1];
-  if (i > 0) s += L.Tx[c - 1] * x[c - 1];
-  if (j + 1 < L.n1) s += L.Ty[c] * x[c + sy];
-  if (j > 0) s += L.Ty[c - sy] * x[c - sy];
-  if (k + 1 < L.n2) s += L.Tz[c] * x[c + sz];
-  if (k > 0) s += L.Tz[c - sz] * x[c - sz];
-  return s;
-}
-
-template <typename R>
-__global__ void __launch_bounds__(NTHREADS) k_smoothc(LV<R> L, const R *__restrict__ b,
-                                                      R *__restrict__ x, int color,
-                                                      int zero_init) {
-  const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y,
-            k = blockIdx.z;
-  if (i >= L.n0 || j >= L.n1) return;
-  const int c = i + L.n0 * (j + L.n1 * k);
-  const bool mine = red(i, j, k) == (color == 0);
-  const R D = L.D[c];
-  if (zero_init) {
-    x[c] = mine && D > 0 ? b[c] / D : (R)0;
-    return;
+    }
+    bc[I + cn0 * (J + cn1 * K)] = s;
   }
-  if (!mine) return;
-  x[c] = D > 0 ? (b[c] + coarse_off(L, i, j, k, c, x)) / D : (R)0;
-}
-
-template <typename R>
-__global__ void __launch_bounds__(NTHREADS) k_restrictc(LV<R> L, int cn0, int cn1, int cn2,
-                                                        const R *__restrict__ b,
-                                                        const R *__restrict__ x,
-                                                        R *__restrict__ bc) {
-  const int I = blockIdx.x * BX + threadIdx.x, J = blockIdx.y * BY + threadIdx.y,
-            K = blockIdx.z;
-  if (I >= cn0 || J >= cn1) return;
-  R s = 0;
-  for (int dk = 0; dk < 2; dk++)
-    for (int dj = 0; dj < 2; dj++)
-      for (int di = 0; di < 2; di++) {
-        const int i = 2 * I + di, j = 2 * J + dj, k = 2 * K + dk;
-        if (i >= L.n0 || j >= L.n1 || k >= L.n2) continue;
-        const int c = i + L.n0 * (j + L.n1 * k);
-        s += b[c] - (L.D[c] * x[c] - coarse_off(L, i, j, k, c, x));
-      }
-  bc[I + cn0 * (J + cn1 * K)] = s;
 }
 
 // x_fine += x_coarse(parent)
 template <typename R>
-__global__ void __launch_bounds__(NTHREADS) k_prolong(int n0, int n1, int n2, int cn0, int cn1,
-                                                      const R *__restrict__ xc,
+__global__ void __launch_bounds__(NTHREADS) k_prolong(int n0, int n1, int n2, ZG z, int cn0,
+                                                      int cn1, const R *__restrict__ xc,
                                                       R *__restrict__ x) {
-  const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y,
-            k = blockIdx.z;
-  if (i >= n0 || j >= n1) return;
-  x[i + n0 * (j + n1 * k)] += xc[(i >> 1) + cn0 * ((j >> 1) + cn1 * (k >> 1))];
+  int i, j, k0, k1;
+  if (!column(z, n0, n1, n2, i, j, k0, k1)) return;
+  int c = i + n0 * (j + n1 * k0);
+  for (int k = k0; k < k1; k++, c += n0 * n1)
+    x[c] += xc[(i >> 1) + cn0 * ((j >> 1) + cn1 * (k >> 1))];
 }
 
-// coarsest level: symmetric red-black sweeps by one block
+// coarse operator of the next level from this level's operator
 template <typename R>
-__global__ void __launch_bounds__(1024) k_coarse_solve(LV<R> L, const R *__restrict__ b,
-                                                       R *__restrict__ x, int sweeps) {
-  const int n = L.n0 * L.n1 * L.n2;
-  for (int c = threadIdx.x; c < n; c += blockDim.x) x[c] = 0;
-  __syncthreads();
-  for (int sw = 0; sw < 2 * sweeps; sw++) {
-    for (int h = 0; h < 2; h++) {
-      // forward sweeps red,black; backward sweeps black,red
-      const int color = (sw < sweeps) ? h : 1 - h;
-      for (int c = threadIdx.x; c < n; c += blockDim.x) {
-        const int i = c % L.n0, j = (c / L.n0) % L.n1, k = c / (L.n0 * L.n1);
-        if (red(i, j, k) != (color == 0)) continue;
-        const R D = L.D[c];
-        x[c] = D > 0 ? (b[c] + coarse_off(L, i, j, k, c, x)) / D : (R)0;
-      }
-      __syncthreads();
-    }
+__global__ void __launch_bounds__(NTHREADS) k_build_coarse(Op<R> L, const R *__restrict__ Dbf,
+                                                           ZG zc, int cn0, int cn1, int cn2,
+                                                           R *__restrict__ Tx, R *__restrict__ Ty,
+                                                           R *__restrict__ Tz,
+                                                           R *__restrict__ Db) {
+  int I, J, K0, K1;
+  if (!column(zc, cn0, cn1, cn2, I, J, K0, K1)) return;
+  for (int K = K0; K < K1; K++) {
+    R tx = 0, ty = 0, tz = 0, db = 0;
+    for (int dk = 0; dk < 2; dk++)
+      for (int dj = 0; dj < 2; dj++)
+        for (int di = 0; di < 2; di++) {
+          const int i = 2 * I + di, j = 2 * J + dj, k = 2 * K + dk;
+          if (i >= L.n0 || j >= L.n1 || k >= L.n2) continue;
+          const int c = i + L.n0 * (j + L.n1 * k);
+          R D, T[6];
+          op_row(L, i, j, k, c, D, T);
+          if (di == 1) tx += T[1];
+          if (dj == 1) ty += T[3];
+          if (dk == 1) tz += T[5];
+          db += L.matfree ? op_outlet(L, i, j, k, c) : Dbf[c];
+        }
+    const int C = I + cn0 * (J + cn1 * K);
+    Tx[C] = (R)0.5 * tx;
+    Ty[C] = (R)0.5 * ty;
+    Tz[C] = (R)0.5 * tz;
+    Db[C] = (R)0.5 * db;
   }
 }
 
-// level-1 operator from the fine rAU
 template <typename R>
-__global__ void __launch_bounds__(NTHREADS) k_build_coarse0(Geom G, const double *__restrict__ rAU,
-                                                            int cn0, int cn1, int cn2,
-                                                            R *__restrict__ Tx, R *__restrict__ Ty,
-                                                            R *__restrict__ Tz,
-                                                            R *__restrict__ Db) {
-  const int I = blockIdx.x * BX + threadIdx.x, J = blockIdx.y * BY + threadIdx.y,
-            K = blockIdx.z;
-  if (I >= cn0 || J >= cn1) return;
-  double tx = 0, ty = 0, tz = 0, db = 0;
-  for (int dk = 0; dk < 2; dk++)
-    for (int dj = 0; dj < 2; dj++)
-      for (int di = 0; di < 2; di++) {
-        const int i = 2 * I + di, j = 2 * J + dj, k = 2 * K + dk;
-        if (i >= G.n[0] || j >= G.n[1] || k >= G.n[2]) continue;
-        const int c = cidx(G, i, j, k);
-        const double r = rAU[c];
-        // fine faces on the coarse cell's + side
-        if (di == 1 && i + 1 < G.n[0]) tx += 0.5 * (r + rAU[c + 1]) * G.area[0] * G.ih[0];
-        if (dj == 1 && j + 1 < G.n[1]) ty += 0.5 * (r + rAU[c + G.n[0]]) * G.area[1] * G.ih[1];
-        if (dk == 1 && k + 1 < G.n[2])
-          tz += 0.5 * (r + rAU[c + G.n[0] * G.n[1]]) * G.area[2] * G.ih[2];
-        for (int a = 0; a < 3; a++) {
-          const int co[3] = {i, j, k};
-          if (co[a] == 0 && G.bck[2 * a] == BC_OUTLET) db += r * G.area[a] * 2.0 * G.ih[a];
-          if (co[a] == G.n[a] - 1 && G.bck[2 * a + 1] == BC_OUTLET)
-            db += r * G.area[a] * 2.0 * G.ih[a];
-        }
-      }
-  const int C = I + cn0 * (J + cn1 * K);
-  Tx[C] = (R)(0.5 * tx);
-  Ty[C] = (R)(0.5 * ty);
-  Tz[C] = (R)(0.5 * tz);
-  Db[C] = (R)(0.5 * db);
-}
-
-template <typename R>
-__global__ void __launch_bounds__(NTHREADS) k_build_coarsec(LV<R> L, const R *__restrict__ Dbf,
-                                                            int cn0, int cn1, int cn2,
-                                                            R *__restrict__ Tx, R *__restrict__ Ty,
-                                                            R *__restrict__ Tz,
-                                                            R *__restrict__ Db) {
-  const int I = blockIdx.x * BX + threadIdx.x, J = blockIdx.y * BY + threadIdx.y,
-            K = blockIdx.z;
-  if (I >= cn0 || J >= cn1) return;
-  R tx = 0, ty = 0, tz = 0, db = 0;
-  for (int dk = 0; dk < 2; dk++)
-    for (int dj = 0; dj < 2; dj++)
-      for (int di = 0; di < 2; di++) {
-        const int i = 2 * I + di, j = 2 * J + dj, k = 2 * K + dk;
-        if (i >= L.n0 || j >= L.n1 || k >= L.n2) continue;
-        const int c = i + L.n0 * (j + L.n1 * k);
-        if (di == 1 && i + 1 < L.n0) tx += L.Tx[c];
-        if (dj == 1 && j + 1 < L.n1) ty += L.Ty[c];
-        if (dk == 1 && k + 1 < L.n2) tz += L.Tz[c];
-        db += Dbf[c];
-      }
-  const int C = I + cn0 * (J + cn1 * K);
-  Tx[C] = (R)0.5 * tx;
-  Ty[C] = (R)0.5 * ty;
-  Tz[C] = (R)0.5 * tz;
-  Db[C] = (R)0.5 * db;
-}
-
-template <typename R>
-__global__ void __launch_bounds__(NTHREADS) k_diag(LV<R> L, const R *__restrict__ Db,
+__global__ void __launch_bounds__(NTHREADS) k_diag(int n0, int n1, int n2, ZG z,
+                                                   const R *__restrict__ Tx,
+                                                   const R *__restrict__ Ty,
+                                                   const R *__restrict__ Tz,
+                                                   const R *__restrict__ Db,
                                                    R *__restrict__ D) {
-  const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y,
-            k = blockIdx.z;
-  if (i >= L.n0 || j >= L.n1) return;
-  const int c = i + L.n0 * (j + L.n1 * k);
+  int i, j, k0, k1;
+  if (!column(z, n0, n1, n2, i, j, k0, k1)) return;
+  const int sy = n0, sz = n0 * n1;
+  int c = i + n0 * (j + n1 * k0);
+  for (int k = k0; k < k1; k++, c += sz) {
+    R d = Db[c] + Tx[c] + Ty[c] + Tz[c];
+    if (i > 0) d += Tx[c - 1];
+    if (j > 0) d += Ty[c - sy];
+    if (k > 0) d += Tz[c - sz];
+    D[c] = d;
+  }
+}
+
+// ----------------------------------------------- single work-group bottom
+//
+// The smallest levels (from the first one whose whole sub-hierarchy fits in
+// BOTTOM_LDS bytes) are cycled by one work-group of 1024 threads with every
+// array in LDS: coefficients and b of the top bottom level are loaded once,
+// the V-cycle runs with LDS-latency barriers, and x goes back to memory.
+
+template <typename R>
+struct BLevel {
+  int n0, n1, n2, off;  // off: first cell of the level in the LDS arrays
+  const R *Tx, *Ty, *Tz, *D;
+  R *x, *b;             // global x and b (b read and x written for the top level)
+};
+
+template <typename R>
+struct Bottom {
+  int nl, ntot;
+  int pre, post, coarse_sweeps;
+  BLevel<R> L[MAXLV];
+};
+
+template <typename R>
+struct LdsView {
+  R *tx, *ty, *tz, *d, *x, *b;
+};
+
+template <typename R>
+__device__ inline void bl_sweep(const LdsView<R> &S, const BLevel<R> &L, int color, bool zero) {
+  const int n = L.n0 * L.n1 * L.n2;
   const int sy = L.n0, sz = L.n0 * L.n1;
-  R d = Db[c] + L.Tx[c] + L.Ty[c] + L.Tz[c];
-  if (i > 0) d += L.Tx[c - 1];
-  if (j > 0) d += L.Ty[c - sy];
-  if (k > 0) d += L.Tz[c - sz];
-  D[c] = d;
+  for (int c = threadIdx.x; c < n; c += blockDim.x) {
+    const int i = c % L.n0, j = (c / L.n0) % L.n1, k = c / sz;
+    const int g = L.off + c;
+    const bool mine = (((i + j + k) & 1) == color);
+    if (zero) {
+      S.x[g] = mine && S.d[g] > (R)0 ? S.b[g] / S.d[g] : (R)0;
+      continue;
+    }
+    if (!mine) continue;
+    R s = S.b[g];
+    if (i > 0) s += S.tx[g - 1] * S.x[g - 1];
+    if (i + 1 < L.n0) s += S.tx[g] * S.x[g + 1];
+    if (j > 0) s += S.ty[g - sy] * S.x[g - sy];
+    if (j + 1 < L.n1) s += S.ty[g] * S.x[g + sy];
+    if (k > 0) s += S.tz[g - sz] * S.x[g - sz];
+    if (k + 1 < L.n2) s += S.tz[g] * S.x[g + sz];
+    S.x[g] = S.d[g] > (R)0 ? s / S.d[g] : (R)0;
+  }
+  __syncthreads();
+}
+
+template <typename R>
+__device__ inline void bl_restrict(const LdsView<R> &S, const BLevel<R> &F, const BLevel<R> &C) {
+  const int n = C.n0 * C.n1 * C.n2;
+  const int sy = F.n0, sz = F.n0 * F.n1;
+  for (int cc = threadIdx.x; cc < n; cc += blockDim.x) {
+    const int I = cc % C.n0, J = (cc / C.n0) % C.n1, K = cc / (C.n0 * C.n1);
+    R s = 0;
+    for (int dk = 0; dk < 2; dk++)
+      for (int dj = 0; dj < 2; dj++)
+        for (int di = 0; di < 2; di++) {
+          const int i = 2 * I + di, j = 2 * J + dj, k = 2 * K + dk;
+          if (i >= F.n0 || j >= F.n1 || k >= F.n2) continue;
+          const int g = F.off + i + F.n0 * (j + F.n1 * k);
+          R ax = S.d[g] * S.x[g];
+          if (i > 0) ax -= S.tx[g - 1] * S.x[g - 1];
+          if (i + 1 < F.n0) ax -= S.tx[g] * S.x[g + 1];
+          if (j > 0) ax -= S.ty[g - sy] * S.x[g - sy];
+          if (j + 1 < F.n1) ax -= S.ty[g] * S.x[g + sy];
+          if (k > 0) ax -= S.tz[g - sz] * S.x[g - sz];
+          if (k + 1 < F.n2) ax -= S.tz[g] * S.x[g + sz];
+          s += S.b[g] - ax;
+        }
+    S.b[C.off + cc] = s;
+  }
+  __syncthreads();
+}
+
+template <typename R>
+__device__ inline void bl_prolong(const LdsView<R> &S, const BLevel<R> &F, const BLevel<R> &C) {
+  const int n = F.n0 * F.n1 * F.n2;
+  for (int c = threadIdx.x; c < n; c += blockDim.x) {
+    const int i = c % F.n0, j = (c / F.n0) % F.n1, k = c / (F.n0 * F.n1);
+    S.x[F.off + c] += S.x[C.off + (i >> 1) + C.n0 * ((j >> 1) + C.n1 * (k >> 1))];
+  }
+  __syncthreads();
+}
+
+template <typename R>
+__global__ void __launch_bounds__(1024) k_bottom(Bottom<R> A) {
+  __shared__ R lds[BOTTOM_LDS / sizeof(R)];
+  const int N = A.ntot;
+  LdsView<R> S{lds, lds + N, lds + 2 * N, lds + 3 * N, lds + 4 * N, lds + 5 * N};
+  for (int l = 0; l < A.nl; l++) {
+    const BLevel<R> &L = A.L[l];
+    const int n = L.n0 * L.n1 * L.n2;
+    for (int c = threadIdx.x; c < n; c += blockDim.x) {
+      const int g = L.off + c;
+      S.tx[g] = L.Tx[c];
+      S.ty[g] = L.Ty[c];
+      S.tz[g] = L.Tz[c];
+      S.d[g] = L.D[c];
+      if (l == 0) S.b[g] = L.b[c];
+    }
+  }
+  __syncthreads();
+  for (int l = 0; l < A.nl - 1; l++) {
+    for (int s = 0; s < A.pre; s++) {
+      bl_sweep(S, A.L[l], 0, s == 0);
+      bl_sweep(S, A.L[l], 1, false);
+    }
+    bl_restrict(S, A.L[l], A.L[l + 1]);
+  }
+  const BLevel<R> &C = A.L[A.nl - 1];
+  for (int s = 0; s < A.coarse_sweeps; s++) {
+    bl_sweep(S, C, 0, s == 0);
+    bl_sweep(S, C, 1, false);
+  }
+  for (int s = 0; s < A.coarse_sweeps; s++) {
+    bl_sweep(S, C, 1, false);
+    bl_sweep(S, C, 0, false);
+  }
+  for (int l = A.nl - 2; l >= 0; l--) {
+    bl_prolong(S, A.L[l], A.L[l + 1]);
+    for (int s = 0; s < A.post; s++) {
+      bl_sweep(S, A.L[l], 1, false);
+      bl_sweep(S, A.L[l], 0, false);
+    }
+  }
+  const BLevel<R> &T = A.L[0];
+  const int n = T.n0 * T.n1 * T.n2;
+  for (int c = threadIdx.x; c < n; c += blockDim.x) T.x[c] = S.x[T.off + c];
+}
+
+// ------------------------------------------------ fine level, 2.5-D tiles
+//
+// A block of 64 x TY2 threads owns a tile of W x TY2 cells (W = 64 one cell
+// per thread, or 128 with an x-pair per thread) and walks KZ2 planes.  Each
+// plane of x (or p) and rAU is staged with a one-cell halo in LDS; the z
+// neighbours of a thread's own cells stay in registers, so each array is
+// read from memory about once per pass (plus the halo and the chunk ends).
+
+constexpr int TY2 = 8;
+constexpr int KZ2 = 16;
+constexpr int NT2 = 64 * TY2;
+constexpr int MIN_BLOCKS2 = 1024;
+
+struct ZG2 {
+  int nbx, nby, nbz, kz;
+};
+
+static ZG2 make_zg2(int n0, int n1, int n2, int W, bool even_kz) {
+  ZG2 z;
+  z.nbx = (n0 + W - 1) / W;
+  z.nby = (n1 + TY2 - 1) / TY2;
+  z.kz = even_kz && n2 > 1 ? 2 : 1;
+  while (z.kz < KZ2 && (long long)z.nbx * z.nby * ((n2 + 2 * z.kz - 1) / (2 * z.kz)) >= MIN_BLOCKS2)
+    z.kz *= 2;
+  z.nbz = (n2 + z.kz - 1) / z.kz;
+  return z;
+}
+
+static int nblk2(const ZG2 &z) { return z.nbx * z.nby * z.nbz; }
+
+__device__ __forceinline__ void tile_of(const ZG2 &z, int n2, int &x0b, int &y0, int &k0,
+                                        int &k1) {
+  const int nb = z.nbx * z.nby * z.nbz;
+  const int b = blockIdx.x;
+  const int full = nb & ~7;
+  int L = b;
+  if (b < full) L = (b & 7) * (full >> 3) + (b >> 3);  // XCD-contiguous runs
+  x0b = L % z.nbx;
+  L /= z.nbx;
+  y0 = (L % z.nby) * TY2;
+  k0 = (L / z.nby) * z.kz;
+  k1 = min(k0 + z.kz, n2);
+}
+
+#define LIX(W, lx, ly) (((ly) + 1) * ((W) + 2) + (lx) + 1)
+
+template <int NW>
+__device__ __forceinline__ double block_sum_n(double v, double *lds) {
+  v = wave_sum(v);
+  const int t = threadIdx.x + 64 * threadIdx.y;
+  if ((t & 63) == 0) lds[t >> 6] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (t == 0)
+    for (int q = 0; q < NW; q++) s += lds[q];
+  __syncthreads();
+  return s;
+}
+
+template <typename R>
+__device__ __forceinline__ R ld_or0(const R *__restrict__ a, int i, int j, int k, int n0, int n1,
+                                    int n2) {
+  return (i >= 0 && i < n0 && j >= 0 && j < n1 && k >= 0 && k < n2) ? a[i + n0 * (j + n1 * k)]
+                                                                     : (R)0;
+}
+
+// two cells of one thread, selected without dynamic register indexing
+template <typename R>
+struct P2 {
+  R v0, v1;
+  __device__ __forceinline__ R get(int off) const { return off ? v1 : v0; }
+  __device__ __forceinline__ void set(int off, R v) {
+    if (off) v1 = v; else v0 = v;
+  }
+};
+
+// Halo of one plane for a thread: the cell left of the tile (tx == 0), right
+// of it (tx == 63), and below / above its two cells (ty == 0 / ty == TY2-1),
+// for the iterate and rAU.  Loaded one plane ahead, so the loads are in
+// flight while the current plane is computed.  Plain scalars (no arrays):
+// they must stay in registers.
+template <typename R>
+struct Halo {
+  R xl, xr, rl, rr, xs0, xs1, xn0, xn1, rs0, rs1, rn0, rn1;
+};
+
+template <typename R, int CPT, int W, typename FX>
+__device__ __forceinline__ Halo<R> halo_load(const FX &X, const R *__restrict__ rA, int x0, int y0,
+                                             int i0, int j, int k, int n0, int n1, int n2) {
+  const int tx = threadIdx.x, ty = threadIdx.y;
+  Halo<R> h;
+  const bool L = tx == 0, Rt = tx == 63, S = ty == 0, N = ty == TY2 - 1;
+  h.xl = L ? X(x0 - 1, j, k) : (R)0;
+  h.rl = L ? ld_or0(rA, x0 - 1, j, k, n0, n1, n2) : (R)0;
+  h.xr = Rt ? X(x0 + W, j, k) : (R)0;
+  h.rr = Rt ? ld_or0(rA, x0 + W, j, k, n0, n1, n2) : (R)0;
+  h.xs0 = S ? X(i0, y0 - 1, k) : (R)0;
+  h.rs0 = S ? ld_or0(rA, i0, y0 - 1, k, n0, n1, n2) : (R)0;
+  h.xn0 = N ? X(i0, y0 + TY2, k) : (R)0;
+  h.rn0 = N ? ld_or0(rA, i0, y0 + TY2, k, n0, n1, n2) : (R)0;
+  h.xs1 = (S && CPT == 2) ? X(i0 + 1, y0 - 1, k) : (R)0;
+  h.rs1 = (S && CPT == 2) ? ld_or0(rA, i0 + 1, y0 - 1, k, n0, n1, n2) : (R)0;
+  h.xn1 = (N && CPT == 2) ? X(i0 + 1, y0 + TY2, k) : (R)0;
+  h.rn1 = (N && CPT == 2) ? ld_or0(rA, i0 + 1, y0 + TY2, k, n0, n1, n2) : (R)0;
+  return h;
+}
+
+template <typename R, int CPT, int W>
+__device__ __forceinline__ void halo_store(const Halo<R> &h, R *sx, R *sr) {
+  const int tx = threadIdx.x, ty = threadIdx.y;
+  if (tx == 0) { sx[LIX(W, -1, ty)] = h.xl; sr[LIX(W, -1, ty)] = h.rl; }
+  if (tx == 63) { sx[LIX(W, W, ty)] = h.xr; sr[LIX(W, W, ty)] = h.rr; }
+  if (ty == 0) {
+    sx[LIX(W, CPT * tx, -1)] = h.xs0;
+    sr[LIX(W, CPT * tx, -1)] = h.rs0;
+    if (CPT == 2) { sx[LIX(W, CPT * tx + 1, -1)] = h.xs1; sr[LIX(W, CPT * tx + 1, -1)] = h.rs1; }
+  }
+  if (ty == TY2 - 1) {
+    sx[LIX(W, CPT * tx, TY2)] = h.xn0;
+    sr[LIX(W, CPT * tx, TY2)] = h.rn0;
+    if (CPT == 2) { sx[LIX(W, CPT * tx + 1, TY2)] = h.xn1; sr[LIX(W, CPT * tx + 1, TY2)] = h.rn1; }
+  }
+}
+
+// row of the fine operator at (i,j,k), lx/ty its LDS position; z
+// neighbours' rAU from registers
+template <typename R, int W>
+__device__ __forceinline__ void row25(const Op<R> &L, int i, int j, int k, int lx, int ty,
+                                      const R *sr, R rc, R rm, R rp, R T[6], R &D) {
+  const R h = (R)0.5;
+  T[0] = i > 0 ? h * (rc + sr[LIX(W, lx - 1, ty)]) * L.c[0] : (R)0;
+  T[1] = i + 1 < L.n0 ? h * (rc + sr[LIX(W, lx + 1, ty)]) * L.c[0] : (R)0;
+  T[2] = j > 0 ? h * (rc + sr[LIX(W, lx, ty - 1)]) * L.c[1] : (R)0;
+  T[3] = j + 1 < L.n1 ? h * (rc + sr[LIX(W, lx, ty + 1)]) * L.c[1] : (R)0;
+  T[4] = k > 0 ? h * (rc + rm) * L.c[2] : (R)0;
+  T[5] = k + 1 < L.n2 ? h * (rc + rp) * L.c[2] : (R)0;
+  const R db = (i == 0 ? L.ob[0] : (R)0) + (i + 1 == L.n0 ? L.ob[1] : (R)0) +
+               (j == 0 ? L.ob[2] : (R)0) + (j + 1 == L.n1 ? L.ob[3] : (R)0) +
+               (k == 0 ? L.ob[4] : (R)0) + (k + 1 == L.n2 ? L.ob[5] : (R)0);
+  D = T[0] + T[1] + T[2] + T[3] + T[4] + T[5] + rc * db;
+}
+
+template <typename R, int W>
+__device__ __forceinline__ R off25(const R T[6], int lx, int ty, const R *sx, R xm, R xp) {
+  return T[0] * sx[LIX(W, lx - 1, ty)] + T[1] * sx[LIX(W, lx + 1, ty)] +
+         T[2] * sx[LIX(W, lx, ty - 1)] + T[3] * sx[LIX(W, lx, ty + 1)] + T[4] * xm + T[5] * xp;
+}
+
+// MODE 0: q = A p and partial p.q;  MODE 1: r = b - A p and partials r.r, b.b
+template <int MODE>
+__global__ void __launch_bounds__(NT2) k_stencil25(Op<double> L, ZG2 z,
+                                                   const double *__restrict__ p,
+                                                   const double *__restrict__ b,
+                                                   double *__restrict__ out,
+                                                   double *__restrict__ partials) {
+  constexpr int W = 64;
+  __shared__ double sp[(TY2 + 2) * (W + 2)], sr[(TY2 + 2) * (W + 2)];
+  __shared__ double lred[NT2 / 64];
+  int xb, y0, k0, k1;
+  tile_of(z, L.n2, xb, y0, k0, k1);
+  const int x0 = xb * W;
+  const int tx = threadIdx.x, ty = threadIdx.y;
+  const int i = x0 + tx, j = y0 + ty;
+  const int n0 = L.n0, n1 = L.n1, n2 = L.n2;
+  const bool in = i < n0 && j < n1;
+  const double *rA = L.rAU;
+  auto X = [&](int ii, int jj, int kk) -> double { return ld_or0(p, ii, jj, kk, n0, n1, n2); };
+  double pm = X(i, j, k0 - 1), pc = X(i, j, k0), pp = X(i, j, k0 + 1), pq = X(i, j, k0 + 2);
+  double rm = ld_or0(rA, i, j, k0 - 1, n0, n1, n2), rc = ld_or0(rA, i, j, k0, n0, n1, n2),
+         rp = ld_or0(rA, i, j, k0 + 1, n0, n1, n2), rq = ld_or0(rA, i, j, k0 + 2, n0, n1, n2);
+  Halo<double> hc = halo_load<double, 1, W>(X, rA, x0, y0, i, j, k0, n0, n1, n2), hn = hc;
+  double v1 = 0.0, v2 = 0.0;
+  for (int k = k0; k < k1; k++) {
+    sp[LIX(W, tx, ty)] = pc;
+    sr[LIX(W, tx, ty)] = rc;
+    halo_store<double, 1, W>(hc, sp, sr);
+    __syncthreads();
+    if (k + 1 < k1) hn = halo_load<double, 1, W>(X, rA, x0, y0, i, j, k + 1, n0, n1, n2);
+    const double pr = X(i, j, k + 3), rr3 = ld_or0(rA, i, j, k + 3, n0, n1, n2);
+    double bb = 0.0;
+    const int c = i + n0 * (j + n1 * k);
+    if (MODE == 1 && in) bb = b[c];
+    if (in) {
+      double T[6], D;
+      row25<double, W>(L, i, j, k, tx, ty, sr, rc, rm, rp, T, D);
+      const double y = D * pc - off25<double, W>(T, tx, ty, sp, pm, pp);
+      if (MODE == 0) {
+        out[c] = y;
+        v1 += pc * y;
+      } else {
+        const double res = bb - y;
+        out[c] = res;
+        v1 += res * res;
+        v2 += bb * bb;
+      }
+    }
+    __syncthreads();
+    pm = pc; pc = pp; pp = pq; pq = pr;
+    rm = rc; rc = rp; rp = rq; rq = rr3;
+    hc = hn;
+  }
+  const double s1 = block_sum_n<NT2 / 64>(v1, lred);
+  if (tx == 0 && ty == 0) partials[blockIdx.x] = s1;
+  if (MODE == 1) {
+    const double s2 = block_sum_n<NT2 / 64>(v2, lred);
+    if (tx == 0 && ty == 0) partials[z.nbx * z.nby * z.nbz + blockIdx.x] = s2;
+  }
+}
+
+enum { SM_NORMAL = 0, SM_ZERO = 1, SM_PROLONG = 2 };
+
+// Red-black Gauss-Seidel half sweep on the fine level, one x-pair per thread.
+// SM_ZERO: x = b/D on this colour, 0 on the other (zero initial guess).
+// SM_PROLONG: x_in + (coarse correction of the parent) is the current
+// iterate; this colour is relaxed and both colours go to x_out.
+// Otherwise x_out == x_in and only this colour is written.
+template <typename R, typename B, int MODE>
+__global__ void __launch_bounds__(NT2) k_smooth25(Op<R> L, ZG2 z, const B *__restrict__ b,
+                                                  const R *xin, R *xout, int color,
+                                                  const R *__restrict__ xc, int cn0, int cn1) {
+  constexpr int W = 128;
+  __shared__ R sx[(TY2 + 2) * (W + 2)], sr[(TY2 + 2) * (W + 2)];
+  int xb, y0, k0, k1;
+  tile_of(z, L.n2, xb, y0, k0, k1);
+  const int x0 = xb * W;
+  const int tx = threadIdx.x, ty = threadIdx.y;
+  const int i0 = x0 + 2 * tx, j = y0 + ty;
+  const int n0 = L.n0, n1 = L.n1, n2 = L.n2;
+  const R *rA = L.rAU;
+  auto X = [&](int ii, int jj, int kk) -> R {
+    if (MODE == SM_ZERO) return (R)0;
+    R v = ld_or0(xin, ii, jj, kk, n0, n1, n2);
+    if (MODE == SM_PROLONG && ii >= 0 && ii < n0 && jj >= 0 && jj < n1 && kk >= 0 && kk < n2)
+      v += xc[(ii >> 1) + cn0 * ((jj >> 1) + cn1 * (kk >> 1))];
+    return v;
+  };
+  auto XP = [&](int kk) -> P2<R> { return P2<R>{X(i0, j, kk), X(i0 + 1, j, kk)}; };
+  auto RP = [&](int kk) -> P2<R> {
+    return P2<R>{ld_or0(rA, i0, j, kk, n0, n1, n2), ld_or0(rA, i0 + 1, j, kk, n0, n1, n2)};
+  };
+  P2<R> xm = XP(k0 - 1), xk = XP(k0), xp = XP(k0 + 1), xq = XP(k0 + 2);
+  P2<R> rm = RP(k0 - 1), rk = RP(k0), rp = RP(k0 + 1), rq = RP(k0 + 2);
+  Halo<R> hc = halo_load<R, 2, W>(X, rA, x0, y0, i0, j, k0, n0, n1, n2), hn = hc;
+  for (int k = k0; k < k1; k++) {
+    sx[LIX(W, 2 * tx, ty)] = xk.v0;
+    sx[LIX(W, 2 * tx + 1, ty)] = xk.v1;
+    sr[LIX(W, 2 * tx, ty)] = rk.v0;
+    sr[LIX(W, 2 * tx + 1, ty)] = rk.v1;
+    halo_store<R, 2, W>(hc, sx, sr);
+    __syncthreads();
+    if (k + 1 < k1) hn = halo_load<R, 2, W>(X, rA, x0, y0, i0, j, k + 1, n0, n1, n2);
+    const P2<R> xr = XP(k + 3), rr = RP(k + 3);
+    const int off = ((j + k) & 1) == color ? 0 : 1;
+    const int i = i0 + off;
+    const int c = i + n0 * (j + n1 * k);
+    const bool act = j < n1 && i < n0;
+    const R bc = act ? (R)b[c] : (R)0;
+    if (act) {
+      const int lx = 2 * tx + off;
+      R T[6], D;
+      row25<R, W>(L, i, j, k, lx, ty, sr, rk.get(off), rm.get(off), rp.get(off), T, D);
+      R xn;
+      if (MODE == SM_ZERO)
+        xn = D > (R)0 ? bc / D : (R)0;
+      else
+        xn = D > (R)0 ? (bc + off25<R, W>(T, lx, ty, sx, xm.get(off), xp.get(off))) / D : (R)0;
+      xout[c] = xn;
+      xk.set(off, xn);
+    }
+    if (MODE != SM_NORMAL && j < n1 && i0 + 1 - off < n0)
+      xout[i0 + 1 - off + n0 * (j + n1 * k)] = MODE == SM_ZERO ? (R)0 : xk.get(1 - off);
+    __syncthreads();
+    xm = xk; xk = xp; xp = xq; xq = xr;
+    rm = rk; rk = rp; rp = rq; rq = rr;
+    hc = hn;
+  }
+}
+
+// Restriction after a pre-smoothing that ended with a black half sweep: the
+// black residual is zero, so the coarse right-hand side is the sum of the
+// red children's residuals.  Block tiles are 128 x 8 fine cells and walk
+// plane pairs; rows 2J and 2J+1 are combined through LDS.
+template <typename R, typename B>
+__global__ void __launch_bounds__(NT2) k_restrict25(Op<R> L, ZG2 z, const B *__restrict__ b,
+                                                    const R *__restrict__ x, R *__restrict__ bc,
+                                                    int cn0, int cn1) {
+  constexpr int W = 128;
+  __shared__ R sx[(TY2 + 2) * (W + 2)], sr[(TY2 + 2) * (W + 2)];
+  __shared__ R part[TY2 / 2][64];
+  int xb, y0, k0, k1;
+  tile_of(z, L.n2, xb, y0, k0, k1);
+  const int x0 = xb * W;
+  const int tx = threadIdx.x, ty = threadIdx.y;
+  const int i0 = x0 + 2 * tx, j = y0 + ty;
+  const int n0 = L.n0, n1 = L.n1, n2 = L.n2;
+  const R *rA = L.rAU;
+  auto X = [&](int ii, int jj, int kk) -> R { return ld_or0(x, ii, jj, kk, n0, n1, n2); };
+  auto XP = [&](int kk) -> P2<R> { return P2<R>{X(i0, j, kk), X(i0 + 1, j, kk)}; };
+  auto RP = [&](int kk) -> P2<R> {
+    return P2<R>{ld_or0(rA, i0, j, kk, n0, n1, n2), ld_or0(rA, i0 + 1, j, kk, n0, n1, n2)};
+  };
+  P2<R> xm = XP(k0 - 1), xk = XP(k0), xp = XP(k0 + 1), xq = XP(k0 + 2);
+  P2<R> rm = RP(k0 - 1), rk = RP(k0), rp = RP(k0 + 1), rq = RP(k0 + 2);
+  Halo<R> hc = halo_load<R, 2, W>(X, rA, x0, y0, i0, j, k0, n0, n1, n2), hn = hc;
+  R acc = 0;
+  for (int k = k0; k < k1; k++) {
+    sx[LIX(W, 2 * tx, ty)] = xk.v0;
+    sx[LIX(W, 2 * tx + 1, ty)] = xk.v1;
+    sr[LIX(W, 2 * tx, ty)] = rk.v0;
+    sr[LIX(W, 2 * tx + 1, ty)] = rk.v1;
+    halo_store<R, 2, W>(hc, sx, sr);
+    __syncthreads();
+    if (k + 1 < k1) hn = halo_load<R, 2, W>(X, rA, x0, y0, i0, j, k + 1, n0, n1, n2);
+    const P2<R> xr = XP(k + 3), rr = RP(k + 3);
+    const int off = ((j + k) & 1) == 0 ? 0 : 1;  // the red cell of the pair
+    const int i = i0 + off;
+    if (j < n1 && i < n0) {
+      const int lx = 2 * tx + off;
+      R T[6], D;
+      row25<R, W>(L, i, j, k, lx, ty, sr, rk.get(off), rm.get(off), rp.get(off), T, D);
+      const R s = off25<R, W>(T, lx, ty, sx, xm.get(off), xp.get(off));
+      acc += (R)b[i + n0 * (j + n1 * k)] - (D * xk.get(off) - s);
+    }
+    const bool flush = (k & 1) == 1 || k + 1 == n2;
+    if (flush && (ty & 1)) part[ty >> 1][tx] = acc;
+    __syncthreads();
+    if (flush) {
+      if (!(ty & 1)) {
+        const int I = i0 >> 1, J = j >> 1, K = k >> 1;
+        const R other = (j + 1 < n1) ? part[ty >> 1][tx] : (R)0;
+        if (i0 < n0 && j < n1) bc[I + cn0 * (J + cn1 * K)] = acc + other;
+      }
+      acc = 0;
+    }
+    xm = xk; xk = xp; xp = xq; xq = xr;
+    rm = rk; rk = rp; rp = rq; rq = rr;
+    hc = hn;
+  }
 }
 
 // ------------------------------------------------------------------ host
 
-static dim3 grid_of(int n0, int n1, int n2) {
-  return dim3((n0 + BX - 1) / BX, (n1 + BY - 1) / BY, n2);
-}
-
-template <typename R>
-static LV<R> view(const Level &L);
-template <>
-LV<double> view<double>(const Level &L) {
-  return LV<double>{L.n[0], L.n[1], L.n[2], L.Tx, L.Ty, L.Tz, L.D};
-}
-template <>
-LV<float> view<float>(const Level &L) {
-  return LV<float>{L.n[0], L.n[1], L.n[2], L.Txf, L.Tyf, L.Tzf, L.Df};
-}
 template <typename R> static R *lx(Level &L);
 template <> double *lx<double>(Level &L) { return L.x; }
 template <> float *lx<float>(Level &L) { return L.xf; }
@@ -498,14 +968,37 @@ template <typename R> static R *lD(Level &L);
 template <> double *lD<double>(Level &L) { return L.D; }
 template <> float *lD<float>(Level &L) { return L.Df; }
 
+template <typename R>
+static Op<R> op_of(Handle *h, int l, const R *rAU) {
+  Op<R> o;
+  Level &L = h->lv[l];
+  o.n0 = L.n[0]; o.n1 = L.n[1]; o.n2 = L.n[2];
+  o.matfree = l == 0;
+  o.rAU = rAU;
+  for (int a = 0; a < 3; a++) o.c[a] = (R)(h->G.area[a] * h->G.ih[a]);
+  for (int b = 0; b < 6; b++) o.ob[b] = h->G.bck[b] == BC_OUTLET ? (R)2 * o.c[b / 2] : (R)0;
+  o.Tx = lTx<R>(L); o.Ty = lTy<R>(L); o.Tz = lTz<R>(L); o.D = lD<R>(L);
+  return o;
+}
+
 static void *dalloc(Handle *h, size_t bytes, int &rc) {
   void *p = nullptr;
+  if (rc) return nullptr;
   if (hipMalloc(&p, bytes < 256 ? 256 : bytes) != hipSuccess) {
     rc = DBS_ENOMEM;
     return nullptr;
   }
   h->allocs.push_back(p);
   return p;
+}
+
+// launch shapes of each level: one cell per thread, and red/black pairs
+struct LShape {
+  ZG one, pair;
+  ZG2 st, sm, rs;  // fine level: stencil (64 wide), smoother and restriction (128 wide)
+};
+static std::vector<LShape> &shapes(Handle *h) {
+  return *reinterpret_cast<std::vector<LShape> *>(h->lvshape);
 }
 
 int pressure_setup(Handle *h) {
@@ -515,29 +1008,26 @@ int pressure_setup(Handle *h) {
   Level L0;
   for (int a = 0; a < 3; a++) L0.n[a] = h->G.n[a];
   L0.nc = h->G.nc;
-  L0.grid = h->grid;
   h->lv.push_back(L0);
-  // coarsen until the level is small enough for one block
-  while (true) {
+  while ((int)h->lv.size() < MAXLV) {
     const Level &F = h->lv.back();
-    if (F.nc <= 64 || (F.n[0] == 1 && F.n[1] == 1 && F.n[2] == 1)) break;
+    if (F.nc <= 1) break;
     Level C;
     for (int a = 0; a < 3; a++) C.n[a] = (F.n[a] + 1) / 2;
     C.nc = C.n[0] * C.n[1] * C.n[2];
-    C.grid = grid_of(C.n[0], C.n[1], C.n[2]);
-    size_t n = (size_t)C.nc;
-    if (mixed) {
-      C.Txf = (float *)dalloc(h, n * 4, rc); C.Tyf = (float *)dalloc(h, n * 4, rc);
-      C.Tzf = (float *)dalloc(h, n * 4, rc); C.Dbf = (float *)dalloc(h, n * 4, rc);
-      C.Df = (float *)dalloc(h, n * 4, rc); C.xf = (float *)dalloc(h, n * 4, rc);
-      C.bf = (float *)dalloc(h, n * 4, rc);
-    } else {
-      C.Tx = (double *)dalloc(h, n * 8, rc); C.Ty = (double *)dalloc(h, n * 8, rc);
-      C.Tz = (double *)dalloc(h, n * 8, rc); C.Db = (double *)dalloc(h, n * 8, rc);
-      C.D = (double *)dalloc(h, n * 8, rc); C.x = (double *)dalloc(h, n * 8, rc);
-      C.b = (double *)dalloc(h, n * 8, rc);
-    }
+    const size_t n = (size_t)C.nc;
+    const size_t s = mixed ? 4 : 8;
+    void *Tx = dalloc(h, n * s, rc), *Ty = dalloc(h, n * s, rc), *Tz = dalloc(h, n * s, rc);
+    void *Db = dalloc(h, n * s, rc), *D = dalloc(h, n * s, rc), *x = dalloc(h, n * s, rc);
+    void *b = dalloc(h, n * s, rc);
     if (rc) return rc;
+    if (mixed) {
+      C.Txf = (float *)Tx; C.Tyf = (float *)Ty; C.Tzf = (float *)Tz; C.Dbf = (float *)Db;
+      C.Df = (float *)D; C.xf = (float *)x; C.bf = (float *)b;
+    } else {
+      C.Tx = (double *)Tx; C.Ty = (double *)Ty; C.Tz = (double *)Tz; C.Db = (double *)Db;
+      C.D = (double *)D; C.x = (double *)x; C.b = (double *)b;
+    }
     h->lv.push_back(C);
   }
   if (mixed) {
@@ -545,201 +1035,275 @@ int pressure_setup(Handle *h) {
     h->lv[0].bf = (float *)dalloc(h, (size_t)h->G.nc * 4, rc);   // rAU (FP32)
     h->rf = (float *)dalloc(h, (size_t)h->G.nc * 4, rc);         // r (FP32)
     h->zoldf = (float *)dalloc(h, (size_t)h->G.nc * 4, rc);      // previous z (FP32)
+    h->zf2 = (float *)dalloc(h, (size_t)h->G.nc * 4, rc);        // second z buffer (FP32)
+  } else {
+    h->z2 = (double *)dalloc(h, (size_t)h->G.nc * 8, rc);        // second z buffer
+  }
+  if (rc) return rc;
+  auto *sh = new std::vector<LShape>();
+  for (auto &L : h->lv)
+    sh->push_back(LShape{make_zg(L.n[0], L.n[1], L.n[2], false),
+                         make_zg(L.n[0], L.n[1], L.n[2], true),
+                         make_zg2(L.n[0], L.n[1], L.n[2], 64, false),
+                         make_zg2(L.n[0], L.n[1], L.n[2], 128, false),
+                         make_zg2(L.n[0], L.n[1], L.n[2], 128, true)});
+  h->lvshape = sh;
+  // bottom: the first level (>= 1) whose sub-hierarchy fits in the LDS budget
+  const size_t rs = mixed ? 4 : 8;
+  h->bottom = (int)h->lv.size() - 1;
+  for (int l = 1; l < (int)h->lv.size(); l++) {
+    size_t cells = 0;
+    for (int m = l; m < (int)h->lv.size(); m++) cells += (size_t)h->lv[m].nc;
+    if (cells * 6 * rs <= (size_t)BOTTOM_LDS) { h->bottom = l; break; }
   }
   h->st.mg_levels = (int)h->lv.size();
+  h->red_blocks = zg_blocks((*sh)[0].one);
   return rc;
 }
 
-void pressure_free(Handle *h) { h->lv.clear(); }
+void pressure_free(Handle *h) {
+  delete reinterpret_cast<std::vector<LShape> *>(h->lvshape);
+  h->lvshape = nullptr;
+  h->lv.clear();
+}
 
-// build coarse operators for the current rAU (rAUr: rAU in the V-cycle type)
+static dim3 blk() { return dim3(BX, BY); }
+static dim3 g1(const ZG &z) { return dim3(zg_blocks(z)); }
+
 template <typename R>
-static void build_hierarchy(Handle *h, const double *rAU) {
-  dim3 blk(BX, BY);
+static void build_hierarchy(Handle *h, const R *rAUr) {
+  auto &S = shapes(h);
   for (size_t l = 1; l < h->lv.size(); l++) {
     Level &C = h->lv[l];
-    if (l == 1) {
-      DBS_LAUNCH(h, KC_BUILD_COARSE, k_build_coarse0<R>, C.grid, blk, h->G, rAU, C.n[0], C.n[1],
-                 C.n[2], lTx<R>(C), lTy<R>(C), lTz<R>(C), lDb<R>(C));
-    } else {
-      Level &F = h->lv[l - 1];
-      DBS_LAUNCH(h, KC_BUILD_COARSE, k_build_coarsec<R>, C.grid, blk, view<R>(F),
-                 (const R *)lDb<R>(F), C.n[0], C.n[1], C.n[2], lTx<R>(C), lTy<R>(C), lTz<R>(C),
-                 lDb<R>(C));
-    }
-    DBS_LAUNCH(h, KC_BUILD_COARSE, k_diag<R>, C.grid, blk, view<R>(C), (const R *)lDb<R>(C),
-               lD<R>(C));
+    Level &F = h->lv[l - 1];
+    Op<R> opF = op_of<R>(h, (int)l - 1, rAUr);
+    DBS_LAUNCH(h, KC_BUILD_COARSE, k_build_coarse<R>, g1(S[l].one), blk(), opF,
+               (const R *)lDb<R>(F), S[l].one, C.n[0], C.n[1], C.n[2], lTx<R>(C), lTy<R>(C),
+               lTz<R>(C), lDb<R>(C));
+    DBS_LAUNCH(h, KC_BUILD_COARSE, k_diag<R>, g1(S[l].one), blk(), C.n[0], C.n[1], C.n[2],
+               S[l].one, (const R *)lTx<R>(C), (const R *)lTy<R>(C), (const R *)lTz<R>(C),
+               (const R *)lDb<R>(C), lD<R>(C));
   }
 }
 
-// z = M r: one V-cycle.  Level 0 uses the matrix-free operator of rAUr.
+template <typename R>
+static void run_bottom(Handle *h) {
+  Bottom<R> A;
+  A.nl = (int)h->lv.size() - h->bottom;
+  A.pre = h->mg_pre;
+  A.post = h->mg_post;
+  int off = 0;
+  for (int l = 0; l < A.nl; l++) {
+    Level &L = h->lv[h->bottom + l];
+    A.L[l] = BLevel<R>{L.n[0], L.n[1], L.n[2], off, lTx<R>(L), lTy<R>(L), lTz<R>(L), lD<R>(L),
+                       lx<R>(L), lb<R>(L)};
+    off += L.nc;
+  }
+  A.ntot = off;
+  // a one-cell coarsest level is solved exactly by one sweep
+  A.coarse_sweeps = h->lv.back().nc == 1 ? 1 : h->coarse_sweeps;
+  DBS_LAUNCH(h, KC_COARSE, k_bottom<R>, dim3(1), dim3(1024), A);
+}
+
 template <typename R, typename B>
-static void vcycle(Handle *h, const R *rAUr, const B *b0, R *z0) {
-  dim3 blk(BX, BY);
-  const Geom &G = h->G;
-  const int nl = (int)h->lv.size();
-  if (nl == 1) {
-    // single level: symmetric sweeps on the fine grid
-    for (int s = 0; s < h->mg_pre; s++) {
-      DBS_LAUNCH(h, KC_SMOOTH0, (k_smooth0<R, B>), h->grid, blk, G, rAUr, b0, z0, 0, s == 0);
-      DBS_LAUNCH(h, KC_SMOOTH0, (k_smooth0<R, B>), h->grid, blk, G, rAUr, b0, z0, 1, 0);
-    }
-    for (int s = 0; s < h->mg_post; s++) {
-      DBS_LAUNCH(h, KC_SMOOTH0, (k_smooth0<R, B>), h->grid, blk, G, rAUr, b0, z0, 1, 0);
-      DBS_LAUNCH(h, KC_SMOOTH0, (k_smooth0<R, B>), h->grid, blk, G, rAUr, b0, z0, 0, 0);
-    }
-    return;
-  }
-  // down
-  for (int s = 0; s < h->mg_pre; s++) {
-    DBS_LAUNCH(h, KC_SMOOTH0, (k_smooth0<R, B>), h->grid, blk, G, rAUr, b0, z0, 0, s == 0);
-    DBS_LAUNCH(h, KC_SMOOTH0, (k_smooth0<R, B>), h->grid, blk, G, rAUr, b0, z0, 1, 0);
-  }
-  {
-    Level &C = h->lv[1];
-    DBS_LAUNCH(h, KC_RESTRICT0, (k_restrict0<R, B>), C.grid, blk, G, C.n[0], C.n[1], C.n[2],
-               rAUr, b0, (const R *)z0, lb<R>(C));
-  }
-  for (int l = 1; l < nl - 1; l++) {
-    Level &L = h->lv[l];
-    Level &C = h->lv[l + 1];
-    for (int s = 0; s < h->mg_pre; s++) {
-      DBS_LAUNCH(h, KC_SMOOTHC, k_smoothc<R>, L.grid, blk, view<R>(L), (const R *)lb<R>(L),
-                 lx<R>(L), 0, s == 0);
-      DBS_LAUNCH(h, KC_SMOOTHC, k_smoothc<R>, L.grid, blk, view<R>(L), (const R *)lb<R>(L),
-                 lx<R>(L), 1, 0);
-    }
-    DBS_LAUNCH(h, KC_RESTRICTC, k_restrictc<R>, C.grid, blk, view<R>(L), C.n[0], C.n[1], C.n[2],
-               (const R *)lb<R>(L), (const R *)lx<R>(L), lb<R>(C));
-  }
-  {
-    Level &L = h->lv[nl - 1];
-    DBS_LAUNCH(h, KC_COARSE, k_coarse_solve<R>, dim3(1), dim3(1024), view<R>(L),
-               (const R *)lb<R>(L), lx<R>(L), h->coarse_sweeps);
-  }
-  // up
-  for (int l = nl - 2; l >= 1; l--) {
-    Level &L = h->lv[l];
-    Level &C = h->lv[l + 1];
-    DBS_LAUNCH(h, KC_PROLONGC, k_prolong<R>, L.grid, blk, L.n[0], L.n[1], L.n[2], C.n[0], C.n[1],
-               (const R *)lx<R>(C), lx<R>(L));
-    for (int s = 0; s < h->mg_post; s++) {
-      DBS_LAUNCH(h, KC_SMOOTHC, k_smoothc<R>, L.grid, blk, view<R>(L), (const R *)lb<R>(L),
-                 lx<R>(L), 1, 0);
-      DBS_LAUNCH(h, KC_SMOOTHC, k_smoothc<R>, L.grid, blk, view<R>(L), (const R *)lb<R>(L),
-                 lx<R>(L), 0, 0);
-    }
-  }
-  {
-    Level &C = h->lv[1];
-    DBS_LAUNCH(h, KC_PROLONG0, k_prolong<R>, h->grid, blk, G.n[0], G.n[1], G.n[2], C.n[0], C.n[1],
-               (const R *)lx<R>(C), z0);
-  }
-  for (int s = 0; s < h->mg_post; s++) {
-    DBS_LAUNCH(h, KC_SMOOTH0, (k_smooth0<R, B>), h->grid, blk, G, rAUr, b0, z0, 1, 0);
-    DBS_LAUNCH(h, KC_SMOOTH0, (k_smooth0<R, B>), h->grid, blk, G, rAUr, b0, z0, 0, 0);
+static void smooth_level(Handle *h, int l, const Op<R> &o, const B *b, R *x, bool down) {
+  auto &S = shapes(h);
+  const int cls = l == 0 ? KC_SMOOTH0 : KC_SMOOTHC;
+  const int sweeps = down ? h->mg_pre : h->mg_post;
+  for (int s = 0; s < sweeps; s++) {
+    const int first = down ? 0 : 1;
+    DBS_LAUNCH(h, cls, (k_smooth<R, B>), g1(S[l].pair), blk(), o, S[l].pair, b, x, first,
+               down && s == 0);
+    DBS_LAUNCH(h, cls, (k_smooth<R, B>), g1(S[l].pair), blk(), o, S[l].pair, b, x, 1 - first, 0);
   }
 }
 
-static void finalize(Handle *h, int two, int slot, int slot2, int op) {
-  DBS_LAUNCH(h, KC_FINALIZE, k_finalize, dim3(1), dim3(1024), (const double *)h->partials,
-             h->nblocks, two, h->scal, slot, slot2, op);
+// fine-level half sweep with the 2.5-D kernel
+template <typename R, typename B>
+static void smooth_fine(Handle *h, const Op<R> &o, const B *b, const R *xin, R *xout, int color,
+                        int mode, const R *xc, int cn0, int cn1) {
+  const ZG2 &z = shapes(h)[0].sm;
+  const dim3 g(nblk2(z)), t(64, TY2);
+  if (mode == SM_ZERO)
+    DBS_LAUNCH(h, KC_SMOOTH0, (k_smooth25<R, B, SM_ZERO>), g, t, o, z, b, xin, xout, color, xc,
+               cn0, cn1);
+  else if (mode == SM_PROLONG)
+    DBS_LAUNCH(h, KC_PROLONG0, (k_smooth25<R, B, SM_PROLONG>), g, t, o, z, b, xin, xout, color, xc,
+               cn0, cn1);
+  else
+    DBS_LAUNCH(h, KC_SMOOTH0, (k_smooth25<R, B, SM_NORMAL>), g, t, o, z, b, xin, xout, color, xc,
+               cn0, cn1);
 }
+
+// z = M r: one V-cycle.  b0 is the fine right-hand side (r); z0 and z1 are
+// the two fine correction buffers; returns the one holding the result.
+template <typename R, typename B>
+static R *vcycle(Handle *h, const R *rAUr, const B *b0, R *z0, R *z1) {
+  auto &S = shapes(h);
+  const int nl = (int)h->lv.size();
+  Op<R> o0 = op_of<R>(h, 0, rAUr);
+  if (nl == 1) {
+    for (int s = 0; s < h->mg_pre; s++) {
+      smooth_fine<R, B>(h, o0, b0, z0, z0, 0, s == 0 ? SM_ZERO : SM_NORMAL, nullptr, 0, 0);
+      smooth_fine<R, B>(h, o0, b0, z0, z0, 1, SM_NORMAL, nullptr, 0, 0);
+    }
+    for (int s = 0; s < h->mg_post; s++) {
+      smooth_fine<R, B>(h, o0, b0, z0, z0, 1, SM_NORMAL, nullptr, 0, 0);
+      smooth_fine<R, B>(h, o0, b0, z0, z0, 0, SM_NORMAL, nullptr, 0, 0);
+    }
+    return z0;
+  }
+  // fine level down: red (zero guess), black, ...; red-only restriction
+  for (int s = 0; s < h->mg_pre; s++) {
+    smooth_fine<R, B>(h, o0, b0, z0, z0, 0, s == 0 ? SM_ZERO : SM_NORMAL, nullptr, 0, 0);
+    smooth_fine<R, B>(h, o0, b0, z0, z0, 1, SM_NORMAL, nullptr, 0, 0);
+  }
+  {
+    Level &C = h->lv[1];
+    const ZG2 &z = S[0].rs;
+    DBS_LAUNCH(h, KC_RESTRICT0, (k_restrict25<R, B>), dim3(nblk2(z)), dim3(64, TY2), o0, z, b0,
+               (const R *)z0, lb<R>(C), C.n[0], C.n[1]);
+  }
+  for (int l = 1; l < h->bottom; l++) {
+    Op<R> o = op_of<R>(h, l, rAUr);
+    Level &L = h->lv[l];
+    Level &C = h->lv[l + 1];
+    smooth_level<R, R>(h, l, o, (const R *)lb<R>(L), lx<R>(L), true);
+    DBS_LAUNCH(h, KC_RESTRICTC, (k_restrict<R, R>), g1(S[l + 1].one), blk(), o, S[l + 1].one,
+               C.n[0], C.n[1], C.n[2], (const R *)lb<R>(L), (const R *)lx<R>(L), lb<R>(C));
+  }
+  run_bottom<R>(h);
+  for (int l = h->bottom - 1; l >= 1; l--) {
+    Op<R> o = op_of<R>(h, l, rAUr);
+    Level &L = h->lv[l];
+    Level &C = h->lv[l + 1];
+    DBS_LAUNCH(h, KC_PROLONGC, k_prolong<R>, g1(S[l].one), blk(), L.n[0], L.n[1], L.n[2],
+               S[l].one, C.n[0], C.n[1], (const R *)lx<R>(C), lx<R>(L));
+    smooth_level<R, R>(h, l, o, (const R *)lb<R>(L), lx<R>(L), false);
+  }
+  // fine level up: the prolongation rides on the first (black) half sweep
+  Level &C = h->lv[1];
+  for (int s = 0; s < h->mg_post; s++) {
+    if (s == 0)
+      smooth_fine<R, B>(h, o0, b0, z0, z1, 1, SM_PROLONG, (const R *)lx<R>(C), C.n[0], C.n[1]);
+    else
+      smooth_fine<R, B>(h, o0, b0, z1, z1, 1, SM_NORMAL, nullptr, 0, 0);
+    smooth_fine<R, B>(h, o0, b0, z1, z1, 0, SM_NORMAL, nullptr, 0, 0);
+  }
+  return z1;
+}
+
+static void finalize(Handle *h, int two, int slot, int slot2, int op, int n = -1) {
+  DBS_LAUNCH(h, KC_FINALIZE, k_finalize, dim3(1), dim3(1024), (const double *)h->partials,
+             n < 0 ? h->red_blocks : n, two, h->scal, slot, slot2, op);
+}
+
 
 static double fetch(Handle *h, int slot) {
-  hipMemcpyAsync(h->hscal, h->scal, sizeof(double) * S_NSCAL, hipMemcpyDeviceToHost, h->stream);
-  hipStreamSynchronize(h->stream);
+  (void)hipMemcpyAsync(h->hscal, h->scal, sizeof(double) * S_NSCAL, hipMemcpyDeviceToHost, h->stream);
+  (void)hipStreamSynchronize(h->stream);
   return h->hscal[slot];
 }
 
 static void remove_mean(Handle *h, double *x) {
-  dim3 blk(BX, BY);
-  DBS_LAUNCH(h, KC_MISC, k_sum, h->grid, blk, h->G, (const double *)x, h->partials);
+  const ZG &z = shapes(h)[0].one;
+  const Geom &G = h->G;
+  DBS_LAUNCH(h, KC_MISC, k_sum, g1(z), blk(), G.n[0], G.n[1], G.n[2], z, (const double *)x,
+             h->partials);
   finalize(h, 0, S_SUM, 0, FIN_STORE);
-  DBS_LAUNCH(h, KC_MISC, k_sub_mean, h->grid, blk, h->G, (const double *)h->scal, x);
+  DBS_LAUNCH(h, KC_MISC, k_sub_mean, g1(z), blk(), G.n[0], G.n[1], G.n[2], z,
+             (const double *)h->scal, x);
+}
+
+static void dot_self(Handle *h, const double *a, int slot) {
+  const ZG &z = shapes(h)[0].one;
+  const Geom &G = h->G;
+  DBS_LAUNCH(h, KC_DOT, k_dot2<double>, g1(z), blk(), G.n[0], G.n[1], G.n[2], z, a, a,
+             (const double *)nullptr, h->partials);
+  finalize(h, 0, slot, 0, FIN_STORE);
 }
 
 // true residual r = b - A x; returns ||r|| and sets ||b||
 static double true_residual(Handle *h, const double *rAU, const double *b, const double *x,
                             double *nb) {
-  dim3 blk(BX, BY);
-  DBS_LAUNCH(h, KC_SPMV, k_resid0, h->grid, blk, h->G, rAU, b, x, h->r, h->partials, h->nblocks);
-  finalize(h, 1, S_RR, S_BB, FIN_STORE);
+  const ZG2 &z = shapes(h)[0].st;
+  Op<double> o = op_of<double>(h, 0, rAU);
+  DBS_LAUNCH(h, KC_SPMV, k_stencil25<1>, dim3(nblk2(z)), dim3(64, TY2), o, z, x, b, h->r,
+             h->partials);
+  finalize(h, 1, S_RR, S_BB, FIN_STORE, nblk2(z));
   if (!h->G.has_outlet) {
     remove_mean(h, h->r);
-    dim3 blk2(BX, BY);
-    DBS_LAUNCH(h, KC_DOT, k_dot_rz<double>, h->grid, blk2, h->G, (const double *)h->r,
-               (const double *)h->r, (const double *)nullptr, h->partials, h->nblocks);
-    finalize(h, 0, S_RR, 0, FIN_STORE);
+    dot_self(h, h->r, S_RR);
   }
   fetch(h, S_RR);
   *nb = sqrt(h->hscal[S_BB]);
   return sqrt(h->hscal[S_RR]);
 }
 
-// z = M r (FP32 V-cycle on an FP32 copy of r in the mixed form)
+// z = M r (FP32 V-cycle on an FP32 copy of r in the mixed form); returns z
 template <typename R>
-static void precondition(Handle *h, const R *rAUr, R *zR) {
-  dim3 blk(BX, BY);
+static R *precondition(Handle *h, const R *rAUr) {
+  const ZG &z = shapes(h)[0].one;
+  const Geom &G = h->G;
   if (std::is_same<R, float>::value) {
-    DBS_LAUNCH(h, KC_MISC, k_cast<float>, h->grid, blk, h->G, (const double *)h->r, h->rf);
-    vcycle<R, R>(h, rAUr, (const R *)h->rf, zR);
-  } else {
-    vcycle<R, double>(h, rAUr, (const double *)h->r, zR);
+    DBS_LAUNCH(h, KC_MISC, k_cast<float>, g1(z), blk(), G.n[0], G.n[1], G.n[2], z,
+               (const double *)h->r, h->rf);
+    return (R *)vcycle<float, float>(h, (const float *)rAUr, (const float *)h->rf, h->lv[0].xf,
+                                     h->zf2);
   }
+  return (R *)vcycle<double, double>(h, (const double *)rAUr, (const double *)h->r, h->z, h->z2);
 }
 
 template <typename R>
 static int pcg(Handle *h, const double *rAU, const double *b, double *x, int *iters,
                double *relres) {
-  dim3 blk(BX, BY);
   const Geom &G = h->G;
+  const ZG &z = shapes(h)[0].one;
   const bool flex = std::is_same<R, float>::value;
   const R *rAUr;
   if (flex) {
     float *rf = h->lv[0].bf;
-    DBS_LAUNCH(h, KC_MISC, k_cast<float>, h->grid, blk, G, rAU, rf);
+    DBS_LAUNCH(h, KC_MISC, k_cast<float>, g1(z), blk(), G.n[0], G.n[1], G.n[2], z, rAU, rf);
     rAUr = (const R *)rf;
   } else {
     rAUr = (const R *)rAU;
   }
-  build_hierarchy<R>(h, rAU);
-  // closed domains: the right-hand side must be compatible (zero mean)
+  build_hierarchy<R>(h, rAUr);
   double nb;
   double nr = true_residual(h, rAU, b, x, &nb);
   if (!G.has_outlet) {
-    // ||b|| of the projected right-hand side: project a copy into z
-    hipMemcpyAsync(h->z, b, sizeof(double) * G.nc, hipMemcpyDeviceToDevice, h->stream);
+    // closed domain: norm of the projected (compatible) right-hand side
+    (void)hipMemcpyAsync(h->z, b, sizeof(double) * G.nc, hipMemcpyDeviceToDevice, h->stream);
     remove_mean(h, h->z);
-    DBS_LAUNCH(h, KC_DOT, k_dot_rz<double>, h->grid, blk, G, (const double *)h->z,
-               (const double *)h->z, (const double *)nullptr, h->partials, h->nblocks);
-    finalize(h, 0, S_BB, 0, FIN_STORE);
+    dot_self(h, h->z, S_BB);
     nb = sqrt(fetch(h, S_BB));
   }
   const double norm = nb > 0.0 ? nb : nr;
   const double tol = h->ctl.p_tol;
   int it = 0, rc = DBS_OK;
-  R *zR = flex ? (R *)h->lv[0].xf : (R *)h->z;
+  R *zR = nullptr;
   R *zold = flex ? (R *)h->zoldf : nullptr;
+  const int n0 = G.n[0], n1 = G.n[1], n2 = G.n[2];
+  const LShape &S0 = shapes(h)[0];
   if (norm > 0.0 && nr > tol * norm) {
     const int replace_every = flex ? 8 : 0;
-    // z = M r, p = z, rz = r.z
-    precondition<R>(h, rAUr, zR);
-    DBS_LAUNCH(h, KC_DOT, k_dot_rz<R>, h->grid, blk, G, (const double *)h->r, (const R *)zR,
-               (const R *)nullptr, h->partials, h->nblocks);
+    Op<double> o = op_of<double>(h, 0, rAU);
+    zR = precondition<R>(h, rAUr);
+    DBS_LAUNCH(h, KC_DOT, k_dot2<R>, g1(z), blk(), n0, n1, n2, z, (const double *)h->r,
+               (const R *)zR, (const R *)nullptr, h->partials);
     finalize(h, 0, S_RZ, 0, FIN_STORE);
-    DBS_LAUNCH(h, KC_XPBY, k_xpby<R>, h->grid, blk, G, (const double *)h->scal, (const R *)zR,
-               h->pv, 1, zold);
+    DBS_LAUNCH(h, KC_XPBY, k_xpby<R>, g1(z), blk(), n0, n1, n2, z, (const double *)h->scal,
+               (const R *)zR, h->pv, 1, zold);
     for (;;) {
       if (it >= h->ctl.p_maxit) { rc = DBS_ENOCONV; break; }
-      DBS_LAUNCH(h, KC_SPMV, k_spmv0_dot, h->grid, blk, G, rAU, (const double *)h->pv, h->q,
-                 h->partials);
-      finalize(h, 0, S_PQ, 0, FIN_ALPHA);
-      DBS_LAUNCH(h, KC_AXPY, k_axpy_dot, h->grid, blk, G, (const double *)h->scal,
+      DBS_LAUNCH(h, KC_SPMV, k_stencil25<0>, dim3(nblk2(S0.st)), dim3(64, TY2), o, S0.st,
+                 (const double *)h->pv, (const double *)nullptr, h->q, h->partials);
+      finalize(h, 0, S_PQ, 0, FIN_ALPHA, nblk2(S0.st));
+      DBS_LAUNCH(h, KC_AXPY, k_axpy_dot, g1(z), blk(), n0, n1, n2, z, (const double *)h->scal,
                  (const double *)h->pv, (const double *)h->q, x, h->r, h->partials);
       it++;
       bool replaced = false;
-      if (replace_every && it % replace_every == 0) {
+      if (replace_every > 0 && it % (replace_every > 0 ? replace_every : 1) == 0) {
         // residual replacement: the true FP64 residual takes the recursive one's place
         nr = true_residual(h, rAU, b, x, &nb);
         replaced = true;
@@ -754,22 +1318,21 @@ static int pcg(Handle *h, const double *rAU, const double *b, double *x, int *it
         nr = true_residual(h, rAU, b, x, &nb);
         if (nr <= tol * norm) break;
       }
-      precondition<R>(h, rAUr, zR);
+      zR = precondition<R>(h, rAUr);
       if (flex) {
-        DBS_LAUNCH(h, KC_DOT, k_dot_rz<R>, h->grid, blk, G, (const double *)h->r, (const R *)zR,
-                   (const R *)zold, h->partials, h->nblocks);
+        DBS_LAUNCH(h, KC_DOT, k_dot2<R>, g1(z), blk(), n0, n1, n2, z, (const double *)h->r,
+                   (const R *)zR, (const R *)zold, h->partials);
         finalize(h, 1, S_RZNEW, S_RZOLD, FIN_BETA_FLEX);
       } else {
-        DBS_LAUNCH(h, KC_DOT, k_dot_rz<R>, h->grid, blk, G, (const double *)h->r, (const R *)zR,
-                   (const R *)nullptr, h->partials, h->nblocks);
+        DBS_LAUNCH(h, KC_DOT, k_dot2<R>, g1(z), blk(), n0, n1, n2, z, (const double *)h->r,
+                   (const R *)zR, (const R *)nullptr, h->partials);
         finalize(h, 0, S_RZNEW, 0, FIN_BETA);
       }
-      DBS_LAUNCH(h, KC_XPBY, k_xpby<R>, h->grid, blk, G, (const double *)h->scal, (const R *)zR,
-                 h->pv, 0, zold);
+      DBS_LAUNCH(h, KC_XPBY, k_xpby<R>, g1(z), blk(), n0, n1, n2, z, (const double *)h->scal,
+                 (const R *)zR, h->pv, 0, zold);
     }
   }
   if (!G.has_outlet) remove_mean(h, x);
-  // report the true residual
   nr = true_residual(h, rAU, b, x, &nb);
   if (iters) *iters = it;
   if (relres) *relres = norm > 0.0 ? nr / norm : 0.0;
