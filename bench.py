@@ -38,14 +38,45 @@ def alg_bytes_per_cell(cls: str, rsize: int) -> float:
     """
     s = rsize
     return {
+        # rAU (all), b (own colour), x (other colour) read; own colour written
         "smooth_fine": s + 0.5 * s + 0.5 * s + 0.5 * s,
-        "restrict_fine": 3 * s + s / 8.0,
-        "prolong_fine": 2 * s + s / 8.0,
+        # zero initial guess: rAU and own-colour b read, both colours written
+        "smooth_fine_zero": s + 0.5 * s + s,
+        # prolongation fused in the first up-sweep: x and the coarse
+        # correction read, rAU and own-colour b read, both colours written
+        "prolong_fine": s + s / 8.0 + s + 0.5 * s + s,
+        # red residuals only: x and rAU read, red b read, coarse b written
+        "restrict_fine": 2 * s + 0.5 * s + s / 8.0,
         "spmv": 24.0,                  # rAU, p read; q written (FP64)
         "axpy": 48.0,                  # x, p, r, q read; x, r written
         "dot": 8.0 + s + (s if s == 4 else 0.0),
         "xpby": 8.0 + s + 8.0 + (s if s == 4 else 0.0),
     }.get(cls, 0.0)
+
+
+def measured_traffic(kernel, precision, n):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summaries (FETCH_SIZE + WRITE_SIZE, each scaled by the same counter's
+    reading for a plain copy of known size).  None when no summary matches
+    this kernel, precision and size, or when the kernel source has changed
+    since the counters were taken."""
+    import glob
+    import hashlib
+    import re
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+        m = re.search(r"<!-- bench-traffic (\{.*?\}) -->", open(path).read())
+        if not m:
+            continue
+        rec = json.loads(m.group(1))
+        if (rec.get("kernel"), rec.get("precision"), rec.get("n")) != (kernel, precision, n):
+            continue
+        src = os.path.join(ROOT, rec["source"])
+        if not os.path.exists(src):
+            continue
+        if hashlib.sha1(open(src, "rb").read()).hexdigest() != rec["source_sha1"]:
+            continue
+        return float(rec["traffic_bytes_per_launch"]), os.path.relpath(path, ROOT)
+    return None, None
 
 
 def time_solver(case, precision, steps, warmup, prof_class=None, profile_all=False):
@@ -82,7 +113,7 @@ def time_solver(case, precision, steps, warmup, prof_class=None, profile_all=Fal
             "stats": st}
 
 
-def cpu_baseline(n=48, steps=3):
+def cpu_baseline(n=64, steps=2):
     sys.path.insert(0, os.path.join(ROOT, "oracle"))
     import oracle as O
     from paper_2003_08374_amd import workloads as W
@@ -115,6 +146,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 leg")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--kernel", default=None, help="kernel class for the roofline")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -128,6 +161,15 @@ def main():
         print("bench.py needs a HIP device", file=sys.stderr)
         sys.exit(1)
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        # a plain copy of known size: 2^27 doubles = 1 GiB read + 1 GiB written
+        a = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_each_way": a.numel() * 8, "launches": 3}))
+        return
     from paper_2003_08374_amd import workloads as W
 
     case = W.fractured_3d(n=args.n, seed_k=3, seed_phi=4, fractures="planes", frac_seed=5,
@@ -147,10 +189,15 @@ def main():
     if launches and per_cell:
         avg_s = kms / launches * 1e-3
         achieved = per_cell * cells / avg_s / 1e9
+        traffic, tsrc = measured_traffic(kname, args.precision, args.n)
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": kname, "bytes_per_launch": per_cell * cells,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": traffic,
+                "kernel": kname, "alg_bytes_per_launch": per_cell * cells,
                 "avg_launch_us": round(avg_s * 1e6, 2), "launches": launches}
+        if traffic:
+            roof["traffic_rate_GBs"] = round(traffic / avg_s / 1e9, 1)
+            roof["traffic_source"] = tsrc
 
     fp64 = None
     if not args.no_fp64 and args.precision == "mixed":

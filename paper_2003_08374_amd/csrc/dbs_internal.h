@@ -16,7 +16,7 @@ enum KClass {
   KC_SPMV, KC_AXPY, KC_DOT, KC_XPBY, KC_FINALIZE,
   KC_SMOOTH0, KC_RESTRICT0, KC_PROLONG0,
   KC_SMOOTHC, KC_RESTRICTC, KC_PROLONGC, KC_COARSE, KC_BUILD_COARSE,
-  KC_STATS, KC_MISC, KC_COUNT
+  KC_STATS, KC_MISC, KC_SMOOTH0_ZERO, KC_COUNT
 };
 
 struct Level {

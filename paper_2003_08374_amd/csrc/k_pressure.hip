@@ -1125,7 +1125,7 @@ static void smooth_fine(Handle *h, const Op<R> &o, const B *b, const R *xin, R *
   const ZG2 &z = shapes(h)[0].sm;
   const dim3 g(nblk2(z)), t(64, TY2);
   if (mode == SM_ZERO)
-    DBS_LAUNCH(h, KC_SMOOTH0, (k_smooth25<R, B, SM_ZERO>), g, t, o, z, b, xin, xout, color, xc,
+    DBS_LAUNCH(h, KC_SMOOTH0_ZERO, (k_smooth25<R, B, SM_ZERO>), g, t, o, z, b, xin, xout, color, xc,
                cn0, cn1);
   else if (mode == SM_PROLONG)
     DBS_LAUNCH(h, KC_PROLONG0, (k_smooth25<R, B, SM_PROLONG>), g, t, o, z, b, xin, xout, color, xc,
