@@ -158,14 +158,68 @@ const char *dbs_kernel_name(int cls);
 int dbs_kernel_classes(void);
 void dbs_reset_profiling(dbs_handle *h);
 
-/* Tests only.  Solve the p_rgh pressure equation of this handle's mesh and
-   boundary conditions, -div(rAU_f grad x) with outlet faces as Dirichlet
+/* ------------------------------------------------------------- batches
+ *
+ * A batch advances n independent samples (meshes of uneven sizes, each with
+ * its own porosity, permeability, boundary values and state) together: each
+ * stage of the step is one launch over all samples, and each sample's
+ * pressure solve runs its own CG iterations (converged samples are masked
+ * off), so a sample's result does not depend on the rest of the batch.  The
+ * batch is not in the paper; it serves many porous samples at once.
+ *
+ * grids[i] and bcs[6*i .. 6*i+5] describe sample i; physics and controls are
+ * shared.  A handle from dbs_create is a batch of one; the single-sample
+ * calls (dbs_set_static, dbs_set_state, dbs_get_state, dbs_get_stats and
+ * their _dev forms) act on sample 0.  dbs_step advances every sample;
+ * DBS_ENOCONV, DBS_ENAN and DBS_EBOUNDS are reported if any sample raises
+ * them, DBS_ECOURANT names the sample in dbs_last_error.  Arrays per sample
+ * have the single-mesh layouts above.  Errors: DBS_EINVAL for n < 1, a bad
+ * sample or an index outside [0, n). */
+int dbs_batch_create(int n, const dbs_grid *grids, const dbs_physics *phys, const dbs_bc *bcs,
+                     const dbs_controls *ctl, dbs_handle **out);
+int dbs_batch_size(const dbs_handle *h);
+int dbs_batch_set_static(dbs_handle *h, int i, const double *phi, const double *kinv);
+int dbs_batch_set_state(dbs_handle *h, int i, const double *alpha, const double *U,
+                        const double *p_rgh, const double *F);
+int dbs_batch_get_state(dbs_handle *h, int i, double *alpha, double *U, double *p_rgh,
+                        double *p, double *F);
+int dbs_batch_set_state_dev(dbs_handle *h, int i, const double *alpha, const double *U,
+                            const double *p_rgh, const double *F, void *stream);
+int dbs_batch_get_state_dev(dbs_handle *h, int i, double *alpha, double *U, double *p_rgh,
+                            double *p, double *F, void *stream);
+int dbs_batch_get_stats(dbs_handle *h, int i, dbs_stats *out);
+
+/* Graph mode (on != 0): each step is replayed from a captured HIP graph.
+   The first step after switching runs eagerly and sets a PCG iteration
+   budget per corrector (the largest count over the samples plus a margin);
+   the captured step runs exactly that many iterations with converged
+   samples masked and no host synchronisation inside.  If a sample has not
+   converged within the budget, the step is redone eagerly from a saved copy
+   of the state and the budget grows, so results equal eager stepping.  The
+   saved state costs 5 cell arrays and one face array of device memory.
+   on > 1 starts from a budget of on - 1 iterations instead of measuring it
+   (this exercises the recovery path when the budget is too small). */
+int dbs_set_graph(dbs_handle *h, int on);
+
+/* Autotuner: times the pressure solve of the current state's first
+   corrector under candidate settings and keeps the fastest that converges:
+   red-black sweeps per level (1..3, pre = post), the depth at which the
+   single work-group bottom takes over (bottom_shift 0 or 1 levels coarser
+   than the first that fits in LDS), then the planes per fine-level tile
+   (kz 2..16).  The state is unchanged afterwards.  Outputs may be NULL;
+   *ms receives the best solve time in milliseconds. */
+int dbs_autotune(dbs_handle *h, int *kz, int *sweeps, int *bottom_shift, double *ms);
+/* Set the same knobs by hand (kz = 0: the launch-size heuristic). */
+int dbs_set_tuning(dbs_handle *h, int kz, int sweeps, int bottom_shift);
+
+/* Tests only (single-sample handles).  Solve the p_rgh pressure equation of
+   this handle's mesh and boundary conditions, -div(rAU_f grad x) with outlet faces as Dirichlet
    faces (the operator of Eq. (pressure_predictor)), for host arrays rAU and
    b; x holds the initial guess and receives the solution. */
 int dbs_debug_pressure_solve(dbs_handle *h, const double *rAU, const double *b, double *x,
                              int *iters, double *relres);
 
-/* Tests only.  Run one step and copy intermediate fields to host arrays
+/* Tests only (single-sample handles).  Run one step and copy intermediate fields to host arrays
    (any pointer may be NULL): the MULES antidiffusive flux A (faces), 1/a_P
    (cells), momentum source Shat and predicted U (3 x cells), and from the
    first corrector HbyA (3 x cells), phiHbyA (faces) and the pressure

@@ -1,9 +1,11 @@
 // C ABI of the DBS PISO step (declared in include/dbs.h): validation, device
-// state, the step sequence of Sec. 3.2, state transfer, statistics and event
+// state, the step sequence of Sec. 3.2 over a batch of samples, state
+// transfer, statistics, graph-captured steps, the autotuner and event
 // timing.  No C++ exception leaves this file.
 #include <math.h>
 #include <string.h>
 
+#include <algorithm>
 #include <new>
 #include <string>
 
@@ -62,7 +64,7 @@ void prof_collect(Handle *h) {
 // ------------------------------------------------------------- statistics
 
 // per block: min alpha, max alpha, sum phi alpha V, max Courant, non-finite count
-__global__ void __launch_bounds__(NTHREADS) k_stats(Geom G, const double *__restrict__ alpha,
+__global__ void __launch_bounds__(NTHREADS) k_stats(Segs SG, const double *__restrict__ alpha,
                                                     const double *__restrict__ U,
                                                     const double *__restrict__ prgh,
                                                     const double *__restrict__ phi,
@@ -70,7 +72,7 @@ __global__ void __launch_bounds__(NTHREADS) k_stats(Geom G, const double *__rest
                                                     double *__restrict__ part, int nb) {
   __shared__ double lds[5][NTHREADS / 64];
   double amin = 1e300, amax = -1e300, vol = 0.0, co = 0.0, bad = 0.0;
-  FOR_CELLS(G, P) {
+  FOR_CELLS(SG, G, P) {
     const double a = alpha[P.c];
     amin = fmin(amin, a);
     amax = fmax(amax, a);
@@ -82,7 +84,7 @@ __global__ void __launch_bounds__(NTHREADS) k_stats(Geom G, const double *__rest
     }
     co = fmax(co, G.dt * out / (phi[P.c] * G.V));
     bool ok = isfinite(a) && isfinite(prgh[P.c]);
-    for (int d = 0; d < 3; d++) ok = ok && isfinite(U[(size_t)d * G.nc + P.c]);
+    for (int d = 0; d < 3; d++) ok = ok && isfinite(U[(size_t)d * G.vs + P.c]);
     bad += ok ? 0.0 : 1.0;
   }
   amin = wave_min(amin);
@@ -102,16 +104,18 @@ __global__ void __launch_bounds__(NTHREADS) k_stats(Geom G, const double *__rest
       r[0] = fmin(r[0], lds[0][w]); r[1] = fmax(r[1], lds[1][w]); r[2] += lds[2][w];
       r[3] = fmax(r[3], lds[3][w]); r[4] += lds[4][w];
     }
-    for (int q = 0; q < 5; q++) part[q * nb + blockIdx.x] = r[q];
+    for (int q = 0; q < 5; q++) part[q * nb + cell_gb] = r[q];
   }
 }
 
-__global__ void __launch_bounds__(1024) k_stats_final(const double *__restrict__ part, int nb,
-                                                      double *__restrict__ out) {
-  __shared__ double lds[5][16];
-  const int t = threadIdx.x;
+// one block per sample: reduce the sample's block partials
+__global__ void __launch_bounds__(256) k_stats_final(const double *__restrict__ part, int nb,
+                                                     const int *__restrict__ bp,
+                                                     double *__restrict__ out) {
+  __shared__ double lds[5][4];
+  const int t = threadIdx.x, s = blockIdx.x;
   double r[5] = {1e300, -1e300, 0.0, 0.0, 0.0};
-  for (int i = t; i < nb; i += 1024) {
+  for (int i = bp[s] + t; i < bp[s + 1]; i += 256) {
     r[0] = fmin(r[0], part[i]); r[1] = fmax(r[1], part[nb + i]); r[2] += part[2 * nb + i];
     r[3] = fmax(r[3], part[3 * nb + i]); r[4] += part[4 * nb + i];
   }
@@ -121,27 +125,26 @@ __global__ void __launch_bounds__(1024) k_stats_final(const double *__restrict__
     for (int q = 0; q < 5; q++) lds[q][t >> 6] = r[q];
   __syncthreads();
   if (t == 0) {
-    double s[5] = {1e300, -1e300, 0.0, 0.0, 0.0};
-    for (int w = 0; w < 16; w++) {
-      s[0] = fmin(s[0], lds[0][w]); s[1] = fmax(s[1], lds[1][w]); s[2] += lds[2][w];
-      s[3] = fmax(s[3], lds[3][w]); s[4] += lds[4][w];
+    double v[5] = {1e300, -1e300, 0.0, 0.0, 0.0};
+    for (int w = 0; w < 4; w++) {
+      v[0] = fmin(v[0], lds[0][w]); v[1] = fmax(v[1], lds[1][w]); v[2] += lds[2][w];
+      v[3] = fmax(v[3], lds[3][w]); v[4] += lds[4][w];
     }
-    for (int q = 0; q < 5; q++) out[q] = s[q];
+    for (int q = 0; q < 5; q++) out[s * 5 + q] = v[q];
   }
 }
 
-void cell_stats(Handle *h, double out[5]) {
+void cell_stats(Handle *h) {
   dim3 blk(BX, BY);
-  // partials holds 2 x nblocks doubles; the statistics need 5 x nblocks
-  DBS_LAUNCH(h, KC_STATS, k_stats, h->grid, blk, h->G, (const double *)h->alpha,
+  const int nb = h->cell.nblk;
+  DBS_LAUNCH(h, KC_STATS, k_stats, h->cgrid, blk, h->seg, (const double *)h->alpha,
              (const double *)h->U, (const double *)h->prgh, (const double *)h->phi,
-             (const double *)h->F, h->Qp, h->nblocks);
-  DBS_LAUNCH(h, KC_STATS, k_stats_final, dim3(1), dim3(1024), (const double *)h->Qp,
-             h->nblocks, h->scal + 16);
-  hipMemcpyAsync(h->hscal + 16, h->scal + 16, 5 * sizeof(double), hipMemcpyDeviceToHost,
+             (const double *)h->F, h->partials, nb);
+  DBS_LAUNCH(h, KC_STATS, k_stats_final, dim3(h->ns), dim3(256), (const double *)h->partials,
+             nb, (const int *)h->cell.bp, h->sstat);
+  hipMemcpyAsync(h->hsstat, h->sstat, 5 * sizeof(double) * h->ns, hipMemcpyDeviceToHost,
                  h->stream);
   hipStreamSynchronize(h->stream);
-  for (int q = 0; q < 5; q++) out[q] = h->hscal[16 + q];
 }
 
 }  // namespace dbs
@@ -158,16 +161,20 @@ static int hip_check(Handle *h, hipError_t e, const char *what) {
   return fail(h, DBS_EHIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
-static double *dmalloc(Handle *h, size_t n, int &rc) {
+static void *dmalloc_bytes(Handle *h, size_t bytes, int &rc) {
   void *p = nullptr;
   if (rc) return nullptr;
-  if (hipMalloc(&p, (n ? n : 1) * sizeof(double)) != hipSuccess) {
+  if (hipMalloc(&p, bytes ? bytes : 8) != hipSuccess) {
     rc = DBS_ENOMEM;
     return nullptr;
   }
-  hipMemsetAsync(p, 0, (n ? n : 1) * sizeof(double), h->stream);
+  if (hipMemset(p, 0, bytes ? bytes : 8) != hipSuccess) rc = DBS_EHIP;
   h->allocs.push_back(p);
-  return (double *)p;
+  return p;
+}
+
+static double *dmalloc(Handle *h, size_t n, int &rc) {
+  return (double *)dmalloc_bytes(h, n * sizeof(double), rc);
 }
 
 static bool all_finite(const double *a, size_t n) {
@@ -176,24 +183,8 @@ static bool all_finite(const double *a, size_t n) {
   return true;
 }
 
-static int validate(const dbs_grid *g, const dbs_physics *p, const dbs_bc *bc,
-                    const dbs_controls *c, std::string &msg) {
-  if (!g || !p || !bc || !c) { msg = "null argument"; return DBS_EINVAL; }
-  const int n[3] = {g->nx, g->ny, g->nz};
-  const double hh[3] = {g->dx, g->dy, g->dz};
-  long long nc = 1;
-  for (int a = 0; a < 3; a++) {
-    if (n[a] < 1 || !(hh[a] > 0.0) || !isfinite(hh[a])) { msg = "bad grid"; return DBS_EINVAL; }
-    nc *= n[a];
-    const bool e0 = bc[2 * a].kind == DBS_BC_EMPTY, e1 = bc[2 * a + 1].kind == DBS_BC_EMPTY;
-    if (e0 != e1 || (e0 && n[a] != 1)) {
-      msg = "EMPTY faces must pair on an axis of one cell";
-      return DBS_EINVAL;
-    }
-  }
-  if (nc * 4 > 2000000000LL) { msg = "mesh too large for 32-bit indices"; return DBS_EINVAL; }
-  for (int b = 0; b < 6; b++)
-    if (bc[b].kind < DBS_BC_WALL || bc[b].kind > DBS_BC_EMPTY) { msg = "bad bc kind"; return DBS_EINVAL; }
+static int validate_shared(const dbs_physics *p, const dbs_controls *c, std::string &msg) {
+  if (!p || !c) { msg = "null argument"; return DBS_EINVAL; }
   if (p->kr_model != DBS_BROOKS_COREY && p->kr_model != DBS_VAN_GENUCHTEN) { msg = "kr_model"; return DBS_EINVAL; }
   if (p->pc_model != DBS_BROOKS_COREY && p->pc_model != DBS_VAN_GENUCHTEN) { msg = "pc_model"; return DBS_EINVAL; }
   if (!(p->kr_m > 0.0) || !(1.0 - p->s_girr - p->s_lirr > 0.0)) { msg = "kr parameters"; return DBS_EINVAL; }
@@ -211,42 +202,44 @@ static int validate(const dbs_grid *g, const dbs_physics *p, const dbs_bc *bc,
   return DBS_OK;
 }
 
-// ----------------------------------------------------------------- the ABI
-
-extern "C" {
-
-int dbs_kernel_classes(void) { return KC_COUNT; }
-
-const char *dbs_kernel_name(int cls) {
-  return (cls >= 0 && cls < KC_COUNT) ? kNames[cls] : "";
+static int validate_sample(const dbs_grid *g, const dbs_bc *bc, std::string &msg) {
+  if (!g || !bc) { msg = "null argument"; return DBS_EINVAL; }
+  const int n[3] = {g->nx, g->ny, g->nz};
+  const double hh[3] = {g->dx, g->dy, g->dz};
+  for (int a = 0; a < 3; a++) {
+    if (n[a] < 1 || !(hh[a] > 0.0) || !isfinite(hh[a])) { msg = "bad grid"; return DBS_EINVAL; }
+    const bool e0 = bc[2 * a].kind == DBS_BC_EMPTY, e1 = bc[2 * a + 1].kind == DBS_BC_EMPTY;
+    if (e0 != e1 || (e0 && n[a] != 1)) {
+      msg = "EMPTY faces must pair on an axis of one cell";
+      return DBS_EINVAL;
+    }
+  }
+  if ((long long)n[0] * n[1] * n[2] * 4 > 2000000000LL) { msg = "mesh too large"; return DBS_EINVAL; }
+  for (int b = 0; b < 6; b++)
+    if (bc[b].kind < DBS_BC_WALL || bc[b].kind > DBS_BC_EMPTY) { msg = "bad bc kind"; return DBS_EINVAL; }
+  return DBS_OK;
 }
 
-int dbs_create(const dbs_grid *grid, const dbs_physics *phys, const dbs_bc bc[6],
-               const dbs_controls *ctl, dbs_handle **out) {
-  if (!out) return DBS_EINVAL;
-  *out = nullptr;
-  std::string msg;
-  int rc = validate(grid, phys, bc, ctl, msg);
-  if (rc) return rc;
-  dbs_handle *H = new (std::nothrow) dbs_handle();
-  if (!H) return DBS_ENOMEM;
-  Handle *h = &H->h;
-  Geom &G = h->G;
+static Geom make_geom(const dbs_grid *grid, const dbs_bc *bc, double dt) {
+  Geom G;
   memset(&G, 0, sizeof(G));
   G.n[0] = grid->nx; G.n[1] = grid->ny; G.n[2] = grid->nz;
   G.h[0] = grid->dx; G.h[1] = grid->dy; G.h[2] = grid->dz;
   G.nc = G.n[0] * G.n[1] * G.n[2];
+  const int nfx = (G.n[0] + 1) * G.n[1] * G.n[2];
+  const int nfy = G.n[0] * (G.n[1] + 1) * G.n[2];
+  const int nfz = G.n[0] * G.n[1] * (G.n[2] + 1);
   G.fo[0] = 0;
-  G.fo[1] = (G.n[0] + 1) * G.n[1] * G.n[2];
-  G.fo[2] = G.fo[1] + G.n[0] * (G.n[1] + 1) * G.n[2];
-  G.nf = G.fo[2] + G.n[0] * G.n[1] * (G.n[2] + 1);
+  G.fo[1] = nfx;
+  G.fo[2] = nfx + nfy;
+  G.nf = nfx + nfy + nfz;
   G.V = G.h[0] * G.h[1] * G.h[2];
   G.iV = 1.0 / G.V;
   for (int a = 0; a < 3; a++) {
     G.ih[a] = 1.0 / G.h[a];
     G.area[a] = G.V / G.h[a];
   }
-  G.dt = ctl->dt;
+  G.dt = dt;
   G.has_outlet = 0;
   for (int b = 0; b < 6; b++) {
     G.bck[b] = bc[b].kind;
@@ -256,7 +249,12 @@ int dbs_create(const dbs_grid *grid, const dbs_physics *phys, const dbs_bc bc[6]
     if (bc[b].kind == DBS_BC_OUTLET) G.has_outlet = 1;
   }
   G.dN = 1e-8 / cbrt(G.V);
-  Phys &P = h->P;
+  return G;
+}
+
+static Phys make_phys(const dbs_physics *phys) {
+  Phys P;
+  memset(&P, 0, sizeof(P));
   P.rho_l = phys->rho_l; P.rho_g = phys->rho_g; P.mu_l = phys->mu_l; P.mu_g = phys->mu_g;
   for (int a = 0; a < 3; a++) P.g[a] = phys->g[a];
   P.c_alpha = phys->c_alpha;
@@ -271,41 +269,110 @@ int dbs_create(const dbs_grid *grid, const dbs_physics *phys, const dbs_bc bc[6]
   P.a_pcirr = phys->a_pcirr;
   P.inv_span_pc = 1.0 / (phys->a_pcmax - phys->a_pcirr);
   P.eps_pc = phys->eps_pc;
+  return P;
+}
+
+static void clear_graphs(Handle *h) {
+  for (auto &kv : h->graphs) hipGraphExecDestroy(kv.second);
+  h->graphs.clear();
+}
+
+extern "C" void dbs_destroy(dbs_handle *H);
+
+static int create_impl(int n, const dbs_grid *grids, const dbs_physics *phys, const dbs_bc *bcs,
+                       const dbs_controls *ctl, dbs_handle **out) {
+  if (!out) return DBS_EINVAL;
+  *out = nullptr;
+  if (n < 1 || !grids || !bcs) return DBS_EINVAL;
+  std::string msg;
+  int rc = validate_shared(phys, ctl, msg);
+  for (int s = 0; s < n && !rc; s++) rc = validate_sample(&grids[s], &bcs[6 * s], msg);
+  if (rc) return rc;
+  dbs_handle *H = new (std::nothrow) dbs_handle();
+  if (!H) return DBS_ENOMEM;
+  Handle *h = &H->h;
+  h->ns = n;
+  h->hG.resize(n);
+  h->hrng.resize(n);
+  h->st.assign(n, dbs_stats());
+  for (auto &s : h->st) memset(&s, 0, sizeof(s));
+  // arenas: cells padded per sample to whole vector-kernel blocks
+  long long c0 = 0, f0 = 0;
+  for (int s = 0; s < n; s++) {
+    Geom G = make_geom(&grids[s], &bcs[6 * s], ctl->dt);
+    G.c0 = (int)c0;
+    for (int a = 0; a < 3; a++) G.fo[a] += (int)f0;
+    h->hrng[s] = Rng{(int)c0, G.nc, G.has_outlet ? 0 : 1, 0};
+    c0 += ((long long)G.nc + FLAT_CELLS - 1) / FLAT_CELLS * FLAT_CELLS;
+    f0 += G.nf;
+    h->hG[s] = G;
+  }
+  h->NC = c0;
+  h->NF = f0;
+  if (3 * h->NC > 2000000000LL || h->NF > 2000000000LL) {
+    delete H;
+    return DBS_EINVAL;  // 32-bit cell and face indices
+  }
+  for (int s = 0; s < n; s++) h->hG[s].vs = (int)h->NC;
+  h->P = make_phys(phys);
   h->ctl = *ctl;
   h->mg_pre = ctl->mg_pre > 0 ? ctl->mg_pre : 2;
   h->mg_post = ctl->mg_post > 0 ? ctl->mg_post : 2;
-  memset(&h->st, 0, sizeof(h->st));
   if ((rc = hip_check(h, hipStreamCreate(&h->own_stream), "hipStreamCreate"))) {
     delete H;
     return rc;
   }
   h->stream = h->own_stream;
-  h->nblocks = cell_blocks(G);
-  h->grid = dim3(h->nblocks);
-  const size_t nc = G.nc, nf = G.nf;
+  const size_t NC = (size_t)h->NC, NF = (size_t)h->NF;
   rc = DBS_OK;
-  h->phi = dmalloc(h, nc, rc); h->kinv = dmalloc(h, nc, rc);
-  h->alpha = dmalloc(h, nc, rc); h->alpha_old = dmalloc(h, nc, rc);
-  h->U = dmalloc(h, 3 * nc, rc); h->U2 = dmalloc(h, 3 * nc, rc);
-  h->prgh = dmalloc(h, nc, rc); h->p = dmalloc(h, nc, rc);
-  h->F = dmalloc(h, nf, rc);
-  h->ml = dmalloc(h, nc, rc); h->mg = dmalloc(h, nc, rc); h->pc = dmalloc(h, nc, rc);
-  h->cf = dmalloc(h, nc, rc);
-  h->A = dmalloc(h, nf, rc); h->lam = dmalloc(h, nf, rc); h->rhoPhi = dmalloc(h, nf, rc);
-  h->Qp = dmalloc(h, nc > 5 * (size_t)h->nblocks ? nc : 5 * (size_t)h->nblocks, rc);
-  h->Qm = dmalloc(h, nc, rc); h->Pin = dmalloc(h, nc, rc); h->Pout = dmalloc(h, nc, rc);
-  h->Rp = dmalloc(h, nc, rc); h->Rm = dmalloc(h, nc, rc);
-  h->rAU = dmalloc(h, nc, rc); h->Sh = dmalloc(h, 3 * nc, rc); h->B = dmalloc(h, 3 * nc, rc);
-  h->HbyA = dmalloc(h, 3 * nc, rc); h->phiH = dmalloc(h, nf, rc); h->rhs = dmalloc(h, nc, rc);
-  h->r = dmalloc(h, nc, rc); h->z = dmalloc(h, nc, rc); h->pv = dmalloc(h, nc, rc);
-  h->q = dmalloc(h, nc, rc);
-  h->partials = dmalloc(h, 2 * (size_t)h->nblocks, rc);
-  h->scal = dmalloc(h, 32, rc);
-  if (!rc && hipHostMalloc((void **)&h->hscal, 32 * sizeof(double), hipHostMallocDefault) !=
-                 hipSuccess)
+  // per-cell launch shape and flat vector shape
+  h->cell.hbp.assign(n + 1, 0);
+  h->flat.hbp.assign(n + 1, 0);
+  for (int s = 0; s < n; s++) {
+    h->cell.hbp[s + 1] = h->cell.hbp[s] + cell_blocks(h->hG[s]);
+    h->flat.hbp[s] = h->hG[s].c0 / FLAT_CELLS;
+  }
+  h->flat.hbp[n] = (int)(NC / FLAT_CELLS);
+  h->cell.nblk = h->cell.hbp[n];
+  h->flat.nblk = h->flat.hbp[n];
+  h->cell.bp = (int *)dmalloc_bytes(h, sizeof(int) * (n + 1), rc);
+  h->flat.bp = (int *)dmalloc_bytes(h, sizeof(int) * (n + 1), rc);
+  h->dG = (Geom *)dmalloc_bytes(h, sizeof(Geom) * n, rc);
+  h->rng = (Rng *)dmalloc_bytes(h, sizeof(Rng) * n, rc);
+  if (!rc) {
+    int e = 0;
+    e |= hip_check(h, hipMemcpy(h->cell.bp, h->cell.hbp.data(), sizeof(int) * (n + 1), hipMemcpyHostToDevice), "upload");
+    e |= hip_check(h, hipMemcpy(h->flat.bp, h->flat.hbp.data(), sizeof(int) * (n + 1), hipMemcpyHostToDevice), "upload");
+    e |= hip_check(h, hipMemcpy(h->dG, h->hG.data(), sizeof(Geom) * n, hipMemcpyHostToDevice), "upload");
+    e |= hip_check(h, hipMemcpy(h->rng, h->hrng.data(), sizeof(Rng) * n, hipMemcpyHostToDevice), "upload");
+    if (e) rc = DBS_EHIP;
+  }
+  h->seg = Segs{h->dG, h->cell.bp, n};
+  h->cgrid = dim3(h->cell.nblk);
+  h->phi = dmalloc(h, NC, rc); h->kinv = dmalloc(h, NC, rc);
+  h->alpha = dmalloc(h, NC, rc); h->alpha_old = dmalloc(h, NC, rc);
+  h->U = dmalloc(h, 3 * NC, rc); h->U2 = dmalloc(h, 3 * NC, rc);
+  h->prgh = dmalloc(h, NC, rc); h->p = dmalloc(h, NC, rc);
+  h->F = dmalloc(h, NF, rc);
+  h->ml = dmalloc(h, NC, rc); h->mg = dmalloc(h, NC, rc); h->pc = dmalloc(h, NC, rc);
+  h->cf = dmalloc(h, NC, rc);
+  h->A = dmalloc(h, NF, rc); h->lam = dmalloc(h, NF, rc); h->rhoPhi = dmalloc(h, NF, rc);
+  h->Qp = dmalloc(h, NC, rc); h->Qm = dmalloc(h, NC, rc); h->Pin = dmalloc(h, NC, rc);
+  h->Pout = dmalloc(h, NC, rc); h->Rp = dmalloc(h, NC, rc); h->Rm = dmalloc(h, NC, rc);
+  h->rAU = dmalloc(h, NC, rc); h->Sh = dmalloc(h, 3 * NC, rc); h->B = dmalloc(h, 3 * NC, rc);
+  h->HbyA = dmalloc(h, 3 * NC, rc); h->phiH = dmalloc(h, NF, rc); h->rhs = dmalloc(h, NC, rc);
+  h->r = dmalloc(h, NC, rc); h->z = dmalloc(h, NC, rc); h->pv = dmalloc(h, NC, rc);
+  h->q = dmalloc(h, NC, rc);
+  h->scal = dmalloc(h, (size_t)NSC * n, rc);
+  h->sstat = dmalloc(h, 5 * (size_t)n, rc);
+  h->rec = dmalloc(h, (size_t)n * 16 * 3, rc);
+  if (!rc && (hipHostMalloc((void **)&h->hscal, sizeof(double) * NSC * n, hipHostMallocDefault) != hipSuccess ||
+              hipHostMalloc((void **)&h->hflags, sizeof(int) * 2 * n, hipHostMallocDefault) != hipSuccess ||
+              hipHostMalloc((void **)&h->hsstat, sizeof(double) * 5 * n, hipHostMallocDefault) != hipSuccess ||
+              hipHostMalloc((void **)&h->hrec, sizeof(double) * 48 * n, hipHostMallocDefault) != hipSuccess))
     rc = DBS_ENOMEM;
   if (!rc) rc = pressure_setup(h);
-  if (!rc) rc = hip_check(h, hipStreamSynchronize(h->stream), "create");
+  if (!rc) rc = hip_check(h, hipDeviceSynchronize(), "create");
   if (rc) {
     dbs_destroy(H);
     return rc;
@@ -314,12 +381,319 @@ int dbs_create(const dbs_grid *grid, const dbs_physics *phys, const dbs_bc bc[6]
   return DBS_OK;
 }
 
+// ---------------------------------------------------------- sample access
+
+static int check_sample(Handle *h, int i) {
+  if (i < 0 || i >= h->ns) return fail(h, DBS_EINVAL, "sample index out of range");
+  return DBS_OK;
+}
+
+static int set_static_impl(Handle *h, int i, const double *phi, const double *kinv) {
+  if (int rc = check_sample(h, i)) return rc;
+  const Geom &G = h->hG[i];
+  const size_t nc = G.nc;
+  for (size_t c = 0; c < nc; c++) {
+    if (!(phi[c] > 0.0 && phi[c] <= 1.0)) return fail(h, DBS_EINVAL, "porosity outside (0,1]");
+    if (!(kinv[c] >= 0.0) || !isfinite(kinv[c])) return fail(h, DBS_EINVAL, "bad k^-1");
+  }
+  int rc = hip_check(h, hipMemcpyAsync(h->phi + G.c0, phi, nc * 8, hipMemcpyHostToDevice, h->stream), "copy phi");
+  if (!rc) rc = hip_check(h, hipMemcpyAsync(h->kinv + G.c0, kinv, nc * 8, hipMemcpyHostToDevice, h->stream), "copy kinv");
+  if (!rc) update_closures(h);
+  if (!rc) rc = hip_check(h, hipStreamSynchronize(h->stream), "set_static");
+  return rc;
+}
+
+static int set_state_impl(Handle *h, int i, const double *alpha, const double *U,
+                          const double *prgh, const double *F, hipMemcpyKind kind,
+                          hipStream_t s) {
+  const Geom &G = h->hG[i];
+  const size_t nc = G.nc, nf = G.nf;
+  int rc = DBS_OK;
+  if (alpha) rc = hip_check(h, hipMemcpyAsync(h->alpha + G.c0, alpha, nc * 8, kind, s), "copy alpha");
+  for (int d = 0; d < 3 && !rc && U; d++)
+    rc = hip_check(h, hipMemcpyAsync(h->U + (size_t)d * h->NC + G.c0, U + d * nc, nc * 8, kind, s), "copy U");
+  if (!rc && prgh) rc = hip_check(h, hipMemcpyAsync(h->prgh + G.c0, prgh, nc * 8, kind, s), "copy p_rgh");
+  if (!rc && F) rc = hip_check(h, hipMemcpyAsync(h->F + G.fo[0], F, nf * 8, kind, s), "copy F");
+  if (!rc) rc = hip_check(h, hipStreamSynchronize(s), "set_state");
+  if (rc) return rc;
+  if (!F) init_flux(h, i);
+  update_closures(h);
+  return hip_check(h, hipStreamSynchronize(h->stream), "set_state");
+}
+
+static int get_state_impl(Handle *h, int i, double *alpha, double *U, double *prgh, double *p,
+                          double *F, hipMemcpyKind kind, hipStream_t s) {
+  const Geom &G = h->hG[i];
+  const size_t nc = G.nc, nf = G.nf;
+  int rc = hip_check(h, hipStreamSynchronize(h->stream), "get_state");
+  if (!rc && alpha) rc = hip_check(h, hipMemcpyAsync(alpha, h->alpha + G.c0, nc * 8, kind, s), "copy alpha");
+  for (int d = 0; d < 3 && !rc && U; d++)
+    rc = hip_check(h, hipMemcpyAsync(U + d * nc, h->U + (size_t)d * h->NC + G.c0, nc * 8, kind, s), "copy U");
+  if (!rc && prgh) rc = hip_check(h, hipMemcpyAsync(prgh, h->prgh + G.c0, nc * 8, kind, s), "copy p_rgh");
+  if (!rc && p) rc = hip_check(h, hipMemcpyAsync(p, h->p + G.c0, nc * 8, kind, s), "copy p");
+  if (!rc && F) rc = hip_check(h, hipMemcpyAsync(F, h->F + G.fo[0], nf * 8, kind, s), "copy F");
+  if (!rc) rc = hip_check(h, hipStreamSynchronize(s), "get_state");
+  return rc;
+}
+
+// ----------------------------------------------------------------- stepping
+
+struct TraceOut {
+  double *A, *rAU, *Shat, *Ustar, *HbyA, *phiHbyA, *b;
+};
+
+static int copy_out(Handle *h, double *dst, const double *src, size_t n) {
+  if (!dst) return DBS_OK;
+  return hip_check(h, hipMemcpyAsync(dst, src, n * 8, hipMemcpyDeviceToHost, h->stream), "trace");
+}
+
+// copy the 3 components of a vector field of sample 0 (arena stride NC)
+static int copy_out3(Handle *h, double *dst, const double *src) {
+  if (!dst) return DBS_OK;
+  const Geom &G = h->hG[0];
+  int rc = DBS_OK;
+  for (int d = 0; d < 3; d++)
+    rc |= copy_out(h, dst + (size_t)d * G.nc, src + (size_t)d * h->NC + G.c0, G.nc);
+  return rc;
+}
+
+static int courant_check(Handle *h) {
+  if (!(h->ctl.max_courant > 0.0)) return DBS_OK;
+  cell_stats(h);
+  for (int s = 0; s < h->ns; s++) {
+    const double co = h->hsstat[5 * s + 3];
+    h->st[s].max_courant = co;
+    if (co > h->ctl.max_courant)
+      return fail(h, DBS_ECOURANT, "Courant number " + std::to_string(co) +
+                                       " above limit (sample " + std::to_string(s) + ")");
+  }
+  return DBS_OK;
+}
+
+// The step body.  budget > 0: every pressure solve runs the per-corrector
+// iteration budget with no host synchronisation (graph capture) and its
+// per-sample results go to h->rec; else results go to the statistics and
+// the largest iteration count per corrector to its_out.
+static int step_body(Handle *h, TraceOut *tr, int budget, std::vector<int> *its_out) {
+  int rc = DBS_OK;
+  alpha_stage(h);
+  if (tr) rc |= copy_out(h, tr->A, h->A, h->hG[0].nf);
+  momentum_predictor(h);
+  if (tr) {
+    rc |= copy_out(h, tr->rAU, h->rAU, h->hG[0].nc);
+    rc |= copy_out3(h, tr->Shat, h->Sh);
+    rc |= copy_out3(h, tr->Ustar, h->U);
+  }
+  int solve_rc = DBS_OK;
+  std::vector<int> its(h->ns);
+  std::vector<double> rel(h->ns);
+  for (int c = 0; c < h->ctl.n_corr; c++) {
+    corrector_assemble(h);
+    if (tr && c == 0) {
+      rc |= copy_out3(h, tr->HbyA, h->HbyA);
+      rc |= copy_out(h, tr->phiHbyA, h->phiH, h->hG[0].nf);
+      rc |= copy_out(h, tr->b, h->rhs, h->hG[0].nc);
+    }
+    const int b = budget > 0 ? h->graph_budget[c] : 0;
+    const int src = pressure_solve(h, h->rAU, h->rhs, h->prgh, b, its.data(), rel.data());
+    if (budget > 0) {
+      pressure_record(h, h->rec, c);
+    } else {
+      for (int s = 0; s < h->ns; s++) {
+        h->st[s].p_iters[c] = its[s];
+        h->st[s].p_relres[c] = rel[s];
+        if (its_out) (*its_out)[c] = std::max((*its_out)[c], its[s]);
+      }
+    }
+    if (src) solve_rc = src;
+    corrector_update(h, c == h->ctl.n_corr - 1);
+  }
+  if (rc) return fail(h, DBS_EHIP, "trace copy failed");
+  if (solve_rc) return fail(h, solve_rc, "pressure solve did not converge");
+  return DBS_OK;
+}
+
+static int eager_step(Handle *h, TraceOut *tr, std::vector<int> *its_out) {
+  int rc = courant_check(h);
+  if (rc) return rc;
+  rc = step_body(h, tr, 0, its_out);
+  for (int s = 0; s < h->ns; s++) h->st[s].steps++;
+  return rc;
+}
+
+// state arrays saved before a graph step: alpha | U (3) | p_rgh (cells), F (faces)
+static void snapshot(Handle *h, bool save) {
+  const size_t NC = (size_t)h->NC;
+  double *S = h->snap;
+  auto mv = [&](double *live, double *saved, size_t n) {
+    if (save) copy_n(h, live, saved, n);
+    else copy_n(h, saved, live, n);
+  };
+  mv(h->alpha, S, NC);
+  mv(h->U, S + NC, 3 * NC);
+  mv(h->prgh, S + 4 * NC, NC);
+  mv(h->F, S + 5 * NC, (size_t)h->NF);
+}
+
+// the host side of a step swaps buffer roles: alpha once, U once per sweep
+static void swap_roles(Handle *h) {
+  std::swap(h->alpha, h->alpha_old);
+  if (h->ctl.mom_sweeps & 1) std::swap(h->U, h->U2);
+}
+
+// One step in graph mode: the step is captured once per buffer-role
+// combination with a fixed PCG budget per corrector, then replayed.  A
+// sample that does not converge within the budget makes the step run again
+// eagerly from the saved state, and the budget grows.
+static int graph_step(Handle *h) {
+  int rc = courant_check(h);
+  if (rc) return rc;
+  const int nc = h->ctl.n_corr;
+  if (h->graph_budget[0] == 0) {
+    std::vector<int> its(nc, 0);
+    rc = step_body(h, nullptr, 0, &its);
+    for (int s = 0; s < h->ns; s++) h->st[s].steps++;
+    if (rc) return rc;
+    for (int c = 0; c < nc; c++) h->graph_budget[c] = its[c] + std::max(2, its[c] / 4);
+    return DBS_OK;
+  }
+  if (!h->snap) {
+    h->snap = dmalloc(h, 5 * (size_t)h->NC + (size_t)h->NF, rc);
+    if (rc) return fail(h, rc, "snapshot allocation");
+  }
+  const GraphKey key{h->alpha, h->U};
+  auto it = h->graphs.find(key);
+  if (it == h->graphs.end()) {
+    hipGraph_t g = nullptr;
+    rc = hip_check(h, hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal),
+                   "capture");
+    if (rc) return rc;
+    const unsigned long long pm = h->prof_mask;
+    h->prof_mask = 0;
+    snapshot(h, true);
+    step_body(h, nullptr, 1, nullptr);
+    h->prof_mask = pm;
+    rc = hip_check(h, hipStreamEndCapture(h->stream, &g), "capture");
+    if (rc) return rc;
+    hipGraphExec_t ex = nullptr;
+    rc = hip_check(h, hipGraphInstantiate(&ex, g, nullptr, nullptr, 0), "instantiate");
+    hipGraphDestroy(g);
+    if (rc) return rc;
+    it = h->graphs.emplace(key, ex).first;
+    // capturing ran the host side of the step: the roles are already swapped
+  } else {
+    swap_roles(h);
+  }
+  rc = hip_check(h, hipGraphLaunch(it->second, h->stream), "graph launch");
+  if (rc) return rc;
+  rc = hip_check(h, hipMemcpyAsync(h->hrec, h->rec, sizeof(double) * 48 * h->ns,
+                                   hipMemcpyDeviceToHost, h->stream), "records");
+  if (!rc) rc = hip_check(h, hipStreamSynchronize(h->stream), "graph step");
+  if (rc) return rc;
+  bool ok = true;
+  for (int s = 0; s < h->ns; s++)
+    for (int c = 0; c < nc; c++) {
+      const double *o = h->hrec + ((size_t)s * 16 + c) * 3;
+      h->st[s].p_iters[c] = (int)o[0];
+      h->st[s].p_relres[c] = o[1];
+      ok = ok && o[2] != 0.0;
+    }
+  if (ok) {
+    for (int s = 0; s < h->ns; s++) h->st[s].steps++;
+    return DBS_OK;
+  }
+  // redo eagerly from the saved state with the budget raised
+  swap_roles(h);
+  snapshot(h, false);
+  update_closures(h);
+  std::vector<int> its(nc, 0);
+  rc = step_body(h, nullptr, 0, &its);
+  for (int s = 0; s < h->ns; s++) h->st[s].steps++;
+  for (int c = 0; c < nc; c++)
+    h->graph_budget[c] = std::max(h->graph_budget[c] + 2, its[c] + std::max(2, its[c] / 4));
+  clear_graphs(h);
+  return rc;
+}
+
+static int finish_steps(Handle *h, int rc) {
+  int e = hip_check(h, hipStreamSynchronize(h->stream), "step");
+  if (!e) e = hip_check(h, hipGetLastError(), "kernel launch");
+  if (e) return e;
+  prof_collect(h);
+  cell_stats(h);
+  bool bad = false, out = false;
+  for (int s = 0; s < h->ns; s++) {
+    const double *v = h->hsstat + 5 * s;
+    h->st[s].alpha_min = v[0];
+    h->st[s].alpha_max = v[1];
+    h->st[s].phase_volume = v[2];
+    bad = bad || v[4] > 0.0;
+    out = out || v[0] < -h->ctl.bounds_tol || v[1] > 1.0 + h->ctl.bounds_tol;
+  }
+  if (bad) return fail(h, DBS_ENAN, "non-finite value in the state");
+  if (rc) return rc;
+  if (h->ctl.bounds_tol > 0.0 && out)
+    return fail(h, DBS_EBOUNDS, "alpha outside the admissible band");
+  return DBS_OK;
+}
+
+// time one pressure solve of the current system (from x0) under the present knobs
+static double time_solve(Handle *h, const double *x0, int *ok) {
+  hipEvent_t e0, e1;
+  hipEventCreate(&e0);
+  hipEventCreate(&e1);
+  copy_n(h, x0, h->prgh, (size_t)h->NC);
+  std::vector<int> its(h->ns);
+  std::vector<double> rel(h->ns);
+  hipEventRecord(e0, h->stream);
+  const int rc = pressure_solve(h, h->rAU, h->rhs, h->prgh, 0, its.data(), rel.data());
+  hipEventRecord(e1, h->stream);
+  hipEventSynchronize(e1);
+  float ms = 0.f;
+  hipEventElapsedTime(&ms, e0, e1);
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  *ok = rc == DBS_OK;
+  return ms;
+}
+
+static void reset_graphs(Handle *h) {
+  clear_graphs(h);
+  for (int c = 0; c < 16; c++) h->graph_budget[c] = 0;
+}
+
+// ----------------------------------------------------------------- the ABI
+
+extern "C" {
+
+int dbs_kernel_classes(void) { return KC_COUNT; }
+
+const char *dbs_kernel_name(int cls) {
+  return (cls >= 0 && cls < KC_COUNT) ? kNames[cls] : "";
+}
+
+int dbs_create(const dbs_grid *grid, const dbs_physics *phys, const dbs_bc bc[6],
+               const dbs_controls *ctl, dbs_handle **out) {
+  return create_impl(1, grid, phys, bc, ctl, out);
+}
+
+int dbs_batch_create(int n, const dbs_grid *grids, const dbs_physics *phys, const dbs_bc *bcs,
+                     const dbs_controls *ctl, dbs_handle **out) {
+  return create_impl(n, grids, phys, bcs, ctl, out);
+}
+
+int dbs_batch_size(const dbs_handle *H) { return H ? H->h.ns : 0; }
+
 void dbs_destroy(dbs_handle *H) {
   if (!H) return;
   Handle *h = &H->h;
   if (h->stream) hipStreamSynchronize(h->stream);
+  clear_graphs(h);
   for (void *p : h->allocs) hipFree(p);
   if (h->hscal) hipHostFree(h->hscal);
+  if (h->hflags) hipHostFree(h->hflags);
+  if (h->hsstat) hipHostFree(h->hsstat);
+  if (h->hrec) hipHostFree(h->hrec);
   for (hipEvent_t e : h->tm.ev) hipEventDestroy(e);
   pressure_free(h);
   if (h->own_stream) hipStreamDestroy(h->own_stream);
@@ -336,173 +710,184 @@ int dbs_set_stream(dbs_handle *H, void *stream) {
   return DBS_OK;
 }
 
-int dbs_set_static(dbs_handle *H, const double *phi, const double *kinv) {
+int dbs_batch_set_static(dbs_handle *H, int i, const double *phi, const double *kinv) {
   if (!H || !phi || !kinv) return DBS_EINVAL;
-  Handle *h = &H->h;
-  const size_t nc = h->G.nc;
-  for (size_t i = 0; i < nc; i++) {
-    if (!(phi[i] > 0.0 && phi[i] <= 1.0)) return fail(h, DBS_EINVAL, "porosity outside (0,1]");
-    if (!(kinv[i] >= 0.0) || !isfinite(kinv[i])) return fail(h, DBS_EINVAL, "bad k^-1");
-  }
-  int rc = hip_check(h, hipMemcpyAsync(h->phi, phi, nc * 8, hipMemcpyHostToDevice, h->stream), "copy phi");
-  if (!rc) rc = hip_check(h, hipMemcpyAsync(h->kinv, kinv, nc * 8, hipMemcpyHostToDevice, h->stream), "copy kinv");
-  if (!rc) update_closures(h);
-  if (!rc) rc = hip_check(h, hipStreamSynchronize(h->stream), "set_static");
-  return rc;
+  return set_static_impl(&H->h, i, phi, kinv);
 }
 
-static int set_state_impl(Handle *h, const double *alpha, const double *U, const double *prgh,
-                          const double *F, hipMemcpyKind kind, hipStream_t s) {
-  const size_t nc = h->G.nc, nf = h->G.nf;
-  int rc = DBS_OK;
-  if (alpha) rc = hip_check(h, hipMemcpyAsync(h->alpha, alpha, nc * 8, kind, s), "copy alpha");
-  if (!rc && U) rc = hip_check(h, hipMemcpyAsync(h->U, U, 3 * nc * 8, kind, s), "copy U");
-  if (!rc && prgh) rc = hip_check(h, hipMemcpyAsync(h->prgh, prgh, nc * 8, kind, s), "copy p_rgh");
-  if (!rc && F) rc = hip_check(h, hipMemcpyAsync(h->F, F, nf * 8, kind, s), "copy F");
-  if (!rc) rc = hip_check(h, hipStreamSynchronize(s), "set_state");
-  if (rc) return rc;
-  if (!F) init_flux(h);
-  update_closures(h);
-  return hip_check(h, hipStreamSynchronize(h->stream), "set_state");
+int dbs_set_static(dbs_handle *H, const double *phi, const double *kinv) {
+  return dbs_batch_set_static(H, 0, phi, kinv);
+}
+
+int dbs_batch_set_state(dbs_handle *H, int i, const double *alpha, const double *U,
+                        const double *prgh, const double *F) {
+  if (!H || !alpha || !U || !prgh) return DBS_EINVAL;
+  Handle *h = &H->h;
+  if (int rc = check_sample(h, i)) return rc;
+  const size_t nc = h->hG[i].nc;
+  if (!all_finite(alpha, nc) || !all_finite(U, 3 * nc) || !all_finite(prgh, nc) ||
+      (F && !all_finite(F, h->hG[i].nf)))
+    return fail(h, DBS_EINVAL, "non-finite input state");
+  return set_state_impl(h, i, alpha, U, prgh, F, hipMemcpyHostToDevice, h->stream);
 }
 
 int dbs_set_state(dbs_handle *H, const double *alpha, const double *U, const double *prgh,
                   const double *F) {
+  return dbs_batch_set_state(H, 0, alpha, U, prgh, F);
+}
+
+int dbs_batch_set_state_dev(dbs_handle *H, int i, const double *alpha, const double *U,
+                            const double *prgh, const double *F, void *stream) {
   if (!H || !alpha || !U || !prgh) return DBS_EINVAL;
   Handle *h = &H->h;
-  const size_t nc = h->G.nc;
-  if (!all_finite(alpha, nc) || !all_finite(U, 3 * nc) || !all_finite(prgh, nc) ||
-      (F && !all_finite(F, h->G.nf)))
-    return fail(h, DBS_EINVAL, "non-finite input state");
-  return set_state_impl(h, alpha, U, prgh, F, hipMemcpyHostToDevice, h->stream);
+  if (int rc = check_sample(h, i)) return rc;
+  hipStream_t s = stream ? (hipStream_t)stream : h->stream;
+  hipStreamSynchronize(h->stream);
+  return set_state_impl(h, i, alpha, U, prgh, F, hipMemcpyDeviceToDevice, s);
 }
 
 int dbs_set_state_dev(dbs_handle *H, const double *alpha, const double *U, const double *prgh,
                       const double *F, void *stream) {
-  if (!H || !alpha || !U || !prgh) return DBS_EINVAL;
-  Handle *h = &H->h;
-  hipStream_t s = stream ? (hipStream_t)stream : h->stream;
-  hipStreamSynchronize(h->stream);
-  return set_state_impl(h, alpha, U, prgh, F, hipMemcpyDeviceToDevice, s);
+  return dbs_batch_set_state_dev(H, 0, alpha, U, prgh, F, stream);
 }
 
-static int get_state_impl(Handle *h, double *alpha, double *U, double *prgh, double *p, double *F,
-                          hipMemcpyKind kind, hipStream_t s) {
-  const size_t nc = h->G.nc, nf = h->G.nf;
-  int rc = hip_check(h, hipStreamSynchronize(h->stream), "get_state");
-  if (!rc && alpha) rc = hip_check(h, hipMemcpyAsync(alpha, h->alpha, nc * 8, kind, s), "copy alpha");
-  if (!rc && U) rc = hip_check(h, hipMemcpyAsync(U, h->U, 3 * nc * 8, kind, s), "copy U");
-  if (!rc && prgh) rc = hip_check(h, hipMemcpyAsync(prgh, h->prgh, nc * 8, kind, s), "copy p_rgh");
-  if (!rc && p) rc = hip_check(h, hipMemcpyAsync(p, h->p, nc * 8, kind, s), "copy p");
-  if (!rc && F) rc = hip_check(h, hipMemcpyAsync(F, h->F, nf * 8, kind, s), "copy F");
-  if (!rc) rc = hip_check(h, hipStreamSynchronize(s), "get_state");
-  return rc;
+int dbs_batch_get_state(dbs_handle *H, int i, double *alpha, double *U, double *prgh, double *p,
+                        double *F) {
+  if (!H) return DBS_EINVAL;
+  Handle *h = &H->h;
+  if (int rc = check_sample(h, i)) return rc;
+  return get_state_impl(h, i, alpha, U, prgh, p, F, hipMemcpyDeviceToHost, h->stream);
 }
 
 int dbs_get_state(dbs_handle *H, double *alpha, double *U, double *prgh, double *p, double *F) {
+  return dbs_batch_get_state(H, 0, alpha, U, prgh, p, F);
+}
+
+int dbs_batch_get_state_dev(dbs_handle *H, int i, double *alpha, double *U, double *prgh,
+                            double *p, double *F, void *stream) {
   if (!H) return DBS_EINVAL;
   Handle *h = &H->h;
-  return get_state_impl(h, alpha, U, prgh, p, F, hipMemcpyDeviceToHost, h->stream);
+  if (int rc = check_sample(h, i)) return rc;
+  hipStream_t s = stream ? (hipStream_t)stream : h->stream;
+  return get_state_impl(h, i, alpha, U, prgh, p, F, hipMemcpyDeviceToDevice, s);
 }
 
 int dbs_get_state_dev(dbs_handle *H, double *alpha, double *U, double *prgh, double *p,
                       double *F, void *stream) {
-  if (!H) return DBS_EINVAL;
-  Handle *h = &H->h;
-  hipStream_t s = stream ? (hipStream_t)stream : h->stream;
-  return get_state_impl(h, alpha, U, prgh, p, F, hipMemcpyDeviceToDevice, s);
-}
-
-struct TraceOut {
-  double *A, *rAU, *Shat, *Ustar, *HbyA, *phiHbyA, *b;
-};
-
-static int copy_out(Handle *h, double *dst, const double *src, size_t n) {
-  if (!dst) return DBS_OK;
-  return hip_check(h, hipMemcpyAsync(dst, src, n * 8, hipMemcpyDeviceToHost, h->stream), "trace");
-}
-
-static int one_step(Handle *h, TraceOut *tr) {
-  int rc = DBS_OK;
-  if (h->ctl.max_courant > 0.0) {
-    double s[5];
-    cell_stats(h, s);
-    h->st.max_courant = s[3];
-    if (s[3] > h->ctl.max_courant)
-      return fail(h, DBS_ECOURANT, "Courant number " + std::to_string(s[3]) + " above limit");
-  }
-  alpha_stage(h);
-  if (tr) rc |= copy_out(h, tr->A, h->A, h->G.nf);
-  momentum_predictor(h);
-  if (tr) {
-    rc |= copy_out(h, tr->rAU, h->rAU, h->G.nc);
-    rc |= copy_out(h, tr->Shat, h->Sh, 3 * (size_t)h->G.nc);
-    rc |= copy_out(h, tr->Ustar, h->U, 3 * (size_t)h->G.nc);
-  }
-  int solve_rc = DBS_OK;
-  for (int c = 0; c < h->ctl.n_corr; c++) {
-    corrector_assemble(h);
-    if (tr && c == 0) {
-      rc |= copy_out(h, tr->HbyA, h->HbyA, 3 * (size_t)h->G.nc);
-      rc |= copy_out(h, tr->phiHbyA, h->phiH, h->G.nf);
-      rc |= copy_out(h, tr->b, h->rhs, h->G.nc);
-    }
-    int its = 0;
-    double rr = 0.0;
-    int src = pressure_solve(h, h->rAU, h->rhs, h->prgh, &its, &rr);
-    h->st.p_iters[c] = its;
-    h->st.p_relres[c] = rr;
-    if (src) solve_rc = src;
-    corrector_update(h, c == h->ctl.n_corr - 1);
-  }
-  h->st.steps++;
-  if (rc) return fail(h, DBS_EHIP, "trace copy failed");
-  if (solve_rc) return fail(h, solve_rc, "pressure solve did not converge");
-  return DBS_OK;
-}
-
-static int finish_steps(Handle *h, int rc) {
-  int e = hip_check(h, hipStreamSynchronize(h->stream), "step");
-  if (!e) e = hip_check(h, hipGetLastError(), "kernel launch");
-  if (e) return e;
-  prof_collect(h);
-  double s[5];
-  cell_stats(h, s);
-  h->st.alpha_min = s[0];
-  h->st.alpha_max = s[1];
-  h->st.phase_volume = s[2];
-  if (s[4] > 0.0) return fail(h, DBS_ENAN, "non-finite value in the state");
-  if (rc) return rc;
-  if (h->ctl.bounds_tol > 0.0 &&
-      (s[0] < -h->ctl.bounds_tol || s[1] > 1.0 + h->ctl.bounds_tol))
-    return fail(h, DBS_EBOUNDS, "alpha outside the admissible band");
-  return DBS_OK;
+  return dbs_batch_get_state_dev(H, 0, alpha, U, prgh, p, F, stream);
 }
 
 int dbs_step(dbs_handle *H, int nsteps) {
   if (!H || nsteps < 0) return DBS_EINVAL;
   Handle *h = &H->h;
   int rc = DBS_OK;
-  for (int s = 0; s < nsteps && !rc; s++) rc = one_step(h, nullptr);
-  if (rc == DBS_ECOURANT) return rc;
+  for (int s = 0; s < nsteps && !rc; s++)
+    rc = h->graph_mode ? graph_step(h) : eager_step(h, nullptr, nullptr);
+  if (rc == DBS_ECOURANT || rc == DBS_EHIP) return rc;
   return finish_steps(h, rc);
+}
+
+int dbs_set_graph(dbs_handle *H, int on) {
+  if (!H) return DBS_EINVAL;
+  Handle *h = &H->h;
+  hipStreamSynchronize(h->stream);
+  h->graph_mode = on ? 1 : 0;
+  reset_graphs(h);
+  // on > 1: start from a budget of on - 1 iterations instead of measuring it
+  if (on > 1)
+    for (int c = 0; c < 16; c++) h->graph_budget[c] = on - 1;
+  return DBS_OK;
+}
+
+int dbs_autotune(dbs_handle *H, int *kz_out, int *sweeps_out, int *shift_out, double *ms_out) {
+  if (!H) return DBS_EINVAL;
+  Handle *h = &H->h;
+  int rc = DBS_OK;
+  if (!h->snap) {
+    h->snap = dmalloc(h, 5 * (size_t)h->NC + (size_t)h->NF, rc);
+    if (rc) return fail(h, rc, "snapshot allocation");
+  }
+  double *x0 = h->Rp;  // transport scratch, free once the transport is done
+  const unsigned long long pm = h->prof_mask;
+  h->prof_mask = 0;
+  // the first corrector's system of the current state (p_rgh is untouched
+  // until the solve)
+  snapshot(h, true);
+  alpha_stage(h);
+  momentum_predictor(h);
+  corrector_assemble(h);
+  copy_n(h, h->prgh, x0, (size_t)h->NC);
+  struct Cand {
+    int kz, sweeps, shift;
+  };
+  Cand best{h->kz_fine, h->mg_pre, h->bottom_shift};
+  double best_ms = 1e300;
+  auto trial = [&](const Cand &c) {
+    h->kz_fine = c.kz;
+    h->mg_pre = h->mg_post = c.sweeps;
+    h->bottom_shift = c.shift;
+    if (pressure_retune(h)) return;
+    int ok = 0;
+    time_solve(h, x0, &ok);  // first run: caches and clocks
+    const double ms = time_solve(h, x0, &ok);
+    if (ok && ms < best_ms) {
+      best_ms = ms;
+      best = c;
+    }
+  };
+  for (int sw = 1; sw <= 3; sw++)
+    for (int shf = 0; shf <= 1; shf++) trial(Cand{0, sw, shf});
+  const Cand mid = best;
+  for (int kz : {2, 4, 8, 16}) trial(Cand{kz, mid.sweeps, mid.shift});
+  h->kz_fine = best.kz;
+  h->mg_pre = h->mg_post = best.sweeps;
+  h->bottom_shift = best.shift;
+  rc = pressure_retune(h);
+  // restore the state as it was before tuning
+  swap_roles(h);
+  snapshot(h, false);
+  update_closures(h);
+  h->prof_mask = pm;
+  reset_graphs(h);
+  if (!rc) rc = hip_check(h, hipStreamSynchronize(h->stream), "autotune");
+  if (kz_out) *kz_out = best.kz;
+  if (sweeps_out) *sweeps_out = best.sweeps;
+  if (shift_out) *shift_out = best.shift;
+  if (ms_out) *ms_out = best_ms;
+  return rc;
+}
+
+int dbs_set_tuning(dbs_handle *H, int kz, int sweeps, int shift) {
+  if (!H || kz < 0 || kz > 64 || sweeps < 1 || sweeps > 8 || shift < 0 || shift > 4)
+    return DBS_EINVAL;
+  Handle *h = &H->h;
+  hipStreamSynchronize(h->stream);
+  h->kz_fine = kz;
+  h->mg_pre = h->mg_post = sweeps;
+  h->bottom_shift = shift;
+  reset_graphs(h);
+  return pressure_retune(h);
 }
 
 int dbs_debug_step_trace(dbs_handle *H, double *A, double *rAU, double *Shat, double *Ustar,
                          double *HbyA, double *phiHbyA, double *b) {
   if (!H) return DBS_EINVAL;
   Handle *h = &H->h;
+  if (h->ns != 1) return fail(h, DBS_EINVAL, "trace needs a single-sample handle");
   TraceOut tr{A, rAU, Shat, Ustar, HbyA, phiHbyA, b};
-  int rc = one_step(h, &tr);
+  int rc = eager_step(h, &tr, nullptr);
   if (rc == DBS_ECOURANT) return rc;
   return finish_steps(h, rc);
 }
 
-int dbs_get_stats(dbs_handle *H, dbs_stats *out) {
+int dbs_batch_get_stats(dbs_handle *H, int i, dbs_stats *out) {
   if (!H || !out) return DBS_EINVAL;
-  *out = H->h.st;
+  if (int rc = check_sample(&H->h, i)) return rc;
+  *out = H->h.st[i];
   return DBS_OK;
 }
+
+int dbs_get_stats(dbs_handle *H, dbs_stats *out) { return dbs_batch_get_stats(H, 0, out); }
 
 int dbs_set_profiling(dbs_handle *H, unsigned long long mask) {
   if (!H) return DBS_EINVAL;
@@ -530,12 +915,17 @@ int dbs_debug_pressure_solve(dbs_handle *H, const double *rAU, const double *b, 
                              int *iters, double *relres) {
   if (!H || !rAU || !b || !x) return DBS_EINVAL;
   Handle *h = &H->h;
-  const size_t nc = h->G.nc;
+  if (h->ns != 1) return fail(h, DBS_EINVAL, "debug solve needs a single-sample handle");
+  const size_t nc = h->hG[0].nc;
   int rc = hip_check(h, hipMemcpyAsync(h->rAU, rAU, nc * 8, hipMemcpyHostToDevice, h->stream), "copy");
   if (!rc) rc = hip_check(h, hipMemcpyAsync(h->rhs, b, nc * 8, hipMemcpyHostToDevice, h->stream), "copy");
   if (!rc) rc = hip_check(h, hipMemcpyAsync(h->Rp, x, nc * 8, hipMemcpyHostToDevice, h->stream), "copy");
   if (rc) return rc;
-  int src = pressure_solve(h, h->rAU, h->rhs, h->Rp, iters, relres);
+  int its = 0;
+  double rel = 0.0;
+  const int src = pressure_solve(h, h->rAU, h->rhs, h->Rp, 0, &its, &rel);
+  if (iters) *iters = its;
+  if (relres) *relres = rel;
   rc = hip_check(h, hipMemcpyAsync(x, h->Rp, nc * 8, hipMemcpyDeviceToHost, h->stream), "copy");
   if (!rc) rc = hip_check(h, hipStreamSynchronize(h->stream), "solve");
   if (!rc) rc = hip_check(h, hipGetLastError(), "kernel launch");

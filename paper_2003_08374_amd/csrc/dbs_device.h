@@ -27,11 +27,17 @@ struct Phys {
   double pc0, pc_exp, a_pcirr, inv_span_pc, eps_pc;
 };
 
+// One sample (one mesh) of a batch.  Cell and face indices are absolute in
+// the batch arenas: a sample's cells start at c0, its x|y|z face blocks at
+// fo[0..2]; vector fields are component-major over the whole cell arena
+// (component stride vs).
 struct Geom {
   int n[3];
-  int nc;
-  int fo[3];        // offsets of the x|y|z face blocks in a concatenated face array
-  int nf;           // total faces
+  int nc;           // cells of this sample
+  int c0;           // first cell of this sample in the cell arena
+  int vs;           // component stride of vector fields (cells in the arena)
+  int fo[3];        // first x|y|z face of this sample in the face arena
+  int nf;           // faces of this sample
   double h[3], ih[3], area[3], V, iV;
   double dt;
   int bck[6];
@@ -45,7 +51,7 @@ struct Geom {
 // ---------------------------------------------------------------- indexing
 
 __device__ __forceinline__ int cidx(const Geom &G, int i, int j, int k) {
-  return i + G.n[0] * (j + G.n[1] * k);
+  return G.c0 + i + G.n[0] * (j + G.n[1] * k);
 }
 
 // face on the minus side of cell coordinate (i,j,k) along axis a (the
@@ -65,22 +71,44 @@ struct Cell {
   int co[3];
 };
 
-// Per-cell kernels run one cell per thread on a 1-D grid of 64x4 blocks.
-// Blocks are renumbered so that each of the 8 XCDs receives a contiguous run
-// (a slab of planes): the y and z neighbours of a tile then sit in the same
-// L2.  (Walking several planes per thread was tried: the heavy per-cell
-// kernels then hold more registers and lose occupancy.)
+// Launches cover a whole batch: the blocks of all samples are concatenated
+// and bp[s] is the first block of sample s (bp has ns + 1 entries).  Global
+// block numbers are first renumbered so that each of the 8 XCDs receives a
+// contiguous run (a slab of planes of one sample, or whole small samples):
+// the y and z neighbours of a tile then sit in the same L2.
+__device__ __forceinline__ int xcd_remap(int b, int nb) {
+  const int full = nb & ~7;
+  return b < full ? (b & 7) * (full >> 3) + (b >> 3) : b;
+}
+
+// the sample owning global block b: the last s with bp[s] <= b
+__device__ __forceinline__ int find_seg(const int *__restrict__ bp, int ns, int b) {
+  int lo = 0, hi = ns - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (bp[mid] <= b) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// per-cell launch over a batch: sample table and block prefix
+struct Segs {
+  const Geom *g;
+  const int *bp;
+  int ns;
+};
+
+// Per-cell kernels run one cell per thread on 64x4 blocks; blocks of one
+// sample walk its x-row segments, rows and planes.  (Walking several planes
+// per thread was tried: the heavy per-cell kernels then hold more registers
+// and lose occupancy.)
 __host__ __device__ inline int cell_blocks(const Geom &G) {
   return ((G.n[0] + BX - 1) / BX) * ((G.n[1] + BY - 1) / BY) * G.n[2];
 }
 
-__device__ __forceinline__ bool cell_of_thread(const Geom &G, Cell &P) {
+__device__ __forceinline__ bool cell_of_thread(const Geom &G, int lb, Cell &P) {
   const int nbx = (G.n[0] + BX - 1) / BX, nby = (G.n[1] + BY - 1) / BY;
-  const int nb = nbx * nby * G.n[2];
-  const int b = blockIdx.x;
-  const int full = nb & ~7;
-  int L = b;
-  if (b < full) L = (b & 7) * (full >> 3) + (b >> 3);
+  int L = lb;
   const int bx = L % nbx;
   L /= nbx;
   P.i = bx * BX + threadIdx.x;
@@ -91,10 +119,14 @@ __device__ __forceinline__ bool cell_of_thread(const Geom &G, Cell &P) {
   return P.i < G.n[0] && P.j < G.n[1];
 }
 
-// body executed for this thread's cell
-#define FOR_CELLS(G, P) \
-  Cell P;               \
-  if (cell_of_thread(G, P))
+// Body executed for this thread's cell; G names the cell's sample and
+// cell_gb the block's global number in the concatenated order.
+#define FOR_CELLS(S, G, P)                                         \
+  const int cell_gb = xcd_remap(blockIdx.x, gridDim.x);            \
+  const int cell_sg = find_seg((S).bp, (S).ns, cell_gb);           \
+  const Geom &G = (S).g[cell_sg];                                  \
+  Cell P;                                                          \
+  if (cell_of_thread(G, cell_gb - (S).bp[cell_sg], P))
 
 // face index of side s (0 = minus, 1 = plus) of cell P along axis a
 __device__ __forceinline__ int face_of(const Geom &G, const Cell &P, int a, int s) {

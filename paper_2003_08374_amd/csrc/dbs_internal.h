@@ -1,6 +1,13 @@
 // Host-side state of a dbs_handle and the launchers each translation unit
 // provides.  Not part of the public ABI.
+//
+// A handle holds a batch of ns independent samples (ns = 1 for dbs_create).
+// Every field lives in one arena per kind: cell fields hold the samples one
+// after the other (each padded to a multiple of FLAT_CELLS cells, padding
+// kept at zero), face fields likewise without padding, and each multigrid
+// level has its own arena.  Every kernel is one launch over all samples.
 #pragma once
+#include <map>
 #include <string>
 #include <vector>
 
@@ -19,16 +26,50 @@ enum KClass {
   KC_STATS, KC_MISC, KC_SMOOTH0_ZERO, KC_COUNT
 };
 
+constexpr int FLAT_T = 256;               // threads of a vector-kernel block
+constexpr int FLAT_CELLS = 4 * FLAT_T;    // cells of a vector-kernel block
+constexpr int NSC = 16;                   // device scalars per sample
+
+// first cell, cell count and closed-domain flag of a sample's fine cells
+struct Rng {
+  int c0, nc, closed, pad;
+};
+
+// one sample on one multigrid level (device table entry)
+struct LvS {
+  int n0, n1, n2;     // cells per axis (0: the sample has no such level)
+  int c0;             // first cell in the level's arena
+  int cn0, cn1, cn2;  // the sample's next coarser level (0: none)
+  int cc0;            // its first cell in the coarser arena
+  int outlet;         // the sample has an outlet (Dirichlet) face
+  int pad;
+  double c[3];        // area / h per axis
+  double ob[6];       // outlet diagonal factor per domain face (2 c or 0)
+};
+
+// a launch over (a subset of) the batch: block prefix per sample
+struct Shape {
+  int *bp = nullptr;       // device, ns + 1 entries
+  std::vector<int> hbp;
+  int nblk = 0;
+  int kz = 1;
+};
+
 struct Level {
-  int n[3] = {0, 0, 0};
-  int nc = 0;
+  long long nc = 0;        // cells in this level's arena
+  std::vector<LvS> hs;     // per sample
+  LvS *ds = nullptr;
   // coarse-level operator (level >= 1): coefficient of the +x/+y/+z face of
   // each cell, Dirichlet diagonal part and full diagonal
   double *Tx = nullptr, *Ty = nullptr, *Tz = nullptr, *Db = nullptr, *D = nullptr;
   float *Txf = nullptr, *Tyf = nullptr, *Tzf = nullptr, *Dbf = nullptr, *Df = nullptr;
   double *x = nullptr, *b = nullptr;  // correction and right-hand side
   float *xf = nullptr, *bf = nullptr;
-  dim3 grid;
+  // launch shapes: fine level
+  Shape st, sm, rs;
+  // coarse levels: every sample holding the level; samples cycled on it by
+  // grid kernels (pairs and single cells); samples restricted into it
+  Shape one_all, pair_cyc, one_cyc, one_rc;
 };
 
 struct Timer {
@@ -37,21 +78,37 @@ struct Timer {
   size_t used = 0;
 };
 
+// one captured step (graph mode), keyed by the buffer roles it was captured with
+struct GraphKey {
+  const void *alpha, *U;
+  bool operator<(const GraphKey &o) const {
+    return alpha != o.alpha ? alpha < o.alpha : U < o.U;
+  }
+};
+
 struct Handle {
-  Geom G;
+  int ns = 1;
+  std::vector<Geom> hG;   // per sample, absolute arena offsets
+  Geom *dG = nullptr;
+  long long NC = 0, NF = 0;  // cell arena (padded) and face arena sizes
   Phys P;
   dbs_controls ctl;
   std::string err;
   hipStream_t own_stream = nullptr;
   hipStream_t stream = nullptr;
-  dim3 grid;  // cell launch grid of the fine mesh
-  int nblocks = 0;
+
+  Shape cell;           // per-cell kernels (64 x 4 blocks)
+  Segs seg;             // device view of cell
+  dim3 cgrid;
+  Shape flat;           // vector kernels (FLAT_CELLS cells per block)
+  Rng *rng = nullptr;   // per sample
+  std::vector<Rng> hrng;
 
   // static fields
   double *phi = nullptr, *kinv = nullptr;
   // state (alpha is double-buffered: alpha holds n+1 after the transport)
   double *alpha = nullptr, *alpha_old = nullptr;
-  double *U = nullptr, *U2 = nullptr;  // 3 x nc each
+  double *U = nullptr, *U2 = nullptr;  // 3 x NC each
   double *prgh = nullptr, *p = nullptr;
   double *F = nullptr;                 // faces
   // closures of the current alpha: k_rl/mu_l, k_rg/mu_g, p_c (0 in clear cells)
@@ -62,25 +119,42 @@ struct Handle {
   double *Qp = nullptr, *Qm = nullptr, *Pin = nullptr, *Pout = nullptr, *Rp = nullptr,
          *Rm = nullptr;
   // momentum / pressure work arrays
-  double *rAU = nullptr, *Sh = nullptr, *B = nullptr, *HbyA = nullptr;  // Sh,B,HbyA 3 x nc
+  double *rAU = nullptr, *Sh = nullptr, *B = nullptr, *HbyA = nullptr;  // Sh,B,HbyA 3 x NC
   double *phiH = nullptr;  // faces
   double *rhs = nullptr;
   // PCG vectors
   double *r = nullptr, *z = nullptr, *pv = nullptr, *q = nullptr;
-  float *rf = nullptr;  // FP32 residual (mixed precision)
+  float *rf = nullptr;     // FP32 residual (mixed precision)
   float *zoldf = nullptr;  // previous preconditioned residual (flexible CG)
   float *zf2 = nullptr;    // second fine correction buffer (FP32 V-cycle)
   double *z2 = nullptr;    // second fine correction buffer (FP64 V-cycle)
   double *partials = nullptr;  // per-block partial sums
-  double *scal = nullptr;      // device scalars
+  size_t npartials = 0;
+  double *scal = nullptr;      // NSC device scalars per sample
   double *hscal = nullptr;     // pinned host mirror
-  std::vector<Level> lv;
-  void *lvshape = nullptr;  // launch shapes per level (owned by k_pressure.hip)
-  int bottom = 0;           // first level cycled by one work-group
-  int red_blocks = 0;       // blocks of the fine-level reduction kernels
-  int mg_pre = 2, mg_post = 2, coarse_sweeps = 16;
+  int *act = nullptr, *want = nullptr;  // per-sample CG flags
+  int *hflags = nullptr;       // pinned mirror: act | want
+  double *sstat = nullptr, *hsstat = nullptr;  // per-sample statistics (5 each)
 
-  dbs_stats st;
+  std::vector<Level> lv;
+  std::vector<int> nlev;     // levels per sample
+  std::vector<int> bottom;   // per sample: first level cycled by one work-group
+  int maxbottom = 0;         // largest bottom level over the samples
+  void *btab = nullptr;      // device table of bottom descriptors
+  int nbt = 0;               // samples with a bottom (>= 2 levels)
+  int mg_pre = 2, mg_post = 2, coarse_sweeps = 16;
+  // tuning knobs (autotuner): fine tile depth (0 = heuristic), bottom shift
+  int kz_fine = 0, bottom_shift = 0;
+
+  std::vector<dbs_stats> st;  // per sample
+
+  // graph mode
+  int graph_mode = 0;
+  int graph_budget[16] = {0};  // PCG iterations per corrector in a captured step
+  std::map<GraphKey, hipGraphExec_t> graphs;
+  double *snap = nullptr;      // state snapshot for a step redone eagerly
+  double *rec = nullptr, *hrec = nullptr;  // per-sample solve records (ns x 16 x 3)
+
   // profiling
   unsigned long long prof_mask = 0;
   Timer tm;
@@ -105,17 +179,33 @@ void prof_collect(Handle *h);
 // k_alpha.hip
 void alpha_stage(Handle *h);
 void update_closures(Handle *h);  // pc/ml/mg from the current alpha
-void init_flux(Handle *h);        // F from U (linear interpolation)
+void init_flux(Handle *h, int only = -1);  // F from U (linear interpolation)
 // k_momentum.hip
 void momentum_predictor(Handle *h);
 void corrector_assemble(Handle *h);
 void corrector_update(Handle *h, bool last);
 // k_pressure.hip
-int pressure_setup(Handle *h);    // allocate the multigrid hierarchy
+int pressure_setup(Handle *h);    // multigrid hierarchy and launch shapes
+int pressure_retune(Handle *h);   // rebuild launch shapes after a knob changed
 void pressure_free(Handle *h);
-int pressure_solve(Handle *h, const double *rAU, const double *b, double *x, int *iters,
-                   double *relres);
+// Solve every sample's system; budget > 0: exactly that many iterations with
+// converged samples masked and no host synchronisation (graph capture).
+// Per-sample iterations and relative residuals go to iters[s], relres[s] (or
+// are left on the device when budget > 0).  Returns DBS_ENOCONV if a sample
+// hit p_maxit.
+int pressure_solve(Handle *h, const double *rAU, const double *b, double *x, int budget,
+                   int *iters, double *relres);
+// after a budgeted solve: per-sample iterations, relative residuals and
+// whether the sample converged
+void pressure_results(Handle *h, int *iters, double *relres, int *converged);
+// k_pressure.hip: flat copy kernel over the cell arena (n arrays of NC)
+void arena_copy(Handle *h, const double *src, double *dst, int narrays);
+// copy n doubles with a kernel (safe under graph capture)
+void copy_n(Handle *h, const double *src, double *dst, size_t n);
+// store the last solve's per-sample iterations, relative residual and
+// convergence flag for corrector c in rec (ns x 16 x 3 doubles)
+void pressure_record(Handle *h, double *rec, int c);
 // api.hip
-void cell_stats(Handle *h, double out[5]);  // min a, max a, sum phi a V, max Co, nonfinite
+void cell_stats(Handle *h);  // per sample: min a, max a, sum phi a V, max Co, nonfinite
 
 }  // namespace dbs

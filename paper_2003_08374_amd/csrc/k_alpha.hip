@@ -104,9 +104,9 @@ __device__ inline double face_antidiffusive(const Geom &G, const Phys &Ph, const
   return Ff * avl + Gr - FL;
 }
 
-__global__ void __launch_bounds__(NTHREADS) k_alpha_face(Geom G, Phys Ph, AlphaArgs X,
+__global__ void __launch_bounds__(NTHREADS) k_alpha_face(Segs SG, Phys Ph, AlphaArgs X,
                                                          double *__restrict__ A) {
-  FOR_CELLS(G, P) {
+  FOR_CELLS(SG, G, P) {
   for (int a = 0; a < 3; a++) {
     int f = face_of(G, P, a, 0);
     A[f] = on_boundary(G, P, a, 0) ? 0.0 : face_antidiffusive(G, Ph, X, P, a, f);
@@ -126,11 +126,10 @@ __device__ __forceinline__ double low_order_flux(const Geom &G, const double *__
   return Ff * (Ff >= 0.0 ? alpha[own] : alpha[nbr]);
 }
 
-__global__ void __launch_bounds__(NTHREADS) k_alpha_bounds(
-    Geom G, const double *__restrict__ alpha, const double *__restrict__ F,
+__global__ void __launch_bounds__(NTHREADS) k_alpha_bounds(Segs SG, const double *__restrict__ alpha, const double *__restrict__ F,
     const double *__restrict__ phi, const double *__restrict__ A, double *__restrict__ Qp,
     double *__restrict__ Qm, double *__restrict__ Pin, double *__restrict__ Pout) {
-  FOR_CELLS(G, P) {
+  FOR_CELLS(SG, G, P) {
   const double aP = alpha[P.c];
   double outL = 0.0, amax = aP, amin = aP, pin = 0.0, pout = 0.0;
   for (int a = 0; a < 3; a++) {
@@ -165,11 +164,10 @@ __global__ void __launch_bounds__(NTHREADS) k_alpha_bounds(
   }
 }
 
-__global__ void __launch_bounds__(NTHREADS) k_alpha_R(
-    Geom G, const double *__restrict__ A, const double *__restrict__ lam, int first,
+__global__ void __launch_bounds__(NTHREADS) k_alpha_R(Segs SG, const double *__restrict__ A, const double *__restrict__ lam, int first,
     const double *__restrict__ Qp, const double *__restrict__ Qm, const double *__restrict__ Pin,
     const double *__restrict__ Pout, double *__restrict__ Rp, double *__restrict__ Rm) {
-  FOR_CELLS(G, P) {
+  FOR_CELLS(SG, G, P) {
   double lout = 0.0, lin = 0.0;
   for (int a = 0; a < 3; a++) {
     if (G.n[a] == 1 && G.bck[2 * a] == BC_EMPTY) continue;
@@ -189,11 +187,11 @@ __global__ void __launch_bounds__(NTHREADS) k_alpha_R(
   }
 }
 
-__global__ void __launch_bounds__(NTHREADS) k_alpha_lambda(Geom G, const double *__restrict__ A,
+__global__ void __launch_bounds__(NTHREADS) k_alpha_lambda(Segs SG, const double *__restrict__ A,
                                                            const double *__restrict__ Rp,
                                                            const double *__restrict__ Rm,
                                                            int first, double *__restrict__ lam) {
-  FOR_CELLS(G, P) {
+  FOR_CELLS(SG, G, P) {
   for (int a = 0; a < 3; a++) {
     const int f = face_of(G, P, a, 0);
     if (on_boundary(G, P, a, 0)) {
@@ -208,13 +206,12 @@ __global__ void __launch_bounds__(NTHREADS) k_alpha_lambda(Geom G, const double 
   }
 }
 
-__global__ void __launch_bounds__(NTHREADS) k_alpha_update(
-    Geom G, Phys Ph, const double *__restrict__ alpha, const double *__restrict__ F,
+__global__ void __launch_bounds__(NTHREADS) k_alpha_update(Segs SG, Phys Ph, const double *__restrict__ alpha, const double *__restrict__ F,
     const double *__restrict__ phi, const double *__restrict__ kinv, const double *__restrict__ A,
     const double *__restrict__ lam, double *__restrict__ alpha_new, double *__restrict__ rhoPhi,
     double *__restrict__ ml, double *__restrict__ mg, double *__restrict__ pc,
     double *__restrict__ cf) {
-  FOR_CELLS(G, P) {
+  FOR_CELLS(SG, G, P) {
   double out = 0.0;
   const double drho = Ph.rho_l - Ph.rho_g;
   for (int a = 0; a < 3; a++) {
@@ -244,14 +241,14 @@ __global__ void __launch_bounds__(NTHREADS) k_alpha_update(
   }
 }
 
-__global__ void __launch_bounds__(NTHREADS) k_closures(Geom G, Phys Ph,
+__global__ void __launch_bounds__(NTHREADS) k_closures(Segs SG, Phys Ph,
                                                        const double *__restrict__ alpha,
                                                        const double *__restrict__ kinv,
                                                        double *__restrict__ ml,
                                                        double *__restrict__ mg,
                                                        double *__restrict__ pc,
                                                        double *__restrict__ cf) {
-  FOR_CELLS(G, P) {
+  FOR_CELLS(SG, G, P) {
   double l, g, p;
   const double a = alpha[P.c];
   closures(Ph, a, l, g, p);
@@ -265,11 +262,13 @@ __global__ void __launch_bounds__(NTHREADS) k_closures(Geom G, Phys Ph,
 
 // F = (linearly interpolated U) . S, boundary: inlet velocity, 0 at walls,
 // the cell velocity at outlets.
-__global__ void __launch_bounds__(NTHREADS) k_init_flux(Geom G, const double *__restrict__ U,
-                                                        double *__restrict__ F) {
-  FOR_CELLS(G, P) {
+// only >= 0: that sample alone
+__global__ void __launch_bounds__(NTHREADS) k_init_flux(Segs SG, const double *__restrict__ U,
+                                                        double *__restrict__ F, int only) {
+  FOR_CELLS(SG, G, P) {
+  if (only >= 0 && cell_sg != only) return;
   for (int a = 0; a < 3; a++) {
-    const double *Ua = U + (size_t)a * G.nc;
+    const double *Ua = U + (size_t)a * G.vs;
     for (int s = 0; s < 2; s++) {
       const bool bnd = on_boundary(G, P, a, s);
       if (s == 1 && !bnd) continue;
@@ -289,23 +288,22 @@ __global__ void __launch_bounds__(NTHREADS) k_init_flux(Geom G, const double *__
 }
 
 void alpha_stage(Handle *h) {
-  const Geom &G = h->G;
   dim3 blk(BX, BY);
   AlphaArgs X{h->alpha, h->F, h->phi, h->kinv, h->prgh, h->ml, h->mg, h->pc};
-  DBS_LAUNCH(h, KC_ALPHA_FACE, k_alpha_face, h->grid, blk, G, h->P, X, h->A);
-  DBS_LAUNCH(h, KC_ALPHA_BOUNDS, k_alpha_bounds, h->grid, blk, G, (const double *)h->alpha,
+  DBS_LAUNCH(h, KC_ALPHA_FACE, k_alpha_face, h->cgrid, blk, h->seg, h->P, X, h->A);
+  DBS_LAUNCH(h, KC_ALPHA_BOUNDS, k_alpha_bounds, h->cgrid, blk, h->seg, (const double *)h->alpha,
              (const double *)h->F, (const double *)h->phi, (const double *)h->A, h->Qp, h->Qm,
              h->Pin, h->Pout);
   for (int it = 0; it < h->ctl.mules_iter; it++) {
     int first = it == 0;
-    DBS_LAUNCH(h, KC_ALPHA_LIMIT, k_alpha_R, h->grid, blk, G, (const double *)h->A,
+    DBS_LAUNCH(h, KC_ALPHA_LIMIT, k_alpha_R, h->cgrid, blk, h->seg, (const double *)h->A,
                (const double *)h->lam, first, (const double *)h->Qp, (const double *)h->Qm,
                (const double *)h->Pin, (const double *)h->Pout, h->Rp, h->Rm);
-    DBS_LAUNCH(h, KC_ALPHA_LIMIT, k_alpha_lambda, h->grid, blk, G, (const double *)h->A,
+    DBS_LAUNCH(h, KC_ALPHA_LIMIT, k_alpha_lambda, h->cgrid, blk, h->seg, (const double *)h->A,
                (const double *)h->Rp, (const double *)h->Rm, first, h->lam);
   }
   // alpha^{n+1} goes to the spare buffer; the old one stays for rho^n
-  DBS_LAUNCH(h, KC_ALPHA_UPDATE, k_alpha_update, h->grid, blk, G, h->P,
+  DBS_LAUNCH(h, KC_ALPHA_UPDATE, k_alpha_update, h->cgrid, blk, h->seg, h->P,
              (const double *)h->alpha, (const double *)h->F, (const double *)h->phi,
              (const double *)h->kinv, (const double *)h->A, (const double *)h->lam,
              h->alpha_old, h->rhoPhi, h->ml, h->mg, h->pc, h->cf);
@@ -316,13 +314,13 @@ void alpha_stage(Handle *h) {
 
 void update_closures(Handle *h) {
   dim3 blk(BX, BY);
-  DBS_LAUNCH(h, KC_MISC, k_closures, h->grid, blk, h->G, h->P, (const double *)h->alpha,
+  DBS_LAUNCH(h, KC_MISC, k_closures, h->cgrid, blk, h->seg, h->P, (const double *)h->alpha,
              (const double *)h->kinv, h->ml, h->mg, h->pc, h->cf);
 }
 
-void init_flux(Handle *h) {
+void init_flux(Handle *h, int only) {
   dim3 blk(BX, BY);
-  DBS_LAUNCH(h, KC_MISC, k_init_flux, h->grid, blk, h->G, (const double *)h->U, h->F);
+  DBS_LAUNCH(h, KC_MISC, k_init_flux, h->cgrid, blk, h->seg, (const double *)h->U, h->F, only);
 }
 
 }  // namespace dbs

@@ -93,7 +93,7 @@ __device__ inline double reconstruct_axis(const Geom &G, const Phys &Ph, const M
     if (hbya) {
       const int b = 2 * a + s;
       const double Fb = G.bck[b] == BC_INLET ? G.bcU[b][a] * G.area[a] : 0.0;
-      q[s] = (Fb - hbya[(size_t)a * G.nc + P.c] * G.area[a]) / M.rAU[P.c];
+      q[s] = (Fb - hbya[(size_t)a * G.vs + P.c] * G.area[a]) / M.rAU[P.c];
     } else {
       q[s] = ff[1 - s] ? 0.0 : q[1 - s];
     }
@@ -148,7 +148,7 @@ __device__ inline FaceCoef mom_face(const Geom &G, const Phys &Ph, const MomArgs
 __device__ inline double dU(const Geom &G, const double *__restrict__ U, int Qc, const int Qco[3],
                             int comp, int axis) {
   if (empty_axis(G, axis)) return 0.0;
-  const double *Uc = U + (size_t)comp * G.nc;
+  const double *Uc = U + (size_t)comp * G.vs;
   const double uq = Uc[Qc];
   double fv[2];
   for (int s = 0; s < 2; s++) {
@@ -163,13 +163,13 @@ __device__ inline double dU(const Geom &G, const double *__restrict__ U, int Qc,
   return (fv[1] - fv[0]) * G.ih[axis];
 }
 
-__global__ void __launch_bounds__(NTHREADS) k_mom_assemble(Geom G, Phys Ph, MomArgs M,
+__global__ void __launch_bounds__(NTHREADS) k_mom_assemble(Segs SG, Phys Ph, MomArgs M,
                                                            const double *__restrict__ U,
                                                            int transpose,
                                                            double *__restrict__ rAU,
                                                            double *__restrict__ Sh,
                                                            double *__restrict__ B) {
-  FOR_CELLS(G, P) {
+  FOR_CELLS(SG, G, P) {
   const int c = P.c;
   const double phP = M.phi[c];
   const double an = M.alpha[c];
@@ -178,7 +178,7 @@ __global__ void __launch_bounds__(NTHREADS) k_mom_assemble(Geom G, Phys Ph, MomA
   double aP = rho_of(Ph, an) / (phP * G.dt) + K;
   const double rho_o = rho_of(Ph, M.alpha_old[c]);
   double S[3];
-  for (int d = 0; d < 3; d++) S[d] = rho_o * U[(size_t)d * G.nc + c] / (phP * G.dt);
+  for (int d = 0; d < 3; d++) S[d] = rho_o * U[(size_t)d * G.vs + c] / (phP * G.dt);
   for (int a = 0; a < 3; a++) {
     if (empty_axis(G, a)) continue;
     for (int s = 0; s < 2; s++) {
@@ -220,8 +220,8 @@ __global__ void __launch_bounds__(NTHREADS) k_mom_assemble(Geom G, Phys Ph, MomA
   const double r = 1.0 / aP;
   rAU[c] = r;
   for (int d = 0; d < 3; d++) {
-    Sh[(size_t)d * G.nc + c] = S[d];
-    B[(size_t)d * G.nc + c] =
+    Sh[(size_t)d * G.vs + c] = S[d];
+    B[(size_t)d * G.vs + c] =
         S[d] + reconstruct_axis(G, Ph, M, M.prgh, nullptr, P, d);
   }
   }
@@ -229,23 +229,23 @@ __global__ void __launch_bounds__(NTHREADS) k_mom_assemble(Geom G, Phys Ph, MomA
 
 // Uout = rAU (sum_N a_N Uin_N + src): one Jacobi sweep (src = S + R(q)) or
 // HbyA (src = S)
-__global__ void __launch_bounds__(NTHREADS) k_mom_offdiag(Geom G, Phys Ph, MomArgs M,
+__global__ void __launch_bounds__(NTHREADS) k_mom_offdiag(Segs SG, Phys Ph, MomArgs M,
                                                           const double *__restrict__ Uin,
                                                           const double *__restrict__ src,
                                                           double *__restrict__ Uout) {
-  FOR_CELLS(G, P) {
+  FOR_CELLS(SG, G, P) {
   const int c = P.c;
-  double acc[3] = {src[c], src[(size_t)G.nc + c], src[2 * (size_t)G.nc + c]};
+  double acc[3] = {src[c], src[(size_t)G.vs + c], src[2 * (size_t)G.vs + c]};
   for (int a = 0; a < 3; a++) {
     if (empty_axis(G, a)) continue;
     for (int s = 0; s < 2; s++) {
       if (on_boundary(G, P, a, s)) continue;
       FaceCoef fc = mom_face(G, Ph, M, P, a, s);
-      for (int d = 0; d < 3; d++) acc[d] += fc.aN * Uin[(size_t)d * G.nc + fc.nb];
+      for (int d = 0; d < 3; d++) acc[d] += fc.aN * Uin[(size_t)d * G.vs + fc.nb];
     }
   }
   const double r = M.rAU[c];
-  for (int d = 0; d < 3; d++) Uout[(size_t)d * G.nc + c] = r * acc[d];
+  for (int d = 0; d < 3; d++) Uout[(size_t)d * G.vs + c] = r * acc[d];
   }
 }
 
@@ -256,23 +256,23 @@ __device__ inline double phi_hbya(const Geom &G, const Phys &Ph, const MomArgs &
   if (on_boundary(G, P, a, s)) {
     const int b = 2 * a + s;
     if (G.bck[b] == BC_INLET) return G.bcU[b][a] * G.area[a];
-    if (G.bck[b] == BC_OUTLET) return H[(size_t)a * G.nc + P.c] * G.area[a];
+    if (G.bck[b] == BC_OUTLET) return H[(size_t)a * G.vs + P.c] * G.area[a];
     return 0.0;
   }
   const int nb = nbr_of(G, P, a, s);
   const int own = s ? P.c : nb, nbr = s ? nb : P.c;
-  const double *Ha = H + (size_t)a * G.nc;
+  const double *Ha = H + (size_t)a * G.vs;
   const double rAUf = 0.5 * (M.rAU[own] + M.rAU[nbr]);
   const double gxf = gdotx_face(G, Ph, P, a, s);
   return 0.5 * (Ha[own] + Ha[nbr]) * G.area[a] +
          rAUf * face_body(G, Ph, M, own, nbr, a, gxf) * G.area[a];
 }
 
-__global__ void __launch_bounds__(NTHREADS) k_phihbya(Geom G, Phys Ph, MomArgs M,
+__global__ void __launch_bounds__(NTHREADS) k_phihbya(Segs SG, Phys Ph, MomArgs M,
                                                       const double *__restrict__ H,
                                                       double *__restrict__ phiH,
                                                       double *__restrict__ rhs) {
-  FOR_CELLS(G, P) {
+  FOR_CELLS(SG, G, P) {
   double div = 0.0, dir = 0.0;
   for (int a = 0; a < 3; a++) {
     const bool empty = empty_axis(G, a);
@@ -294,13 +294,13 @@ __global__ void __launch_bounds__(NTHREADS) k_phihbya(Geom G, Phys Ph, MomArgs M
 }
 
 // flux and velocity correction; last corrector also writes p = p_rgh + rho g.x
-__global__ void __launch_bounds__(NTHREADS) k_correct(Geom G, Phys Ph, MomArgs M,
+__global__ void __launch_bounds__(NTHREADS) k_correct(Segs SG, Phys Ph, MomArgs M,
                                                       const double *__restrict__ H,
                                                       const double *__restrict__ phiH,
                                                       double *__restrict__ F,
                                                       double *__restrict__ U,
                                                       double *__restrict__ p, int last) {
-  FOR_CELLS(G, P) {
+  FOR_CELLS(SG, G, P) {
   const int c = P.c;
   const double *prgh = M.prgh;
   for (int a = 0; a < 3; a++) {
@@ -323,8 +323,8 @@ __global__ void __launch_bounds__(NTHREADS) k_correct(Geom G, Phys Ph, MomArgs M
   }
   const double r = M.rAU[c];
   for (int d = 0; d < 3; d++)
-    U[(size_t)d * G.nc + c] =
-        H[(size_t)d * G.nc + c] + r * reconstruct_axis(G, Ph, M, prgh, H, P, d);
+    U[(size_t)d * G.vs + c] =
+        H[(size_t)d * G.vs + c] + r * reconstruct_axis(G, Ph, M, prgh, H, P, d);
   if (last) p[c] = prgh[c] + rho_of(Ph, M.alpha[c]) * gdotx_cell(G, Ph, P);
   }
 }
@@ -337,10 +337,10 @@ static MomArgs mom_args(Handle *h) {
 void momentum_predictor(Handle *h) {
   dim3 blk(BX, BY);
   MomArgs M = mom_args(h);
-  DBS_LAUNCH(h, KC_MOM_ASSEMBLE, k_mom_assemble, h->grid, blk, h->G, h->P, M,
+  DBS_LAUNCH(h, KC_MOM_ASSEMBLE, k_mom_assemble, h->cgrid, blk, h->seg, h->P, M,
              (const double *)h->U, h->ctl.transpose_visc, h->rAU, h->Sh, h->B);
   for (int s = 0; s < h->ctl.mom_sweeps; s++) {
-    DBS_LAUNCH(h, KC_MOM_OFFDIAG, k_mom_offdiag, h->grid, blk, h->G, h->P, M,
+    DBS_LAUNCH(h, KC_MOM_OFFDIAG, k_mom_offdiag, h->cgrid, blk, h->seg, h->P, M,
                (const double *)h->U, (const double *)h->B, h->U2);
     double *t = h->U;
     h->U = h->U2;
@@ -351,16 +351,16 @@ void momentum_predictor(Handle *h) {
 void corrector_assemble(Handle *h) {
   dim3 blk(BX, BY);
   MomArgs M = mom_args(h);
-  DBS_LAUNCH(h, KC_MOM_OFFDIAG, k_mom_offdiag, h->grid, blk, h->G, h->P, M,
+  DBS_LAUNCH(h, KC_MOM_OFFDIAG, k_mom_offdiag, h->cgrid, blk, h->seg, h->P, M,
              (const double *)h->U, (const double *)h->Sh, h->HbyA);
-  DBS_LAUNCH(h, KC_PHIHBYA, k_phihbya, h->grid, blk, h->G, h->P, M, (const double *)h->HbyA,
+  DBS_LAUNCH(h, KC_PHIHBYA, k_phihbya, h->cgrid, blk, h->seg, h->P, M, (const double *)h->HbyA,
              h->phiH, h->rhs);
 }
 
 void corrector_update(Handle *h, bool last) {
   dim3 blk(BX, BY);
   MomArgs M = mom_args(h);
-  DBS_LAUNCH(h, KC_CORRECT, k_correct, h->grid, blk, h->G, h->P, M, (const double *)h->HbyA,
+  DBS_LAUNCH(h, KC_CORRECT, k_correct, h->cgrid, blk, h->seg, h->P, M, (const double *)h->HbyA,
              (const double *)h->phiH, h->F, h->U, h->p, (int)last);
 }
 

@@ -13,7 +13,8 @@
 // operator).  Smoother: red-black Gauss-Seidel, red then black on the way
 // down and black then red on the way up, so the V-cycle is a symmetric
 // preconditioner.  Restriction sums the 8 children's residuals (transpose of
-// piecewise-constant prolongation).  Levels of at most BOTTOM_CELLS cells are
+// piecewise-constant prolongation).  The smallest levels of a sample (from
+// the first one whose remaining hierarchy fits in BOTTOM_LDS bytes) are
 // cycled by one work-group in a single launch.
 //
 // Mixed precision (DBS_MIXED): the V-cycle runs in FP32 (rAU, coefficients,
@@ -21,72 +22,77 @@
 // test stay FP64; CG becomes flexible (Polak-Ribiere beta) and the true FP64
 // residual b - A x replaces the recursive one every few iterations.
 //
-// Launch shape: 1-D grids of 64x4 work-groups; each thread walks KZ planes
-// of one (x, y) column.  Smoothers give each thread a pair of x-adjacent
-// cells, one of each colour, so no lane idles in a half sweep.  Blocks are
-// renumbered so that each of the 8 XCDs receives a contiguous run of blocks
-// (a z-slab), keeping the y and z neighbours of a tile in the same L2.
+// Batches: every launch covers all samples; a block finds its sample in the
+// block prefix of its launch shape.  CG runs per sample in lockstep: alpha,
+// beta and the convergence test are per-sample device scalars, converged
+// samples are masked off (their blocks return at once), so each sample
+// follows the iterations it would follow alone.  With a fixed iteration
+// budget the solve needs no host synchronisation and can be captured in a
+// graph.
 //
-// Reductions are deterministic: each block writes one partial sum, a single
-// block adds the partials in a fixed order.
+// Reductions are deterministic: each block writes one partial sum and one
+// block per sample adds that sample's partials in a fixed order.
+#include <algorithm>
+#include <array>
+#include <cstring>
 #include <type_traits>
 
 #include "dbs_internal.h"
 
 namespace dbs {
 
-enum { S_RZ = 0, S_PQ, S_RR, S_ALPHA, S_BETA, S_RZNEW, S_RZOLD, S_BB, S_SUM, S_NSCAL };
+enum {
+  S_RZ = 0, S_PQ, S_RR, S_ALPHA, S_BETA, S_RZNEW, S_RZOLD, S_BB, S_SUM, S_NRM2, S_ITS,
+  S_NOCONV, S_RRFIN
+};
 
-constexpr int KZ = 8;              // planes per thread column
+constexpr int KZ = 8;               // planes per thread column (coarse levels)
 constexpr int BOTTOM_LDS = 144000;  // bytes of LDS for the single work-group bottom
 constexpr int MAXLV = 16;
+constexpr int MIN_BLOCKS = 2048;
 
 // ------------------------------------------------------------ launch shape
 
-struct ZG {
-  int nbx, nby, nbz;  // blocks per axis
-  int kz;             // planes per thread
-  int pair;           // 1: two x-cells per thread
+// device view of a Shape
+struct SH {
+  const int *bp;
+  int ns;
+  int kz;
 };
 
-__host__ __device__ inline int zg_blocks(const ZG &z) { return z.nbx * z.nby * z.nbz; }
-
-// planes per thread: as many as KZ while the launch keeps >= MIN_BLOCKS blocks
-constexpr int MIN_BLOCKS = 2048;
-static ZG make_zg(int n0, int n1, int n2, bool pair) {
-  ZG z;
-  const int cx = pair ? 2 * BX : BX;
-  z.nbx = (n0 + cx - 1) / cx;
-  z.nby = (n1 + BY - 1) / BY;
-  z.kz = 1;
-  while (z.kz < KZ && (long long)z.nbx * z.nby * ((n2 + 2 * z.kz - 1) / (2 * z.kz)) >= MIN_BLOCKS)
-    z.kz *= 2;
-  z.nbz = (n2 + z.kz - 1) / z.kz;
-  z.pair = pair;
-  return z;
+// This block's global tile number (XCD order), sample and block within the
+// sample; false when the sample is masked off.
+__device__ __forceinline__ bool locate(const SH &S, const int *__restrict__ mask, int &g, int &s,
+                                       int &lb) {
+  g = xcd_remap(blockIdx.x, gridDim.x);
+  s = find_seg(S.bp, S.ns, g);
+  lb = g - S.bp[s];
+  return !mask || mask[s];
 }
 
-// column owned by this thread: x index (first of the pair), y index, plane range
-__device__ __forceinline__ bool column(const ZG &z, int n0, int n1, int n2, int &i, int &j,
-                                       int &k0, int &k1) {
-  const int nb = zg_blocks(z);
-  const int b = blockIdx.x;
-  const int full = nb & ~7;
-  int L = b;
-  if (b < full) L = (b & 7) * (full >> 3) + (b >> 3);  // XCD-contiguous runs
-  const int bx = L % z.nbx;
-  L /= z.nbx;
-  const int by = L % z.nby;
-  const int bz = L / z.nby;
-  i = (bx * BX + threadIdx.x) * (z.pair ? 2 : 1);
-  j = by * BY + threadIdx.y;
-  k0 = bz * z.kz;
-  k1 = min(k0 + z.kz, n2);
+__host__ __device__ inline int column_blocks(int n0, int n1, int n2, int kz, bool pair) {
+  const int cx = pair ? 2 * BX : BX;
+  return ((n0 + cx - 1) / cx) * ((n1 + BY - 1) / BY) * ((n2 + kz - 1) / kz);
+}
+
+// column owned by this thread in block lb of a level of n0 x n1 x n2 cells:
+// x index (first of the pair), y index, plane range
+__device__ __forceinline__ bool column(int n0, int n1, int n2, int lb, int kz, bool pair, int &i,
+                                       int &j, int &k0, int &k1) {
+  const int cx = pair ? 2 * BX : BX;
+  const int nbx = (n0 + cx - 1) / cx, nby = (n1 + BY - 1) / BY;
+  const int bx = lb % nbx;
+  const int L = lb / nbx;
+  i = (bx * BX + threadIdx.x) * (pair ? 2 : 1);
+  j = (L % nby) * BY + threadIdx.y;
+  k0 = (L / nby) * kz;
+  k1 = min(k0 + kz, n2);
   return i < n0 && j < n1;
 }
 
 // ------------------------------------------------------------------ operator
 
+// one sample on one level; pointers start at the sample's first cell
 template <typename R>
 struct Op {
   int n0, n1, n2;
@@ -96,6 +102,33 @@ struct Op {
   R ob[6];               // outlet diagonal factor per domain face (2 c or 0)
   const R *Tx, *Ty, *Tz, *D;  // stored operator (coarse levels)
 };
+
+// one level over the batch
+template <typename R>
+struct OpB {
+  const LvS *ls;
+  int matfree;
+  const R *rAU, *Tx, *Ty, *Tz, *D;
+};
+
+template <typename R>
+__device__ __forceinline__ Op<R> op_at(const OpB<R> &B, int s) {
+  const LvS &Q = B.ls[s];
+  Op<R> o;
+  o.n0 = Q.n0; o.n1 = Q.n1; o.n2 = Q.n2;
+  o.matfree = B.matfree;
+  const int c0 = Q.c0;
+  for (int a = 0; a < 3; a++) o.c[a] = (R)Q.c[a];
+  for (int b = 0; b < 6; b++) o.ob[b] = (R)Q.ob[b];
+  if (B.matfree) {
+    o.rAU = B.rAU + c0;
+    o.Tx = o.Ty = o.Tz = o.D = nullptr;
+  } else {
+    o.rAU = nullptr;
+    o.Tx = B.Tx + c0; o.Ty = B.Ty + c0; o.Tz = B.Tz + c0; o.D = B.D + c0;
+  }
+  return o;
+}
 
 // diagonal and the six neighbour coefficients of cell (i,j,k); neighbour
 // order -x,+x,-y,+y,-z,+z; 0 where there is no neighbour
@@ -151,122 +184,94 @@ __device__ __forceinline__ R op_off(const Op<R> &L, int c, const R T[6],
   return s;
 }
 
-__device__ __forceinline__ void put_partial(double v, double *lds, double *partials, int slot0) {
-  double s = block_sum(v, lds);
-  if (threadIdx.x == 0 && threadIdx.y == 0) partials[slot0 + blockIdx.x] = s;
-}
+// ------------------------------------------------ vector kernels (flat)
+//
+// FLAT_CELLS consecutive cells of the fine arena per block of FLAT_T
+// threads; a sample's cells are padded to whole blocks and the padding is
+// zero in every vector, so dot products and updates may run over it.
 
-// ------------------------------------------------------------- CG kernels
+struct FL {
+  const int *bp;   // first block of each sample
+  int ns;
+  const Rng *rng;
+};
 
-// q = A p, partial sum of p.q
-__global__ void __launch_bounds__(NTHREADS) k_spmv_dot(Op<double> L, ZG z,
-                                                       const double *__restrict__ p,
-                                                       double *__restrict__ q,
-                                                       double *__restrict__ partials) {
-  __shared__ double lds[NTHREADS / 64];
-  int i, j, k0, k1;
-  double v = 0.0;
-  if (column(z, L.n0, L.n1, L.n2, i, j, k0, k1)) {
-    int c = i + L.n0 * (j + L.n1 * k0);
-    for (int k = k0; k < k1; k++, c += L.n0 * L.n1) {
-      double D, T[6];
-      op_row(L, i, j, k, c, D, T);
-      const double pp = p[c];
-      const double y = D * pp - op_off(L, c, T, p);
-      q[c] = y;
-      v += pp * y;
-    }
-  }
-  put_partial(v, lds, partials, 0);
-}
-
-// r = b - A x, partial sums of r.r and b.b
-__global__ void __launch_bounds__(NTHREADS) k_resid_dot(Op<double> L, ZG z,
-                                                        const double *__restrict__ b,
-                                                        const double *__restrict__ x,
-                                                        double *__restrict__ r,
-                                                        double *__restrict__ partials) {
-  __shared__ double lds[NTHREADS / 64];
-  int i, j, k0, k1;
-  double v = 0.0, vb = 0.0;
-  if (column(z, L.n0, L.n1, L.n2, i, j, k0, k1)) {
-    int c = i + L.n0 * (j + L.n1 * k0);
-    for (int k = k0; k < k1; k++, c += L.n0 * L.n1) {
-      double D, T[6];
-      op_row(L, i, j, k, c, D, T);
-      const double bb = b[c];
-      const double rr = bb - (D * x[c] - op_off(L, c, T, x));
-      r[c] = rr;
-      v += rr * rr;
-      vb += bb * bb;
-    }
-  }
-  put_partial(v, lds, partials, 0);
+__device__ __forceinline__ void flat_partial(double v, double *lds, double *partials, int slot0) {
+  v = wave_sum(v);
+  const int t = threadIdx.x;
+  if ((t & 63) == 0) lds[t >> 6] = v;
   __syncthreads();
-  put_partial(vb, lds, partials, zg_blocks(z));
+  if (t == 0) partials[slot0 + blockIdx.x] = (lds[0] + lds[1]) + (lds[2] + lds[3]);
 }
 
-// x += alpha p, r -= alpha q, partial sum of r.r
-__global__ void __launch_bounds__(NTHREADS) k_axpy_dot(int n0, int n1, int n2, ZG z,
-                                                       const double *__restrict__ scal,
-                                                       const double *__restrict__ p,
-                                                       const double *__restrict__ q,
-                                                       double *__restrict__ x,
-                                                       double *__restrict__ r,
-                                                       double *__restrict__ partials) {
-  __shared__ double lds[NTHREADS / 64];
-  int i, j, k0, k1;
+__device__ __forceinline__ size_t flat_cell(int m) {
+  return (size_t)blockIdx.x * FLAT_CELLS + m * FLAT_T + threadIdx.x;
+}
+
+// x += alpha p, r -= alpha q (and its FP32 copy), partial sum of r.r
+__global__ void __launch_bounds__(FLAT_T) k_axpy_dot(FL F, const double *__restrict__ scal,
+                                                     const double *__restrict__ p,
+                                                     const double *__restrict__ q,
+                                                     double *__restrict__ x,
+                                                     double *__restrict__ r,
+                                                     float *__restrict__ rf,
+                                                     double *__restrict__ partials,
+                                                     const int *__restrict__ act) {
+  __shared__ double lds[FLAT_T / 64];
+  const int s = find_seg(F.bp, F.ns, blockIdx.x);
+  if (!act[s]) return;
+  const double al = scal[s * NSC + S_ALPHA];
   double v = 0.0;
-  if (column(z, n0, n1, n2, i, j, k0, k1)) {
-    const double al = scal[S_ALPHA];
-    int c = i + n0 * (j + n1 * k0);
-    for (int k = k0; k < k1; k++, c += n0 * n1) {
-      x[c] = fma(al, p[c], x[c]);
-      const double rr = fma(-al, q[c], r[c]);
-      r[c] = rr;
-      v += rr * rr;
-    }
+#pragma unroll
+  for (int m = 0; m < FLAT_CELLS / FLAT_T; m++) {
+    const size_t c = flat_cell(m);
+    x[c] = fma(al, p[c], x[c]);
+    const double rr = fma(-al, q[c], r[c]);
+    r[c] = rr;
+    if (rf) rf[c] = (float)rr;
+    v += rr * rr;
   }
-  put_partial(v, lds, partials, 0);
+  flat_partial(v, lds, partials, 0);
 }
 
 // partial sums of a.z and (flexible) a.zold
 template <typename Z>
-__global__ void __launch_bounds__(NTHREADS) k_dot2(int n0, int n1, int n2, ZG z,
-                                                   const double *__restrict__ a,
-                                                   const Z *__restrict__ zz,
-                                                   const Z *__restrict__ zold,
-                                                   double *__restrict__ partials) {
-  __shared__ double lds[NTHREADS / 64];
-  int i, j, k0, k1;
+__global__ void __launch_bounds__(FLAT_T) k_dot2(FL F, const double *__restrict__ a,
+                                                 const Z *__restrict__ zz,
+                                                 const Z *__restrict__ zold,
+                                                 double *__restrict__ partials, int off2,
+                                                 const int *__restrict__ mask, int closed_only) {
+  __shared__ double lds[FLAT_T / 64];
+  const int s = find_seg(F.bp, F.ns, blockIdx.x);
+  if ((mask && !mask[s]) || (closed_only && !F.rng[s].closed)) return;
   double v = 0.0, vo = 0.0;
-  if (column(z, n0, n1, n2, i, j, k0, k1)) {
-    int c = i + n0 * (j + n1 * k0);
-    for (int k = k0; k < k1; k++, c += n0 * n1) {
-      const double ac = a[c];
-      v += ac * (double)zz[c];
-      if (zold) vo += ac * (double)zold[c];
-    }
+#pragma unroll
+  for (int m = 0; m < FLAT_CELLS / FLAT_T; m++) {
+    const size_t c = flat_cell(m);
+    const double ac = a[c];
+    v += ac * (double)zz[c];
+    if (zold) vo += ac * (double)zold[c];
   }
-  put_partial(v, lds, partials, 0);
+  flat_partial(v, lds, partials, 0);
   if (zold) {
     __syncthreads();
-    put_partial(vo, lds, partials, zg_blocks(z));
+    flat_partial(vo, lds, partials, off2);
   }
 }
 
 // p = z + beta p (first: p = z); flexible CG keeps zold = z
 template <typename Z>
-__global__ void __launch_bounds__(NTHREADS) k_xpby(int n0, int n1, int n2, ZG z,
-                                                   const double *__restrict__ scal,
-                                                   const Z *__restrict__ zz,
-                                                   double *__restrict__ p, int first,
-                                                   Z *__restrict__ zold) {
-  int i, j, k0, k1;
-  if (!column(z, n0, n1, n2, i, j, k0, k1)) return;
-  const double be = first ? 0.0 : scal[S_BETA];
-  int c = i + n0 * (j + n1 * k0);
-  for (int k = k0; k < k1; k++, c += n0 * n1) {
+__global__ void __launch_bounds__(FLAT_T) k_xpby(FL F, const double *__restrict__ scal,
+                                                 const Z *__restrict__ zz,
+                                                 double *__restrict__ p, int first,
+                                                 Z *__restrict__ zold,
+                                                 const int *__restrict__ act) {
+  const int s = find_seg(F.bp, F.ns, blockIdx.x);
+  if (!act[s]) return;
+  const double be = first ? 0.0 : scal[s * NSC + S_BETA];
+#pragma unroll
+  for (int m = 0; m < FLAT_CELLS / FLAT_T; m++) {
+    const size_t c = flat_cell(m);
     const Z zc = zz[c];
     p[c] = first ? (double)zc : fma(be, p[c], (double)zc);
     if (zold) zold[c] = zc;
@@ -274,91 +279,183 @@ __global__ void __launch_bounds__(NTHREADS) k_xpby(int n0, int n1, int n2, ZG z,
 }
 
 template <typename R>
-__global__ void __launch_bounds__(NTHREADS) k_cast(int n0, int n1, int n2, ZG z,
-                                                   const double *__restrict__ in,
-                                                   R *__restrict__ out) {
-  int i, j, k0, k1;
-  if (!column(z, n0, n1, n2, i, j, k0, k1)) return;
-  int c = i + n0 * (j + n1 * k0);
-  for (int k = k0; k < k1; k++, c += n0 * n1) out[c] = (R)in[c];
+__global__ void __launch_bounds__(FLAT_T) k_cast(const double *__restrict__ in,
+                                                 R *__restrict__ out) {
+#pragma unroll
+  for (int m = 0; m < FLAT_CELLS / FLAT_T; m++) {
+    const size_t c = flat_cell(m);
+    out[c] = (R)in[c];
+  }
 }
 
-__global__ void __launch_bounds__(NTHREADS) k_sum(int n0, int n1, int n2, ZG z,
-                                                  const double *__restrict__ x,
-                                                  double *__restrict__ partials) {
-  __shared__ double lds[NTHREADS / 64];
-  int i, j, k0, k1;
+__global__ void __launch_bounds__(FLAT_T) k_copy(const double *__restrict__ in,
+                                                 double *__restrict__ out) {
+#pragma unroll
+  for (int m = 0; m < FLAT_CELLS / FLAT_T; m++) {
+    const size_t c = flat_cell(m);
+    out[c] = in[c];
+  }
+}
+
+// partial sums of x over closed samples
+__global__ void __launch_bounds__(FLAT_T) k_sum(FL F, const double *__restrict__ x,
+                                                double *__restrict__ partials,
+                                                const int *__restrict__ mask) {
+  __shared__ double lds[FLAT_T / 64];
+  const int s = find_seg(F.bp, F.ns, blockIdx.x);
+  if ((mask && !mask[s]) || !F.rng[s].closed) return;
   double v = 0.0;
-  if (column(z, n0, n1, n2, i, j, k0, k1)) {
-    int c = i + n0 * (j + n1 * k0);
-    for (int k = k0; k < k1; k++, c += n0 * n1) v += x[c];
+#pragma unroll
+  for (int m = 0; m < FLAT_CELLS / FLAT_T; m++) v += x[flat_cell(m)];
+  flat_partial(v, lds, partials, 0);
+}
+
+// x -= mean(x) on the real cells of closed samples (and refresh an FP32 copy)
+__global__ void __launch_bounds__(FLAT_T) k_sub_mean(FL F, const double *__restrict__ scal,
+                                                     double *__restrict__ x,
+                                                     float *__restrict__ xf,
+                                                     const int *__restrict__ mask) {
+  const int s = find_seg(F.bp, F.ns, blockIdx.x);
+  const Rng g = F.rng[s];
+  if ((mask && !mask[s]) || !g.closed) return;
+  const double mean = scal[s * NSC + S_SUM] / (double)g.nc;
+#pragma unroll
+  for (int m = 0; m < FLAT_CELLS / FLAT_T; m++) {
+    const size_t c = flat_cell(m);
+    if ((long long)c - g.c0 < g.nc) {
+      const double v = x[c] - mean;
+      x[c] = v;
+      if (xf) xf[c] = (float)v;
+    }
   }
-  put_partial(v, lds, partials, 0);
 }
 
-__global__ void __launch_bounds__(NTHREADS) k_sub_mean(int n0, int n1, int n2, ZG z,
-                                                       const double *__restrict__ scal,
-                                                       double *__restrict__ x) {
-  int i, j, k0, k1;
-  if (!column(z, n0, n1, n2, i, j, k0, k1)) return;
-  const double m = scal[S_SUM] / ((double)n0 * n1 * n2);
-  int c = i + n0 * (j + n1 * k0);
-  for (int k = k0; k < k1; k++, c += n0 * n1) x[c] -= m;
+// a[s] = va (unless a is NULL), w[s] = vw
+__global__ void k_flags(int *__restrict__ a, int va, int *__restrict__ w, int vw, int n) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) {
+    if (a) a[t] = va;
+    w[t] = vw;
+  }
 }
 
-enum { FIN_STORE = 0, FIN_ALPHA = 1, FIN_BETA = 2, FIN_BETA_FLEX = 3 };
+enum {
+  FIN_STORE = 0, FIN_ALPHA, FIN_BETA, FIN_BETA_FLEX, FIN_RR, FIN_CHECK, FIN_INIT, FIN_RRFIN
+};
 
-// one block: scal[slot] = sum(partials[0..n)) (and scal[slot2] from the
-// second half); then derive alpha or beta on the device
-__global__ void __launch_bounds__(1024) k_finalize(const double *__restrict__ partials, int n,
-                                                   int two, double *__restrict__ scal, int slot,
-                                                   int slot2, int op) {
-  __shared__ double lds[16];
+struct FinArgs {
+  const double *partials;
+  const int *bp;        // block prefix of the producing launch (NULL: no sum)
+  int off2;             // offset of the second partial array
+  int two;              // 1: also reduce the second array into slot2
+  int slot, slot2, op;
+  const int *mask;      // samples taking part (NULL: all)
+  const Rng *rng;
+  int closed_only;
+  int *act, *want;
+  double tol2;          // p_tol^2
+  int maxit, replace_every;
+};
+
+// one block per sample: scal[slot] = sum of the sample's partials (and slot2
+// from the second array), then the CG scalar and flag updates of `op`
+__global__ void __launch_bounds__(FLAT_T) k_finalize(FinArgs A, double *__restrict__ scal) {
+  __shared__ double lds[FLAT_T / 64];
+  const int s = blockIdx.x;
+  if ((A.mask && !A.mask[s]) || (A.closed_only && !A.rng[s].closed)) return;
   const int t = threadIdx.x;
-  for (int hh = 0; hh < (two ? 2 : 1); hh++) {
-    double v0 = 0.0, v1 = 0.0, v2 = 0.0, v3 = 0.0;
-    int i = t;
-    for (; i + 3 * 1024 < n; i += 4 * 1024) {
-      v0 += partials[hh * n + i];
-      v1 += partials[hh * n + i + 1024];
-      v2 += partials[hh * n + i + 2048];
-      v3 += partials[hh * n + i + 3072];
+  double *S = scal + (size_t)s * NSC;
+  if (A.bp) {
+    const int b0 = A.bp[s], b1 = A.bp[s + 1];
+    for (int hh = 0; hh < (A.two ? 2 : 1); hh++) {
+      const double *P = A.partials + (hh ? A.off2 : 0);
+      double v0 = 0.0, v1 = 0.0;
+      int i = b0 + t;
+      for (; i + FLAT_T < b1; i += 2 * FLAT_T) {
+        v0 += P[i];
+        v1 += P[i + FLAT_T];
+      }
+      if (i < b1) v0 += P[i];
+      const double v = wave_sum(v0 + v1);
+      if ((t & 63) == 0) lds[t >> 6] = v;
+      __syncthreads();
+      if (t == 0) S[hh ? A.slot2 : A.slot] = (lds[0] + lds[1]) + (lds[2] + lds[3]);
+      __syncthreads();
     }
-    for (; i < n; i += 1024) v0 += partials[hh * n + i];
-    double v = (v0 + v1) + (v2 + v3);
-    v = wave_sum(v);
-    if ((t & 63) == 0) lds[t >> 6] = v;
-    __syncthreads();
-    if (t == 0) {
-      double s = 0.0;
-      for (int w = 0; w < 16; w++) s += lds[w];
-      scal[hh ? slot2 : slot] = s;
-    }
-    __syncthreads();
   }
-  if (t == 0) {
-    if (op == FIN_ALPHA) {
-      const double pq = scal[S_PQ];
-      scal[S_ALPHA] = pq != 0.0 ? scal[S_RZ] / pq : 0.0;
-    } else if (op == FIN_BETA || op == FIN_BETA_FLEX) {
-      const double num = op == FIN_BETA ? scal[S_RZNEW] : scal[S_RZNEW] - scal[S_RZOLD];
-      scal[S_BETA] = scal[S_RZ] != 0.0 ? num / scal[S_RZ] : 0.0;
-      scal[S_RZ] = scal[S_RZNEW];
+  if (t != 0) return;
+  switch (A.op) {
+    case FIN_ALPHA: {
+      const double pq = S[S_PQ];
+      S[S_ALPHA] = pq != 0.0 ? S[S_RZ] / pq : 0.0;
+      break;
     }
+    case FIN_BETA:
+    case FIN_BETA_FLEX: {
+      const double num = A.op == FIN_BETA ? S[S_RZNEW] : S[S_RZNEW] - S[S_RZOLD];
+      S[S_BETA] = S[S_RZ] != 0.0 ? num / S[S_RZ] : 0.0;
+      S[S_RZ] = S[S_RZNEW];
+      break;
+    }
+    case FIN_RR: {
+      const double its = S[S_ITS] + 1.0;
+      S[S_ITS] = its;
+      const bool small = S[S_RR] <= A.tol2 * S[S_NRM2];
+      const bool repl = A.replace_every > 0 && ((long long)its % A.replace_every) == 0;
+      // the true residual decides convergence; it also replaces the
+      // recursive one every replace_every iterations
+      A.want[s] = (small || repl) ? 1 : 0;
+      if (!small && !repl && its >= A.maxit) {
+        A.act[s] = 0;
+        S[S_NOCONV] = 1.0;
+      }
+      break;
+    }
+    case FIN_CHECK: {
+      if (S[S_RR] <= A.tol2 * S[S_NRM2]) {
+        A.act[s] = 0;
+      } else if (S[S_ITS] >= A.maxit) {
+        A.act[s] = 0;
+        S[S_NOCONV] = 1.0;
+      }
+      A.want[s] = 0;
+      break;
+    }
+    case FIN_INIT: {
+      const double n2 = S[S_BB] > 0.0 ? S[S_BB] : S[S_RR];
+      S[S_NRM2] = n2;
+      S[S_ITS] = 0.0;
+      S[S_NOCONV] = 0.0;
+      A.act[s] = (n2 > 0.0 && S[S_RR] > A.tol2 * n2) ? 1 : 0;
+      A.want[s] = 0;
+      break;
+    }
+    case FIN_RRFIN:
+      S[S_RRFIN] = S[S_RR];
+      break;
+    default:
+      break;
   }
 }
 
 // ------------------------------------------------------ multigrid kernels
 
-// red-black Gauss-Seidel half sweep of colour `color` (0 = red: i+j+k even).
-// Each thread owns the x-pair (i, i+1) and updates the one of this colour in
-// every plane.  zero_init: x = b/D on this colour and 0 on the other.
+// red-black Gauss-Seidel half sweep of colour `color` (0 = red: i+j+k even)
+// on a coarse level.  Each thread owns the x-pair (i, i+1) and updates the
+// one of this colour in every plane.  zero_init: x = b/D on this colour and
+// 0 on the other.
 template <typename R, typename B>
-__global__ void __launch_bounds__(NTHREADS) k_smooth(Op<R> L, ZG z, const B *__restrict__ b,
-                                                     R *__restrict__ x, int color,
-                                                     int zero_init) {
+__global__ void __launch_bounds__(NTHREADS) k_smooth(OpB<R> LB, SH S, const B *__restrict__ b,
+                                                     R *__restrict__ x, int color, int zero_init,
+                                                     const int *__restrict__ mask) {
+  int g, s, lb;
+  if (!locate(S, mask, g, s, lb)) return;
+  const Op<R> L = op_at(LB, s);
+  const int c0 = LB.ls[s].c0;
+  b += c0;
+  x += c0;
   int i0, j, k0, k1;
-  if (!column(z, L.n0, L.n1, L.n2, i0, j, k0, k1)) return;
+  if (!column(L.n0, L.n1, L.n2, lb, S.kz, true, i0, j, k0, k1)) return;
   const int sz = L.n0 * L.n1;
   int base = i0 + L.n0 * (j + L.n1 * k0);
   for (int k = k0; k < k1; k++, base += sz) {
@@ -376,16 +473,25 @@ __global__ void __launch_bounds__(NTHREADS) k_smooth(Op<R> L, ZG z, const B *__r
   }
 }
 
-// coarse right-hand side: sum over the 8 children of the fine residual
+// coarse right-hand side: sum over the 8 children of the fine residual; the
+// launch covers the coarse cells of the samples cycled on the fine level
 template <typename R, typename B>
-__global__ void __launch_bounds__(NTHREADS) k_restrict(Op<R> L, ZG zc, int cn0, int cn1, int cn2,
-                                                       const B *__restrict__ b,
+__global__ void __launch_bounds__(NTHREADS) k_restrict(OpB<R> LB, SH S, const B *__restrict__ b,
                                                        const R *__restrict__ x,
-                                                       R *__restrict__ bc) {
+                                                       R *__restrict__ bc,
+                                                       const int *__restrict__ mask) {
+  int g, s, lb;
+  if (!locate(S, mask, g, s, lb)) return;
+  const Op<R> L = op_at(LB, s);
+  const LvS &Q = LB.ls[s];
+  b += Q.c0;
+  x += Q.c0;
+  bc += Q.cc0;
+  const int cn0 = Q.cn0, cn1 = Q.cn1, cn2 = Q.cn2;
   int I, J, K0, K1;
-  if (!column(zc, cn0, cn1, cn2, I, J, K0, K1)) return;
+  if (!column(cn0, cn1, cn2, lb, S.kz, false, I, J, K0, K1)) return;
   for (int K = K0; K < K1; K++) {
-    R s = 0;
+    R sum = 0;
     for (int dk = 0; dk < 2; dk++) {
       const int k = 2 * K + dk;
       if (k >= L.n2) continue;
@@ -398,35 +504,50 @@ __global__ void __launch_bounds__(NTHREADS) k_restrict(Op<R> L, ZG zc, int cn0, 
           const int c = i + L.n0 * (j + L.n1 * k);
           R D, T[6];
           op_row(L, i, j, k, c, D, T);
-          s += (R)b[c] - (D * x[c] - op_off(L, c, T, x));
+          sum += (R)b[c] - (D * x[c] - op_off(L, c, T, x));
         }
       }
     }
-    bc[I + cn0 * (J + cn1 * K)] = s;
+    bc[I + cn0 * (J + cn1 * K)] = sum;
   }
 }
 
-// x_fine += x_coarse(parent)
+// x_fine += x_coarse(parent) on a coarse level
 template <typename R>
-__global__ void __launch_bounds__(NTHREADS) k_prolong(int n0, int n1, int n2, ZG z, int cn0,
-                                                      int cn1, const R *__restrict__ xc,
-                                                      R *__restrict__ x) {
+__global__ void __launch_bounds__(NTHREADS) k_prolong(const LvS *__restrict__ ls, SH S,
+                                                      const R *__restrict__ xc,
+                                                      R *__restrict__ x,
+                                                      const int *__restrict__ mask) {
+  int g, s, lb;
+  if (!locate(S, mask, g, s, lb)) return;
+  const LvS &Q = ls[s];
+  const int n0 = Q.n0, n1 = Q.n1, n2 = Q.n2, cn0 = Q.cn0, cn1 = Q.cn1;
+  x += Q.c0;
+  xc += Q.cc0;
   int i, j, k0, k1;
-  if (!column(z, n0, n1, n2, i, j, k0, k1)) return;
+  if (!column(n0, n1, n2, lb, S.kz, false, i, j, k0, k1)) return;
   int c = i + n0 * (j + n1 * k0);
   for (int k = k0; k < k1; k++, c += n0 * n1)
     x[c] += xc[(i >> 1) + cn0 * ((j >> 1) + cn1 * (k >> 1))];
 }
 
-// coarse operator of the next level from this level's operator
+// coarse operator of the next level from this level's operator; the launch
+// covers the coarse cells of every sample that has the coarse level
 template <typename R>
-__global__ void __launch_bounds__(NTHREADS) k_build_coarse(Op<R> L, const R *__restrict__ Dbf,
-                                                           ZG zc, int cn0, int cn1, int cn2,
-                                                           R *__restrict__ Tx, R *__restrict__ Ty,
+__global__ void __launch_bounds__(NTHREADS) k_build_coarse(OpB<R> LB, const R *__restrict__ Dbf,
+                                                           SH S, R *__restrict__ Tx,
+                                                           R *__restrict__ Ty,
                                                            R *__restrict__ Tz,
                                                            R *__restrict__ Db) {
+  int g, s, lb;
+  if (!locate(S, nullptr, g, s, lb)) return;
+  const Op<R> L = op_at(LB, s);
+  const LvS &Q = LB.ls[s];
+  if (Dbf) Dbf += Q.c0;
+  Tx += Q.cc0; Ty += Q.cc0; Tz += Q.cc0; Db += Q.cc0;
+  const int cn0 = Q.cn0, cn1 = Q.cn1, cn2 = Q.cn2;
   int I, J, K0, K1;
-  if (!column(zc, cn0, cn1, cn2, I, J, K0, K1)) return;
+  if (!column(cn0, cn1, cn2, lb, S.kz, false, I, J, K0, K1)) return;
   for (int K = K0; K < K1; K++) {
     R tx = 0, ty = 0, tz = 0, db = 0;
     for (int dk = 0; dk < 2; dk++)
@@ -451,14 +572,19 @@ __global__ void __launch_bounds__(NTHREADS) k_build_coarse(Op<R> L, const R *__r
 }
 
 template <typename R>
-__global__ void __launch_bounds__(NTHREADS) k_diag(int n0, int n1, int n2, ZG z,
+__global__ void __launch_bounds__(NTHREADS) k_diag(const LvS *__restrict__ ls, SH S,
                                                    const R *__restrict__ Tx,
                                                    const R *__restrict__ Ty,
                                                    const R *__restrict__ Tz,
                                                    const R *__restrict__ Db,
                                                    R *__restrict__ D) {
+  int g, s, lb;
+  if (!locate(S, nullptr, g, s, lb)) return;
+  const LvS &Q = ls[s];
+  const int n0 = Q.n0, n1 = Q.n1, n2 = Q.n2;
+  Tx += Q.c0; Ty += Q.c0; Tz += Q.c0; Db += Q.c0; D += Q.c0;
   int i, j, k0, k1;
-  if (!column(z, n0, n1, n2, i, j, k0, k1)) return;
+  if (!column(n0, n1, n2, lb, S.kz, false, i, j, k0, k1)) return;
   const int sy = n0, sz = n0 * n1;
   int c = i + n0 * (j + n1 * k0);
   for (int k = k0; k < k1; k++, c += sz) {
@@ -472,10 +598,11 @@ __global__ void __launch_bounds__(NTHREADS) k_diag(int n0, int n1, int n2, ZG z,
 
 // ----------------------------------------------- single work-group bottom
 //
-// The smallest levels (from the first one whose whole sub-hierarchy fits in
-// BOTTOM_LDS bytes) are cycled by one work-group of 1024 threads with every
-// array in LDS: coefficients and b of the top bottom level are loaded once,
-// the V-cycle runs with LDS-latency barriers, and x goes back to memory.
+// The smallest levels of a sample (from the first one whose whole
+// sub-hierarchy fits in BOTTOM_LDS bytes) are cycled by one work-group of
+// 1024 threads with every array in LDS: coefficients and b of the top bottom
+// level are loaded once, the V-cycle runs with LDS-latency barriers, and x
+// goes back to memory.  One work-group per sample.
 
 template <typename R>
 struct BLevel {
@@ -486,6 +613,7 @@ struct BLevel {
 
 template <typename R>
 struct Bottom {
+  int s;                // sample
   int nl, ntot;
   int pre, post, coarse_sweeps;
   BLevel<R> L[MAXLV];
@@ -559,8 +687,11 @@ __device__ inline void bl_prolong(const LdsView<R> &S, const BLevel<R> &F, const
 }
 
 template <typename R>
-__global__ void __launch_bounds__(1024) k_bottom(Bottom<R> A) {
+__global__ void __launch_bounds__(1024) k_bottom(const Bottom<R> *__restrict__ tab,
+                                                 const int *__restrict__ mask) {
   __shared__ R lds[BOTTOM_LDS / sizeof(R)];
+  const Bottom<R> &A = tab[blockIdx.x];
+  if (mask && !mask[A.s]) return;
   const int N = A.ntot;
   LdsView<R> S{lds, lds + N, lds + 2 * N, lds + 3 * N, lds + 4 * N, lds + 5 * N};
   for (int l = 0; l < A.nl; l++) {
@@ -607,7 +738,7 @@ __global__ void __launch_bounds__(1024) k_bottom(Bottom<R> A) {
 // ------------------------------------------------ fine level, 2.5-D tiles
 //
 // A block of 64 x TY2 threads owns a tile of W x TY2 cells (W = 64 one cell
-// per thread, or 128 with an x-pair per thread) and walks KZ2 planes.  Each
+// per thread, or 128 with an x-pair per thread) and walks kz planes.  Each
 // plane of x (or p) and rAU is staged with a one-cell halo in LDS; the z
 // neighbours of a thread's own cells stay in registers, so each array is
 // read from memory about once per pass (plus the halo and the chunk ends).
@@ -617,35 +748,18 @@ constexpr int KZ2 = 16;
 constexpr int NT2 = 64 * TY2;
 constexpr int MIN_BLOCKS2 = 1024;
 
-struct ZG2 {
-  int nbx, nby, nbz, kz;
-};
-
-static ZG2 make_zg2(int n0, int n1, int n2, int W, bool even_kz) {
-  ZG2 z;
-  z.nbx = (n0 + W - 1) / W;
-  z.nby = (n1 + TY2 - 1) / TY2;
-  z.kz = even_kz && n2 > 1 ? 2 : 1;
-  while (z.kz < KZ2 && (long long)z.nbx * z.nby * ((n2 + 2 * z.kz - 1) / (2 * z.kz)) >= MIN_BLOCKS2)
-    z.kz *= 2;
-  z.nbz = (n2 + z.kz - 1) / z.kz;
-  return z;
+__host__ __device__ inline int tiles25(int n0, int n1, int n2, int W, int kz) {
+  return ((n0 + W - 1) / W) * ((n1 + TY2 - 1) / TY2) * ((n2 + kz - 1) / kz);
 }
 
-static int nblk2(const ZG2 &z) { return z.nbx * z.nby * z.nbz; }
-
-__device__ __forceinline__ void tile_of(const ZG2 &z, int n2, int &x0b, int &y0, int &k0,
-                                        int &k1) {
-  const int nb = z.nbx * z.nby * z.nbz;
-  const int b = blockIdx.x;
-  const int full = nb & ~7;
-  int L = b;
-  if (b < full) L = (b & 7) * (full >> 3) + (b >> 3);  // XCD-contiguous runs
-  x0b = L % z.nbx;
-  L /= z.nbx;
-  y0 = (L % z.nby) * TY2;
-  k0 = (L / z.nby) * z.kz;
-  k1 = min(k0 + z.kz, n2);
+__device__ __forceinline__ void tile_of(int lb, int n0, int n1, int n2, int W, int kz, int &x0b,
+                                        int &y0, int &k0, int &k1) {
+  const int nbx = (n0 + W - 1) / W, nby = (n1 + TY2 - 1) / TY2;
+  x0b = lb % nbx;
+  const int L = lb / nbx;
+  y0 = (L % nby) * TY2;
+  k0 = (L / nby) * kz;
+  k1 = min(k0 + kz, n2);
 }
 
 #define LIX(W, lx, ly) (((ly) + 1) * ((W) + 2) + (lx) + 1)
@@ -752,22 +866,33 @@ __device__ __forceinline__ R off25(const R T[6], int lx, int ty, const R *sx, R 
          T[2] * sx[LIX(W, lx, ty - 1)] + T[3] * sx[LIX(W, lx, ty + 1)] + T[4] * xm + T[5] * xp;
 }
 
-// MODE 0: q = A p and partial p.q;  MODE 1: r = b - A p and partials r.r, b.b
+// MODE 0: q = A p and partial p.q;  MODE 1: r = b - A p (and its FP32 copy)
+// and partials r.r, b.b
 template <int MODE>
-__global__ void __launch_bounds__(NT2) k_stencil25(Op<double> L, ZG2 z,
+__global__ void __launch_bounds__(NT2) k_stencil25(OpB<double> LB, SH S,
                                                    const double *__restrict__ p,
                                                    const double *__restrict__ b,
                                                    double *__restrict__ out,
-                                                   double *__restrict__ partials) {
+                                                   float *__restrict__ outf,
+                                                   double *__restrict__ partials, int off2,
+                                                   const int *__restrict__ mask) {
   constexpr int W = 64;
   __shared__ double sp[(TY2 + 2) * (W + 2)], sr[(TY2 + 2) * (W + 2)];
   __shared__ double lred[NT2 / 64];
+  int g, s, lb;
+  if (!locate(S, mask, g, s, lb)) return;
+  const Op<double> L = op_at(LB, s);
+  const int c0 = LB.ls[s].c0;
+  p += c0;
+  if (MODE == 1) b += c0;
+  out += c0;
+  if (outf) outf += c0;
+  const int n0 = L.n0, n1 = L.n1, n2 = L.n2;
   int xb, y0, k0, k1;
-  tile_of(z, L.n2, xb, y0, k0, k1);
+  tile_of(lb, n0, n1, n2, W, S.kz, xb, y0, k0, k1);
   const int x0 = xb * W;
   const int tx = threadIdx.x, ty = threadIdx.y;
   const int i = x0 + tx, j = y0 + ty;
-  const int n0 = L.n0, n1 = L.n1, n2 = L.n2;
   const bool in = i < n0 && j < n1;
   const double *rA = L.rAU;
   auto X = [&](int ii, int jj, int kk) -> double { return ld_or0(p, ii, jj, kk, n0, n1, n2); };
@@ -796,6 +921,7 @@ __global__ void __launch_bounds__(NT2) k_stencil25(Op<double> L, ZG2 z,
       } else {
         const double res = bb - y;
         out[c] = res;
+        if (outf) outf[c] = (float)res;
         v1 += res * res;
         v2 += bb * bb;
       }
@@ -806,10 +932,10 @@ __global__ void __launch_bounds__(NT2) k_stencil25(Op<double> L, ZG2 z,
     hc = hn;
   }
   const double s1 = block_sum_n<NT2 / 64>(v1, lred);
-  if (tx == 0 && ty == 0) partials[blockIdx.x] = s1;
+  if (tx == 0 && ty == 0) partials[g] = s1;
   if (MODE == 1) {
     const double s2 = block_sum_n<NT2 / 64>(v2, lred);
-    if (tx == 0 && ty == 0) partials[z.nbx * z.nby * z.nbz + blockIdx.x] = s2;
+    if (tx == 0 && ty == 0) partials[off2 + g] = s2;
   }
 }
 
@@ -817,27 +943,39 @@ enum { SM_NORMAL = 0, SM_ZERO = 1, SM_PROLONG = 2 };
 
 // Red-black Gauss-Seidel half sweep on the fine level, one x-pair per thread.
 // SM_ZERO: x = b/D on this colour, 0 on the other (zero initial guess).
-// SM_PROLONG: x_in + (coarse correction of the parent) is the current
-// iterate; this colour is relaxed and both colours go to x_out.
-// Otherwise x_out == x_in and only this colour is written.
+// SM_PROLONG: x_in + (coarse correction of the parent, if the sample has a
+// coarse level) is the current iterate; this colour is relaxed and both
+// colours go to x_out.  Otherwise x_out == x_in and only this colour is
+// written.
 template <typename R, typename B, int MODE>
-__global__ void __launch_bounds__(NT2) k_smooth25(Op<R> L, ZG2 z, const B *__restrict__ b,
+__global__ void __launch_bounds__(NT2) k_smooth25(OpB<R> LB, SH S, const B *__restrict__ b,
                                                   const R *xin, R *xout, int color,
-                                                  const R *__restrict__ xc, int cn0, int cn1) {
+                                                  const R *__restrict__ xc,
+                                                  const int *__restrict__ mask) {
   constexpr int W = 128;
   __shared__ R sx[(TY2 + 2) * (W + 2)], sr[(TY2 + 2) * (W + 2)];
+  int g, s, lb;
+  if (!locate(S, mask, g, s, lb)) return;
+  const Op<R> L = op_at(LB, s);
+  const LvS &Q = LB.ls[s];
+  b += Q.c0;
+  xin += Q.c0;
+  xout += Q.c0;
+  const R *xcs = (MODE == SM_PROLONG && Q.cn0 > 0) ? xc + Q.cc0 : nullptr;
+  const int cn0 = Q.cn0, cn1 = Q.cn1;
+  const int n0 = L.n0, n1 = L.n1, n2 = L.n2;
   int xb, y0, k0, k1;
-  tile_of(z, L.n2, xb, y0, k0, k1);
+  tile_of(lb, n0, n1, n2, W, S.kz, xb, y0, k0, k1);
   const int x0 = xb * W;
   const int tx = threadIdx.x, ty = threadIdx.y;
   const int i0 = x0 + 2 * tx, j = y0 + ty;
-  const int n0 = L.n0, n1 = L.n1, n2 = L.n2;
   const R *rA = L.rAU;
   auto X = [&](int ii, int jj, int kk) -> R {
     if (MODE == SM_ZERO) return (R)0;
     R v = ld_or0(xin, ii, jj, kk, n0, n1, n2);
-    if (MODE == SM_PROLONG && ii >= 0 && ii < n0 && jj >= 0 && jj < n1 && kk >= 0 && kk < n2)
-      v += xc[(ii >> 1) + cn0 * ((jj >> 1) + cn1 * (kk >> 1))];
+    if (MODE == SM_PROLONG && xcs && ii >= 0 && ii < n0 && jj >= 0 && jj < n1 && kk >= 0 &&
+        kk < n2)
+      v += xcs[(ii >> 1) + cn0 * ((jj >> 1) + cn1 * (kk >> 1))];
     return v;
   };
   auto XP = [&](int kk) -> P2<R> { return P2<R>{X(i0, j, kk), X(i0 + 1, j, kk)}; };
@@ -887,18 +1025,26 @@ __global__ void __launch_bounds__(NT2) k_smooth25(Op<R> L, ZG2 z, const B *__res
 // red children's residuals.  Block tiles are 128 x 8 fine cells and walk
 // plane pairs; rows 2J and 2J+1 are combined through LDS.
 template <typename R, typename B>
-__global__ void __launch_bounds__(NT2) k_restrict25(Op<R> L, ZG2 z, const B *__restrict__ b,
+__global__ void __launch_bounds__(NT2) k_restrict25(OpB<R> LB, SH S, const B *__restrict__ b,
                                                     const R *__restrict__ x, R *__restrict__ bc,
-                                                    int cn0, int cn1) {
+                                                    const int *__restrict__ mask) {
   constexpr int W = 128;
   __shared__ R sx[(TY2 + 2) * (W + 2)], sr[(TY2 + 2) * (W + 2)];
   __shared__ R part[TY2 / 2][64];
+  int g, s, lb;
+  if (!locate(S, mask, g, s, lb)) return;
+  const Op<R> L = op_at(LB, s);
+  const LvS &Q = LB.ls[s];
+  b += Q.c0;
+  x += Q.c0;
+  bc += Q.cc0;
+  const int cn0 = Q.cn0, cn1 = Q.cn1;
+  const int n0 = L.n0, n1 = L.n1, n2 = L.n2;
   int xb, y0, k0, k1;
-  tile_of(z, L.n2, xb, y0, k0, k1);
+  tile_of(lb, n0, n1, n2, W, S.kz, xb, y0, k0, k1);
   const int x0 = xb * W;
   const int tx = threadIdx.x, ty = threadIdx.y;
   const int i0 = x0 + 2 * tx, j = y0 + ty;
-  const int n0 = L.n0, n1 = L.n1, n2 = L.n2;
   const R *rA = L.rAU;
   auto X = [&](int ii, int jj, int kk) -> R { return ld_or0(x, ii, jj, kk, n0, n1, n2); };
   auto XP = [&](int kk) -> P2<R> { return P2<R>{X(i0, j, kk), X(i0 + 1, j, kk)}; };
@@ -924,8 +1070,8 @@ __global__ void __launch_bounds__(NT2) k_restrict25(Op<R> L, ZG2 z, const B *__r
       const int lx = 2 * tx + off;
       R T[6], D;
       row25<R, W>(L, i, j, k, lx, ty, sr, rk.get(off), rm.get(off), rp.get(off), T, D);
-      const R s = off25<R, W>(T, lx, ty, sx, xm.get(off), xp.get(off));
-      acc += (R)b[i + n0 * (j + n1 * k)] - (D * xk.get(off) - s);
+      const R sm = off25<R, W>(T, lx, ty, sx, xm.get(off), xp.get(off));
+      acc += (R)b[i + n0 * (j + n1 * k)] - (D * xk.get(off) - sm);
     }
     const bool flush = (k & 1) == 1 || k + 1 == n2;
     if (flush && (ty & 1)) part[ty >> 1][tx] = acc;
@@ -968,15 +1114,16 @@ template <typename R> static R *lD(Level &L);
 template <> double *lD<double>(Level &L) { return L.D; }
 template <> float *lD<float>(Level &L) { return L.Df; }
 
+static SH sh(const Handle *h, const Shape &S) { return SH{S.bp, h->ns, S.kz}; }
+static FL fl(const Handle *h) { return FL{h->flat.bp, h->ns, h->rng}; }
+
 template <typename R>
-static Op<R> op_of(Handle *h, int l, const R *rAU) {
-  Op<R> o;
+static OpB<R> opb(Handle *h, int l, const R *rAU) {
   Level &L = h->lv[l];
-  o.n0 = L.n[0]; o.n1 = L.n[1]; o.n2 = L.n[2];
+  OpB<R> o;
+  o.ls = L.ds;
   o.matfree = l == 0;
   o.rAU = rAU;
-  for (int a = 0; a < 3; a++) o.c[a] = (R)(h->G.area[a] * h->G.ih[a]);
-  for (int b = 0; b < 6; b++) o.ob[b] = h->G.bck[b] == BC_OUTLET ? (R)2 * o.c[b / 2] : (R)0;
   o.Tx = lTx<R>(L); o.Ty = lTy<R>(L); o.Tz = lTz<R>(L); o.D = lD<R>(L);
   return o;
 }
@@ -984,365 +1131,594 @@ static Op<R> op_of(Handle *h, int l, const R *rAU) {
 static void *dalloc(Handle *h, size_t bytes, int &rc) {
   void *p = nullptr;
   if (rc) return nullptr;
-  if (hipMalloc(&p, bytes < 256 ? 256 : bytes) != hipSuccess) {
+  const size_t n = bytes < 256 ? 256 : bytes;
+  if (hipMalloc(&p, n) != hipSuccess) {
     rc = DBS_ENOMEM;
     return nullptr;
   }
+  if (hipMemset(p, 0, n) != hipSuccess) rc = DBS_EHIP;
   h->allocs.push_back(p);
   return p;
 }
 
-// launch shapes of each level: one cell per thread, and red/black pairs
-struct LShape {
-  ZG one, pair;
-  ZG2 st, sm, rs;  // fine level: stencil (64 wide), smoother and restriction (128 wide)
-};
-static std::vector<LShape> &shapes(Handle *h) {
-  return *reinterpret_cast<std::vector<LShape> *>(h->lvshape);
+static int upload(void *dst, const void *src, size_t bytes) {
+  return hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice) == hipSuccess ? DBS_OK : DBS_EHIP;
+}
+
+// fill a shape from per-sample block counts
+static void set_shape(Handle *h, Shape &S, const std::vector<int> &blocks, int kz, int &rc) {
+  if (rc) return;
+  S.kz = kz;
+  S.hbp.assign(h->ns + 1, 0);
+  for (int s = 0; s < h->ns; s++) S.hbp[s + 1] = S.hbp[s] + blocks[s];
+  S.nblk = S.hbp[h->ns];
+  if (!S.bp) S.bp = (int *)dalloc(h, sizeof(int) * (h->ns + 1), rc);
+  if (!rc) rc = upload(S.bp, S.hbp.data(), sizeof(int) * (h->ns + 1));
+}
+
+static dim3 blk() { return dim3(BX, BY); }
+static dim3 blk2() { return dim3(64, TY2); }
+
+// planes per block: as many as kzmax while the launch keeps at least
+// minblocks blocks
+template <typename F>
+static int pick_kz(int start, int kzmax, long long minblocks, F total_blocks) {
+  int kz = start;
+  while (kz < kzmax && total_blocks(2 * kz) >= minblocks) kz *= 2;
+  return kz;
+}
+
+// launch shapes of every level and the bottom table; depends on the tuning
+// knobs kz_fine and bottom_shift
+int pressure_retune(Handle *h) {
+  int rc = DBS_OK;
+  const int ns = h->ns;
+  const bool mixed = h->ctl.precision == DBS_MIXED;
+  const size_t rs = mixed ? 4 : 8;
+  auto nlev = [&](int s) { return h->nlev[s]; };
+  // bottom level per sample
+  h->maxbottom = 0;
+  h->nbt = 0;
+  h->bottom.assign(ns, 0);
+  for (int s = 0; s < ns; s++) {
+    const int nl = nlev(s);
+    if (nl < 2) continue;
+    int bl = nl - 1;
+    for (int l = 1; l < nl; l++) {
+      size_t cells = 0;
+      for (int m = l; m < nl; m++) {
+        const LvS &Q = h->lv[m].hs[s];
+        cells += (size_t)Q.n0 * Q.n1 * Q.n2;
+      }
+      if (cells * 6 * rs <= (size_t)BOTTOM_LDS) { bl = l; break; }
+    }
+    bl = std::min(bl + h->bottom_shift, nl - 1);
+    h->bottom[s] = bl;
+    h->maxbottom = std::max(h->maxbottom, bl);
+    h->nbt++;
+  }
+  // fine level shapes
+  Level &F = h->lv[0];
+  std::vector<int> blocks(ns);
+  auto fine_total = [&](int W, int kz, bool need_coarse) {
+    long long t = 0;
+    for (int s = 0; s < ns; s++)
+      if (!need_coarse || nlev(s) > 1) t += tiles25(F.hs[s].n0, F.hs[s].n1, F.hs[s].n2, W, kz);
+    return t;
+  };
+  const int kst = h->kz_fine > 0 ? h->kz_fine : pick_kz(1, KZ2, MIN_BLOCKS2, [&](int kz) {
+    return fine_total(64, kz, false);
+  });
+  const int ksm = h->kz_fine > 0 ? h->kz_fine : pick_kz(1, KZ2, MIN_BLOCKS2, [&](int kz) {
+    return fine_total(128, kz, false);
+  });
+  int krs = h->kz_fine > 1 ? h->kz_fine : pick_kz(2, KZ2, MIN_BLOCKS2, [&](int kz) {
+    return fine_total(128, kz, true);
+  });
+  if (krs & 1) krs++;
+  for (int s = 0; s < ns; s++) blocks[s] = tiles25(F.hs[s].n0, F.hs[s].n1, F.hs[s].n2, 64, kst);
+  set_shape(h, F.st, blocks, kst, rc);
+  for (int s = 0; s < ns; s++) blocks[s] = tiles25(F.hs[s].n0, F.hs[s].n1, F.hs[s].n2, 128, ksm);
+  set_shape(h, F.sm, blocks, ksm, rc);
+  for (int s = 0; s < ns; s++)
+    blocks[s] = nlev(s) > 1 ? tiles25(F.hs[s].n0, F.hs[s].n1, F.hs[s].n2, 128, krs) : 0;
+  set_shape(h, F.rs, blocks, krs, rc);
+  // coarse levels
+  for (int l = 1; l < (int)h->lv.size() && !rc; l++) {
+    Level &L = h->lv[l];
+    auto shape_of = [&](Shape &S, bool pair, auto member) {
+      auto total = [&](int kz) {
+        long long t = 0;
+        for (int s = 0; s < ns; s++)
+          if (member(s)) t += column_blocks(L.hs[s].n0, L.hs[s].n1, L.hs[s].n2, kz, pair);
+        return t;
+      };
+      const int kz = pick_kz(1, KZ, MIN_BLOCKS, total);
+      for (int s = 0; s < ns; s++)
+        blocks[s] = member(s) ? column_blocks(L.hs[s].n0, L.hs[s].n1, L.hs[s].n2, kz, pair) : 0;
+      set_shape(h, S, blocks, kz, rc);
+    };
+    shape_of(L.one_all, false, [&](int s) { return nlev(s) > l; });
+    shape_of(L.pair_cyc, true, [&](int s) { return nlev(s) > l && h->bottom[s] > l; });
+    shape_of(L.one_cyc, false, [&](int s) { return nlev(s) > l && h->bottom[s] > l; });
+    shape_of(L.one_rc, false, [&](int s) { return l >= 2 && nlev(s) > l && h->bottom[s] >= l; });
+  }
+  if (rc) return rc;
+  // bottom table (one work-group per sample with a coarse level)
+  auto build = [&](auto tag) -> int {
+    using R = decltype(tag);
+    std::vector<Bottom<R>> tab;
+    for (int s = 0; s < ns; s++) {
+      const int nl = nlev(s);
+      if (nl < 2) continue;
+      Bottom<R> A;
+      memset(&A, 0, sizeof(A));
+      A.s = s;
+      A.nl = nl - h->bottom[s];
+      A.pre = h->mg_pre;
+      A.post = h->mg_post;
+      int off = 0;
+      for (int m = 0; m < A.nl; m++) {
+        Level &L = h->lv[h->bottom[s] + m];
+        const LvS &Q = L.hs[s];
+        A.L[m] = BLevel<R>{Q.n0, Q.n1, Q.n2, off, lTx<R>(L) + Q.c0, lTy<R>(L) + Q.c0,
+                           lTz<R>(L) + Q.c0, lD<R>(L) + Q.c0, lx<R>(L) + Q.c0, lb<R>(L) + Q.c0};
+        off += Q.n0 * Q.n1 * Q.n2;
+      }
+      A.ntot = off;
+      // a one-cell coarsest level is solved exactly by one sweep
+      const LvS &Cq = h->lv[nl - 1].hs[s];
+      A.coarse_sweeps = Cq.n0 * Cq.n1 * Cq.n2 == 1 ? 1 : h->coarse_sweeps;
+      tab.push_back(A);
+    }
+    if (tab.empty()) return DBS_OK;
+    int r2 = DBS_OK;
+    if (!h->btab) h->btab = dalloc(h, sizeof(Bottom<R>) * tab.size(), r2);
+    if (r2) return r2;
+    return upload(h->btab, tab.data(), sizeof(Bottom<R>) * tab.size());
+  };
+  rc = mixed ? build(0.0f) : build(0.0);
+  return rc;
 }
 
 int pressure_setup(Handle *h) {
   int rc = DBS_OK;
+  const int ns = h->ns;
   const bool mixed = h->ctl.precision == DBS_MIXED;
-  h->lv.clear();
-  Level L0;
-  for (int a = 0; a < 3; a++) L0.n[a] = h->G.n[a];
-  L0.nc = h->G.nc;
-  h->lv.push_back(L0);
-  while ((int)h->lv.size() < MAXLV) {
-    const Level &F = h->lv.back();
-    if (F.nc <= 1) break;
-    Level C;
-    for (int a = 0; a < 3; a++) C.n[a] = (F.n[a] + 1) / 2;
-    C.nc = C.n[0] * C.n[1] * C.n[2];
-    const size_t n = (size_t)C.nc;
+  // per-sample level dimensions
+  std::vector<std::vector<std::array<int, 3>>> dims(ns);
+  int nlmax = 0;
+  h->nlev.assign(ns, 0);
+  for (int s = 0; s < ns; s++) {
+    std::array<int, 3> d = {h->hG[s].n[0], h->hG[s].n[1], h->hG[s].n[2]};
+    dims[s].push_back(d);
+    while ((int)dims[s].size() < MAXLV && (long long)d[0] * d[1] * d[2] > 1) {
+      for (int a = 0; a < 3; a++) d[a] = (d[a] + 1) / 2;
+      dims[s].push_back(d);
+    }
+    h->nlev[s] = (int)dims[s].size();
+    nlmax = std::max(nlmax, h->nlev[s]);
+  }
+  h->lv.assign(nlmax, Level());
+  // arenas: level 0 is the fine cell arena; coarse levels are packed
+  for (int l = 0; l < nlmax; l++) {
+    Level &L = h->lv[l];
+    L.hs.assign(ns, LvS());
+    long long off = 0;
+    for (int s = 0; s < ns; s++) {
+      LvS &Q = L.hs[s];
+      memset(&Q, 0, sizeof(Q));
+      const Geom &G = h->hG[s];
+      for (int a = 0; a < 3; a++) Q.c[a] = G.area[a] * G.ih[a];
+      for (int b = 0; b < 6; b++) Q.ob[b] = G.bck[b] == BC_OUTLET ? 2.0 * Q.c[b / 2] : 0.0;
+      Q.outlet = G.has_outlet;
+      if (l >= h->nlev[s]) continue;
+      Q.n0 = dims[s][l][0]; Q.n1 = dims[s][l][1]; Q.n2 = dims[s][l][2];
+      if (l == 0) {
+        Q.c0 = G.c0;
+      } else {
+        Q.c0 = (int)off;
+        off += (long long)Q.n0 * Q.n1 * Q.n2;
+      }
+    }
+    L.nc = l == 0 ? h->NC : off;
+  }
+  for (int l = 0; l + 1 < nlmax; l++)
+    for (int s = 0; s < ns; s++) {
+      if (l + 1 >= h->nlev[s]) continue;
+      LvS &Q = h->lv[l].hs[s];
+      const LvS &C = h->lv[l + 1].hs[s];
+      Q.cn0 = C.n0; Q.cn1 = C.n1; Q.cn2 = C.n2; Q.cc0 = C.c0;
+    }
+  for (int l = 0; l < nlmax && !rc; l++) {
+    Level &L = h->lv[l];
+    L.ds = (LvS *)dalloc(h, sizeof(LvS) * ns, rc);
+    if (!rc) rc = upload(L.ds, L.hs.data(), sizeof(LvS) * ns);
+    if (l == 0 || rc) continue;
+    const size_t n = (size_t)L.nc;
     const size_t s = mixed ? 4 : 8;
     void *Tx = dalloc(h, n * s, rc), *Ty = dalloc(h, n * s, rc), *Tz = dalloc(h, n * s, rc);
     void *Db = dalloc(h, n * s, rc), *D = dalloc(h, n * s, rc), *x = dalloc(h, n * s, rc);
     void *b = dalloc(h, n * s, rc);
     if (rc) return rc;
     if (mixed) {
-      C.Txf = (float *)Tx; C.Tyf = (float *)Ty; C.Tzf = (float *)Tz; C.Dbf = (float *)Db;
-      C.Df = (float *)D; C.xf = (float *)x; C.bf = (float *)b;
+      L.Txf = (float *)Tx; L.Tyf = (float *)Ty; L.Tzf = (float *)Tz; L.Dbf = (float *)Db;
+      L.Df = (float *)D; L.xf = (float *)x; L.bf = (float *)b;
     } else {
-      C.Tx = (double *)Tx; C.Ty = (double *)Ty; C.Tz = (double *)Tz; C.Db = (double *)Db;
-      C.D = (double *)D; C.x = (double *)x; C.b = (double *)b;
+      L.Tx = (double *)Tx; L.Ty = (double *)Ty; L.Tz = (double *)Tz; L.Db = (double *)Db;
+      L.D = (double *)D; L.x = (double *)x; L.b = (double *)b;
     }
-    h->lv.push_back(C);
-  }
-  if (mixed) {
-    h->lv[0].xf = (float *)dalloc(h, (size_t)h->G.nc * 4, rc);   // z (FP32)
-    h->lv[0].bf = (float *)dalloc(h, (size_t)h->G.nc * 4, rc);   // rAU (FP32)
-    h->rf = (float *)dalloc(h, (size_t)h->G.nc * 4, rc);         // r (FP32)
-    h->zoldf = (float *)dalloc(h, (size_t)h->G.nc * 4, rc);      // previous z (FP32)
-    h->zf2 = (float *)dalloc(h, (size_t)h->G.nc * 4, rc);        // second z buffer (FP32)
-  } else {
-    h->z2 = (double *)dalloc(h, (size_t)h->G.nc * 8, rc);        // second z buffer
   }
   if (rc) return rc;
-  auto *sh = new std::vector<LShape>();
-  for (auto &L : h->lv)
-    sh->push_back(LShape{make_zg(L.n[0], L.n[1], L.n[2], false),
-                         make_zg(L.n[0], L.n[1], L.n[2], true),
-                         make_zg2(L.n[0], L.n[1], L.n[2], 64, false),
-                         make_zg2(L.n[0], L.n[1], L.n[2], 128, false),
-                         make_zg2(L.n[0], L.n[1], L.n[2], 128, true)});
-  h->lvshape = sh;
-  // bottom: the first level (>= 1) whose sub-hierarchy fits in the LDS budget
-  const size_t rs = mixed ? 4 : 8;
-  h->bottom = (int)h->lv.size() - 1;
-  for (int l = 1; l < (int)h->lv.size(); l++) {
-    size_t cells = 0;
-    for (int m = l; m < (int)h->lv.size(); m++) cells += (size_t)h->lv[m].nc;
-    if (cells * 6 * rs <= (size_t)BOTTOM_LDS) { h->bottom = l; break; }
+  const size_t NC = (size_t)h->NC;
+  if (mixed) {
+    h->lv[0].xf = (float *)dalloc(h, NC * 4, rc);   // z (FP32)
+    h->lv[0].bf = (float *)dalloc(h, NC * 4, rc);   // rAU (FP32)
+    h->rf = (float *)dalloc(h, NC * 4, rc);         // r (FP32)
+    h->zoldf = (float *)dalloc(h, NC * 4, rc);      // previous z (FP32)
+    h->zf2 = (float *)dalloc(h, NC * 4, rc);        // second z buffer (FP32)
+  } else {
+    h->z2 = (double *)dalloc(h, NC * 8, rc);        // second z buffer
   }
-  h->st.mg_levels = (int)h->lv.size();
-  h->red_blocks = zg_blocks((*sh)[0].one);
-  return rc;
+  h->act = (int *)dalloc(h, sizeof(int) * ns, rc);
+  h->want = (int *)dalloc(h, sizeof(int) * ns, rc);
+  if (rc) return rc;
+  // partial sums: the largest launch (fine tiles at one plane per block)
+  size_t np = 2 * (size_t)(NC / FLAT_CELLS);
+  size_t t1 = 0;
+  for (int s = 0; s < ns; s++)
+    t1 += (size_t)tiles25(h->hG[s].n[0], h->hG[s].n[1], h->hG[s].n[2], 64, 1);
+  np = std::max(np, 2 * t1);
+  np = std::max(np, 5 * (size_t)h->cell.nblk);
+  h->partials = (double *)dalloc(h, np * 8, rc);
+  h->npartials = np;
+  if (rc) return rc;
+  for (int s = 0; s < ns; s++) h->st[s].mg_levels = h->nlev[s];
+  return pressure_retune(h);
 }
 
-void pressure_free(Handle *h) {
-  delete reinterpret_cast<std::vector<LShape> *>(h->lvshape);
-  h->lvshape = nullptr;
-  h->lv.clear();
-}
-
-static dim3 blk() { return dim3(BX, BY); }
-static dim3 g1(const ZG &z) { return dim3(zg_blocks(z)); }
+void pressure_free(Handle *h) { h->lv.clear(); }
 
 template <typename R>
 static void build_hierarchy(Handle *h, const R *rAUr) {
-  auto &S = shapes(h);
   for (size_t l = 1; l < h->lv.size(); l++) {
     Level &C = h->lv[l];
     Level &F = h->lv[l - 1];
-    Op<R> opF = op_of<R>(h, (int)l - 1, rAUr);
-    DBS_LAUNCH(h, KC_BUILD_COARSE, k_build_coarse<R>, g1(S[l].one), blk(), opF,
-               (const R *)lDb<R>(F), S[l].one, C.n[0], C.n[1], C.n[2], lTx<R>(C), lTy<R>(C),
-               lTz<R>(C), lDb<R>(C));
-    DBS_LAUNCH(h, KC_BUILD_COARSE, k_diag<R>, g1(S[l].one), blk(), C.n[0], C.n[1], C.n[2],
-               S[l].one, (const R *)lTx<R>(C), (const R *)lTy<R>(C), (const R *)lTz<R>(C),
-               (const R *)lDb<R>(C), lD<R>(C));
+    if (!C.one_all.nblk) continue;
+    OpB<R> opF = opb<R>(h, (int)l - 1, rAUr);
+    DBS_LAUNCH(h, KC_BUILD_COARSE, k_build_coarse<R>, dim3(C.one_all.nblk), blk(), opF,
+               (const R *)(l == 1 ? nullptr : lDb<R>(F)), sh(h, C.one_all), lTx<R>(C),
+               lTy<R>(C), lTz<R>(C), lDb<R>(C));
+    DBS_LAUNCH(h, KC_BUILD_COARSE, k_diag<R>, dim3(C.one_all.nblk), blk(), (const LvS *)C.ds,
+               sh(h, C.one_all), (const R *)lTx<R>(C), (const R *)lTy<R>(C),
+               (const R *)lTz<R>(C), (const R *)lDb<R>(C), lD<R>(C));
   }
-}
-
-template <typename R>
-static void run_bottom(Handle *h) {
-  Bottom<R> A;
-  A.nl = (int)h->lv.size() - h->bottom;
-  A.pre = h->mg_pre;
-  A.post = h->mg_post;
-  int off = 0;
-  for (int l = 0; l < A.nl; l++) {
-    Level &L = h->lv[h->bottom + l];
-    A.L[l] = BLevel<R>{L.n[0], L.n[1], L.n[2], off, lTx<R>(L), lTy<R>(L), lTz<R>(L), lD<R>(L),
-                       lx<R>(L), lb<R>(L)};
-    off += L.nc;
-  }
-  A.ntot = off;
-  // a one-cell coarsest level is solved exactly by one sweep
-  A.coarse_sweeps = h->lv.back().nc == 1 ? 1 : h->coarse_sweeps;
-  DBS_LAUNCH(h, KC_COARSE, k_bottom<R>, dim3(1), dim3(1024), A);
 }
 
 template <typename R, typename B>
-static void smooth_level(Handle *h, int l, const Op<R> &o, const B *b, R *x, bool down) {
-  auto &S = shapes(h);
-  const int cls = l == 0 ? KC_SMOOTH0 : KC_SMOOTHC;
-  const int sweeps = down ? h->mg_pre : h->mg_post;
-  for (int s = 0; s < sweeps; s++) {
-    const int first = down ? 0 : 1;
-    DBS_LAUNCH(h, cls, (k_smooth<R, B>), g1(S[l].pair), blk(), o, S[l].pair, b, x, first,
-               down && s == 0);
-    DBS_LAUNCH(h, cls, (k_smooth<R, B>), g1(S[l].pair), blk(), o, S[l].pair, b, x, 1 - first, 0);
+static void smooth_level(Handle *h, int l, const OpB<R> &o, const B *b, R *x, bool down) {
+  Level &L = h->lv[l];
+  if (!L.pair_cyc.nblk) return;
+  const SH S = sh(h, L.pair_cyc);
+  const dim3 g(L.pair_cyc.nblk);
+  const int n = down ? h->mg_pre : h->mg_post;
+  const int first = down ? 0 : 1;
+  for (int s = 0; s < n; s++) {
+    DBS_LAUNCH(h, KC_SMOOTHC, (k_smooth<R, B>), g, blk(), o, S, b, x, first,
+               (int)(down && s == 0), (const int *)h->act);
+    DBS_LAUNCH(h, KC_SMOOTHC, (k_smooth<R, B>), g, blk(), o, S, b, x, 1 - first, 0,
+               (const int *)h->act);
   }
 }
 
 // fine-level half sweep with the 2.5-D kernel
 template <typename R, typename B>
-static void smooth_fine(Handle *h, const Op<R> &o, const B *b, const R *xin, R *xout, int color,
-                        int mode, const R *xc, int cn0, int cn1) {
-  const ZG2 &z = shapes(h)[0].sm;
-  const dim3 g(nblk2(z)), t(64, TY2);
+static void smooth_fine(Handle *h, const OpB<R> &o, const B *b, const R *xin, R *xout, int color,
+                        int mode, const R *xc) {
+  const Shape &Z = h->lv[0].sm;
+  const dim3 g(Z.nblk);
+  const SH S = sh(h, Z);
+  const int *m = h->act;
   if (mode == SM_ZERO)
-    DBS_LAUNCH(h, KC_SMOOTH0_ZERO, (k_smooth25<R, B, SM_ZERO>), g, t, o, z, b, xin, xout, color, xc,
-               cn0, cn1);
+    DBS_LAUNCH(h, KC_SMOOTH0_ZERO, (k_smooth25<R, B, SM_ZERO>), g, blk2(), o, S, b, xin, xout,
+               color, xc, m);
   else if (mode == SM_PROLONG)
-    DBS_LAUNCH(h, KC_PROLONG0, (k_smooth25<R, B, SM_PROLONG>), g, t, o, z, b, xin, xout, color, xc,
-               cn0, cn1);
+    DBS_LAUNCH(h, KC_PROLONG0, (k_smooth25<R, B, SM_PROLONG>), g, blk2(), o, S, b, xin, xout,
+               color, xc, m);
   else
-    DBS_LAUNCH(h, KC_SMOOTH0, (k_smooth25<R, B, SM_NORMAL>), g, t, o, z, b, xin, xout, color, xc,
-               cn0, cn1);
+    DBS_LAUNCH(h, KC_SMOOTH0, (k_smooth25<R, B, SM_NORMAL>), g, blk2(), o, S, b, xin, xout,
+               color, xc, m);
 }
 
-// z = M r: one V-cycle.  b0 is the fine right-hand side (r); z0 and z1 are
-// the two fine correction buffers; returns the one holding the result.
+// z = M r: one V-cycle over the active samples.  b0 is the fine right-hand
+// side (r); z0 and z1 are the two fine correction buffers; returns the one
+// holding the result.
 template <typename R, typename B>
 static R *vcycle(Handle *h, const R *rAUr, const B *b0, R *z0, R *z1) {
-  auto &S = shapes(h);
+  const int *act = h->act;
   const int nl = (int)h->lv.size();
-  Op<R> o0 = op_of<R>(h, 0, rAUr);
-  if (nl == 1) {
-    for (int s = 0; s < h->mg_pre; s++) {
-      smooth_fine<R, B>(h, o0, b0, z0, z0, 0, s == 0 ? SM_ZERO : SM_NORMAL, nullptr, 0, 0);
-      smooth_fine<R, B>(h, o0, b0, z0, z0, 1, SM_NORMAL, nullptr, 0, 0);
-    }
-    for (int s = 0; s < h->mg_post; s++) {
-      smooth_fine<R, B>(h, o0, b0, z0, z0, 1, SM_NORMAL, nullptr, 0, 0);
-      smooth_fine<R, B>(h, o0, b0, z0, z0, 0, SM_NORMAL, nullptr, 0, 0);
-    }
-    return z0;
-  }
+  OpB<R> o0 = opb<R>(h, 0, rAUr);
   // fine level down: red (zero guess), black, ...; red-only restriction
   for (int s = 0; s < h->mg_pre; s++) {
-    smooth_fine<R, B>(h, o0, b0, z0, z0, 0, s == 0 ? SM_ZERO : SM_NORMAL, nullptr, 0, 0);
-    smooth_fine<R, B>(h, o0, b0, z0, z0, 1, SM_NORMAL, nullptr, 0, 0);
+    smooth_fine<R, B>(h, o0, b0, z0, z0, 0, s == 0 ? SM_ZERO : SM_NORMAL, (const R *)nullptr);
+    smooth_fine<R, B>(h, o0, b0, z0, z0, 1, SM_NORMAL, (const R *)nullptr);
   }
-  {
-    Level &C = h->lv[1];
-    const ZG2 &z = S[0].rs;
-    DBS_LAUNCH(h, KC_RESTRICT0, (k_restrict25<R, B>), dim3(nblk2(z)), dim3(64, TY2), o0, z, b0,
-               (const R *)z0, lb<R>(C), C.n[0], C.n[1]);
+  const R *xc1 = nl > 1 ? (const R *)lx<R>(h->lv[1]) : nullptr;
+  if (nl > 1 && h->lv[0].rs.nblk) {
+    const Shape &Z = h->lv[0].rs;
+    DBS_LAUNCH(h, KC_RESTRICT0, (k_restrict25<R, B>), dim3(Z.nblk), blk2(), o0, sh(h, Z), b0,
+               (const R *)z0, lb<R>(h->lv[1]), act);
   }
-  for (int l = 1; l < h->bottom; l++) {
-    Op<R> o = op_of<R>(h, l, rAUr);
+  for (int l = 1; l < h->maxbottom; l++) {
+    OpB<R> o = opb<R>(h, l, rAUr);
     Level &L = h->lv[l];
     Level &C = h->lv[l + 1];
     smooth_level<R, R>(h, l, o, (const R *)lb<R>(L), lx<R>(L), true);
-    DBS_LAUNCH(h, KC_RESTRICTC, (k_restrict<R, R>), g1(S[l + 1].one), blk(), o, S[l + 1].one,
-               C.n[0], C.n[1], C.n[2], (const R *)lb<R>(L), (const R *)lx<R>(L), lb<R>(C));
+    if (C.one_rc.nblk)
+      DBS_LAUNCH(h, KC_RESTRICTC, (k_restrict<R, R>), dim3(C.one_rc.nblk), blk(), o,
+                 sh(h, C.one_rc), (const R *)lb<R>(L), (const R *)lx<R>(L), lb<R>(C), act);
   }
-  run_bottom<R>(h);
-  for (int l = h->bottom - 1; l >= 1; l--) {
-    Op<R> o = op_of<R>(h, l, rAUr);
+  if (h->nbt)
+    DBS_LAUNCH(h, KC_COARSE, k_bottom<R>, dim3(h->nbt), dim3(1024),
+               (const Bottom<R> *)h->btab, act);
+  for (int l = h->maxbottom - 1; l >= 1; l--) {
+    OpB<R> o = opb<R>(h, l, rAUr);
     Level &L = h->lv[l];
     Level &C = h->lv[l + 1];
-    DBS_LAUNCH(h, KC_PROLONGC, k_prolong<R>, g1(S[l].one), blk(), L.n[0], L.n[1], L.n[2],
-               S[l].one, C.n[0], C.n[1], (const R *)lx<R>(C), lx<R>(L));
+    if (L.one_cyc.nblk)
+      DBS_LAUNCH(h, KC_PROLONGC, k_prolong<R>, dim3(L.one_cyc.nblk), blk(), (const LvS *)L.ds,
+                 sh(h, L.one_cyc), (const R *)lx<R>(C), lx<R>(L), act);
     smooth_level<R, R>(h, l, o, (const R *)lb<R>(L), lx<R>(L), false);
   }
   // fine level up: the prolongation rides on the first (black) half sweep
-  Level &C = h->lv[1];
   for (int s = 0; s < h->mg_post; s++) {
     if (s == 0)
-      smooth_fine<R, B>(h, o0, b0, z0, z1, 1, SM_PROLONG, (const R *)lx<R>(C), C.n[0], C.n[1]);
+      smooth_fine<R, B>(h, o0, b0, z0, z1, 1, SM_PROLONG, xc1);
     else
-      smooth_fine<R, B>(h, o0, b0, z1, z1, 1, SM_NORMAL, nullptr, 0, 0);
-    smooth_fine<R, B>(h, o0, b0, z1, z1, 0, SM_NORMAL, nullptr, 0, 0);
+      smooth_fine<R, B>(h, o0, b0, z1, z1, 1, SM_NORMAL, (const R *)nullptr);
+    smooth_fine<R, B>(h, o0, b0, z1, z1, 0, SM_NORMAL, (const R *)nullptr);
   }
   return z1;
 }
 
-static void finalize(Handle *h, int two, int slot, int slot2, int op, int n = -1) {
-  DBS_LAUNCH(h, KC_FINALIZE, k_finalize, dim3(1), dim3(1024), (const double *)h->partials,
-             n < 0 ? h->red_blocks : n, two, h->scal, slot, slot2, op);
+// ---------------------------------------------------------------- CG
+
+static FinArgs fin_args(Handle *h, const Shape *S, int two, int slot, int slot2, int op,
+                        const int *mask, int closed_only = 0) {
+  FinArgs A;
+  A.partials = h->partials;
+  A.bp = S ? S->bp : nullptr;
+  A.off2 = S ? S->nblk : 0;
+  A.two = two;
+  A.slot = slot;
+  A.slot2 = slot2;
+  A.op = op;
+  A.mask = mask;
+  A.rng = h->rng;
+  A.closed_only = closed_only;
+  A.act = h->act;
+  A.want = h->want;
+  A.tol2 = h->ctl.p_tol * h->ctl.p_tol;
+  A.maxit = h->ctl.p_maxit;
+  A.replace_every = h->ctl.precision == DBS_MIXED ? 8 : 0;
+  return A;
 }
 
+static void finalize(Handle *h, const FinArgs &A) {
+  DBS_LAUNCH(h, KC_FINALIZE, k_finalize, dim3(h->ns), dim3(FLAT_T), A, h->scal);
+}
 
-static double fetch(Handle *h, int slot) {
-  (void)hipMemcpyAsync(h->hscal, h->scal, sizeof(double) * S_NSCAL, hipMemcpyDeviceToHost, h->stream);
+static bool any_closed(const Handle *h) {
+  for (const Rng &g : h->hrng)
+    if (g.closed) return true;
+  return false;
+}
+
+static dim3 flat_grid(const Handle *h) { return dim3((unsigned)(h->NC / FLAT_CELLS)); }
+
+void arena_copy(Handle *h, const double *src, double *dst, int narrays) {
+  DBS_LAUNCH(h, KC_MISC, k_copy, dim3((unsigned)(narrays * (h->NC / FLAT_CELLS))),
+             dim3(FLAT_T), src, dst);
+}
+
+// x -= mean(x) on the closed samples selected by mask (FP32 copy refreshed)
+static void remove_mean(Handle *h, double *x, float *xf, const int *mask) {
+  DBS_LAUNCH(h, KC_MISC, k_sum, flat_grid(h), dim3(FLAT_T), fl(h), (const double *)x,
+             h->partials, mask);
+  finalize(h, fin_args(h, &h->flat, 0, S_SUM, 0, FIN_STORE, mask, 1));
+  DBS_LAUNCH(h, KC_MISC, k_sub_mean, flat_grid(h), dim3(FLAT_T), fl(h), (const double *)h->scal,
+             x, xf, mask);
+}
+
+// slot = a.a over the closed samples selected by mask
+static void dot_self_closed(Handle *h, const double *a, int slot, const int *mask) {
+  DBS_LAUNCH(h, KC_DOT, k_dot2<double>, flat_grid(h), dim3(FLAT_T), fl(h), a, a,
+             (const double *)nullptr, h->partials, (int)h->flat.nblk, mask, 1);
+  finalize(h, fin_args(h, &h->flat, 0, slot, 0, FIN_STORE, mask, 1));
+}
+
+// true residual r = b - A x (and its FP32 copy) of the samples selected by
+// mask; S_RR = r.r (projected on closed samples) and S_BB = b.b
+static void true_residual(Handle *h, const double *rAU, const double *b, const double *x,
+                          float *rf, const int *mask) {
+  const Shape &Z = h->lv[0].st;
+  OpB<double> o = opb<double>(h, 0, rAU);
+  DBS_LAUNCH(h, KC_SPMV, k_stencil25<1>, dim3(Z.nblk), blk2(), o, sh(h, Z), x, b, h->r, rf,
+             h->partials, (int)Z.nblk, mask);
+  finalize(h, fin_args(h, &Z, 1, S_RR, S_BB, FIN_STORE, mask));
+  if (any_closed(h)) {
+    remove_mean(h, h->r, rf, mask);
+    dot_self_closed(h, h->r, S_RR, mask);
+  }
+}
+
+// copies the CG flags to the host; returns the number of active samples and
+// sets *nwant to the number asking for a true residual
+static int fetch_flags(Handle *h, int *nwant) {
+  (void)hipMemcpyAsync(h->hflags, h->act, sizeof(int) * h->ns, hipMemcpyDeviceToHost,
+                       h->stream);
+  (void)hipMemcpyAsync(h->hflags + h->ns, h->want, sizeof(int) * h->ns, hipMemcpyDeviceToHost,
+                       h->stream);
   (void)hipStreamSynchronize(h->stream);
-  return h->hscal[slot];
-}
-
-static void remove_mean(Handle *h, double *x) {
-  const ZG &z = shapes(h)[0].one;
-  const Geom &G = h->G;
-  DBS_LAUNCH(h, KC_MISC, k_sum, g1(z), blk(), G.n[0], G.n[1], G.n[2], z, (const double *)x,
-             h->partials);
-  finalize(h, 0, S_SUM, 0, FIN_STORE);
-  DBS_LAUNCH(h, KC_MISC, k_sub_mean, g1(z), blk(), G.n[0], G.n[1], G.n[2], z,
-             (const double *)h->scal, x);
-}
-
-static void dot_self(Handle *h, const double *a, int slot) {
-  const ZG &z = shapes(h)[0].one;
-  const Geom &G = h->G;
-  DBS_LAUNCH(h, KC_DOT, k_dot2<double>, g1(z), blk(), G.n[0], G.n[1], G.n[2], z, a, a,
-             (const double *)nullptr, h->partials);
-  finalize(h, 0, slot, 0, FIN_STORE);
-}
-
-// true residual r = b - A x; returns ||r|| and sets ||b||
-static double true_residual(Handle *h, const double *rAU, const double *b, const double *x,
-                            double *nb) {
-  const ZG2 &z = shapes(h)[0].st;
-  Op<double> o = op_of<double>(h, 0, rAU);
-  DBS_LAUNCH(h, KC_SPMV, k_stencil25<1>, dim3(nblk2(z)), dim3(64, TY2), o, z, x, b, h->r,
-             h->partials);
-  finalize(h, 1, S_RR, S_BB, FIN_STORE, nblk2(z));
-  if (!h->G.has_outlet) {
-    remove_mean(h, h->r);
-    dot_self(h, h->r, S_RR);
+  int na = 0, nw = 0;
+  for (int s = 0; s < h->ns; s++) {
+    na += h->hflags[s] != 0;
+    nw += h->hflags[h->ns + s] != 0;
   }
-  fetch(h, S_RR);
-  *nb = sqrt(h->hscal[S_BB]);
-  return sqrt(h->hscal[S_RR]);
+  if (nwant) *nwant = nw;
+  return na;
 }
 
-// z = M r (FP32 V-cycle on an FP32 copy of r in the mixed form); returns z
-template <typename R>
-static R *precondition(Handle *h, const R *rAUr) {
-  const ZG &z = shapes(h)[0].one;
-  const Geom &G = h->G;
-  if (std::is_same<R, float>::value) {
-    DBS_LAUNCH(h, KC_MISC, k_cast<float>, g1(z), blk(), G.n[0], G.n[1], G.n[2], z,
-               (const double *)h->r, h->rf);
-    return (R *)vcycle<float, float>(h, (const float *)rAUr, (const float *)h->rf, h->lv[0].xf,
-                                     h->zf2);
-  }
-  return (R *)vcycle<double, double>(h, (const double *)rAUr, (const double *)h->r, h->z, h->z2);
+// act[s] = va (va < 0: unchanged), want[s] = vw
+static void set_flags(Handle *h, int va, int vw) {
+  DBS_LAUNCH(h, KC_MISC, k_flags, dim3((h->ns + 255) / 256), dim3(256), va < 0 ? nullptr : h->act,
+             va, h->want, vw, h->ns);
 }
 
 template <typename R>
-static int pcg(Handle *h, const double *rAU, const double *b, double *x, int *iters,
-               double *relres) {
-  const Geom &G = h->G;
-  const ZG &z = shapes(h)[0].one;
+static int pcg(Handle *h, const double *rAU, const double *b, double *x, int budget,
+               int *iters, double *relres) {
   const bool flex = std::is_same<R, float>::value;
+  const bool graph = budget > 0;
   const R *rAUr;
+  float *rf = flex ? h->rf : nullptr;
   if (flex) {
-    float *rf = h->lv[0].bf;
-    DBS_LAUNCH(h, KC_MISC, k_cast<float>, g1(z), blk(), G.n[0], G.n[1], G.n[2], z, rAU, rf);
-    rAUr = (const R *)rf;
+    float *rAUf = h->lv[0].bf;
+    DBS_LAUNCH(h, KC_MISC, k_cast<float>, flat_grid(h), dim3(FLAT_T), rAU, rAUf);
+    rAUr = (const R *)rAUf;
   } else {
     rAUr = (const R *)rAU;
   }
   build_hierarchy<R>(h, rAUr);
-  double nb;
-  double nr = true_residual(h, rAU, b, x, &nb);
-  if (!G.has_outlet) {
+  // initial residual and norms of every sample
+  set_flags(h, 1, 1);
+  true_residual(h, rAU, b, x, rf, h->want);
+  if (any_closed(h)) {
     // closed domain: norm of the projected (compatible) right-hand side
-    (void)hipMemcpyAsync(h->z, b, sizeof(double) * G.nc, hipMemcpyDeviceToDevice, h->stream);
-    remove_mean(h, h->z);
-    dot_self(h, h->z, S_BB);
-    nb = sqrt(fetch(h, S_BB));
+    arena_copy(h, b, h->z, 1);
+    remove_mean(h, h->z, nullptr, nullptr);
+    dot_self_closed(h, h->z, S_BB, nullptr);
   }
-  const double norm = nb > 0.0 ? nb : nr;
-  const double tol = h->ctl.p_tol;
-  int it = 0, rc = DBS_OK;
-  R *zR = nullptr;
+  finalize(h, fin_args(h, nullptr, 0, 0, 0, FIN_INIT, nullptr));
+  const FL F = fl(h);
+  const dim3 fg = flat_grid(h), ft(FLAT_T);
+  const int *act = h->act;
   R *zold = flex ? (R *)h->zoldf : nullptr;
-  const int n0 = G.n[0], n1 = G.n[1], n2 = G.n[2];
-  const LShape &S0 = shapes(h)[0];
-  if (norm > 0.0 && nr > tol * norm) {
-    const int replace_every = flex ? 8 : 0;
-    Op<double> o = op_of<double>(h, 0, rAU);
-    zR = precondition<R>(h, rAUr);
-    DBS_LAUNCH(h, KC_DOT, k_dot2<R>, g1(z), blk(), n0, n1, n2, z, (const double *)h->r,
-               (const R *)zR, (const R *)nullptr, h->partials);
-    finalize(h, 0, S_RZ, 0, FIN_STORE);
-    DBS_LAUNCH(h, KC_XPBY, k_xpby<R>, g1(z), blk(), n0, n1, n2, z, (const double *)h->scal,
-               (const R *)zR, h->pv, 1, zold);
-    for (;;) {
-      if (it >= h->ctl.p_maxit) { rc = DBS_ENOCONV; break; }
-      DBS_LAUNCH(h, KC_SPMV, k_stencil25<0>, dim3(nblk2(S0.st)), dim3(64, TY2), o, S0.st,
-                 (const double *)h->pv, (const double *)nullptr, h->q, h->partials);
-      finalize(h, 0, S_PQ, 0, FIN_ALPHA, nblk2(S0.st));
-      DBS_LAUNCH(h, KC_AXPY, k_axpy_dot, g1(z), blk(), n0, n1, n2, z, (const double *)h->scal,
-                 (const double *)h->pv, (const double *)h->q, x, h->r, h->partials);
-      it++;
-      bool replaced = false;
-      if (replace_every > 0 && it % (replace_every > 0 ? replace_every : 1) == 0) {
-        // residual replacement: the true FP64 residual takes the recursive one's place
-        nr = true_residual(h, rAU, b, x, &nb);
-        replaced = true;
-      } else {
-        finalize(h, 0, S_RR, 0, FIN_STORE);
-        nr = sqrt(fetch(h, S_RR));
+  const Shape &ST = h->lv[0].st;
+  OpB<double> o = opb<double>(h, 0, rAU);
+  auto precondition = [&]() -> R * {
+    if (flex)
+      return (R *)vcycle<float, float>(h, (const float *)rAUr, (const float *)h->rf,
+                                       h->lv[0].xf, h->zf2);
+    return (R *)vcycle<double, double>(h, (const double *)rAUr, (const double *)h->r, h->z,
+                                       h->z2);
+  };
+  int nact = graph ? 1 : fetch_flags(h, nullptr);
+  if (nact > 0) {
+    R *zR = precondition();
+    DBS_LAUNCH(h, KC_DOT, k_dot2<R>, fg, ft, F, (const double *)h->r, (const R *)zR,
+               (const R *)nullptr, h->partials, (int)h->flat.nblk, act, 0);
+    finalize(h, fin_args(h, &h->flat, 0, S_RZ, 0, FIN_STORE, act));
+    DBS_LAUNCH(h, KC_XPBY, k_xpby<R>, fg, ft, F, (const double *)h->scal, (const R *)zR, h->pv,
+               1, zold, act);
+    for (int it = 0;; it++) {
+      if (graph && it >= budget) break;
+      DBS_LAUNCH(h, KC_SPMV, k_stencil25<0>, dim3(ST.nblk), blk2(), o, sh(h, ST),
+                 (const double *)h->pv, (const double *)nullptr, h->q, (float *)nullptr,
+                 h->partials, 0, act);
+      finalize(h, fin_args(h, &ST, 0, S_PQ, 0, FIN_ALPHA, act));
+      DBS_LAUNCH(h, KC_AXPY, k_axpy_dot, fg, ft, F, (const double *)h->scal,
+                 (const double *)h->pv, (const double *)h->q, x, h->r, rf, h->partials, act);
+      finalize(h, fin_args(h, &h->flat, 0, S_RR, 0, FIN_RR, act));
+      int nwant = 1;
+      if (!graph) nact = fetch_flags(h, &nwant);
+      if (nwant > 0) {
+        // the true residual decides convergence (and replaces the recursive one)
+        true_residual(h, rAU, b, x, rf, h->want);
+        finalize(h, fin_args(h, nullptr, 0, 0, 0, FIN_CHECK, h->want));
+        if (!graph) nact = fetch_flags(h, nullptr);
       }
-      if (nr <= tol * norm) {
-        // stop only when the true residual b - A x meets the tolerance; else
-        // continue with it in place of the recursive one
-        if (replaced) break;
-        nr = true_residual(h, rAU, b, x, &nb);
-        if (nr <= tol * norm) break;
-      }
-      zR = precondition<R>(h, rAUr);
+      if (!graph && nact == 0) break;
+      R *zn = precondition();
       if (flex) {
-        DBS_LAUNCH(h, KC_DOT, k_dot2<R>, g1(z), blk(), n0, n1, n2, z, (const double *)h->r,
-                   (const R *)zR, (const R *)zold, h->partials);
-        finalize(h, 1, S_RZNEW, S_RZOLD, FIN_BETA_FLEX);
+        DBS_LAUNCH(h, KC_DOT, k_dot2<R>, fg, ft, F, (const double *)h->r, (const R *)zn,
+                   (const R *)zold, h->partials, (int)h->flat.nblk, act, 0);
+        finalize(h, fin_args(h, &h->flat, 1, S_RZNEW, S_RZOLD, FIN_BETA_FLEX, act));
       } else {
-        DBS_LAUNCH(h, KC_DOT, k_dot2<R>, g1(z), blk(), n0, n1, n2, z, (const double *)h->r,
-                   (const R *)zR, (const R *)nullptr, h->partials);
-        finalize(h, 0, S_RZNEW, 0, FIN_BETA);
+        DBS_LAUNCH(h, KC_DOT, k_dot2<R>, fg, ft, F, (const double *)h->r, (const R *)zn,
+                   (const R *)nullptr, h->partials, (int)h->flat.nblk, act, 0);
+        finalize(h, fin_args(h, &h->flat, 0, S_RZNEW, 0, FIN_BETA, act));
       }
-      DBS_LAUNCH(h, KC_XPBY, k_xpby<R>, g1(z), blk(), n0, n1, n2, z, (const double *)h->scal,
-                 (const R *)zR, h->pv, 0, zold);
+      DBS_LAUNCH(h, KC_XPBY, k_xpby<R>, fg, ft, F, (const double *)h->scal, (const R *)zn,
+                 h->pv, 0, zold, act);
     }
   }
-  if (!G.has_outlet) remove_mean(h, x);
-  nr = true_residual(h, rAU, b, x, &nb);
-  if (iters) *iters = it;
-  if (relres) *relres = norm > 0.0 ? nr / norm : 0.0;
-  return rc;
+  if (any_closed(h)) remove_mean(h, x, nullptr, nullptr);
+  // final true residual of every sample (act is kept: a sample still active
+  // here did not converge within the budget)
+  set_flags(h, -1, 1);
+  true_residual(h, rAU, b, x, nullptr, h->want);
+  finalize(h, fin_args(h, nullptr, 0, 0, 0, FIN_RRFIN, nullptr));
+  if (graph) return DBS_OK;
+  std::vector<int> conv(h->ns);
+  pressure_results(h, iters, relres, conv.data());
+  for (int s = 0; s < h->ns; s++)
+    if (!conv[s]) return DBS_ENOCONV;
+  return DBS_OK;
 }
 
-int pressure_solve(Handle *h, const double *rAU, const double *b, double *x, int *iters,
-                   double *relres) {
-  if (h->ctl.precision == DBS_MIXED) return pcg<float>(h, rAU, b, x, iters, relres);
-  return pcg<double>(h, rAU, b, x, iters, relres);
+void pressure_results(Handle *h, int *iters, double *relres, int *converged) {
+  const int ns = h->ns;
+  (void)hipMemcpyAsync(h->hscal, h->scal, sizeof(double) * NSC * ns, hipMemcpyDeviceToHost,
+                       h->stream);
+  (void)hipMemcpyAsync(h->hflags, h->act, sizeof(int) * ns, hipMemcpyDeviceToHost, h->stream);
+  (void)hipStreamSynchronize(h->stream);
+  for (int s = 0; s < ns; s++) {
+    const double *S = h->hscal + (size_t)s * NSC;
+    if (iters) iters[s] = (int)S[S_ITS];
+    if (relres) relres[s] = S[S_NRM2] > 0.0 ? sqrt(S[S_RRFIN] / S[S_NRM2]) : 0.0;
+    if (converged) converged[s] = S[S_NOCONV] == 0.0 && h->hflags[s] == 0;
+  }
+}
+
+int pressure_solve(Handle *h, const double *rAU, const double *b, double *x, int budget,
+                   int *iters, double *relres) {
+  if (h->ctl.precision == DBS_MIXED) return pcg<float>(h, rAU, b, x, budget, iters, relres);
+  return pcg<double>(h, rAU, b, x, budget, iters, relres);
+}
+
+}  // namespace dbs
+
+namespace dbs {
+
+// per-sample results of the last solve, stored for corrector c (graph mode:
+// read back once after the replayed step)
+__global__ void k_record(const double *__restrict__ scal, const int *__restrict__ act, int ns,
+                         double *__restrict__ rec, int c) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= ns) return;
+  const double *S = scal + (size_t)s * NSC;
+  double *o = rec + ((size_t)s * 16 + c) * 3;
+  o[0] = S[S_ITS];
+  o[1] = S[S_NRM2] > 0.0 ? sqrt(S[S_RRFIN] / S[S_NRM2]) : 0.0;
+  o[2] = (S[S_NOCONV] == 0.0 && act[s] == 0) ? 1.0 : 0.0;
+}
+
+__global__ void __launch_bounds__(FLAT_T) k_copyn(const double *__restrict__ in,
+                                                  double *__restrict__ out, size_t n) {
+  const size_t c = (size_t)blockIdx.x * FLAT_T + threadIdx.x;
+  if (c < n) out[c] = in[c];
+}
+
+void pressure_record(Handle *h, double *rec, int c) {
+  DBS_LAUNCH(h, KC_MISC, k_record, dim3((h->ns + 255) / 256), dim3(256),
+             (const double *)h->scal, (const int *)h->act, h->ns, rec, c);
+}
+
+void copy_n(Handle *h, const double *src, double *dst, size_t n) {
+  if (!n) return;
+  DBS_LAUNCH(h, KC_MISC, k_copyn, dim3((unsigned)((n + FLAT_T - 1) / FLAT_T)), dim3(FLAT_T), src,
+             dst, n);
 }
 
 }  // namespace dbs

@@ -25,6 +25,9 @@ EXPORTS = (
     "dbs_last_error", "dbs_destroy", "dbs_set_profiling", "dbs_kernel_time",
     "dbs_kernel_name", "dbs_kernel_classes", "dbs_reset_profiling",
     "dbs_debug_pressure_solve", "dbs_debug_step_trace",
+    "dbs_batch_create", "dbs_batch_size", "dbs_batch_set_static", "dbs_batch_set_state",
+    "dbs_batch_get_state", "dbs_batch_set_state_dev", "dbs_batch_get_state_dev",
+    "dbs_batch_get_stats", "dbs_set_graph", "dbs_autotune", "dbs_set_tuning",
 )
 
 
@@ -105,6 +108,19 @@ def lib():
         L.dbs_reset_profiling.restype = None
         L.dbs_debug_pressure_solve.argtypes = [H, _DP, _DP, _DP, C.POINTER(C.c_int), _DP]
         L.dbs_debug_step_trace.argtypes = [H] + [_DP] * 7
+        L.dbs_batch_create.argtypes = [C.c_int, C.POINTER(Grid), C.POINTER(Physics),
+                                       C.POINTER(BC), C.POINTER(Controls), C.POINTER(H)]
+        L.dbs_batch_size.argtypes = [H]
+        L.dbs_batch_set_static.argtypes = [H, C.c_int, _DP, _DP]
+        L.dbs_batch_set_state.argtypes = [H, C.c_int, _DP, _DP, _DP, _DP]
+        L.dbs_batch_get_state.argtypes = [H, C.c_int, _DP, _DP, _DP, _DP, _DP]
+        L.dbs_batch_set_state_dev.argtypes = [H, C.c_int] + [C.c_void_p] * 5
+        L.dbs_batch_get_state_dev.argtypes = [H, C.c_int] + [C.c_void_p] * 6
+        L.dbs_batch_get_stats.argtypes = [H, C.c_int, C.POINTER(Stats)]
+        L.dbs_set_graph.argtypes = [H, C.c_int]
+        L.dbs_autotune.argtypes = [H, C.POINTER(C.c_int), C.POINTER(C.c_int),
+                                   C.POINTER(C.c_int), _DP]
+        L.dbs_set_tuning.argtypes = [H, C.c_int, C.c_int, C.c_int]
         _lib = L
     return _lib
 
@@ -164,29 +180,10 @@ def make_structs(case, precision=None, p_tol=None, mg=None, max_courant=0.0, bou
     return g, p, bcs, c
 
 
-class Solver:
-    """One single-domain problem resident on the current HIP device."""
+class _Handle:
+    """Methods shared by single-sample and batch handles."""
 
-    def __init__(self, case, precision=None, p_tol=None, mg=None, max_courant=0.0,
-                 bounds_tol=0.0, state=None):
-        self.case = case
-        self.shape = tuple(case.shape)
-        self.nc = int(np.prod(self.shape))
-        self.nf = nfaces(self.shape)
-        L = lib()
-        g, p, bcs, c = make_structs(case, precision, p_tol, mg, max_courant, bounds_tol)
-        h = C.c_void_p()
-        self._check(L.dbs_create(C.byref(g), C.byref(p), bcs, C.byref(c), C.byref(h)), None)
-        self.h = h
-        phi = np.ascontiguousarray(case.phi, dtype=np.float64).reshape(self.nc)
-        kinv = np.ascontiguousarray(case.kinv, dtype=np.float64).reshape(self.nc)
-        self._check(L.dbs_set_static(h, _ptr(phi), _ptr(kinv)))
-        if state is None:
-            F = None
-            if getattr(case, "F", None) is not None:
-                F = np.concatenate([np.asarray(f, dtype=np.float64).ravel() for f in case.F])
-            state = {"alpha": case.alpha, "U": case.U, "p_rgh": case.p_rgh, "F": F}
-        self.set_state(state)
+    h = None
 
     def _check(self, rc, h="self"):
         if rc != OK:
@@ -196,75 +193,36 @@ class Solver:
             raise DBSError(rc, msg)
         return rc
 
-    def set_state(self, st):
-        a = np.ascontiguousarray(st["alpha"], dtype=np.float64).reshape(self.nc)
-        U = np.ascontiguousarray(st["U"], dtype=np.float64).reshape(3 * self.nc)
-        pr = np.ascontiguousarray(st["p_rgh"], dtype=np.float64).reshape(self.nc)
-        F = st.get("F")
-        if F is not None:
-            if isinstance(F, (tuple, list)):
-                F = np.concatenate([np.asarray(f, dtype=np.float64).ravel() for f in F])
-            F = np.ascontiguousarray(F, dtype=np.float64)
-            assert F.size == self.nf
-        self._check(lib().dbs_set_state(self.h, _ptr(a), _ptr(U), _ptr(pr), _ptr(F)))
-
     def step(self, n=1, check=True):
         rc = lib().dbs_step(self.h, int(n))
         if check:
             self._check(rc)
         return rc
 
-    def state(self):
-        a = np.zeros(self.nc)
-        U = np.zeros(3 * self.nc)
-        pr = np.zeros(self.nc)
-        p = np.zeros(self.nc)
-        F = np.zeros(self.nf)
-        self._check(lib().dbs_get_state(self.h, _ptr(a), _ptr(U), _ptr(pr), _ptr(p), _ptr(F)))
-        nx, ny, nz = self.shape
-        n1 = (nx + 1) * ny * nz
-        n2 = n1 + nx * (ny + 1) * nz
-        return {"alpha": a, "U": U.reshape(3, self.nc), "p_rgh": pr, "p": p,
-                "F": (F[:n1], F[n1:n2], F[n2:])}
-
-    def set_state_dev(self, alpha, U, p_rgh, F=None, stream=None):
-        """Device buffers given as raw pointers (e.g. torch ``data_ptr()``)."""
-        self._check(lib().dbs_set_state_dev(self.h, alpha, U, p_rgh, F, stream))
-
-    def get_state_dev(self, alpha=None, U=None, p_rgh=None, p=None, F=None, stream=None):
-        self._check(lib().dbs_get_state_dev(self.h, alpha, U, p_rgh, p, F, stream))
-
     def set_stream(self, stream):
         self._check(lib().dbs_set_stream(self.h, stream))
 
-    def stats(self):
-        s = Stats()
-        self._check(lib().dbs_get_stats(self.h, C.byref(s)))
-        n = self.case.n_corr
+    def set_graph(self, on=True):
+        """Replay steps from captured HIP graphs (see dbs_set_graph)."""
+        self._check(lib().dbs_set_graph(self.h, int(bool(on))))
+
+    def autotune(self):
+        """Tune tile depth, sweeps and bottom depth on the current state."""
+        kz, sw, sh = C.c_int(), C.c_int(), C.c_int()
+        ms = C.c_double()
+        self._check(lib().dbs_autotune(self.h, C.byref(kz), C.byref(sw), C.byref(sh),
+                                       C.byref(ms)))
+        return {"kz": kz.value, "sweeps": sw.value, "bottom_shift": sh.value, "ms": ms.value}
+
+    def set_tuning(self, kz=0, sweeps=2, bottom_shift=0):
+        self._check(lib().dbs_set_tuning(self.h, int(kz), int(sweeps), int(bottom_shift)))
+
+    @staticmethod
+    def _stats_dict(s, n):
         return {"steps": s.steps, "p_iters": list(s.p_iters)[:n],
                 "p_relres": list(s.p_relres)[:n], "mg_levels": s.mg_levels,
                 "alpha_min": s.alpha_min, "alpha_max": s.alpha_max,
                 "phase_volume": s.phase_volume, "max_courant": s.max_courant}
-
-    def pressure_solve(self, rAU, b, x0=None):
-        rAU = np.ascontiguousarray(rAU, dtype=np.float64).ravel()
-        b = np.ascontiguousarray(b, dtype=np.float64).ravel()
-        x = np.zeros(self.nc) if x0 is None else np.ascontiguousarray(x0, dtype=np.float64).copy()
-        it = C.c_int()
-        rr = C.c_double()
-        self._check(lib().dbs_debug_pressure_solve(self.h, _ptr(rAU), _ptr(b), _ptr(x),
-                                                   C.byref(it), C.byref(rr)))
-        return x, it.value, rr.value
-
-    def trace_step(self):
-        nc, nf = self.nc, self.nf
-        out = {"A": np.zeros(nf), "rAU": np.zeros(nc), "Shat": np.zeros(3 * nc),
-               "Ustar": np.zeros(3 * nc), "HbyA": np.zeros(3 * nc), "phiHbyA": np.zeros(nf),
-               "b": np.zeros(nc)}
-        self._check(lib().dbs_debug_step_trace(
-            self.h, *[_ptr(out[k]) for k in ("A", "rAU", "Shat", "Ustar", "HbyA", "phiHbyA",
-                                              "b")]))
-        return out
 
     # -------------------------------------------------------------- profiling
     def set_profiling(self, mask):
@@ -308,3 +266,164 @@ class Solver:
 
     def __exit__(self, *a):
         self.close()
+
+
+def _flat_faces(F):
+    if isinstance(F, (tuple, list)):
+        F = np.concatenate([np.asarray(f, dtype=np.float64).ravel() for f in F])
+    return np.ascontiguousarray(F, dtype=np.float64)
+
+
+def _split_faces(F, shape):
+    nx, ny, nz = shape
+    n1 = (nx + 1) * ny * nz
+    n2 = n1 + nx * (ny + 1) * nz
+    return (F[:n1], F[n1:n2], F[n2:])
+
+
+class Solver(_Handle):
+    """One single-domain problem resident on the current HIP device."""
+
+    def __init__(self, case, precision=None, p_tol=None, mg=None, max_courant=0.0,
+                 bounds_tol=0.0, state=None):
+        self.case = case
+        self.shape = tuple(case.shape)
+        self.nc = int(np.prod(self.shape))
+        self.nf = nfaces(self.shape)
+        L = lib()
+        g, p, bcs, c = make_structs(case, precision, p_tol, mg, max_courant, bounds_tol)
+        h = C.c_void_p()
+        self._check(L.dbs_create(C.byref(g), C.byref(p), bcs, C.byref(c), C.byref(h)), None)
+        self.h = h
+        phi = np.ascontiguousarray(case.phi, dtype=np.float64).reshape(self.nc)
+        kinv = np.ascontiguousarray(case.kinv, dtype=np.float64).reshape(self.nc)
+        self._check(L.dbs_set_static(h, _ptr(phi), _ptr(kinv)))
+        if state is None:
+            F = None
+            if getattr(case, "F", None) is not None:
+                F = np.concatenate([np.asarray(f, dtype=np.float64).ravel() for f in case.F])
+            state = {"alpha": case.alpha, "U": case.U, "p_rgh": case.p_rgh, "F": F}
+        self.set_state(state)
+
+    def set_state(self, st):
+        a = np.ascontiguousarray(st["alpha"], dtype=np.float64).reshape(self.nc)
+        U = np.ascontiguousarray(st["U"], dtype=np.float64).reshape(3 * self.nc)
+        pr = np.ascontiguousarray(st["p_rgh"], dtype=np.float64).reshape(self.nc)
+        F = st.get("F")
+        if F is not None:
+            if isinstance(F, (tuple, list)):
+                F = np.concatenate([np.asarray(f, dtype=np.float64).ravel() for f in F])
+            F = np.ascontiguousarray(F, dtype=np.float64)
+            assert F.size == self.nf
+        self._check(lib().dbs_set_state(self.h, _ptr(a), _ptr(U), _ptr(pr), _ptr(F)))
+
+    def state(self):
+        a = np.zeros(self.nc)
+        U = np.zeros(3 * self.nc)
+        pr = np.zeros(self.nc)
+        p = np.zeros(self.nc)
+        F = np.zeros(self.nf)
+        self._check(lib().dbs_get_state(self.h, _ptr(a), _ptr(U), _ptr(pr), _ptr(p), _ptr(F)))
+        nx, ny, nz = self.shape
+        n1 = (nx + 1) * ny * nz
+        n2 = n1 + nx * (ny + 1) * nz
+        return {"alpha": a, "U": U.reshape(3, self.nc), "p_rgh": pr, "p": p,
+                "F": (F[:n1], F[n1:n2], F[n2:])}
+
+    def set_state_dev(self, alpha, U, p_rgh, F=None, stream=None):
+        """Device buffers given as raw pointers (e.g. torch ``data_ptr()``)."""
+        self._check(lib().dbs_set_state_dev(self.h, alpha, U, p_rgh, F, stream))
+
+    def get_state_dev(self, alpha=None, U=None, p_rgh=None, p=None, F=None, stream=None):
+        self._check(lib().dbs_get_state_dev(self.h, alpha, U, p_rgh, p, F, stream))
+
+    def stats(self):
+        s = Stats()
+        self._check(lib().dbs_get_stats(self.h, C.byref(s)))
+        return self._stats_dict(s, self.case.n_corr)
+
+    def pressure_solve(self, rAU, b, x0=None):
+        rAU = np.ascontiguousarray(rAU, dtype=np.float64).ravel()
+        b = np.ascontiguousarray(b, dtype=np.float64).ravel()
+        x = np.zeros(self.nc) if x0 is None else np.ascontiguousarray(x0, dtype=np.float64).copy()
+        it = C.c_int()
+        rr = C.c_double()
+        self._check(lib().dbs_debug_pressure_solve(self.h, _ptr(rAU), _ptr(b), _ptr(x),
+                                                   C.byref(it), C.byref(rr)))
+        return x, it.value, rr.value
+
+    def trace_step(self):
+        nc, nf = self.nc, self.nf
+        out = {"A": np.zeros(nf), "rAU": np.zeros(nc), "Shat": np.zeros(3 * nc),
+               "Ustar": np.zeros(3 * nc), "HbyA": np.zeros(3 * nc), "phiHbyA": np.zeros(nf),
+               "b": np.zeros(nc)}
+        self._check(lib().dbs_debug_step_trace(
+            self.h, *[_ptr(out[k]) for k in ("A", "rAU", "Shat", "Ustar", "HbyA", "phiHbyA",
+                                              "b")]))
+        return out
+
+
+
+class BatchSolver(_Handle):
+    """Many independent samples advanced together (one launch per stage).
+
+    The cases share fluids, closures, gravity, dt and solver controls; each
+    has its own mesh, boundary values, porosity, permeability and state."""
+
+    def __init__(self, cases, precision=None, p_tol=None, mg=None, max_courant=0.0,
+                 bounds_tol=0.0):
+        cases = list(cases)
+        assert cases, "empty batch"
+        self.cases = cases
+        n = len(cases)
+        grids = (Grid * n)()
+        bcs = (BC * (6 * n))()
+        phys = ctl = None
+        for i, cs in enumerate(cases):
+            g, p, b6, c = make_structs(cs, precision, p_tol, mg, max_courant, bounds_tol)
+            grids[i] = g
+            for b in range(6):
+                bcs[6 * i + b] = b6[b]
+            if phys is None:
+                phys, ctl = p, c
+        h = C.c_void_p()
+        self._check(lib().dbs_batch_create(n, grids, C.byref(phys), bcs, C.byref(ctl),
+                                           C.byref(h)), None)
+        self.h = h
+        self.n = n
+        self.shapes = [tuple(cs.shape) for cs in cases]
+        for i, cs in enumerate(cases):
+            nc = int(np.prod(cs.shape))
+            phi = np.ascontiguousarray(cs.phi, dtype=np.float64).reshape(nc)
+            kinv = np.ascontiguousarray(cs.kinv, dtype=np.float64).reshape(nc)
+            self._check(lib().dbs_batch_set_static(h, i, _ptr(phi), _ptr(kinv)))
+            F = getattr(cs, "F", None)
+            self.set_state(i, {"alpha": cs.alpha, "U": cs.U, "p_rgh": cs.p_rgh,
+                               "F": None if F is None else _flat_faces(F)})
+
+    def set_state(self, i, st):
+        nc = int(np.prod(self.shapes[i]))
+        a = np.ascontiguousarray(st["alpha"], dtype=np.float64).reshape(nc)
+        U = np.ascontiguousarray(st["U"], dtype=np.float64).reshape(3 * nc)
+        pr = np.ascontiguousarray(st["p_rgh"], dtype=np.float64).reshape(nc)
+        F = st.get("F")
+        if F is not None:
+            F = _flat_faces(F)
+            assert F.size == nfaces(self.shapes[i])
+        self._check(lib().dbs_batch_set_state(self.h, int(i), _ptr(a), _ptr(U), _ptr(pr),
+                                              _ptr(F)))
+
+    def state(self, i):
+        shape = self.shapes[i]
+        nc = int(np.prod(shape))
+        a, U, pr, p = np.zeros(nc), np.zeros(3 * nc), np.zeros(nc), np.zeros(nc)
+        F = np.zeros(nfaces(shape))
+        self._check(lib().dbs_batch_get_state(self.h, int(i), _ptr(a), _ptr(U), _ptr(pr),
+                                              _ptr(p), _ptr(F)))
+        return {"alpha": a, "U": U.reshape(3, nc), "p_rgh": pr, "p": p,
+                "F": _split_faces(F, shape)}
+
+    def stats(self, i):
+        s = Stats()
+        self._check(lib().dbs_batch_get_stats(self.h, int(i), C.byref(s)))
+        return self._stats_dict(s, self.cases[0].n_corr)

@@ -1,0 +1,152 @@
+"""GPU tests of the batched form: many samples of uneven sizes advanced with
+one launch per stage, graph-captured steps, the autotuner, and the mixed
+precision errors against the FP64 oracle.  All GPU work goes through the C
+ABI (libdbs.so)."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2003_08374_amd import workloads as W
+from parity_util import compare_states, max_abs, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    torch.cuda.set_device(0)
+    O.build(force=False)
+
+
+def _dbs():
+    from paper_2003_08374_amd import dbs
+    return dbs
+
+
+def _mixed_batch(p_tol=1e-13):
+    """Ragged cubes and boxes, one closed sample (walls only), one sample
+    with a slab fracture: every per-sample branch of the batched solver."""
+    cs = W.batch_cases(n_samples=3, seed=11, lo=9, hi=21, p_tol=p_tol)
+    cs.append(W.fractured_3d(shape=(23, 10, 13), fractures="slab", steps=3).replace(
+        p_tol=p_tol, name="box_23x10x13"))
+    closed = W.fractured_3d(shape=(12, 14, 9), fractures=None, seed_k=77, seed_phi=78,
+                            steps=3).replace(p_tol=p_tol, name="closed_12x14x9")
+    alpha = np.zeros(closed.phi.shape)
+    alpha[:, 7:, :] = 1.0  # water over oil in a closed box
+    closed = closed.replace(bc=[W.wall()] * 6, alpha=alpha)
+    cs.append(closed)
+    return cs
+
+
+def test_batch_samples_match_oracle():
+    """Each sample of a batch equals the FP64 oracle run on it alone."""
+    dbs = _dbs()
+    cases = _mixed_batch()
+    nsteps = 3
+    with dbs.BatchSolver(cases) as B:
+        B.step(nsteps)
+        outs = [B.state(i) for i in range(len(cases))]
+        stats = [B.stats(i) for i in range(len(cases))]
+    for cs, out, st in zip(cases, outs, stats):
+        ref, _ = O.step(cs.replace(p_tol=1e-14, p_maxit=200000), O.initial_state(cs), nsteps)
+        compare_states(out, ref, label=f"batch:{cs.name}")
+        assert st["steps"] == nsteps
+        assert max(st["p_relres"]) <= 1e-13
+
+
+def test_batch_equals_single_runs():
+    """A sample's result does not depend on the rest of the batch."""
+    dbs = _dbs()
+    cases = _mixed_batch()
+    with dbs.BatchSolver(cases) as B:
+        B.step(2)
+        outs = [B.state(i) for i in range(len(cases))]
+        its = [B.stats(i)["p_iters"] for i in range(len(cases))]
+    for cs, out, it in zip(cases, outs, its):
+        with dbs.Solver(cs) as s:
+            s.step(2)
+            ref = s.state()
+            assert s.stats()["p_iters"] == it, cs.name
+        compare_states(out, ref, tol_l2=1e-12, tol_alpha=1e-13, label=f"single:{cs.name}")
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_graph_replay_equals_eager(precision):
+    """Graph mode replays captured steps; every replay equals the eager step."""
+    dbs = _dbs()
+    cases = _mixed_batch(p_tol=1e-10)
+    with dbs.BatchSolver(cases, precision=precision) as E, \
+            dbs.BatchSolver(cases, precision=precision) as G:
+        G.set_graph(True)
+        for step in range(6):
+            E.step(1)
+            G.step(1)
+            for i, cs in enumerate(cases):
+                a, b = E.state(i), G.state(i)
+                assert max_abs(a["alpha"], b["alpha"]) <= 1e-14, (step, cs.name)
+                assert rel_l2(a["p_rgh"], b["p_rgh"]) <= 1e-13, (step, cs.name)
+                assert rel_l2(a["U"], b["U"]) <= 1e-13, (step, cs.name)
+                assert E.stats(i)["p_iters"] == G.stats(i)["p_iters"], (step, cs.name)
+
+
+def test_graph_budget_too_small_is_recovered():
+    """A captured step whose PCG budget is too small is redone eagerly."""
+    dbs = _dbs()
+    cases = _mixed_batch(p_tol=1e-11)
+    with dbs.BatchSolver(cases) as E, dbs.BatchSolver(cases) as G:
+        G.set_graph(2)  # a budget of one iteration per corrector
+        for step in range(3):
+            E.step(1)
+            G.step(1)
+            for i in range(len(cases)):
+                a, b = E.state(i), G.state(i)
+                assert rel_l2(a["p_rgh"], b["p_rgh"]) <= 1e-13
+                assert max_abs(a["alpha"], b["alpha"]) <= 1e-14
+                assert max(G.stats(i)["p_relres"]) <= 1e-11
+
+
+def test_autotune_keeps_state_and_converges():
+    dbs = _dbs()
+    case = W.fractured_3d(n=24, fractures="slab", steps=4).replace(p_tol=1e-13)
+    with dbs.Solver(case) as s:
+        s.step(1)
+        before = s.state()
+        knobs = s.autotune()
+        after = s.state()
+        for k in ("alpha", "p_rgh", "U"):
+            assert np.array_equal(before[k], after[k]), k
+        assert knobs["sweeps"] in (1, 2, 3) and knobs["bottom_shift"] in (0, 1)
+        assert knobs["kz"] in (0, 2, 4, 8, 16) and knobs["ms"] > 0
+        s.step(2)
+        out = s.state()
+        assert max(s.stats()["p_relres"]) <= 1e-13
+    ref, _ = O.step(case.replace(p_tol=1e-14, p_maxit=200000), O.initial_state(case), 3)
+    compare_states(out, ref, label=f"autotuned {knobs}")
+
+
+def test_mixed_precision_errors_per_field():
+    """Mixed form (FP32 V-cycle inside flexible FP64 CG, relative residual
+    1e-8) against the FP64 oracle at 1e-14: the error is stated per field."""
+    dbs = _dbs()
+    case = W.fractured_3d(shape=(32, 28, 24), fractures="planes", n_frac=2, steps=4)
+    nsteps = 4
+    with dbs.Solver(case.replace(p_tol=1e-8), precision="mixed") as s:
+        s.step(nsteps)
+        out = s.state()
+        st = s.stats()
+    ref, _ = O.step(case.replace(p_tol=1e-14, p_maxit=200000), O.initial_state(case), nsteps)
+    e = {"alpha_maxabs": max_abs(out["alpha"], ref["alpha"]),
+         "U_relL2": rel_l2(out["U"], ref["U"]),
+         "p_rgh_relL2": rel_l2(out["p_rgh"], ref["p_rgh"]),
+         "F_relL2": rel_l2(np.concatenate(out["F"]), np.concatenate(ref["F"]))}
+    print("mixed vs oracle", e, st["p_iters"], st["p_relres"], flush=True)
+    assert max(st["p_relres"]) <= 1e-8
+    # a 1e-8 residual leaves errors of that order times the conditioning of
+    # the pressure operator; alpha only feels them through the fluxes
+    assert e["p_rgh_relL2"] <= 1e-7 and e["U_relL2"] <= 1e-7 and e["F_relL2"] <= 1e-7
+    assert e["alpha_maxabs"] <= 1e-8
