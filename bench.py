@@ -29,22 +29,27 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, AMD public figure
 
 
-def alg_bytes_per_cell(cls: str, rsize: int) -> float:
+def alg_bytes_per_cell(cls: str, rsize: int, fused: bool = False) -> float:
     """Algorithmic bytes per fine cell and launch of a kernel class.
 
-    rsize = 8 (FP64 V-cycle) or 4 (FP32 V-cycle).  Red-black half sweeps touch
-    every coefficient (rAU) once, half of b, the other colour of x and write
-    their own colour of x.
+    rsize = 8 (FP64 V-cycle) or 4 (FP32 V-cycle).  fused: the fine-level
+    smoother launches are full red-black sweeps; else half sweeps, which
+    read all of rAU, b on their own colour and x on the other colour, and
+    write their own colour.
     """
     s = rsize
+    if not fused and cls in ("smooth_fine", "smooth_fine_zero", "prolong_fine"):
+        return {"smooth_fine": 2.5 * s,
+                "smooth_fine_zero": s + 0.5 * s + s,
+                "prolong_fine": s + s / 8.0 + s + 0.5 * s + s}[cls]
     return {
-        # rAU (all), b (own colour), x (other colour) read; own colour written
-        "smooth_fine": s + 0.5 * s + 0.5 * s + 0.5 * s,
-        # zero initial guess: rAU and own-colour b read, both colours written
-        "smooth_fine_zero": s + 0.5 * s + s,
+        # fused red-black sweep (both colours): x, b, rAU read once, x written
+        "smooth_fine": 4 * s,
+        # zero initial guess: b and rAU read, x written
+        "smooth_fine_zero": 3 * s,
         # prolongation fused in the first up-sweep: x and the coarse
-        # correction read, rAU and own-colour b read, both colours written
-        "prolong_fine": s + s / 8.0 + s + 0.5 * s + s,
+        # correction (one value per 8 cells) read as well
+        "prolong_fine": 4 * s + s / 8.0,
         # red residuals only: x and rAU read, red b read, coarse b written
         "restrict_fine": 2 * s + 0.5 * s + s / 8.0,
         "spmv": 24.0,                  # rAU, p read; q written (FP64)
@@ -79,11 +84,32 @@ def measured_traffic(kernel, precision, n):
     return None, None
 
 
-def time_solver(case, precision, steps, warmup, prof_class=None, profile_all=False):
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def time_solver(case, precision, steps, warmup, prof_class=None, profile_all=False,
+                graph=False, tune=False, knobs=None):
+    """Time `steps` steps of one case (or a list of cases: a batch) after
+    `warmup` untimed ones; optionally profile every kernel class over one
+    extra untimed step, and time one class with HIP events over the timed
+    region."""
     import torch
     from paper_2003_08374_amd import dbs
 
-    s = dbs.Solver(case, precision=precision)
+    batch = isinstance(case, (list, tuple))
+    log(f"{'batch of %d' % len(case) if batch else case.name}: {precision}"
+        f"{' graph' if graph else ''}{' tuned' if tune else ''}")
+    s = dbs.BatchSolver(case, precision=precision) if batch else dbs.Solver(case,
+                                                                              precision=precision)
+    tuning = None
+    if knobs:
+        s.set_tuning(**knobs)
+    if tune:
+        s.step(1)
+        tuning = s.autotune()
+    if graph:
+        s.set_graph(True)
     s.step(warmup)
     all_times = None
     if profile_all:
@@ -94,23 +120,30 @@ def time_solver(case, precision, steps, warmup, prof_class=None, profile_all=Fal
         s.set_profiling(0)
     dom = prof_class
     if dom is None and all_times:
-        dom = max(all_times.items(), key=lambda kv: kv[1][1])[0]
-    if dom:
+        # the most expensive class that has an algorithmic byte model
+        modelled = {k: v for k, v in all_times.items() if alg_bytes_per_cell(k, 4) > 0}
+        dom = max(modelled.items(), key=lambda kv: kv[1][1])[0] if modelled else None
+    if dom and not graph:
         s.set_profiling(1 << dbs.Solver.kernel_class(dom))
     s.reset_profiling()
     its = []
+    stats = (lambda: s.stats(0)) if batch else s.stats
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
         s.step(1)
-        its.append(s.stats()["p_iters"])
+        its.append(stats()["p_iters"])
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    log(f"  {steps} steps in {t1 - t0:.3f} s")
     kt = s.kernel_times()
-    st = s.stats()
+    st = stats()
+    if batch:
+        its_all = [s.stats(i)["p_iters"] for i in range(len(case))]
+        st["p_iters_max"] = [max(v[c] for v in its_all) for c in range(len(its_all[0]))]
     s.close()
     return {"sec": t1 - t0, "p_iters": its, "kernel": dom, "ktimes": kt, "all": all_times,
-            "stats": st}
+            "stats": st, "tuning": tuning}
 
 
 def cpu_baseline(n=64, steps=2):
@@ -135,6 +168,32 @@ def cpu_baseline(n=64, steps=2):
     }
 
 
+def batch_leg(args):
+    """The 512-sample batch (edges U{32..96}, no fracture, k seed 1000+s, phi
+    seed 2000+s): mixed precision in graph mode after autotuning, and plain
+    FP64 eagerly, both to a relative residual of 1e-8."""
+    from paper_2003_08374_amd import workloads as W
+
+    log(f"generating {args.batch_samples} samples")
+    cases = W.batch_cases(n_samples=args.batch_samples, seed=6, lo=32, hi=96, p_tol=args.p_tol)
+    cases = [c.replace(p_maxit=500) for c in cases]
+    cells = sum(c.ncells for c in cases)
+    out = {"workload": f"batch{len(cases)}_edges32to96", "samples": len(cases), "cells": cells,
+           "p_tol": args.p_tol}
+    rm = time_solver(cases, "mixed", args.steps, args.warmup, graph=True, tune=True)
+    out["mixed_graph_tuned"] = {"value": cells / (rm["sec"] / args.steps),
+                                "ms_per_step": rm["sec"] / args.steps * 1e3,
+                                "tuning": rm["tuning"],
+                                "p_iters_max_last": rm["stats"].get("p_iters_max")}
+    r64 = time_solver(cases, "fp64", args.steps, args.warmup)
+    out["fp64_eager"] = {"value": cells / (r64["sec"] / args.steps),
+                         "ms_per_step": r64["sec"] / args.steps * 1e3,
+                         "p_iters_max_last": r64["stats"].get("p_iters_max")}
+    out["speedup_mixed_batched_vs_fp64"] = (out["mixed_graph_tuned"]["value"] /
+                                            out["fp64_eager"]["value"])
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -146,6 +205,11 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 leg")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--kernel", default=None, help="kernel class for the roofline")
+    ap.add_argument("--no-graph", action="store_true", help="skip the graph-mode leg")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched leg")
+    ap.add_argument("--batch-samples", type=int, default=512)
+    ap.add_argument("--fused", type=int, default=1,
+                    help="1: fused full sweeps on the fine level (else half sweeps)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -177,14 +241,15 @@ def main():
     case = case.replace(p_tol=args.p_tol, p_maxit=500)
     cells = case.ncells
 
+    knobs = {"kz": 0, "sweeps": 2, "bottom_shift": 0, "fused": args.fused}
     main_run = time_solver(case, args.precision, args.steps, args.warmup,
-                           prof_class=args.kernel, profile_all=args.kernel is None)
+                           prof_class=args.kernel, profile_all=args.kernel is None, knobs=knobs)
     ms = main_run["sec"] / args.steps * 1e3
     value = cells / (main_run["sec"] / args.steps)
     rsize = 4 if args.precision == "mixed" else 8
     kname = main_run["kernel"]
     launches, kms = main_run["ktimes"].get(kname, (0, 0.0))
-    per_cell = alg_bytes_per_cell(kname, rsize)
+    per_cell = alg_bytes_per_cell(kname, rsize, bool(args.fused))
     roof = None
     if launches and per_cell:
         avg_s = kms / launches * 1e-3
@@ -205,9 +270,15 @@ def main():
         fp64 = {"value": cells / (r64["sec"] / args.steps),
                 "ms_per_step": r64["sec"] / args.steps * 1e3,
                 "p_iters_last": r64["p_iters"][-1]}
+    graph = None
+    if not args.no_graph:
+        rg = time_solver(case, args.precision, args.steps, args.warmup, graph=True)
+        graph = {"value": cells / (rg["sec"] / args.steps),
+                 "ms_per_step": rg["sec"] / args.steps * 1e3,
+                 "p_iters_last": rg["p_iters"][-1]}
+    batched = None if args.no_batch else batch_leg(args)
     cpu = None if args.no_cpu else cpu_baseline()
 
-    # whole-step bytes from the profile of all kernel classes (ideal model)
     line = {
         "metric": "cell-updates/s per PISO step at 256^3 (FP64 vs mixed/batched); % HBM roofline",
         "value": value,
@@ -228,6 +299,8 @@ def main():
         "cpu_baseline": cpu,
         "fp64_same_tol": fp64,
         "speedup_mixed_vs_fp64": (value / fp64["value"]) if fp64 else None,
+        "graph_mode": graph,
+        "batched": batched,
     }
     if main_run["all"]:
         line["kernel_ms_one_step"] = {k: round(v[1], 3) for k, v in sorted(

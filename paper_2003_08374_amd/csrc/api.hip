@@ -398,7 +398,7 @@ static int set_static_impl(Handle *h, int i, const double *phi, const double *ki
   }
   int rc = hip_check(h, hipMemcpyAsync(h->phi + G.c0, phi, nc * 8, hipMemcpyHostToDevice, h->stream), "copy phi");
   if (!rc) rc = hip_check(h, hipMemcpyAsync(h->kinv + G.c0, kinv, nc * 8, hipMemcpyHostToDevice, h->stream), "copy kinv");
-  if (!rc) update_closures(h);
+  if (!rc) update_closures(h, i);
   if (!rc) rc = hip_check(h, hipStreamSynchronize(h->stream), "set_static");
   return rc;
 }
@@ -417,7 +417,7 @@ static int set_state_impl(Handle *h, int i, const double *alpha, const double *U
   if (!rc) rc = hip_check(h, hipStreamSynchronize(s), "set_state");
   if (rc) return rc;
   if (!F) init_flux(h, i);
-  update_closures(h);
+  update_closures(h, i);
   return hip_check(h, hipStreamSynchronize(h->stream), "set_state");
 }
 
@@ -799,7 +799,8 @@ int dbs_set_graph(dbs_handle *H, int on) {
   return DBS_OK;
 }
 
-int dbs_autotune(dbs_handle *H, int *kz_out, int *sweeps_out, int *shift_out, double *ms_out) {
+int dbs_autotune(dbs_handle *H, int *kz_out, int *sweeps_out, int *shift_out, int *fused_out,
+                 double *ms_out) {
   if (!H) return DBS_EINVAL;
   Handle *h = &H->h;
   int rc = DBS_OK;
@@ -818,14 +819,15 @@ int dbs_autotune(dbs_handle *H, int *kz_out, int *sweeps_out, int *shift_out, do
   corrector_assemble(h);
   copy_n(h, h->prgh, x0, (size_t)h->NC);
   struct Cand {
-    int kz, sweeps, shift;
+    int kz, sweeps, shift, fused;
   };
-  Cand best{h->kz_fine, h->mg_pre, h->bottom_shift};
+  Cand best{h->kz_fine, h->mg_pre, h->bottom_shift, h->fused_sweep};
   double best_ms = 1e300;
   auto trial = [&](const Cand &c) {
     h->kz_fine = c.kz;
     h->mg_pre = h->mg_post = c.sweeps;
     h->bottom_shift = c.shift;
+    h->fused_sweep = c.fused;
     if (pressure_retune(h)) return;
     int ok = 0;
     time_solve(h, x0, &ok);  // first run: caches and clocks
@@ -836,12 +838,14 @@ int dbs_autotune(dbs_handle *H, int *kz_out, int *sweeps_out, int *shift_out, do
     }
   };
   for (int sw = 1; sw <= 3; sw++)
-    for (int shf = 0; shf <= 1; shf++) trial(Cand{0, sw, shf});
+    for (int shf = 0; shf <= 1; shf++) trial(Cand{0, sw, shf, 1});
+  trial(Cand{0, best.sweeps, best.shift, 0});
   const Cand mid = best;
-  for (int kz : {2, 4, 8, 16}) trial(Cand{kz, mid.sweeps, mid.shift});
+  for (int kz : {2, 4, 8, 16}) trial(Cand{kz, mid.sweeps, mid.shift, mid.fused});
   h->kz_fine = best.kz;
   h->mg_pre = h->mg_post = best.sweeps;
   h->bottom_shift = best.shift;
+  h->fused_sweep = best.fused;
   rc = pressure_retune(h);
   // restore the state as it was before tuning
   swap_roles(h);
@@ -853,11 +857,12 @@ int dbs_autotune(dbs_handle *H, int *kz_out, int *sweeps_out, int *shift_out, do
   if (kz_out) *kz_out = best.kz;
   if (sweeps_out) *sweeps_out = best.sweeps;
   if (shift_out) *shift_out = best.shift;
+  if (fused_out) *fused_out = best.fused;
   if (ms_out) *ms_out = best_ms;
   return rc;
 }
 
-int dbs_set_tuning(dbs_handle *H, int kz, int sweeps, int shift) {
+int dbs_set_tuning(dbs_handle *H, int kz, int sweeps, int shift, int fused) {
   if (!H || kz < 0 || kz > 64 || sweeps < 1 || sweeps > 8 || shift < 0 || shift > 4)
     return DBS_EINVAL;
   Handle *h = &H->h;
@@ -865,6 +870,7 @@ int dbs_set_tuning(dbs_handle *H, int kz, int sweeps, int shift) {
   h->kz_fine = kz;
   h->mg_pre = h->mg_post = sweeps;
   h->bottom_shift = shift;
+  h->fused_sweep = fused ? 1 : 0;
   reset_graphs(h);
   return pressure_retune(h);
 }

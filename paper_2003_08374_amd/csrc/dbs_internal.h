@@ -143,8 +143,9 @@ struct Handle {
   void *btab = nullptr;      // device table of bottom descriptors
   int nbt = 0;               // samples with a bottom (>= 2 levels)
   int mg_pre = 2, mg_post = 2, coarse_sweeps = 16;
-  // tuning knobs (autotuner): fine tile depth (0 = heuristic), bottom shift
-  int kz_fine = 0, bottom_shift = 0;
+  // tuning knobs (autotuner): fine tile depth (0 = heuristic), bottom shift,
+  // fused full sweeps on the fine level (else two half-sweep launches)
+  int kz_fine = 0, bottom_shift = 0, fused_sweep = 1;
 
   std::vector<dbs_stats> st;  // per sample
 
@@ -178,7 +179,7 @@ void prof_collect(Handle *h);
 
 // k_alpha.hip
 void alpha_stage(Handle *h);
-void update_closures(Handle *h);  // pc/ml/mg from the current alpha
+void update_closures(Handle *h, int only = -1);  // pc/ml/mg/cf from the current alpha
 void init_flux(Handle *h, int only = -1);  // F from U (linear interpolation)
 // k_momentum.hip
 void momentum_predictor(Handle *h);

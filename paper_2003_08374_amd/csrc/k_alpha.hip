@@ -241,14 +241,16 @@ __global__ void __launch_bounds__(NTHREADS) k_alpha_update(Segs SG, Phys Ph, con
   }
 }
 
+// only >= 0: that sample alone
 __global__ void __launch_bounds__(NTHREADS) k_closures(Segs SG, Phys Ph,
                                                        const double *__restrict__ alpha,
                                                        const double *__restrict__ kinv,
                                                        double *__restrict__ ml,
                                                        double *__restrict__ mg,
                                                        double *__restrict__ pc,
-                                                       double *__restrict__ cf) {
+                                                       double *__restrict__ cf, int only) {
   FOR_CELLS(SG, G, P) {
+  if (only >= 0 && cell_sg != only) return;
   double l, g, p;
   const double a = alpha[P.c];
   closures(Ph, a, l, g, p);
@@ -312,10 +314,10 @@ void alpha_stage(Handle *h) {
   h->alpha_old = t;
 }
 
-void update_closures(Handle *h) {
+void update_closures(Handle *h, int only) {
   dim3 blk(BX, BY);
   DBS_LAUNCH(h, KC_MISC, k_closures, h->cgrid, blk, h->seg, h->P, (const double *)h->alpha,
-             (const double *)h->kinv, h->ml, h->mg, h->pc, h->cf);
+             (const double *)h->kinv, h->ml, h->mg, h->pc, h->cf, only);
 }
 
 void init_flux(Handle *h, int only) {

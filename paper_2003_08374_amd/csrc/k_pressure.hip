@@ -359,8 +359,9 @@ struct FinArgs {
 
 // one block per sample: scal[slot] = sum of the sample's partials (and slot2
 // from the second array), then the CG scalar and flag updates of `op`
-__global__ void __launch_bounds__(FLAT_T) k_finalize(FinArgs A, double *__restrict__ scal) {
-  __shared__ double lds[FLAT_T / 64];
+constexpr int FIN_T = 1024;
+__global__ void __launch_bounds__(FIN_T) k_finalize(FinArgs A, double *__restrict__ scal) {
+  __shared__ double lds[FIN_T / 64];
   const int s = blockIdx.x;
   if ((A.mask && !A.mask[s]) || (A.closed_only && !A.rng[s].closed)) return;
   const int t = threadIdx.x;
@@ -371,15 +372,19 @@ __global__ void __launch_bounds__(FLAT_T) k_finalize(FinArgs A, double *__restri
       const double *P = A.partials + (hh ? A.off2 : 0);
       double v0 = 0.0, v1 = 0.0;
       int i = b0 + t;
-      for (; i + FLAT_T < b1; i += 2 * FLAT_T) {
+      for (; i + FIN_T < b1; i += 2 * FIN_T) {
         v0 += P[i];
-        v1 += P[i + FLAT_T];
+        v1 += P[i + FIN_T];
       }
       if (i < b1) v0 += P[i];
       const double v = wave_sum(v0 + v1);
       if ((t & 63) == 0) lds[t >> 6] = v;
       __syncthreads();
-      if (t == 0) S[hh ? A.slot2 : A.slot] = (lds[0] + lds[1]) + (lds[2] + lds[3]);
+      if (t == 0) {
+        double sum = 0.0;
+        for (int w = 0; w < FIN_T / 64; w++) sum += lds[w];
+        S[hh ? A.slot2 : A.slot] = sum;
+      }
       __syncthreads();
     }
   }
@@ -1020,6 +1025,281 @@ __global__ void __launch_bounds__(NT2) k_smooth25(OpB<R> LB, SH S, const B *__re
   }
 }
 
+// ------------------------------------------------ fused full sweep (fine level)
+//
+// One red-black Gauss-Seidel sweep (colour A then colour B) in a single pass
+// over memory.  An A cell's six neighbours are all B cells, so its update
+// needs only old values; a B cell's update needs the new A values around
+// it.  A block owns a 128 x 8 tile and walks its planes as a wavefront: at
+// step k it relaxes the A cells of plane k on the tile and on a one-cell
+// ring around it (the ring values are recomputed, bit for bit, by the
+// blocks owning them), then the B cells of plane k-1 on the tile, and writes
+// both colours of plane k-1.  x is read from one buffer and written to
+// another, so neighbours' old values are never overwritten under a block.
+// Each thread owns an x-pair: it relaxes the A cell of its pair in every
+// plane (138 threads also take one ring cell) and the B cell one plane
+// behind, keeping its own column's new A values, rAU and b in registers.
+// LDS holds three planes of old x and rAU (rows widened to whole 16-byte
+// vectors, two rows of ring above and below) and two planes of new A
+// values, 50 KB in FP32.  Planes are fetched one step ahead with 16-byte
+// loads.  Per sweep each of x, b and rAU is read once and x written once,
+// where two half sweeps read and write every cache line twice.
+
+constexpr int FW = 128;              // tile width (cells), one x-pair per thread
+constexpr int FY2 = TY2 + 4;         // rows of a plane with a 2-row ring
+constexpr int FX1 = FW + 2;          // row stride of planes with a 1-cell ring
+constexpr int FY1 = TY2 + 2;
+constexpr int NX1 = FX1 * FY1;
+constexpr int NRING = FX1 + TY2;     // A cells on the 1-ring of a plane
+#define I1(lx, ly) (((ly) + 1) * FX1 + (lx) + 1)
+
+enum { SW_NORMAL = 0, SW_ZERO = 1, SW_PROLONG = 2 };
+
+template <typename R> struct Vec16;
+template <> struct Vec16<float> { using T = float4; using T2 = float2; };
+template <> struct Vec16<double> { using T = double2; using T2 = double2; };
+
+// plane geometry of the fused sweep for element type R: the x-ring is one
+// 16-byte vector wide (at least 2 cells) so rows start on a vector boundary
+template <typename R>
+struct SwPlane {
+  static constexpr int VEC = 16 / sizeof(R);
+  static constexpr int RX = VEC < 2 ? 2 : VEC;
+  static constexpr int FXR = FW + 2 * RX;        // row stride
+  static constexpr int NX = FXR * FY2;           // elements per plane
+  static constexpr int NV = NX / VEC;            // vectors per plane
+  static constexpr int MV = (NV + NT2 - 1) / NT2;
+  __device__ static constexpr int at(int lx, int ly) { return (ly + 2) * FXR + lx + RX; }
+};
+
+// row of the fine operator at (i,j,k) from the seven rAU values around it
+template <typename R>
+__device__ __forceinline__ void coef7(const Op<R> &L, int i, int j, int k, R rc, R rxm, R rxp,
+                                      R rym, R ryp, R rzm, R rzp, R T[6], R &D) {
+  const R h = (R)0.5;
+  T[0] = i > 0 ? h * (rc + rxm) * L.c[0] : (R)0;
+  T[1] = i + 1 < L.n0 ? h * (rc + rxp) * L.c[0] : (R)0;
+  T[2] = j > 0 ? h * (rc + rym) * L.c[1] : (R)0;
+  T[3] = j + 1 < L.n1 ? h * (rc + ryp) * L.c[1] : (R)0;
+  T[4] = k > 0 ? h * (rc + rzm) * L.c[2] : (R)0;
+  T[5] = k + 1 < L.n2 ? h * (rc + rzp) * L.c[2] : (R)0;
+  const R db = (i == 0 ? L.ob[0] : (R)0) + (i + 1 == L.n0 ? L.ob[1] : (R)0) +
+               (j == 0 ? L.ob[2] : (R)0) + (j + 1 == L.n1 ? L.ob[3] : (R)0) +
+               (k == 0 ? L.ob[4] : (R)0) + (k + 1 == L.n2 ? L.ob[5] : (R)0);
+  D = T[0] + T[1] + T[2] + T[3] + T[4] + T[5] + rc * db;
+}
+
+// position (lx, ly) of ring A cell r (0 <= r < NRING) of plane k: rows above
+// and below the tile (65 each), then the columns left and right (4 each)
+__device__ __forceinline__ void ring_cell(int r, int x0, int y0, int k, int colA, int &lx,
+                                          int &ly) {
+  if (r < 2 * (FX1 / 2)) {
+    ly = r < FX1 / 2 ? -1 : TY2;
+    const int q = r < FX1 / 2 ? r : r - FX1 / 2;
+    lx = 2 * q - 1 + ((colA - (x0 - 1 + y0 + ly + k)) & 1);
+  } else {
+    const int q = r - 2 * (FX1 / 2);
+    lx = q < TY2 / 2 ? -1 : FW;
+    const int qq = q < TY2 / 2 ? q : q - TY2 / 2;
+    ly = 2 * qq + ((colA - (x0 + lx + y0 + k)) & 1);
+  }
+}
+
+// MODE SW_ZERO: the iterate starts at zero (xin unused).  SW_PROLONG: the
+// iterate is xin plus the coarse correction of each cell's parent (when the
+// sample has a coarse level).  colA: colour relaxed first.  xout != xin.
+template <typename R, typename B, int MODE>
+__global__ void __launch_bounds__(NT2) k_sweep25(OpB<R> LB, SH S, const B *__restrict__ b,
+                                                 const R *__restrict__ xin,
+                                                 R *__restrict__ xout, int colA,
+                                                 const R *__restrict__ xc,
+                                                 const int *__restrict__ mask) {
+  using PL = SwPlane<R>;
+  using VT = typename Vec16<R>::T;
+  constexpr int VEC = PL::VEC, NX = PL::NX, FXR = PL::FXR;
+  __shared__ __align__(16) R sX[3 * NX];   // old x, planes k-1, k, k+1 (slot k mod 3)
+  __shared__ __align__(16) R sR[3 * NX];   // rAU, planes k-1, k, k+1 (slot k mod 3)
+  __shared__ R sA[2 * NX1];                // new A values, planes k-1, k (slot k mod 2)
+  int g, s, lb;
+  if (!locate(S, mask, g, s, lb)) return;
+  const Op<R> L = op_at(LB, s);
+  const LvS &Q = LB.ls[s];
+  b += Q.c0;
+  if (MODE != SW_ZERO) xin += Q.c0;
+  xout += Q.c0;
+  const R *xcs = (MODE == SW_PROLONG && Q.cn0 > 0) ? xc + Q.cc0 : nullptr;
+  const int cn0 = Q.cn0, cn1 = Q.cn1;
+  const int n0 = L.n0, n1 = L.n1, n2 = L.n2;
+  int xb, y0, k0, k1;
+  tile_of(lb, n0, n1, n2, FW, S.kz, xb, y0, k0, k1);
+  const int x0 = xb * FW;
+  const int tx = threadIdx.x, ty = threadIdx.y, t = tx + 64 * ty;
+  const int i0 = x0 + 2 * tx, j = y0 + ty;
+  const R *rA = L.rAU;
+  const bool vec_ok = n0 % VEC == 0;  // rows then start on 16-byte boundaries
+  auto inside = [&](int i, int jj, int k) {
+    return i >= 0 && i < n0 && jj >= 0 && jj < n1 && k >= 0 && k < n2;
+  };
+  auto xs = [](int k) { return (k + 3) % 3; };
+  VT px[PL::MV], pr[PL::MV];
+  // one vector of x (old iterate) and rAU at element e of plane k
+  auto load_planes = [&](int k) {
+#pragma unroll
+    for (int m = 0; m < PL::MV; m++) {
+      const int e = t + m * NT2;
+      R vx[VEC], vr[VEC];
+#pragma unroll
+      for (int u = 0; u < VEC; u++) vx[u] = vr[u] = (R)0;
+      if (e < PL::NV) {
+        const int ia = x0 - PL::RX + (e % (FXR / VEC)) * VEC, jj = y0 + e / (FXR / VEC) - 2;
+        if (jj >= 0 && jj < n1 && k >= 0 && k < n2 && ia + VEC > 0 && ia < n0) {
+          const int c = ia + n0 * (jj + n1 * k);
+          if (vec_ok && ia >= 0) {
+            const VT w = *reinterpret_cast<const VT *>(rA + c);
+            memcpy(vr, &w, sizeof(w));
+            if (MODE != SW_ZERO) {
+              const VT v = *reinterpret_cast<const VT *>(xin + c);
+              memcpy(vx, &v, sizeof(v));
+            }
+          } else {
+#pragma unroll
+            for (int u = 0; u < VEC; u++)
+              if (ia + u >= 0 && ia + u < n0) {
+                vr[u] = rA[c + u];
+                if (MODE != SW_ZERO) vx[u] = xin[c + u];
+              }
+          }
+          if (MODE == SW_PROLONG && xcs) {
+#pragma unroll
+            for (int u = 0; u < VEC; u++)
+              if (ia + u >= 0 && ia + u < n0)
+                vx[u] += xcs[((ia + u) >> 1) + cn0 * ((jj >> 1) + cn1 * (k >> 1))];
+          }
+        }
+      }
+      memcpy(&px[m], vx, sizeof(VT));
+      memcpy(&pr[m], vr, sizeof(VT));
+    }
+  };
+  auto store_planes = [&](int k) {
+#pragma unroll
+    for (int m = 0; m < PL::MV; m++) {
+      const int e = t + m * NT2;
+      if (e < PL::NV) {
+        if (MODE != SW_ZERO) *reinterpret_cast<VT *>(sX + xs(k) * NX + e * VEC) = px[m];
+        *reinterpret_cast<VT *>(sR + xs(k) * NX + e * VEC) = pr[m];
+      }
+    }
+  };
+  // b of the own pair and of the ring cell (if any) of plane k
+  const bool ringer = t < NRING;
+  auto load_b = [&](int k, P2<R> &own, R &ring) {
+    own.v0 = inside(i0, j, k) ? (R)b[i0 + n0 * (j + n1 * k)] : (R)0;
+    own.v1 = inside(i0 + 1, j, k) ? (R)b[i0 + 1 + n0 * (j + n1 * k)] : (R)0;
+    ring = (R)0;
+    if (ringer) {
+      int lx, ly;
+      ring_cell(t, x0, y0, k, colA, lx, ly);
+      if (inside(x0 + lx, y0 + ly, k)) ring = (R)b[x0 + lx + n0 * (y0 + ly + n1 * k)];
+    }
+  };
+  // new A value at (lx, ly) of plane k from LDS neighbours
+  auto relax_a = [&](int lx, int ly, int k, R bb) -> R {
+    const int i = x0 + lx, jj = y0 + ly;
+    if (!inside(i, jj, k)) return (R)0;
+    const R *Xm = sX + xs(k - 1) * NX, *Xc = sX + xs(k) * NX, *Xp = sX + xs(k + 1) * NX;
+    const R *Rm = sR + xs(k - 1) * NX, *Rc = sR + xs(k) * NX, *Rp = sR + xs(k + 1) * NX;
+    const int c2 = PL::at(lx, ly);
+    R T[6], D;
+    coef7(L, i, jj, k, Rc[c2], Rc[c2 - 1], Rc[c2 + 1], Rc[c2 - FXR], Rc[c2 + FXR], Rm[c2],
+          Rp[c2], T, D);
+    if (MODE == SW_ZERO) return D > (R)0 ? bb / D : (R)0;
+    const R off = T[0] * Xc[c2 - 1] + T[1] * Xc[c2 + 1] + T[2] * Xc[c2 - FXR] +
+                  T[3] * Xc[c2 + FXR] + T[4] * Xm[c2] + T[5] * Xp[c2];
+    return D > (R)0 ? (bb + off) / D : (R)0;
+  };
+  // prologue: x and rAU of planes k0-2, k0-1 in LDS, plane k0 in registers;
+  // b of plane k0-1 in registers
+  for (int k = k0 - 2; k <= k0 - 1; k++) {
+    load_planes(k);
+    store_planes(k);
+  }
+  load_planes(k0);
+  P2<R> b_prev = {(R)0, (R)0}, b_cur, b_next = {(R)0, (R)0};
+  R br_cur, br_next = (R)0;
+  load_b(k0 - 1, b_cur, br_cur);
+  P2<R> r_m2 = {(R)0, (R)0}, r_m1 = {(R)0, (R)0}, r_0;
+  R a_m2 = (R)0, a_m1 = (R)0, a_0;
+  for (int k = k0 - 1; k <= k1; k++) {
+    store_planes(k + 1);  // loaded one step earlier; its slot (plane k-2) is free
+    __syncthreads();
+    const bool more = k + 1 <= k1;
+    if (more) {
+      load_planes(k + 2);
+      load_b(k + 1, b_next, br_next);
+    }
+    const int offA = ((j + k) & 1) == colA ? 0 : 1;  // x0 and 2 tx are even
+    // own column: rAU of plane k; rAU around the own B cell of plane k-1
+    const R *Rk = sR + xs(k) * NX;
+    r_0 = P2<R>{Rk[PL::at(2 * tx, ty)], Rk[PL::at(2 * tx + 1, ty)]};
+    const int lxB = 2 * tx + offA;  // B cell of plane k-1 = A position of plane k
+    const R *Rb = sR + xs(k - 1) * NX;
+    const int cb = PL::at(lxB, ty);
+    const R rbc = Rb[cb], rbxm = Rb[cb - 1], rbxp = Rb[cb + 1], rbym = Rb[cb - FXR],
+            rbyp = Rb[cb + FXR];
+    // A cells of plane k: own, then one ring cell
+    R *An = sA + (k & 1) * NX1;
+    a_0 = j < n1 ? relax_a(2 * tx + offA, ty, k, b_cur.get(offA)) : (R)0;
+    An[I1(2 * tx + offA, ty)] = a_0;
+    if (ringer) {
+      int lx, ly;
+      ring_cell(t, x0, y0, k, colA, lx, ly);
+      An[I1(lx, ly)] = relax_a(lx, ly, k, br_cur);
+    }
+    __syncthreads();
+    // B cell of plane k-1; write both colours of plane k-1
+    const int kb = k - 1;
+    if (kb >= k0 && kb < k1 && j < n1) {
+      const int iB = i0 + offA;
+      R vB = (R)0;
+      if (iB < n0) {
+        const R *Ac = sA + (kb & 1) * NX1;
+        const int c1 = I1(lxB, ty);
+        R T[6], D;
+        coef7(L, iB, j, kb, rbc, rbxm, rbxp, rbym, rbyp, r_m2.get(offA), r_0.get(offA), T, D);
+        const R off = T[0] * Ac[c1 - 1] + T[1] * Ac[c1 + 1] + T[2] * Ac[c1 - FX1] +
+                      T[3] * Ac[c1 + FX1] + T[4] * a_m2 + T[5] * a_0;
+        vB = D > (R)0 ? (b_prev.get(offA) + off) / D : (R)0;
+      }
+      // the pair in memory order: offset 0 first
+      const R v0 = offA == 0 ? vB : a_m1, v1 = offA == 0 ? a_m1 : vB;
+      R *row = xout + n0 * (j + n1 * kb);
+      if ((n0 & 1) == 0 && i0 + 1 < n0) {
+        using V2 = typename Vec16<R>::T2;
+        R pv[2] = {v0, v1};
+        V2 w;
+        memcpy(&w, pv, sizeof(R) * 2);
+        if (sizeof(V2) == 2 * sizeof(R)) {
+          *reinterpret_cast<V2 *>(row + i0) = w;
+        } else {
+          row[i0] = v0;
+          row[i0 + 1] = v1;
+        }
+      } else {
+        if (i0 < n0) row[i0] = v0;
+        if (i0 + 1 < n0) row[i0 + 1] = v1;
+      }
+    }
+    r_m2 = r_m1;
+    r_m1 = r_0;
+    a_m2 = a_m1;
+    a_m1 = a_0;
+    b_prev = b_cur;
+    b_cur = b_next;
+    br_cur = br_next;
+  }
+}
+
 // Restriction after a pre-smoothing that ended with a black half sweep: the
 // black residual is zero, so the coarse right-hand side is the sum of the
 // red children's residuals.  Block tiles are 128 x 8 fine cells and walk
@@ -1430,6 +1710,25 @@ static void smooth_fine(Handle *h, const OpB<R> &o, const B *b, const R *xin, R 
                color, xc, m);
 }
 
+// one fused fine-level sweep (colour colA first), xin -> xout
+template <typename R, typename B>
+static void sweep_fine(Handle *h, const OpB<R> &o, const B *b, const R *xin, R *xout, int colA,
+                       int mode, const R *xc) {
+  const Shape &Z = h->lv[0].sm;
+  const dim3 g(Z.nblk);
+  const SH S = sh(h, Z);
+  const int *m = h->act;
+  if (mode == SW_ZERO)
+    DBS_LAUNCH(h, KC_SMOOTH0_ZERO, (k_sweep25<R, B, SW_ZERO>), g, blk2(), o, S, b, xin, xout,
+               colA, xc, m);
+  else if (mode == SW_PROLONG)
+    DBS_LAUNCH(h, KC_PROLONG0, (k_sweep25<R, B, SW_PROLONG>), g, blk2(), o, S, b, xin, xout,
+               colA, xc, m);
+  else
+    DBS_LAUNCH(h, KC_SMOOTH0, (k_sweep25<R, B, SW_NORMAL>), g, blk2(), o, S, b, xin, xout,
+               colA, xc, m);
+}
+
 // z = M r: one V-cycle over the active samples.  b0 is the fine right-hand
 // side (r); z0 and z1 are the two fine correction buffers; returns the one
 // holding the result.
@@ -1438,16 +1737,27 @@ static R *vcycle(Handle *h, const R *rAUr, const B *b0, R *z0, R *z1) {
   const int *act = h->act;
   const int nl = (int)h->lv.size();
   OpB<R> o0 = opb<R>(h, 0, rAUr);
-  // fine level down: red (zero guess), black, ...; red-only restriction
-  for (int s = 0; s < h->mg_pre; s++) {
-    smooth_fine<R, B>(h, o0, b0, z0, z0, 0, s == 0 ? SM_ZERO : SM_NORMAL, (const R *)nullptr);
-    smooth_fine<R, B>(h, o0, b0, z0, z0, 1, SM_NORMAL, (const R *)nullptr);
-  }
   const R *xc1 = nl > 1 ? (const R *)lx<R>(h->lv[1]) : nullptr;
+  // fine level down: red (zero guess), black, ...; red-only restriction.
+  // Fused sweeps alternate between the two buffers; cur holds the iterate.
+  R *cur = z0, *oth = z1;
+  for (int s = 0; s < h->mg_pre; s++) {
+    if (h->fused_sweep) {
+      if (s == 0) {
+        sweep_fine<R, B>(h, o0, b0, (const R *)nullptr, cur, 0, SW_ZERO, (const R *)nullptr);
+      } else {
+        sweep_fine<R, B>(h, o0, b0, cur, oth, 0, SW_NORMAL, (const R *)nullptr);
+        std::swap(cur, oth);
+      }
+    } else {
+      smooth_fine<R, B>(h, o0, b0, z0, z0, 0, s == 0 ? SM_ZERO : SM_NORMAL, (const R *)nullptr);
+      smooth_fine<R, B>(h, o0, b0, z0, z0, 1, SM_NORMAL, (const R *)nullptr);
+    }
+  }
   if (nl > 1 && h->lv[0].rs.nblk) {
     const Shape &Z = h->lv[0].rs;
     DBS_LAUNCH(h, KC_RESTRICT0, (k_restrict25<R, B>), dim3(Z.nblk), blk2(), o0, sh(h, Z), b0,
-               (const R *)z0, lb<R>(h->lv[1]), act);
+               (const R *)cur, lb<R>(h->lv[1]), act);
   }
   for (int l = 1; l < h->maxbottom; l++) {
     OpB<R> o = opb<R>(h, l, rAUr);
@@ -1471,6 +1781,13 @@ static R *vcycle(Handle *h, const R *rAUr, const B *b0, R *z0, R *z1) {
     smooth_level<R, R>(h, l, o, (const R *)lb<R>(L), lx<R>(L), false);
   }
   // fine level up: the prolongation rides on the first (black) half sweep
+  if (h->fused_sweep) {
+    for (int s = 0; s < h->mg_post; s++) {
+      sweep_fine<R, B>(h, o0, b0, cur, oth, 1, s == 0 ? SW_PROLONG : SW_NORMAL, xc1);
+      std::swap(cur, oth);
+    }
+    return cur;
+  }
   for (int s = 0; s < h->mg_post; s++) {
     if (s == 0)
       smooth_fine<R, B>(h, o0, b0, z0, z1, 1, SM_PROLONG, xc1);
@@ -1505,7 +1822,7 @@ static FinArgs fin_args(Handle *h, const Shape *S, int two, int slot, int slot2,
 }
 
 static void finalize(Handle *h, const FinArgs &A) {
-  DBS_LAUNCH(h, KC_FINALIZE, k_finalize, dim3(h->ns), dim3(FLAT_T), A, h->scal);
+  DBS_LAUNCH(h, KC_FINALIZE, k_finalize, dim3(h->ns), dim3(FIN_T), A, h->scal);
 }
 
 static bool any_closed(const Handle *h) {

@@ -150,3 +150,22 @@ def test_mixed_precision_errors_per_field():
     # the pressure operator; alpha only feels them through the fluxes
     assert e["p_rgh_relL2"] <= 1e-7 and e["U_relL2"] <= 1e-7 and e["F_relL2"] <= 1e-7
     assert e["alpha_maxabs"] <= 1e-8
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_fused_sweeps_agree_with_half_sweeps(precision):
+    """The fused full-sweep smoother and the two half-sweep launches are the
+    same red-black Gauss-Seidel sweep: solves agree to the tolerance."""
+    dbs = _dbs()
+    case = W.fractured_3d(shape=(45, 38, 21), fractures="planes", n_frac=2, steps=3).replace(
+        p_tol=1e-12)
+    outs, its = [], []
+    for fused in (1, 0):
+        with dbs.Solver(case, precision=precision) as s:
+            s.set_tuning(kz=0, sweeps=2, bottom_shift=0, fused=fused)
+            s.step(3)
+            outs.append(s.state())
+            its.append(s.stats()["p_iters"])
+    print("fused vs half sweeps", precision, its, flush=True)
+    compare_states(outs[0], outs[1], tol_l2=1e-9, tol_alpha=1e-12, label=f"fused/{precision}")
+    assert abs(sum(its[0]) - sum(its[1])) <= 2
