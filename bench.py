@@ -208,6 +208,7 @@ def main():
     ap.add_argument("--no-graph", action="store_true", help="skip the graph-mode leg")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched leg")
     ap.add_argument("--batch-samples", type=int, default=512)
+    ap.add_argument("--coarse-sweeps", type=int, default=2)
     ap.add_argument("--fused", type=int, default=1,
                     help="1: fused full sweeps on the fine level (else half sweeps)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -241,7 +242,8 @@ def main():
     case = case.replace(p_tol=args.p_tol, p_maxit=500)
     cells = case.ncells
 
-    knobs = {"kz": 0, "sweeps": 2, "bottom_shift": 0, "fused": args.fused}
+    knobs = {"kz": 0, "sweeps": 2, "coarse_sweeps": args.coarse_sweeps, "bottom_shift": 0,
+             "fused": args.fused}
     main_run = time_solver(case, args.precision, args.steps, args.warmup,
                            prof_class=args.kernel, profile_all=args.kernel is None, knobs=knobs)
     ms = main_run["sec"] / args.steps * 1e3

@@ -203,16 +203,18 @@ int dbs_set_graph(dbs_handle *h, int on);
 
 /* Autotuner: times the pressure solve of the current state's first
    corrector under candidate settings and keeps the fastest that converges:
-   red-black sweeps per level (1..3, pre = post), the depth at which the
-   single work-group bottom takes over (bottom_shift 0 or 1 levels coarser
-   than the first that fits in LDS), fused full sweeps on the finest level
-   or two half-sweep launches, then the planes per fine-level tile (kz
-   2..16).  The state is unchanged afterwards.  Outputs may be NULL; *ms
-   receives the best solve time in milliseconds. */
-int dbs_autotune(dbs_handle *h, int *kz, int *sweeps, int *bottom_shift, int *fused,
-                 double *ms);
+   red-black sweeps on the finest level (1..3, pre = post) with the same
+   count on the coarse levels, then one sweep on the coarse levels, the
+   depth at which the single work-group bottom takes over (bottom_shift 0
+   or 1 levels coarser than the first that fits in LDS), fused full sweeps
+   on the finest level or two half-sweep launches, then the planes per
+   fine-level tile (kz 2..16).  The state is unchanged afterwards.  Outputs
+   may be NULL; *ms receives the best solve time in milliseconds. */
+int dbs_autotune(dbs_handle *h, int *kz, int *sweeps, int *coarse_sweeps, int *bottom_shift,
+                 int *fused, double *ms);
 /* Set the same knobs by hand (kz = 0: the launch-size heuristic). */
-int dbs_set_tuning(dbs_handle *h, int kz, int sweeps, int bottom_shift, int fused);
+int dbs_set_tuning(dbs_handle *h, int kz, int sweeps, int coarse_sweeps, int bottom_shift,
+                   int fused);
 
 /* Tests only (single-sample handles).  Solve the p_rgh pressure equation of
    this handle's mesh and boundary conditions, -div(rAU_f grad x) with outlet faces as Dirichlet

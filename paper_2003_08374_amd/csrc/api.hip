@@ -799,8 +799,8 @@ int dbs_set_graph(dbs_handle *H, int on) {
   return DBS_OK;
 }
 
-int dbs_autotune(dbs_handle *H, int *kz_out, int *sweeps_out, int *shift_out, int *fused_out,
-                 double *ms_out) {
+int dbs_autotune(dbs_handle *H, int *kz_out, int *sweeps_out, int *coarse_out, int *shift_out,
+                 int *fused_out, double *ms_out) {
   if (!H) return DBS_EINVAL;
   Handle *h = &H->h;
   int rc = DBS_OK;
@@ -819,13 +819,14 @@ int dbs_autotune(dbs_handle *H, int *kz_out, int *sweeps_out, int *shift_out, in
   corrector_assemble(h);
   copy_n(h, h->prgh, x0, (size_t)h->NC);
   struct Cand {
-    int kz, sweeps, shift, fused;
+    int kz, sweeps, coarse, shift, fused;
   };
-  Cand best{h->kz_fine, h->mg_pre, h->bottom_shift, h->fused_sweep};
+  Cand best{h->kz_fine, h->mg_pre, h->mgc, h->bottom_shift, h->fused_sweep};
   double best_ms = 1e300;
   auto trial = [&](const Cand &c) {
     h->kz_fine = c.kz;
     h->mg_pre = h->mg_post = c.sweeps;
+    h->mgc = c.coarse;
     h->bottom_shift = c.shift;
     h->fused_sweep = c.fused;
     if (pressure_retune(h)) return;
@@ -838,12 +839,14 @@ int dbs_autotune(dbs_handle *H, int *kz_out, int *sweeps_out, int *shift_out, in
     }
   };
   for (int sw = 1; sw <= 3; sw++)
-    for (int shf = 0; shf <= 1; shf++) trial(Cand{0, sw, shf, 1});
-  trial(Cand{0, best.sweeps, best.shift, 0});
+    for (int shf = 0; shf <= 1; shf++) trial(Cand{0, sw, sw, shf, 1});
+  trial(Cand{0, best.sweeps, 1, best.shift, 1});
+  trial(Cand{0, best.sweeps, best.coarse, best.shift, 0});
   const Cand mid = best;
-  for (int kz : {2, 4, 8, 16}) trial(Cand{kz, mid.sweeps, mid.shift, mid.fused});
+  for (int kz : {2, 4, 8, 16}) trial(Cand{kz, mid.sweeps, mid.coarse, mid.shift, mid.fused});
   h->kz_fine = best.kz;
   h->mg_pre = h->mg_post = best.sweeps;
+  h->mgc = best.coarse;
   h->bottom_shift = best.shift;
   h->fused_sweep = best.fused;
   rc = pressure_retune(h);
@@ -856,19 +859,22 @@ int dbs_autotune(dbs_handle *H, int *kz_out, int *sweeps_out, int *shift_out, in
   if (!rc) rc = hip_check(h, hipStreamSynchronize(h->stream), "autotune");
   if (kz_out) *kz_out = best.kz;
   if (sweeps_out) *sweeps_out = best.sweeps;
+  if (coarse_out) *coarse_out = best.coarse;
   if (shift_out) *shift_out = best.shift;
   if (fused_out) *fused_out = best.fused;
   if (ms_out) *ms_out = best_ms;
   return rc;
 }
 
-int dbs_set_tuning(dbs_handle *H, int kz, int sweeps, int shift, int fused) {
-  if (!H || kz < 0 || kz > 64 || sweeps < 1 || sweeps > 8 || shift < 0 || shift > 4)
+int dbs_set_tuning(dbs_handle *H, int kz, int sweeps, int coarse_sweeps, int shift, int fused) {
+  if (!H || kz < 0 || kz > 64 || sweeps < 1 || sweeps > 8 || coarse_sweeps < 1 ||
+      coarse_sweeps > 8 || shift < 0 || shift > 4)
     return DBS_EINVAL;
   Handle *h = &H->h;
   hipStreamSynchronize(h->stream);
   h->kz_fine = kz;
   h->mg_pre = h->mg_post = sweeps;
+  h->mgc = coarse_sweeps;
   h->bottom_shift = shift;
   h->fused_sweep = fused ? 1 : 0;
   reset_graphs(h);

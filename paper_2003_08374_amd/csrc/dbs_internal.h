@@ -143,6 +143,7 @@ struct Handle {
   void *btab = nullptr;      // device table of bottom descriptors
   int nbt = 0;               // samples with a bottom (>= 2 levels)
   int mg_pre = 2, mg_post = 2, coarse_sweeps = 16;
+  int mgc = 2;  // sweeps per coarse level (pre = post), bottom levels included
   // tuning knobs (autotuner): fine tile depth (0 = heuristic), bottom shift,
   // fused full sweeps on the fine level (else two half-sweep launches)
   int kz_fine = 0, bottom_shift = 0, fused_sweep = 1;

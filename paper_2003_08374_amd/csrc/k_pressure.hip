@@ -1072,6 +1072,11 @@ struct SwPlane {
   __device__ static constexpr int at(int lx, int ly) { return (ly + 2) * FXR + lx + RX; }
 };
 
+// 1/D for the smoother: the hardware reciprocal in FP32 (the V-cycle is a
+// preconditioner; the outer FP64 CG is unaffected), exact in FP64
+__device__ __forceinline__ float sw_rcp(float d) { return __builtin_amdgcn_rcpf(d); }
+__device__ __forceinline__ double sw_rcp(double d) { return 1.0 / d; }
+
 // row of the fine operator at (i,j,k) from the seven rAU values around it
 template <typename R>
 __device__ __forceinline__ void coef7(const Op<R> &L, int i, int j, int k, R rc, R rxm, R rxp,
@@ -1213,10 +1218,10 @@ __global__ void __launch_bounds__(NT2) k_sweep25(OpB<R> LB, SH S, const B *__res
     R T[6], D;
     coef7(L, i, jj, k, Rc[c2], Rc[c2 - 1], Rc[c2 + 1], Rc[c2 - FXR], Rc[c2 + FXR], Rm[c2],
           Rp[c2], T, D);
-    if (MODE == SW_ZERO) return D > (R)0 ? bb / D : (R)0;
+    if (MODE == SW_ZERO) return D > (R)0 ? bb * sw_rcp(D) : (R)0;
     const R off = T[0] * Xc[c2 - 1] + T[1] * Xc[c2 + 1] + T[2] * Xc[c2 - FXR] +
                   T[3] * Xc[c2 + FXR] + T[4] * Xm[c2] + T[5] * Xp[c2];
-    return D > (R)0 ? (bb + off) / D : (R)0;
+    return D > (R)0 ? (bb + off) * sw_rcp(D) : (R)0;
   };
   // prologue: x and rAU of planes k0-2, k0-1 in LDS, plane k0 in registers;
   // b of plane k0-1 in registers
@@ -1269,7 +1274,7 @@ __global__ void __launch_bounds__(NT2) k_sweep25(OpB<R> LB, SH S, const B *__res
         coef7(L, iB, j, kb, rbc, rbxm, rbxp, rbym, rbyp, r_m2.get(offA), r_0.get(offA), T, D);
         const R off = T[0] * Ac[c1 - 1] + T[1] * Ac[c1 + 1] + T[2] * Ac[c1 - FX1] +
                       T[3] * Ac[c1 + FX1] + T[4] * a_m2 + T[5] * a_0;
-        vB = D > (R)0 ? (b_prev.get(offA) + off) / D : (R)0;
+        vB = D > (R)0 ? (b_prev.get(offA) + off) * sw_rcp(D) : (R)0;
       }
       // the pair in memory order: offset 0 first
       const R v0 = offA == 0 ? vB : a_m1, v1 = offA == 0 ? a_m1 : vB;
@@ -1535,8 +1540,8 @@ int pressure_retune(Handle *h) {
       memset(&A, 0, sizeof(A));
       A.s = s;
       A.nl = nl - h->bottom[s];
-      A.pre = h->mg_pre;
-      A.post = h->mg_post;
+      A.pre = h->mgc;
+      A.post = h->mgc;
       int off = 0;
       for (int m = 0; m < A.nl; m++) {
         Level &L = h->lv[h->bottom[s] + m];
@@ -1681,7 +1686,7 @@ static void smooth_level(Handle *h, int l, const OpB<R> &o, const B *b, R *x, bo
   if (!L.pair_cyc.nblk) return;
   const SH S = sh(h, L.pair_cyc);
   const dim3 g(L.pair_cyc.nblk);
-  const int n = down ? h->mg_pre : h->mg_post;
+  const int n = h->mgc;
   const int first = down ? 0 : 1;
   for (int s = 0; s < n; s++) {
     DBS_LAUNCH(h, KC_SMOOTHC, (k_smooth<R, B>), g, blk(), o, S, b, x, first,

@@ -118,9 +118,8 @@ def lib():
         L.dbs_batch_get_state_dev.argtypes = [H, C.c_int] + [C.c_void_p] * 6
         L.dbs_batch_get_stats.argtypes = [H, C.c_int, C.POINTER(Stats)]
         L.dbs_set_graph.argtypes = [H, C.c_int]
-        L.dbs_autotune.argtypes = [H, C.POINTER(C.c_int), C.POINTER(C.c_int),
-                                   C.POINTER(C.c_int), C.POINTER(C.c_int), _DP]
-        L.dbs_set_tuning.argtypes = [H, C.c_int, C.c_int, C.c_int, C.c_int]
+        L.dbs_autotune.argtypes = [H] + [C.POINTER(C.c_int)] * 5 + [_DP]
+        L.dbs_set_tuning.argtypes = [H] + [C.c_int] * 5
         _lib = L
     return _lib
 
@@ -207,18 +206,17 @@ class _Handle:
         self._check(lib().dbs_set_graph(self.h, int(bool(on))))
 
     def autotune(self):
-        """Tune tile depth, sweeps, bottom depth and sweep fusion on the
-        current state (which is left unchanged)."""
-        kz, sw, sh, fu = C.c_int(), C.c_int(), C.c_int(), C.c_int()
+        """Tune tile depth, sweeps, coarse sweeps, bottom depth and sweep
+        fusion on the current state (which is left unchanged)."""
+        v = [C.c_int() for _ in range(5)]
         ms = C.c_double()
-        self._check(lib().dbs_autotune(self.h, C.byref(kz), C.byref(sw), C.byref(sh),
-                                       C.byref(fu), C.byref(ms)))
-        return {"kz": kz.value, "sweeps": sw.value, "bottom_shift": sh.value,
-                "fused": fu.value, "ms": ms.value}
+        self._check(lib().dbs_autotune(self.h, *[C.byref(x) for x in v], C.byref(ms)))
+        return {"kz": v[0].value, "sweeps": v[1].value, "coarse_sweeps": v[2].value,
+                "bottom_shift": v[3].value, "fused": v[4].value, "ms": ms.value}
 
-    def set_tuning(self, kz=0, sweeps=2, bottom_shift=0, fused=1):
-        self._check(lib().dbs_set_tuning(self.h, int(kz), int(sweeps), int(bottom_shift),
-                                         int(fused)))
+    def set_tuning(self, kz=0, sweeps=2, coarse_sweeps=2, bottom_shift=0, fused=1):
+        self._check(lib().dbs_set_tuning(self.h, int(kz), int(sweeps), int(coarse_sweeps),
+                                         int(bottom_shift), int(fused)))
 
     @staticmethod
     def _stats_dict(s, n):

@@ -121,6 +121,7 @@ def test_autotune_keeps_state_and_converges():
         for k in ("alpha", "p_rgh", "U"):
             assert np.array_equal(before[k], after[k]), k
         assert knobs["sweeps"] in (1, 2, 3) and knobs["bottom_shift"] in (0, 1)
+        assert knobs["coarse_sweeps"] in (1, 2, 3) and knobs["fused"] in (0, 1)
         assert knobs["kz"] in (0, 2, 4, 8, 16) and knobs["ms"] > 0
         s.step(2)
         out = s.state()
@@ -162,7 +163,7 @@ def test_fused_sweeps_agree_with_half_sweeps(precision):
     outs, its = [], []
     for fused in (1, 0):
         with dbs.Solver(case, precision=precision) as s:
-            s.set_tuning(kz=0, sweeps=2, bottom_shift=0, fused=fused)
+            s.set_tuning(kz=0, sweeps=2, coarse_sweeps=2, bottom_shift=0, fused=fused)
             s.step(3)
             outs.append(s.state())
             its.append(s.stats()["p_iters"])
