@@ -50,7 +50,7 @@ extern "C" {
 #define DBS_ECOURANT (-6) /* Courant number above max_courant; step not taken */
 #define DBS_EBOUNDS (-7)  /* alpha left [-bounds_tol, 1 + bounds_tol] */
 
-enum { DBS_BC_WALL = 0, DBS_BC_INLET = 1, DBS_BC_OUTLET = 2, DBS_BC_EMPTY = 3 };
+enum { DBS_BC_WALL = 0, DBS_BC_INLET = 1, DBS_BC_OUTLET = 2, DBS_BC_EMPTY = 3, DBS_BC_WAVE = 4 };
 enum { DBS_BROOKS_COREY = 0, DBS_VAN_GENUCHTEN = 1 };
 enum { DBS_FP64 = 0, DBS_MIXED = 1 };
 
@@ -79,6 +79,15 @@ typedef struct {
   double U[3];          /* inlet velocity */
   double alpha;         /* inlet alpha; outlet backflow alpha */
   double p;             /* outlet static pressure p [Pa] */
+  double wave[3];       /* DBS_BC_WAVE (x faces): amplitude A [m], period T [s] and
+                           still-water depth d [m] above y = 0 of a linear wave:
+                           surface d + A sin(w t), w = 2 pi / T, w^2 = |g| k tanh(k d);
+                           below it alpha = 1, u = A w cosh(k y)/sinh(k d) sin(w t)
+                           into the domain and v = A w sinh(k y)/sinh(k d) cos(w t);
+                           above it alpha = 0 and U = 0.  Values of a step are taken
+                           at its end time; outflowing faces carry the cell alpha.
+                           The paper gives no formula for its coastal-barrier inlet
+                           (Sec. 4.2); this is linear wave theory. */
 } dbs_bc;
 
 typedef struct {
@@ -103,6 +112,7 @@ typedef struct {
   double alpha_min, alpha_max;
   double phase_volume;  /* sum phi alpha V */
   double max_courant;   /* at the start of the last step */
+  double time;          /* time reached (steps x dt from dbs_set_time's value) */
 } dbs_stats;
 
 typedef struct dbs_handle dbs_handle;
@@ -145,6 +155,9 @@ int dbs_get_state_dev(dbs_handle *h, double *alpha, double *U, double *p_rgh, do
 int dbs_set_stream(dbs_handle *h, void *stream);
 
 int dbs_get_stats(dbs_handle *h, dbs_stats *out);
+/* Time of the state of every sample (default 0); time-dependent boundary
+   values (DBS_BC_WAVE) of the next step are taken at t + dt. */
+int dbs_set_time(dbs_handle *h, double t);
 const char *dbs_last_error(const dbs_handle *h);
 void dbs_destroy(dbs_handle *h);
 

@@ -69,7 +69,17 @@
  *       zero-gradient U, alpha zero-gradient on outflow and the given value on
  *       backflow; wall = no-slip, zero flux, zero-gradient alpha; empty = 2D;
  *   R14 closed domains: zero-mean p_rgh;
- *   R15 the pressure solve ends at ||b - A x||_2 <= tol ||b||_2.
+ *   R15 the pressure solve ends at ||b - A x||_2 <= tol ||b||_2;
+ *   R16 wave inlet (the coastal-barrier configuration of Sec. 4; the paper
+ *       gives no boundary formula): linear (Airy) wave theory on still water
+ *       of depth d, surface elevation A sin(w t) at the inlet, w = 2 pi / T,
+ *       wavenumber from w^2 = |g| k tanh(k d); below the surface the face
+ *       carries alpha = 1 and the orbital velocity
+ *       u = A w cosh(k y)/sinh(k d) sin(w t) (into the domain),
+ *       v = A w sinh(k y)/sinh(k d) cos(w t) (so v = d eta/dt at y = d),
+ *       above it alpha = 0 and U = 0; y is the face-centre height; all
+ *       boundary values of a step are taken at its end time t^{n+1};
+ *       outflowing wave faces carry the cell alpha.
  */
 #include "dbs_oracle.h"
 
@@ -95,6 +105,7 @@ typedef struct {
   double h[3], V;
   face_t *f;
   int *cf; /* six face ids per cell: x-, x+, y-, y+, z-, z+ */
+  double t; /* time at which boundary values are taken */
 } mesh_t;
 
 static double clampd(double x, double lo, double hi) {
@@ -126,7 +137,12 @@ static int validate_case(const dbso_case *cs) {
     if (e0 && n[a] != 1) return -1;
   }
   for (int b = 0; b < 6; b++)
-    if (cs->bc_kind[b] < DBSO_WALL || cs->bc_kind[b] > DBSO_EMPTY) return -1;
+    if (cs->bc_kind[b] < DBSO_WALL || cs->bc_kind[b] > DBSO_WAVE) return -1;
+  for (int b = 2; b < 6; b++)
+    if (cs->bc_kind[b] == DBSO_WAVE) return -1; /* wave inlets sit on x faces */
+  for (int b = 0; b < 2; b++)
+    if (cs->bc_kind[b] == DBSO_WAVE &&
+        !(cs->bc_wave[b][1] > 0.0 && cs->bc_wave[b][2] > 0.0)) return -1;
   if (!(cs->dt > 0.0) || cs->n_corr < 1 || cs->n_corr > 16 || cs->mom_sweeps < 0)
     return -1;
   return 0;
@@ -249,12 +265,55 @@ static void cell_props(const dbso_case *cs, double a, double kinv, props_t *p) {
   p->mu = a * cs->mu_l + (1.0 - a) * cs->mu_g;
 }
 
-/* alpha on a boundary face (R13) given the face flux along +axis */
-static double bnd_alpha(const dbso_case *cs, const face_t *F, const double *alpha,
-                        double flux) {
+static const double PI = 3.14159265358979323846;
+
+static int is_inlet(int kind) { return kind == DBSO_INLET || kind == DBSO_WAVE; }
+
+/* wavenumber of linear waves: the root of w^2 = gm k tanh(k d), by bisection */
+static double wave_number(double w, double gm, double d) {
+  double lo = 0.0, hi = 1.0;
+  while (gm * hi * tanh(hi * d) < w * w) hi *= 2.0;
+  for (int it = 0; it < 200; it++) {
+    double mid = 0.5 * (lo + hi);
+    if (gm * mid * tanh(mid * d) < w * w) lo = mid; else hi = mid;
+  }
+  return 0.5 * (lo + hi);
+}
+
+/* velocity and alpha prescribed on an inlet face at time m->t (R13, R16) */
+static void inlet_face(const mesh_t *m, const face_t *F, double U[3], double *alpha) {
+  const dbso_case *cs = m->cs;
+  if (F->kind != DBSO_WAVE) {
+    for (int d = 0; d < 3; d++) U[d] = cs->bc_U[F->bnd][d];
+    *alpha = cs->bc_alpha[F->bnd];
+    return;
+  }
+  const double *wv = cs->bc_wave[F->bnd];
+  double A = wv[0], w = 2.0 * PI / wv[1], d = wv[2];
+  double gm = sqrt(cs->g[0] * cs->g[0] + cs->g[1] * cs->g[1] + cs->g[2] * cs->g[2]);
+  double k = wave_number(w, gm, d);
+  double y = F->xf[1], t = m->t;
+  U[0] = U[1] = U[2] = 0.0;
+  *alpha = 0.0;
+  if (y < d + A * sin(w * t)) {
+    double into = F->bnd == 0 ? 1.0 : -1.0;
+    U[0] = into * A * w * cosh(k * y) / sinh(k * d) * sin(w * t);
+    U[1] = A * w * sinh(k * y) / sinh(k * d) * cos(w * t);
+    *alpha = 1.0;
+  }
+}
+
+/* alpha on a boundary face (R13, R16) given the face flux along +axis */
+static double bnd_alpha(const mesh_t *m, const face_t *F, const double *alpha, double flux) {
+  const dbso_case *cs = m->cs;
   double so;
   int c = bnd_cell(F, &so);
   if (F->kind == DBSO_INLET) return cs->bc_alpha[F->bnd];
+  if (F->kind == DBSO_WAVE && so * flux < 0.0) {
+    double U[3], ab;
+    inlet_face(m, F, U, &ab);
+    return ab;
+  }
   if (F->kind == DBSO_OUTLET && so * flux < 0.0) return cs->bc_alpha[F->bnd];
   return alpha[c];
 }
@@ -287,7 +346,7 @@ static void alpha_stage(const mesh_t *m, const double *phi, const double *kinv,
     const face_t *Fc = &m->f[f];
     if (Fc->kind == DBSO_EMPTY) continue;
     double af = Fc->bnd < 0 ? 0.5 * (alpha[Fc->own] + alpha[Fc->nbr])
-                            : bnd_alpha(cs, Fc, alpha, F[f]);
+                            : bnd_alpha(m, Fc, alpha, F[f]);
     if (Fc->own >= 0) grad[Fc->own * 3 + Fc->axis] += af * Fc->area / V;
     if (Fc->nbr >= 0) grad[Fc->nbr * 3 + Fc->axis] -= af * Fc->area / V;
   }
@@ -299,7 +358,7 @@ static void alpha_stage(const mesh_t *m, const double *phi, const double *kinv,
     if (Fc->kind == DBSO_EMPTY) continue;
     double Ff = F[f];
     if (Fc->bnd >= 0) {
-      FL[f] = Ff * bnd_alpha(cs, Fc, alpha, Ff);
+      FL[f] = Ff * bnd_alpha(m, Fc, alpha, Ff);
       A[f] = 0.0;
       continue;
     }
@@ -367,7 +426,7 @@ static void alpha_stage(const mesh_t *m, const double *phi, const double *kinv,
         amax = maxd(amax, alpha[nb]);
         amin = mind(amin, alpha[nb]);
       } else if (so * F[f] < 0.0) {
-        double ab = bnd_alpha(cs, Fc, alpha, F[f]);
+        double ab = bnd_alpha(m, Fc, alpha, F[f]);
         amax = maxd(amax, ab);
         amin = mind(amin, ab);
       }
@@ -474,15 +533,16 @@ static void face_forces(const mesh_t *m, const props_t *pr, const double *alpha,
    force density is extrapolated from the opposite face of the same cell. */
 static void fixed_flux_forces(const mesh_t *m, const double *HbyA, const double *rAU,
                               double *q) {
-  const dbso_case *cs = m->cs;
   for (int f = 0; f < m->nf; f++) {
     const face_t *Fc = &m->f[f];
-    if (Fc->bnd < 0 || (Fc->kind != DBSO_WALL && Fc->kind != DBSO_INLET)) continue;
+    if (Fc->bnd < 0 || (Fc->kind != DBSO_WALL && !is_inlet(Fc->kind))) continue;
     double so;
     int c = bnd_cell(Fc, &so);
     int a = Fc->axis;
     if (HbyA) {
-      double Fb = Fc->kind == DBSO_INLET ? cs->bc_U[Fc->bnd][a] * Fc->area : 0.0;
+      double Ub[3], ab;
+      if (is_inlet(Fc->kind)) inlet_face(m, Fc, Ub, &ab);
+      double Fb = is_inlet(Fc->kind) ? Ub[a] * Fc->area : 0.0;
       q[f] = (Fb - HbyA[a * m->nc + c] * Fc->area) / rAU[c];
     } else {
       int opp = m->cf[c * 6 + 2 * a + (so > 0.0 ? 0 : 1)];
@@ -559,9 +619,9 @@ static void momentum_assemble(const mesh_t *m, const double *phi, const props_t 
     double conv = 1.0 / (phi[c] * phi[c] * V);
     if (Fc->kind == DBSO_WALL) {
       eq->aP[c] += pn[c].mu * Fc->area / (Fc->dist * V);
-    } else if (Fc->kind == DBSO_INLET) {
-      const double *Ub = cs->bc_U[Fc->bnd];
-      double ab = cs->bc_alpha[Fc->bnd];
+    } else if (is_inlet(Fc->kind)) {
+      double Ub[3], ab;
+      inlet_face(m, Fc, Ub, &ab);
       double vis = (ab * cs->mu_l + (1.0 - ab) * cs->mu_g) * Fc->area / (Fc->dist * V);
       if (out >= 0.0) eq->aP[c] += out * conv;
       else
@@ -582,11 +642,11 @@ static void momentum_assemble(const mesh_t *m, const double *phi, const props_t 
       if (Fc->bnd < 0) {
         for (int d = 0; d < 3; d++) Uf[d] = 0.5 * (U[d * nc + Fc->own] + U[d * nc + Fc->nbr]);
       } else {
-        double so;
+        double so, Ub[3], ab;
         int c = bnd_cell(Fc, &so);
+        if (is_inlet(Fc->kind)) inlet_face(m, Fc, Ub, &ab);
         for (int d = 0; d < 3; d++)
-          Uf[d] = Fc->kind == DBSO_WALL ? 0.0
-                  : Fc->kind == DBSO_INLET ? cs->bc_U[Fc->bnd][d] : U[d * nc + c];
+          Uf[d] = Fc->kind == DBSO_WALL ? 0.0 : is_inlet(Fc->kind) ? Ub[d] : U[d * nc + c];
       }
       for (int d = 0; d < 3; d++) {
         if (Fc->own >= 0) gU[Fc->own * 9 + Fc->axis * 3 + d] += Uf[d] * Fc->area / V;
@@ -609,8 +669,9 @@ static void momentum_assemble(const mesh_t *m, const double *phi, const props_t 
           double so;
           int c = bnd_cell(Fc, &so);
           gfi = gU[c * 9 + i * 3 + a];
-          if (Fc->kind == DBSO_INLET) {
-            double ab = cs->bc_alpha[Fc->bnd];
+          if (is_inlet(Fc->kind)) {
+            double Ub[3], ab;
+            inlet_face(m, Fc, Ub, &ab);
             muf = ab * cs->mu_l + (1.0 - ab) * cs->mu_g;
           } else {
             muf = pn[c].mu;
@@ -739,6 +800,7 @@ int dbso_init_flux(const dbso_case *cs, const double *Ux, const double *Uy,
                    const double *Uz, double *Fx, double *Fy, double *Fz) {
   mesh_t m;
   if (build_mesh(cs, &m)) { free_mesh(&m); return -1; }
+  m.t = cs->t0;
   const double *U[3] = {Ux, Uy, Uz};
   double *Fo[3] = {Fx, Fy, Fz};
   int off = 0;
@@ -748,8 +810,10 @@ int dbso_init_flux(const dbso_case *cs, const double *Ux, const double *Uy,
       double v = 0.0;
       if (Fc->bnd < 0) {
         v = 0.5 * (U[a][Fc->own] + U[a][Fc->nbr]) * Fc->area;
-      } else if (Fc->kind == DBSO_INLET) {
-        v = cs->bc_U[Fc->bnd][a] * Fc->area;
+      } else if (is_inlet(Fc->kind)) {
+        double Ub[3], ab;
+        inlet_face(&m, Fc, Ub, &ab);
+        v = Ub[a] * Fc->area;
       } else if (Fc->kind == DBSO_OUTLET) {
         double so;
         v = U[a][bnd_cell(Fc, &so)] * Fc->area;
@@ -828,6 +892,7 @@ int dbso_step(const dbso_case *cs, const double *phi, const double *kinv,
 
   for (int step = 0; step < nsteps && rc == 0; step++) {
     dbso_trace *tr = step == 0 ? trace : NULL;
+    m.t = cs->t0 + (step + 1) * cs->dt;  /* boundary values at t^{n+1} (R16) */
     /* 1. saturation */
     for (int c = 0; c < nc; c++) cell_props(cs, alpha[c], kinv[c], &po[c]);
     alpha_stage(&m, phi, kinv, alpha, F, p_rgh, an, aPhi, rPhi, tr);
@@ -866,8 +931,10 @@ int dbso_step(const dbso_case *cs, const double *phi, const double *kinv,
           double rAUf = 0.5 * (rAU[o] + rAU[n]);
           phiH[f] = 0.5 * (HbyA[a * nc + o] + HbyA[a * nc + n]) * Fc->area +
                     rAUf * face_body_force(&m, pn, an, f) * Fc->area;
-        } else if (Fc->kind == DBSO_INLET) {
-          phiH[f] = cs->bc_U[Fc->bnd][a] * Fc->area;
+        } else if (is_inlet(Fc->kind)) {
+          double Ub[3], ab;
+          inlet_face(&m, Fc, Ub, &ab);
+          phiH[f] = Ub[a] * Fc->area;
         } else {
           double so;
           phiH[f] = HbyA[a * nc + bnd_cell(Fc, &so)] * Fc->area;

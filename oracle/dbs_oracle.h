@@ -22,7 +22,7 @@
 extern "C" {
 #endif
 
-enum { DBSO_WALL = 0, DBSO_INLET = 1, DBSO_OUTLET = 2, DBSO_EMPTY = 3 };
+enum { DBSO_WALL = 0, DBSO_INLET = 1, DBSO_OUTLET = 2, DBSO_EMPTY = 3, DBSO_WAVE = 4 };
 enum { DBSO_BROOKS_COREY = 0, DBSO_VAN_GENUCHTEN = 1 };
 
 typedef struct {
@@ -51,6 +51,10 @@ typedef struct {
   int mules_iter;           /* MULES limiter iterations */
   double p_tol;             /* relative residual of the pressure solve */
   int p_maxit;
+  /* wave inlet (x faces only): amplitude A [m], period T [s], still-water
+     depth d [m] measured from y = 0 */
+  double bc_wave[6][3];
+  double t0;                /* time at the start of the first step [s] */
 } dbso_case;
 
 typedef struct {

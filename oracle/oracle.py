@@ -20,7 +20,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libdbs_oracle.so")
 
-_KIND = {"wall": 0, "inlet": 1, "outlet": 2, "empty": 3}
+_KIND = {"wall": 0, "inlet": 1, "outlet": 2, "empty": 3, "wave": 4}
 _MODEL = {"brooks_corey": 0, "van_genuchten": 1}
 
 
@@ -44,6 +44,8 @@ class OracleCase(C.Structure):
         ("n_corr", C.c_int), ("mom_sweeps", C.c_int), ("transpose_visc", C.c_int),
         ("mules_iter", C.c_int),
         ("p_tol", C.c_double), ("p_maxit", C.c_int),
+        ("bc_wave", (C.c_double * 3) * 6),
+        ("t0", C.c_double),
     ]
 
 
@@ -67,8 +69,11 @@ class OracleTrace(C.Structure):
 
 def build(force: bool = True) -> str:
     """Compile the oracle with gcc (plain C99, FP64, no FMA contraction)."""
-    if force or not os.path.exists(LIB_PATH):
-        src = os.path.join(_HERE, "dbs_oracle.c")
+    src = os.path.join(_HERE, "dbs_oracle.c")
+    hdr = os.path.join(_HERE, "dbs_oracle.h")
+    stale = (not os.path.exists(LIB_PATH) or
+             max(os.path.getmtime(src), os.path.getmtime(hdr)) > os.path.getmtime(LIB_PATH))
+    if force or stale:
         tmp = LIB_PATH + ".tmp"
         subprocess.check_call([
             "gcc", "-std=c99", "-O2", "-ffp-contract=off", "-fPIC", "-shared",
@@ -83,8 +88,7 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB_PATH):
-            build()
+        build(force=False)
         L = C.CDLL(LIB_PATH)
         L.dbso_closures.argtypes = [C.POINTER(OracleCase), C.c_double, _DP, _DP, _DP, _DP]
         L.dbso_closures.restype = None
@@ -133,6 +137,10 @@ def make_case(cs) -> OracleCase:
             o.bc_U[b][a] = bc.get("U", (0.0, 0.0, 0.0))[a]
         o.bc_alpha[b] = bc.get("alpha", 0.0)
         o.bc_p[b] = bc.get("p", 0.0)
+        wave = bc.get("wave", (0.0, 0.0, 0.0))
+        for q in range(3):
+            o.bc_wave[b][q] = wave[q]
+    o.t0 = float(getattr(cs, "t0", 0.0))
     o.dt = cs.dt
     o.n_corr = cs.n_corr
     o.mom_sweeps = cs.mom_sweeps
@@ -179,12 +187,16 @@ def initial_state(cs) -> dict:
     else:
         st["F"] = init_flux(cs, st["U"])
     st["p"] = np.zeros(nc)
+    st["t"] = float(getattr(cs, "t0", 0.0))
     return st
 
 
 def step(cs, state: dict, nsteps: int, trace: bool = False, check: bool = True):
-    """Advance a copy of ``state`` by nsteps; returns (state, info[, trace])."""
+    """Advance a copy of ``state`` by nsteps; returns (state, info[, trace]).
+    The state's time ``t`` (default: the case's t0) is where the steps start."""
     o = make_case(cs)
+    t0 = float(state.get("t", getattr(cs, "t0", 0.0)))
+    o.t0 = t0
     nc = int(np.prod(cs.shape))
     nf = nfaces(cs.shape)
     phi = np.ascontiguousarray(cs.phi, dtype=np.float64).reshape(nc)
@@ -210,7 +222,8 @@ def step(cs, state: dict, nsteps: int, trace: bool = False, check: bool = True):
                          int(nsteps), C.byref(info), C.byref(tr) if tr is not None else None)
     if check and rc:
         raise RuntimeError(f"dbso_step failed ({rc})")
-    out = {"alpha": a, "U": np.stack(U), "p_rgh": prgh, "p": p, "F": tuple(F), "rc": rc}
+    out = {"alpha": a, "U": np.stack(U), "p_rgh": prgh, "p": p, "F": tuple(F), "rc": rc,
+           "t": t0 + nsteps * cs.dt}
     inf = {
         "p_iters": list(info.p_iters)[: cs.n_corr],
         "p_relres": list(info.p_relres)[: cs.n_corr],

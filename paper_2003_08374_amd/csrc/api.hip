@@ -134,6 +134,18 @@ __global__ void __launch_bounds__(256) k_stats_final(const double *__restrict__ 
   }
 }
 
+// the boundary-value time of every sample moves by dt (kept on the device
+// so that captured steps replay correctly)
+__global__ void k_add_time(Geom *__restrict__ g, int ns, double dt) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s < ns) g[s].t += dt;
+}
+
+void add_time(Handle *h, double dt) {
+  DBS_LAUNCH(h, KC_MISC, k_add_time, dim3((h->ns + 255) / 256), dim3(256), h->dG, h->ns, dt);
+  h->tnow += dt;
+}
+
 void cell_stats(Handle *h) {
   dim3 blk(BX, BY);
   const int nb = h->cell.nblk;
@@ -215,12 +227,33 @@ static int validate_sample(const dbs_grid *g, const dbs_bc *bc, std::string &msg
     }
   }
   if ((long long)n[0] * n[1] * n[2] * 4 > 2000000000LL) { msg = "mesh too large"; return DBS_EINVAL; }
-  for (int b = 0; b < 6; b++)
-    if (bc[b].kind < DBS_BC_WALL || bc[b].kind > DBS_BC_EMPTY) { msg = "bad bc kind"; return DBS_EINVAL; }
+  for (int b = 0; b < 6; b++) {
+    if (bc[b].kind < DBS_BC_WALL || bc[b].kind > DBS_BC_WAVE) { msg = "bad bc kind"; return DBS_EINVAL; }
+    if (bc[b].kind == DBS_BC_WAVE &&
+        (b > 1 || !(bc[b].wave[1] > 0.0) || !(bc[b].wave[2] > 0.0) || !isfinite(bc[b].wave[0]))) {
+      msg = "a wave inlet needs an x face, a positive period and a positive depth";
+      return DBS_EINVAL;
+    }
+  }
   return DBS_OK;
 }
 
-static Geom make_geom(const dbs_grid *grid, const dbs_bc *bc, double dt) {
+// wavenumber of a linear wave of angular frequency w on depth d: Newton on
+// f(k) = g k tanh(k d) - w^2 from the deep-water value
+static double wavenumber(double w, double gm, double d) {
+  double k = w * w / gm;
+  for (int it = 0; it < 100; it++) {
+    const double th = tanh(k * d);
+    const double f = gm * k * th - w * w;
+    const double df = gm * (th + k * d * (1.0 - th * th));
+    const double dk = f / df;
+    k -= dk;
+    if (fabs(dk) <= 1e-15 * k) break;
+  }
+  return k;
+}
+
+static Geom make_geom(const dbs_grid *grid, const dbs_bc *bc, double dt, const double g[3]) {
   Geom G;
   memset(&G, 0, sizeof(G));
   G.n[0] = grid->nx; G.n[1] = grid->ny; G.n[2] = grid->nz;
@@ -249,6 +282,15 @@ static Geom make_geom(const dbs_grid *grid, const dbs_bc *bc, double dt) {
     if (bc[b].kind == DBS_BC_OUTLET) G.has_outlet = 1;
   }
   G.dN = 1e-8 / cbrt(G.V);
+  const double gm = sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
+  for (int b = 0; b < 2; b++) {
+    if (bc[b].kind != DBS_BC_WAVE) continue;
+    G.wA[b] = bc[b].wave[0];
+    G.wom[b] = 2.0 * M_PI / bc[b].wave[1];
+    G.wd[b] = bc[b].wave[2];
+    G.wk[b] = gm > 0.0 ? wavenumber(G.wom[b], gm, G.wd[b]) : 0.0;
+  }
+  G.t = 0.0;
   return G;
 }
 
@@ -299,7 +341,7 @@ static int create_impl(int n, const dbs_grid *grids, const dbs_physics *phys, co
   // arenas: cells padded per sample to whole vector-kernel blocks
   long long c0 = 0, f0 = 0;
   for (int s = 0; s < n; s++) {
-    Geom G = make_geom(&grids[s], &bcs[6 * s], ctl->dt);
+    Geom G = make_geom(&grids[s], &bcs[6 * s], ctl->dt, phys->g);
     G.c0 = (int)c0;
     for (int a = 0; a < 3; a++) G.fo[a] += (int)f0;
     h->hrng[s] = Rng{(int)c0, G.nc, G.has_outlet ? 0 : 1, 0};
@@ -476,6 +518,7 @@ static int courant_check(Handle *h) {
 // the largest iteration count per corrector to its_out.
 static int step_body(Handle *h, TraceOut *tr, int budget, std::vector<int> *its_out) {
   int rc = DBS_OK;
+  add_time(h, h->ctl.dt);  // boundary values of this step are taken at its end
   alpha_stage(h);
   if (tr) rc |= copy_out(h, tr->A, h->A, h->hG[0].nf);
   momentum_predictor(h);
@@ -581,8 +624,10 @@ static int graph_step(Handle *h) {
     if (rc) return rc;
     it = h->graphs.emplace(key, ex).first;
     // capturing ran the host side of the step: the roles are already swapped
+    // and the host time moved
   } else {
     swap_roles(h);
+    h->tnow += h->ctl.dt;
   }
   rc = hip_check(h, hipGraphLaunch(it->second, h->stream), "graph launch");
   if (rc) return rc;
@@ -605,6 +650,7 @@ static int graph_step(Handle *h) {
   // redo eagerly from the saved state with the budget raised
   swap_roles(h);
   snapshot(h, false);
+  add_time(h, -h->ctl.dt);
   update_closures(h);
   std::vector<int> its(nc, 0);
   rc = step_body(h, nullptr, 0, &its);
@@ -896,7 +942,19 @@ int dbs_batch_get_stats(dbs_handle *H, int i, dbs_stats *out) {
   if (!H || !out) return DBS_EINVAL;
   if (int rc = check_sample(&H->h, i)) return rc;
   *out = H->h.st[i];
+  out->time = H->h.tnow;
   return DBS_OK;
+}
+
+int dbs_set_time(dbs_handle *H, double t) {
+  if (!H || !isfinite(t)) return DBS_EINVAL;
+  Handle *h = &H->h;
+  int rc = hip_check(h, hipStreamSynchronize(h->stream), "set_time");
+  if (rc) return rc;
+  for (auto &G : h->hG) G.t = t;
+  h->tnow = t;
+  return hip_check(h, hipMemcpy(h->dG, h->hG.data(), sizeof(Geom) * h->ns,
+                                hipMemcpyHostToDevice), "set_time");
 }
 
 int dbs_get_stats(dbs_handle *H, dbs_stats *out) { return dbs_batch_get_stats(H, 0, out); }

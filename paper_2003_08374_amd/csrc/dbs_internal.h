@@ -149,6 +149,7 @@ struct Handle {
   int kz_fine = 0, bottom_shift = 0, fused_sweep = 1;
 
   std::vector<dbs_stats> st;  // per sample
+  double tnow = 0.0;          // time reached by the samples
 
   // graph mode
   int graph_mode = 0;
@@ -208,6 +209,7 @@ void copy_n(Handle *h, const double *src, double *dst, size_t n);
 // convergence flag for corrector c in rec (ns x 16 x 3 doubles)
 void pressure_record(Handle *h, double *rec, int c);
 // api.hip
+void add_time(Handle *h, double dt);  // move the boundary-value time
 void cell_stats(Handle *h);  // per sample: min a, max a, sum phi a V, max Co, nonfinite
 
 }  // namespace dbs

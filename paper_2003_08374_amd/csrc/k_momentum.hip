@@ -71,7 +71,7 @@ __device__ inline double face_force(const Geom &G, const Phys &Ph, const MomArgs
 }
 
 __device__ __forceinline__ bool fixed_flux(const Geom &G, int b) {
-  return G.bck[b] == BC_WALL || G.bck[b] == BC_INLET;
+  return G.bck[b] == BC_WALL || is_inlet(G.bck[b]);
 }
 
 // R(q)_a of cell P.  hbya == nullptr: predictor (a fixed-flux face copies the
@@ -92,7 +92,9 @@ __device__ inline double reconstruct_axis(const Geom &G, const Phys &Ph, const M
     if (!ff[s]) continue;
     if (hbya) {
       const int b = 2 * a + s;
-      const double Fb = G.bck[b] == BC_INLET ? G.bcU[b][a] * G.area[a] : 0.0;
+      double Ub[3] = {0.0, 0.0, 0.0}, ab;
+      if (is_inlet(G.bck[b])) inlet_state(G, b, y_of(G, P), Ub, ab);
+      const double Fb = Ub[a] * G.area[a];
       q[s] = (Fb - hbya[(size_t)a * G.vs + P.c] * G.area[a]) / M.rAU[P.c];
     } else {
       q[s] = ff[1 - s] ? 0.0 : q[1 - s];
@@ -132,8 +134,10 @@ __device__ inline FaceCoef mom_face(const Geom &G, const Phys &Ph, const MomArgs
   const double d2 = 2.0 * G.ih[a];  // 1 / (h/2)
   if (G.bck[b] == BC_WALL) {
     r.diag = mu_of(Ph, M.alpha[P.c]) * G.area[a] * d2 * G.iV;
-  } else if (G.bck[b] == BC_INLET) {
-    const double vis = mu_of(Ph, G.bca[b]) * G.area[a] * d2 * G.iV;
+  } else if (is_inlet(G.bck[b])) {
+    double Ub[3], ab;
+    inlet_state(G, b, y_of(G, P), Ub, ab);
+    const double vis = mu_of(Ph, ab) * G.area[a] * d2 * G.iV;
     if (out >= 0.0) r.diag = out * conv;
     else r.src = -out * conv;
     r.diag += vis;
@@ -155,7 +159,15 @@ __device__ inline double dU(const Geom &G, const double *__restrict__ U, int Qc,
     const bool bnd = s ? Qco[axis] == G.n[axis] - 1 : Qco[axis] == 0;
     if (bnd) {
       const int b = 2 * axis + s;
-      fv[s] = G.bck[b] == BC_WALL ? 0.0 : (G.bck[b] == BC_INLET ? G.bcU[b][comp] : uq);
+      if (G.bck[b] == BC_WALL) {
+        fv[s] = 0.0;
+      } else if (is_inlet(G.bck[b])) {
+        double Ub[3], ab;
+        inlet_state(G, b, (Qco[1] + 0.5) * G.h[1], Ub, ab);
+        fv[s] = Ub[comp];
+      } else {
+        fv[s] = uq;
+      }
     } else {
       fv[s] = 0.5 * (uq + Uc[Qc + (s ? 1 : -1) * stride_of(G, axis)]);
     }
@@ -185,7 +197,8 @@ __global__ void __launch_bounds__(NTHREADS) k_mom_assemble(Segs SG, Phys Ph, Mom
       FaceCoef fc = mom_face(G, Ph, M, P, a, s);
       aP += fc.diag;
       if (fc.src != 0.0) {
-        const double *Ub = G.bcU[2 * a + s];
+        double Ub[3], ab;
+        inlet_state(G, 2 * a + s, y_of(G, P), Ub, ab);
         for (int d = 0; d < 3; d++) S[d] += fc.src * Ub[d];
       }
     }
@@ -207,7 +220,13 @@ __global__ void __launch_bounds__(NTHREADS) k_mom_assemble(Segs SG, Phys Ph, Mom
           for (int i = 0; i < 3; i++) gN[i] = dU(G, U, nb, nco, a, i);
         } else {
           const int b = 2 * a + s;
-          muf = G.bck[b] == BC_INLET ? mu_of(Ph, G.bca[b]) : mu_of(Ph, an);
+          if (is_inlet(G.bck[b])) {
+            double Ub[3], ab;
+            inlet_state(G, b, y_of(G, P), Ub, ab);
+            muf = mu_of(Ph, ab);
+          } else {
+            muf = mu_of(Ph, an);
+          }
         }
         for (int i = 0; i < 3; i++) {
           const double gP = dU(G, U, c, P.co, a, i);
@@ -255,7 +274,11 @@ __device__ inline double phi_hbya(const Geom &G, const Phys &Ph, const MomArgs &
                                   const double *__restrict__ H, const Cell &P, int a, int s) {
   if (on_boundary(G, P, a, s)) {
     const int b = 2 * a + s;
-    if (G.bck[b] == BC_INLET) return G.bcU[b][a] * G.area[a];
+    if (is_inlet(G.bck[b])) {
+      double Ub[3], ab;
+      inlet_state(G, b, y_of(G, P), Ub, ab);
+      return Ub[a] * G.area[a];
+    }
     if (G.bck[b] == BC_OUTLET) return H[(size_t)a * G.vs + P.c] * G.area[a];
     return 0.0;
   }

@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libdbs.so")
 
 OK, EINVAL, ENOMEM, EHIP, ENOCONV, ENAN, ECOURANT, EBOUNDS = 0, -1, -2, -3, -4, -5, -6, -7
-_KIND = {"wall": 0, "inlet": 1, "outlet": 2, "empty": 3}
+_KIND = {"wall": 0, "inlet": 1, "outlet": 2, "empty": 3, "wave": 4}
 _MODEL = {"brooks_corey": 0, "van_genuchten": 1}
 _PREC = {"fp64": 0, "mixed": 1}
 
@@ -27,7 +27,7 @@ EXPORTS = (
     "dbs_debug_pressure_solve", "dbs_debug_step_trace",
     "dbs_batch_create", "dbs_batch_size", "dbs_batch_set_static", "dbs_batch_set_state",
     "dbs_batch_get_state", "dbs_batch_set_state_dev", "dbs_batch_get_state_dev",
-    "dbs_batch_get_stats", "dbs_set_graph", "dbs_autotune", "dbs_set_tuning",
+    "dbs_batch_get_stats", "dbs_set_graph", "dbs_autotune", "dbs_set_tuning", "dbs_set_time",
 )
 
 
@@ -47,7 +47,7 @@ class Physics(C.Structure):
 
 class BC(C.Structure):
     _fields_ = [("kind", C.c_int), ("U", C.c_double * 3), ("alpha", C.c_double),
-                ("p", C.c_double)]
+                ("p", C.c_double), ("wave", C.c_double * 3)]
 
 
 class Controls(C.Structure):
@@ -61,7 +61,8 @@ class Stats(C.Structure):
     _fields_ = [("steps", C.c_longlong), ("p_iters", C.c_int * 16),
                 ("p_relres", C.c_double * 16), ("mg_levels", C.c_int),
                 ("alpha_min", C.c_double), ("alpha_max", C.c_double),
-                ("phase_volume", C.c_double), ("max_courant", C.c_double)]
+                ("phase_volume", C.c_double), ("max_courant", C.c_double),
+                ("time", C.c_double)]
 
 
 _DP = C.POINTER(C.c_double)
@@ -120,6 +121,7 @@ def lib():
         L.dbs_set_graph.argtypes = [H, C.c_int]
         L.dbs_autotune.argtypes = [H] + [C.POINTER(C.c_int)] * 5 + [_DP]
         L.dbs_set_tuning.argtypes = [H] + [C.c_int] * 5
+        L.dbs_set_time.argtypes = [H, C.c_double]
         _lib = L
     return _lib
 
@@ -164,6 +166,8 @@ def make_structs(case, precision=None, p_tol=None, mg=None, max_courant=0.0, bou
             bcs[b].U[a] = d.get("U", (0.0, 0.0, 0.0))[a]
         bcs[b].alpha = d.get("alpha", 0.0)
         bcs[b].p = d.get("p", 0.0)
+        for q in range(3):
+            bcs[b].wave[q] = d.get("wave", (0.0, 0.0, 0.0))[q]
     c = Controls()
     c.dt = case.dt
     c.n_corr = case.n_corr
@@ -214,6 +218,9 @@ class _Handle:
         return {"kz": v[0].value, "sweeps": v[1].value, "coarse_sweeps": v[2].value,
                 "bottom_shift": v[3].value, "fused": v[4].value, "ms": ms.value}
 
+    def set_time(self, t):
+        self._check(lib().dbs_set_time(self.h, float(t)))
+
     def set_tuning(self, kz=0, sweeps=2, coarse_sweeps=2, bottom_shift=0, fused=1):
         self._check(lib().dbs_set_tuning(self.h, int(kz), int(sweeps), int(coarse_sweeps),
                                          int(bottom_shift), int(fused)))
@@ -223,7 +230,8 @@ class _Handle:
         return {"steps": s.steps, "p_iters": list(s.p_iters)[:n],
                 "p_relres": list(s.p_relres)[:n], "mg_levels": s.mg_levels,
                 "alpha_min": s.alpha_min, "alpha_max": s.alpha_max,
-                "phase_volume": s.phase_volume, "max_courant": s.max_courant}
+                "phase_volume": s.phase_volume, "max_courant": s.max_courant,
+                "time": s.time}
 
     # -------------------------------------------------------------- profiling
     def set_profiling(self, mask):

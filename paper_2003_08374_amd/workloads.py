@@ -46,6 +46,11 @@ def outlet(p=0.0, backflow_alpha=0.0):
     return {"kind": "outlet", "p": float(p), "alpha": float(backflow_alpha)}
 
 
+def wave(amplitude, period, depth):
+    """Linear-wave inlet (x faces): surface depth + A sin(2 pi t / T)."""
+    return {"kind": "wave", "wave": (float(amplitude), float(period), float(depth))}
+
+
 @dataclass
 class Case:
     """One single-domain problem: mesh, physics, boundaries, controls, fields.
@@ -78,6 +83,7 @@ class Case:
     p_maxit: int = 2000
     precision: str = "fp64"
     steps: int = 1
+    t0: float = 0.0
 
     @property
     def ncells(self) -> int:
@@ -242,3 +248,49 @@ def batch_cases(n_samples=512, seed=6, lo=32, hi=96, precision="fp64", p_tol=1e-
                          steps=12, name=f"sample_{s}_{n}")
         out.append(c.replace(precision=precision, p_tol=p_tol))
     return out
+
+
+# ---------------------------------------------------------- 2D wave flume
+
+
+def wave_flume(nx=2048, ny=512, h=5e-3, dt=1e-3, amplitude=0.05, period=1.5, depth=0.3,
+               x_barrier=7.0, crest_height=0.4, crest_width=0.4, slope=2.0, steps=2000,
+               name=None):
+    """2D wave flume after the paper's coastal-barrier application (Sec. 4.2):
+    still water of the given depth over the whole length (barrier pores
+    included), a trapezoidal porous barrier (porosity 0.5, k = 1e-8 m^2,
+    Van Genuchten k_r and p_c with m = 0.8, p_c0 = 1e3 Pa) centred at
+    x_barrier with the given crest height and width and side slopes of
+    slope:1 (horizontal:vertical), a linear-wave inlet at x-, a wall at x+
+    and at the bottom, and an open top (p = 0, air on backflow).  Water
+    under air.  The paper's geometry exists only as a figure; these sizes
+    are a stand-in (full size: 10.24 m x 2.56 m, 5 mm cells)."""
+    shape = (nx, ny, 1)
+    x = (np.arange(nx) + 0.5) * h
+    y = (np.arange(ny) + 0.5) * h
+    X, Y = np.meshgrid(x, y)  # (ny, nx)
+    half = 0.5 * crest_width + slope * (crest_height - Y)
+    barrier = (Y < crest_height) & (np.abs(X - x_barrier) < half)
+    phi = np.where(barrier, 0.5, 1.0)[None]
+    kinv = np.where(barrier, 1e8, 0.0)[None]
+    alpha = np.where(Y < depth, 1.0, 0.0)[None]
+    _, U, prgh = _blank_state(shape)
+    bc = [wave(amplitude, period, depth), wall(), wall(), outlet(0.0, 0.0), empty(), empty()]
+    nm = name or f"wave_flume_{nx}x{ny}_A{amplitude:.4f}"
+    return Case(name=nm, shape=shape, h=(h, h, h), fluids=fluids(WATER, AIR),
+                g=(0.0, -GRAVITY, 0.0), bc=bc, phi=phi, kinv=kinv, alpha=alpha, U=U,
+                p_rgh=prgh, dt=dt, steps=steps,
+                kr={"model": "van_genuchten", "m": 0.8},
+                pc={"model": "van_genuchten", "pc0": 1e3, "exp": 0.8})
+
+
+def flume_amplitudes(n=16, seed=7, a0=0.05):
+    """Wave amplitudes a0 (0.75 + 0.5 u), u ~ U[0, 1) seeded."""
+    rng = np.random.default_rng(seed)
+    return a0 * (0.75 + 0.5 * rng.uniform(0.0, 1.0, size=n))
+
+
+def flume_batch(n=16, seed=7, precision="mixed", p_tol=1e-8, **kw):
+    """The flume with n seeded wave amplitudes (one sample each)."""
+    return [wave_flume(amplitude=float(a), **kw).replace(precision=precision, p_tol=p_tol)
+            for a in flume_amplitudes(n, seed)]

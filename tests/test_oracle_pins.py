@@ -528,3 +528,57 @@ def test_momentum_convection_speed(phi):
     shift = (x * uy).sum() / uy.sum() - (x * uy0).sum() / uy0.sum()
     assert uy.sum() == pytest.approx(uy0.sum(), rel=1e-6)
     assert shift == pytest.approx(Ux / phi * dt * steps, rel=2e-3)
+
+
+def _small_flume(**kw):
+    args = dict(nx=48, ny=20, h=0.02, dt=2e-3, amplitude=0.03, period=1.0, depth=0.2,
+                x_barrier=0.6, crest_height=0.25, crest_width=0.1, slope=1.0)
+    args.update(kw)
+    return W.wave_flume(**args)
+
+
+@pytest.mark.parametrize("phase", [0.25, 0.5, 0.75])
+def test_wave_inlet_flux_matches_linear_wave_theory(phase):
+    """Wave inlet (linear wave theory, the flume reading): at time t the
+    inlet-face fluxes are A w cosh(k y)/sinh(k d) sin(w t) times the face area
+    below the surface d + A sin(w t) and zero above, with k the root of the
+    dispersion relation w^2 = g k tanh(k d) (found here by a library root
+    finder, independently of the oracle's bisection)."""
+    from scipy.optimize import brentq
+    c = _small_flume()
+    A, T, d = c.bc[0]["wave"]
+    t = phase * T
+    c = c.replace(t0=t)
+    Fx, _, _ = O.init_flux(c, np.zeros((3, c.ncells)))
+    nx, ny, _ = c.shape
+    h = c.h[0]
+    w = 2 * np.pi / T
+    k = brentq(lambda q: w * w - W.GRAVITY * q * np.tanh(q * d), 1e-9, 1e4)
+    y = (np.arange(ny) + 0.5) * h
+    expect = np.where(y < d + A * np.sin(w * t),
+                      A * w * np.cosh(k * y) / np.sinh(k * d) * np.sin(w * t) * h * h, 0.0)
+    got = Fx.reshape(1, ny, nx + 1)[0, :, 0]
+    assert np.allclose(got, expect, rtol=1e-12, atol=1e-18)
+    # no flux through the walls
+    assert np.all(Fx.reshape(1, ny, nx + 1)[0, :, -1] == 0.0)
+
+
+def test_flume_at_zero_amplitude_is_at_rest_and_conserves_water():
+    """Zero amplitude: the wave inlet prescribes no flow.  Without the
+    barrier, still water under air stays at rest (hydrostatic balance in the
+    p_rgh form); with it, capillary suction draws water into the dry barrier
+    pores, but the water volume is kept (nothing reaches the open top)."""
+    c = _small_flume(amplitude=0.0, crest_height=0.0)
+    assert float(np.asarray(c.kinv).max()) == 0.0
+    st = O.initial_state(c)
+    out, _ = O.step(c.replace(p_tol=1e-13), st, 5)
+    # solver-tolerance level: |U| far below the 0.1 m/s of the wave motion
+    assert np.abs(out["U"]).max() < 1e-6
+    assert np.abs(out["alpha"] - st["alpha"]).max() < 1e-7
+    c = _small_flume(amplitude=0.0)
+    st = O.initial_state(c)
+    out, _ = O.step(c.replace(p_tol=1e-13), st, 5)
+    phi = np.asarray(c.phi).ravel()
+    v0 = float((phi * st["alpha"]).sum())
+    v1 = float((phi * out["alpha"]).sum())
+    assert abs(v1 - v0) <= 1e-12 * v0
