@@ -194,6 +194,21 @@ def batch_leg(args):
     return out
 
 
+def flume_leg(args):
+    """The 2D wave flume (2048 x 512, 5 mm cells, dt 1e-3 s) batched over 16
+    seeded wave amplitudes, mixed precision in graph mode, p_tol 1e-8."""
+    from paper_2003_08374_amd import workloads as W
+
+    log("generating the flume batch")
+    cases = [c.replace(p_maxit=500) for c in W.flume_batch(n=16, seed=7, p_tol=args.p_tol)]
+    cells = sum(c.ncells for c in cases)
+    rm = time_solver(cases, "mixed", args.steps, args.warmup, graph=True)
+    return {"workload": "wave_flume_2048x512_batch16", "samples": len(cases), "cells": cells,
+            "p_tol": args.p_tol, "value": cells / (rm["sec"] / args.steps),
+            "ms_per_step": rm["sec"] / args.steps * 1e3,
+            "p_iters_max_last": rm["stats"].get("p_iters_max")}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -207,6 +222,7 @@ def main():
     ap.add_argument("--kernel", default=None, help="kernel class for the roofline")
     ap.add_argument("--no-graph", action="store_true", help="skip the graph-mode leg")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched leg")
+    ap.add_argument("--no-flume", action="store_true", help="skip the wave-flume batch leg")
     ap.add_argument("--batch-samples", type=int, default=512)
     ap.add_argument("--coarse-sweeps", type=int, default=2)
     ap.add_argument("--fused", type=int, default=1,
@@ -279,6 +295,7 @@ def main():
                  "ms_per_step": rg["sec"] / args.steps * 1e3,
                  "p_iters_last": rg["p_iters"][-1]}
     batched = None if args.no_batch else batch_leg(args)
+    flume = None if args.no_flume else flume_leg(args)
     cpu = None if args.no_cpu else cpu_baseline()
 
     line = {
@@ -303,6 +320,7 @@ def main():
         "speedup_mixed_vs_fp64": (value / fp64["value"]) if fp64 else None,
         "graph_mode": graph,
         "batched": batched,
+        "flume_batch": flume,
     }
     if main_run["all"]:
         line["kernel_ms_one_step"] = {k: round(v[1], 3) for k, v in sorted(

@@ -141,9 +141,43 @@ __global__ void k_add_time(Geom *__restrict__ g, int ns, double dt) {
   if (s < ns) g[s].t += dt;
 }
 
+// Wave inlet values of every row at each sample's time (linear wave on
+// still water of depth d, surface d + A sin(w t)): below the surface
+// alpha = 1, u = A w cosh(k y)/sinh(k d) sin(w t) into the domain and
+// v = A w sinh(k y)/sinh(k d) cos(w t); above it air at rest.  One block per
+// sample, threads over the rows of both x faces.
+__global__ void k_wave_profile(const Geom *__restrict__ g) {
+  const Geom &G = g[blockIdx.x];
+  const int ny = G.n[1];
+  for (int r = threadIdx.x; r < 2 * ny; r += blockDim.x) {
+    const int b = r / ny, j = r % ny;
+    if (G.bck[b] != BC_WAVE) continue;
+    const double y = (j + 0.5) * G.h[1];
+    const double A = G.wA[b], w = G.wom[b], k = G.wk[b], d = G.wd[b];
+    const double st = sin(w * G.t), ct = cos(w * G.t);
+    double u = 0.0, v = 0.0, a = 0.0;
+    if (y < d + A * st) {
+      const double amp = A * w / sinh(k * d);
+      u = (b == 0 ? 1.0 : -1.0) * amp * cosh(k * y) * st;
+      v = amp * sinh(k * y) * ct;
+      a = 1.0;
+    }
+    double *o = G.wprof + ((size_t)b * ny + j) * 3;
+    o[0] = u;
+    o[1] = v;
+    o[2] = a;
+  }
+}
+
+void wave_profile(Handle *h) {
+  if (!h->has_wave) return;
+  DBS_LAUNCH(h, KC_MISC, k_wave_profile, dim3(h->ns), dim3(256), (const Geom *)h->dG);
+}
+
 void add_time(Handle *h, double dt) {
   DBS_LAUNCH(h, KC_MISC, k_add_time, dim3((h->ns + 255) / 256), dim3(256), h->dG, h->ns, dt);
   h->tnow += dt;
+  wave_profile(h);
 }
 
 void cell_stats(Handle *h) {
@@ -377,6 +411,20 @@ static int create_impl(int n, const dbs_grid *grids, const dbs_physics *phys, co
   h->flat.hbp[n] = (int)(NC / FLAT_CELLS);
   h->cell.nblk = h->cell.hbp[n];
   h->flat.nblk = h->flat.hbp[n];
+  // wave inlet tables: 2 faces x ny rows x (u, v, alpha) per sample
+  {
+    size_t np = 0;
+    for (int s = 0; s < n; s++) {
+      np += 6 * (size_t)h->hG[s].n[1];
+      if (h->hG[s].bck[0] == BC_WAVE || h->hG[s].bck[1] == BC_WAVE) h->has_wave = 1;
+    }
+    double *wp = dmalloc(h, np, rc);
+    size_t off = 0;
+    for (int s = 0; s < n && wp; s++) {
+      h->hG[s].wprof = wp + off;
+      off += 6 * (size_t)h->hG[s].n[1];
+    }
+  }
   h->cell.bp = (int *)dmalloc_bytes(h, sizeof(int) * (n + 1), rc);
   h->flat.bp = (int *)dmalloc_bytes(h, sizeof(int) * (n + 1), rc);
   h->dG = (Geom *)dmalloc_bytes(h, sizeof(Geom) * n, rc);
@@ -458,7 +506,10 @@ static int set_state_impl(Handle *h, int i, const double *alpha, const double *U
   if (!rc && F) rc = hip_check(h, hipMemcpyAsync(h->F + G.fo[0], F, nf * 8, kind, s), "copy F");
   if (!rc) rc = hip_check(h, hipStreamSynchronize(s), "set_state");
   if (rc) return rc;
-  if (!F) init_flux(h, i);
+  if (!F) {
+    wave_profile(h);
+    init_flux(h, i);
+  }
   update_closures(h, i);
   return hip_check(h, hipStreamSynchronize(h->stream), "set_state");
 }
@@ -953,8 +1004,11 @@ int dbs_set_time(dbs_handle *H, double t) {
   if (rc) return rc;
   for (auto &G : h->hG) G.t = t;
   h->tnow = t;
-  return hip_check(h, hipMemcpy(h->dG, h->hG.data(), sizeof(Geom) * h->ns,
-                                hipMemcpyHostToDevice), "set_time");
+  rc = hip_check(h, hipMemcpy(h->dG, h->hG.data(), sizeof(Geom) * h->ns,
+                              hipMemcpyHostToDevice), "set_time");
+  if (!rc) wave_profile(h);
+  if (!rc) rc = hip_check(h, hipStreamSynchronize(h->stream), "set_time");
+  return rc;
 }
 
 int dbs_get_stats(dbs_handle *H, dbs_stats *out) { return dbs_batch_get_stats(H, 0, out); }

@@ -50,6 +50,7 @@ struct Geom {
   // still-water depth of a linear (Airy) wave
   double wA[2], wom[2], wk[2], wd[2];
   double t;         // time of the boundary values: the end of the current step
+  double *wprof;    // wave inlet values at time t: [face 0|1][row j][u, v, alpha]
 };
 
 // ---------------------------------------------------------------- indexing
@@ -197,47 +198,30 @@ __device__ inline void closures(const Phys &Ph, double a, double &ml, double &mg
 
 __device__ __forceinline__ bool is_inlet(int kind) { return kind == BC_INLET || kind == BC_WAVE; }
 
-// Velocity and alpha of inlet face b at height y.  A wave inlet (x faces)
-// carries a linear wave on still water of depth d: surface A sin(w t); below
-// it alpha = 1 and the orbital velocity u = A w cosh(k y)/sinh(k d) sin(w t)
-// into the domain, v = A w sinh(k y)/sinh(k d) cos(w t); above it air at rest.
-__device__ inline void inlet_state(const Geom &G, int b, double y, double U[3], double &alpha) {
-  if (G.bck[b] != BC_WAVE) {
-    for (int d = 0; d < 3; d++) U[d] = G.bcU[b][d];
-    alpha = G.bca[b];
-    return;
-  }
-  const double A = G.wA[b], w = G.wom[b], k = G.wk[b], dep = G.wd[b];
-  const double st = sin(w * G.t), ct = cos(w * G.t);
-  U[0] = U[1] = U[2] = 0.0;
-  alpha = 0.0;
-  if (y < dep + A * st) {
-    const double ish = 1.0 / sinh(k * dep);
-    U[0] = (b == 0 ? 1.0 : -1.0) * A * w * cosh(k * y) * ish * st;
-    U[1] = A * w * sinh(k * y) * ish * ct;
-    alpha = 1.0;
-  }
+// Velocity component comp and alpha of inlet face b in row j.  Wave inlet
+// values are tabulated once per step (wave_profile), so the heavy kernels
+// only read them.
+__device__ __forceinline__ double inlet_u(const Geom &G, int b, int j, int comp) {
+  if (G.bck[b] != BC_WAVE) return G.bcU[b][comp];
+  if (comp == 2) return 0.0;  // the wave moves in the x-y plane
+  return G.wprof[((size_t)b * G.n[1] + j) * 3 + comp];
 }
 
-// boundary alpha at a face of height y: inlet value; wave or outlet value
-// on inflow; else the cell value
-__device__ __forceinline__ double bnd_alpha(const Geom &G, int b, double y, double a_cell,
+__device__ __forceinline__ double inlet_alpha(const Geom &G, int b, int j) {
+  if (G.bck[b] != BC_WAVE) return G.bca[b];
+  return G.wprof[((size_t)b * G.n[1] + j) * 3 + 2];
+}
+
+// boundary alpha at a face in row j: inlet value; wave or outlet value on
+// inflow; else the cell value
+__device__ __forceinline__ double bnd_alpha(const Geom &G, int b, int j, double a_cell,
                                             double Fb) {
   const int kind = G.bck[b];
   const double so = (b & 1) ? 1.0 : -1.0;
   if (kind == BC_INLET) return G.bca[b];
-  if (kind == BC_WAVE && so * Fb < 0.0) {
-    double U[3], a;
-    inlet_state(G, b, y, U, a);
-    return a;
-  }
+  if (kind == BC_WAVE && so * Fb < 0.0) return inlet_alpha(G, b, j);
   if (kind == BC_OUTLET && so * Fb < 0.0) return G.bca[b];
   return a_cell;
-}
-
-// height of the faces of cell P normal to x or z (cell-centre y)
-__device__ __forceinline__ double y_of(const Geom &G, const Cell &P) {
-  return (P.j + 0.5) * G.h[1];
 }
 
 // ---------------------------------------------------------- reductions

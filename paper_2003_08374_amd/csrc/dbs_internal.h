@@ -150,6 +150,7 @@ struct Handle {
 
   std::vector<dbs_stats> st;  // per sample
   double tnow = 0.0;          // time reached by the samples
+  int has_wave = 0;           // some sample has a wave inlet
 
   // graph mode
   int graph_mode = 0;

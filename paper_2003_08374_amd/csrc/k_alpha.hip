@@ -37,7 +37,7 @@ __device__ inline void grad_alpha(const Geom &G, const AlphaArgs &X, const Cell 
     double fv[2];
     for (int s = 0; s < 2; s++) {
       if (on_boundary(G, P, a, s))
-        fv[s] = bnd_alpha(G, 2 * a + s, y_of(G, P), aP, X.F[face_of(G, P, a, s)]);
+        fv[s] = bnd_alpha(G, 2 * a + s, P.j, aP, X.F[face_of(G, P, a, s)]);
       else
         fv[s] = 0.5 * (aP + X.alpha[P.c + (s ? 1 : -1) * stride_of(G, a)]);
     }
@@ -120,7 +120,7 @@ __device__ __forceinline__ double low_order_flux(const Geom &G, const double *__
                                                  const double *__restrict__ F, const Cell &P,
                                                  int a, int s, int f, bool bnd) {
   double Ff = F[f];
-  if (bnd) return Ff * bnd_alpha(G, 2 * a + s, y_of(G, P), alpha[P.c], Ff);
+  if (bnd) return Ff * bnd_alpha(G, 2 * a + s, P.j, alpha[P.c], Ff);
   int nb = P.c + (s ? 1 : -1) * stride_of(G, a);
   int own = s ? P.c : nb, nbr = s ? nb : P.c;
   return Ff * (Ff >= 0.0 ? alpha[own] : alpha[nbr]);
@@ -144,7 +144,7 @@ __global__ void __launch_bounds__(NTHREADS) k_alpha_bounds(Segs SG, const double
         amax = fmax(amax, an);
         amin = fmin(amin, an);
       } else if (so * F[f] < 0.0) {
-        double ab = bnd_alpha(G, 2 * a + s, y_of(G, P), aP, F[f]);
+        double ab = bnd_alpha(G, 2 * a + s, P.j, aP, F[f]);
         amax = fmax(amax, ab);
         amin = fmin(amin, ab);
       }
@@ -280,11 +280,7 @@ __global__ void __launch_bounds__(NTHREADS) k_init_flux(Segs SG, const double *_
         v = 0.5 * (Ua[P.c - stride_of(G, a)] + Ua[P.c]) * G.area[a];
       } else {
         int kind = G.bck[2 * a + s];
-        if (is_inlet(kind)) {
-          double Ub[3], ab;
-          inlet_state(G, 2 * a + s, y_of(G, P), Ub, ab);
-          v = Ub[a] * G.area[a];
-        }
+        if (is_inlet(kind)) v = inlet_u(G, 2 * a + s, P.j, a) * G.area[a];
         else if (kind == BC_OUTLET) v = Ua[P.c] * G.area[a];
       }
       F[f] = v;

@@ -92,9 +92,7 @@ __device__ inline double reconstruct_axis(const Geom &G, const Phys &Ph, const M
     if (!ff[s]) continue;
     if (hbya) {
       const int b = 2 * a + s;
-      double Ub[3] = {0.0, 0.0, 0.0}, ab;
-      if (is_inlet(G.bck[b])) inlet_state(G, b, y_of(G, P), Ub, ab);
-      const double Fb = Ub[a] * G.area[a];
+      const double Fb = is_inlet(G.bck[b]) ? inlet_u(G, b, P.j, a) * G.area[a] : 0.0;
       q[s] = (Fb - hbya[(size_t)a * G.vs + P.c] * G.area[a]) / M.rAU[P.c];
     } else {
       q[s] = ff[1 - s] ? 0.0 : q[1 - s];
@@ -135,9 +133,7 @@ __device__ inline FaceCoef mom_face(const Geom &G, const Phys &Ph, const MomArgs
   if (G.bck[b] == BC_WALL) {
     r.diag = mu_of(Ph, M.alpha[P.c]) * G.area[a] * d2 * G.iV;
   } else if (is_inlet(G.bck[b])) {
-    double Ub[3], ab;
-    inlet_state(G, b, y_of(G, P), Ub, ab);
-    const double vis = mu_of(Ph, ab) * G.area[a] * d2 * G.iV;
+    const double vis = mu_of(Ph, inlet_alpha(G, b, P.j)) * G.area[a] * d2 * G.iV;
     if (out >= 0.0) r.diag = out * conv;
     else r.src = -out * conv;
     r.diag += vis;
@@ -162,9 +158,7 @@ __device__ inline double dU(const Geom &G, const double *__restrict__ U, int Qc,
       if (G.bck[b] == BC_WALL) {
         fv[s] = 0.0;
       } else if (is_inlet(G.bck[b])) {
-        double Ub[3], ab;
-        inlet_state(G, b, (Qco[1] + 0.5) * G.h[1], Ub, ab);
-        fv[s] = Ub[comp];
+        fv[s] = inlet_u(G, b, Qco[1], comp);
       } else {
         fv[s] = uq;
       }
@@ -197,9 +191,9 @@ __global__ void __launch_bounds__(NTHREADS) k_mom_assemble(Segs SG, Phys Ph, Mom
       FaceCoef fc = mom_face(G, Ph, M, P, a, s);
       aP += fc.diag;
       if (fc.src != 0.0) {
-        double Ub[3], ab;
-        inlet_state(G, 2 * a + s, y_of(G, P), Ub, ab);
-        for (int d = 0; d < 3; d++) S[d] += fc.src * Ub[d];
+        S[0] += fc.src * inlet_u(G, 2 * a + s, P.j, 0);
+        S[1] += fc.src * inlet_u(G, 2 * a + s, P.j, 1);
+        S[2] += fc.src * inlet_u(G, 2 * a + s, P.j, 2);
       }
     }
   }
@@ -220,13 +214,7 @@ __global__ void __launch_bounds__(NTHREADS) k_mom_assemble(Segs SG, Phys Ph, Mom
           for (int i = 0; i < 3; i++) gN[i] = dU(G, U, nb, nco, a, i);
         } else {
           const int b = 2 * a + s;
-          if (is_inlet(G.bck[b])) {
-            double Ub[3], ab;
-            inlet_state(G, b, y_of(G, P), Ub, ab);
-            muf = mu_of(Ph, ab);
-          } else {
-            muf = mu_of(Ph, an);
-          }
+          muf = is_inlet(G.bck[b]) ? mu_of(Ph, inlet_alpha(G, b, P.j)) : mu_of(Ph, an);
         }
         for (int i = 0; i < 3; i++) {
           const double gP = dU(G, U, c, P.co, a, i);
@@ -274,11 +262,7 @@ __device__ inline double phi_hbya(const Geom &G, const Phys &Ph, const MomArgs &
                                   const double *__restrict__ H, const Cell &P, int a, int s) {
   if (on_boundary(G, P, a, s)) {
     const int b = 2 * a + s;
-    if (is_inlet(G.bck[b])) {
-      double Ub[3], ab;
-      inlet_state(G, b, y_of(G, P), Ub, ab);
-      return Ub[a] * G.area[a];
-    }
+    if (is_inlet(G.bck[b])) return inlet_u(G, b, P.j, a) * G.area[a];
     if (G.bck[b] == BC_OUTLET) return H[(size_t)a * G.vs + P.c] * G.area[a];
     return 0.0;
   }
