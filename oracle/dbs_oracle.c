@@ -826,6 +826,28 @@ int dbso_init_flux(const dbso_case *cs, const double *Ux, const double *Uy,
   return 0;
 }
 
+int dbso_inlet_values(const dbso_case *cs, int b, double t, double *out) {
+  if (b < 0 || b > 5 || !is_inlet(cs->bc_kind[b])) return -1;
+  mesh_t m;
+  if (build_mesh(cs, &m)) { free_mesh(&m); return -1; }
+  m.t = t;
+  int n = 0, off = 0;
+  for (int a = 0; a < 3; a++) {
+    for (int l = 0; l < m.nfa[a]; l++) {
+      const face_t *Fc = &m.f[off + l];
+      if (Fc->bnd != b) continue;
+      double Ub[3], ab;
+      inlet_face(&m, Fc, Ub, &ab);
+      for (int d = 0; d < 3; d++) out[4 * n + d] = Ub[d];
+      out[4 * n + 3] = ab;
+      n++;
+    }
+    off += m.nfa[a];
+  }
+  free_mesh(&m);
+  return n;
+}
+
 int dbso_pressure_apply(const dbso_case *cs, const double *rAU, const double *x,
                         double *y) {
   mesh_t m;

@@ -90,6 +90,12 @@ void dbso_closures(const dbso_case *cs, double alpha, double *krl, double *krg,
 int dbso_init_flux(const dbso_case *cs, const double *Ux, const double *Uy,
                    const double *Uz, double *Fx, double *Fy, double *Fz);
 
+/* Values an inlet boundary b (x-, x+, y-, ... = 0..5) prescribes at time t:
+   out[4*l + 0..2] = U, out[4*l + 3] = alpha for the l-th face of that side
+   (faces in the order of the side's face array).  Returns the face count, or
+   -1 when b is not an inlet. */
+int dbso_inlet_values(const dbso_case *cs, int b, double t, double *out);
+
 /* Advance nsteps PISO steps in place.  p (out) may be NULL.  Returns 0, or a
    negative code: -1 bad input, -4 pressure solve did not converge. */
 int dbso_step(const dbso_case *cs, const double *phi, const double *kinv,

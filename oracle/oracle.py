@@ -94,6 +94,8 @@ def lib():
         L.dbso_closures.restype = None
         L.dbso_init_flux.argtypes = [C.POINTER(OracleCase)] + [_DP] * 6
         L.dbso_init_flux.restype = C.c_int
+        L.dbso_inlet_values.argtypes = [C.POINTER(OracleCase), C.c_int, C.c_double, _DP]
+        L.dbso_inlet_values.restype = C.c_int
         L.dbso_step.argtypes = ([C.POINTER(OracleCase)] + [_DP] * 11 +
                                 [C.c_int, C.POINTER(OracleInfo), C.POINTER(OracleTrace)])
         L.dbso_step.restype = C.c_int
@@ -172,6 +174,19 @@ def init_flux(cs, U: np.ndarray):
     if rc:
         raise ValueError(f"dbso_init_flux failed ({rc})")
     return tuple(F)
+
+
+def inlet_values(cs, b: int, t: float) -> np.ndarray:
+    """(n_faces, 4) array of the U and alpha that inlet side b prescribes at
+    time t, faces in the order of that side's face array."""
+    o = make_case(cs)
+    nx, ny, nz = cs.shape
+    side = (ny * nz, nx * nz, nx * ny)[b // 2]
+    out = np.zeros((side, 4))
+    n = lib().dbso_inlet_values(C.byref(o), int(b), float(t), _ptr(out))
+    if n != side:
+        raise ValueError(f"dbso_inlet_values failed ({n})")
+    return out
 
 
 def initial_state(cs) -> dict:

@@ -582,3 +582,34 @@ def test_flume_at_zero_amplitude_is_at_rest_and_conserves_water():
     v0 = float((phi * st["alpha"]).sum())
     v1 = float((phi * out["alpha"]).sum())
     assert abs(v1 - v0) <= 1e-12 * v0
+
+
+@pytest.mark.parametrize("phase", [0.1, 0.4, 0.9])
+def test_wave_inlet_vertical_velocity_from_continuity(phase):
+    """The vertical inlet velocity of the linear wave is fixed by the
+    horizontal one: the wave travels into the domain, u(x, t) = f(t - x/c)
+    with c = w/k, so incompressibility gives dv/dy = -du/dx = (k/w) du/dt,
+    with v = 0 on the bed.  The oracle's u (pinned by the flux test) is
+    differenced in time, its v in y; α is 1 below the surface, 0 above."""
+    from scipy.optimize import brentq
+    c = _small_flume(nx=4, ny=300, h=1e-3)
+    A, T, d = c.bc[0]["wave"]
+    w = 2 * np.pi / T
+    k = brentq(lambda q: w * w - W.GRAVITY * q * np.tanh(q * d), 1e-9, 1e4)
+    h = c.h[0]
+    y = (np.arange(c.shape[1]) + 0.5) * h
+    t, eps = phase * T, 1e-5 * T
+    now = O.inlet_values(c, 0, t)
+    dudt = (O.inlet_values(c, 0, t + eps)[:, 0] - O.inlet_values(c, 0, t - eps)[:, 0]) / (2 * eps)
+    wet = y < d + A * np.sin(w * t)
+    assert np.array_equal(now[:, 3], np.where(wet, 1.0, 0.0))
+    assert np.all(now[~wet, :3] == 0.0) and np.all(now[:, 2] == 0.0)
+    deep = y < d - A  # submerged at every phase, so du/dt exists there
+    v = now[deep, 1]
+    lhs = np.diff(v) / h
+    rhs = (k / w) * 0.5 * (dudt[deep][1:] + dudt[deep][:-1])
+    scale = np.abs(rhs).max()
+    assert scale > 0
+    assert np.abs(lhs - rhs).max() <= 1e-4 * scale
+    # v vanishes on the bed: v(y0) = y0 dv/dy + O(h^3)
+    assert abs(v[0] - y[0] * (k / w) * dudt[0]) <= 1e-4 * np.abs(v).max()
