@@ -201,6 +201,9 @@ int dbs_batch_set_state_dev(dbs_handle *h, int i, const double *alpha, const dou
 int dbs_batch_get_state_dev(dbs_handle *h, int i, double *alpha, double *U, double *p_rgh,
                             double *p, double *F, void *stream);
 int dbs_batch_get_stats(dbs_handle *h, int i, dbs_stats *out);
+/* Advance every sample of the batch nsteps time steps: the same call as
+   dbs_step, under the batch's name. */
+int dbs_batch_step(dbs_handle *h, int nsteps);
 
 /* Graph mode (on != 0): each step is replayed from a captured HIP graph.
    The first step after switching runs eagerly and sets a PCG iteration

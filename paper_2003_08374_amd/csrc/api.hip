@@ -884,6 +884,8 @@ int dbs_step(dbs_handle *H, int nsteps) {
   return finish_steps(h, rc);
 }
 
+int dbs_batch_step(dbs_handle *H, int nsteps) { return dbs_step(H, nsteps); }
+
 int dbs_set_graph(dbs_handle *H, int on) {
   if (!H) return DBS_EINVAL;
   Handle *h = &H->h;

@@ -27,7 +27,7 @@ EXPORTS = (
     "dbs_debug_pressure_solve", "dbs_debug_step_trace",
     "dbs_batch_create", "dbs_batch_size", "dbs_batch_set_static", "dbs_batch_set_state",
     "dbs_batch_get_state", "dbs_batch_set_state_dev", "dbs_batch_get_state_dev",
-    "dbs_batch_get_stats", "dbs_set_graph", "dbs_autotune", "dbs_set_tuning", "dbs_set_time",
+    "dbs_batch_get_stats", "dbs_batch_step", "dbs_set_graph", "dbs_autotune", "dbs_set_tuning", "dbs_set_time",
 )
 
 
@@ -89,6 +89,7 @@ def lib():
         L.dbs_set_static.argtypes = [H, _DP, _DP]
         L.dbs_set_state.argtypes = [H, _DP, _DP, _DP, _DP]
         L.dbs_step.argtypes = [H, C.c_int]
+        L.dbs_batch_step.argtypes = [H, C.c_int]
         L.dbs_get_state.argtypes = [H, _DP, _DP, _DP, _DP, _DP]
         L.dbs_set_state_dev.argtypes = [H, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                         C.c_void_p]
@@ -196,8 +197,10 @@ class _Handle:
             raise DBSError(rc, msg)
         return rc
 
+    _STEP = "dbs_step"
+
     def step(self, n=1, check=True):
-        rc = lib().dbs_step(self.h, int(n))
+        rc = getattr(lib(), self._STEP)(self.h, int(n))
         if check:
             self._check(rc)
         return rc
@@ -378,6 +381,7 @@ class BatchSolver(_Handle):
 
     The cases share fluids, closures, gravity, dt and solver controls; each
     has its own mesh, boundary values, porosity, permeability and state."""
+    _STEP = "dbs_batch_step"
 
     def __init__(self, cases, precision=None, p_tol=None, mg=None, max_courant=0.0,
                  bounds_tol=0.0):
