@@ -1059,6 +1059,24 @@ template <typename R> struct Vec16;
 template <> struct Vec16<float> { using T = float4; using T2 = float2; };
 template <> struct Vec16<double> { using T = double2; using T2 = double2; };
 
+// component access and arithmetic on the 16-byte vectors (indices are
+// compile-time constants after unrolling, so these stay in registers)
+template <typename VT> __device__ __forceinline__ VT vzero();
+template <> __device__ __forceinline__ float4 vzero<float4>() { return make_float4(0.f, 0.f, 0.f, 0.f); }
+template <> __device__ __forceinline__ double2 vzero<double2>() { return make_double2(0.0, 0.0); }
+__device__ __forceinline__ void vset(float4 &v, int u, float a) {
+  if (u == 0) v.x = a; else if (u == 1) v.y = a; else if (u == 2) v.z = a; else v.w = a;
+}
+__device__ __forceinline__ void vset(double2 &v, int u, double a) {
+  if (u == 0) v.x = a; else v.y = a;
+}
+__device__ __forceinline__ float4 vadd(float4 a, float4 b) {
+  return make_float4(a.x + b.x, a.y + b.y, a.z + b.z, a.w + b.w);
+}
+__device__ __forceinline__ double2 vadd(double2 a, double2 b) {
+  return make_double2(a.x + b.x, a.y + b.y);
+}
+
 // plane geometry of the fused sweep for element type R: the x-ring is one
 // 16-byte vector wide (at least 2 cells) so rows start on a vector boundary
 template <typename R>
@@ -1124,6 +1142,8 @@ __global__ void __launch_bounds__(NT2) k_sweep25(OpB<R> LB, SH S, const B *__res
   constexpr int VEC = PL::VEC, NX = PL::NX, FXR = PL::FXR;
   __shared__ __align__(16) R sX[3 * NX];   // old x, planes k-1, k, k+1 (slot k mod 3)
   __shared__ __align__(16) R sR[3 * NX];   // rAU, planes k-1, k, k+1 (slot k mod 3)
+  __shared__ __align__(16) R sB[3 * NX];   // right-hand side, planes k-1, k, k+1
+  static_assert(std::is_same<R, B>::value, "the right-hand side is staged as R");
   __shared__ R sA[2 * NX1];                // new A values, planes k-1, k (slot k mod 2)
   int g, s, lb;
   if (!locate(S, mask, g, s, lb)) return;
@@ -1146,44 +1166,46 @@ __global__ void __launch_bounds__(NT2) k_sweep25(OpB<R> LB, SH S, const B *__res
     return i >= 0 && i < n0 && jj >= 0 && jj < n1 && k >= 0 && k < n2;
   };
   auto xs = [](int k) { return (k + 3) % 3; };
-  VT px[PL::MV], pr[PL::MV];
-  // one vector of x (old iterate) and rAU at element e of plane k
+  // Registers of the plane in flight: x, rAU and (SW_PROLONG) the coarse
+  // correction, kept apart from x until the LDS store so that nothing reads
+  // a loaded value before the next plane step (the loads stay in flight
+  // while the current plane is relaxed).
+  VT px[PL::MV], pr[PL::MV], pb[PL::MV], pc[PL::MV];
   auto load_planes = [&](int k) {
 #pragma unroll
     for (int m = 0; m < PL::MV; m++) {
       const int e = t + m * NT2;
-      R vx[VEC], vr[VEC];
-#pragma unroll
-      for (int u = 0; u < VEC; u++) vx[u] = vr[u] = (R)0;
-      if (e < PL::NV) {
-        const int ia = x0 - PL::RX + (e % (FXR / VEC)) * VEC, jj = y0 + e / (FXR / VEC) - 2;
-        if (jj >= 0 && jj < n1 && k >= 0 && k < n2 && ia + VEC > 0 && ia < n0) {
-          const int c = ia + n0 * (jj + n1 * k);
-          if (vec_ok && ia >= 0) {
-            const VT w = *reinterpret_cast<const VT *>(rA + c);
-            memcpy(vr, &w, sizeof(w));
-            if (MODE != SW_ZERO) {
-              const VT v = *reinterpret_cast<const VT *>(xin + c);
-              memcpy(vx, &v, sizeof(v));
-            }
-          } else {
-#pragma unroll
-            for (int u = 0; u < VEC; u++)
-              if (ia + u >= 0 && ia + u < n0) {
-                vr[u] = rA[c + u];
-                if (MODE != SW_ZERO) vx[u] = xin[c + u];
-              }
-          }
-          if (MODE == SW_PROLONG && xcs) {
-#pragma unroll
-            for (int u = 0; u < VEC; u++)
-              if (ia + u >= 0 && ia + u < n0)
-                vx[u] += xcs[((ia + u) >> 1) + cn0 * ((jj >> 1) + cn1 * (k >> 1))];
-          }
+      VT vx = vzero<VT>(), vr = vzero<VT>(), vb = vzero<VT>(), vc = vzero<VT>();
+      const int ia = x0 - PL::RX + (e % (FXR / VEC)) * VEC, jj = y0 + e / (FXR / VEC) - 2;
+      const bool in = e < PL::NV && jj >= 0 && jj < n1 && k >= 0 && k < n2 && ia + VEC > 0 &&
+                      ia < n0;
+      const int c = ia + n0 * (jj + n1 * k);
+      if (vec_ok) {
+        // n0 and x0 are multiples of VEC: a vector is wholly inside or outside
+        if (in) {
+          vr = *reinterpret_cast<const VT *>(rA + c);
+          vb = *reinterpret_cast<const VT *>(b + c);
+          if (MODE != SW_ZERO) vx = *reinterpret_cast<const VT *>(xin + c);
         }
+      } else if (in) {
+#pragma unroll
+        for (int u = 0; u < VEC; u++)
+          if (ia + u >= 0 && ia + u < n0) {
+            vset(vr, u, rA[c + u]);
+            vset(vb, u, b[c + u]);
+            if (MODE != SW_ZERO) vset(vx, u, xin[c + u]);
+          }
       }
-      memcpy(&px[m], vx, sizeof(VT));
-      memcpy(&pr[m], vr, sizeof(VT));
+      if (MODE == SW_PROLONG && xcs && in) {
+#pragma unroll
+        for (int u = 0; u < VEC; u++)
+          if (ia + u >= 0 && ia + u < n0)
+            vset(vc, u, xcs[((ia + u) >> 1) + cn0 * ((jj >> 1) + cn1 * (k >> 1))]);
+      }
+      px[m] = vx;
+      pr[m] = vr;
+      pb[m] = vb;
+      if (MODE == SW_PROLONG) pc[m] = vc;
     }
   };
   auto store_planes = [&](int k) {
@@ -1191,27 +1213,21 @@ __global__ void __launch_bounds__(NT2) k_sweep25(OpB<R> LB, SH S, const B *__res
     for (int m = 0; m < PL::MV; m++) {
       const int e = t + m * NT2;
       if (e < PL::NV) {
-        if (MODE != SW_ZERO) *reinterpret_cast<VT *>(sX + xs(k) * NX + e * VEC) = px[m];
+        if (MODE == SW_PROLONG)
+          *reinterpret_cast<VT *>(sX + xs(k) * NX + e * VEC) = vadd(px[m], pc[m]);
+        else if (MODE != SW_ZERO)
+          *reinterpret_cast<VT *>(sX + xs(k) * NX + e * VEC) = px[m];
         *reinterpret_cast<VT *>(sR + xs(k) * NX + e * VEC) = pr[m];
+        *reinterpret_cast<VT *>(sB + xs(k) * NX + e * VEC) = pb[m];
       }
     }
   };
-  // b of the own pair and of the ring cell (if any) of plane k
   const bool ringer = t < NRING;
-  auto load_b = [&](int k, P2<R> &own, R &ring) {
-    own.v0 = inside(i0, j, k) ? (R)b[i0 + n0 * (j + n1 * k)] : (R)0;
-    own.v1 = inside(i0 + 1, j, k) ? (R)b[i0 + 1 + n0 * (j + n1 * k)] : (R)0;
-    ring = (R)0;
-    if (ringer) {
-      int lx, ly;
-      ring_cell(t, x0, y0, k, colA, lx, ly);
-      if (inside(x0 + lx, y0 + ly, k)) ring = (R)b[x0 + lx + n0 * (y0 + ly + n1 * k)];
-    }
-  };
   // new A value at (lx, ly) of plane k from LDS neighbours
-  auto relax_a = [&](int lx, int ly, int k, R bb) -> R {
+  auto relax_a = [&](int lx, int ly, int k) -> R {
     const int i = x0 + lx, jj = y0 + ly;
     if (!inside(i, jj, k)) return (R)0;
+    const R bb = sB[xs(k) * NX + PL::at(lx, ly)];
     const R *Xm = sX + xs(k - 1) * NX, *Xc = sX + xs(k) * NX, *Xp = sX + xs(k + 1) * NX;
     const R *Rm = sR + xs(k - 1) * NX, *Rc = sR + xs(k) * NX, *Rp = sR + xs(k + 1) * NX;
     const int c2 = PL::at(lx, ly);
@@ -1223,26 +1239,19 @@ __global__ void __launch_bounds__(NT2) k_sweep25(OpB<R> LB, SH S, const B *__res
                   T[3] * Xc[c2 + FXR] + T[4] * Xm[c2] + T[5] * Xp[c2];
     return D > (R)0 ? (bb + off) * sw_rcp(D) : (R)0;
   };
-  // prologue: x and rAU of planes k0-2, k0-1 in LDS, plane k0 in registers;
-  // b of plane k0-1 in registers
+  // prologue: planes k0-2, k0-1 in LDS, plane k0 in registers
   for (int k = k0 - 2; k <= k0 - 1; k++) {
     load_planes(k);
     store_planes(k);
   }
   load_planes(k0);
-  P2<R> b_prev = {(R)0, (R)0}, b_cur, b_next = {(R)0, (R)0};
-  R br_cur, br_next = (R)0;
-  load_b(k0 - 1, b_cur, br_cur);
   P2<R> r_m2 = {(R)0, (R)0}, r_m1 = {(R)0, (R)0}, r_0;
   R a_m2 = (R)0, a_m1 = (R)0, a_0;
   for (int k = k0 - 1; k <= k1; k++) {
     store_planes(k + 1);  // loaded one step earlier; its slot (plane k-2) is free
     __syncthreads();
     const bool more = k + 1 <= k1;
-    if (more) {
-      load_planes(k + 2);
-      load_b(k + 1, b_next, br_next);
-    }
+    if (more) load_planes(k + 2);
     const int offA = ((j + k) & 1) == colA ? 0 : 1;  // x0 and 2 tx are even
     // own column: rAU of plane k; rAU around the own B cell of plane k-1
     const R *Rk = sR + xs(k) * NX;
@@ -1252,14 +1261,16 @@ __global__ void __launch_bounds__(NT2) k_sweep25(OpB<R> LB, SH S, const B *__res
     const int cb = PL::at(lxB, ty);
     const R rbc = Rb[cb], rbxm = Rb[cb - 1], rbxp = Rb[cb + 1], rbym = Rb[cb - FXR],
             rbyp = Rb[cb + FXR];
+    // (read before the barrier: the next plane step overwrites plane k-1's slot)
+    const R bB = sB[xs(k - 1) * NX + cb];
     // A cells of plane k: own, then one ring cell
     R *An = sA + (k & 1) * NX1;
-    a_0 = j < n1 ? relax_a(2 * tx + offA, ty, k, b_cur.get(offA)) : (R)0;
+    a_0 = j < n1 ? relax_a(2 * tx + offA, ty, k) : (R)0;
     An[I1(2 * tx + offA, ty)] = a_0;
     if (ringer) {
       int lx, ly;
       ring_cell(t, x0, y0, k, colA, lx, ly);
-      An[I1(lx, ly)] = relax_a(lx, ly, k, br_cur);
+      An[I1(lx, ly)] = relax_a(lx, ly, k);
     }
     __syncthreads();
     // B cell of plane k-1; write both colours of plane k-1
@@ -1274,7 +1285,7 @@ __global__ void __launch_bounds__(NT2) k_sweep25(OpB<R> LB, SH S, const B *__res
         coef7(L, iB, j, kb, rbc, rbxm, rbxp, rbym, rbyp, r_m2.get(offA), r_0.get(offA), T, D);
         const R off = T[0] * Ac[c1 - 1] + T[1] * Ac[c1 + 1] + T[2] * Ac[c1 - FX1] +
                       T[3] * Ac[c1 + FX1] + T[4] * a_m2 + T[5] * a_0;
-        vB = D > (R)0 ? (b_prev.get(offA) + off) * sw_rcp(D) : (R)0;
+        vB = D > (R)0 ? (bB + off) * sw_rcp(D) : (R)0;
       }
       // the pair in memory order: offset 0 first
       const R v0 = offA == 0 ? vB : a_m1, v1 = offA == 0 ? a_m1 : vB;
@@ -1299,9 +1310,6 @@ __global__ void __launch_bounds__(NT2) k_sweep25(OpB<R> LB, SH S, const B *__res
     r_m1 = r_0;
     a_m2 = a_m1;
     a_m1 = a_0;
-    b_prev = b_cur;
-    b_cur = b_next;
-    br_cur = br_next;
   }
 }
 
