@@ -799,6 +799,147 @@ struct P2 {
   }
 };
 
+template <typename R> struct Vec16;
+template <> struct Vec16<float> { using T = float4; using T2 = float2; };
+template <> struct Vec16<double> { using T = double2; using T2 = double2; };
+
+// component access and arithmetic on the 16-byte vectors (indices are
+// compile-time constants after unrolling, so these stay in registers)
+template <typename VT> __device__ __forceinline__ VT vzero();
+template <> __device__ __forceinline__ float4 vzero<float4>() { return make_float4(0.f, 0.f, 0.f, 0.f); }
+template <> __device__ __forceinline__ double2 vzero<double2>() { return make_double2(0.0, 0.0); }
+__device__ __forceinline__ void vset(float4 &v, int u, float a) {
+  if (u == 0) v.x = a; else if (u == 1) v.y = a; else if (u == 2) v.z = a; else v.w = a;
+}
+__device__ __forceinline__ void vset(double2 &v, int u, double a) {
+  if (u == 0) v.x = a; else v.y = a;
+}
+// packed parents (one per two cells) spread over the vector's cells
+__device__ __forceinline__ float4 vspread(float4 a) { return make_float4(a.x, a.x, a.y, a.y); }
+__device__ __forceinline__ double2 vspread(double2 a) { return make_double2(a.x, a.x); }
+__device__ __forceinline__ float4 vadd(float4 a, float4 b) {
+  return make_float4(a.x + b.x, a.y + b.y, a.z + b.z, a.w + b.w);
+}
+__device__ __forceinline__ double2 vadd(double2 a, double2 b) {
+  return make_double2(a.x + b.x, a.y + b.y);
+}
+
+// 1/D for the smoother: the hardware reciprocal in FP32 (the V-cycle is a
+// preconditioner; the outer FP64 CG is unaffected), exact in FP64
+__device__ __forceinline__ float sw_rcp(float d) { return __builtin_amdgcn_rcpf(d); }
+__device__ __forceinline__ double sw_rcp(double d) { return 1.0 / d; }
+
+// row of the fine operator at (i,j,k) from the seven rAU values around it
+template <typename R>
+__device__ __forceinline__ void coef7(const Op<R> &L, int i, int j, int k, R rc, R rxm, R rxp,
+                                      R rym, R ryp, R rzm, R rzp, R T[6], R &D) {
+  const R h = (R)0.5;
+  T[0] = i > 0 ? h * (rc + rxm) * L.c[0] : (R)0;
+  T[1] = i + 1 < L.n0 ? h * (rc + rxp) * L.c[0] : (R)0;
+  T[2] = j > 0 ? h * (rc + rym) * L.c[1] : (R)0;
+  T[3] = j + 1 < L.n1 ? h * (rc + ryp) * L.c[1] : (R)0;
+  T[4] = k > 0 ? h * (rc + rzm) * L.c[2] : (R)0;
+  T[5] = k + 1 < L.n2 ? h * (rc + rzp) * L.c[2] : (R)0;
+  const R db = (i == 0 ? L.ob[0] : (R)0) + (i + 1 == L.n0 ? L.ob[1] : (R)0) +
+               (j == 0 ? L.ob[2] : (R)0) + (j + 1 == L.n1 ? L.ob[3] : (R)0) +
+               (k == 0 ? L.ob[4] : (R)0) + (k + 1 == L.n2 ? L.ob[5] : (R)0);
+  D = T[0] + T[1] + T[2] + T[3] + T[4] + T[5] + rc * db;
+}
+
+// Planes of a W x TY2 tile staged in LDS with a ring of one 16-byte vector
+// in x and RY rows in y (zero outside the mesh).  Thread t loads vectors t,
+// t + NT2, ... of a plane into registers one plane step before it stores
+// them, so the loads are in flight while the current plane is computed.
+// With four slots per array one barrier per plane suffices: the slot
+// written at plane k+1 held plane k-3, which no thread still reads.
+template <typename R, int W, int RY>
+struct PlG {
+  static constexpr int VEC = 16 / sizeof(R);
+  static constexpr int RX = VEC;                // x-ring width (cells)
+  static constexpr int FXR = W + 2 * RX;        // row stride
+  static constexpr int NX = FXR * (TY2 + 2 * RY);  // elements per plane
+  static constexpr int NV = NX / VEC;           // vectors per plane
+  static constexpr int MV = (NV + NT2 - 1) / NT2;
+  __device__ static constexpr int at(int lx, int ly) { return (ly + RY) * FXR + lx + RX; }
+};
+template <typename R, int W>
+using Pl1 = PlG<R, W, 1>;
+
+template <int NS>
+__device__ __forceinline__ int slot_of(int k) { return (k + NS) % NS; }  // k >= -NS
+
+// vector handled by thread t in pass m of a plane of NV vectors: threads past
+// the end repeat a vector of the last pass (same value to the same place),
+// so every thread stores unconditionally and no load is left pending on a
+// path that skipped its store
+template <int NV, int MV>
+__device__ __forceinline__ int pl_vec(int t, int m) {
+  static_assert(2 * NV >= MV * NT2 && NV <= MV * NT2, "plane vectors per pass");
+  const int e = t + m * NT2;
+  return e < NV ? e : e - (MV * NT2 - NV);
+}
+
+// A sample's array as a buffer resource: loads at byte offsets at or past
+// its end return zero, so cells outside the mesh need no branch (and no
+// load waits on a path that skipped it).
+struct Buf {
+  __amdgpu_buffer_rsrc_t r;
+  unsigned oob;  // an offset past the end
+};
+template <typename R>
+__device__ __forceinline__ Buf mkbuf(const R *base, int n) {
+  const unsigned bytes = (unsigned)n * (unsigned)sizeof(R);
+  // 0x00020000: 32-bit data format of a raw (unstructured) buffer on CDNA
+  return Buf{__builtin_amdgcn_make_buffer_rsrc((void *)base, (short)0, (int)bytes, 0x00020000),
+             bytes};
+}
+__device__ __forceinline__ float4 bld_vec(const Buf &B, unsigned off, float4) {
+  const auto v = __builtin_amdgcn_raw_buffer_load_b128(B.r, off, 0, 0);
+  return make_float4(__uint_as_float(v[0]), __uint_as_float(v[1]), __uint_as_float(v[2]),
+                     __uint_as_float(v[3]));
+}
+__device__ __forceinline__ double2 bld_vec(const Buf &B, unsigned off, double2) {
+  const auto v = __builtin_amdgcn_raw_buffer_load_b128(B.r, off, 0, 0);
+  return make_double2(__hiloint2double((int)v[1], (int)v[0]),
+                      __hiloint2double((int)v[3], (int)v[2]));
+}
+__device__ __forceinline__ float bld1(const Buf &B, unsigned off, float) {
+  return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(B.r, off, 0, 0));
+}
+__device__ __forceinline__ double bld1(const Buf &B, unsigned off, double) {
+  const auto v = __builtin_amdgcn_raw_buffer_load_b64(B.r, off, 0, 0);
+  return __hiloint2double((int)v[1], (int)v[0]);
+}
+
+// vector m of thread t of plane k of a sample's array B (zero outside the
+// mesh).  VOK: n0 is a multiple of the vector length, so rows start on
+// 16-byte boundaries and a vector is wholly inside or outside; otherwise
+// cells are loaded one by one.
+template <typename PL, bool VOK, typename R>
+__device__ __forceinline__ typename Vec16<R>::T pl_load(const Buf &B, int t, int m, int x0,
+                                                        int y0, int k, int n0, int n1, int n2) {
+  using VT = typename Vec16<R>::T;
+  constexpr int VEC = PL::VEC, RV = PL::FXR / VEC, RY = (PL::NX / PL::FXR - TY2) / 2;
+  const int e = pl_vec<PL::NV, PL::MV>(t, m);
+  const int ia = x0 - PL::RX + (e % RV) * VEC, jj = y0 - RY + e / RV;
+  const bool in = jj >= 0 && jj < n1 && k >= 0 && k < n2 && ia + VEC > 0 && ia < n0;
+  const int c = ia + n0 * (jj + n1 * k);
+  if (VOK) return bld_vec(B, in ? (unsigned)c * (unsigned)sizeof(R) : B.oob, VT{});
+  VT v;
+#pragma unroll
+  for (int u = 0; u < VEC; u++) {
+    const bool ok = in && ia + u >= 0 && ia + u < n0;
+    vset(v, u, bld1(B, ok ? (unsigned)(c + u) * (unsigned)sizeof(R) : B.oob, R{}));
+  }
+  return v;
+}
+
+template <typename PL, typename R>
+__device__ __forceinline__ void pl_store(R *s, int t, int m, typename Vec16<R>::T v) {
+  const int e = pl_vec<PL::NV, PL::MV>(t, m);
+  *reinterpret_cast<typename Vec16<R>::T *>(s + e * PL::VEC) = v;
+}
+
 // Halo of one plane for a thread: the cell left of the tile (tx == 0), right
 // of it (tx == 63), and below / above its two cells (ty == 0 / ty == TY2-1),
 // for the iterate and rAU.  Loaded one plane ahead, so the loads are in
@@ -872,7 +1013,8 @@ __device__ __forceinline__ R off25(const R T[6], int lx, int ty, const R *sx, R 
 }
 
 // MODE 0: q = A p and partial p.q;  MODE 1: r = b - A p (and its FP32 copy)
-// and partials r.r, b.b
+// and partials r.r, b.b.  64 x 8 tiles walk up to kz planes; p, rAU (and b)
+// are staged in LDS slots one plane ahead (one cell per thread).
 template <int MODE>
 __global__ void __launch_bounds__(NT2) k_stencil25(OpB<double> LB, SH S,
                                                    const double *__restrict__ p,
@@ -881,8 +1023,12 @@ __global__ void __launch_bounds__(NT2) k_stencil25(OpB<double> LB, SH S,
                                                    float *__restrict__ outf,
                                                    double *__restrict__ partials, int off2,
                                                    const int *__restrict__ mask) {
-  constexpr int W = 64;
-  __shared__ double sp[(TY2 + 2) * (W + 2)], sr[(TY2 + 2) * (W + 2)];
+  constexpr int W = 64, NS = 4, NSB = 3;
+  using PL = Pl1<double, W>;
+  using VT = typename Vec16<double>::T;
+  constexpr int NX = PL::NX, FXR = PL::FXR;
+  __shared__ __align__(16) double sp[NS * NX], sr[NS * NX];
+  __shared__ __align__(16) double sb[MODE == 1 ? NSB * NX : 2];
   __shared__ double lred[NT2 / 64];
   int g, s, lb;
   if (!locate(S, mask, g, s, lb)) return;
@@ -896,34 +1042,67 @@ __global__ void __launch_bounds__(NT2) k_stencil25(OpB<double> LB, SH S,
   int xb, y0, k0, k1;
   tile_of(lb, n0, n1, n2, W, S.kz, xb, y0, k0, k1);
   const int x0 = xb * W;
-  const int tx = threadIdx.x, ty = threadIdx.y;
+  const int tx = threadIdx.x, ty = threadIdx.y, t = tx + 64 * ty;
   const int i = x0 + tx, j = y0 + ty;
   const bool in = i < n0 && j < n1;
-  const double *rA = L.rAU;
-  auto X = [&](int ii, int jj, int kk) -> double { return ld_or0(p, ii, jj, kk, n0, n1, n2); };
-  double pm = X(i, j, k0 - 1), pc = X(i, j, k0), pp = X(i, j, k0 + 1), pq = X(i, j, k0 + 2);
-  double rm = ld_or0(rA, i, j, k0 - 1, n0, n1, n2), rc = ld_or0(rA, i, j, k0, n0, n1, n2),
-         rp = ld_or0(rA, i, j, k0 + 1, n0, n1, n2), rq = ld_or0(rA, i, j, k0 + 2, n0, n1, n2);
-  Halo<double> hc = halo_load<double, 1, W>(X, rA, x0, y0, i, j, k0, n0, n1, n2), hn = hc;
+  const int ncs = n0 * n1 * n2;
+  const Buf Bp = mkbuf(p, ncs), Br = mkbuf(L.rAU, ncs), Bb = mkbuf(MODE == 1 ? b : p, ncs);
+  const bool vec_ok = (n0 % PL::VEC) == 0;
+  VT vp[PL::MV], vr[PL::MV], vb[PL::MV];
+  auto load = [&](int k) {
+    if (vec_ok) {
+#pragma unroll
+      for (int m = 0; m < PL::MV; m++) {
+        vp[m] = pl_load<PL, true, double>(Bp, t, m, x0, y0, k, n0, n1, n2);
+        vr[m] = pl_load<PL, true, double>(Br, t, m, x0, y0, k, n0, n1, n2);
+        if (MODE == 1) vb[m] = pl_load<PL, true, double>(Bb, t, m, x0, y0, k, n0, n1, n2);
+      }
+    } else {
+#pragma unroll
+      for (int m = 0; m < PL::MV; m++) {
+        vp[m] = pl_load<PL, false, double>(Bp, t, m, x0, y0, k, n0, n1, n2);
+        vr[m] = pl_load<PL, false, double>(Br, t, m, x0, y0, k, n0, n1, n2);
+        if (MODE == 1) vb[m] = pl_load<PL, false, double>(Bb, t, m, x0, y0, k, n0, n1, n2);
+      }
+    }
+  };
+  auto store = [&](int k) {
+#pragma unroll
+    for (int m = 0; m < PL::MV; m++) {
+      pl_store<PL>(sp + slot_of<NS>(k) * NX, t, m, vp[m]);
+      pl_store<PL>(sr + slot_of<NS>(k) * NX, t, m, vr[m]);
+      if (MODE == 1) pl_store<PL>(sb + slot_of<NSB>(k) * NX, t, m, vb[m]);
+    }
+  };
+  load(k0 - 1);
+  store(k0 - 1);
+  load(k0);
+  store(k0);
+  load(k0 + 1);
+  const int c2 = PL::at(tx, ty);
   double v1 = 0.0, v2 = 0.0;
   for (int k = k0; k < k1; k++) {
-    sp[LIX(W, tx, ty)] = pc;
-    sr[LIX(W, tx, ty)] = rc;
-    halo_store<double, 1, W>(hc, sp, sr);
+    store(k + 1);
     __syncthreads();
-    if (k + 1 < k1) hn = halo_load<double, 1, W>(X, rA, x0, y0, i, j, k + 1, n0, n1, n2);
-    const double pr = X(i, j, k + 3), rr3 = ld_or0(rA, i, j, k + 3, n0, n1, n2);
-    double bb = 0.0;
-    const int c = i + n0 * (j + n1 * k);
-    if (MODE == 1 && in) bb = b[c];
+    if (k + 2 <= k1) load(k + 2);
     if (in) {
+      const double *Pm = sp + slot_of<NS>(k - 1) * NX, *Pc = sp + slot_of<NS>(k) * NX,
+                   *Pp = sp + slot_of<NS>(k + 1) * NX;
+      const double *Rm = sr + slot_of<NS>(k - 1) * NX, *Rc = sr + slot_of<NS>(k) * NX,
+                   *Rp = sr + slot_of<NS>(k + 1) * NX;
       double T[6], D;
-      row25<double, W>(L, i, j, k, tx, ty, sr, rc, rm, rp, T, D);
-      const double y = D * pc - off25<double, W>(T, tx, ty, sp, pm, pp);
+      coef7(L, i, j, k, Rc[c2], Rc[c2 - 1], Rc[c2 + 1], Rc[c2 - FXR], Rc[c2 + FXR], Rm[c2],
+            Rp[c2], T, D);
+      const double pc = Pc[c2];
+      const double off = T[0] * Pc[c2 - 1] + T[1] * Pc[c2 + 1] + T[2] * Pc[c2 - FXR] +
+                         T[3] * Pc[c2 + FXR] + T[4] * Pm[c2] + T[5] * Pp[c2];
+      const double y = D * pc - off;
+      const int c = i + n0 * (j + n1 * k);
       if (MODE == 0) {
         out[c] = y;
         v1 += pc * y;
       } else {
+        const double bb = sb[slot_of<NSB>(k) * NX + c2];
         const double res = bb - y;
         out[c] = res;
         if (outf) outf[c] = (float)res;
@@ -931,10 +1110,6 @@ __global__ void __launch_bounds__(NT2) k_stencil25(OpB<double> LB, SH S,
         v2 += bb * bb;
       }
     }
-    __syncthreads();
-    pm = pc; pc = pp; pp = pq; pq = pr;
-    rm = rc; rc = rp; rp = rq; rq = rr3;
-    hc = hn;
   }
   const double s1 = block_sum_n<NT2 / 64>(v1, lred);
   if (tx == 0 && ty == 0) partials[g] = s1;
@@ -1055,62 +1230,9 @@ constexpr int NRING = FX1 + TY2;     // A cells on the 1-ring of a plane
 
 enum { SW_NORMAL = 0, SW_ZERO = 1, SW_PROLONG = 2 };
 
-template <typename R> struct Vec16;
-template <> struct Vec16<float> { using T = float4; using T2 = float2; };
-template <> struct Vec16<double> { using T = double2; using T2 = double2; };
-
-// component access and arithmetic on the 16-byte vectors (indices are
-// compile-time constants after unrolling, so these stay in registers)
-template <typename VT> __device__ __forceinline__ VT vzero();
-template <> __device__ __forceinline__ float4 vzero<float4>() { return make_float4(0.f, 0.f, 0.f, 0.f); }
-template <> __device__ __forceinline__ double2 vzero<double2>() { return make_double2(0.0, 0.0); }
-__device__ __forceinline__ void vset(float4 &v, int u, float a) {
-  if (u == 0) v.x = a; else if (u == 1) v.y = a; else if (u == 2) v.z = a; else v.w = a;
-}
-__device__ __forceinline__ void vset(double2 &v, int u, double a) {
-  if (u == 0) v.x = a; else v.y = a;
-}
-__device__ __forceinline__ float4 vadd(float4 a, float4 b) {
-  return make_float4(a.x + b.x, a.y + b.y, a.z + b.z, a.w + b.w);
-}
-__device__ __forceinline__ double2 vadd(double2 a, double2 b) {
-  return make_double2(a.x + b.x, a.y + b.y);
-}
-
-// plane geometry of the fused sweep for element type R: the x-ring is one
-// 16-byte vector wide (at least 2 cells) so rows start on a vector boundary
+// plane geometry of the fused sweep: 128 x TY2 tiles with a two-row ring
 template <typename R>
-struct SwPlane {
-  static constexpr int VEC = 16 / sizeof(R);
-  static constexpr int RX = VEC < 2 ? 2 : VEC;
-  static constexpr int FXR = FW + 2 * RX;        // row stride
-  static constexpr int NX = FXR * FY2;           // elements per plane
-  static constexpr int NV = NX / VEC;            // vectors per plane
-  static constexpr int MV = (NV + NT2 - 1) / NT2;
-  __device__ static constexpr int at(int lx, int ly) { return (ly + 2) * FXR + lx + RX; }
-};
-
-// 1/D for the smoother: the hardware reciprocal in FP32 (the V-cycle is a
-// preconditioner; the outer FP64 CG is unaffected), exact in FP64
-__device__ __forceinline__ float sw_rcp(float d) { return __builtin_amdgcn_rcpf(d); }
-__device__ __forceinline__ double sw_rcp(double d) { return 1.0 / d; }
-
-// row of the fine operator at (i,j,k) from the seven rAU values around it
-template <typename R>
-__device__ __forceinline__ void coef7(const Op<R> &L, int i, int j, int k, R rc, R rxm, R rxp,
-                                      R rym, R ryp, R rzm, R rzp, R T[6], R &D) {
-  const R h = (R)0.5;
-  T[0] = i > 0 ? h * (rc + rxm) * L.c[0] : (R)0;
-  T[1] = i + 1 < L.n0 ? h * (rc + rxp) * L.c[0] : (R)0;
-  T[2] = j > 0 ? h * (rc + rym) * L.c[1] : (R)0;
-  T[3] = j + 1 < L.n1 ? h * (rc + ryp) * L.c[1] : (R)0;
-  T[4] = k > 0 ? h * (rc + rzm) * L.c[2] : (R)0;
-  T[5] = k + 1 < L.n2 ? h * (rc + rzp) * L.c[2] : (R)0;
-  const R db = (i == 0 ? L.ob[0] : (R)0) + (i + 1 == L.n0 ? L.ob[1] : (R)0) +
-               (j == 0 ? L.ob[2] : (R)0) + (j + 1 == L.n1 ? L.ob[3] : (R)0) +
-               (k == 0 ? L.ob[4] : (R)0) + (k + 1 == L.n2 ? L.ob[5] : (R)0);
-  D = T[0] + T[1] + T[2] + T[3] + T[4] + T[5] + rc * db;
-}
+using SwPlane = PlG<R, FW, 2>;
 
 // position (lx, ly) of ring A cell r (0 <= r < NRING) of plane k: rows above
 // and below the tile (65 each), then the columns left and right (4 each)
@@ -1166,60 +1288,77 @@ __global__ void __launch_bounds__(NT2) k_sweep25(OpB<R> LB, SH S, const B *__res
     return i >= 0 && i < n0 && jj >= 0 && jj < n1 && k >= 0 && k < n2;
   };
   auto xs = [](int k) { return (k + 3) % 3; };
-  // Registers of the plane in flight: x, rAU and (SW_PROLONG) the coarse
+  // Registers of the plane in flight: x, rAU, b and (SW_PROLONG) the coarse
   // correction, kept apart from x until the LDS store so that nothing reads
   // a loaded value before the next plane step (the loads stay in flight
   // while the current plane is relaxed).
+  const int ncs = n0 * n1 * n2;
+  const Buf Bx = mkbuf(MODE == SW_ZERO ? rA : xin, ncs), Br = mkbuf(rA, ncs),
+            Bb = mkbuf(b, ncs);
+  const Buf Bc = mkbuf(xcs ? xcs : rA, xcs ? cn0 * cn1 * Q.cn2 : 0);
   VT px[PL::MV], pr[PL::MV], pb[PL::MV], pc[PL::MV];
+  // coarse correction of the parents of vector m of plane k
+  auto parent = [&](int m, int k, auto vok) -> VT {
+    constexpr bool VOK = decltype(vok)::value;
+    constexpr int RV = FXR / VEC;
+    const int e = pl_vec<PL::NV, PL::MV>(t, m);
+    const int ia = x0 - PL::RX + (e % RV) * VEC, jj = y0 - 2 + e / RV;
+    const bool in = jj >= 0 && jj < n1 && k >= 0 && k < n2 && ia + VEC > 0 && ia < n0;
+    const int pidx = (ia >> 1) + cn0 * ((jj >> 1) + cn1 * (k >> 1));
+    VT v = vzero<VT>();
+    if (VOK) {
+      // ia is a multiple of VEC (even): the vector has VEC/2 parents, and
+      // cn0 = n0/2 is even, so they are one aligned 8-byte load.  They are
+      // kept packed in the leading components (no use of the loaded values
+      // until the LDS store, which spreads them with vspread).
+      const unsigned off = in ? (unsigned)pidx * (unsigned)sizeof(R) : Bc.oob;
+      if constexpr (VEC == 4) {
+        const auto w = __builtin_amdgcn_raw_buffer_load_b64(Bc.r, off, 0, 0);
+        vset(v, 0, __uint_as_float(w[0]));
+        vset(v, 1, __uint_as_float(w[1]));
+      } else {
+        vset(v, 0, bld1(Bc, off, R{}));
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < VEC; u++) {
+        const bool ok = in && ia + u >= 0 && ia + u < n0;
+        const int q = ((ia + u) >> 1) + cn0 * ((jj >> 1) + cn1 * (k >> 1));
+        vset(v, u, bld1(Bc, ok ? (unsigned)q * (unsigned)sizeof(R) : Bc.oob, R{}));
+      }
+    }
+    return v;
+  };
   auto load_planes = [&](int k) {
+    if (vec_ok) {
 #pragma unroll
-    for (int m = 0; m < PL::MV; m++) {
-      const int e = t + m * NT2;
-      VT vx = vzero<VT>(), vr = vzero<VT>(), vb = vzero<VT>(), vc = vzero<VT>();
-      const int ia = x0 - PL::RX + (e % (FXR / VEC)) * VEC, jj = y0 + e / (FXR / VEC) - 2;
-      const bool in = e < PL::NV && jj >= 0 && jj < n1 && k >= 0 && k < n2 && ia + VEC > 0 &&
-                      ia < n0;
-      const int c = ia + n0 * (jj + n1 * k);
-      if (vec_ok) {
-        // n0 and x0 are multiples of VEC: a vector is wholly inside or outside
-        if (in) {
-          vr = *reinterpret_cast<const VT *>(rA + c);
-          vb = *reinterpret_cast<const VT *>(b + c);
-          if (MODE != SW_ZERO) vx = *reinterpret_cast<const VT *>(xin + c);
-        }
-      } else if (in) {
-#pragma unroll
-        for (int u = 0; u < VEC; u++)
-          if (ia + u >= 0 && ia + u < n0) {
-            vset(vr, u, rA[c + u]);
-            vset(vb, u, b[c + u]);
-            if (MODE != SW_ZERO) vset(vx, u, xin[c + u]);
-          }
+      for (int m = 0; m < PL::MV; m++) {
+        if (MODE != SW_ZERO) px[m] = pl_load<PL, true, R>(Bx, t, m, x0, y0, k, n0, n1, n2);
+        pr[m] = pl_load<PL, true, R>(Br, t, m, x0, y0, k, n0, n1, n2);
+        pb[m] = pl_load<PL, true, R>(Bb, t, m, x0, y0, k, n0, n1, n2);
+        if (MODE == SW_PROLONG) pc[m] = parent(m, k, std::true_type{});
       }
-      if (MODE == SW_PROLONG && xcs && in) {
+    } else {
 #pragma unroll
-        for (int u = 0; u < VEC; u++)
-          if (ia + u >= 0 && ia + u < n0)
-            vset(vc, u, xcs[((ia + u) >> 1) + cn0 * ((jj >> 1) + cn1 * (k >> 1))]);
+      for (int m = 0; m < PL::MV; m++) {
+        if (MODE != SW_ZERO) px[m] = pl_load<PL, false, R>(Bx, t, m, x0, y0, k, n0, n1, n2);
+        pr[m] = pl_load<PL, false, R>(Br, t, m, x0, y0, k, n0, n1, n2);
+        pb[m] = pl_load<PL, false, R>(Bb, t, m, x0, y0, k, n0, n1, n2);
+        if (MODE == SW_PROLONG) pc[m] = parent(m, k, std::false_type{});
       }
-      px[m] = vx;
-      pr[m] = vr;
-      pb[m] = vb;
-      if (MODE == SW_PROLONG) pc[m] = vc;
     }
   };
   auto store_planes = [&](int k) {
 #pragma unroll
     for (int m = 0; m < PL::MV; m++) {
-      const int e = t + m * NT2;
-      if (e < PL::NV) {
-        if (MODE == SW_PROLONG)
-          *reinterpret_cast<VT *>(sX + xs(k) * NX + e * VEC) = vadd(px[m], pc[m]);
-        else if (MODE != SW_ZERO)
-          *reinterpret_cast<VT *>(sX + xs(k) * NX + e * VEC) = px[m];
-        *reinterpret_cast<VT *>(sR + xs(k) * NX + e * VEC) = pr[m];
-        *reinterpret_cast<VT *>(sB + xs(k) * NX + e * VEC) = pb[m];
-      }
+      const int e = pl_vec<PL::NV, PL::MV>(t, m);
+      if (MODE == SW_PROLONG)
+        *reinterpret_cast<VT *>(sX + xs(k) * NX + e * VEC) =
+            vadd(px[m], vec_ok ? vspread(pc[m]) : pc[m]);
+      else if (MODE != SW_ZERO)
+        *reinterpret_cast<VT *>(sX + xs(k) * NX + e * VEC) = px[m];
+      *reinterpret_cast<VT *>(sR + xs(k) * NX + e * VEC) = pr[m];
+      *reinterpret_cast<VT *>(sB + xs(k) * NX + e * VEC) = pb[m];
     }
   };
   const bool ringer = t < NRING;
@@ -1321,8 +1460,12 @@ template <typename R, typename B>
 __global__ void __launch_bounds__(NT2) k_restrict25(OpB<R> LB, SH S, const B *__restrict__ b,
                                                     const R *__restrict__ x, R *__restrict__ bc,
                                                     const int *__restrict__ mask) {
-  constexpr int W = 128;
-  __shared__ R sx[(TY2 + 2) * (W + 2)], sr[(TY2 + 2) * (W + 2)];
+  constexpr int W = 128, NS = 4, NSB = 3;
+  using PL = Pl1<R, W>;
+  using VT = typename Vec16<R>::T;
+  constexpr int NX = PL::NX, FXR = PL::FXR;
+  static_assert(std::is_same<R, B>::value, "the right-hand side is staged as R");
+  __shared__ __align__(16) R sx[NS * NX], sr[NS * NX], sb[NSB * NX];
   __shared__ R part[TY2 / 2][64];
   int g, s, lb;
   if (!locate(S, mask, g, s, lb)) return;
@@ -1336,35 +1479,61 @@ __global__ void __launch_bounds__(NT2) k_restrict25(OpB<R> LB, SH S, const B *__
   int xb, y0, k0, k1;
   tile_of(lb, n0, n1, n2, W, S.kz, xb, y0, k0, k1);
   const int x0 = xb * W;
-  const int tx = threadIdx.x, ty = threadIdx.y;
+  const int tx = threadIdx.x, ty = threadIdx.y, t = tx + 64 * ty;
   const int i0 = x0 + 2 * tx, j = y0 + ty;
-  const R *rA = L.rAU;
-  auto X = [&](int ii, int jj, int kk) -> R { return ld_or0(x, ii, jj, kk, n0, n1, n2); };
-  auto XP = [&](int kk) -> P2<R> { return P2<R>{X(i0, j, kk), X(i0 + 1, j, kk)}; };
-  auto RP = [&](int kk) -> P2<R> {
-    return P2<R>{ld_or0(rA, i0, j, kk, n0, n1, n2), ld_or0(rA, i0 + 1, j, kk, n0, n1, n2)};
+  const int ncs = n0 * n1 * n2;
+  const Buf Bx = mkbuf(x, ncs), Br = mkbuf(L.rAU, ncs), Bb = mkbuf(b, ncs);
+  const bool vec_ok = (n0 % PL::VEC) == 0;
+  VT vx[PL::MV], vr[PL::MV], vb[PL::MV];
+  auto load = [&](int k) {
+    if (vec_ok) {
+#pragma unroll
+      for (int m = 0; m < PL::MV; m++) {
+        vx[m] = pl_load<PL, true, R>(Bx, t, m, x0, y0, k, n0, n1, n2);
+        vr[m] = pl_load<PL, true, R>(Br, t, m, x0, y0, k, n0, n1, n2);
+        vb[m] = pl_load<PL, true, R>(Bb, t, m, x0, y0, k, n0, n1, n2);
+      }
+    } else {
+#pragma unroll
+      for (int m = 0; m < PL::MV; m++) {
+        vx[m] = pl_load<PL, false, R>(Bx, t, m, x0, y0, k, n0, n1, n2);
+        vr[m] = pl_load<PL, false, R>(Br, t, m, x0, y0, k, n0, n1, n2);
+        vb[m] = pl_load<PL, false, R>(Bb, t, m, x0, y0, k, n0, n1, n2);
+      }
+    }
   };
-  P2<R> xm = XP(k0 - 1), xk = XP(k0), xp = XP(k0 + 1), xq = XP(k0 + 2);
-  P2<R> rm = RP(k0 - 1), rk = RP(k0), rp = RP(k0 + 1), rq = RP(k0 + 2);
-  Halo<R> hc = halo_load<R, 2, W>(X, rA, x0, y0, i0, j, k0, n0, n1, n2), hn = hc;
+  auto store = [&](int k) {
+#pragma unroll
+    for (int m = 0; m < PL::MV; m++) {
+      pl_store<PL>(sx + slot_of<NS>(k) * NX, t, m, vx[m]);
+      pl_store<PL>(sr + slot_of<NS>(k) * NX, t, m, vr[m]);
+      pl_store<PL>(sb + slot_of<NSB>(k) * NX, t, m, vb[m]);
+    }
+  };
+  load(k0 - 1);
+  store(k0 - 1);
+  load(k0);
+  store(k0);
+  load(k0 + 1);
   R acc = 0;
   for (int k = k0; k < k1; k++) {
-    sx[LIX(W, 2 * tx, ty)] = xk.v0;
-    sx[LIX(W, 2 * tx + 1, ty)] = xk.v1;
-    sr[LIX(W, 2 * tx, ty)] = rk.v0;
-    sr[LIX(W, 2 * tx + 1, ty)] = rk.v1;
-    halo_store<R, 2, W>(hc, sx, sr);
+    store(k + 1);
     __syncthreads();
-    if (k + 1 < k1) hn = halo_load<R, 2, W>(X, rA, x0, y0, i0, j, k + 1, n0, n1, n2);
-    const P2<R> xr = XP(k + 3), rr = RP(k + 3);
+    if (k + 2 <= k1) load(k + 2);
     const int off = ((j + k) & 1) == 0 ? 0 : 1;  // the red cell of the pair
     const int i = i0 + off;
     if (j < n1 && i < n0) {
-      const int lx = 2 * tx + off;
+      const int c2 = PL::at(2 * tx + off, ty);
+      const R *Xm = sx + slot_of<NS>(k - 1) * NX, *Xc = sx + slot_of<NS>(k) * NX,
+              *Xp = sx + slot_of<NS>(k + 1) * NX;
+      const R *Rm = sr + slot_of<NS>(k - 1) * NX, *Rc = sr + slot_of<NS>(k) * NX,
+              *Rp = sr + slot_of<NS>(k + 1) * NX;
       R T[6], D;
-      row25<R, W>(L, i, j, k, lx, ty, sr, rk.get(off), rm.get(off), rp.get(off), T, D);
-      const R sm = off25<R, W>(T, lx, ty, sx, xm.get(off), xp.get(off));
-      acc += (R)b[i + n0 * (j + n1 * k)] - (D * xk.get(off) - sm);
+      coef7(L, i, j, k, Rc[c2], Rc[c2 - 1], Rc[c2 + 1], Rc[c2 - FXR], Rc[c2 + FXR], Rm[c2],
+            Rp[c2], T, D);
+      const R sm = T[0] * Xc[c2 - 1] + T[1] * Xc[c2 + 1] + T[2] * Xc[c2 - FXR] +
+                   T[3] * Xc[c2 + FXR] + T[4] * Xm[c2] + T[5] * Xp[c2];
+      acc += sb[slot_of<NSB>(k) * NX + c2] - (D * Xc[c2] - sm);
     }
     const bool flush = (k & 1) == 1 || k + 1 == n2;
     if (flush && (ty & 1)) part[ty >> 1][tx] = acc;
@@ -1377,9 +1546,6 @@ __global__ void __launch_bounds__(NT2) k_restrict25(OpB<R> LB, SH S, const B *__
       }
       acc = 0;
     }
-    xm = xk; xk = xp; xp = xq; xq = xr;
-    rm = rk; rk = rp; rp = rq; rq = rr;
-    hc = hn;
   }
 }
 
