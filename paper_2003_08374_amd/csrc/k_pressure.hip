@@ -1048,44 +1048,35 @@ __global__ void __launch_bounds__(NT2) k_stencil25(OpB<double> LB, SH S,
   const int ncs = n0 * n1 * n2;
   const Buf Bp = mkbuf(p, ncs), Br = mkbuf(L.rAU, ncs), Bb = mkbuf(MODE == 1 ? b : p, ncs);
   const bool vec_ok = (n0 % PL::VEC) == 0;
-  VT vp[PL::MV], vr[PL::MV], vb[PL::MV];
-  auto load = [&](int k) {
-    if (vec_ok) {
-#pragma unroll
-      for (int m = 0; m < PL::MV; m++) {
-        vp[m] = pl_load<PL, true, double>(Bp, t, m, x0, y0, k, n0, n1, n2);
-        vr[m] = pl_load<PL, true, double>(Br, t, m, x0, y0, k, n0, n1, n2);
-        if (MODE == 1) vb[m] = pl_load<PL, true, double>(Bb, t, m, x0, y0, k, n0, n1, n2);
-      }
-    } else {
-#pragma unroll
-      for (int m = 0; m < PL::MV; m++) {
-        vp[m] = pl_load<PL, false, double>(Bp, t, m, x0, y0, k, n0, n1, n2);
-        vr[m] = pl_load<PL, false, double>(Br, t, m, x0, y0, k, n0, n1, n2);
-        if (MODE == 1) vb[m] = pl_load<PL, false, double>(Bb, t, m, x0, y0, k, n0, n1, n2);
-      }
-    }
-  };
-  auto store = [&](int k) {
-#pragma unroll
-    for (int m = 0; m < PL::MV; m++) {
-      pl_store<PL>(sp + slot_of<NS>(k) * NX, t, m, vp[m]);
-      pl_store<PL>(sr + slot_of<NS>(k) * NX, t, m, vr[m]);
-      if (MODE == 1) pl_store<PL>(sb + slot_of<NSB>(k) * NX, t, m, vb[m]);
-    }
-  };
-  load(k0 - 1);
-  store(k0 - 1);
-  load(k0);
-  store(k0);
-  load(k0 + 1);
-  const int c2 = PL::at(tx, ty);
   double v1 = 0.0, v2 = 0.0;
-  for (int k = k0; k < k1; k++) {
-    store(k + 1);
-    __syncthreads();
-    if (k + 2 <= k1) load(k + 2);
-    if (in) {
+  // the body is instantiated for aligned rows (16-byte loads) and not,
+  // so that each copy issues a fixed number of loads per plane
+  auto run = [&](auto vok) {
+    constexpr bool VOK = decltype(vok)::value;
+    // two register sets alternate: plane k+2 is in flight in one while plane
+    // k+1 is stored from the other and plane k computed
+    struct Regs {
+      VT p[PL::MV], r[PL::MV], b[PL::MV];
+    } RA, RB;
+    auto load = [&](Regs &G, int k) {
+#pragma unroll
+      for (int m = 0; m < PL::MV; m++) {
+        G.p[m] = pl_load<PL, VOK, double>(Bp, t, m, x0, y0, k, n0, n1, n2);
+        G.r[m] = pl_load<PL, VOK, double>(Br, t, m, x0, y0, k, n0, n1, n2);
+        if (MODE == 1) G.b[m] = pl_load<PL, VOK, double>(Bb, t, m, x0, y0, k, n0, n1, n2);
+      }
+    };
+    auto store = [&](const Regs &G, int k) {
+#pragma unroll
+      for (int m = 0; m < PL::MV; m++) {
+        pl_store<PL>(sp + slot_of<NS>(k) * NX, t, m, G.p[m]);
+        pl_store<PL>(sr + slot_of<NS>(k) * NX, t, m, G.r[m]);
+        if (MODE == 1) pl_store<PL>(sb + slot_of<NSB>(k) * NX, t, m, G.b[m]);
+      }
+    };
+    const int c2 = PL::at(tx, ty);
+    auto compute = [&](int k) {
+      if (!in) return;
       const double *Pm = sp + slot_of<NS>(k - 1) * NX, *Pc = sp + slot_of<NS>(k) * NX,
                    *Pp = sp + slot_of<NS>(k + 1) * NX;
       const double *Rm = sr + slot_of<NS>(k - 1) * NX, *Rc = sr + slot_of<NS>(k) * NX,
@@ -1109,8 +1100,29 @@ __global__ void __launch_bounds__(NT2) k_stencil25(OpB<double> LB, SH S,
         v1 += res * res;
         v2 += bb * bb;
       }
+    };
+    // G holds plane k+1 on entry and plane k+3 in flight on exit
+    auto step = [&](Regs &G, int k) {
+      store(G, k + 1);
+      __syncthreads();
+      load(G, k + 3 <= k1 ? k + 3 : n2);  // plane n2: no memory access
+      if (k < k1) compute(k);
+    };
+    load(RA, k0 - 1);
+    store(RA, k0 - 1);
+    load(RA, k0);
+    store(RA, k0);
+    load(RA, k0 + 1);
+    load(RB, k0 + 2 <= k1 ? k0 + 2 : n2);
+    // planes in pairs; an odd count ends with a step that only stores and
+    // loads, so that both steps issue the same loads on every path
+    for (int k = k0; k < k1; k += 2) {
+      step(RA, k);
+      step(RB, k + 1);
     }
-  }
+  };
+  if (vec_ok) run(std::true_type{});
+  else run(std::false_type{});
   const double s1 = block_sum_n<NT2 / 64>(v1, lred);
   if (tx == 0 && ty == 0) partials[g] = s1;
   if (MODE == 1) {
@@ -1296,7 +1308,6 @@ __global__ void __launch_bounds__(NT2) k_sweep25(OpB<R> LB, SH S, const B *__res
   const Buf Bx = mkbuf(MODE == SW_ZERO ? rA : xin, ncs), Br = mkbuf(rA, ncs),
             Bb = mkbuf(b, ncs);
   const Buf Bc = mkbuf(xcs ? xcs : rA, xcs ? cn0 * cn1 * Q.cn2 : 0);
-  VT px[PL::MV], pr[PL::MV], pb[PL::MV], pc[PL::MV];
   // coarse correction of the parents of vector m of plane k
   auto parent = [&](int m, int k, auto vok) -> VT {
     constexpr bool VOK = decltype(vok)::value;
@@ -1329,38 +1340,6 @@ __global__ void __launch_bounds__(NT2) k_sweep25(OpB<R> LB, SH S, const B *__res
     }
     return v;
   };
-  auto load_planes = [&](int k) {
-    if (vec_ok) {
-#pragma unroll
-      for (int m = 0; m < PL::MV; m++) {
-        if (MODE != SW_ZERO) px[m] = pl_load<PL, true, R>(Bx, t, m, x0, y0, k, n0, n1, n2);
-        pr[m] = pl_load<PL, true, R>(Br, t, m, x0, y0, k, n0, n1, n2);
-        pb[m] = pl_load<PL, true, R>(Bb, t, m, x0, y0, k, n0, n1, n2);
-        if (MODE == SW_PROLONG) pc[m] = parent(m, k, std::true_type{});
-      }
-    } else {
-#pragma unroll
-      for (int m = 0; m < PL::MV; m++) {
-        if (MODE != SW_ZERO) px[m] = pl_load<PL, false, R>(Bx, t, m, x0, y0, k, n0, n1, n2);
-        pr[m] = pl_load<PL, false, R>(Br, t, m, x0, y0, k, n0, n1, n2);
-        pb[m] = pl_load<PL, false, R>(Bb, t, m, x0, y0, k, n0, n1, n2);
-        if (MODE == SW_PROLONG) pc[m] = parent(m, k, std::false_type{});
-      }
-    }
-  };
-  auto store_planes = [&](int k) {
-#pragma unroll
-    for (int m = 0; m < PL::MV; m++) {
-      const int e = pl_vec<PL::NV, PL::MV>(t, m);
-      if (MODE == SW_PROLONG)
-        *reinterpret_cast<VT *>(sX + xs(k) * NX + e * VEC) =
-            vadd(px[m], vec_ok ? vspread(pc[m]) : pc[m]);
-      else if (MODE != SW_ZERO)
-        *reinterpret_cast<VT *>(sX + xs(k) * NX + e * VEC) = px[m];
-      *reinterpret_cast<VT *>(sR + xs(k) * NX + e * VEC) = pr[m];
-      *reinterpret_cast<VT *>(sB + xs(k) * NX + e * VEC) = pb[m];
-    }
-  };
   const bool ringer = t < NRING;
   // new A value at (lx, ly) of plane k from LDS neighbours
   auto relax_a = [&](int lx, int ly, int k) -> R {
@@ -1378,19 +1357,11 @@ __global__ void __launch_bounds__(NT2) k_sweep25(OpB<R> LB, SH S, const B *__res
                   T[3] * Xc[c2 + FXR] + T[4] * Xm[c2] + T[5] * Xp[c2];
     return D > (R)0 ? (bb + off) * sw_rcp(D) : (R)0;
   };
-  // prologue: planes k0-2, k0-1 in LDS, plane k0 in registers
-  for (int k = k0 - 2; k <= k0 - 1; k++) {
-    load_planes(k);
-    store_planes(k);
-  }
-  load_planes(k0);
   P2<R> r_m2 = {(R)0, (R)0}, r_m1 = {(R)0, (R)0}, r_0;
   R a_m2 = (R)0, a_m1 = (R)0, a_0;
-  for (int k = k0 - 1; k <= k1; k++) {
-    store_planes(k + 1);  // loaded one step earlier; its slot (plane k-2) is free
-    __syncthreads();
-    const bool more = k + 1 <= k1;
-    if (more) load_planes(k + 2);
+  // relax the A cells of plane k and the B cells of plane k-1 (planes k-1,
+  // k, k+1 in LDS)
+  auto relax_planes = [&](int k) {
     const int offA = ((j + k) & 1) == colA ? 0 : 1;  // x0 and 2 tx are even
     // own column: rAU of plane k; rAU around the own B cell of plane k-1
     const R *Rk = sR + xs(k) * NX;
@@ -1449,7 +1420,63 @@ __global__ void __launch_bounds__(NT2) k_sweep25(OpB<R> LB, SH S, const B *__res
     r_m1 = r_0;
     a_m2 = a_m1;
     a_m1 = a_0;
-  }
+  };
+  // Registers of the planes in flight: x, rAU, b and (SW_PROLONG) the coarse
+  // correction, kept apart from x until the LDS store so that nothing reads
+  // a loaded value before its plane step.  Two sets alternate: plane k+2 is
+  // in flight in one while plane k+1 is stored from the other.  The body is
+  // instantiated for aligned rows (16-byte loads) and not, so that each copy
+  // issues a fixed number of loads per plane.
+  auto run = [&](auto vok) {
+    constexpr bool VOK = decltype(vok)::value;
+    struct Regs {
+      VT x[PL::MV], r[PL::MV], b[PL::MV], c[PL::MV];
+    } RA, RB;
+    auto load_planes = [&](Regs &G, int k) {
+#pragma unroll
+      for (int m = 0; m < PL::MV; m++) {
+        if (MODE != SW_ZERO) G.x[m] = pl_load<PL, VOK, R>(Bx, t, m, x0, y0, k, n0, n1, n2);
+        G.r[m] = pl_load<PL, VOK, R>(Br, t, m, x0, y0, k, n0, n1, n2);
+        G.b[m] = pl_load<PL, VOK, R>(Bb, t, m, x0, y0, k, n0, n1, n2);
+        if (MODE == SW_PROLONG) G.c[m] = parent(m, k, vok);
+      }
+    };
+    auto store_planes = [&](const Regs &G, int k) {
+#pragma unroll
+      for (int m = 0; m < PL::MV; m++) {
+        const int e = pl_vec<PL::NV, PL::MV>(t, m);
+        if (MODE == SW_PROLONG)
+          *reinterpret_cast<VT *>(sX + xs(k) * NX + e * VEC) =
+              vadd(G.x[m], VOK ? vspread(G.c[m]) : G.c[m]);
+        else if (MODE != SW_ZERO)
+          *reinterpret_cast<VT *>(sX + xs(k) * NX + e * VEC) = G.x[m];
+        *reinterpret_cast<VT *>(sR + xs(k) * NX + e * VEC) = G.r[m];
+        *reinterpret_cast<VT *>(sB + xs(k) * NX + e * VEC) = G.b[m];
+      }
+    };
+    // G holds plane k+1 on entry and plane k+3 in flight on exit
+    auto step = [&](Regs &G, int k) {
+      store_planes(G, k + 1);  // its slot (plane k-2) is free
+      __syncthreads();
+      load_planes(G, k + 3 <= k1 + 1 ? k + 3 : n2);  // plane n2: no memory access
+      if (k <= k1) relax_planes(k);
+    };
+    // prologue: planes k0-2, k0-1 in LDS, k0 and k0+1 in flight
+    load_planes(RA, k0 - 2);
+    store_planes(RA, k0 - 2);
+    load_planes(RA, k0 - 1);
+    store_planes(RA, k0 - 1);
+    load_planes(RA, k0);
+    load_planes(RB, k0 + 1);
+    // planes in pairs; an odd count ends with a step that only stores and
+    // loads, so that both steps issue the same loads on every path
+    for (int k = k0 - 1; k <= k1; k += 2) {
+      step(RA, k);
+      step(RB, k + 1);
+    }
+  };
+  if (vec_ok) run(std::true_type{});
+  else run(std::false_type{});
 }
 
 // Restriction after a pre-smoothing that ended with a black half sweep: the
@@ -1484,69 +1511,81 @@ __global__ void __launch_bounds__(NT2) k_restrict25(OpB<R> LB, SH S, const B *__
   const int ncs = n0 * n1 * n2;
   const Buf Bx = mkbuf(x, ncs), Br = mkbuf(L.rAU, ncs), Bb = mkbuf(b, ncs);
   const bool vec_ok = (n0 % PL::VEC) == 0;
-  VT vx[PL::MV], vr[PL::MV], vb[PL::MV];
-  auto load = [&](int k) {
-    if (vec_ok) {
+  // the body is instantiated for aligned rows (16-byte loads) and not,
+  // so that each copy issues a fixed number of loads per plane
+  auto run = [&](auto vok) {
+    constexpr bool VOK = decltype(vok)::value;
+    // two register sets alternate: plane k+2 is in flight in one while plane
+    // k+1 is stored from the other and plane k computed
+    struct Regs {
+      VT x[PL::MV], r[PL::MV], b[PL::MV];
+    } RA, RB;
+    auto load = [&](Regs &G, int k) {
 #pragma unroll
       for (int m = 0; m < PL::MV; m++) {
-        vx[m] = pl_load<PL, true, R>(Bx, t, m, x0, y0, k, n0, n1, n2);
-        vr[m] = pl_load<PL, true, R>(Br, t, m, x0, y0, k, n0, n1, n2);
-        vb[m] = pl_load<PL, true, R>(Bb, t, m, x0, y0, k, n0, n1, n2);
+        G.x[m] = pl_load<PL, VOK, R>(Bx, t, m, x0, y0, k, n0, n1, n2);
+        G.r[m] = pl_load<PL, VOK, R>(Br, t, m, x0, y0, k, n0, n1, n2);
+        G.b[m] = pl_load<PL, VOK, R>(Bb, t, m, x0, y0, k, n0, n1, n2);
       }
-    } else {
+    };
+    auto store = [&](const Regs &G, int k) {
 #pragma unroll
       for (int m = 0; m < PL::MV; m++) {
-        vx[m] = pl_load<PL, false, R>(Bx, t, m, x0, y0, k, n0, n1, n2);
-        vr[m] = pl_load<PL, false, R>(Br, t, m, x0, y0, k, n0, n1, n2);
-        vb[m] = pl_load<PL, false, R>(Bb, t, m, x0, y0, k, n0, n1, n2);
+        pl_store<PL>(sx + slot_of<NS>(k) * NX, t, m, G.x[m]);
+        pl_store<PL>(sr + slot_of<NS>(k) * NX, t, m, G.r[m]);
+        pl_store<PL>(sb + slot_of<NSB>(k) * NX, t, m, G.b[m]);
       }
+    };
+    R acc = 0;
+    auto compute = [&](int k) {
+      const int off = ((j + k) & 1) == 0 ? 0 : 1;  // the red cell of the pair
+      const int i = i0 + off;
+      if (j < n1 && i < n0) {
+        const int c2 = PL::at(2 * tx + off, ty);
+        const R *Xm = sx + slot_of<NS>(k - 1) * NX, *Xc = sx + slot_of<NS>(k) * NX,
+                *Xp = sx + slot_of<NS>(k + 1) * NX;
+        const R *Rm = sr + slot_of<NS>(k - 1) * NX, *Rc = sr + slot_of<NS>(k) * NX,
+                *Rp = sr + slot_of<NS>(k + 1) * NX;
+        R T[6], D;
+        coef7(L, i, j, k, Rc[c2], Rc[c2 - 1], Rc[c2 + 1], Rc[c2 - FXR], Rc[c2 + FXR], Rm[c2],
+              Rp[c2], T, D);
+        const R sm = T[0] * Xc[c2 - 1] + T[1] * Xc[c2 + 1] + T[2] * Xc[c2 - FXR] +
+                     T[3] * Xc[c2 + FXR] + T[4] * Xm[c2] + T[5] * Xp[c2];
+        acc += sb[slot_of<NSB>(k) * NX + c2] - (D * Xc[c2] - sm);
+      }
+      const bool flush = (k & 1) == 1 || k + 1 == n2;
+      if (flush && (ty & 1)) part[ty >> 1][tx] = acc;
+      __syncthreads();
+      if (flush) {
+        if (!(ty & 1)) {
+          const int I = i0 >> 1, J = j >> 1, K = k >> 1;
+          const R other = (j + 1 < n1) ? part[ty >> 1][tx] : (R)0;
+          if (i0 < n0 && j < n1) bc[I + cn0 * (J + cn1 * K)] = acc + other;
+        }
+        acc = 0;
+      }
+    };
+    auto step = [&](Regs &G, int k) {
+      store(G, k + 1);
+      __syncthreads();
+      load(G, k + 3 <= k1 ? k + 3 : n2);  // plane n2: no memory access
+      if (k < k1) compute(k);
+    };
+    load(RA, k0 - 1);
+    store(RA, k0 - 1);
+    load(RA, k0);
+    store(RA, k0);
+    load(RA, k0 + 1);
+    load(RB, k0 + 2 <= k1 ? k0 + 2 : n2);
+    // planes in pairs; an odd count ends with a step that only stores and
+    // loads, so that both steps issue the same loads on every path
+    for (int k = k0; k < k1; k += 2) {
+      step(RA, k);
+      step(RB, k + 1);
     }
   };
-  auto store = [&](int k) {
-#pragma unroll
-    for (int m = 0; m < PL::MV; m++) {
-      pl_store<PL>(sx + slot_of<NS>(k) * NX, t, m, vx[m]);
-      pl_store<PL>(sr + slot_of<NS>(k) * NX, t, m, vr[m]);
-      pl_store<PL>(sb + slot_of<NSB>(k) * NX, t, m, vb[m]);
-    }
-  };
-  load(k0 - 1);
-  store(k0 - 1);
-  load(k0);
-  store(k0);
-  load(k0 + 1);
-  R acc = 0;
-  for (int k = k0; k < k1; k++) {
-    store(k + 1);
-    __syncthreads();
-    if (k + 2 <= k1) load(k + 2);
-    const int off = ((j + k) & 1) == 0 ? 0 : 1;  // the red cell of the pair
-    const int i = i0 + off;
-    if (j < n1 && i < n0) {
-      const int c2 = PL::at(2 * tx + off, ty);
-      const R *Xm = sx + slot_of<NS>(k - 1) * NX, *Xc = sx + slot_of<NS>(k) * NX,
-              *Xp = sx + slot_of<NS>(k + 1) * NX;
-      const R *Rm = sr + slot_of<NS>(k - 1) * NX, *Rc = sr + slot_of<NS>(k) * NX,
-              *Rp = sr + slot_of<NS>(k + 1) * NX;
-      R T[6], D;
-      coef7(L, i, j, k, Rc[c2], Rc[c2 - 1], Rc[c2 + 1], Rc[c2 - FXR], Rc[c2 + FXR], Rm[c2],
-            Rp[c2], T, D);
-      const R sm = T[0] * Xc[c2 - 1] + T[1] * Xc[c2 + 1] + T[2] * Xc[c2 - FXR] +
-                   T[3] * Xc[c2 + FXR] + T[4] * Xm[c2] + T[5] * Xp[c2];
-      acc += sb[slot_of<NSB>(k) * NX + c2] - (D * Xc[c2] - sm);
-    }
-    const bool flush = (k & 1) == 1 || k + 1 == n2;
-    if (flush && (ty & 1)) part[ty >> 1][tx] = acc;
-    __syncthreads();
-    if (flush) {
-      if (!(ty & 1)) {
-        const int I = i0 >> 1, J = j >> 1, K = k >> 1;
-        const R other = (j + 1 < n1) ? part[ty >> 1][tx] : (R)0;
-        if (i0 < n0 && j < n1) bc[I + cn0 * (J + cn1 * K)] = acc + other;
-      }
-      acc = 0;
-    }
-  }
+  if (vec_ok) run(std::true_type{});
+  else run(std::false_type{});
 }
 
 // ------------------------------------------------------------------ host
