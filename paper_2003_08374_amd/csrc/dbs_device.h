@@ -111,14 +111,34 @@ __host__ __device__ inline int cell_blocks(const Geom &G) {
   return ((G.n[0] + BX - 1) / BX) * ((G.n[1] + BY - 1) / BY) * G.n[2];
 }
 
+// Blocks of a sample are ordered in bands of CELL_BAND block rows: a band
+// runs through all planes before the next band starts.  The blocks in
+// flight on one XCD then cover a few consecutive planes of one band, so the
+// z neighbours of a cell (read again one and two planes later) are still in
+// that XCD's L2; plane-by-plane order over the whole cross-section evicts
+// them first when a kernel touches many arrays.
+constexpr int CELL_BAND = 4;
+
 __device__ __forceinline__ bool cell_of_thread(const Geom &G, int lb, Cell &P) {
-  const int nbx = (G.n[0] + BX - 1) / BX, nby = (G.n[1] + BY - 1) / BY;
-  int L = lb;
-  const int bx = L % nbx;
-  L /= nbx;
-  P.i = bx * BX + threadIdx.x;
-  P.j = (L % nby) * BY + threadIdx.y;
-  P.k = L / nby;
+  const int nbx = (G.n[0] + BX - 1) / BX, nby = (G.n[1] + BY - 1) / BY, n2 = G.n[2];
+  const int full = nby / CELL_BAND;               // bands of CELL_BAND block rows
+  const int full_blocks = full * nbx * CELL_BAND * n2;
+  int band, rows, r;
+  if (lb < full_blocks) {
+    band = lb / (nbx * CELL_BAND * n2);
+    r = lb - band * (nbx * CELL_BAND * n2);
+    rows = CELL_BAND;
+  } else {
+    band = full;
+    r = lb - full_blocks;
+    rows = nby - full * CELL_BAND;
+  }
+  const int per_plane = nbx * rows;
+  P.k = r / per_plane;
+  r -= P.k * per_plane;
+  const int byl = r / nbx;
+  P.i = (r - byl * nbx) * BX + threadIdx.x;
+  P.j = (band * CELL_BAND + byl) * BY + threadIdx.y;
   P.co[0] = P.i; P.co[1] = P.j; P.co[2] = P.k;
   P.c = cidx(G, P.i, P.j, P.k);
   return P.i < G.n[0] && P.j < G.n[1];
