@@ -846,6 +846,40 @@ __device__ __forceinline__ void coef7(const Op<R> &L, int i, int j, int k, R rc,
   D = T[0] + T[1] + T[2] + T[3] + T[4] + T[5] + rc * db;
 }
 
+// The same row when the neighbour values outside the mesh are zero (as in
+// the LDS planes): T = (rc + rn) hc needs no mask, since its product with a
+// zero iterate vanishes, and D removes the spurious rc hc of each face to
+// the outside again while adding the outlet's Dirichlet part: e = ob - hc
+// per domain side.  hc = c/2 is exact, so T is the same number as h (rc +
+// rn) c; D differs from the masked sum in rounding only.
+template <typename R>
+struct RowK {
+  R hc[3];
+  R e[6];
+};
+template <typename R>
+__device__ __forceinline__ RowK<R> rowk(const Op<R> &L) {
+  RowK<R> K;
+  for (int a = 0; a < 3; a++) K.hc[a] = (R)0.5 * L.c[a];
+  for (int q = 0; q < 6; q++) K.e[q] = L.ob[q] - K.hc[q >> 1];
+  return K;
+}
+template <typename R>
+__device__ __forceinline__ void coefu(const RowK<R> &K, int i, int j, int k, int n0, int n1,
+                                      int n2, R rc, R rxm, R rxp, R rym, R ryp, R rzm, R rzp,
+                                      R T[6], R &D) {
+  T[0] = (rc + rxm) * K.hc[0];
+  T[1] = (rc + rxp) * K.hc[0];
+  T[2] = (rc + rym) * K.hc[1];
+  T[3] = (rc + ryp) * K.hc[1];
+  T[4] = (rc + rzm) * K.hc[2];
+  T[5] = (rc + rzp) * K.hc[2];
+  const R db = (i == 0 ? K.e[0] : (R)0) + (i + 1 == n0 ? K.e[1] : (R)0) +
+               (j == 0 ? K.e[2] : (R)0) + (j + 1 == n1 ? K.e[3] : (R)0) +
+               (k == 0 ? K.e[4] : (R)0) + (k + 1 == n2 ? K.e[5] : (R)0);
+  D = T[0] + T[1] + T[2] + T[3] + T[4] + T[5] + rc * db;
+}
+
 // Planes of a W x TY2 tile staged in LDS with a ring of one 16-byte vector
 // in x and RY rows in y (zero outside the mesh).  Thread t loads vectors t,
 // t + NT2, ... of a plane into registers one plane step before it stores
@@ -1342,20 +1376,27 @@ __global__ void __launch_bounds__(NT2) k_sweep25(OpB<R> LB, SH S, const B *__res
   };
   const bool ringer = t < NRING;
   // new A value at (lx, ly) of plane k from LDS neighbours
+  const RowK<R> K = rowk(L);
+  // new A value at (lx, ly) of plane k from LDS neighbours (zero outside
+  // the mesh; computed without a branch and selected)
   auto relax_a = [&](int lx, int ly, int k) -> R {
     const int i = x0 + lx, jj = y0 + ly;
-    if (!inside(i, jj, k)) return (R)0;
     const R bb = sB[xs(k) * NX + PL::at(lx, ly)];
     const R *Xm = sX + xs(k - 1) * NX, *Xc = sX + xs(k) * NX, *Xp = sX + xs(k + 1) * NX;
     const R *Rm = sR + xs(k - 1) * NX, *Rc = sR + xs(k) * NX, *Rp = sR + xs(k + 1) * NX;
     const int c2 = PL::at(lx, ly);
     R T[6], D;
-    coef7(L, i, jj, k, Rc[c2], Rc[c2 - 1], Rc[c2 + 1], Rc[c2 - FXR], Rc[c2 + FXR], Rm[c2],
-          Rp[c2], T, D);
-    if (MODE == SW_ZERO) return D > (R)0 ? bb * sw_rcp(D) : (R)0;
-    const R off = T[0] * Xc[c2 - 1] + T[1] * Xc[c2 + 1] + T[2] * Xc[c2 - FXR] +
-                  T[3] * Xc[c2 + FXR] + T[4] * Xm[c2] + T[5] * Xp[c2];
-    return D > (R)0 ? (bb + off) * sw_rcp(D) : (R)0;
+    coefu(K, i, jj, k, n0, n1, n2, Rc[c2], Rc[c2 - 1], Rc[c2 + 1], Rc[c2 - FXR], Rc[c2 + FXR],
+          Rm[c2], Rp[c2], T, D);
+    R v;
+    if (MODE == SW_ZERO) {
+      v = bb * sw_rcp(D);
+    } else {
+      const R off = T[0] * Xc[c2 - 1] + T[1] * Xc[c2 + 1] + T[2] * Xc[c2 - FXR] +
+                    T[3] * Xc[c2 + FXR] + T[4] * Xm[c2] + T[5] * Xp[c2];
+      v = (bb + off) * sw_rcp(D);
+    }
+    return inside(i, jj, k) && D > (R)0 ? v : (R)0;
   };
   P2<R> r_m2 = {(R)0, (R)0}, r_m1 = {(R)0, (R)0}, r_0;
   R a_m2 = (R)0, a_m1 = (R)0, a_0;
@@ -1392,7 +1433,8 @@ __global__ void __launch_bounds__(NT2) k_sweep25(OpB<R> LB, SH S, const B *__res
         const R *Ac = sA + (kb & 1) * NX1;
         const int c1 = I1(lxB, ty);
         R T[6], D;
-        coef7(L, iB, j, kb, rbc, rbxm, rbxp, rbym, rbyp, r_m2.get(offA), r_0.get(offA), T, D);
+        coefu(K, iB, j, kb, n0, n1, n2, rbc, rbxm, rbxp, rbym, rbyp, r_m2.get(offA),
+              r_0.get(offA), T, D);
         const R off = T[0] * Ac[c1 - 1] + T[1] * Ac[c1 + 1] + T[2] * Ac[c1 - FX1] +
                       T[3] * Ac[c1 + FX1] + T[4] * a_m2 + T[5] * a_0;
         vB = D > (R)0 ? (bB + off) * sw_rcp(D) : (R)0;
