@@ -52,10 +52,14 @@ def alg_bytes_per_cell(cls: str, rsize: int, fused: bool = False) -> float:
         "prolong_fine": 4 * s + s / 8.0,
         # red residuals only: x and rAU read, red b read, coarse b written
         "restrict_fine": 2 * s + 0.5 * s + s / 8.0,
-        "spmv": 24.0,                  # rAU, p read; q written (FP64)
-        "axpy": 48.0,                  # x, p, r, q read; x, r written
+        # direction update fused in: z (s), old p and rAU read; new p and q
+        # written (FP64), and z_old (s) in flexible (mixed) CG
+        "spmv": 32.0 + s + (s if s == 4 else 0.0),
+        # true residual r = b - A x: x, rAU, b read; r (and its FP32 copy) written
+        "residual": 32.0 + (4.0 if s == 4 else 0.0),
+        # x, p, r, q read; x, r (and the FP32 copy of r) written
+        "axpy": 48.0 + (4.0 if s == 4 else 0.0),
         "dot": 8.0 + s + (s if s == 4 else 0.0),
-        "xpby": 8.0 + s + 8.0 + (s if s == 4 else 0.0),
     }.get(cls, 0.0)
 
 

@@ -24,7 +24,7 @@ static const char *kNames[KC_COUNT] = {
     "mom_offdiag", "phihbya",     "correct",     "spmv",         "axpy",
     "dot",         "xpby",        "finalize",    "smooth_fine",  "restrict_fine",
     "prolong_fine", "smooth_coarse", "restrict_coarse", "prolong_coarse", "coarse_solve",
-    "build_coarse", "stats",      "misc",        "smooth_fine_zero"};
+    "build_coarse", "stats",      "misc",        "smooth_fine_zero", "residual"};
 
 void prof_begin(Handle *h, int cls) {
   Timer &t = h->tm;
@@ -452,7 +452,7 @@ static int create_impl(int n, const dbs_grid *grids, const dbs_physics *phys, co
   h->rAU = dmalloc(h, NC, rc); h->Sh = dmalloc(h, 3 * NC, rc); h->B = dmalloc(h, 3 * NC, rc);
   h->HbyA = dmalloc(h, 3 * NC, rc); h->phiH = dmalloc(h, NF, rc); h->rhs = dmalloc(h, NC, rc);
   h->r = dmalloc(h, NC, rc); h->z = dmalloc(h, NC, rc); h->pv = dmalloc(h, NC, rc);
-  h->q = dmalloc(h, NC, rc);
+  h->q = dmalloc(h, NC, rc); h->pv2 = dmalloc(h, NC, rc);
   h->scal = dmalloc(h, (size_t)NSC * n, rc);
   h->sstat = dmalloc(h, 5 * (size_t)n, rc);
   h->rec = dmalloc(h, (size_t)n * 16 * 3, rc);

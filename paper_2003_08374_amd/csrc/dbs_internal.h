@@ -23,7 +23,7 @@ enum KClass {
   KC_SPMV, KC_AXPY, KC_DOT, KC_XPBY, KC_FINALIZE,
   KC_SMOOTH0, KC_RESTRICT0, KC_PROLONG0,
   KC_SMOOTHC, KC_RESTRICTC, KC_PROLONGC, KC_COARSE, KC_BUILD_COARSE,
-  KC_STATS, KC_MISC, KC_SMOOTH0_ZERO, KC_COUNT
+  KC_STATS, KC_MISC, KC_SMOOTH0_ZERO, KC_RESIDUAL, KC_COUNT
 };
 
 constexpr int FLAT_T = 256;               // threads of a vector-kernel block
@@ -124,6 +124,7 @@ struct Handle {
   double *rhs = nullptr;
   // PCG vectors
   double *r = nullptr, *z = nullptr, *pv = nullptr, *q = nullptr;
+  double *pv2 = nullptr;  // CG directions alternate between pv and pv2
   float *rf = nullptr;     // FP32 residual (mixed precision)
   float *zoldf = nullptr;  // previous preconditioned residual (flexible CG)
   float *zf2 = nullptr;    // second fine correction buffer (FP32 V-cycle)

@@ -259,25 +259,6 @@ __global__ void __launch_bounds__(FLAT_T) k_dot2(FL F, const double *__restrict_
   }
 }
 
-// p = z + beta p (first: p = z); flexible CG keeps zold = z
-template <typename Z>
-__global__ void __launch_bounds__(FLAT_T) k_xpby(FL F, const double *__restrict__ scal,
-                                                 const Z *__restrict__ zz,
-                                                 double *__restrict__ p, int first,
-                                                 Z *__restrict__ zold,
-                                                 const int *__restrict__ act) {
-  const int s = find_seg(F.bp, F.ns, blockIdx.x);
-  if (!act[s]) return;
-  const double be = first ? 0.0 : scal[s * NSC + S_BETA];
-#pragma unroll
-  for (int m = 0; m < FLAT_CELLS / FLAT_T; m++) {
-    const size_t c = flat_cell(m);
-    const Z zc = zz[c];
-    p[c] = first ? (double)zc : fma(be, p[c], (double)zc);
-    if (zold) zold[c] = zc;
-  }
-}
-
 template <typename R>
 __global__ void __launch_bounds__(FLAT_T) k_cast(const double *__restrict__ in,
                                                  R *__restrict__ out) {
@@ -1046,21 +1027,64 @@ __device__ __forceinline__ R off25(const R T[6], int lx, int ty, const R *sx, R 
          T[2] * sx[LIX(W, lx, ty - 1)] + T[3] * sx[LIX(W, lx, ty + 1)] + T[4] * xm + T[5] * xp;
 }
 
-// MODE 0: q = A p and partial p.q;  MODE 1: r = b - A p (and its FP32 copy)
-// and partials r.r, b.b.  64 x 8 tiles walk up to kz planes; p, rAU (and b)
-// are staged in LDS slots one plane ahead (one cell per thread).
-template <int MODE>
+// two cells of the preconditioned residual z in the raw loaded form (kept
+// unconverted until the plane is stored)
+template <typename Z> struct ZPair;
+template <> struct ZPair<float> {
+  using T = unsigned __attribute__((ext_vector_type(2)));
+  __device__ static T ld(const Buf &B, unsigned off) {
+    return __builtin_amdgcn_raw_buffer_load_b64(B.r, off, 0, 0);
+  }
+  __device__ static double get(const T &v, int u) { return (double)__uint_as_float(v[u]); }
+  __device__ static T one(const Buf &B, unsigned off, T v, int u) {
+    v[u] = __builtin_amdgcn_raw_buffer_load_b32(B.r, off, 0, 0);
+    return v;
+  }
+};
+template <> struct ZPair<double> {
+  using T = unsigned __attribute__((ext_vector_type(4)));
+  __device__ static T ld(const Buf &B, unsigned off) {
+    return __builtin_amdgcn_raw_buffer_load_b128(B.r, off, 0, 0);
+  }
+  __device__ static double get(const T &v, int u) {
+    return __hiloint2double((int)v[2 * u + 1], (int)v[2 * u]);
+  }
+  __device__ static T one(const Buf &B, unsigned off, T v, int u) {
+    const auto w = __builtin_amdgcn_raw_buffer_load_b64(B.r, off, 0, 0);
+    v[2 * u] = w[0];
+    v[2 * u + 1] = w[1];
+    return v;
+  }
+};
+
+// MODE 0: q = A p and partial p.q.  MODE 1: r = b - A p (and its FP32 copy)
+// and partials r.r, b.b.  MODE 2: the CG direction update fused in front of
+// MODE 0: p_new = z + beta p (p_new = z when first) is formed while the
+// planes are staged (ring cells included, from z and the old p, which no
+// block writes), written for the tile's own cells to a second buffer with
+// the copy z_old = z of flexible CG, and q = A p_new, p_new.q follow.
+// 64 x 8 tiles walk up to kz planes; the inputs are staged in LDS slots,
+// two planes in flight (one cell per thread).
+template <int MODE, typename Z = double>
 __global__ void __launch_bounds__(NT2) k_stencil25(OpB<double> LB, SH S,
                                                    const double *__restrict__ p,
                                                    const double *__restrict__ b,
                                                    double *__restrict__ out,
                                                    float *__restrict__ outf,
                                                    double *__restrict__ partials, int off2,
-                                                   const int *__restrict__ mask) {
+                                                   const int *__restrict__ mask,
+                                                   const Z *__restrict__ z = nullptr,
+                                                   double *__restrict__ pnew = nullptr,
+                                                   Z *__restrict__ zold = nullptr,
+                                                   const double *__restrict__ scal = nullptr,
+                                                   int first = 0) {
   constexpr int W = 64, NS = 4, NSB = 3;
   using PL = Pl1<double, W>;
   using VT = typename Vec16<double>::T;
-  constexpr int NX = PL::NX, FXR = PL::FXR;
+  using ZP = ZPair<Z>;
+  using ZT = typename ZP::T;
+  constexpr int NX = PL::NX, FXR = PL::FXR, RV = FXR / PL::VEC;
+  static_assert(PL::VEC == 2, "two cells per staged vector");
   __shared__ __align__(16) double sp[NS * NX], sr[NS * NX];
   __shared__ __align__(16) double sb[MODE == 1 ? NSB * NX : 2];
   __shared__ double lred[NT2 / 64];
@@ -1072,6 +1096,12 @@ __global__ void __launch_bounds__(NT2) k_stencil25(OpB<double> LB, SH S,
   if (MODE == 1) b += c0;
   out += c0;
   if (outf) outf += c0;
+  if (MODE == 2) {
+    z += c0;
+    pnew += c0;
+    if (zold) zold += c0;
+  }
+  const double beta = (MODE == 2 && !first) ? scal[s * NSC + S_BETA] : 0.0;
   const int n0 = L.n0, n1 = L.n1, n2 = L.n2;
   int xb, y0, k0, k1;
   tile_of(lb, n0, n1, n2, W, S.kz, xb, y0, k0, k1);
@@ -1081,6 +1111,7 @@ __global__ void __launch_bounds__(NT2) k_stencil25(OpB<double> LB, SH S,
   const bool in = i < n0 && j < n1;
   const int ncs = n0 * n1 * n2;
   const Buf Bp = mkbuf(p, ncs), Br = mkbuf(L.rAU, ncs), Bb = mkbuf(MODE == 1 ? b : p, ncs);
+  const Buf Bz = mkbuf(MODE == 2 ? z : (const Z *)p, MODE == 2 ? ncs : 0);
   const bool vec_ok = (n0 % PL::VEC) == 0;
   double v1 = 0.0, v2 = 0.0;
   // the body is instantiated for aligned rows (16-byte loads) and not,
@@ -1091,18 +1122,70 @@ __global__ void __launch_bounds__(NT2) k_stencil25(OpB<double> LB, SH S,
     // k+1 is stored from the other and plane k computed
     struct Regs {
       VT p[PL::MV], r[PL::MV], b[PL::MV];
+      ZT z[PL::MV];
     } RA, RB;
     auto load = [&](Regs &G, int k) {
 #pragma unroll
       for (int m = 0; m < PL::MV; m++) {
-        G.p[m] = pl_load<PL, VOK, double>(Bp, t, m, x0, y0, k, n0, n1, n2);
         G.r[m] = pl_load<PL, VOK, double>(Br, t, m, x0, y0, k, n0, n1, n2);
         if (MODE == 1) G.b[m] = pl_load<PL, VOK, double>(Bb, t, m, x0, y0, k, n0, n1, n2);
+        if (MODE == 2) {
+          // z of the same two cells as the p vector (zero outside the mesh)
+          const int e = pl_vec<PL::NV, PL::MV>(t, m);
+          const int ia = x0 - PL::RX + (e % RV) * 2, jj = y0 - 1 + e / RV;
+          const bool inz = jj >= 0 && jj < n1 && k >= 0 && k < n2 && ia + 2 > 0 && ia < n0;
+          const int c = ia + n0 * (jj + n1 * k);
+          if (VOK) {
+            G.z[m] = ZP::ld(Bz, inz ? (unsigned)c * (unsigned)sizeof(Z) : Bz.oob);
+          } else {
+            ZT v = ZT{};
+#pragma unroll
+            for (int u = 0; u < 2; u++) {
+              const bool ok = inz && ia + u >= 0 && ia + u < n0;
+              v = ZP::one(Bz, ok ? (unsigned)(c + u) * (unsigned)sizeof(Z) : Bz.oob, v, u);
+            }
+            G.z[m] = v;
+          }
+        }
+        // (the old p is loaded when first as well, so that every path issues
+        // the same loads; first discards it)
+        G.p[m] = pl_load<PL, VOK, double>(Bp, t, m, x0, y0, k, n0, n1, n2);
       }
     };
-    auto store = [&](const Regs &G, int k) {
+    auto store = [&](Regs &G, int k) {
 #pragma unroll
       for (int m = 0; m < PL::MV; m++) {
+        if (MODE == 2) {
+          // p_new of the vector's two cells; the tile's own cells also go to
+          // memory (planes k0..k1-1, rows y0.., columns x0..x0+63)
+          const double z0 = ZP::get(G.z[m], 0), z1 = ZP::get(G.z[m], 1);
+          VT pn;
+          pn.x = first ? z0 : fma(beta, G.p[m].x, z0);
+          pn.y = first ? z1 : fma(beta, G.p[m].y, z1);
+          G.p[m] = pn;
+          const int e = pl_vec<PL::NV, PL::MV>(t, m);
+          const int lx = (e % RV) * 2 - PL::RX, ly = e / RV - 1;
+          const int ia = x0 + lx, jj = y0 + ly;
+          const bool own = k >= k0 && k < k1 && lx >= 0 && lx < W && ly >= 0 && ly < TY2 &&
+                           jj < n1 && ia < n0 && e == t + m * NT2;
+          if (own) {
+            const int c = ia + n0 * (jj + n1 * k);
+            if (VOK) {
+              *reinterpret_cast<VT *>(pnew + c) = pn;
+              if (zold) {
+                zold[c] = (Z)z0;
+                zold[c + 1] = (Z)z1;
+              }
+            } else {
+              pnew[c] = pn.x;
+              if (zold) zold[c] = (Z)z0;
+              if (ia + 1 < n0) {
+                pnew[c + 1] = pn.y;
+                if (zold) zold[c + 1] = (Z)z1;
+              }
+            }
+          }
+        }
         pl_store<PL>(sp + slot_of<NS>(k) * NX, t, m, G.p[m]);
         pl_store<PL>(sr + slot_of<NS>(k) * NX, t, m, G.r[m]);
         if (MODE == 1) pl_store<PL>(sb + slot_of<NSB>(k) * NX, t, m, G.b[m]);
@@ -1123,7 +1206,7 @@ __global__ void __launch_bounds__(NT2) k_stencil25(OpB<double> LB, SH S,
                          T[3] * Pc[c2 + FXR] + T[4] * Pm[c2] + T[5] * Pp[c2];
       const double y = D * pc - off;
       const int c = i + n0 * (j + n1 * k);
-      if (MODE == 0) {
+      if (MODE != 1) {
         out[c] = y;
         v1 += pc * y;
       } else {
@@ -2120,7 +2203,7 @@ static void true_residual(Handle *h, const double *rAU, const double *b, const d
                           float *rf, const int *mask) {
   const Shape &Z = h->lv[0].st;
   OpB<double> o = opb<double>(h, 0, rAU);
-  DBS_LAUNCH(h, KC_SPMV, k_stencil25<1>, dim3(Z.nblk), blk2(), o, sh(h, Z), x, b, h->r, rf,
+  DBS_LAUNCH(h, KC_RESIDUAL, k_stencil25<1>, dim3(Z.nblk), blk2(), o, sh(h, Z), x, b, h->r, rf,
              h->partials, (int)Z.nblk, mask);
   finalize(h, fin_args(h, &Z, 1, S_RR, S_BB, FIN_STORE, mask));
   if (any_closed(h)) {
@@ -2196,16 +2279,19 @@ static int pcg(Handle *h, const double *rAU, const double *b, double *x, int bud
     DBS_LAUNCH(h, KC_DOT, k_dot2<R>, fg, ft, F, (const double *)h->r, (const R *)zR,
                (const R *)nullptr, h->partials, (int)h->flat.nblk, act, 0);
     finalize(h, fin_args(h, &h->flat, 0, S_RZ, 0, FIN_STORE, act));
-    DBS_LAUNCH(h, KC_XPBY, k_xpby<R>, fg, ft, F, (const double *)h->scal, (const R *)zR, h->pv,
-               1, zold, act);
+    // the direction update p = z + beta p rides on the SpMV, which reads the
+    // old direction from pc and writes the new one to pn
+    double *pc = h->pv, *pn = h->pv2;
+    const R *zc = zR;
     for (int it = 0;; it++) {
       if (graph && it >= budget) break;
-      DBS_LAUNCH(h, KC_SPMV, k_stencil25<0>, dim3(ST.nblk), blk2(), o, sh(h, ST),
-                 (const double *)h->pv, (const double *)nullptr, h->q, (float *)nullptr,
-                 h->partials, 0, act);
+      DBS_LAUNCH(h, KC_SPMV, (k_stencil25<2, R>), dim3(ST.nblk), blk2(), o, sh(h, ST),
+                 (const double *)pc, (const double *)nullptr, h->q, (float *)nullptr,
+                 h->partials, 0, act, zc, pn, zold, (const double *)h->scal, it == 0 ? 1 : 0);
+      std::swap(pc, pn);
       finalize(h, fin_args(h, &ST, 0, S_PQ, 0, FIN_ALPHA, act));
       DBS_LAUNCH(h, KC_AXPY, k_axpy_dot, fg, ft, F, (const double *)h->scal,
-                 (const double *)h->pv, (const double *)h->q, x, h->r, rf, h->partials, act);
+                 (const double *)pc, (const double *)h->q, x, h->r, rf, h->partials, act);
       finalize(h, fin_args(h, &h->flat, 0, S_RR, 0, FIN_RR, act));
       int nwant = 1;
       if (!graph) nact = fetch_flags(h, &nwant);
@@ -2226,8 +2312,7 @@ static int pcg(Handle *h, const double *rAU, const double *b, double *x, int bud
                    (const R *)nullptr, h->partials, (int)h->flat.nblk, act, 0);
         finalize(h, fin_args(h, &h->flat, 0, S_RZNEW, 0, FIN_BETA, act));
       }
-      DBS_LAUNCH(h, KC_XPBY, k_xpby<R>, fg, ft, F, (const double *)h->scal, (const R *)zn,
-                 h->pv, 0, zold, act);
+      zc = zn;
     }
   }
   if (any_closed(h)) remove_mean(h, x, nullptr, nullptr);
