@@ -228,7 +228,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched leg")
     ap.add_argument("--no-flume", action="store_true", help="skip the wave-flume batch leg")
     ap.add_argument("--batch-samples", type=int, default=512)
-    ap.add_argument("--coarse-sweeps", type=int, default=2)
+    ap.add_argument("--coarse-sweeps", type=int, default=3)
     ap.add_argument("--fused", type=int, default=1,
                     help="1: fused full sweeps on the fine level (else half sweeps)")
     ap.add_argument("--copy-calibration", action="store_true",

@@ -220,9 +220,9 @@ int dbs_set_graph(dbs_handle *h, int on);
 /* Autotuner: times the pressure solve of the current state's first
    corrector under candidate settings and keeps the fastest that converges:
    red-black sweeps on the finest level (1..3, pre = post) with the same
-   count on the coarse levels, then one sweep on the coarse levels, the
-   depth at which the single work-group bottom takes over (bottom_shift 0
-   or 1 levels coarser than the first that fits in LDS), fused full sweeps
+   count on the coarse levels and the depth at which the single work-group
+   bottom takes over (bottom_shift 0 or 1 levels coarser than the first that
+   fits in LDS), then 1..4 sweeps on the coarse levels, fused full sweeps
    on the finest level or two half-sweep launches, then the planes per
    fine-level tile (kz 2..16).  The state is unchanged afterwards.  Outputs
    may be NULL; *ms receives the best solve time in milliseconds. */

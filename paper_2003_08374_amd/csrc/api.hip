@@ -939,7 +939,11 @@ int dbs_autotune(dbs_handle *H, int *kz_out, int *sweeps_out, int *coarse_out, i
   };
   for (int sw = 1; sw <= 3; sw++)
     for (int shf = 0; shf <= 1; shf++) trial(Cand{0, sw, sw, shf, 1});
-  trial(Cand{0, best.sweeps, 1, best.shift, 1});
+  {
+    const Cand b0 = best;
+    for (int cs = 1; cs <= 4; cs++)
+      if (cs != b0.coarse) trial(Cand{0, b0.sweeps, cs, b0.shift, 1});
+  }
   trial(Cand{0, best.sweeps, best.coarse, best.shift, 0});
   const Cand mid = best;
   for (int kz : {2, 4, 8, 16}) trial(Cand{kz, mid.sweeps, mid.coarse, mid.shift, mid.fused});

@@ -65,11 +65,13 @@ struct Level {
   float *Txf = nullptr, *Tyf = nullptr, *Tzf = nullptr, *Dbf = nullptr, *Df = nullptr;
   double *x = nullptr, *b = nullptr;  // correction and right-hand side
   float *xf = nullptr, *bf = nullptr;
+  float *xf2 = nullptr;  // second FP32 correction buffer (fused coarse sweeps)
   // launch shapes: fine level
   Shape st, sm, rs;
   // coarse levels: every sample holding the level; samples cycled on it by
   // grid kernels (pairs and single cells); samples restricted into it
   Shape one_all, pair_cyc, one_cyc, one_rc;
+  Shape sw;  // coarse levels: 2.5-D tiles of the cycled samples (fused sweeps)
 };
 
 struct Timer {
@@ -144,7 +146,7 @@ struct Handle {
   void *btab = nullptr;      // device table of bottom descriptors
   int nbt = 0;               // samples with a bottom (>= 2 levels)
   int mg_pre = 2, mg_post = 2, coarse_sweeps = 16;
-  int mgc = 2;  // sweeps per coarse level (pre = post), bottom levels included
+  int mgc = 3;  // sweeps per coarse level (pre = post), bottom levels included
   // tuning knobs (autotuner): fine tile depth (0 = heuristic), bottom shift,
   // fused full sweeps on the fine level (else two half-sweep launches)
   int kz_fine = 0, bottom_shift = 0, fused_sweep = 1;

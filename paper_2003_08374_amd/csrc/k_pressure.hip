@@ -733,6 +733,7 @@ constexpr int TY2 = 8;
 constexpr int KZ2 = 16;
 constexpr int NT2 = 64 * TY2;
 constexpr int MIN_BLOCKS2 = 1024;
+constexpr int MIN_BLOCKS_CSW = 256;  // fused coarse sweeps (one block per CU)
 
 __host__ __device__ inline int tiles25(int n0, int n1, int n2, int W, int kz) {
   return ((n0 + W - 1) / W) * ((n1 + TY2 - 1) / TY2) * ((n2 + kz - 1) / kz);
@@ -1382,7 +1383,10 @@ __device__ __forceinline__ void ring_cell(int r, int x0, int y0, int k, int colA
 // MODE SW_ZERO: the iterate starts at zero (xin unused).  SW_PROLONG: the
 // iterate is xin plus the coarse correction of each cell's parent (when the
 // sample has a coarse level).  colA: colour relaxed first.  xout != xin.
-template <typename R, typename B, int MODE>
+// OPK 0: the fine level (rows rebuilt from rAU); OPK 1: a coarse level with
+// stored face coefficients Tx, Ty, Tz (zero on domain faces) and diagonal D,
+// staged like rAU.
+template <typename R, typename B, int MODE, int OPK = 0>
 __global__ void __launch_bounds__(NT2) k_sweep25(OpB<R> LB, SH S, const B *__restrict__ b,
                                                  const R *__restrict__ xin,
                                                  R *__restrict__ xout, int colA,
@@ -1392,7 +1396,8 @@ __global__ void __launch_bounds__(NT2) k_sweep25(OpB<R> LB, SH S, const B *__res
   using VT = typename Vec16<R>::T;
   constexpr int VEC = PL::VEC, NX = PL::NX, FXR = PL::FXR;
   __shared__ __align__(16) R sX[3 * NX];   // old x, planes k-1, k, k+1 (slot k mod 3)
-  __shared__ __align__(16) R sR[3 * NX];   // rAU, planes k-1, k, k+1 (slot k mod 3)
+  constexpr int NR = OPK ? 4 : 1;          // coefficient arrays: rAU, or Tx Ty Tz D
+  __shared__ __align__(16) R sR[3 * NR * NX];  // array q, plane k at slot 3 q + k mod 3
   __shared__ __align__(16) R sB[3 * NX];   // right-hand side, planes k-1, k, k+1
   static_assert(std::is_same<R, B>::value, "the right-hand side is staged as R");
   __shared__ R sA[2 * NX1];                // new A values, planes k-1, k (slot k mod 2)
@@ -1411,8 +1416,9 @@ __global__ void __launch_bounds__(NT2) k_sweep25(OpB<R> LB, SH S, const B *__res
   const int x0 = xb * FW;
   const int tx = threadIdx.x, ty = threadIdx.y, t = tx + 64 * ty;
   const int i0 = x0 + 2 * tx, j = y0 + ty;
-  const R *rA = L.rAU;
-  const bool vec_ok = n0 % VEC == 0;  // rows then start on 16-byte boundaries
+  const R *rA = OPK ? L.D : L.rAU;
+  // rows start on 16-byte boundaries
+  const bool vec_ok = n0 % VEC == 0 && Q.c0 % VEC == 0;
   auto inside = [&](int i, int jj, int k) {
     return i >= 0 && i < n0 && jj >= 0 && jj < n1 && k >= 0 && k < n2;
   };
@@ -1422,8 +1428,17 @@ __global__ void __launch_bounds__(NT2) k_sweep25(OpB<R> LB, SH S, const B *__res
   // a loaded value before the next plane step (the loads stay in flight
   // while the current plane is relaxed).
   const int ncs = n0 * n1 * n2;
-  const Buf Bx = mkbuf(MODE == SW_ZERO ? rA : xin, ncs), Br = mkbuf(rA, ncs),
-            Bb = mkbuf(b, ncs);
+  const Buf Bx = mkbuf(MODE == SW_ZERO ? rA : xin, ncs), Bb = mkbuf(b, ncs);
+  Buf Br[NR];
+  if constexpr (OPK) {
+    Br[0] = mkbuf(L.Tx, ncs);
+    Br[1] = mkbuf(L.Ty, ncs);
+    Br[2] = mkbuf(L.Tz, ncs);
+    Br[3] = mkbuf(L.D, ncs);
+  } else {
+    Br[0] = mkbuf(rA, ncs);
+  }
+  auto sr = [&](int q, int k) -> R * { return sR + (3 * q + xs(k)) * NX; };
   const Buf Bc = mkbuf(xcs ? xcs : rA, xcs ? cn0 * cn1 * Q.cn2 : 0);
   // coarse correction of the parents of vector m of plane k
   auto parent = [&](int m, int k, auto vok) -> VT {
@@ -1466,11 +1481,22 @@ __global__ void __launch_bounds__(NT2) k_sweep25(OpB<R> LB, SH S, const B *__res
     const int i = x0 + lx, jj = y0 + ly;
     const R bb = sB[xs(k) * NX + PL::at(lx, ly)];
     const R *Xm = sX + xs(k - 1) * NX, *Xc = sX + xs(k) * NX, *Xp = sX + xs(k + 1) * NX;
-    const R *Rm = sR + xs(k - 1) * NX, *Rc = sR + xs(k) * NX, *Rp = sR + xs(k + 1) * NX;
     const int c2 = PL::at(lx, ly);
     R T[6], D;
-    coefu(K, i, jj, k, n0, n1, n2, Rc[c2], Rc[c2 - 1], Rc[c2 + 1], Rc[c2 - FXR], Rc[c2 + FXR],
-          Rm[c2], Rp[c2], T, D);
+    if constexpr (OPK) {
+      const R *Tx = sr(0, k), *Ty = sr(1, k);
+      T[0] = Tx[c2 - 1];
+      T[1] = Tx[c2];
+      T[2] = Ty[c2 - FXR];
+      T[3] = Ty[c2];
+      T[4] = sr(2, k - 1)[c2];
+      T[5] = sr(2, k)[c2];
+      D = sr(3, k)[c2];
+    } else {
+      const R *Rm = sr(0, k - 1), *Rc = sr(0, k), *Rp = sr(0, k + 1);
+      coefu(K, i, jj, k, n0, n1, n2, Rc[c2], Rc[c2 - 1], Rc[c2 + 1], Rc[c2 - FXR],
+            Rc[c2 + FXR], Rm[c2], Rp[c2], T, D);
+    }
     R v;
     if (MODE == SW_ZERO) {
       v = bb * sw_rcp(D);
@@ -1487,14 +1513,27 @@ __global__ void __launch_bounds__(NT2) k_sweep25(OpB<R> LB, SH S, const B *__res
   // k, k+1 in LDS)
   auto relax_planes = [&](int k) {
     const int offA = ((j + k) & 1) == colA ? 0 : 1;  // x0 and 2 tx are even
-    // own column: rAU of plane k; rAU around the own B cell of plane k-1
-    const R *Rk = sR + xs(k) * NX;
+    // own column: rAU (OPK 1: Tz) of plane k; the coefficients around the
+    // own B cell of plane k-1
+    const R *Rk = sr(OPK ? 2 : 0, k);
     r_0 = P2<R>{Rk[PL::at(2 * tx, ty)], Rk[PL::at(2 * tx + 1, ty)]};
     const int lxB = 2 * tx + offA;  // B cell of plane k-1 = A position of plane k
-    const R *Rb = sR + xs(k - 1) * NX;
     const int cb = PL::at(lxB, ty);
-    const R rbc = Rb[cb], rbxm = Rb[cb - 1], rbxp = Rb[cb + 1], rbym = Rb[cb - FXR],
-            rbyp = Rb[cb + FXR];
+    R rbc, rbxm, rbxp, rbym, rbyp;
+    if constexpr (OPK) {
+      rbxm = sr(0, k - 1)[cb - 1];
+      rbxp = sr(0, k - 1)[cb];
+      rbym = sr(1, k - 1)[cb - FXR];
+      rbyp = sr(1, k - 1)[cb];
+      rbc = sr(3, k - 1)[cb];
+    } else {
+      const R *Rb = sr(0, k - 1);
+      rbc = Rb[cb];
+      rbxm = Rb[cb - 1];
+      rbxp = Rb[cb + 1];
+      rbym = Rb[cb - FXR];
+      rbyp = Rb[cb + FXR];
+    }
     // (read before the barrier: the next plane step overwrites plane k-1's slot)
     const R bB = sB[xs(k - 1) * NX + cb];
     // A cells of plane k: own, then one ring cell
@@ -1516,8 +1555,18 @@ __global__ void __launch_bounds__(NT2) k_sweep25(OpB<R> LB, SH S, const B *__res
         const R *Ac = sA + (kb & 1) * NX1;
         const int c1 = I1(lxB, ty);
         R T[6], D;
-        coefu(K, iB, j, kb, n0, n1, n2, rbc, rbxm, rbxp, rbym, rbyp, r_m2.get(offA),
-              r_0.get(offA), T, D);
+        if constexpr (OPK) {
+          T[0] = rbxm;
+          T[1] = rbxp;
+          T[2] = rbym;
+          T[3] = rbyp;
+          T[4] = r_m2.get(offA);  // Tz of plane k-2: the face below plane k-1
+          T[5] = r_m1.get(offA);
+          D = rbc;
+        } else {
+          coefu(K, iB, j, kb, n0, n1, n2, rbc, rbxm, rbxp, rbym, rbyp, r_m2.get(offA),
+                r_0.get(offA), T, D);
+        }
         const R off = T[0] * Ac[c1 - 1] + T[1] * Ac[c1 + 1] + T[2] * Ac[c1 - FX1] +
                       T[3] * Ac[c1 + FX1] + T[4] * a_m2 + T[5] * a_0;
         vB = D > (R)0 ? (bB + off) * sw_rcp(D) : (R)0;
@@ -1555,13 +1604,15 @@ __global__ void __launch_bounds__(NT2) k_sweep25(OpB<R> LB, SH S, const B *__res
   auto run = [&](auto vok) {
     constexpr bool VOK = decltype(vok)::value;
     struct Regs {
-      VT x[PL::MV], r[PL::MV], b[PL::MV], c[PL::MV];
+      VT x[PL::MV], r[NR][PL::MV], b[PL::MV], c[PL::MV];
     } RA, RB;
     auto load_planes = [&](Regs &G, int k) {
 #pragma unroll
       for (int m = 0; m < PL::MV; m++) {
         if (MODE != SW_ZERO) G.x[m] = pl_load<PL, VOK, R>(Bx, t, m, x0, y0, k, n0, n1, n2);
-        G.r[m] = pl_load<PL, VOK, R>(Br, t, m, x0, y0, k, n0, n1, n2);
+#pragma unroll
+        for (int q = 0; q < NR; q++)
+          G.r[q][m] = pl_load<PL, VOK, R>(Br[q], t, m, x0, y0, k, n0, n1, n2);
         G.b[m] = pl_load<PL, VOK, R>(Bb, t, m, x0, y0, k, n0, n1, n2);
         if (MODE == SW_PROLONG) G.c[m] = parent(m, k, vok);
       }
@@ -1575,7 +1626,8 @@ __global__ void __launch_bounds__(NT2) k_sweep25(OpB<R> LB, SH S, const B *__res
               vadd(G.x[m], VOK ? vspread(G.c[m]) : G.c[m]);
         else if (MODE != SW_ZERO)
           *reinterpret_cast<VT *>(sX + xs(k) * NX + e * VEC) = G.x[m];
-        *reinterpret_cast<VT *>(sR + xs(k) * NX + e * VEC) = G.r[m];
+#pragma unroll
+        for (int q = 0; q < NR; q++) *reinterpret_cast<VT *>(sr(q, k) + e * VEC) = G.r[q][m];
         *reinterpret_cast<VT *>(sB + xs(k) * NX + e * VEC) = G.b[m];
       }
     };
@@ -1865,6 +1917,20 @@ int pressure_retune(Handle *h) {
     shape_of(L.pair_cyc, true, [&](int s) { return nlev(s) > l && h->bottom[s] > l; });
     shape_of(L.one_cyc, false, [&](int s) { return nlev(s) > l && h->bottom[s] > l; });
     shape_of(L.one_rc, false, [&](int s) { return l >= 2 && nlev(s) > l && h->bottom[s] >= l; });
+    // fused coarse sweeps: about a block per CU (the kernel's LDS holds one)
+    {
+      auto cyc = [&](int s) { return nlev(s) > l && h->bottom[s] > l; };
+      auto total = [&](int kz) {
+        long long t = 0;
+        for (int s = 0; s < ns; s++)
+          if (cyc(s)) t += tiles25(L.hs[s].n0, L.hs[s].n1, L.hs[s].n2, 128, kz);
+        return t;
+      };
+      const int kz = pick_kz(1, KZ2, MIN_BLOCKS_CSW, total);
+      for (int s = 0; s < ns; s++)
+        blocks[s] = cyc(s) ? tiles25(L.hs[s].n0, L.hs[s].n1, L.hs[s].n2, 128, kz) : 0;
+      set_shape(h, L.sw, blocks, kz, rc);
+    }
   }
   if (rc) return rc;
   // bottom table (one work-group per sample with a coarse level)
@@ -1941,7 +2007,8 @@ int pressure_setup(Handle *h) {
         Q.c0 = G.c0;
       } else {
         Q.c0 = (int)off;
-        off += (long long)Q.n0 * Q.n1 * Q.n2;
+        // next sample on a 4-cell boundary: its rows may use 16-byte loads
+        off += ((long long)Q.n0 * Q.n1 * Q.n2 + 3) & ~3LL;
       }
     }
     L.nc = l == 0 ? h->NC : off;
@@ -1967,6 +2034,7 @@ int pressure_setup(Handle *h) {
     if (mixed) {
       L.Txf = (float *)Tx; L.Tyf = (float *)Ty; L.Tzf = (float *)Tz; L.Dbf = (float *)Db;
       L.Df = (float *)D; L.xf = (float *)x; L.bf = (float *)b;
+      L.xf2 = (float *)dalloc(h, n * s, rc);
     } else {
       L.Tx = (double *)Tx; L.Ty = (double *)Ty; L.Tz = (double *)Tz; L.Db = (double *)Db;
       L.D = (double *)D; L.x = (double *)x; L.b = (double *)b;
@@ -2072,6 +2140,25 @@ static void sweep_fine(Handle *h, const OpB<R> &o, const B *b, const R *xin, R *
                colA, xc, m);
 }
 
+// one fused sweep on coarse level l (FP32, stored coefficients), xin -> xout
+static void sweep_coarse(Handle *h, int l, const OpB<float> &o, const float *b,
+                         const float *xin, float *xout, int colA, int mode, const float *xc) {
+  const Shape &Z = h->lv[l].sw;
+  if (!Z.nblk) return;
+  const dim3 g(Z.nblk);
+  const SH S = sh(h, Z);
+  const int *m = h->act;
+  if (mode == SW_ZERO)
+    DBS_LAUNCH(h, KC_SMOOTHC, (k_sweep25<float, float, SW_ZERO, 1>), g, blk2(), o, S, b, xin,
+               xout, colA, xc, m);
+  else if (mode == SW_PROLONG)
+    DBS_LAUNCH(h, KC_SMOOTHC, (k_sweep25<float, float, SW_PROLONG, 1>), g, blk2(), o, S, b,
+               xin, xout, colA, xc, m);
+  else
+    DBS_LAUNCH(h, KC_SMOOTHC, (k_sweep25<float, float, SW_NORMAL, 1>), g, blk2(), o, S, b,
+               xin, xout, colA, xc, m);
+}
+
 // z = M r: one V-cycle over the active samples.  b0 is the fine right-hand
 // side (r); z0 and z1 are the two fine correction buffers; returns the one
 // holding the result.
@@ -2102,14 +2189,36 @@ static R *vcycle(Handle *h, const R *rAUr, const B *b0, R *z0, R *z1) {
     DBS_LAUNCH(h, KC_RESTRICT0, (k_restrict25<R, B>), dim3(Z.nblk), blk2(), o0, sh(h, Z), b0,
                (const R *)cur, lb<R>(h->lv[1]), act);
   }
+  // Coarse levels.  In the FP32 V-cycle with fused sweeps, a level's sweeps
+  // alternate between its two correction buffers; the first (zero guess)
+  // writes xf2, so the 2 mgc sweeps of a cycle end in xf, where the bottom
+  // also leaves its result.  ccur[l] holds the pre-smoothed iterate.
+  constexpr bool flexr = std::is_same<R, float>::value;
+  const bool cfused = flexr && h->fused_sweep;
+  std::vector<R *> ccur(h->lv.size(), nullptr), coth(h->lv.size(), nullptr);
   for (int l = 1; l < h->maxbottom; l++) {
     OpB<R> o = opb<R>(h, l, rAUr);
     Level &L = h->lv[l];
     Level &C = h->lv[l + 1];
-    smooth_level<R, R>(h, l, o, (const R *)lb<R>(L), lx<R>(L), true);
+    ccur[l] = lx<R>(L);
+    if constexpr (flexr) {
+      if (cfused) {
+        R *a = (R *)L.xf2, *b2 = lx<R>(L);
+        sweep_coarse(h, l, o, (const R *)lb<R>(L), (const R *)nullptr, a, 0, SW_ZERO,
+                     (const R *)nullptr);
+        for (int s = 1; s < h->mgc; s++) {
+          sweep_coarse(h, l, o, (const R *)lb<R>(L), (const R *)a, b2, 0, SW_NORMAL,
+                       (const R *)nullptr);
+          std::swap(a, b2);
+        }
+        ccur[l] = a;
+        coth[l] = b2;
+      }
+    }
+    if (!cfused) smooth_level<R, R>(h, l, o, (const R *)lb<R>(L), lx<R>(L), true);
     if (C.one_rc.nblk)
       DBS_LAUNCH(h, KC_RESTRICTC, (k_restrict<R, R>), dim3(C.one_rc.nblk), blk(), o,
-                 sh(h, C.one_rc), (const R *)lb<R>(L), (const R *)lx<R>(L), lb<R>(C), act);
+                 sh(h, C.one_rc), (const R *)lb<R>(L), (const R *)ccur[l], lb<R>(C), act);
   }
   if (h->nbt)
     DBS_LAUNCH(h, KC_COARSE, k_bottom<R>, dim3(h->nbt), dim3(1024),
@@ -2118,6 +2227,18 @@ static R *vcycle(Handle *h, const R *rAUr, const B *b0, R *z0, R *z1) {
     OpB<R> o = opb<R>(h, l, rAUr);
     Level &L = h->lv[l];
     Level &C = h->lv[l + 1];
+    if constexpr (flexr) {
+      if (cfused) {
+        // the prolongation rides on the first (black) sweep
+        R *a = ccur[l], *b2 = coth[l];
+        for (int s = 0; s < h->mgc; s++) {
+          sweep_coarse(h, l, o, (const R *)lb<R>(L), (const R *)a, b2, 1,
+                       s == 0 ? SW_PROLONG : SW_NORMAL, (const R *)lx<R>(C));
+          std::swap(a, b2);
+        }
+        continue;
+      }
+    }
     if (L.one_cyc.nblk)
       DBS_LAUNCH(h, KC_PROLONGC, k_prolong<R>, dim3(L.one_cyc.nblk), blk(), (const LvS *)L.ds,
                  sh(h, L.one_cyc), (const R *)lx<R>(C), lx<R>(L), act);

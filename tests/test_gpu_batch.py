@@ -121,7 +121,7 @@ def test_autotune_keeps_state_and_converges():
         for k in ("alpha", "p_rgh", "U"):
             assert np.array_equal(before[k], after[k]), k
         assert knobs["sweeps"] in (1, 2, 3) and knobs["bottom_shift"] in (0, 1)
-        assert knobs["coarse_sweeps"] in (1, 2, 3) and knobs["fused"] in (0, 1)
+        assert knobs["coarse_sweeps"] in (1, 2, 3, 4) and knobs["fused"] in (0, 1)
         assert knobs["kz"] in (0, 2, 4, 8, 16) and knobs["ms"] > 0
         s.step(2)
         out = s.state()
