@@ -242,17 +242,35 @@ __global__ void __launch_bounds__(NTHREADS) k_mom_offdiag(Segs SG, Phys Ph, MomA
                                                           double *__restrict__ Uout) {
   FOR_CELLS(SG, G, P) {
   const int c = P.c;
-  double acc[3] = {src[c], src[(size_t)G.vs + c], src[2 * (size_t)G.vs + c]};
+  const size_t vs = (size_t)G.vs;
+  // All six faces without branches: a boundary face reads the cell itself
+  // and is dropped by a zero weight, so every load can be issued at once.
+  double aN[6], un[6][3];
+  const double phP = M.phi[c], muP = mu_of(Ph, M.alpha[c]);
+#pragma unroll
   for (int a = 0; a < 3; a++) {
-    if (empty_axis(G, a)) continue;
+#pragma unroll
     for (int s = 0; s < 2; s++) {
-      if (on_boundary(G, P, a, s)) continue;
-      FaceCoef fc = mom_face(G, Ph, M, P, a, s);
-      for (int d = 0; d < 3; d++) acc[d] += fc.aN * Uin[(size_t)d * G.vs + fc.nb];
+      const int q = 2 * a + s;
+      const bool interior = !empty_axis(G, a) && !on_boundary(G, P, a, s);
+      const int nb = interior ? nbr_of(G, P, a, s) : c;
+      const double rp = M.rhoPhi[face_of(G, P, a, s)];
+      const double out = s ? rp : -rp;
+      const double phf = 0.5 * (phP + M.phi[nb]);
+      const double vis = 0.5 * (muP + mu_of(Ph, M.alpha[nb])) * G.area[a] * G.ih[a] * G.iV;
+      const double conv = 1.0 / (phf * phP * G.V);
+      aN[q] = interior ? fmax(-out, 0.0) * conv + vis : 0.0;
+#pragma unroll
+      for (int d = 0; d < 3; d++) un[q][d] = Uin[(size_t)d * vs + nb];
     }
   }
+  double acc[3] = {src[c], src[vs + c], src[2 * vs + c]};
+#pragma unroll
+  for (int q = 0; q < 6; q++)
+#pragma unroll
+    for (int d = 0; d < 3; d++) acc[d] += aN[q] * un[q][d];
   const double r = M.rAU[c];
-  for (int d = 0; d < 3; d++) Uout[(size_t)d * G.vs + c] = r * acc[d];
+  for (int d = 0; d < 3; d++) Uout[(size_t)d * vs + c] = r * acc[d];
   }
 }
 
