@@ -72,6 +72,7 @@ struct Level {
   // grid kernels (pairs and single cells); samples restricted into it
   Shape one_all, pair_cyc, one_cyc, one_rc;
   Shape sw;  // coarse levels: 2.5-D tiles of the cycled samples (fused sweeps)
+  int sw_ok = 0;  // every cycled sample is deep enough in z for fused sweeps
 };
 
 struct Timer {

@@ -734,6 +734,7 @@ constexpr int KZ2 = 16;
 constexpr int NT2 = 64 * TY2;
 constexpr int MIN_BLOCKS2 = 1024;
 constexpr int MIN_BLOCKS_CSW = 256;  // fused coarse sweeps (one block per CU)
+constexpr int CSW_MIN_DEPTH = 8;     // planes a level needs for fused coarse sweeps
 
 __host__ __device__ inline int tiles25(int n0, int n1, int n2, int W, int kz) {
   return ((n0 + W - 1) / W) * ((n1 + TY2 - 1) / TY2) * ((n2 + kz - 1) / kz);
@@ -1638,16 +1639,20 @@ __global__ void __launch_bounds__(NT2) k_sweep25(OpB<R> LB, SH S, const B *__res
       load_planes(G, k + 3 <= k1 + 1 ? k + 3 : n2);  // plane n2: no memory access
       if (k <= k1) relax_planes(k);
     };
-    // prologue: planes k0-2, k0-1 in LDS, k0 and k0+1 in flight
-    load_planes(RA, k0 - 2);
-    store_planes(RA, k0 - 2);
-    load_planes(RA, k0 - 1);
-    store_planes(RA, k0 - 1);
-    load_planes(RA, k0);
-    load_planes(RB, k0 + 1);
+    // The A cells of plane k0-1 are relaxed only for the B cells of plane
+    // k0-1, which belong to the tile below; at the bottom of the mesh there
+    // is none, so the walk starts at k0 (a 2D tile then takes two steps).
+    // Prologue: planes k0-2 .. ks in LDS, ks+1 and ks+2 in flight.
+    const int ks = k0 > 0 ? k0 - 1 : k0;
+    for (int q = k0 - 2; q <= ks; q++) {
+      load_planes(RA, q);
+      store_planes(RA, q);
+    }
+    load_planes(RA, ks + 1);
+    load_planes(RB, ks + 2 <= k1 + 1 ? ks + 2 : n2);
     // planes in pairs; an odd count ends with a step that only stores and
     // loads, so that both steps issue the same loads on every path
-    for (int k = k0 - 1; k <= k1; k += 2) {
+    for (int k = ks; k <= k1; k += 2) {
       step(RA, k);
       step(RB, k + 1);
     }
@@ -1930,6 +1935,11 @@ int pressure_retune(Handle *h) {
       for (int s = 0; s < ns; s++)
         blocks[s] = cyc(s) ? tiles25(L.hs[s].n0, L.hs[s].n1, L.hs[s].n2, 128, kz) : 0;
       set_shape(h, L.sw, blocks, kz, rc);
+      // the plane wavefront stages three planes beyond a tile's own: thin
+      // (2D or nearly) levels keep the half-sweep kernels
+      L.sw_ok = 1;
+      for (int s = 0; s < ns; s++)
+        if (cyc(s) && L.hs[s].n2 < CSW_MIN_DEPTH) L.sw_ok = 0;
     }
   }
   if (rc) return rc;
@@ -2201,8 +2211,9 @@ static R *vcycle(Handle *h, const R *rAUr, const B *b0, R *z0, R *z1) {
     Level &L = h->lv[l];
     Level &C = h->lv[l + 1];
     ccur[l] = lx<R>(L);
+    const bool lf = cfused && L.sw_ok;
     if constexpr (flexr) {
-      if (cfused) {
+      if (lf) {
         R *a = (R *)L.xf2, *b2 = lx<R>(L);
         sweep_coarse(h, l, o, (const R *)lb<R>(L), (const R *)nullptr, a, 0, SW_ZERO,
                      (const R *)nullptr);
@@ -2215,7 +2226,7 @@ static R *vcycle(Handle *h, const R *rAUr, const B *b0, R *z0, R *z1) {
         coth[l] = b2;
       }
     }
-    if (!cfused) smooth_level<R, R>(h, l, o, (const R *)lb<R>(L), lx<R>(L), true);
+    if (!lf) smooth_level<R, R>(h, l, o, (const R *)lb<R>(L), lx<R>(L), true);
     if (C.one_rc.nblk)
       DBS_LAUNCH(h, KC_RESTRICTC, (k_restrict<R, R>), dim3(C.one_rc.nblk), blk(), o,
                  sh(h, C.one_rc), (const R *)lb<R>(L), (const R *)ccur[l], lb<R>(C), act);
@@ -2228,7 +2239,7 @@ static R *vcycle(Handle *h, const R *rAUr, const B *b0, R *z0, R *z1) {
     Level &L = h->lv[l];
     Level &C = h->lv[l + 1];
     if constexpr (flexr) {
-      if (cfused) {
+      if (cfused && L.sw_ok) {
         // the prolongation rides on the first (black) sweep
         R *a = ccur[l], *b2 = coth[l];
         for (int s = 0; s < h->mgc; s++) {
