@@ -144,29 +144,25 @@ __device__ inline FaceCoef mom_face(const Geom &G, const Phys &Ph, const MomArgs
   return r;
 }
 
-// dU_comp/dx_axis at cell Q (Gauss; boundary: wall 0, inlet U_b, outlet U_Q)
-__device__ inline double dU(const Geom &G, const double *__restrict__ U, int Qc, const int Qco[3],
-                            int comp, int axis) {
-  if (empty_axis(G, axis)) return 0.0;
+// dU_comp/dx_axis at cell Q (Gauss; boundary: wall 0, inlet U_b, outlet U_Q).
+// Both neighbour loads are issued unconditionally (a boundary side reads the
+// cell itself); the boundary value replaces the face value afterwards.
+__device__ inline double dU(const Geom &G, const double *__restrict__ U, int Qc,
+                             const int Qco[3], int comp, int axis) {
   const double *Uc = U + (size_t)comp * G.vs;
+  const int st = stride_of(G, axis);
+  const bool bm = Qco[axis] == 0, bp = Qco[axis] == G.n[axis] - 1;
   const double uq = Uc[Qc];
-  double fv[2];
-  for (int s = 0; s < 2; s++) {
-    const bool bnd = s ? Qco[axis] == G.n[axis] - 1 : Qco[axis] == 0;
-    if (bnd) {
-      const int b = 2 * axis + s;
-      if (G.bck[b] == BC_WALL) {
-        fv[s] = 0.0;
-      } else if (is_inlet(G.bck[b])) {
-        fv[s] = inlet_u(G, b, Qco[1], comp);
-      } else {
-        fv[s] = uq;
-      }
-    } else {
-      fv[s] = 0.5 * (uq + Uc[Qc + (s ? 1 : -1) * stride_of(G, axis)]);
-    }
-  }
-  return (fv[1] - fv[0]) * G.ih[axis];
+  const double um = Uc[bm ? Qc : Qc - st], up = Uc[bp ? Qc : Qc + st];
+  double f0 = 0.5 * (uq + um), f1 = 0.5 * (uq + up);
+  auto bval = [&](int b) -> double {
+    if (G.bck[b] == BC_WALL) return 0.0;
+    if (is_inlet(G.bck[b])) return inlet_u(G, b, Qco[1], comp);
+    return uq;
+  };
+  if (bm) f0 = bval(2 * axis);
+  if (bp) f1 = bval(2 * axis + 1);
+  return empty_axis(G, axis) ? 0.0 : (f1 - f0) * G.ih[axis];
 }
 
 __global__ void __launch_bounds__(NTHREADS) k_mom_assemble(Segs SG, Phys Ph, MomArgs M,
@@ -198,27 +194,34 @@ __global__ void __launch_bounds__(NTHREADS) k_mom_assemble(Segs SG, Phys Ph, Mom
     }
   }
   if (transpose) {
-    // explicit div(mu grad(U)^T): face flux mu_f A dU_a/dx_i, outward sign
+    // explicit div(mu grad(U)^T): face flux mu_f A dU_a/dx_i, outward sign.
+    // The cell's own gradient is formed once; a boundary face evaluates its
+    // "neighbour" at the cell itself and discards it.
+    double gP[3][3];
+#pragma unroll
+    for (int a = 0; a < 3; a++)
+#pragma unroll
+      for (int i = 0; i < 3; i++) gP[a][i] = dU(G, U, c, P.co, a, i);
+    const double muP = mu_of(Ph, an);
+#pragma unroll
     for (int a = 0; a < 3; a++) {
       if (empty_axis(G, a)) continue;
+#pragma unroll
       for (int s = 0; s < 2; s++) {
         const double sg = s ? 1.0 : -1.0;
-        double muf;
-        double gN[3] = {0.0, 0.0, 0.0};
         const bool bnd = on_boundary(G, P, a, s);
-        if (!bnd) {
-          const int nb = nbr_of(G, P, a, s);
-          int nco[3] = {P.co[0], P.co[1], P.co[2]};
-          nco[a] += s ? 1 : -1;
-          muf = 0.5 * (mu_of(Ph, an) + mu_of(Ph, M.alpha[nb]));
-          for (int i = 0; i < 3; i++) gN[i] = dU(G, U, nb, nco, a, i);
-        } else {
+        const int nb = bnd ? c : nbr_of(G, P, a, s);
+        int nco[3] = {P.co[0], P.co[1], P.co[2]};
+        if (!bnd) nco[a] += s ? 1 : -1;
+        double muf = 0.5 * (muP + mu_of(Ph, M.alpha[nb]));
+        if (bnd) {
           const int b = 2 * a + s;
-          muf = is_inlet(G.bck[b]) ? mu_of(Ph, inlet_alpha(G, b, P.j)) : mu_of(Ph, an);
+          muf = is_inlet(G.bck[b]) ? mu_of(Ph, inlet_alpha(G, b, P.j)) : muP;
         }
+#pragma unroll
         for (int i = 0; i < 3; i++) {
-          const double gP = dU(G, U, c, P.co, a, i);
-          const double gf = bnd ? gP : 0.5 * (gP + gN[i]);
+          const double gN = dU(G, U, nb, nco, a, i);
+          const double gf = bnd ? gP[a][i] : 0.5 * (gP[a][i] + gN);
           S[i] += sg * muf * G.area[a] * gf * G.iV;
         }
       }
