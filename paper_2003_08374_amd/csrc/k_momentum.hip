@@ -53,11 +53,26 @@ __device__ inline double face_body(const Geom &G, const Phys &Ph, const MomArgs 
 }
 
 // q on side s of P along a for interior and outlet faces (fixed-flux faces
-// are handled by the caller); p_rgh from `prgh`
+// are handled by the caller); p_rgh from `prgh`.  BF: both forms are
+// evaluated and one selected, so that the neighbour loads need no branch (a
+// boundary side reads the cell itself for the interior form); faster where
+// little else hides the load latency (the corrector), slower in the
+// assembly.
+template <bool BF = false>
 __device__ inline double face_force(const Geom &G, const Phys &Ph, const MomArgs &M,
                                     const double *__restrict__ prgh, const Cell &P, int a,
                                     int s) {
   const double gxf = gdotx_face(G, Ph, P, a, s);
+  if constexpr (BF) {
+    const bool bnd = on_boundary(G, P, a, s);
+    const int nb = bnd ? P.c : nbr_of(G, P, a, s);
+    const int own = s ? P.c : nb, nbr = s ? nb : P.c;
+    const double vi =
+        (face_body(G, Ph, M, own, nbr, a, gxf) - (prgh[nbr] - prgh[own]) * G.ih[a]) * G.area[a];
+    const double pb = G.bcp[2 * a + s] - rho_of(Ph, M.alpha[P.c]) * gxf;
+    const double sn = s ? (pb - prgh[P.c]) * 2.0 * G.ih[a] : (prgh[P.c] - pb) * 2.0 * G.ih[a];
+    return bnd ? -sn * G.area[a] : vi;
+  }
   if (on_boundary(G, P, a, s)) {
     // outlet: fixed static pressure, p_rgh_b = p_b - rho_P g.x_b
     const double pb = G.bcp[2 * a + s] - rho_of(Ph, M.alpha[P.c]) * gxf;
@@ -77,6 +92,7 @@ __device__ __forceinline__ bool fixed_flux(const Geom &G, int b) {
 // R(q)_a of cell P.  hbya == nullptr: predictor (a fixed-flux face copies the
 // opposite face's force); otherwise corrector (a fixed-flux face carries the
 // p_rgh gradient that reproduces its prescribed flux).
+template <bool BF = false>
 __device__ inline double reconstruct_axis(const Geom &G, const Phys &Ph, const MomArgs &M,
                                           const double *__restrict__ prgh,
                                           const double *__restrict__ hbya, const Cell &P,
@@ -86,7 +102,7 @@ __device__ inline double reconstruct_axis(const Geom &G, const Phys &Ph, const M
   bool ff[2];
   for (int s = 0; s < 2; s++) {
     ff[s] = on_boundary(G, P, a, s) && fixed_flux(G, 2 * a + s);
-    if (!ff[s]) q[s] = face_force(G, Ph, M, prgh, P, a, s);
+    if (BF || !ff[s]) q[s] = face_force<BF>(G, Ph, M, prgh, P, a, s);
   }
   for (int s = 0; s < 2; s++) {
     if (!ff[s]) continue;
@@ -331,28 +347,33 @@ __global__ void __launch_bounds__(NTHREADS) k_correct(Segs SG, Phys Ph, MomArgs 
   FOR_CELLS(SG, G, P) {
   const int c = P.c;
   const double *prgh = M.prgh;
+  // the minus face of every axis (interior: the neighbour's loads are issued
+  // without a branch), and the plus face where it is a domain boundary
+  auto bflux = [&](int a, int s, double v) {
+    if (G.bck[2 * a + s] == BC_OUTLET) {
+      const double pb = G.bcp[2 * a + s] - rho_of(Ph, M.alpha[c]) * gdotx_face(G, Ph, P, a, s);
+      const double Tb = M.rAU[c] * G.area[a] * 2.0 * G.ih[a];
+      v -= s ? Tb * (pb - prgh[c]) : Tb * (prgh[c] - pb);
+    }
+    return v;
+  };
   for (int a = 0; a < 3; a++) {
-    for (int s = 0; s < 2; s++) {
-      const bool bnd = on_boundary(G, P, a, s);
-      if (s == 1 && !bnd) continue;
-      const int f = face_of(G, P, a, s);
-      double v = phiH[f];
-      if (!bnd) {
-        const int own = c - stride_of(G, a);
-        const double T = 0.5 * (M.rAU[own] + M.rAU[c]) * G.area[a] * G.ih[a];
-        v -= T * (prgh[c] - prgh[own]);
-      } else if (G.bck[2 * a + s] == BC_OUTLET) {
-        const double pb = G.bcp[2 * a + s] - rho_of(Ph, M.alpha[c]) * gdotx_face(G, Ph, P, a, s);
-        const double Tb = M.rAU[c] * G.area[a] * 2.0 * G.ih[a];
-        v -= s ? Tb * (pb - prgh[c]) : Tb * (prgh[c] - pb);
-      }
-      F[f] = v;
+    const bool bnd = on_boundary(G, P, a, 0);
+    const int own = bnd ? c : c - stride_of(G, a);
+    const int f = face_of(G, P, a, 0);
+    const double v = phiH[f];
+    const double T = 0.5 * (M.rAU[own] + M.rAU[c]) * G.area[a] * G.ih[a];
+    const double vi = v - T * (prgh[c] - prgh[own]);
+    F[f] = bnd ? bflux(a, 0, v) : vi;
+    if (on_boundary(G, P, a, 1)) {
+      const int f1 = face_of(G, P, a, 1);
+      F[f1] = bflux(a, 1, phiH[f1]);
     }
   }
   const double r = M.rAU[c];
   for (int d = 0; d < 3; d++)
     U[(size_t)d * G.vs + c] =
-        H[(size_t)d * G.vs + c] + r * reconstruct_axis(G, Ph, M, prgh, H, P, d);
+        H[(size_t)d * G.vs + c] + r * reconstruct_axis<true>(G, Ph, M, prgh, H, P, d);
   if (last) p[c] = prgh[c] + rho_of(Ph, M.alpha[c]) * gdotx_cell(G, Ph, P);
   }
 }
