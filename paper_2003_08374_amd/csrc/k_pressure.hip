@@ -582,6 +582,11 @@ __global__ void __launch_bounds__(NTHREADS) k_diag(const LvS *__restrict__ ls, S
   }
 }
 
+// 1/D for the smoother: the hardware reciprocal in FP32 (the V-cycle is a
+// preconditioner; the outer FP64 CG is unaffected), exact in FP64
+__device__ __forceinline__ float sw_rcp(float d) { return __builtin_amdgcn_rcpf(d); }
+__device__ __forceinline__ double sw_rcp(double d) { return 1.0 / d; }
+
 // ----------------------------------------------- single work-group bottom
 //
 // The smallest levels of a sample (from the first one whose whole
@@ -610,27 +615,45 @@ struct LdsView {
   R *tx, *ty, *tz, *d, *x, *b;
 };
 
+// q / d for 0 <= q < 2^22 and d >= 1: a float reciprocal and one
+// correction (the float product is within 1/2 of q/d), no integer division
+__device__ __forceinline__ int sdiv(int q, int d, float invd) {
+  int t = (int)((float)q * invd);
+  t -= (t * d > q) ? 1 : 0;
+  t += ((t + 1) * d <= q) ? 1 : 0;
+  return t;
+}
+
+// one red-black half sweep of a bottom level: one x-pair per thread
+// iteration, the pair's cell of this colour relaxed (zero: x = b/D on this
+// colour and 0 on the other)
 template <typename R>
 __device__ inline void bl_sweep(const LdsView<R> &S, const BLevel<R> &L, int color, bool zero) {
-  const int n = L.n0 * L.n1 * L.n2;
-  const int sy = L.n0, sz = L.n0 * L.n1;
-  for (int c = threadIdx.x; c < n; c += blockDim.x) {
-    const int i = c % L.n0, j = (c / L.n0) % L.n1, k = c / sz;
-    const int g = L.off + c;
-    const bool mine = (((i + j + k) & 1) == color);
+  const int n0 = L.n0, n1 = L.n1, n2 = L.n2;
+  const int hx = (n0 + 1) >> 1, np = hx * n1 * n2;
+  const int sy = n0, sz = n0 * n1;
+  const float ihx = 1.0f / (float)hx, in1 = 1.0f / (float)n1;
+  for (int q = threadIdx.x; q < np; q += blockDim.x) {
+    const int row = sdiv(q, hx, ihx), iq = q - row * hx;
+    const int k = sdiv(row, n1, in1), j = row - k * n1;
+    const int off = (j + k + color) & 1;  // (i + j + k) & 1 == color
+    const int i = 2 * iq + off;
+    const int g = L.off + i + n0 * row;
     if (zero) {
-      S.x[g] = mine && S.d[g] > (R)0 ? S.b[g] / S.d[g] : (R)0;
+      if (i < n0) S.x[g] = S.d[g] > (R)0 ? S.b[g] * sw_rcp(S.d[g]) : (R)0;
+      const int io = 2 * iq + 1 - off;
+      if (io < n0) S.x[g + io - i] = (R)0;
       continue;
     }
-    if (!mine) continue;
+    if (i >= n0) continue;
     R s = S.b[g];
     if (i > 0) s += S.tx[g - 1] * S.x[g - 1];
-    if (i + 1 < L.n0) s += S.tx[g] * S.x[g + 1];
+    if (i + 1 < n0) s += S.tx[g] * S.x[g + 1];
     if (j > 0) s += S.ty[g - sy] * S.x[g - sy];
-    if (j + 1 < L.n1) s += S.ty[g] * S.x[g + sy];
+    if (j + 1 < n1) s += S.ty[g] * S.x[g + sy];
     if (k > 0) s += S.tz[g - sz] * S.x[g - sz];
-    if (k + 1 < L.n2) s += S.tz[g] * S.x[g + sz];
-    S.x[g] = S.d[g] > (R)0 ? s / S.d[g] : (R)0;
+    if (k + 1 < n2) s += S.tz[g] * S.x[g + sz];
+    S.x[g] = S.d[g] > (R)0 ? s * sw_rcp(S.d[g]) : (R)0;
   }
   __syncthreads();
 }
@@ -639,8 +662,10 @@ template <typename R>
 __device__ inline void bl_restrict(const LdsView<R> &S, const BLevel<R> &F, const BLevel<R> &C) {
   const int n = C.n0 * C.n1 * C.n2;
   const int sy = F.n0, sz = F.n0 * F.n1;
+  const float cin0 = 1.0f / (float)C.n0, cin1 = 1.0f / (float)C.n1;
   for (int cc = threadIdx.x; cc < n; cc += blockDim.x) {
-    const int I = cc % C.n0, J = (cc / C.n0) % C.n1, K = cc / (C.n0 * C.n1);
+    const int crow = sdiv(cc, C.n0, cin0), I = cc - crow * C.n0;
+    const int K = sdiv(crow, C.n1, cin1), J = crow - K * C.n1;
     R s = 0;
     for (int dk = 0; dk < 2; dk++)
       for (int dj = 0; dj < 2; dj++)
@@ -665,8 +690,10 @@ __device__ inline void bl_restrict(const LdsView<R> &S, const BLevel<R> &F, cons
 template <typename R>
 __device__ inline void bl_prolong(const LdsView<R> &S, const BLevel<R> &F, const BLevel<R> &C) {
   const int n = F.n0 * F.n1 * F.n2;
+  const float in0 = 1.0f / (float)F.n0, in1 = 1.0f / (float)F.n1;
   for (int c = threadIdx.x; c < n; c += blockDim.x) {
-    const int i = c % F.n0, j = (c / F.n0) % F.n1, k = c / (F.n0 * F.n1);
+    const int row = sdiv(c, F.n0, in0), i = c - row * F.n0;
+    const int k = sdiv(row, F.n1, in1), j = row - k * F.n1;
     S.x[F.off + c] += S.x[C.off + (i >> 1) + C.n0 * ((j >> 1) + C.n1 * (k >> 1))];
   }
   __syncthreads();
@@ -807,10 +834,6 @@ __device__ __forceinline__ double2 vadd(double2 a, double2 b) {
   return make_double2(a.x + b.x, a.y + b.y);
 }
 
-// 1/D for the smoother: the hardware reciprocal in FP32 (the V-cycle is a
-// preconditioner; the outer FP64 CG is unaffected), exact in FP64
-__device__ __forceinline__ float sw_rcp(float d) { return __builtin_amdgcn_rcpf(d); }
-__device__ __forceinline__ double sw_rcp(double d) { return 1.0 / d; }
 
 // row of the fine operator at (i,j,k) from the seven rAU values around it
 template <typename R>
