@@ -613,3 +613,38 @@ def test_wave_inlet_vertical_velocity_from_continuity(phase):
     assert np.abs(lhs - rhs).max() <= 1e-4 * scale
     # v vanishes on the bed: v(y0) = y0 dv/dy + O(h^3)
     assert abs(v[0] - y[0] * (k / w) * dudt[0]) <= 1e-4 * np.abs(v).max()
+
+
+def test_capillary_gravity_relaxation_reaches_the_equilibrium_profile():
+    """Sec. 4.1 gravity-capillarity equilibrium, at reduced scale: a 0.2 m
+    porous column (40 cells, phi 0.5, k 1e-10 m^2, Brooks-Corey k_r m = 2 and
+    p_c with p_c0 = 1e3 Pa, beta = 1/2), closed at the bottom and open at the
+    top, starts with its lower half at alpha = 0.5 and its upper half dry.
+    At rest, Eq. (gravity-capillarity) fixes dp_c/dy = (rho_g - rho_l) g_y,
+    so with the App. A closed form alpha = (p_c/p_c0)^(-1/beta) the profile
+    is known up to one constant, which the conserved water volume fixes.
+    The oracle relaxes to that profile and keeps the water volume."""
+    from scipy.optimize import brentq
+    n, L = 40, 0.2
+    h = L / n
+    y = (np.arange(n) + 0.5) * h
+    alpha0 = np.where(y < L / 2, 0.5, 0.0)
+    fl = W.fluids(W.WATER, W.AIR)
+    c = PC.column_1d(n, h, axis=1, phi=0.5, kinv=1e10, alpha0=0.0, U_in=0.0,
+                     g=(0.0, -9.81, 0.0), kr={"model": "brooks_corey", "m": 2.0},
+                     pc={"model": "brooks_corey", "pc0": 1e3, "exp": 0.5}, dt=0.05,
+                     bc_lo=W.wall(), bc_hi=W.outlet(0.0, 0.0), fl=fl)
+    c = c.replace(alpha=alpha0.reshape(1, n, 1), p_tol=1e-12)
+    st = O.initial_state(c)
+    out, _ = O.step(c, st, 40000)  # 2000 s, many relaxation times
+    a = out["alpha"]
+    # the open top passes the total flux, zero only to the pressure solver's
+    # tolerance (1e-12 per step, 4e4 steps)
+    assert abs(a.sum() - alpha0.sum()) <= 1e-8 * alpha0.sum()
+    rho_l, rho_g = fl["rho_l"], fl["rho_g"]
+    slope = (rho_g - rho_l) * -9.81  # dp_c/dy at rest
+    prof = lambda pc_bottom: (np.asarray(pc_bottom + slope * (y - y[0])) / 1e3) ** -2.0
+    pc_b = brentq(lambda q: prof(q).sum() - alpha0.sum(), 1e3, 1e5)
+    expect = prof(pc_b)
+    assert np.all(np.diff(a) < 0)
+    assert np.abs(a - expect).max() <= 1e-6, np.abs(a - expect).max()
