@@ -128,6 +128,39 @@ def test_darcy_pressure_drop(alpha0):
     np.testing.assert_allclose(out["U"][0][2:-2], U, rtol=1e-9)
 
 
+def test_outlet_static_pressure_half_a_cell_from_the_last_centre():
+    """Fixed-pressure outlet (reading of the outlet condition): the static
+    pressure p_b holds on the outlet face, half a cell beyond the last cell
+    centre.  Upflow through a porous column against gravity at alpha = 1:
+    Darcy's law (Eq. (single-field-darcy-momentum) at alpha = 1) fixes
+    dp/dx = -(mu U k^-1 + rho g), so the last cell carries
+    p_b - (h/2) dp/dx."""
+    n, h, U, kinv, pb = 40, 1e-3, 1e-4, 1e11, 250.0
+    c = PC.column_1d(n, h, alpha0=1.0, U_in=U, kinv=kinv, g=(-9.81, 0.0, 0.0),
+                     bc_hi=W.outlet(pb, 1.0))
+    out, _ = O.step(c, O.initial_state(c), 3)
+    p = out["p"]
+    dpdx = -(c.fluids["mu_l"] * U * kinv + 9.81 * c.fluids["rho_l"])
+    np.testing.assert_allclose((p[3:-3] - p[2:-4]) / h, dpdx, rtol=1e-9)
+    assert p[-1] == pytest.approx(pb - 0.5 * h * dpdx, rel=1e-12)
+    np.testing.assert_allclose(out["U"][0], U, rtol=1e-9)
+
+
+def test_outlet_backflow_brings_the_boundary_saturation():
+    """Flow entering through the outlet (reading of the outlet condition)
+    carries the outlet's backflow saturation alpha_b into the last cell by
+    first-order upwinding, the limiter leaving boundary fluxes unlimited
+    (Eq. (phaseEq), discretised as in Sec. 3.1): from alpha = 1 one step gives
+    alpha_last = 1 - (1 - alpha_b) dt U / (phi h) and leaves the rest at 1."""
+    n, h, U, kinv, ab, phi = 40, 1e-3, 1e-4, 1e11, 0.3, 0.5
+    c = PC.column_1d(n, h, phi=phi, alpha0=1.0, U_in=-U, kinv=kinv,
+                     bc_lo=W.inlet((-U, 0.0, 0.0), 1.0), bc_hi=W.outlet(0.0, ab))
+    out, _ = O.step(c, O.initial_state(c), 1)
+    a = out["alpha"]
+    assert a[-1] == pytest.approx(1.0 - (1.0 - ab) * c.dt * U / (phi * h), abs=1e-15)
+    np.testing.assert_array_equal(a[:-1], 1.0)
+
+
 # ------------------------------------------------- Poiseuille (viscous + PISO)
 
 
