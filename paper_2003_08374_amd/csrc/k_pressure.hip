@@ -602,10 +602,16 @@ struct BLevel {
   R *x, *b;             // global x and b (b read and x written for the top level)
 };
 
+// Each LDS array is preceded by `pad` zero cells (pad >= one plane of the
+// top level).  Face coefficients are zero on domain faces, so every
+// neighbour term is formed without a test: an index past a level's edge
+// lands on a zero coefficient of the same level, on a domain face of the
+// previous (larger) level or in a pad, and multiplies a finite x (all of x
+// starts at zero).
 template <typename R>
 struct Bottom {
   int s;                // sample
-  int nl, ntot;
+  int nl, ntot, pad;
   int pre, post, coarse_sweeps;
   BLevel<R> L[MAXLV];
 };
@@ -624,40 +630,72 @@ __device__ __forceinline__ int sdiv(int q, int d, float invd) {
   return t;
 }
 
-// one red-black half sweep of a bottom level: one x-pair per thread
-// iteration, the pair's cell of this colour relaxed (zero: x = b/D on this
-// colour and 0 on the other)
+// s plus the six neighbour terms of LDS cell g (row stride sy, plane sz)
+template <typename R>
+__device__ __forceinline__ R bl_nsum(const LdsView<R> &S, int g, int sy, int sz, R s) {
+  s += S.tx[g - 1] * S.x[g - 1];
+  s += S.tx[g] * S.x[g + 1];
+  s += S.ty[g - sy] * S.x[g - sy];
+  s += S.ty[g] * S.x[g + sy];
+  s += S.tz[g - sz] * S.x[g - sz];
+  s += S.tz[g] * S.x[g + sz];
+  return s;
+}
+
+// (A x) at LDS cell g
+template <typename R>
+__device__ __forceinline__ R bl_ax(const LdsView<R> &S, int g, int sy, int sz) {
+  R ax = S.d[g] * S.x[g];
+  ax -= S.tx[g - 1] * S.x[g - 1];
+  ax -= S.tx[g] * S.x[g + 1];
+  ax -= S.ty[g - sy] * S.x[g - sy];
+  ax -= S.ty[g] * S.x[g + sy];
+  ax -= S.tz[g - sz] * S.x[g - sz];
+  ax -= S.tz[g] * S.x[g + sz];
+  return ax;
+}
+
+// one red-black half sweep of a bottom level over pairs of cells along x,
+// two pairs per thread iteration with both pairs' loads issued before
+// either store; the pair's cell of this colour is relaxed (zero: x = b/D on
+// this colour and 0 on the other)
 template <typename R>
 __device__ inline void bl_sweep(const LdsView<R> &S, const BLevel<R> &L, int color, bool zero) {
-  const int n0 = L.n0, n1 = L.n1, n2 = L.n2;
-  const int hx = (n0 + 1) >> 1, np = hx * n1 * n2;
+  const int n0 = L.n0, n1 = L.n1;
+  const int hx = (n0 + 1) >> 1, np = hx * n1 * L.n2;
   const int sy = n0, sz = n0 * n1;
   const float ihx = 1.0f / (float)hx, in1 = 1.0f / (float)n1;
-  for (int q = threadIdx.x; q < np; q += blockDim.x) {
-    const int row = sdiv(q, hx, ihx), iq = q - row * hx;
-    const int k = sdiv(row, n1, in1), j = row - k * n1;
-    const int off = (j + k + color) & 1;  // (i + j + k) & 1 == color
-    const int i = 2 * iq + off;
-    const int g = L.off + i + n0 * row;
-    if (zero) {
-      if (i < n0) S.x[g] = S.d[g] > (R)0 ? S.b[g] * sw_rcp(S.d[g]) : (R)0;
-      const int io = 2 * iq + 1 - off;
-      if (io < n0) S.x[g + io - i] = (R)0;
-      continue;
+  const int bs = blockDim.x;
+  for (int q0 = threadIdx.x; q0 < np; q0 += 2 * bs) {
+    int g[2], io[2];
+    bool on[2];
+    R v[2];
+#pragma unroll
+    for (int u = 0; u < 2; u++) {
+      // a second pair past the end repeats the first (same value, same place)
+      const int q = q0 + u * bs < np ? q0 + u * bs : q0;
+      const int row = sdiv(q, hx, ihx), iq = q - row * hx;
+      const int k = sdiv(row, n1, in1), j = row - k * n1;
+      const int off = (j + k + color) & 1;  // (i + j + k) & 1 == color
+      const int i = 2 * iq + off;
+      g[u] = L.off + i + n0 * row;
+      on[u] = i < n0;
+      io[u] = 2 * iq + 1 - off < n0 ? 1 - 2 * off : 0;  // other cell of the pair
+      const R d = S.d[g[u]];
+      const R s = zero ? S.b[g[u]] : bl_nsum(S, g[u], sy, sz, S.b[g[u]]);
+      v[u] = d > (R)0 ? s * sw_rcp(d) : (R)0;
     }
-    if (i >= n0) continue;
-    R s = S.b[g];
-    if (i > 0) s += S.tx[g - 1] * S.x[g - 1];
-    if (i + 1 < n0) s += S.tx[g] * S.x[g + 1];
-    if (j > 0) s += S.ty[g - sy] * S.x[g - sy];
-    if (j + 1 < n1) s += S.ty[g] * S.x[g + sy];
-    if (k > 0) s += S.tz[g - sz] * S.x[g - sz];
-    if (k + 1 < n2) s += S.tz[g] * S.x[g + sz];
-    S.x[g] = S.d[g] > (R)0 ? s * sw_rcp(S.d[g]) : (R)0;
+#pragma unroll
+    for (int u = 0; u < 2; u++) {
+      if (on[u]) S.x[g[u]] = v[u];
+      if (zero && io[u] != 0) S.x[g[u] + io[u]] = (R)0;
+    }
   }
   __syncthreads();
 }
 
+// b of the coarser level: the sum of the residuals of a cell's (up to 8)
+// children; a missing child (odd size) reads the first child and adds zero
 template <typename R>
 __device__ inline void bl_restrict(const LdsView<R> &S, const BLevel<R> &F, const BLevel<R> &C) {
   const int n = C.n0 * C.n1 * C.n2;
@@ -666,21 +704,18 @@ __device__ inline void bl_restrict(const LdsView<R> &S, const BLevel<R> &F, cons
   for (int cc = threadIdx.x; cc < n; cc += blockDim.x) {
     const int crow = sdiv(cc, C.n0, cin0), I = cc - crow * C.n0;
     const int K = sdiv(crow, C.n1, cin1), J = crow - K * C.n1;
+    const int g0 = F.off + 2 * I + F.n0 * (2 * J + F.n1 * 2 * K);
     R s = 0;
+#pragma unroll
     for (int dk = 0; dk < 2; dk++)
+#pragma unroll
       for (int dj = 0; dj < 2; dj++)
+#pragma unroll
         for (int di = 0; di < 2; di++) {
-          const int i = 2 * I + di, j = 2 * J + dj, k = 2 * K + dk;
-          if (i >= F.n0 || j >= F.n1 || k >= F.n2) continue;
-          const int g = F.off + i + F.n0 * (j + F.n1 * k);
-          R ax = S.d[g] * S.x[g];
-          if (i > 0) ax -= S.tx[g - 1] * S.x[g - 1];
-          if (i + 1 < F.n0) ax -= S.tx[g] * S.x[g + 1];
-          if (j > 0) ax -= S.ty[g - sy] * S.x[g - sy];
-          if (j + 1 < F.n1) ax -= S.ty[g] * S.x[g + sy];
-          if (k > 0) ax -= S.tz[g - sz] * S.x[g - sz];
-          if (k + 1 < F.n2) ax -= S.tz[g] * S.x[g + sz];
-          s += S.b[g] - ax;
+          const bool ok = 2 * I + di < F.n0 && 2 * J + dj < F.n1 && 2 * K + dk < F.n2;
+          const int g = ok ? g0 + di + sy * dj + sz * dk : g0;
+          const R r = S.b[g] - bl_ax(S, g, sy, sz);
+          s += ok ? r : (R)0;
         }
     S.b[C.off + cc] = s;
   }
@@ -699,35 +734,70 @@ __device__ inline void bl_prolong(const LdsView<R> &S, const BLevel<R> &F, const
   __syncthreads();
 }
 
+// cells of the bottom hierarchy one thread loads (coefficients and b)
+template <typename R>
+constexpr int bottom_cells_per_thread() {
+  return (int)((BOTTOM_LDS / (6 * sizeof(R)) + 1023) / 1024);
+}
+
 template <typename R>
 __global__ void __launch_bounds__(1024) k_bottom(const Bottom<R> *__restrict__ tab,
                                                  const int *__restrict__ mask) {
-  __shared__ R lds[BOTTOM_LDS / sizeof(R)];
+  __shared__ __align__(16) R lds[BOTTOM_LDS / sizeof(R)];
   const Bottom<R> &A = tab[blockIdx.x];
   if (mask && !mask[A.s]) return;
-  const int N = A.ntot;
-  LdsView<R> S{lds, lds + N, lds + 2 * N, lds + 3 * N, lds + 4 * N, lds + 5 * N};
-  for (int l = 0; l < A.nl; l++) {
-    const BLevel<R> &L = A.L[l];
-    const int n = L.n0 * L.n1 * L.n2;
-    for (int c = threadIdx.x; c < n; c += blockDim.x) {
-      const int g = L.off + c;
-      S.tx[g] = L.Tx[c];
-      S.ty[g] = L.Ty[c];
-      S.tz[g] = L.Tz[c];
-      S.d[g] = L.D[c];
-      if (l == 0) S.b[g] = L.b[c];
+  const int N = A.ntot, P = A.pad, ST = N + P, nl = A.nl;
+  LdsView<R> S{lds + P, lds + P + ST, lds + P + 2 * ST, lds + P + 3 * ST, lds + P + 4 * ST,
+               lds + P + 5 * ST};
+  // zero every array and pad (x starts at zero; pads stay zero)
+  {
+    constexpr int V = 16 / sizeof(R);
+    const int nv = (6 * ST + V - 1) / V;
+    static_assert(BOTTOM_LDS % 16 == 0, "whole vectors");
+    float4 *l4 = reinterpret_cast<float4 *>(lds);
+    for (int e = threadIdx.x; e < nv; e += 1024) l4[e] = make_float4(0.f, 0.f, 0.f, 0.f);
+  }
+  __syncthreads();
+  // coefficients and b of every level, all loads in flight before the
+  // stores (b of the levels below the top is loaded and later overwritten)
+  {
+    constexpr int U = bottom_cells_per_thread<R>();
+    R v[U][5];
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      const int e0 = threadIdx.x + u * 1024;
+      const int e = e0 < N ? e0 : N - 1;
+      int m = 0;
+      for (int q = 1; q < nl; q++) m += e >= A.L[q].off ? 1 : 0;
+      const BLevel<R> &L = A.L[m];
+      const int c = e - L.off;
+      v[u][0] = L.Tx[c];
+      v[u][1] = L.Ty[c];
+      v[u][2] = L.Tz[c];
+      v[u][3] = L.D[c];
+      v[u][4] = L.b[c];
+    }
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      const int e = threadIdx.x + u * 1024;
+      if (e < N) {
+        S.tx[e] = v[u][0];
+        S.ty[e] = v[u][1];
+        S.tz[e] = v[u][2];
+        S.d[e] = v[u][3];
+        S.b[e] = v[u][4];
+      }
     }
   }
   __syncthreads();
-  for (int l = 0; l < A.nl - 1; l++) {
+  for (int l = 0; l < nl - 1; l++) {
     for (int s = 0; s < A.pre; s++) {
       bl_sweep(S, A.L[l], 0, s == 0);
       bl_sweep(S, A.L[l], 1, false);
     }
     bl_restrict(S, A.L[l], A.L[l + 1]);
   }
-  const BLevel<R> &C = A.L[A.nl - 1];
+  const BLevel<R> &C = A.L[nl - 1];
   for (int s = 0; s < A.coarse_sweeps; s++) {
     bl_sweep(S, C, 0, s == 0);
     bl_sweep(S, C, 1, false);
@@ -736,7 +806,7 @@ __global__ void __launch_bounds__(1024) k_bottom(const Bottom<R> *__restrict__ t
     bl_sweep(S, C, 1, false);
     bl_sweep(S, C, 0, false);
   }
-  for (int l = A.nl - 2; l >= 0; l--) {
+  for (int l = nl - 2; l >= 0; l--) {
     bl_prolong(S, A.L[l], A.L[l + 1]);
     for (int s = 0; s < A.post; s++) {
       bl_sweep(S, A.L[l], 1, false);
@@ -745,7 +815,7 @@ __global__ void __launch_bounds__(1024) k_bottom(const Bottom<R> *__restrict__ t
   }
   const BLevel<R> &T = A.L[0];
   const int n = T.n0 * T.n1 * T.n2;
-  for (int c = threadIdx.x; c < n; c += blockDim.x) T.x[c] = S.x[T.off + c];
+  for (int c = threadIdx.x; c < n; c += 1024) T.x[c] = S.x[T.off + c];
 }
 
 // ------------------------------------------------ fine level, 2.5-D tiles
@@ -1893,7 +1963,8 @@ int pressure_retune(Handle *h) {
         const LvS &Q = h->lv[m].hs[s];
         cells += (size_t)Q.n0 * Q.n1 * Q.n2;
       }
-      if (cells * 6 * rs <= (size_t)BOTTOM_LDS) { bl = l; break; }
+      const size_t pad = (size_t)h->lv[l].hs[s].n0 * h->lv[l].hs[s].n1;
+      if ((cells + pad) * 6 * rs + 16 <= (size_t)BOTTOM_LDS) { bl = l; break; }
     }
     bl = std::min(bl + h->bottom_shift, nl - 1);
     h->bottom[s] = bl;
@@ -1988,6 +2059,11 @@ int pressure_retune(Handle *h) {
         off += Q.n0 * Q.n1 * Q.n2;
       }
       A.ntot = off;
+      A.pad = std::max(1, A.L[0].n0 * A.L[0].n1);  // one plane of the top level
+      if ((size_t)6 * (A.ntot + A.pad) * sizeof(R) + 16 > (size_t)BOTTOM_LDS) {
+        h->err = "bottom levels exceed the work-group's LDS";
+        return DBS_EINVAL;
+      }
       // a one-cell coarsest level is solved exactly by one sweep
       const LvS &Cq = h->lv[nl - 1].hs[s];
       A.coarse_sweeps = Cq.n0 * Cq.n1 * Cq.n2 == 1 ? 1 : h->coarse_sweeps;
