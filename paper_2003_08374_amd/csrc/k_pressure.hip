@@ -1479,13 +1479,16 @@ __device__ __forceinline__ void ring_cell(int r, int x0, int y0, int k, int colA
 // sample has a coarse level).  colA: colour relaxed first.  xout != xin.
 // OPK 0: the fine level (rows rebuilt from rAU); OPK 1: a coarse level with
 // stored face coefficients Tx, Ty, Tz (zero on domain faces) and diagonal D,
-// staged like rAU.
-template <typename R, typename B, int MODE, int OPK = 0>
+// staged like rAU.  DOT: the block's partial sums of b.xout and b.zold
+// (zold may be null) go to partials[g] and partials[off2 + g].
+template <typename R, typename B, int MODE, int OPK = 0, int DOT = 0>
 __global__ void __launch_bounds__(NT2) k_sweep25(OpB<R> LB, SH S, const B *__restrict__ b,
                                                  const R *__restrict__ xin,
                                                  R *__restrict__ xout, int colA,
                                                  const R *__restrict__ xc,
-                                                 const int *__restrict__ mask) {
+                                                 const int *__restrict__ mask,
+                                                 const R *__restrict__ zold,
+                                                 double *__restrict__ partials, int off2) {
   using PL = SwPlane<R>;
   using VT = typename Vec16<R>::T;
   constexpr int VEC = PL::VEC, NX = PL::NX, FXR = PL::FXR;
@@ -1495,6 +1498,7 @@ __global__ void __launch_bounds__(NT2) k_sweep25(OpB<R> LB, SH S, const B *__res
   __shared__ __align__(16) R sB[3 * NX];   // right-hand side, planes k-1, k, k+1
   static_assert(std::is_same<R, B>::value, "the right-hand side is staged as R");
   __shared__ R sA[2 * NX1];                // new A values, planes k-1, k (slot k mod 2)
+  __shared__ double lred[DOT ? NT2 / 64 : 1];
   int g, s, lb;
   if (!locate(S, mask, g, s, lb)) return;
   const Op<R> L = op_at(LB, s);
@@ -1534,6 +1538,18 @@ __global__ void __launch_bounds__(NT2) k_sweep25(OpB<R> LB, SH S, const B *__res
   }
   auto sr = [&](int q, int k) -> R * { return sR + (3 * q + xs(k)) * NX; };
   const Buf Bc = mkbuf(xcs ? xcs : rA, xcs ? cn0 * cn1 * Q.cn2 : 0);
+  // DOT: sums over the cells this thread stores, and zold of its pair of
+  // plane k-1 (loaded before the plane loads of the step, used at the store)
+  double dz = 0.0, dzo = 0.0;
+  const Buf Bz = mkbuf(DOT && zold ? zold + Q.c0 : rA, DOT && zold ? ncs : 0);
+  R zo0 = (R)0, zo1 = (R)0;
+  auto zpre = [&](int k) {
+    const int kb = k - 1;
+    const bool ok = kb >= k0 && kb < k1 && j < n1;
+    const unsigned cp = (unsigned)(i0 + n0 * (j + n1 * kb)) * (unsigned)sizeof(R);
+    zo0 = bld1(Bz, ok && i0 < n0 ? cp : Bz.oob, R{});
+    zo1 = bld1(Bz, ok && i0 + 1 < n0 ? cp + (unsigned)sizeof(R) : Bz.oob, R{});
+  };
   // coarse correction of the parents of vector m of plane k
   auto parent = [&](int m, int k, auto vok) -> VT {
     constexpr bool VOK = decltype(vok)::value;
@@ -1630,6 +1646,7 @@ __global__ void __launch_bounds__(NT2) k_sweep25(OpB<R> LB, SH S, const B *__res
     }
     // (read before the barrier: the next plane step overwrites plane k-1's slot)
     const R bB = sB[xs(k - 1) * NX + cb];
+    const R bA = DOT ? sB[xs(k - 1) * NX + PL::at(2 * tx + 1 - offA, ty)] : (R)0;
     // A cells of plane k: own, then one ring cell
     R *An = sA + (k & 1) * NX1;
     a_0 = j < n1 ? relax_a(2 * tx + offA, ty, k) : (R)0;
@@ -1667,6 +1684,12 @@ __global__ void __launch_bounds__(NT2) k_sweep25(OpB<R> LB, SH S, const B *__res
       }
       // the pair in memory order: offset 0 first
       const R v0 = offA == 0 ? vB : a_m1, v1 = offA == 0 ? a_m1 : vB;
+      if constexpr (DOT) {
+        // b and the new x are zero outside the mesh
+        const R b0 = offA == 0 ? bB : bA, b1 = offA == 0 ? bA : bB;
+        dz += (double)b0 * (double)v0 + (double)b1 * (double)v1;
+        dzo += (double)b0 * (double)zo0 + (double)b1 * (double)zo1;
+      }
       R *row = xout + n0 * (j + n1 * kb);
       if ((n0 & 1) == 0 && i0 + 1 < n0) {
         using V2 = typename Vec16<R>::T2;
@@ -1729,6 +1752,7 @@ __global__ void __launch_bounds__(NT2) k_sweep25(OpB<R> LB, SH S, const B *__res
     auto step = [&](Regs &G, int k) {
       store_planes(G, k + 1);  // its slot (plane k-2) is free
       __syncthreads();
+      if constexpr (DOT) zpre(k);
       load_planes(G, k + 3 <= k1 + 1 ? k + 3 : n2);  // plane n2: no memory access
       if (k <= k1) relax_planes(k);
     };
@@ -1752,6 +1776,14 @@ __global__ void __launch_bounds__(NT2) k_sweep25(OpB<R> LB, SH S, const B *__res
   };
   if (vec_ok) run(std::true_type{});
   else run(std::false_type{});
+  if constexpr (DOT) {
+    const double s1 = block_sum_n<NT2 / 64>(dz, lred);
+    if (t == 0) partials[g] = s1;
+    if (zold) {
+      const double s2 = block_sum_n<NT2 / 64>(dzo, lred);
+      if (t == 0) partials[off2 + g] = s2;
+    }
+  }
 }
 
 // Restriction after a pre-smoothing that ended with a black half sweep: the
@@ -2238,15 +2270,34 @@ static void sweep_fine(Handle *h, const OpB<R> &o, const B *b, const R *xin, R *
   const dim3 g(Z.nblk);
   const SH S = sh(h, Z);
   const int *m = h->act;
+  const R *nz = nullptr;
+  double *np = nullptr;
   if (mode == SW_ZERO)
     DBS_LAUNCH(h, KC_SMOOTH0_ZERO, (k_sweep25<R, B, SW_ZERO>), g, blk2(), o, S, b, xin, xout,
-               colA, xc, m);
+               colA, xc, m, nz, np, 0);
   else if (mode == SW_PROLONG)
     DBS_LAUNCH(h, KC_PROLONG0, (k_sweep25<R, B, SW_PROLONG>), g, blk2(), o, S, b, xin, xout,
-               colA, xc, m);
+               colA, xc, m, nz, np, 0);
   else
     DBS_LAUNCH(h, KC_SMOOTH0, (k_sweep25<R, B, SW_NORMAL>), g, blk2(), o, S, b, xin, xout,
-               colA, xc, m);
+               colA, xc, m, nz, np, 0);
+}
+
+// the same sweep (FP32, SW_PROLONG or SW_NORMAL) also forming the partial
+// sums of b.xout and b.zold per block of the fine smoothing shape
+static void sweep_fine_dot(Handle *h, const OpB<float> &o, const float *b, const float *xin,
+                           float *xout, int colA, int mode, const float *xc,
+                           const float *zold) {
+  const Shape &Z = h->lv[0].sm;
+  const dim3 g(Z.nblk);
+  const SH S = sh(h, Z);
+  const int *m = h->act;
+  if (mode == SW_PROLONG)
+    DBS_LAUNCH(h, KC_PROLONG0, (k_sweep25<float, float, SW_PROLONG, 0, 1>), g, blk2(), o, S,
+               b, xin, xout, colA, xc, m, zold, h->partials, (int)Z.nblk);
+  else
+    DBS_LAUNCH(h, KC_SMOOTH0, (k_sweep25<float, float, SW_NORMAL, 0, 1>), g, blk2(), o, S, b,
+               xin, xout, colA, xc, m, zold, h->partials, (int)Z.nblk);
 }
 
 // one fused sweep on coarse level l (FP32, stored coefficients), xin -> xout
@@ -2257,22 +2308,27 @@ static void sweep_coarse(Handle *h, int l, const OpB<float> &o, const float *b,
   const dim3 g(Z.nblk);
   const SH S = sh(h, Z);
   const int *m = h->act;
+  const float *nz = nullptr;
+  double *np = nullptr;
   if (mode == SW_ZERO)
     DBS_LAUNCH(h, KC_SMOOTHC, (k_sweep25<float, float, SW_ZERO, 1>), g, blk2(), o, S, b, xin,
-               xout, colA, xc, m);
+               xout, colA, xc, m, nz, np, 0);
   else if (mode == SW_PROLONG)
     DBS_LAUNCH(h, KC_SMOOTHC, (k_sweep25<float, float, SW_PROLONG, 1>), g, blk2(), o, S, b,
-               xin, xout, colA, xc, m);
+               xin, xout, colA, xc, m, nz, np, 0);
   else
     DBS_LAUNCH(h, KC_SMOOTHC, (k_sweep25<float, float, SW_NORMAL, 1>), g, blk2(), o, S, b,
-               xin, xout, colA, xc, m);
+               xin, xout, colA, xc, m, nz, np, 0);
 }
 
 // z = M r: one V-cycle over the active samples.  b0 is the fine right-hand
 // side (r); z0 and z1 are the two fine correction buffers; returns the one
-// holding the result.
+// holding the result.  dot (FP32 fused sweeps): the last sweep also leaves
+// the per-block partial sums of b0.z and b0.zold (zold may be null) for a
+// finalize over the fine smoothing shape.
 template <typename R, typename B>
-static R *vcycle(Handle *h, const R *rAUr, const B *b0, R *z0, R *z1) {
+static R *vcycle(Handle *h, const R *rAUr, const B *b0, R *z0, R *z1, bool dot = false,
+                 const R *zold = nullptr) {
   const int *act = h->act;
   const int nl = (int)h->lv.size();
   OpB<R> o0 = opb<R>(h, 0, rAUr);
@@ -2357,7 +2413,15 @@ static R *vcycle(Handle *h, const R *rAUr, const B *b0, R *z0, R *z1) {
   // fine level up: the prolongation rides on the first (black) half sweep
   if (h->fused_sweep) {
     for (int s = 0; s < h->mg_post; s++) {
-      sweep_fine<R, B>(h, o0, b0, cur, oth, 1, s == 0 ? SW_PROLONG : SW_NORMAL, xc1);
+      const int mode = s == 0 ? SW_PROLONG : SW_NORMAL;
+      if constexpr (std::is_same<R, float>::value && std::is_same<B, float>::value) {
+        if (dot && s + 1 == h->mg_post) {
+          sweep_fine_dot(h, o0, b0, cur, oth, 1, mode, xc1, zold);
+          std::swap(cur, oth);
+          continue;
+        }
+      }
+      sweep_fine<R, B>(h, o0, b0, cur, oth, 1, mode, xc1);
       std::swap(cur, oth);
     }
     return cur;
@@ -2497,19 +2561,28 @@ static int pcg(Handle *h, const double *rAU, const double *b, double *x, int bud
   R *zold = flex ? (R *)h->zoldf : nullptr;
   const Shape &ST = h->lv[0].st;
   OpB<double> o = opb<double>(h, 0, rAU);
-  auto precondition = [&]() -> R * {
+  // FP32 fused sweeps: r.z and r.zold come from the last sweep of the
+  // V-cycle, with the FP32 copy of r that the V-cycle reads (products and
+  // sums in FP64); otherwise from a separate pass with r in FP64
+  const bool fdot = flex && h->fused_sweep && h->mg_post >= 1;
+  const Shape *SM = &h->lv[0].sm;
+  auto precondition = [&](const R *zo) -> R * {
     if (flex)
       return (R *)vcycle<float, float>(h, (const float *)rAUr, (const float *)h->rf,
-                                       h->lv[0].xf, h->zf2);
+                                       h->lv[0].xf, h->zf2, fdot, (const float *)zo);
     return (R *)vcycle<double, double>(h, (const double *)rAUr, (const double *)h->r, h->z,
                                        h->z2);
   };
   int nact = graph ? 1 : fetch_flags(h, nullptr);
   if (nact > 0) {
-    R *zR = precondition();
-    DBS_LAUNCH(h, KC_DOT, k_dot2<R>, fg, ft, F, (const double *)h->r, (const R *)zR,
-               (const R *)nullptr, h->partials, (int)h->flat.nblk, act, 0);
-    finalize(h, fin_args(h, &h->flat, 0, S_RZ, 0, FIN_STORE, act));
+    R *zR = precondition(nullptr);
+    if (fdot) {
+      finalize(h, fin_args(h, SM, 0, S_RZ, 0, FIN_STORE, act));
+    } else {
+      DBS_LAUNCH(h, KC_DOT, k_dot2<R>, fg, ft, F, (const double *)h->r, (const R *)zR,
+                 (const R *)nullptr, h->partials, (int)h->flat.nblk, act, 0);
+      finalize(h, fin_args(h, &h->flat, 0, S_RZ, 0, FIN_STORE, act));
+    }
     // the direction update p = z + beta p rides on the SpMV, which reads the
     // old direction from pc and writes the new one to pn
     double *pc = h->pv, *pn = h->pv2;
@@ -2533,8 +2606,10 @@ static int pcg(Handle *h, const double *rAU, const double *b, double *x, int bud
         if (!graph) nact = fetch_flags(h, nullptr);
       }
       if (!graph && nact == 0) break;
-      R *zn = precondition();
-      if (flex) {
+      R *zn = precondition(zold);
+      if (fdot) {
+        finalize(h, fin_args(h, SM, 1, S_RZNEW, S_RZOLD, FIN_BETA_FLEX, act));
+      } else if (flex) {
         DBS_LAUNCH(h, KC_DOT, k_dot2<R>, fg, ft, F, (const double *)h->r, (const R *)zn,
                    (const R *)zold, h->partials, (int)h->flat.nblk, act, 0);
         finalize(h, fin_args(h, &h->flat, 1, S_RZNEW, S_RZOLD, FIN_BETA_FLEX, act));
