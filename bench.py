@@ -45,6 +45,9 @@ def alg_bytes_per_cell(cls: str, rsize: int, fused: bool = False) -> float:
     return {
         # fused red-black sweep (both colours): x, b, rAU read once, x written
         "smooth_fine": 4 * s,
+        # the last sweep of a mixed-precision V-cycle: z_old read as well
+        # (b.z and b.z_old formed in the sweep)
+        "smooth_fine_dot": 5 * s,
         # zero initial guess: b and rAU read, x written
         "smooth_fine_zero": 3 * s,
         # prolongation fused in the first up-sweep: x and the coarse
@@ -59,6 +62,7 @@ def alg_bytes_per_cell(cls: str, rsize: int, fused: bool = False) -> float:
         "residual": 32.0 + (4.0 if s == 4 else 0.0),
         # x, p, r, q read; x, r (and the FP32 copy of r) written
         "axpy": 48.0 + (4.0 if s == 4 else 0.0),
+        # r (FP64) and z read, and z_old in flexible CG with half sweeps
         "dot": 8.0 + s + (s if s == 4 else 0.0),
     }.get(cls, 0.0)
 

@@ -24,7 +24,8 @@ static const char *kNames[KC_COUNT] = {
     "mom_offdiag", "phihbya",     "correct",     "spmv",         "axpy",
     "dot",         "xpby",        "finalize",    "smooth_fine",  "restrict_fine",
     "prolong_fine", "smooth_coarse", "restrict_coarse", "prolong_coarse", "coarse_solve",
-    "build_coarse", "stats",      "misc",        "smooth_fine_zero", "residual"};
+    "build_coarse", "stats",      "misc",        "smooth_fine_zero", "residual",
+    "smooth_fine_dot"};
 
 void prof_begin(Handle *h, int cls) {
   Timer &t = h->tm;

@@ -23,7 +23,7 @@ enum KClass {
   KC_SPMV, KC_AXPY, KC_DOT, KC_XPBY, KC_FINALIZE,
   KC_SMOOTH0, KC_RESTRICT0, KC_PROLONG0,
   KC_SMOOTHC, KC_RESTRICTC, KC_PROLONGC, KC_COARSE, KC_BUILD_COARSE,
-  KC_STATS, KC_MISC, KC_SMOOTH0_ZERO, KC_RESIDUAL, KC_COUNT
+  KC_STATS, KC_MISC, KC_SMOOTH0_ZERO, KC_RESIDUAL, KC_SMOOTH0_DOT, KC_COUNT
 };
 
 constexpr int FLAT_T = 256;               // threads of a vector-kernel block

@@ -2296,8 +2296,8 @@ static void sweep_fine_dot(Handle *h, const OpB<float> &o, const float *b, const
     DBS_LAUNCH(h, KC_PROLONG0, (k_sweep25<float, float, SW_PROLONG, 0, 1>), g, blk2(), o, S,
                b, xin, xout, colA, xc, m, zold, h->partials, (int)Z.nblk);
   else
-    DBS_LAUNCH(h, KC_SMOOTH0, (k_sweep25<float, float, SW_NORMAL, 0, 1>), g, blk2(), o, S, b,
-               xin, xout, colA, xc, m, zold, h->partials, (int)Z.nblk);
+    DBS_LAUNCH(h, KC_SMOOTH0_DOT, (k_sweep25<float, float, SW_NORMAL, 0, 1>), g, blk2(), o, S,
+               b, xin, xout, colA, xc, m, zold, h->partials, (int)Z.nblk);
 }
 
 // one fused sweep on coarse level l (FP32, stored coefficients), xin -> xout
