@@ -56,8 +56,9 @@ def alg_bytes_per_cell(cls: str, rsize: int, fused: bool = False) -> float:
         # red residuals only: x and rAU read, red b read, coarse b written
         "restrict_fine": 2 * s + 0.5 * s + s / 8.0,
         # direction update fused in: z (s), old p and rAU read; new p and q
-        # written (FP64), and z_old (s) in flexible (mixed) CG
-        "spmv": 32.0 + s + (s if s == 4 else 0.0),
+        # written (FP64); in flexible (mixed) CG with half sweeps also a
+        # copy z_old (s) (fused sweeps rotate three z buffers instead)
+        "spmv": 32.0 + s + (s if s == 4 and not fused else 0.0),
         # true residual r = b - A x: x, rAU, b read; r (and its FP32 copy) written
         "residual": 32.0 + (4.0 if s == 4 else 0.0),
         # x, p, r, q read; x, r (and the FP32 copy of r) written

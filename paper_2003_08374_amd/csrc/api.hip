@@ -400,6 +400,12 @@ static int create_impl(int n, const dbs_grid *grids, const dbs_physics *phys, co
     return rc;
   }
   h->stream = h->own_stream;
+  if ((rc = hip_check(h, hipEventCreateWithFlags(&h->flag_ev, hipEventDisableTiming),
+                      "hipEventCreateWithFlags"))) {
+    hipStreamDestroy(h->own_stream);
+    delete H;
+    return rc;
+  }
   const size_t NC = (size_t)h->NC, NF = (size_t)h->NF;
   rc = DBS_OK;
   // per-cell launch shape and flat vector shape
@@ -793,6 +799,7 @@ void dbs_destroy(dbs_handle *H) {
   if (h->hsstat) hipHostFree(h->hsstat);
   if (h->hrec) hipHostFree(h->hrec);
   for (hipEvent_t e : h->tm.ev) hipEventDestroy(e);
+  if (h->flag_ev) hipEventDestroy(h->flag_ev);
   pressure_free(h);
   if (h->own_stream) hipStreamDestroy(h->own_stream);
   delete H;

@@ -138,6 +138,7 @@ struct Handle {
   double *hscal = nullptr;     // pinned host mirror
   int *act = nullptr, *want = nullptr;  // per-sample CG flags
   int *hflags = nullptr;       // pinned mirror: act | want
+  hipEvent_t flag_ev = nullptr;  // eager CG: the flags copy of an iteration has landed
   double *sstat = nullptr, *hsstat = nullptr;  // per-sample statistics (5 each)
 
   std::vector<Level> lv;

@@ -2524,6 +2524,20 @@ static int fetch_flags(Handle *h, int *nwant) {
   return na;
 }
 
+// eager CG: the active flags are copied to the host and an event marks
+// their arrival; the host waits on the event while later work is queued
+static void post_flags(Handle *h) {
+  (void)hipMemcpyAsync(h->hflags, h->act, sizeof(int) * h->ns, hipMemcpyDeviceToHost,
+                       h->stream);
+  (void)hipEventRecord(h->flag_ev, h->stream);
+}
+static int wait_flags(Handle *h) {
+  (void)hipEventSynchronize(h->flag_ev);
+  int na = 0;
+  for (int s = 0; s < h->ns; s++) na += h->hflags[s] != 0;
+  return na;
+}
+
 // act[s] = va (va < 0: unchanged), want[s] = vw
 static void set_flags(Handle *h, int va, int vw) {
   DBS_LAUNCH(h, KC_MISC, k_flags, dim3((h->ns + 255) / 256), dim3(256), va < 0 ? nullptr : h->act,
@@ -2558,7 +2572,7 @@ static int pcg(Handle *h, const double *rAU, const double *b, double *x, int bud
   const FL F = fl(h);
   const dim3 fg = flat_grid(h), ft(FLAT_T);
   const int *act = h->act;
-  R *zold = flex ? (R *)h->zoldf : nullptr;
+  R *zold = flex ? (R *)h->zoldf : nullptr;  // written by the SpMV unless z rotates
   const Shape &ST = h->lv[0].st;
   OpB<double> o = opb<double>(h, 0, rAU);
   // FP32 fused sweeps: r.z and r.zold come from the last sweep of the
@@ -2566,10 +2580,18 @@ static int pcg(Handle *h, const double *rAU, const double *b, double *x, int bud
   // sums in FP64); otherwise from a separate pass with r in FP64
   const bool fdot = flex && h->fused_sweep && h->mg_post >= 1;
   const Shape *SM = &h->lv[0].sm;
+  // With fdot, z rotates through three FP32 buffers: each V-cycle works in
+  // the two that do not hold the previous z, which stays as z_old (no copy).
+  float *zb[3] = {h->lv[0].xf, h->zf2, h->zoldf};
+  int zi = 2;  // buffer of the previous z
   auto precondition = [&](const R *zo) -> R * {
-    if (flex)
-      return (R *)vcycle<float, float>(h, (const float *)rAUr, (const float *)h->rf,
-                                       h->lv[0].xf, h->zf2, fdot, (const float *)zo);
+    if (flex) {
+      float *w0 = zb[zi == 0 ? 1 : 0], *w1 = zb[zi == 2 ? 1 : 2];
+      float *zn = vcycle<float, float>(h, (const float *)rAUr, (const float *)h->rf, w0, w1,
+                                       fdot, (const float *)zo);
+      if (fdot) zi = zn == zb[0] ? 0 : zn == zb[1] ? 1 : 2;
+      return (R *)zn;
+    }
     return (R *)vcycle<double, double>(h, (const double *)rAUr, (const double *)h->r, h->z,
                                        h->z2);
   };
@@ -2591,22 +2613,23 @@ static int pcg(Handle *h, const double *rAU, const double *b, double *x, int bud
       if (graph && it >= budget) break;
       DBS_LAUNCH(h, KC_SPMV, (k_stencil25<2, R>), dim3(ST.nblk), blk2(), o, sh(h, ST),
                  (const double *)pc, (const double *)nullptr, h->q, (float *)nullptr,
-                 h->partials, 0, act, zc, pn, zold, (const double *)h->scal, it == 0 ? 1 : 0);
+                 h->partials, 0, act, zc, pn, fdot ? (R *)nullptr : zold, (const double *)h->scal,
+                 it == 0 ? 1 : 0);
       std::swap(pc, pn);
       finalize(h, fin_args(h, &ST, 0, S_PQ, 0, FIN_ALPHA, act));
       DBS_LAUNCH(h, KC_AXPY, k_axpy_dot, fg, ft, F, (const double *)h->scal,
                  (const double *)pc, (const double *)h->q, x, h->r, rf, h->partials, act);
       finalize(h, fin_args(h, &h->flat, 0, S_RR, 0, FIN_RR, act));
-      int nwant = 1;
-      if (!graph) nact = fetch_flags(h, &nwant);
-      if (nwant > 0) {
-        // the true residual decides convergence (and replaces the recursive one)
-        true_residual(h, rAU, b, x, rf, h->want);
-        finalize(h, fin_args(h, nullptr, 0, 0, 0, FIN_CHECK, h->want));
-        if (!graph) nact = fetch_flags(h, nullptr);
-      }
-      if (!graph && nact == 0) break;
-      R *zn = precondition(zold);
+      // the true residual of the samples that ask for it decides convergence
+      // (and replaces the recursive one); launched every iteration, its
+      // blocks skip the other samples
+      true_residual(h, rAU, b, x, rf, h->want);
+      finalize(h, fin_args(h, nullptr, 0, 0, 0, FIN_CHECK, h->want));
+      // Eager: the flags of this iteration travel to the host while the
+      // V-cycle is queued behind them, so the device does not drain; when
+      // no sample is left active, that V-cycle was skipped block by block.
+      if (!graph) post_flags(h);
+      R *zn = precondition(fdot ? zc : zold);
       if (fdot) {
         finalize(h, fin_args(h, SM, 1, S_RZNEW, S_RZOLD, FIN_BETA_FLEX, act));
       } else if (flex) {
@@ -2619,6 +2642,7 @@ static int pcg(Handle *h, const double *rAU, const double *b, double *x, int bud
         finalize(h, fin_args(h, &h->flat, 0, S_RZNEW, 0, FIN_BETA, act));
       }
       zc = zn;
+      if (!graph && wait_flags(h) == 0) break;
     }
   }
   if (any_closed(h)) remove_mean(h, x, nullptr, nullptr);
