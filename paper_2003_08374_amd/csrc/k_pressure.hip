@@ -460,12 +460,14 @@ __global__ void __launch_bounds__(NTHREADS) k_smooth(OpB<R> LB, SH S, const B *_
 }
 
 // coarse right-hand side: sum over the 8 children of the fine residual; the
-// launch covers the coarse cells of the samples cycled on the fine level
+// launch covers the coarse cells of the samples cycled on the fine level.
+// red: the smoothing ended with a black half sweep, so only the red
+// children (even i + j + k) have a residual to add.
 template <typename R, typename B>
 __global__ void __launch_bounds__(NTHREADS) k_restrict(OpB<R> LB, SH S, const B *__restrict__ b,
                                                        const R *__restrict__ x,
                                                        R *__restrict__ bc,
-                                                       const int *__restrict__ mask) {
+                                                       const int *__restrict__ mask, int red) {
   int g, s, lb;
   if (!locate(S, mask, g, s, lb)) return;
   const Op<R> L = op_at(LB, s);
@@ -486,7 +488,7 @@ __global__ void __launch_bounds__(NTHREADS) k_restrict(OpB<R> LB, SH S, const B 
         if (j >= L.n1) continue;
         for (int di = 0; di < 2; di++) {
           const int i = 2 * I + di;
-          if (i >= L.n0) continue;
+          if (i >= L.n0 || (red && ((di + dj + dk) & 1))) continue;
           const int c = i + L.n0 * (j + L.n1 * k);
           R D, T[6];
           op_row(L, i, j, k, c, D, T);
@@ -694,10 +696,93 @@ __device__ inline void bl_sweep(const LdsView<R> &S, const BLevel<R> &L, int col
   __syncthreads();
 }
 
-// b of the coarser level: the sum of the residuals of a cell's (up to 8)
-// children; a missing child (odd size) reads the first child and adds zero
+// The pairs of a level that one thread relaxes when the level has at most
+// NP x 1024 pairs (pair q = threadIdx.x + 1024 u): first LDS cell, x index
+// and parity of j + k, computed once per visit of the level.  A missing
+// pair points at the level's first cell and stores nothing.
+template <int NP>
+struct BPairs {
+  int g[NP], i2[NP], par[NP];
+  bool ok[NP];
+};
+
+template <typename R, int NP>
+__device__ inline BPairs<NP> bl_pairs(const BLevel<R> &L) {
+  const int n0 = L.n0, n1 = L.n1;
+  const int hx = (n0 + 1) >> 1, np = hx * n1 * L.n2;
+  const float ihx = 1.0f / (float)hx, in1 = 1.0f / (float)n1;
+  BPairs<NP> P;
+#pragma unroll
+  for (int u = 0; u < NP; u++) {
+    const int q = (int)threadIdx.x + 1024 * u;
+    P.ok[u] = q < np;
+    const int qq = P.ok[u] ? q : 0;
+    const int row = sdiv(qq, hx, ihx), iq = qq - row * hx;
+    const int k = sdiv(row, n1, in1), j = row - k * n1;
+    P.g[u] = L.off + 2 * iq + n0 * row;
+    P.i2[u] = 2 * iq;
+    P.par[u] = (j + k) & 1;
+  }
+  return P;
+}
+
+// half sweep of colour `color` over planned pairs; the loads of all pairs
+// are issued before any store
+template <typename R, int NP>
+__device__ inline void bl_sweep_p(const LdsView<R> &S, const BLevel<R> &L, const BPairs<NP> &P,
+                                  int color, bool zero) {
+  const int n0 = L.n0, sy = n0, sz = n0 * L.n1;
+  int g[NP], o[NP];
+  R v[NP];
+#pragma unroll
+  for (int u = 0; u < NP; u++) {
+    o[u] = (P.par[u] + color) & 1;  // (i + j + k) & 1 == color
+    g[u] = P.g[u] + (P.ok[u] ? o[u] : 0);
+    const R d = S.d[g[u]];
+    const R sum = zero ? S.b[g[u]] : bl_nsum(S, g[u], sy, sz, S.b[g[u]]);
+    v[u] = d > (R)0 ? sum * sw_rcp(d) : (R)0;
+  }
+#pragma unroll
+  for (int u = 0; u < NP; u++) {
+    if (P.ok[u] && P.i2[u] + o[u] < n0) S.x[g[u]] = v[u];
+    if (zero && P.ok[u] && P.i2[u] + 1 - o[u] < n0) S.x[g[u] + 1 - 2 * o[u]] = (R)0;
+  }
+  __syncthreads();
+}
+
+// ns sweeps of a bottom level, each colour c0 then 1 - c0 (zero: the first
+// starts from x = 0)
 template <typename R>
-__device__ inline void bl_restrict(const LdsView<R> &S, const BLevel<R> &F, const BLevel<R> &C) {
+__device__ inline void bl_smooth(const LdsView<R> &S, const BLevel<R> &L, int ns, int c0,
+                                 bool zero) {
+  const int np = ((L.n0 + 1) >> 1) * L.n1 * L.n2;
+  if (np <= 1024) {
+    const BPairs<1> P = bl_pairs<R, 1>(L);
+    for (int s = 0; s < ns; s++) {
+      bl_sweep_p<R, 1>(S, L, P, c0, zero && s == 0);
+      bl_sweep_p<R, 1>(S, L, P, 1 - c0, false);
+    }
+  } else if (np <= 2048) {
+    const BPairs<2> P = bl_pairs<R, 2>(L);
+    for (int s = 0; s < ns; s++) {
+      bl_sweep_p<R, 2>(S, L, P, c0, zero && s == 0);
+      bl_sweep_p<R, 2>(S, L, P, 1 - c0, false);
+    }
+  } else {
+    for (int s = 0; s < ns; s++) {
+      bl_sweep(S, L, c0, zero && s == 0);
+      bl_sweep(S, L, 1 - c0, false);
+    }
+  }
+}
+
+// b of the coarser level: the sum of the residuals of a cell's (up to 8)
+// children; a missing child (odd size) reads the first child and adds zero.
+// red: the smoothing ended with a black half sweep, whose cells have zero
+// residual, so only the red children (even i + j + k) are summed.
+template <typename R>
+__device__ inline void bl_restrict(const LdsView<R> &S, const BLevel<R> &F, const BLevel<R> &C,
+                                   bool red) {
   const int n = C.n0 * C.n1 * C.n2;
   const int sy = F.n0, sz = F.n0 * F.n1;
   const float cin0 = 1.0f / (float)C.n0, cin1 = 1.0f / (float)C.n1;
@@ -712,6 +797,7 @@ __device__ inline void bl_restrict(const LdsView<R> &S, const BLevel<R> &F, cons
       for (int dj = 0; dj < 2; dj++)
 #pragma unroll
         for (int di = 0; di < 2; di++) {
+          if (red && ((di + dj + dk) & 1)) continue;
           const bool ok = 2 * I + di < F.n0 && 2 * J + dj < F.n1 && 2 * K + dk < F.n2;
           const int g = ok ? g0 + di + sy * dj + sz * dk : g0;
           const R r = S.b[g] - bl_ax(S, g, sy, sz);
@@ -744,9 +830,18 @@ template <typename R>
 __global__ void __launch_bounds__(1024) k_bottom(const Bottom<R> *__restrict__ tab,
                                                  const int *__restrict__ mask) {
   __shared__ __align__(16) R lds[BOTTOM_LDS / sizeof(R)];
+  __shared__ const R *ptab[MAXLV][5];  // per level: Tx, Ty, Tz, D, b
   const Bottom<R> &A = tab[blockIdx.x];
   if (mask && !mask[A.s]) return;
   const int N = A.ntot, P = A.pad, ST = N + P, nl = A.nl;
+  if ((int)threadIdx.x < nl) {
+    const BLevel<R> &L = A.L[threadIdx.x];
+    ptab[threadIdx.x][0] = L.Tx;
+    ptab[threadIdx.x][1] = L.Ty;
+    ptab[threadIdx.x][2] = L.Tz;
+    ptab[threadIdx.x][3] = L.D;
+    ptab[threadIdx.x][4] = L.b;
+  }
   LdsView<R> S{lds + P, lds + P + ST, lds + P + 2 * ST, lds + P + 3 * ST, lds + P + 4 * ST,
                lds + P + 5 * ST};
   // zero every array and pad (x starts at zero; pads stay zero)
@@ -767,15 +862,15 @@ __global__ void __launch_bounds__(1024) k_bottom(const Bottom<R> *__restrict__ t
     for (int u = 0; u < U; u++) {
       const int e0 = threadIdx.x + u * 1024;
       const int e = e0 < N ? e0 : N - 1;
-      int m = 0;
-      for (int q = 1; q < nl; q++) m += e >= A.L[q].off ? 1 : 0;
-      const BLevel<R> &L = A.L[m];
-      const int c = e - L.off;
-      v[u][0] = L.Tx[c];
-      v[u][1] = L.Ty[c];
-      v[u][2] = L.Tz[c];
-      v[u][3] = L.D[c];
-      v[u][4] = L.b[c];
+      int m = 0, off = 0;
+      for (int q = 1; q < nl; q++) {
+        const int oq = A.L[q].off;
+        m += e >= oq ? 1 : 0;
+        off = e >= oq ? oq : off;
+      }
+      const int c = e - off;
+#pragma unroll
+      for (int a = 0; a < 5; a++) v[u][a] = ptab[m][a][c];
     }
 #pragma unroll
     for (int u = 0; u < U; u++) {
@@ -791,27 +886,17 @@ __global__ void __launch_bounds__(1024) k_bottom(const Bottom<R> *__restrict__ t
   }
   __syncthreads();
   for (int l = 0; l < nl - 1; l++) {
-    for (int s = 0; s < A.pre; s++) {
-      bl_sweep(S, A.L[l], 0, s == 0);
-      bl_sweep(S, A.L[l], 1, false);
-    }
-    bl_restrict(S, A.L[l], A.L[l + 1]);
+    bl_smooth(S, A.L[l], A.pre, 0, true);
+    bl_restrict(S, A.L[l], A.L[l + 1], A.pre > 0);
   }
+  // coarsest level; a single cell is solved by its first half sweep
   const BLevel<R> &C = A.L[nl - 1];
-  for (int s = 0; s < A.coarse_sweeps; s++) {
-    bl_sweep(S, C, 0, s == 0);
-    bl_sweep(S, C, 1, false);
-  }
-  for (int s = 0; s < A.coarse_sweeps; s++) {
-    bl_sweep(S, C, 1, false);
-    bl_sweep(S, C, 0, false);
-  }
+  const bool one = C.n0 * C.n1 * C.n2 == 1;
+  bl_smooth(S, C, A.coarse_sweeps, 0, true);
+  if (!one) bl_smooth(S, C, A.coarse_sweeps, 1, false);
   for (int l = nl - 2; l >= 0; l--) {
     bl_prolong(S, A.L[l], A.L[l + 1]);
-    for (int s = 0; s < A.post; s++) {
-      bl_sweep(S, A.L[l], 1, false);
-      bl_sweep(S, A.L[l], 0, false);
-    }
+    bl_smooth(S, A.L[l], A.post, 1, false);
   }
   const BLevel<R> &T = A.L[0];
   const int n = T.n0 * T.n1 * T.n2;
@@ -2384,7 +2469,8 @@ static R *vcycle(Handle *h, const R *rAUr, const B *b0, R *z0, R *z1, bool dot =
     if (!lf) smooth_level<R, R>(h, l, o, (const R *)lb<R>(L), lx<R>(L), true);
     if (C.one_rc.nblk)
       DBS_LAUNCH(h, KC_RESTRICTC, (k_restrict<R, R>), dim3(C.one_rc.nblk), blk(), o,
-                 sh(h, C.one_rc), (const R *)lb<R>(L), (const R *)ccur[l], lb<R>(C), act);
+                 sh(h, C.one_rc), (const R *)lb<R>(L), (const R *)ccur[l], lb<R>(C), act,
+                 h->mgc > 0 ? 1 : 0);
   }
   if (h->nbt)
     DBS_LAUNCH(h, KC_COARSE, k_bottom<R>, dim3(h->nbt), dim3(1024),
@@ -2493,17 +2579,21 @@ static void dot_self_closed(Handle *h, const double *a, int slot, const int *mas
 }
 
 // true residual r = b - A x (and its FP32 copy) of the samples selected by
-// mask; S_RR = r.r (projected on closed samples) and S_BB = b.b
+// mask; S_RR = r.r (projected on closed samples) and S_BB = b.b; then the
+// finalize op `then` on the same samples (in the same launch as the sums
+// when no sample is closed)
 static void true_residual(Handle *h, const double *rAU, const double *b, const double *x,
-                          float *rf, const int *mask) {
+                          float *rf, const int *mask, int then = FIN_STORE) {
   const Shape &Z = h->lv[0].st;
   OpB<double> o = opb<double>(h, 0, rAU);
   DBS_LAUNCH(h, KC_RESIDUAL, k_stencil25<1>, dim3(Z.nblk), blk2(), o, sh(h, Z), x, b, h->r, rf,
              h->partials, (int)Z.nblk, mask);
-  finalize(h, fin_args(h, &Z, 1, S_RR, S_BB, FIN_STORE, mask));
-  if (any_closed(h)) {
+  const bool closed = any_closed(h);
+  finalize(h, fin_args(h, &Z, 1, S_RR, S_BB, closed ? FIN_STORE : then, mask));
+  if (closed) {
     remove_mean(h, h->r, rf, mask);
     dot_self_closed(h, h->r, S_RR, mask);
+    if (then != FIN_STORE) finalize(h, fin_args(h, nullptr, 0, 0, 0, then, mask));
   }
 }
 
@@ -2623,8 +2713,7 @@ static int pcg(Handle *h, const double *rAU, const double *b, double *x, int bud
       // the true residual of the samples that ask for it decides convergence
       // (and replaces the recursive one); launched every iteration, its
       // blocks skip the other samples
-      true_residual(h, rAU, b, x, rf, h->want);
-      finalize(h, fin_args(h, nullptr, 0, 0, 0, FIN_CHECK, h->want));
+      true_residual(h, rAU, b, x, rf, h->want, FIN_CHECK);
       // Eager: the flags of this iteration travel to the host while the
       // V-cycle is queued behind them, so the device does not drain; when
       // no sample is left active, that V-cycle was skipped block by block.
