@@ -457,6 +457,7 @@ static int create_impl(int n, const dbs_grid *grids, const dbs_physics *phys, co
   h->Qp = dmalloc(h, NC, rc); h->Qm = dmalloc(h, NC, rc); h->Pin = dmalloc(h, NC, rc);
   h->Pout = dmalloc(h, NC, rc); h->Rp = dmalloc(h, NC, rc); h->Rm = dmalloc(h, NC, rc);
   h->rAU = dmalloc(h, NC, rc); h->Sh = dmalloc(h, 3 * NC, rc); h->B = dmalloc(h, 3 * NC, rc);
+  h->AN = dmalloc(h, 6 * NC, rc); h->FB = dmalloc(h, NF, rc);
   h->HbyA = dmalloc(h, 3 * NC, rc); h->phiH = dmalloc(h, NF, rc); h->rhs = dmalloc(h, NC, rc);
   h->r = dmalloc(h, NC, rc); h->z = dmalloc(h, NC, rc); h->pv = dmalloc(h, NC, rc);
   h->q = dmalloc(h, NC, rc); h->pv2 = dmalloc(h, NC, rc);

@@ -123,6 +123,8 @@ struct Handle {
          *Rm = nullptr;
   // momentum / pressure work arrays
   double *rAU = nullptr, *Sh = nullptr, *B = nullptr, *HbyA = nullptr;  // Sh,B,HbyA 3 x NC
+  double *AN = nullptr;  // momentum neighbour coefficients of the step, 6 x NC
+  double *FB = nullptr;  // body force F_c - (g.x_f) dn(rho) of each face, for the step
   double *phiH = nullptr;  // faces
   double *rhs = nullptr;
   // PCG vectors

@@ -10,8 +10,12 @@
 //   q_f = [F_c,f - (g.x_f) dn(rho) - dn(p_rgh)] A_f,
 //   F_c = (f_l - alpha)[(rho_l - rho_g) g + grad p_c] - p_c grad alpha   (App. B)
 // are reconstructed to cells as R(q)_x = (q_west + q_east)/(2 A_x).
-// Neighbour coefficients are never stored: every kernel rebuilds them from
-// rhoPhi, alpha (viscosity) and phi, which costs fewer bytes than 7 arrays.
+// Quantities fixed within a step are formed once and stored: the neighbour
+// coefficients a_N (6 per cell, by the assembly) for the three Jacobi sweeps
+// and the two H evaluations, and the face body force F_c - (g.x_f) dn(rho)
+// (one per face) for the assembly and both correctors; the kernels then
+// read them instead of gathering phi, alpha, p_c and f_l - alpha of every
+// neighbour.
 #include "dbs_internal.h"
 
 namespace dbs {
@@ -25,6 +29,7 @@ struct MomArgs {
   const double *__restrict__ cf;  // f_l - alpha (porous), 0 (clear)
   const double *__restrict__ prgh;
   const double *__restrict__ rAU;
+  const double *__restrict__ FB;  // face_body of each interior face (k_face_body)
 };
 
 __device__ __forceinline__ bool empty_axis(const Geom &G, int a) {
@@ -68,7 +73,7 @@ __device__ inline double face_force(const Geom &G, const Phys &Ph, const MomArgs
     const int nb = bnd ? P.c : nbr_of(G, P, a, s);
     const int own = s ? P.c : nb, nbr = s ? nb : P.c;
     const double vi =
-        (face_body(G, Ph, M, own, nbr, a, gxf) - (prgh[nbr] - prgh[own]) * G.ih[a]) * G.area[a];
+        (M.FB[face_of(G, P, a, s)] - (prgh[nbr] - prgh[own]) * G.ih[a]) * G.area[a];
     const double pb = G.bcp[2 * a + s] - rho_of(Ph, M.alpha[P.c]) * gxf;
     const double sn = s ? (pb - prgh[P.c]) * 2.0 * G.ih[a] : (prgh[P.c] - pb) * 2.0 * G.ih[a];
     return bnd ? -sn * G.area[a] : vi;
@@ -81,8 +86,7 @@ __device__ inline double face_force(const Geom &G, const Phys &Ph, const MomArgs
   }
   const int nb = nbr_of(G, P, a, s);
   const int own = s ? P.c : nb, nbr = s ? nb : P.c;
-  return (face_body(G, Ph, M, own, nbr, a, gxf) - (prgh[nbr] - prgh[own]) * G.ih[a]) *
-         G.area[a];
+  return (M.FB[face_of(G, P, a, s)] - (prgh[nbr] - prgh[own]) * G.ih[a]) * G.area[a];
 }
 
 __device__ __forceinline__ bool fixed_flux(const Geom &G, int b) {
@@ -181,12 +185,16 @@ __device__ inline double dU(const Geom &G, const double *__restrict__ U, int Qc,
   return empty_axis(G, axis) ? 0.0 : (f1 - f0) * G.ih[axis];
 }
 
+// rAU = 1/a_P, Sh, B = Sh + R(q), and the neighbour coefficients a_N of the
+// six faces (face 2a+s; zero on boundary and empty faces) into AN, which
+// every Jacobi sweep and H evaluation of the step reads
 __global__ void __launch_bounds__(NTHREADS) k_mom_assemble(Segs SG, Phys Ph, MomArgs M,
                                                            const double *__restrict__ U,
                                                            int transpose,
                                                            double *__restrict__ rAU,
                                                            double *__restrict__ Sh,
-                                                           double *__restrict__ B) {
+                                                           double *__restrict__ B,
+                                                           double *__restrict__ AN) {
   FOR_CELLS(SG, G, P) {
   const int c = P.c;
   const double phP = M.phi[c];
@@ -198,9 +206,14 @@ __global__ void __launch_bounds__(NTHREADS) k_mom_assemble(Segs SG, Phys Ph, Mom
   double S[3];
   for (int d = 0; d < 3; d++) S[d] = rho_o * U[(size_t)d * G.vs + c] / (phP * G.dt);
   for (int a = 0; a < 3; a++) {
-    if (empty_axis(G, a)) continue;
+    if (empty_axis(G, a)) {
+      AN[(size_t)(2 * a) * G.vs + c] = 0.0;
+      AN[(size_t)(2 * a + 1) * G.vs + c] = 0.0;
+      continue;
+    }
     for (int s = 0; s < 2; s++) {
       FaceCoef fc = mom_face(G, Ph, M, P, a, s);
+      AN[(size_t)(2 * a + s) * G.vs + c] = fc.aN;
       aP += fc.diag;
       if (fc.src != 0.0) {
         S[0] += fc.src * inlet_u(G, 2 * a + s, P.j, 0);
@@ -254,8 +267,9 @@ __global__ void __launch_bounds__(NTHREADS) k_mom_assemble(Segs SG, Phys Ph, Mom
 }
 
 // Uout = rAU (sum_N a_N Uin_N + src): one Jacobi sweep (src = S + R(q)) or
-// HbyA (src = S)
+// HbyA (src = S), with the step's a_N from the assembly
 __global__ void __launch_bounds__(NTHREADS) k_mom_offdiag(Segs SG, Phys Ph, MomArgs M,
+                                                          const double *__restrict__ AN,
                                                           const double *__restrict__ Uin,
                                                           const double *__restrict__ src,
                                                           double *__restrict__ Uout) {
@@ -263,9 +277,8 @@ __global__ void __launch_bounds__(NTHREADS) k_mom_offdiag(Segs SG, Phys Ph, MomA
   const int c = P.c;
   const size_t vs = (size_t)G.vs;
   // All six faces without branches: a boundary face reads the cell itself
-  // and is dropped by a zero weight, so every load can be issued at once.
+  // with a zero weight, so every load can be issued at once.
   double aN[6], un[6][3];
-  const double phP = M.phi[c], muP = mu_of(Ph, M.alpha[c]);
 #pragma unroll
   for (int a = 0; a < 3; a++) {
 #pragma unroll
@@ -273,12 +286,7 @@ __global__ void __launch_bounds__(NTHREADS) k_mom_offdiag(Segs SG, Phys Ph, MomA
       const int q = 2 * a + s;
       const bool interior = !empty_axis(G, a) && !on_boundary(G, P, a, s);
       const int nb = interior ? nbr_of(G, P, a, s) : c;
-      const double rp = M.rhoPhi[face_of(G, P, a, s)];
-      const double out = s ? rp : -rp;
-      const double phf = 0.5 * (phP + M.phi[nb]);
-      const double vis = 0.5 * (muP + mu_of(Ph, M.alpha[nb])) * G.area[a] * G.ih[a] * G.iV;
-      const double conv = 1.0 / (phf * phP * G.V);
-      aN[q] = interior ? fmax(-out, 0.0) * conv + vis : 0.0;
+      aN[q] = AN[(size_t)q * vs + c];
 #pragma unroll
       for (int d = 0; d < 3; d++) un[q][d] = Uin[(size_t)d * vs + nb];
     }
@@ -309,7 +317,7 @@ __device__ inline double phi_hbya(const Geom &G, const Phys &Ph, const MomArgs &
   const double rAUf = 0.5 * (M.rAU[own] + M.rAU[nbr]);
   const double gxf = gdotx_face(G, Ph, P, a, s);
   return 0.5 * (Ha[own] + Ha[nbr]) * G.area[a] +
-         rAUf * face_body(G, Ph, M, own, nbr, a, gxf) * G.area[a];
+         rAUf * M.FB[face_of(G, P, a, s)] * G.area[a];
 }
 
 __global__ void __launch_bounds__(NTHREADS) k_phihbya(Segs SG, Phys Ph, MomArgs M,
@@ -379,18 +387,36 @@ __global__ void __launch_bounds__(NTHREADS) k_correct(Segs SG, Phys Ph, MomArgs 
 }
 
 static MomArgs mom_args(Handle *h) {
-  return MomArgs{h->alpha, h->alpha_old, h->rhoPhi, h->phi, h->kinv, h->ml,
-                 h->mg,    h->pc,        h->cf,     h->prgh, h->rAU};
+  return MomArgs{h->alpha, h->alpha_old, h->rhoPhi, h->phi,  h->kinv, h->ml,
+                 h->mg,    h->pc,        h->cf,     h->prgh, h->rAU,  h->FB};
+}
+
+// FB = face_body on every interior face (each cell its minus faces), zero
+// on domain faces: alpha, p_c and f_l - alpha are fixed within a step, so
+// the assembly and both correctors read it instead of gathering them
+__global__ void __launch_bounds__(NTHREADS) k_face_body(Segs SG, Phys Ph, MomArgs M,
+                                                        double *__restrict__ FB) {
+  FOR_CELLS(SG, G, P) {
+  for (int a = 0; a < 3; a++) {
+    const int f0 = face_of(G, P, a, 0);
+    if (on_boundary(G, P, a, 0))
+      FB[f0] = 0.0;
+    else
+      FB[f0] = face_body(G, Ph, M, P.c - stride_of(G, a), P.c, a, gdotx_face(G, Ph, P, a, 0));
+    if (on_boundary(G, P, a, 1)) FB[face_of(G, P, a, 1)] = 0.0;
+  }
+  }
 }
 
 void momentum_predictor(Handle *h) {
   dim3 blk(BX, BY);
   MomArgs M = mom_args(h);
+  DBS_LAUNCH(h, KC_MOM_ASSEMBLE, k_face_body, h->cgrid, blk, h->seg, h->P, M, h->FB);
   DBS_LAUNCH(h, KC_MOM_ASSEMBLE, k_mom_assemble, h->cgrid, blk, h->seg, h->P, M,
-             (const double *)h->U, h->ctl.transpose_visc, h->rAU, h->Sh, h->B);
+             (const double *)h->U, h->ctl.transpose_visc, h->rAU, h->Sh, h->B, h->AN);
   for (int s = 0; s < h->ctl.mom_sweeps; s++) {
     DBS_LAUNCH(h, KC_MOM_OFFDIAG, k_mom_offdiag, h->cgrid, blk, h->seg, h->P, M,
-               (const double *)h->U, (const double *)h->B, h->U2);
+               (const double *)h->AN, (const double *)h->U, (const double *)h->B, h->U2);
     double *t = h->U;
     h->U = h->U2;
     h->U2 = t;
@@ -401,7 +427,7 @@ void corrector_assemble(Handle *h) {
   dim3 blk(BX, BY);
   MomArgs M = mom_args(h);
   DBS_LAUNCH(h, KC_MOM_OFFDIAG, k_mom_offdiag, h->cgrid, blk, h->seg, h->P, M,
-             (const double *)h->U, (const double *)h->Sh, h->HbyA);
+             (const double *)h->AN, (const double *)h->U, (const double *)h->Sh, h->HbyA);
   DBS_LAUNCH(h, KC_PHIHBYA, k_phihbya, h->cgrid, blk, h->seg, h->P, M, (const double *)h->HbyA,
              h->phiH, h->rhs);
 }
