@@ -45,21 +45,26 @@ __device__ inline void grad_alpha(const Geom &G, const AlphaArgs &X, const Cell 
   }
 }
 
-// Antidiffusive flux of the interior face on the minus side of cell N along a.
+// Antidiffusive flux of the face on the minus side of cell N along a
+// (zero on a domain face).  Every load of the upwind stencil and of the
+// porous form is issued before any branch; a domain face reads the cell
+// itself and is discarded.
 __device__ inline double face_antidiffusive(const Geom &G, const Phys &Ph, const AlphaArgs &X,
                                             const Cell &N, int a, int f) {
+  const bool bnd = on_boundary(G, N, a, 0);
   const int sa = stride_of(G, a);
-  const int o = N.c - sa, n = N.c;
+  const int o = bnd ? N.c : N.c - sa, n = N.c;
   const double Ff = X.F[f];
   const double ao = X.alpha[o], an = X.alpha[n];
+  const double ko = X.kinv[o], kn = X.kinv[n];
   const bool fwd = Ff >= 0.0;
+  // second upwind cell, or the upwind cell itself next to a domain face
+  const int iuu = fwd ? (N.co[a] >= 2 ? o - sa : o) : (N.co[a] + 1 < G.n[a] ? n + sa : n);
+  const double auu = X.alpha[iuu];
+  const double pro = X.prgh[o], prn = X.prgh[n], pco = X.pc[o], pcn = X.pc[n];
+  const double mlo = X.ml[o], mln = X.ml[n], mgo = X.mg[o], mgn = X.mg[n];
   const double aU = fwd ? ao : an, aD = fwd ? an : ao;
-  double aUU = aU;
-  if (fwd) {
-    if (N.co[a] >= 2) aUU = X.alpha[o - sa];
-  } else {
-    if (N.co[a] + 1 < G.n[a]) aUU = X.alpha[n + sa];
-  }
+  const double aUU = auu;
   const double FL = Ff * aU;
   double avl = aU;
   if (aD != aU) {
@@ -68,11 +73,10 @@ __device__ inline double face_antidiffusive(const Geom &G, const Phys &Ph, const
     avl = aU + 0.5 * psi * (aD - aU);
   }
   double Gr;
-  const double ko = X.kinv[o], kn = X.kinv[n];
+  Cell O = shifted(G, N, a, bnd ? 0 : -1);
   if (ko == 0.0 && kn == 0.0) {
     // clear face: compression flux along +grad(alpha), face-local |v|
     double go[3], gn[3];
-    Cell O = shifted(G, N, a, -1);
     grad_alpha(G, X, O, go);
     grad_alpha(G, X, N, gn);
     double gf[3], mag2 = 0.0;
@@ -85,45 +89,47 @@ __device__ inline double face_antidiffusive(const Geom &G, const Phys &Ph, const
     Gr = Fr >= 0.0 ? Fr * ao * (1.0 - an) : Fr * an * (1.0 - ao);
   } else {
     // porous face: alpha_g u_l - alpha u_g with phase-upwinded mobilities
-    Cell O = shifted(G, N, a, -1);
     const double k0f = 2.0 / (ko + kn);
     const double af = 0.5 * (ao + an), agf = 1.0 - af;
     const double ga = Ph.g[a];
-    const double po = X.prgh[o] + rho_of(Ph, ao) * gdotx_cell(G, Ph, O);
-    const double pn = X.prgh[n] + rho_of(Ph, an) * gdotx_cell(G, Ph, N);
-    const double pco = X.pc[o], pcn = X.pc[n];
+    const double po = pro + rho_of(Ph, ao) * gdotx_cell(G, Ph, O);
+    const double pn = prn + rho_of(Ph, an) * gdotx_cell(G, Ph, N);
     const double dp = (pn - po) * G.ih[a];
     const double dpl = dp - ((1.0 - an) * pcn - (1.0 - ao) * pco) * G.ih[a] - Ph.rho_l * ga;
     const double dpg = dp + (an * pcn - ao * pco) * G.ih[a] - Ph.rho_g * ga;
-    const double mlf = dpl < 0.0 ? X.ml[o] : X.ml[n];
-    const double mgf = dpg < 0.0 ? X.mg[o] : X.mg[n];
+    const double mlf = dpl < 0.0 ? mlo : mln;
+    const double mgf = dpg < 0.0 ? mgo : mgn;
     const double ul = -k0f * mlf * dpl * G.area[a];
     const double ug = -k0f * mgf * dpg * G.area[a];
     Gr = agf * ul - af * ug;
   }
-  return Ff * avl + Gr - FL;
+  return bnd ? 0.0 : Ff * avl + Gr - FL;
 }
 
 __global__ void __launch_bounds__(NTHREADS) k_alpha_face(Segs SG, Phys Ph, AlphaArgs X,
                                                          double *__restrict__ A) {
   FOR_CELLS(SG, G, P) {
+#pragma unroll
   for (int a = 0; a < 3; a++) {
-    int f = face_of(G, P, a, 0);
-    A[f] = on_boundary(G, P, a, 0) ? 0.0 : face_antidiffusive(G, Ph, X, P, a, f);
+    const int f = face_of(G, P, a, 0);
+    A[f] = face_antidiffusive(G, Ph, X, P, a, f);
     if (P.co[a] == G.n[a] - 1) A[face_of(G, P, a, 1)] = 0.0;
   }
   }
 }
 
 // low-order (upwind) flux of side s of cell P along a, oriented along +axis
+// (both candidate upwind values are loaded with the flux, before any
+// branch; a domain face reads the cell itself)
 __device__ __forceinline__ double low_order_flux(const Geom &G, const double *__restrict__ alpha,
                                                  const double *__restrict__ F, const Cell &P,
                                                  int a, int s, int f, bool bnd) {
-  double Ff = F[f];
-  if (bnd) return Ff * bnd_alpha(G, 2 * a + s, P.j, alpha[P.c], Ff);
-  int nb = P.c + (s ? 1 : -1) * stride_of(G, a);
-  int own = s ? P.c : nb, nbr = s ? nb : P.c;
-  return Ff * (Ff >= 0.0 ? alpha[own] : alpha[nbr]);
+  const double Ff = F[f];
+  const int nb = bnd ? P.c : P.c + (s ? 1 : -1) * stride_of(G, a);
+  const double ac = alpha[P.c], anb = alpha[nb];
+  if (bnd) return Ff * bnd_alpha(G, 2 * a + s, P.j, ac, Ff);
+  const double aown = s ? ac : anb, anbr = s ? anb : ac;
+  return Ff * (Ff >= 0.0 ? aown : anbr);
 }
 
 __global__ void __launch_bounds__(NTHREADS) k_alpha_bounds(Segs SG, const double *__restrict__ alpha, const double *__restrict__ F,
