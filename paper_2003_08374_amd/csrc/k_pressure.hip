@@ -320,6 +320,15 @@ __global__ void k_flags(int *__restrict__ a, int va, int *__restrict__ w, int vw
   }
 }
 
+// after the CG loop: the samples whose last S_RR is not the true residual of
+// the final x (still active, stopped by the iteration limit on the
+// recursive residual, or closed: the mean was removed from x)
+__global__ void k_want_final(const double *__restrict__ scal, const int *__restrict__ act,
+                             const Rng *__restrict__ rng, int *__restrict__ want, int n) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s < n) want[s] = (act[s] || scal[(size_t)s * NSC + S_NOCONV] != 0.0 || rng[s].closed) ? 1 : 0;
+}
+
 enum {
   FIN_STORE = 0, FIN_ALPHA, FIN_BETA, FIN_BETA_FLEX, FIN_RR, FIN_CHECK, FIN_INIT, FIN_RRFIN
 };
@@ -2541,7 +2550,10 @@ static FinArgs fin_args(Handle *h, const Shape *S, int two, int slot, int slot2,
   A.want = h->want;
   A.tol2 = h->ctl.p_tol * h->ctl.p_tol;
   A.maxit = h->ctl.p_maxit;
-  A.replace_every = h->ctl.precision == DBS_MIXED ? 8 : 0;
+  // the recursive residual is updated in FP64 in both forms (only z comes
+  // from the FP32 V-cycle), so the true residual is formed only when the
+  // recursive one reports convergence
+  A.replace_every = 0;
   return A;
 }
 
@@ -2735,9 +2747,10 @@ static int pcg(Handle *h, const double *rAU, const double *b, double *x, int bud
     }
   }
   if (any_closed(h)) remove_mean(h, x, nullptr, nullptr);
-  // final true residual of every sample (act is kept: a sample still active
-  // here did not converge within the budget)
-  set_flags(h, -1, 1);
+  // final true residual (act is kept: a sample still active here did not
+  // converge within the budget); a sample that converged holds it already
+  DBS_LAUNCH(h, KC_MISC, k_want_final, dim3((h->ns + 255) / 256), dim3(256),
+             (const double *)h->scal, (const int *)h->act, (const Rng *)h->rng, h->want, h->ns);
   true_residual(h, rAU, b, x, nullptr, h->want);
   finalize(h, fin_args(h, nullptr, 0, 0, 0, FIN_RRFIN, nullptr));
   if (graph) return DBS_OK;
