@@ -109,14 +109,29 @@ __global__ void __launch_bounds__(NTHREADS) k_stats(Segs SG, const double *__res
   }
 }
 
-// one block per sample: reduce the sample's block partials
-__global__ void __launch_bounds__(256) k_stats_final(const double *__restrict__ part, int nb,
-                                                     const int *__restrict__ bp,
-                                                     double *__restrict__ out) {
-  __shared__ double lds[5][4];
+// one block per sample: reduce the sample's block partials (four per
+// thread and loop trip, so that many loads are in flight)
+__global__ void __launch_bounds__(1024) k_stats_final(const double *__restrict__ part, int nb,
+                                                      const int *__restrict__ bp,
+                                                      double *__restrict__ out) {
+  __shared__ double lds[5][16];
   const int t = threadIdx.x, s = blockIdx.x;
   double r[5] = {1e300, -1e300, 0.0, 0.0, 0.0};
-  for (int i = bp[s] + t; i < bp[s + 1]; i += 256) {
+  const int b0 = bp[s], b1 = bp[s + 1];
+  int i = b0 + t;
+  for (; i + 3 * 1024 < b1; i += 4 * 1024) {
+    double v[4][5];
+#pragma unroll
+    for (int u = 0; u < 4; u++)
+#pragma unroll
+      for (int q = 0; q < 5; q++) v[u][q] = part[q * nb + i + u * 1024];
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+      r[0] = fmin(r[0], v[u][0]); r[1] = fmax(r[1], v[u][1]); r[2] += v[u][2];
+      r[3] = fmax(r[3], v[u][3]); r[4] += v[u][4];
+    }
+  }
+  for (; i < b1; i += 1024) {
     r[0] = fmin(r[0], part[i]); r[1] = fmax(r[1], part[nb + i]); r[2] += part[2 * nb + i];
     r[3] = fmax(r[3], part[3 * nb + i]); r[4] += part[4 * nb + i];
   }
@@ -127,7 +142,7 @@ __global__ void __launch_bounds__(256) k_stats_final(const double *__restrict__ 
   __syncthreads();
   if (t == 0) {
     double v[5] = {1e300, -1e300, 0.0, 0.0, 0.0};
-    for (int w = 0; w < 4; w++) {
+    for (int w = 0; w < 16; w++) {
       v[0] = fmin(v[0], lds[0][w]); v[1] = fmax(v[1], lds[1][w]); v[2] += lds[2][w];
       v[3] = fmax(v[3], lds[3][w]); v[4] += lds[4][w];
     }
@@ -187,7 +202,7 @@ void cell_stats(Handle *h) {
   DBS_LAUNCH(h, KC_STATS, k_stats, h->cgrid, blk, h->seg, (const double *)h->alpha,
              (const double *)h->U, (const double *)h->prgh, (const double *)h->phi,
              (const double *)h->F, h->partials, nb);
-  DBS_LAUNCH(h, KC_STATS, k_stats_final, dim3(h->ns), dim3(256), (const double *)h->partials,
+  DBS_LAUNCH(h, KC_STATS, k_stats_final, dim3(h->ns), dim3(1024), (const double *)h->partials,
              nb, (const int *)h->cell.bp, h->sstat);
   hipMemcpyAsync(h->hsstat, h->sstat, 5 * sizeof(double) * h->ns, hipMemcpyDeviceToHost,
                  h->stream);

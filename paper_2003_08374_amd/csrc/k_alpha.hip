@@ -132,9 +132,12 @@ __device__ __forceinline__ double low_order_flux(const Geom &G, const double *__
   return Ff * (Ff >= 0.0 ? aown : anbr);
 }
 
+// also the cell factors R+- of the first limiter iteration (all face limiters
+// 1, so the limited sums equal P-+)
 __global__ void __launch_bounds__(NTHREADS) k_alpha_bounds(Segs SG, const double *__restrict__ alpha, const double *__restrict__ F,
     const double *__restrict__ phi, const double *__restrict__ A, double *__restrict__ Qp,
-    double *__restrict__ Qm, double *__restrict__ Pin, double *__restrict__ Pout) {
+    double *__restrict__ Qm, double *__restrict__ Pin, double *__restrict__ Pout,
+    double *__restrict__ Rp, double *__restrict__ Rm) {
   FOR_CELLS(SG, G, P) {
   const double aP = alpha[P.c];
   double outL = 0.0, amax = aP, amin = aP, pin = 0.0, pout = 0.0;
@@ -163,10 +166,13 @@ __global__ void __launch_bounds__(NTHREADS) k_alpha_bounds(Segs SG, const double
   amin = fmax(0.0, amin);
   const double vol = phi[P.c] * G.V / G.dt;
   const double aL = aP - outL / vol;
-  Qp[P.c] = vol * fmax(0.0, amax - aL);
-  Qm[P.c] = vol * fmax(0.0, aL - amin);
+  const double qp = vol * fmax(0.0, amax - aL), qm = vol * fmax(0.0, aL - amin);
+  Qp[P.c] = qp;
+  Qm[P.c] = qm;
   Pin[P.c] = pin;
   Pout[P.c] = pout;
+  Rp[P.c] = pin > 0.0 ? clamp01((qp + pout) / pin, 0.0, 1.0) : 1.0;
+  Rm[P.c] = pout > 0.0 ? clamp01((qm + pin) / pout, 0.0, 1.0) : 1.0;
   }
 }
 
@@ -301,12 +307,14 @@ void alpha_stage(Handle *h) {
   DBS_LAUNCH(h, KC_ALPHA_FACE, k_alpha_face, h->cgrid, blk, h->seg, h->P, X, h->A);
   DBS_LAUNCH(h, KC_ALPHA_BOUNDS, k_alpha_bounds, h->cgrid, blk, h->seg, (const double *)h->alpha,
              (const double *)h->F, (const double *)h->phi, (const double *)h->A, h->Qp, h->Qm,
-             h->Pin, h->Pout);
+             h->Pin, h->Pout, h->Rp, h->Rm);
   for (int it = 0; it < h->ctl.mules_iter; it++) {
     int first = it == 0;
-    DBS_LAUNCH(h, KC_ALPHA_LIMIT, k_alpha_R, h->cgrid, blk, h->seg, (const double *)h->A,
-               (const double *)h->lam, first, (const double *)h->Qp, (const double *)h->Qm,
-               (const double *)h->Pin, (const double *)h->Pout, h->Rp, h->Rm);
+    // the first iteration's R+- come from the bounds pass
+    if (!first)
+      DBS_LAUNCH(h, KC_ALPHA_LIMIT, k_alpha_R, h->cgrid, blk, h->seg, (const double *)h->A,
+                 (const double *)h->lam, first, (const double *)h->Qp, (const double *)h->Qm,
+                 (const double *)h->Pin, (const double *)h->Pout, h->Rp, h->Rm);
     DBS_LAUNCH(h, KC_ALPHA_LIMIT, k_alpha_lambda, h->cgrid, blk, h->seg, (const double *)h->A,
                (const double *)h->Rp, (const double *)h->Rm, first, h->lam);
   }
