@@ -3,10 +3,12 @@
 // Sec. 2.3 summary (interface compression in clear regions, Eq. (vr_porous)
 // in porous regions) and the MULES flux limiter (Sec. 3.2).
 //
-// Five passes over the cells (plus two per extra limiter iteration):
+// Four passes over the cells (plus two per extra limiter iteration):
 //   alpha_face     antidiffusive face flux A = F*alpha_VL + G - F*alpha_upwind
-//   alpha_bounds   local extrema, low-order provisional alpha, Q+-, P+-
-//   alpha_R        cell limiter factors R+- (counts limited counter-fluxes)
+//   alpha_bounds   local extrema, low-order provisional alpha, Q+-, P+-, and
+//                  the first iteration's R+- (face limiters all 1)
+//   alpha_R        cell limiter factors R+- of a later iteration (counts
+//                  limited counter-fluxes)
 //   alpha_lambda   face limiter = min over the two cells, never increasing
 //   alpha_update   limited flux, alpha^{n+1}, mass flux rhoPhi, closures
 // Every face is owned by the cell on its plus side (plus the last face of
