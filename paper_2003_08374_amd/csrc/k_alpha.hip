@@ -3,14 +3,15 @@
 // Sec. 2.3 summary (interface compression in clear regions, Eq. (vr_porous)
 // in porous regions) and the MULES flux limiter (Sec. 3.2).
 //
-// Four passes over the cells (plus two per extra limiter iteration):
+// Three passes over the cells (plus two per extra limiter iteration):
 //   alpha_face     antidiffusive face flux A = F*alpha_VL + G - F*alpha_upwind
 //   alpha_bounds   local extrema, low-order provisional alpha, Q+-, P+-, and
 //                  the first iteration's R+- (face limiters all 1)
 //   alpha_R        cell limiter factors R+- of a later iteration (counts
 //                  limited counter-fluxes)
 //   alpha_lambda   face limiter = min over the two cells, never increasing
-//   alpha_update   limited flux, alpha^{n+1}, mass flux rhoPhi, closures
+//   alpha_update   the last iteration's face limiter, limited flux,
+//                  alpha^{n+1}, mass flux rhoPhi, closures
 // Every face is owned by the cell on its plus side (plus the last face of
 // each row, owned by the last cell), so all writes are race-free.
 #include "dbs_internal.h"
@@ -220,11 +221,15 @@ __global__ void __launch_bounds__(NTHREADS) k_alpha_lambda(Segs SG, const double
   }
 }
 
+// The last limiter iteration's face factor is formed here for each of the
+// cell's faces (each interior face by both its cells, with the same
+// arithmetic) from R+- and the previous factors lam (first: none).
 __global__ void __launch_bounds__(NTHREADS) k_alpha_update(Segs SG, Phys Ph, const double *__restrict__ alpha, const double *__restrict__ F,
     const double *__restrict__ phi, const double *__restrict__ kinv, const double *__restrict__ A,
-    const double *__restrict__ lam, double *__restrict__ alpha_new, double *__restrict__ rhoPhi,
-    double *__restrict__ ml, double *__restrict__ mg, double *__restrict__ pc,
-    double *__restrict__ cf) {
+    const double *__restrict__ Rp, const double *__restrict__ Rm,
+    const double *__restrict__ lam, int first, double *__restrict__ alpha_new,
+    double *__restrict__ rhoPhi, double *__restrict__ ml, double *__restrict__ mg,
+    double *__restrict__ pc, double *__restrict__ cf) {
   FOR_CELLS(SG, G, P) {
   double out = 0.0;
   const double drho = Ph.rho_l - Ph.rho_g;
@@ -238,7 +243,14 @@ __global__ void __launch_bounds__(NTHREADS) k_alpha_update(Segs SG, Phys Ph, con
       }
       const bool bnd = on_boundary(G, P, a, s);
       const double FL = low_order_flux(G, alpha, F, P, a, s, f, bnd);
-      const double ap = bnd ? FL : fma(lam[f], A[f], FL);
+      // face factor: minus-side cell o, plus-side cell n (a domain face
+      // reads the cell itself and is not limited)
+      const int nb = bnd ? P.c : P.c + (s ? 1 : -1) * stride_of(G, a);
+      const int o = s ? P.c : nb, n = s ? nb : P.c;
+      const double Af = A[f];
+      const double l = Af >= 0.0 ? fmin(Rm[o], Rp[n]) : fmin(Rp[o], Rm[n]);
+      const double lf = first ? l : fmin(lam[f], l);
+      const double ap = bnd ? FL : fma(lf, Af, FL);
       out += s ? ap : -ap;
       if (s == 0 || bnd) rhoPhi[f] = drho * ap + Ph.rho_g * F[f];
     }
@@ -310,7 +322,8 @@ void alpha_stage(Handle *h) {
   DBS_LAUNCH(h, KC_ALPHA_BOUNDS, k_alpha_bounds, h->cgrid, blk, h->seg, (const double *)h->alpha,
              (const double *)h->F, (const double *)h->phi, (const double *)h->A, h->Qp, h->Qm,
              h->Pin, h->Pout, h->Rp, h->Rm);
-  for (int it = 0; it < h->ctl.mules_iter; it++) {
+  // the last iteration's face factors are formed inside the update
+  for (int it = 0; it < h->ctl.mules_iter - 1; it++) {
     int first = it == 0;
     // the first iteration's R+- come from the bounds pass
     if (!first)
@@ -320,10 +333,16 @@ void alpha_stage(Handle *h) {
     DBS_LAUNCH(h, KC_ALPHA_LIMIT, k_alpha_lambda, h->cgrid, blk, h->seg, (const double *)h->A,
                (const double *)h->Rp, (const double *)h->Rm, first, h->lam);
   }
+  // R+- of the last iteration (unless it is the first)
+  if (h->ctl.mules_iter > 1)
+    DBS_LAUNCH(h, KC_ALPHA_LIMIT, k_alpha_R, h->cgrid, blk, h->seg, (const double *)h->A,
+               (const double *)h->lam, 0, (const double *)h->Qp, (const double *)h->Qm,
+               (const double *)h->Pin, (const double *)h->Pout, h->Rp, h->Rm);
   // alpha^{n+1} goes to the spare buffer; the old one stays for rho^n
   DBS_LAUNCH(h, KC_ALPHA_UPDATE, k_alpha_update, h->cgrid, blk, h->seg, h->P,
              (const double *)h->alpha, (const double *)h->F, (const double *)h->phi,
-             (const double *)h->kinv, (const double *)h->A, (const double *)h->lam,
+             (const double *)h->kinv, (const double *)h->A, (const double *)h->Rp,
+             (const double *)h->Rm, (const double *)h->lam, h->ctl.mules_iter == 1 ? 1 : 0,
              h->alpha_old, h->rhoPhi, h->ml, h->mg, h->pc, h->cf);
   double *t = h->alpha;
   h->alpha = h->alpha_old;
