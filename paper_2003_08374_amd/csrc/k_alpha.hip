@@ -21,6 +21,7 @@ namespace dbs {
 struct AlphaArgs {
   const double *__restrict__ alpha, *__restrict__ F, *__restrict__ phi, *__restrict__ kinv;
   const double *__restrict__ prgh, *__restrict__ ml, *__restrict__ mg, *__restrict__ pc;
+  const double *__restrict__ gx, *__restrict__ gy, *__restrict__ gz;  // cell grad(alpha)
 };
 
 __device__ inline Cell shifted(const Geom &G, const Cell &P, int a, int d) {
@@ -32,19 +33,21 @@ __device__ inline Cell shifted(const Geom &G, const Cell &P, int a, int d) {
 }
 
 // Gauss gradient of alpha in cell P: face values are the mean with the
-// neighbour, or the boundary alpha; empty axes contribute nothing.
+// neighbour, or the boundary alpha; empty axes contribute nothing.  Both
+// neighbour loads of an axis are issued unconditionally (a domain side
+// reads the cell itself), the boundary value replaces the face value after.
 __device__ inline void grad_alpha(const Geom &G, const AlphaArgs &X, const Cell &P, double g[3]) {
-  double aP = X.alpha[P.c];
+  const double aP = X.alpha[P.c];
+#pragma unroll
   for (int a = 0; a < 3; a++) {
     if (G.n[a] == 1 && G.bck[2 * a] == BC_EMPTY) { g[a] = 0.0; continue; }
-    double fv[2];
-    for (int s = 0; s < 2; s++) {
-      if (on_boundary(G, P, a, s))
-        fv[s] = bnd_alpha(G, 2 * a + s, P.j, aP, X.F[face_of(G, P, a, s)]);
-      else
-        fv[s] = 0.5 * (aP + X.alpha[P.c + (s ? 1 : -1) * stride_of(G, a)]);
-    }
-    g[a] = (fv[1] - fv[0]) * G.ih[a];
+    const bool bm = on_boundary(G, P, a, 0), bp = on_boundary(G, P, a, 1);
+    const int st = stride_of(G, a);
+    const double am = X.alpha[bm ? P.c : P.c - st], ap = X.alpha[bp ? P.c : P.c + st];
+    double fv0 = 0.5 * (aP + am), fv1 = 0.5 * (aP + ap);
+    if (bm) fv0 = bnd_alpha(G, 2 * a, P.j, aP, X.F[face_of(G, P, a, 0)]);
+    if (bp) fv1 = bnd_alpha(G, 2 * a + 1, P.j, aP, X.F[face_of(G, P, a, 1)]);
+    g[a] = (fv1 - fv0) * G.ih[a];
   }
 }
 
@@ -79,9 +82,8 @@ __device__ inline double face_antidiffusive(const Geom &G, const Phys &Ph, const
   Cell O = shifted(G, N, a, bnd ? 0 : -1);
   if (ko == 0.0 && kn == 0.0) {
     // clear face: compression flux along +grad(alpha), face-local |v|
-    double go[3], gn[3];
-    grad_alpha(G, X, O, go);
-    grad_alpha(G, X, N, gn);
+    const double go[3] = {X.gx[O.c], X.gy[O.c], X.gz[O.c]};
+    const double gn[3] = {X.gx[N.c], X.gy[N.c], X.gz[N.c]};
     double gf[3], mag2 = 0.0;
     for (int b = 0; b < 3; b++) {
       gf[b] = 0.5 * (go[b] + gn[b]);
@@ -107,6 +109,20 @@ __device__ inline double face_antidiffusive(const Geom &G, const Phys &Ph, const
     Gr = agf * ul - af * ug;
   }
   return bnd ? 0.0 : Ff * avl + Gr - FL;
+}
+
+// grad(alpha) of every cell, read by the compression flux of clear faces
+__global__ void __launch_bounds__(NTHREADS) k_alpha_grad(Segs SG, AlphaArgs X,
+                                                         double *__restrict__ gx,
+                                                         double *__restrict__ gy,
+                                                         double *__restrict__ gz) {
+  FOR_CELLS(SG, G, P) {
+  double g[3];
+  grad_alpha(G, X, P, g);
+  gx[P.c] = g[0];
+  gy[P.c] = g[1];
+  gz[P.c] = g[2];
+  }
 }
 
 __global__ void __launch_bounds__(NTHREADS) k_alpha_face(Segs SG, Phys Ph, AlphaArgs X,
@@ -317,7 +333,10 @@ __global__ void __launch_bounds__(NTHREADS) k_init_flux(Segs SG, const double *_
 
 void alpha_stage(Handle *h) {
   dim3 blk(BX, BY);
-  AlphaArgs X{h->alpha, h->F, h->phi, h->kinv, h->prgh, h->ml, h->mg, h->pc};
+  // the cell gradients borrow Qp, Qm and Pin, which the bounds pass fills later
+  AlphaArgs X{h->alpha, h->F,  h->phi, h->kinv, h->prgh, h->ml,
+              h->mg,    h->pc, h->Qp,  h->Qm,   h->Pin};
+  DBS_LAUNCH(h, KC_ALPHA_FACE, k_alpha_grad, h->cgrid, blk, h->seg, X, h->Qp, h->Qm, h->Pin);
   DBS_LAUNCH(h, KC_ALPHA_FACE, k_alpha_face, h->cgrid, blk, h->seg, h->P, X, h->A);
   DBS_LAUNCH(h, KC_ALPHA_BOUNDS, k_alpha_bounds, h->cgrid, blk, h->seg, (const double *)h->alpha,
              (const double *)h->F, (const double *)h->phi, (const double *)h->A, h->Qp, h->Qm,
