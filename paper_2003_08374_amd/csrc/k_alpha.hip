@@ -3,7 +3,8 @@
 // Sec. 2.3 summary (interface compression in clear regions, Eq. (vr_porous)
 // in porous regions) and the MULES flux limiter (Sec. 3.2).
 //
-// Three passes over the cells (plus two per extra limiter iteration):
+// Four passes over the cells (plus two per extra limiter iteration):
+//   alpha_grad     cell gradient of alpha (for the compression flux)
 //   alpha_face     antidiffusive face flux A = F*alpha_VL + G - F*alpha_upwind
 //   alpha_bounds   local extrema, low-order provisional alpha, Q+-, P+-, and
 //                  the first iteration's R+- (face limiters all 1)
