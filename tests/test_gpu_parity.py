@@ -131,6 +131,28 @@ def test_random_3d_all_terms():
     compare_states(out, ref, tol_alpha=1e-12, label="random3d")
 
 
+CONTROLS = [
+    dict(mules_iter=1),
+    dict(mules_iter=2),
+    dict(mules_iter=4, n_corr=3),
+    dict(n_corr=1, mom_sweeps=1, transpose_visc=False),
+]
+
+
+@pytest.mark.parametrize("ctl", CONTROLS, ids=lambda c: ",".join(f"{k}={v}" for k, v in c.items()))
+def test_controls_match_oracle(ctl):
+    """Limiter iteration counts (the first and last limiter iterations are
+    fused into neighbouring passes), corrector count, predictor sweeps and
+    the transpose viscous term off, on the limiter-stress case and a random
+    3D case."""
+    case = W.layered_2d_stress(n=32).replace(**ctl)
+    out, ref, st, _ = _run_both(case, 4)
+    compare_states(out, ref, tol_alpha=1e-9, tol_l2=1e-9, label=f"stress {ctl}")
+    case = PC.random_3d((9, 7, 6), seed=4).replace(**ctl)
+    out, ref, st, _ = _run_both(case, 1)
+    compare_states(out, ref, label=f"random_3d {ctl}")
+
+
 def test_closed_box_conservation_on_gpu():
     nx, ny, h = 20, 20, 1e-3
     rng = np.random.default_rng(7)
