@@ -93,6 +93,28 @@ def measured_traffic(kernel, precision, n):
     return None, None
 
 
+def copy_bandwidth():
+    """HBM rate of torch's device copy (1 GiB read + 1 GiB written per copy,
+    10 copies timed with events on torch's stream): context for the roofline
+    fraction, which is taken against the published peak."""
+    import torch
+    a = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        b.copy_(a)
+    e1.record()
+    e1.synchronize()
+    sec = e0.elapsed_time(e1) * 1e-3 / 10
+    del a, b
+    torch.cuda.empty_cache()
+    return 2.0 * (1 << 27) * 8 / sec / 1e9
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -291,6 +313,8 @@ def main():
         if traffic:
             roof["traffic_rate_GBs"] = round(traffic / avg_s / 1e9, 1)
             roof["traffic_source"] = tsrc
+        # context: the rate of torch's own device copy on the same box
+        roof["torch_copy_GBs"] = round(copy_bandwidth(), 1)
 
     fp64 = None
     if not args.no_fp64 and args.precision == "mixed":
