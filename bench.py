@@ -201,8 +201,8 @@ def cpu_baseline(n=64, steps=2):
 
 def batch_leg(args):
     """The 512-sample batch (edges U{32..96}, no fracture, k seed 1000+s, phi
-    seed 2000+s): mixed precision in graph mode after autotuning, and plain
-    FP64 eagerly, both to a relative residual of 1e-8."""
+    seed 2000+s): mixed precision after autotuning, eagerly and in graph
+    mode, and plain FP64 eagerly, all to a relative residual of 1e-8."""
     from paper_2003_08374_amd import workloads as W
 
     log(f"generating {args.batch_samples} samples")
@@ -211,34 +211,42 @@ def batch_leg(args):
     cells = sum(c.ncells for c in cases)
     out = {"workload": f"batch{len(cases)}_edges32to96", "samples": len(cases), "cells": cells,
            "p_tol": args.p_tol}
-    rm = time_solver(cases, "mixed", args.steps, args.warmup, graph=True, tune=True)
-    out["mixed_graph_tuned"] = {"value": cells / (rm["sec"] / args.steps),
-                                "ms_per_step": rm["sec"] / args.steps * 1e3,
-                                "tuning": rm["tuning"],
-                                "p_iters_max_last": rm["stats"].get("p_iters_max")}
+    rm = time_solver(cases, "mixed", args.steps, args.warmup, tune=True)
+    out["mixed_tuned"] = {"value": cells / (rm["sec"] / args.steps),
+                          "ms_per_step": rm["sec"] / args.steps * 1e3,
+                          "tuning": rm["tuning"],
+                          "p_iters_max_last": rm["stats"].get("p_iters_max")}
+    rg = time_solver(cases, "mixed", args.steps, args.warmup, graph=True, tune=True)
+    out["mixed_graph_tuned"] = {"value": cells / (rg["sec"] / args.steps),
+                                "ms_per_step": rg["sec"] / args.steps * 1e3,
+                                "tuning": rg["tuning"],
+                                "p_iters_max_last": rg["stats"].get("p_iters_max")}
     r64 = time_solver(cases, "fp64", args.steps, args.warmup)
     out["fp64_eager"] = {"value": cells / (r64["sec"] / args.steps),
                          "ms_per_step": r64["sec"] / args.steps * 1e3,
                          "p_iters_max_last": r64["stats"].get("p_iters_max")}
-    out["speedup_mixed_batched_vs_fp64"] = (out["mixed_graph_tuned"]["value"] /
+    out["speedup_mixed_batched_vs_fp64"] = (max(out["mixed_tuned"]["value"],
+                                                out["mixed_graph_tuned"]["value"]) /
                                             out["fp64_eager"]["value"])
     return out
 
 
 def flume_leg(args):
     """The 2D wave flume (2048 x 512, 5 mm cells, dt 1e-3 s) batched over 16
-    seeded wave amplitudes, mixed precision in graph mode after autotuning,
-    p_tol 1e-8."""
+    seeded wave amplitudes, mixed precision after autotuning, eagerly (the
+    reported value) and in graph mode, p_tol 1e-8."""
     from paper_2003_08374_amd import workloads as W
 
     log("generating the flume batch")
     cases = [c.replace(p_maxit=500) for c in W.flume_batch(n=16, seed=7, p_tol=args.p_tol)]
     cells = sum(c.ncells for c in cases)
-    rm = time_solver(cases, "mixed", args.steps, args.warmup, graph=True, tune=True)
+    rm = time_solver(cases, "mixed", args.steps, args.warmup, tune=True)
+    rg = time_solver(cases, "mixed", args.steps, args.warmup, graph=True, tune=True)
     return {"workload": "wave_flume_2048x512_batch16", "samples": len(cases), "cells": cells,
             "p_tol": args.p_tol, "value": cells / (rm["sec"] / args.steps),
             "ms_per_step": rm["sec"] / args.steps * 1e3, "tuning": rm["tuning"],
-            "p_iters_max_last": rm["stats"].get("p_iters_max")}
+            "p_iters_max_last": rm["stats"].get("p_iters_max"),
+            "graph_ms_per_step": rg["sec"] / args.steps * 1e3}
 
 
 def main():
