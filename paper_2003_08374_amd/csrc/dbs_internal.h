@@ -131,7 +131,7 @@ struct Handle {
   double *r = nullptr, *z = nullptr, *pv = nullptr, *q = nullptr;
   double *pv2 = nullptr;  // CG directions alternate between pv and pv2
   float *rf = nullptr;     // FP32 residual (mixed precision)
-  float *zoldf = nullptr;  // previous preconditioned residual (flexible CG)
+  float *zoldf = nullptr;  // third FP32 z buffer (z rotation), or z_old with half sweeps
   float *zf2 = nullptr;    // second fine correction buffer (FP32 V-cycle)
   double *z2 = nullptr;    // second fine correction buffer (FP64 V-cycle)
   double *partials = nullptr;  // per-block partial sums

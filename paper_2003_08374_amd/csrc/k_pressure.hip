@@ -344,7 +344,7 @@ struct FinArgs {
   int closed_only;
   int *act, *want;
   double tol2;          // p_tol^2
-  int maxit, replace_every;
+  int maxit;
 };
 
 // one block per sample: scal[slot] = sum of the sample's partials (and slot2
@@ -395,12 +395,12 @@ __global__ void __launch_bounds__(FIN_T) k_finalize(FinArgs A, double *__restric
     case FIN_RR: {
       const double its = S[S_ITS] + 1.0;
       S[S_ITS] = its;
+      // the recursive residual is updated in FP64 in both forms (only z
+      // comes from the FP32 V-cycle); once it reports convergence, the true
+      // residual decides (and replaces it if it is not small)
       const bool small = S[S_RR] <= A.tol2 * S[S_NRM2];
-      const bool repl = A.replace_every > 0 && ((long long)its % A.replace_every) == 0;
-      // the true residual decides convergence; it also replaces the
-      // recursive one every replace_every iterations
-      A.want[s] = (small || repl) ? 1 : 0;
-      if (!small && !repl && its >= A.maxit) {
+      A.want[s] = small ? 1 : 0;
+      if (!small && its >= A.maxit) {
         A.act[s] = 0;
         S[S_NOCONV] = 1.0;
       }
@@ -1250,8 +1250,9 @@ template <> struct ZPair<double> {
 // and partials r.r, b.b.  MODE 2: the CG direction update fused in front of
 // MODE 0: p_new = z + beta p (p_new = z when first) is formed while the
 // planes are staged (ring cells included, from z and the old p, which no
-// block writes), written for the tile's own cells to a second buffer with
-// the copy z_old = z of flexible CG, and q = A p_new, p_new.q follow.
+// block writes), written for the tile's own cells to a second buffer (with
+// the copy z_old = z of flexible CG when zold is given), and q = A p_new,
+// p_new.q follow.
 // 64 x 8 tiles walk up to kz planes; the inputs are staged in LDS slots,
 // two planes in flight (one cell per thread).
 template <int MODE, typename Z = double>
@@ -2550,10 +2551,6 @@ static FinArgs fin_args(Handle *h, const Shape *S, int two, int slot, int slot2,
   A.want = h->want;
   A.tol2 = h->ctl.p_tol * h->ctl.p_tol;
   A.maxit = h->ctl.p_maxit;
-  // the recursive residual is updated in FP64 in both forms (only z comes
-  // from the FP32 V-cycle), so the true residual is formed only when the
-  // recursive one reports convergence
-  A.replace_every = 0;
   return A;
 }
 
