@@ -80,6 +80,12 @@
  *       above it alpha = 0 and U = 0; y is the face-centre height; all
  *       boundary values of a step are taken at its end time t^{n+1};
  *       outflowing wave faces carry the cell alpha.
+ *
+ * Pins (tests/test_oracle_pins.py) tie each function to what the paper and
+ * the mathematics fix.  Parity unpinned: the effect of the eps_pc clamp of
+ * R5 on the dynamics near dry cells, which only the GPU path and the
+ * invariants (bounds, conservation) check; the clamp itself is pinned at
+ * the closure level.
  */
 #include "dbs_oracle.h"
 

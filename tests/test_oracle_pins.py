@@ -161,6 +161,38 @@ def test_outlet_backflow_brings_the_boundary_saturation():
     np.testing.assert_array_equal(a[:-1], 1.0)
 
 
+def _two_cell_column(kinv_top, steps=1):
+    """Closed 1x2 column: porous bottom cell (phi 0.5, k^-1 1e11, alpha 0.3)
+    under a top cell (phi 0.9, k^-1 kinv_top, alpha 0.8), no capillarity."""
+    phi = np.array([0.5, 0.9]).reshape(1, 2, 1)
+    kinv = np.array([1e11, kinv_top]).reshape(1, 2, 1)
+    alpha = np.array([0.3, 0.8]).reshape(1, 2, 1)
+    c = PC.closed_box_2d(1, 2, 1e-3, W.fluids(W.WATER, W.AIR), phi=phi, kinv=kinv,
+                         alpha=alpha, dt=1e-3)
+    c = c.replace(kr={"model": "brooks_corey", "m": 2.0},
+                  pc={"model": "brooks_corey", "pc0": 0.0, "exp": 0.5})
+    out, _ = O.step(c, O.initial_state(c), steps)
+    return out["alpha"]
+
+
+def test_porous_clear_face_is_the_porous_limit():
+    """A face between a porous and a clear cell carries the porous relative
+    flux of Eq. (vr_porous) with the face permeability of a harmonic mean
+    (reading of the porous/clear interface): the clear cell is the limit
+    k^-1 -> 0 of a porous one, so the first step's saturations are continuous
+    in that limit, with a difference linear in k^-1 (an arithmetic mean of k
+    would diverge, a compression flux on the face would move nothing).
+    Gravity drives the water of the top cell down, and the phase volume is
+    kept."""
+    a0 = _two_cell_column(0.0)
+    d6 = np.abs(_two_cell_column(1e5) - a0).max()   # k^-1 = 1e-6 of the porous cell's
+    d9 = np.abs(_two_cell_column(1e2) - a0).max()   # 1e-9
+    assert d9 < 1e-10
+    assert d6 / d9 == pytest.approx(1e3, rel=0.05)
+    assert a0[0] > 0.3 + 1e-3 and a0[1] < 0.8 - 1e-3
+    assert float(a0 @ np.array([0.5, 0.9])) == pytest.approx(0.5 * 0.3 + 0.9 * 0.8, rel=1e-14)
+
+
 # ------------------------------------------------- Poiseuille (viscous + PISO)
 
 
