@@ -153,6 +153,16 @@ __device__ __forceinline__ bool cell_of_thread(const Geom &G, int lb, Cell &P) {
   Cell P;                                                          \
   if (cell_of_thread(G, cell_gb - (S).bp[cell_sg], P))
 
+// FOR_CELLS for a launch over all samples (only < 0) or over the blocks of
+// sample `only` alone, which start at block `base` of the shape
+#define FOR_CELLS_ONE(S, G, P, only, base)                                      \
+  const int cell_gb = (only) >= 0 ? (base) + (int)blockIdx.x                    \
+                                  : xcd_remap(blockIdx.x, gridDim.x);           \
+  const int cell_sg = (only) >= 0 ? (only) : find_seg((S).bp, (S).ns, cell_gb); \
+  const Geom &G = (S).g[cell_sg];                                               \
+  Cell P;                                                                       \
+  if (cell_of_thread(G, cell_gb - (S).bp[cell_sg], P))
+
 // face index of side s (0 = minus, 1 = plus) of cell P along axis a
 __device__ __forceinline__ int face_of(const Geom &G, const Cell &P, int a, int s) {
   int ii = P.i + (a == 0 ? s : 0), jj = P.j + (a == 1 ? s : 0), kk = P.k + (a == 2 ? s : 0);

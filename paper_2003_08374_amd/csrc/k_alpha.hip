@@ -291,9 +291,9 @@ __global__ void __launch_bounds__(NTHREADS) k_closures(Segs SG, Phys Ph,
                                                        double *__restrict__ ml,
                                                        double *__restrict__ mg,
                                                        double *__restrict__ pc,
-                                                       double *__restrict__ cf, int only) {
-  FOR_CELLS(SG, G, P) {
-  if (only >= 0 && cell_sg != only) return;
+                                                       double *__restrict__ cf, int only,
+                                                       int base) {
+  FOR_CELLS_ONE(SG, G, P, only, base) {
   double l, g, p;
   const double a = alpha[P.c];
   closures(Ph, a, l, g, p);
@@ -309,9 +309,9 @@ __global__ void __launch_bounds__(NTHREADS) k_closures(Segs SG, Phys Ph,
 // the cell velocity at outlets.
 // only >= 0: that sample alone
 __global__ void __launch_bounds__(NTHREADS) k_init_flux(Segs SG, const double *__restrict__ U,
-                                                        double *__restrict__ F, int only) {
-  FOR_CELLS(SG, G, P) {
-  if (only >= 0 && cell_sg != only) return;
+                                                        double *__restrict__ F, int only,
+                                                        int base) {
+  FOR_CELLS_ONE(SG, G, P, only, base) {
   for (int a = 0; a < 3; a++) {
     const double *Ua = U + (size_t)a * G.vs;
     for (int s = 0; s < 2; s++) {
@@ -369,15 +369,25 @@ void alpha_stage(Handle *h) {
   h->alpha_old = t;
 }
 
+// launch over every sample, or (only >= 0) over that sample's blocks alone
+static dim3 one_grid(const Handle *h, int only, int &base) {
+  base = only >= 0 ? h->cell.hbp[only] : 0;
+  return only >= 0 ? dim3((unsigned)(h->cell.hbp[only + 1] - h->cell.hbp[only])) : h->cgrid;
+}
+
 void update_closures(Handle *h, int only) {
   dim3 blk(BX, BY);
-  DBS_LAUNCH(h, KC_MISC, k_closures, h->cgrid, blk, h->seg, h->P, (const double *)h->alpha,
-             (const double *)h->kinv, h->ml, h->mg, h->pc, h->cf, only);
+  int base;
+  const dim3 g = one_grid(h, only, base);
+  DBS_LAUNCH(h, KC_MISC, k_closures, g, blk, h->seg, h->P, (const double *)h->alpha,
+             (const double *)h->kinv, h->ml, h->mg, h->pc, h->cf, only, base);
 }
 
 void init_flux(Handle *h, int only) {
   dim3 blk(BX, BY);
-  DBS_LAUNCH(h, KC_MISC, k_init_flux, h->cgrid, blk, h->seg, (const double *)h->U, h->F, only);
+  int base;
+  const dim3 g = one_grid(h, only, base);
+  DBS_LAUNCH(h, KC_MISC, k_init_flux, g, blk, h->seg, (const double *)h->U, h->F, only, base);
 }
 
 }  // namespace dbs
