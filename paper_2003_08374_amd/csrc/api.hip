@@ -22,7 +22,7 @@ namespace dbs {
 static const char *kNames[KC_COUNT] = {
     "alpha_face", "alpha_bounds", "alpha_limit", "alpha_update", "mom_assemble",
     "mom_offdiag", "phihbya",     "correct",     "spmv",         "axpy",
-    "dot",         "xpby",        "finalize",    "smooth_fine",  "restrict_fine",
+    "dot",         "finalize",    "smooth_fine",  "restrict_fine",
     "prolong_fine", "smooth_coarse", "restrict_coarse", "prolong_coarse", "coarse_solve",
     "build_coarse", "stats",      "misc",        "smooth_fine_zero", "residual",
     "smooth_fine_dot"};

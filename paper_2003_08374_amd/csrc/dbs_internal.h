@@ -20,7 +20,7 @@ namespace dbs {
 enum KClass {
   KC_ALPHA_FACE = 0, KC_ALPHA_BOUNDS, KC_ALPHA_LIMIT, KC_ALPHA_UPDATE,
   KC_MOM_ASSEMBLE, KC_MOM_OFFDIAG, KC_PHIHBYA, KC_CORRECT,
-  KC_SPMV, KC_AXPY, KC_DOT, KC_XPBY, KC_FINALIZE,
+  KC_SPMV, KC_AXPY, KC_DOT, KC_FINALIZE,
   KC_SMOOTH0, KC_RESTRICT0, KC_PROLONG0,
   KC_SMOOTHC, KC_RESTRICTC, KC_PROLONGC, KC_COARSE, KC_BUILD_COARSE,
   KC_STATS, KC_MISC, KC_SMOOTH0_ZERO, KC_RESIDUAL, KC_SMOOTH0_DOT, KC_COUNT
