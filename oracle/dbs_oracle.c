@@ -82,10 +82,11 @@
  *       outflowing wave faces carry the cell alpha.
  *
  * Pins (tests/test_oracle_pins.py) tie each function to what the paper and
- * the mathematics fix.  Parity unpinned: the effect of the eps_pc clamp of
- * R5 on the dynamics near dry cells, which only the GPU path and the
- * invariants (bounds, conservation) check; the clamp itself is pinned at
- * the closure level.
+ * the mathematics fix.  Parity unpinned: the values the eps_pc clamp of R5
+ * gives in dry porous cells, which only the GPU path checks; pinned are the
+ * clamp at the closure level, that it changes nothing while every porous
+ * cell is inside the range, and that dry cells keep a step finite and
+ * bounded.
  */
 #include "dbs_oracle.h"
 

@@ -193,6 +193,32 @@ def test_porous_clear_face_is_the_porous_limit():
     assert float(a0 @ np.array([0.5, 0.9])) == pytest.approx(0.5 * 0.3 + 0.9 * 0.8, rel=1e-14)
 
 
+def test_eps_pc_acts_only_near_dry_cells():
+    """The clamp of the normalised capillary saturation to [eps_pc, 1]
+    (App. A reading for dry regions, where p_c is unbounded) changes nothing
+    while every porous cell stays inside the range, and keeps a step with
+    dry porous cells finite and bounded, with a result that depends on
+    eps_pc there (p_c(eps_pc) grows as eps_pc shrinks)."""
+    c0 = PC.random_3d((9, 7, 6), seed=4)
+    a = np.random.default_rng(1).uniform(0.2, 0.8, c0.alpha.shape)
+
+    def run(alpha, eps):
+        c = c0.replace(alpha=alpha, pc=dict(c0.pc, eps=eps))
+        out, _ = O.step(c, O.initial_state(c), 2)
+        return out
+
+    o3, o6 = run(a, 1e-3), run(a, 1e-6)
+    for f in ("alpha", "U", "p_rgh"):
+        np.testing.assert_array_equal(o3[f], o6[f])
+    dry = a.copy()
+    dry.ravel()[::7] = 0.0
+    d3, d6 = run(dry, 1e-3), run(dry, 1e-6)
+    for o in (d3, d6):
+        assert np.isfinite(o["p_rgh"]).all() and np.isfinite(o["U"]).all()
+        assert o["alpha"].min() >= -1e-12 and o["alpha"].max() <= 1 + 1e-12
+    assert np.abs(d3["p_rgh"] - d6["p_rgh"]).max() > 1e-3 * np.abs(d3["p_rgh"]).max()
+
+
 # ------------------------------------------------- Poiseuille (viscous + PISO)
 
 
