@@ -388,7 +388,16 @@ __global__ void __launch_bounds__(FIN_T) k_finalize(FinArgs A, double *__restric
     case FIN_BETA:
     case FIN_BETA_FLEX: {
       const double num = A.op == FIN_BETA ? S[S_RZNEW] : S[S_RZNEW] - S[S_RZOLD];
-      S[S_BETA] = S[S_RZ] != 0.0 ? num / S[S_RZ] : 0.0;
+      double beta = S[S_RZ] != 0.0 ? num / S[S_RZ] : 0.0;
+      // Flexible CG restarts (beta = 0) when r.z_old is not small against
+      // r.z, Powell's test (1977) with its factor 0.2.  With r.z taken from
+      // the FP32 copy of r, alpha carries an FP32 rounding error, so r is
+      // orthogonal to the last direction only to that level; once the
+      // residual falls to it (a sample the V-cycle solves almost exactly,
+      // such as a single cell) r.z_old dominates, the Polak-Ribiere
+      // direction would cancel to noise and alpha = r.z / p.q blow up.
+      if (A.op == FIN_BETA_FLEX && !(fabs(S[S_RZOLD]) < 0.2 * S[S_RZNEW])) beta = 0.0;
+      S[S_BETA] = beta;
       S[S_RZ] = S[S_RZNEW];
       break;
     }

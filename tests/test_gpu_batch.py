@@ -59,6 +59,25 @@ def test_batch_samples_match_oracle():
         assert max(st["p_relres"]) <= 1e-13
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_tiny_and_thin_samples_match_oracle(precision):
+    """Edge sizes in one batch: a single cell (one multigrid level), 2^3 (a
+    one-cell coarse level in the bottom solver), one-cell-thin boxes in y and
+    in z (half sweeps on thin levels, scalar plane loads) and a 13^3 cube."""
+    dbs = _dbs()
+    shapes = [(1, 1, 1), (2, 2, 2), (3, 1, 5), (17, 9, 1), (13, 13, 13)]
+    cases = [W.fractured_3d(shape=sh, fractures=None, seed_k=300 + q, seed_phi=400 + q,
+                            steps=2).replace(p_tol=1e-13, name=f"edge_{q}")
+             for q, sh in enumerate(shapes)]
+    nsteps = 2
+    with dbs.BatchSolver(cases, precision=precision) as B:
+        B.step(nsteps)
+        outs = [B.state(i) for i in range(len(cases))]
+    for cs, out in zip(cases, outs):
+        ref, _ = O.step(cs.replace(p_tol=1e-14, p_maxit=200000), O.initial_state(cs), nsteps)
+        compare_states(out, ref, label=f"edge {precision}:{cs.name} {cs.shape}")
+
+
 def test_batch_equals_single_runs():
     """A sample's result does not depend on the rest of the batch."""
     dbs = _dbs()
