@@ -79,7 +79,20 @@
  *       v = A w sinh(k y)/sinh(k d) cos(w t) (so v = d eta/dt at y = d),
  *       above it alpha = 0 and U = 0; y is the face-centre height; all
  *       boundary values of a step are taken at its end time t^{n+1};
- *       outflowing wave faces carry the cell alpha.
+ *       outflowing wave faces carry the cell alpha;
+ *   R17 clear-fluid surface tension (CSF, Brackbill et al. 1992), taken with
+ *       the physical sign: F_c = phi^-1 sigma kappa grad(alpha), kappa =
+ *       div(n_lg) = -div(grad(alpha)/|grad(alpha)|) (curvature as defined
+ *       in Sec. 2.1, positive for a liquid drop).  The two printed forms
+ *       (Sec. 2.2 and the Sec. 2.3 summary) carry the opposite overall sign,
+ *       which would lower the pressure inside a drop; the Laplace jump pins
+ *       the sign taken.  Discretely: Gauss cell gradients (face values as in
+ *       the compression term), face gradient = mean of the two cells (the
+ *       cell's own on a domain face), n_f = grad_f/(|grad_f| + dN), kappa_P
+ *       = -(1/V) sum_f n_f.S_f; per cell s_P = sigma kappa_P / phi_P in clear
+ *       cells and 0 in porous ones (where F_c is the App. B form), and the
+ *       face force gains (s_P + s_N)/2 dn(alpha), alpha^{n+1} throughout.
+ *       The contact angle at porous walls (Sec. 2.3) is not included.
  *
  * Pins (tests/test_oracle_pins.py) tie each function to what the paper and
  * the mathematics fix.  Parity unpinned: the values the eps_pc clamp of R5
@@ -145,6 +158,7 @@ static int validate_case(const dbso_case *cs) {
   }
   for (int b = 0; b < 6; b++)
     if (cs->bc_kind[b] < DBSO_WALL || cs->bc_kind[b] > DBSO_WAVE) return -1;
+  if (!(cs->sigma >= 0.0) || isinf(cs->sigma)) return -1;
   for (int b = 2; b < 6; b++)
     if (cs->bc_kind[b] == DBSO_WAVE) return -1; /* wave inlets sit on x faces */
   for (int b = 0; b < 2; b++)
@@ -256,6 +270,7 @@ typedef struct {
   double cf;     /* f_l - alpha in porous cells, 0 in clear cells (R3) */
   double K;      /* Darcy drag coefficient mu k^-1 (R2) */
   double rho, mu;
+  double sk;     /* sigma kappa / phi in clear cells, 0 in porous cells (R17) */
 } props_t;
 
 static void cell_props(const dbso_case *cs, double a, double kinv, props_t *p) {
@@ -270,6 +285,7 @@ static void cell_props(const dbso_case *cs, double a, double kinv, props_t *p) {
   p->K = porous ? kinv / mt : 0.0;
   p->rho = a * cs->rho_l + (1.0 - a) * cs->rho_g;
   p->mu = a * cs->mu_l + (1.0 - a) * cs->mu_g;
+  p->sk = 0.0;
 }
 
 static const double PI = 3.14159265358979323846;
@@ -327,6 +343,46 @@ static double bnd_alpha(const mesh_t *m, const face_t *F, const double *alpha, d
 
 /* ---------------------------------------------------- 1. alpha transport */
 
+static double dot3(const double *a, const double *b) {
+  return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+}
+
+/* Gauss cell gradient of alpha (face values: mean inside, boundary value);
+   grad holds 3 entries per cell and is overwritten */
+static void gauss_grad(const mesh_t *m, const double *alpha, const double *F, double *grad) {
+  memset(grad, 0, sizeof(double) * 3 * (size_t)m->nc);
+  for (int f = 0; f < m->nf; f++) {
+    const face_t *Fc = &m->f[f];
+    if (Fc->kind == DBSO_EMPTY) continue;
+    double af = Fc->bnd < 0 ? 0.5 * (alpha[Fc->own] + alpha[Fc->nbr])
+                            : bnd_alpha(m, Fc, alpha, F[f]);
+    if (Fc->own >= 0) grad[Fc->own * 3 + Fc->axis] += af * Fc->area / m->V;
+    if (Fc->nbr >= 0) grad[Fc->nbr * 3 + Fc->axis] -= af * Fc->area / m->V;
+  }
+}
+
+/* kappa_P = -(1/V) sum over the cell's faces of n_f . S_f (outward), with
+   n_f the regularised unit face gradient of alpha (R17) */
+static void curvature(const mesh_t *m, const double *alpha, const double *F, double *kappa) {
+  double *grad = (double *)malloc(sizeof(double) * 3 * (size_t)m->nc);
+  gauss_grad(m, alpha, F, grad);
+  double dN = 1e-8 / cbrt(m->V);
+  for (int c = 0; c < m->nc; c++) kappa[c] = 0.0;
+  for (int f = 0; f < m->nf; f++) {
+    const face_t *Fc = &m->f[f];
+    if (Fc->kind == DBSO_EMPTY) continue;
+    double gf[3];
+    for (int d = 0; d < 3; d++) {
+      if (Fc->bnd < 0) gf[d] = 0.5 * (grad[Fc->own * 3 + d] + grad[Fc->nbr * 3 + d]);
+      else gf[d] = grad[(Fc->own >= 0 ? Fc->own : Fc->nbr) * 3 + d];
+    }
+    double nS = gf[Fc->axis] / (sqrt(dot3(gf, gf)) + dN) * Fc->area;
+    if (Fc->own >= 0) kappa[Fc->own] -= nS / m->V;  /* +axis is outward of own */
+    if (Fc->nbr >= 0) kappa[Fc->nbr] += nS / m->V;
+  }
+  free(grad);
+}
+
 static void alpha_stage(const mesh_t *m, const double *phi, const double *kinv,
                         const double *alpha, const double *F, const double *prgh,
                         double *alpha_new, double *alphaPhi, double *rhoPhi,
@@ -348,15 +404,7 @@ static void alpha_stage(const mesh_t *m, const double *phi, const double *kinv,
     cell_centre(m, c, x);
     p[c] = prgh[c] + pr[c].rho * (cs->g[0] * x[0] + cs->g[1] * x[1] + cs->g[2] * x[2]);
   }
-  /* Gauss cell gradient of alpha (face values: mean inside, boundary value) */
-  for (int f = 0; f < nf; f++) {
-    const face_t *Fc = &m->f[f];
-    if (Fc->kind == DBSO_EMPTY) continue;
-    double af = Fc->bnd < 0 ? 0.5 * (alpha[Fc->own] + alpha[Fc->nbr])
-                            : bnd_alpha(m, Fc, alpha, F[f]);
-    if (Fc->own >= 0) grad[Fc->own * 3 + Fc->axis] += af * Fc->area / V;
-    if (Fc->nbr >= 0) grad[Fc->nbr * 3 + Fc->axis] -= af * Fc->area / V;
-  }
+  gauss_grad(m, alpha, F, grad);
   double dN = 1e-8 / cbrt(V);
 
   /* face fluxes: low order, high order, relative flux, antidiffusive part */
@@ -504,9 +552,6 @@ typedef struct {
   double *Sh;        /* explicit source, 3 x nc (component-major) */
 } momeq_t;
 
-static double dot3(const double *a, const double *b) {
-  return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
-}
 
 /* face force q_f = [F_c - (g.x_f) dn(rho) - dn(p_rgh)] A_f along +axis on
    interior and outlet faces (R3, R12).  Fixed-flux faces (walls, inlets) are
@@ -568,6 +613,7 @@ static double face_body_force(const mesh_t *m, const props_t *pr, const double *
   double cff = 0.5 * (pr[o].cf + pr[n].cf), pcf = 0.5 * (pr[o].pc + pr[n].pc);
   double Fcap = cff * ((cs->rho_l - cs->rho_g) * cs->g[Fc->axis] + (pr[n].pc - pr[o].pc) / d) -
                 pcf * (alpha[n] - alpha[o]) / d;
+  if (cs->sigma != 0.0) Fcap += 0.5 * (pr[o].sk + pr[n].sk) * (alpha[n] - alpha[o]) / d;
   return Fcap - dot3(cs->g, Fc->xf) * (pr[n].rho - pr[o].rho) / d;
 }
 
@@ -855,6 +901,20 @@ int dbso_inlet_values(const dbso_case *cs, int b, double t, double *out) {
   return n;
 }
 
+int dbso_curvature(const dbso_case *cs, const double *alpha, const double *Fx,
+                   const double *Fy, const double *Fz, double *kappa) {
+  mesh_t m;
+  if (build_mesh(cs, &m)) { free_mesh(&m); return -1; }
+  double *F = (double *)malloc(sizeof(double) * m.nf);
+  memcpy(F, Fx, sizeof(double) * m.nfa[0]);
+  memcpy(F + m.nfa[0], Fy, sizeof(double) * m.nfa[1]);
+  memcpy(F + m.nfa[0] + m.nfa[1], Fz, sizeof(double) * m.nfa[2]);
+  curvature(&m, alpha, F, kappa);
+  free(F);
+  free_mesh(&m);
+  return 0;
+}
+
 int dbso_pressure_apply(const dbso_case *cs, const double *rAU, const double *x,
                         double *y) {
   mesh_t m;
@@ -894,6 +954,7 @@ int dbso_step(const dbso_case *cs, const double *phi, const double *kinv,
   double *U = (double *)malloc(sizeof(double) * 3 * nc);
   double *U2 = (double *)malloc(sizeof(double) * 3 * nc);
   double *an = (double *)malloc(sizeof(double) * nc);
+  double *kap = (double *)malloc(sizeof(double) * nc);
   double *aPhi = (double *)malloc(sizeof(double) * nf);
   double *rPhi = (double *)malloc(sizeof(double) * nf);
   double *q = (double *)malloc(sizeof(double) * nf);
@@ -925,8 +986,13 @@ int dbso_step(const dbso_case *cs, const double *phi, const double *kinv,
     /* 1. saturation */
     for (int c = 0; c < nc; c++) cell_props(cs, alpha[c], kinv[c], &po[c]);
     alpha_stage(&m, phi, kinv, alpha, F, p_rgh, an, aPhi, rPhi, tr);
-    /* 2. properties at alpha^{n+1} */
+    /* 2. properties at alpha^{n+1}, with the clear-fluid CSF coefficient */
     for (int c = 0; c < nc; c++) cell_props(cs, an[c], kinv[c], &pn[c]);
+    if (cs->sigma != 0.0) {
+      curvature(&m, an, F, kap);
+      for (int c = 0; c < nc; c++)
+        pn[c].sk = kinv[c] > 0.0 ? 0.0 : cs->sigma * kap[c] / phi[c];
+    }
     /* 3. momentum predictor */
     momentum_assemble(&m, phi, po, pn, an, U, rPhi, F, &eq);
     face_forces(&m, pn, an, p_rgh, q);
@@ -1045,7 +1111,7 @@ int dbso_step(const dbso_case *cs, const double *phi, const double *kinv,
       info->max_div = maxd(info->max_div, fabs(div));
     }
   }
-  free(F); free(U); free(U2); free(an); free(aPhi); free(rPhi); free(q); free(R);
+  free(F); free(U); free(U2); free(an); free(kap); free(aPhi); free(rPhi); free(q); free(R);
   free(B); free(rAU); free(HbyA); free(phiH); free(T); free(b); free(po); free(pn);
   free(eq.aP); free(eq.aON); free(eq.aNO); free(eq.Sh);
   free_mesh(&m);

@@ -55,6 +55,7 @@ typedef struct {
      depth d [m] measured from y = 0 */
   double bc_wave[6][3];
   double t0;                /* time at the start of the first step [s] */
+  double sigma;             /* interfacial tension [N/m] (clear-fluid CSF) */
 } dbso_case;
 
 typedef struct {
@@ -84,6 +85,12 @@ typedef struct {
    saturation (paper App. A). */
 void dbso_closures(const dbso_case *cs, double alpha, double *krl, double *krg,
                    double *pc, double *dpc);
+
+/* Interface curvature kappa = -div(grad(alpha)/|grad(alpha)|) of every cell
+   (Brackbill's CSF, Sec. 2.2) for the given alpha and face fluxes (the
+   fluxes pick the outlet backflow value of alpha).  Returns 0 or -1. */
+int dbso_curvature(const dbso_case *cs, const double *alpha, const double *Fx,
+                   const double *Fy, const double *Fz, double *kappa);
 
 /* Face fluxes F = (linear interpolate U) . S; boundary faces take the
    inlet velocity, zero at walls, the cell velocity at outlets. */

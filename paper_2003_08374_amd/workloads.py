@@ -84,6 +84,7 @@ class Case:
     precision: str = "fp64"
     steps: int = 1
     t0: float = 0.0
+    sigma: float = 0.0
 
     @property
     def ncells(self) -> int:
@@ -217,6 +218,45 @@ def fractured_3d(n=128, h=1e-4, dt=1e-5, seed_k=1, seed_phi=2, fractures="slab",
     return Case(name=nm, shape=shape, h=hh, fluids=fluids(WATER, OIL),
                 g=(0.0, -GRAVITY, 0.0), bc=bc, phi=phi, kinv=kinv, alpha=alpha, U=U,
                 p_rgh=prgh, dt=dt, steps=steps,
+                kr={"model": "brooks_corey", "m": 2.0},
+                pc={"model": "brooks_corey", "pc0": 1e3, "exp": 0.5})
+
+
+# ------------------------------------------------------------ clear-fluid drop
+
+
+def droplet(shape=(64, 64, 1), h=1e-4, radius_cells=16.0, width_cells=1.0, centre=None,
+            sigma=0.07, dt=1e-5, porous_rows=0, gravity=False, steps=5, name=None):
+    """A water drop in air inside a closed box (walls; z empty when nz = 1).
+
+    alpha = (1 - tanh((r - R) / w)) / 2 around ``centre`` (cell units, the
+    box centre by default), R = radius_cells h, w = width_cells h;
+    sigma = 0.07 N/m (water-air).  ``porous_rows`` > 0 puts a porous floor
+    of that many cell rows (phi 0.5, k 1e-12 m^2, Brooks-Corey models as the
+    2D layered case) under the drop; gravity -y when ``gravity``.
+    """
+    shape = tuple(shape)
+    nx, ny, nz = shape
+    hh = (h, h, h)
+    x, y, z = _cell_centres(shape, hh)
+    c = centre if centre is not None else (nx / 2, ny / 2, nz / 2)
+    r2 = (x - c[0] * h) ** 2 + (y - c[1] * h) ** 2
+    if nz > 1:
+        r2 = r2 + (z - c[2] * h) ** 2
+    alpha = 0.5 * (1.0 - np.tanh((np.sqrt(r2) - radius_cells * h) / (width_cells * h)))
+    phi = np.ones((nz, ny, nx))
+    kinv = np.zeros((nz, ny, nx))
+    if porous_rows > 0:
+        phi[:, :porous_rows, :] = 0.5
+        kinv[:, :porous_rows, :] = 1e12
+    U = np.zeros((3, nz, ny, nx))
+    prgh = _zeros(shape)
+    zb = [empty(), empty()] if nz == 1 else [wall(), wall()]
+    bc = [wall(), wall(), wall(), wall()] + zb
+    nm = name or f"droplet_{nx}x{ny}x{nz}"
+    return Case(name=nm, shape=shape, h=hh, fluids=fluids(WATER, AIR),
+                g=(0.0, -GRAVITY if gravity else 0.0, 0.0), bc=bc, phi=phi, kinv=kinv,
+                alpha=alpha, U=U, p_rgh=prgh, dt=dt, steps=steps, sigma=sigma,
                 kr={"model": "brooks_corey", "m": 2.0},
                 pc={"model": "brooks_corey", "pc0": 1e3, "exp": 0.5})
 
