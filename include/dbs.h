@@ -72,6 +72,13 @@ typedef struct {
   double pc_exp;        /* beta (Brooks-Corey) or m (Van Genuchten) */
   double a_pcirr, a_pcmax; /* saturation range of the p_c model */
   double eps_pc;        /* clamp of the normalised p_c saturation (>0) */
+  double sigma;         /* interfacial tension [N/m], >= 0.  In solid-free cells
+                           the continuum surface force of Sec. 2.2 (Brackbill's
+                           CSF) adds sigma kappa grad(alpha) / phi, kappa =
+                           div(n_lg) = -div(grad(alpha)/|grad(alpha)|), positive
+                           for a liquid drop; porous cells keep the App. B
+                           capillary force.  0 switches it off (no extra work).
+                           The contact angle at porous walls is not modelled. */
 } dbs_physics;
 
 typedef struct {

@@ -25,7 +25,7 @@ static const char *kNames[KC_COUNT] = {
     "dot",         "finalize",    "smooth_fine",  "restrict_fine",
     "prolong_fine", "smooth_coarse", "restrict_coarse", "prolong_coarse", "coarse_solve",
     "build_coarse", "stats",      "misc",        "smooth_fine_zero", "residual",
-    "smooth_fine_dot"};
+    "smooth_fine_dot", "curvature"};
 
 void prof_begin(Handle *h, int cls) {
   Timer &t = h->tm;
@@ -255,6 +255,7 @@ static int validate_shared(const dbs_physics *p, const dbs_controls *c, std::str
   }
   if (p->pc_model == DBS_VAN_GENUCHTEN && !(p->pc_exp > 0.0 && p->pc_exp < 1.0)) { msg = "VG m"; return DBS_EINVAL; }
   if (!(p->rho_l > 0.0 && p->rho_g > 0.0 && p->mu_l > 0.0 && p->mu_g > 0.0)) { msg = "fluid properties"; return DBS_EINVAL; }
+  if (!(p->sigma >= 0.0 && p->sigma < HUGE_VAL)) { msg = "sigma"; return DBS_EINVAL; }
   if (!(c->dt > 0.0) || c->n_corr < 1 || c->n_corr > 16 || c->mom_sweeps < 0 ||
       c->mules_iter < 1 || !(c->p_tol > 0.0) || c->p_maxit < 1 ||
       (c->precision != DBS_FP64 && c->precision != DBS_MIXED) || c->mg_pre < 0 || c->mg_post < 0) {
@@ -361,6 +362,7 @@ static Phys make_phys(const dbs_physics *phys) {
   P.a_pcirr = phys->a_pcirr;
   P.inv_span_pc = 1.0 / (phys->a_pcmax - phys->a_pcirr);
   P.eps_pc = phys->eps_pc;
+  P.sigma = phys->sigma;
   return P;
 }
 
@@ -473,6 +475,7 @@ static int create_impl(int n, const dbs_grid *grids, const dbs_physics *phys, co
   h->Pout = dmalloc(h, NC, rc); h->Rp = dmalloc(h, NC, rc); h->Rm = dmalloc(h, NC, rc);
   h->rAU = dmalloc(h, NC, rc); h->Sh = dmalloc(h, 3 * NC, rc); h->B = dmalloc(h, 3 * NC, rc);
   h->AN = dmalloc(h, 6 * NC, rc); h->FB = dmalloc(h, NF, rc);
+  if (h->P.sigma != 0.0) h->SK = dmalloc(h, NC, rc);
   h->HbyA = dmalloc(h, 3 * NC, rc); h->phiH = dmalloc(h, NF, rc); h->rhs = dmalloc(h, NC, rc);
   h->r = dmalloc(h, NC, rc); h->z = dmalloc(h, NC, rc); h->pv = dmalloc(h, NC, rc);
   h->q = dmalloc(h, NC, rc); h->pv2 = dmalloc(h, NC, rc);

@@ -25,6 +25,7 @@ struct Phys {
   double kr_m, inv_kr_m, s_lirr, inv_span_kr;
   int pc_model;
   double pc0, pc_exp, a_pcirr, inv_span_pc, eps_pc;
+  double sigma;  // interfacial tension of the clear-fluid CSF force (0: off)
 };
 
 // One sample (one mesh) of a batch.  Cell and face indices are absolute in

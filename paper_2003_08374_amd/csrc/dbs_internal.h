@@ -23,7 +23,7 @@ enum KClass {
   KC_SPMV, KC_AXPY, KC_DOT, KC_FINALIZE,
   KC_SMOOTH0, KC_RESTRICT0, KC_PROLONG0,
   KC_SMOOTHC, KC_RESTRICTC, KC_PROLONGC, KC_COARSE, KC_BUILD_COARSE,
-  KC_STATS, KC_MISC, KC_SMOOTH0_ZERO, KC_RESIDUAL, KC_SMOOTH0_DOT, KC_COUNT
+  KC_STATS, KC_MISC, KC_SMOOTH0_ZERO, KC_RESIDUAL, KC_SMOOTH0_DOT, KC_CURV, KC_COUNT
 };
 
 constexpr int FLAT_T = 256;               // threads of a vector-kernel block
@@ -125,6 +125,7 @@ struct Handle {
   double *rAU = nullptr, *Sh = nullptr, *B = nullptr, *HbyA = nullptr;  // Sh,B,HbyA 3 x NC
   double *AN = nullptr;  // momentum neighbour coefficients of the step, 6 x NC
   double *FB = nullptr;  // body force F_c - (g.x_f) dn(rho) of each face, for the step
+  double *SK = nullptr;  // sigma kappa / phi (clear cells), 0 (porous); only when sigma > 0
   double *phiH = nullptr;  // faces
   double *rhs = nullptr;
   // PCG vectors

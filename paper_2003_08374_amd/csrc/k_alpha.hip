@@ -284,6 +284,37 @@ __global__ void __launch_bounds__(NTHREADS) k_alpha_update(Segs SG, Phys Ph, con
   }
 }
 
+// Clear-fluid surface tension (Sec. 2.2, Brackbill's continuum surface
+// force): SK = sigma kappa / phi in clear cells, 0 in porous cells, with
+// kappa = div(n_lg) = -div(n_f), n_f = grad_f / (|grad_f| + dN) and grad_f
+// the mean of the two cells' Gauss gradients of alpha^{n+1} (the cell's own
+// on a domain face; empty axes carry no face).
+__global__ void __launch_bounds__(NTHREADS) k_curvature(Segs SG, Phys Ph,
+                                                        const double *__restrict__ gx,
+                                                        const double *__restrict__ gy,
+                                                        const double *__restrict__ gz,
+                                                        const double *__restrict__ phi,
+                                                        const double *__restrict__ kinv,
+                                                        double *__restrict__ SK) {
+  FOR_CELLS(SG, G, P) {
+  const double gP[3] = {gx[P.c], gy[P.c], gz[P.c]};
+  double div = 0.0;
+#pragma unroll
+  for (int a = 0; a < 3; a++) {
+    if (G.n[a] == 1 && G.bck[2 * a] == BC_EMPTY) continue;
+    const int st = stride_of(G, a);
+    const int cm = on_boundary(G, P, a, 0) ? P.c : P.c - st;
+    const int cp = on_boundary(G, P, a, 1) ? P.c : P.c + st;
+    const double fm[3] = {0.5 * (gP[0] + gx[cm]), 0.5 * (gP[1] + gy[cm]), 0.5 * (gP[2] + gz[cm])};
+    const double fp[3] = {0.5 * (gP[0] + gx[cp]), 0.5 * (gP[1] + gy[cp]), 0.5 * (gP[2] + gz[cp])};
+    const double nm = fm[a] / (sqrt(fm[0] * fm[0] + fm[1] * fm[1] + fm[2] * fm[2]) + G.dN);
+    const double np = fp[a] / (sqrt(fp[0] * fp[0] + fp[1] * fp[1] + fp[2] * fp[2]) + G.dN);
+    div += (np - nm) * G.ih[a];
+  }
+  SK[P.c] = kinv[P.c] > 0.0 ? 0.0 : Ph.sigma * -div / phi[P.c];
+  }
+}
+
 // only >= 0: that sample alone
 __global__ void __launch_bounds__(NTHREADS) k_closures(Segs SG, Phys Ph,
                                                        const double *__restrict__ alpha,
@@ -367,6 +398,16 @@ void alpha_stage(Handle *h) {
   double *t = h->alpha;
   h->alpha = h->alpha_old;
   h->alpha_old = t;
+  if (h->SK) {
+    // surface tension coefficient from alpha^{n+1}; the gradients borrow
+    // Qp, Qm and Pin again (the limiter is done with them)
+    AlphaArgs Xn = X;
+    Xn.alpha = h->alpha;
+    DBS_LAUNCH(h, KC_CURV, k_alpha_grad, h->cgrid, blk, h->seg, Xn, h->Qp, h->Qm, h->Pin);
+    DBS_LAUNCH(h, KC_CURV, k_curvature, h->cgrid, blk, h->seg, h->P, (const double *)h->Qp,
+               (const double *)h->Qm, (const double *)h->Pin, (const double *)h->phi,
+               (const double *)h->kinv, h->SK);
+  }
 }
 
 // launch over every sample, or (only >= 0) over that sample's blocks alone

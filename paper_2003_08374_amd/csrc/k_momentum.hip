@@ -30,6 +30,7 @@ struct MomArgs {
   const double *__restrict__ prgh;
   const double *__restrict__ rAU;
   const double *__restrict__ FB;  // face_body of each interior face (k_face_body)
+  const double *__restrict__ sk;  // sigma kappa / phi (clear cells), NULL when sigma = 0
 };
 
 __device__ __forceinline__ bool empty_axis(const Geom &G, int a) {
@@ -52,8 +53,10 @@ __device__ inline double face_body(const Geom &G, const Phys &Ph, const MomArgs 
   const double cf = 0.5 * (cap_coef(M, own) + cap_coef(M, nbr));
   const double pco = M.pc[own], pcn = M.pc[nbr];
   const double pcf = 0.5 * (pco + pcn);
-  const double Fcap =
+  double Fcap =
       cf * ((Ph.rho_l - Ph.rho_g) * Ph.g[a] + (pcn - pco) * ih) - pcf * (an - ao) * ih;
+  // clear-fluid CSF force: the face mean of sigma kappa / phi times dn(alpha)
+  if (M.sk) Fcap += 0.5 * (M.sk[own] + M.sk[nbr]) * (an - ao) * ih;
   return Fcap - gxf * (rho_of(Ph, an) - rho_of(Ph, ao)) * ih;
 }
 
@@ -388,7 +391,8 @@ __global__ void __launch_bounds__(NTHREADS) k_correct(Segs SG, Phys Ph, MomArgs 
 
 static MomArgs mom_args(Handle *h) {
   return MomArgs{h->alpha, h->alpha_old, h->rhoPhi, h->phi,  h->kinv, h->ml,
-                 h->mg,    h->pc,        h->cf,     h->prgh, h->rAU,  h->FB};
+                 h->mg,    h->pc,        h->cf,     h->prgh, h->rAU,  h->FB,
+                 h->SK};
 }
 
 // FB = face_body on every interior face (each cell its minus faces), zero

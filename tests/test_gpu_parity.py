@@ -186,12 +186,62 @@ def test_gravity_drainage_plateau_on_gpu():
     assert abs(np.median(a[-40:-5]) - 0.467) < 0.01
 
 
+# --------------------------------------------- clear-fluid surface tension
+
+CSF_DROPS = [
+    # 2D drop resting on a porous floor under gravity: clear, porous and
+    # mixed faces all carry the interface
+    dict(shape=(64, 64, 1), radius_cells=12, width_cells=1.5, centre=(32, 26, 0),
+         porous_rows=16, gravity=True),
+    # 3D drop on a porous floor, odd size (ragged tiles)
+    dict(shape=(23, 24, 21), radius_cells=6, width_cells=1.5, centre=(11.5, 12, 10.5),
+         porous_rows=6, gravity=True),
+    # static 2D drop, no gravity, closed box
+    dict(shape=(48, 48, 1), radius_cells=12, width_cells=1.5),
+]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("kw", CSF_DROPS, ids=["drop2d_porous_floor", "drop3d_porous_floor",
+                                               "drop2d_static"])
+def test_csf_drops_match_oracle(kw, precision):
+    """Clear-fluid CSF surface tension: drops against the oracle over 10
+    steps, in FP64 and mixed precision.  The closed boxes' pressure solves
+    are run to 1e-12: the balanced capillary terms leave the GPU residual
+    b - A x a rounding floor near 1e-13."""
+    case = W.droplet(**kw)
+    out, ref, st, _ = _run_both(case, 10, gpu_tol=1e-12, precision=precision)
+    compare_states(out, ref, label=f"csf {case.name} {precision}")
+    assert st["alpha_min"] >= -1e-12 and st["alpha_max"] <= 1 + 1e-12
+
+
+def test_csf_batch_of_drops_matches_oracle():
+    """Drops of uneven sizes in one batch (one launch per stage, shared
+    physics), each against its own oracle run."""
+    dbs = _dbs()
+    cases = [W.droplet(shape=(40, 36, 1), radius_cells=9, width_cells=1.5, porous_rows=8,
+                       gravity=True, name="b0"),
+             W.droplet(shape=(17, 19, 15), radius_cells=5, width_cells=1.5, gravity=True,
+                       name="b1"),
+             W.droplet(shape=(30, 30, 1), radius_cells=7, width_cells=1.0, gravity=True,
+                       name="b2")]
+    with dbs.BatchSolver([c.replace(p_tol=1e-12) for c in cases]) as B:
+        B.step(5)
+        outs = [B.state(i) for i in range(len(cases))]
+    for cs, out in zip(cases, outs):
+        ref, _ = O.step(cs.replace(p_tol=1e-14, p_maxit=200000), O.initial_state(cs), 5)
+        compare_states(out, ref, label=f"csf batch {cs.name}")
+
+
 def test_error_paths():
     dbs = _dbs()
     case = W.layered_2d(n=16)
     bad = case.replace(phi=np.zeros_like(case.phi))
     with pytest.raises(dbs.DBSError) as e:
         dbs.Solver(bad)
+    assert e.value.code == dbs.EINVAL
+    with pytest.raises(dbs.DBSError) as e:
+        dbs.Solver(case.replace(sigma=-0.07))
     assert e.value.code == dbs.EINVAL
     with dbs.Solver(case.replace(p_maxit=1, p_tol=1e-15)) as s:
         assert s.step(2, check=False) == dbs.ENOCONV
