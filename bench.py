@@ -65,6 +65,10 @@ def alg_bytes_per_cell(cls: str, rsize: int, fused: bool = False) -> float:
         "axpy": 48.0 + (4.0 if s == 4 else 0.0),
         # r (FP64) and z read, and z_old in flexible CG with half sweeps
         "dot": 8.0 + s + (s if s == 4 else 0.0),
+        # clear-fluid CSF, both launches of a step: Gauss gradient of alpha
+        # (alpha read, 3 components written) and curvature (gradients, phi,
+        # k^-1 read, sigma kappa / phi written)
+        "curvature": 32.0 + 48.0,
     }.get(cls, 0.0)
 
 
@@ -249,6 +253,25 @@ def flume_leg(args):
             "graph_ms_per_step": rg["sec"] / args.steps * 1e3}
 
 
+def csf_leg(args, case):
+    """The headline 256^3 workload with clear-fluid CSF surface tension on
+    (sigma = 0.03 N/m, water-oil), mixed precision, eagerly; the curvature
+    kernels are timed with HIP events over the timed steps."""
+    cs = case.replace(sigma=0.03)
+    r = time_solver(cs, "mixed", args.steps, args.warmup, prof_class="curvature")
+    cells = cs.ncells
+    launches, kms = r["ktimes"].get("curvature", (0, 0.0))
+    ms_k = kms / args.steps
+    return {"workload": case.name + "_csf", "sigma": cs.sigma,
+            "value": cells / (r["sec"] / args.steps),
+            "ms_per_step": r["sec"] / args.steps * 1e3,
+            "p_iters_last": r["p_iters"][-1],
+            "curvature": {"ms_per_step": round(ms_k, 4), "launches_per_step": launches / args.steps,
+                          "alg_bytes_per_cell": alg_bytes_per_cell("curvature", 4),
+                          "achieved_GBs": round(alg_bytes_per_cell("curvature", 4) * cells /
+                                                (ms_k * 1e-3) / 1e9, 1) if ms_k > 0 else None}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -263,6 +286,7 @@ def main():
     ap.add_argument("--no-graph", action="store_true", help="skip the graph-mode leg")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched leg")
     ap.add_argument("--no-flume", action="store_true", help="skip the wave-flume batch leg")
+    ap.add_argument("--no-csf", action="store_true", help="skip the surface-tension leg")
     ap.add_argument("--batch-samples", type=int, default=512)
     ap.add_argument("--coarse-sweeps", type=int, default=3)
     ap.add_argument("--fused", type=int, default=1,
@@ -338,6 +362,7 @@ def main():
                  "p_iters_last": rg["p_iters"][-1]}
     batched = None if args.no_batch else batch_leg(args)
     flume = None if args.no_flume else flume_leg(args)
+    csf = None if args.no_csf else csf_leg(args, case)
     cpu = None if args.no_cpu else cpu_baseline()
 
     line = {
@@ -363,6 +388,7 @@ def main():
         "graph_mode": graph,
         "batched": batched,
         "flume_batch": flume,
+        "csf": csf,
     }
     if main_run["all"]:
         line["kernel_ms_one_step"] = {k: round(v[1], 3) for k, v in sorted(
