@@ -43,7 +43,7 @@ namespace dbs {
 
 enum {
   S_RZ = 0, S_PQ, S_RR, S_ALPHA, S_BETA, S_RZNEW, S_RZOLD, S_BB, S_SUM, S_NRM2, S_ITS,
-  S_NOCONV, S_RRFIN
+  S_NOCONV, S_RRFIN, S_RESTART
 };
 
 constexpr int KZ = 8;               // planes per thread column (coarse levels)
@@ -397,6 +397,11 @@ __global__ void __launch_bounds__(FIN_T) k_finalize(FinArgs A, double *__restric
       // such as a single cell) r.z_old dominates, the Polak-Ribiere
       // direction would cancel to noise and alpha = r.z / p.q blow up.
       if (A.op == FIN_BETA_FLEX && !(fabs(S[S_RZOLD]) < 0.2 * S[S_RZNEW])) beta = 0.0;
+      // after a residual replacement the new r is not orthogonal to the old
+      // direction: restart, so that alpha = r.z / p.q is the exact line
+      // minimum along p = z and the error cannot grow
+      if (S[S_RESTART] != 0.0) beta = 0.0;
+      S[S_RESTART] = 0.0;
       S[S_BETA] = beta;
       S[S_RZ] = S[S_RZNEW];
       break;
@@ -421,6 +426,8 @@ __global__ void __launch_bounds__(FIN_T) k_finalize(FinArgs A, double *__restric
       } else if (S[S_ITS] >= A.maxit) {
         A.act[s] = 0;
         S[S_NOCONV] = 1.0;
+      } else {
+        S[S_RESTART] = 1.0;  // the true residual replaced the recursive one
       }
       A.want[s] = 0;
       break;
@@ -430,6 +437,7 @@ __global__ void __launch_bounds__(FIN_T) k_finalize(FinArgs A, double *__restric
       S[S_NRM2] = n2;
       S[S_ITS] = 0.0;
       S[S_NOCONV] = 0.0;
+      S[S_RESTART] = 0.0;
       A.act[s] = (n2 > 0.0 && S[S_RR] > A.tol2 * n2) ? 1 : 0;
       A.want[s] = 0;
       break;
@@ -1025,6 +1033,25 @@ __device__ __forceinline__ void coef7(const Op<R> &L, int i, int j, int k, R rc,
   D = T[0] + T[1] + T[2] + T[3] + T[4] + T[5] + rc * db;
 }
 
+// The FP64 operator row in difference form: (A x)_P = sum_f T_f (x_P - x_N)
+// + Dirichlet part x_P.  Same value as D x_P - sum_f T_f x_N, but the
+// rounding error scales with the differences instead of |x|, so the
+// attainable residual of a pressure field far from zero mean (closed boxes,
+// large hydrostatic levels) does not stall above the oracle's.
+__device__ __forceinline__ double row_diff(const Op<double> &L, int i, int j, int k, double rc,
+                                           double rxm, double rxp, double rym, double ryp,
+                                           double rzm, double rzp, double pc, double pxm,
+                                           double pxp, double pym, double pyp, double pzm,
+                                           double pzp) {
+  double T[6], D;
+  coef7(L, i, j, k, rc, rxm, rxp, rym, ryp, rzm, rzp, T, D);
+  const double db = (i == 0 ? L.ob[0] : 0.0) + (i + 1 == L.n0 ? L.ob[1] : 0.0) +
+                    (j == 0 ? L.ob[2] : 0.0) + (j + 1 == L.n1 ? L.ob[3] : 0.0) +
+                    (k == 0 ? L.ob[4] : 0.0) + (k + 1 == L.n2 ? L.ob[5] : 0.0);
+  return T[0] * (pc - pxm) + T[1] * (pc - pxp) + T[2] * (pc - pym) + T[3] * (pc - pyp) +
+         T[4] * (pc - pzm) + T[5] * (pc - pzp) + rc * db * pc;
+}
+
 // The same row when the neighbour values outside the mesh are zero (as in
 // the LDS planes): T = (rc + rn) hc needs no mask, since its product with a
 // zero iterate vanishes, and D removes the spurious rc hc of each face to
@@ -1397,13 +1424,10 @@ __global__ void __launch_bounds__(NT2) k_stencil25(OpB<double> LB, SH S,
                    *Pp = sp + slot_of<NS>(k + 1) * NX;
       const double *Rm = sr + slot_of<NS>(k - 1) * NX, *Rc = sr + slot_of<NS>(k) * NX,
                    *Rp = sr + slot_of<NS>(k + 1) * NX;
-      double T[6], D;
-      coef7(L, i, j, k, Rc[c2], Rc[c2 - 1], Rc[c2 + 1], Rc[c2 - FXR], Rc[c2 + FXR], Rm[c2],
-            Rp[c2], T, D);
       const double pc = Pc[c2];
-      const double off = T[0] * Pc[c2 - 1] + T[1] * Pc[c2 + 1] + T[2] * Pc[c2 - FXR] +
-                         T[3] * Pc[c2 + FXR] + T[4] * Pm[c2] + T[5] * Pp[c2];
-      const double y = D * pc - off;
+      const double y = row_diff(L, i, j, k, Rc[c2], Rc[c2 - 1], Rc[c2 + 1], Rc[c2 - FXR],
+                                Rc[c2 + FXR], Rm[c2], Rp[c2], pc, Pc[c2 - 1], Pc[c2 + 1],
+                                Pc[c2 - FXR], Pc[c2 + FXR], Pm[c2], Pp[c2]);
       const int c = i + n0 * (j + n1 * k);
       if (MODE != 1) {
         out[c] = y;

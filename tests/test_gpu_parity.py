@@ -207,8 +207,8 @@ CSF_DROPS = [
 def test_csf_drops_match_oracle(kw, precision):
     """Clear-fluid CSF surface tension: drops against the oracle over 10
     steps, in FP64 and mixed precision.  The closed boxes' pressure solves
-    are run to 1e-12: the balanced capillary terms leave the GPU residual
-    b - A x a rounding floor near 1e-13."""
+    are run to 1e-12: the static drop's GPU residual b - A x has a rounding
+    floor near 1.5e-13."""
     case = W.droplet(**kw)
     out, ref, st, _ = _run_both(case, 10, gpu_tol=1e-12, precision=precision)
     compare_states(out, ref, label=f"csf {case.name} {precision}")
@@ -231,6 +231,21 @@ def test_csf_batch_of_drops_matches_oracle():
     for cs, out in zip(cases, outs):
         ref, _ = O.step(cs.replace(p_tol=1e-14, p_maxit=200000), O.initial_state(cs), 5)
         compare_states(out, ref, label=f"csf batch {cs.name}")
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_pcg_below_its_rounding_floor_stalls_without_diverging(precision):
+    """Asked for a residual below what rounding allows (a static drop in a
+    closed box at 1e-13), PCG restarts after each residual replacement: the
+    true residual stays at its floor and the solve reports non-convergence
+    instead of growing (it once reached a relative residual above 1)."""
+    dbs = _dbs()
+    case = W.droplet(**CSF_DROPS[2]).replace(p_tol=1e-13, p_maxit=300)
+    with dbs.Solver(case, precision=precision) as s:
+        for _ in range(2):
+            rc = s.step(1, check=False)
+            assert rc in (0, dbs.ENOCONV)
+            assert max(s.stats()["p_relres"]) < 1e-12
 
 
 def test_error_paths():
