@@ -92,7 +92,18 @@
  *       = -(1/V) sum_f n_f.S_f; per cell s_P = sigma kappa_P / phi_P in clear
  *       cells and 0 in porous ones (where F_c is the App. B form), and the
  *       face force gains (s_P + s_N)/2 dn(alpha), alpha^{n+1} throughout.
- *       The contact angle at porous walls (Sec. 2.3) is not included.
+ *   R18 penalized contact angle (Sec. 2.3, locally modified normal): on a
+ *       face between a clear and a porous cell the wall normal n_w is the
+ *       face axis pointing from the porous into the clear cell, and the
+ *       interface normal n_lg = -grad(alpha)/|grad(alpha)| is replaced by
+ *       cos(theta) n_w + sin(theta) t_w, t_w the unit wall tangent in the
+ *       plane of n_w and the current normal.  On a Cartesian face only the
+ *       normal component enters the divergence, so that face contributes
+ *       n.S = -cos(theta) (n_w . e_axis) |n_f| A to the curvature of grad(alpha)
+ *       normals, |n_f| = |grad_f|/(|grad_f| + dN) (no interface, no term).
+ *       theta is measured through the liquid (alpha = 1) phase; the wall
+ *       being the face between the two cells, the same angle holds at every
+ *       clear/porous face; 0 means not imposed.
  *
  * Pins (tests/test_oracle_pins.py) tie each function to what the paper and
  * the mathematics fix.  Parity unpinned: the values the eps_pc clamp of R5
@@ -159,6 +170,7 @@ static int validate_case(const dbso_case *cs) {
   for (int b = 0; b < 6; b++)
     if (cs->bc_kind[b] < DBSO_WALL || cs->bc_kind[b] > DBSO_WAVE) return -1;
   if (!(cs->sigma >= 0.0) || isinf(cs->sigma)) return -1;
+  if (!(cs->contact_angle >= 0.0 && cs->contact_angle < 3.14159265358979323846)) return -1;
   for (int b = 2; b < 6; b++)
     if (cs->bc_kind[b] == DBSO_WAVE) return -1; /* wave inlets sit on x faces */
   for (int b = 0; b < 2; b++)
@@ -362,8 +374,11 @@ static void gauss_grad(const mesh_t *m, const double *alpha, const double *F, do
 }
 
 /* kappa_P = -(1/V) sum over the cell's faces of n_f . S_f (outward), with
-   n_f the regularised unit face gradient of alpha (R17) */
-static void curvature(const mesh_t *m, const double *alpha, const double *F, double *kappa) {
+   n_f the regularised unit face gradient of alpha (R17), penalized on
+   clear/porous faces when a contact angle is imposed (R18) */
+static void curvature(const mesh_t *m, const double *alpha, const double *kinv,
+                      const double *F, double *kappa) {
+  const double th = m->cs->contact_angle;
   double *grad = (double *)malloc(sizeof(double) * 3 * (size_t)m->nc);
   gauss_grad(m, alpha, F, grad);
   double dN = 1e-8 / cbrt(m->V);
@@ -376,7 +391,13 @@ static void curvature(const mesh_t *m, const double *alpha, const double *F, dou
       if (Fc->bnd < 0) gf[d] = 0.5 * (grad[Fc->own * 3 + d] + grad[Fc->nbr * 3 + d]);
       else gf[d] = grad[(Fc->own >= 0 ? Fc->own : Fc->nbr) * 3 + d];
     }
-    double nS = gf[Fc->axis] / (sqrt(dot3(gf, gf)) + dN) * Fc->area;
+    double mag = sqrt(dot3(gf, gf));
+    double nS = gf[Fc->axis] / (mag + dN) * Fc->area;
+    if (th > 0.0 && kinv && Fc->bnd < 0 && (kinv[Fc->own] > 0.0) != (kinv[Fc->nbr] > 0.0)) {
+      /* n_w . e_axis = +1 when the porous cell is on the minus side */
+      double nw = kinv[Fc->own] > 0.0 ? 1.0 : -1.0;
+      nS = -cos(th) * nw * (mag / (mag + dN)) * Fc->area;
+    }
     if (Fc->own >= 0) kappa[Fc->own] -= nS / m->V;  /* +axis is outward of own */
     if (Fc->nbr >= 0) kappa[Fc->nbr] += nS / m->V;
   }
@@ -901,15 +922,15 @@ int dbso_inlet_values(const dbso_case *cs, int b, double t, double *out) {
   return n;
 }
 
-int dbso_curvature(const dbso_case *cs, const double *alpha, const double *Fx,
-                   const double *Fy, const double *Fz, double *kappa) {
+int dbso_curvature(const dbso_case *cs, const double *alpha, const double *kinv,
+                   const double *Fx, const double *Fy, const double *Fz, double *kappa) {
   mesh_t m;
   if (build_mesh(cs, &m)) { free_mesh(&m); return -1; }
   double *F = (double *)malloc(sizeof(double) * m.nf);
   memcpy(F, Fx, sizeof(double) * m.nfa[0]);
   memcpy(F + m.nfa[0], Fy, sizeof(double) * m.nfa[1]);
   memcpy(F + m.nfa[0] + m.nfa[1], Fz, sizeof(double) * m.nfa[2]);
-  curvature(&m, alpha, F, kappa);
+  curvature(&m, alpha, kinv, F, kappa);
   free(F);
   free_mesh(&m);
   return 0;
@@ -989,7 +1010,7 @@ int dbso_step(const dbso_case *cs, const double *phi, const double *kinv,
     /* 2. properties at alpha^{n+1}, with the clear-fluid CSF coefficient */
     for (int c = 0; c < nc; c++) cell_props(cs, an[c], kinv[c], &pn[c]);
     if (cs->sigma != 0.0) {
-      curvature(&m, an, F, kap);
+      curvature(&m, an, kinv, F, kap);
       for (int c = 0; c < nc; c++)
         pn[c].sk = kinv[c] > 0.0 ? 0.0 : cs->sigma * kap[c] / phi[c];
     }

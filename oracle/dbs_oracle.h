@@ -56,6 +56,7 @@ typedef struct {
   double bc_wave[6][3];
   double t0;                /* time at the start of the first step [s] */
   double sigma;             /* interfacial tension [N/m] (clear-fluid CSF) */
+  double contact_angle;     /* at clear/porous faces [rad], 0 = not imposed */
 } dbso_case;
 
 typedef struct {
@@ -88,9 +89,11 @@ void dbso_closures(const dbso_case *cs, double alpha, double *krl, double *krg,
 
 /* Interface curvature kappa = -div(grad(alpha)/|grad(alpha)|) of every cell
    (Brackbill's CSF, Sec. 2.2) for the given alpha and face fluxes (the
-   fluxes pick the outlet backflow value of alpha).  Returns 0 or -1. */
-int dbso_curvature(const dbso_case *cs, const double *alpha, const double *Fx,
-                   const double *Fy, const double *Fz, double *kappa);
+   fluxes pick the outlet backflow value of alpha); with a contact angle,
+   faces between clear and porous cells (kinv > 0; kinv may be NULL: all
+   clear) carry the penalized normal of Sec. 2.3.  Returns 0 or -1. */
+int dbso_curvature(const dbso_case *cs, const double *alpha, const double *kinv,
+                   const double *Fx, const double *Fy, const double *Fz, double *kappa);
 
 /* Face fluxes F = (linear interpolate U) . S; boundary faces take the
    inlet velocity, zero at walls, the cell velocity at outlets. */

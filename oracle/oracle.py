@@ -47,6 +47,7 @@ class OracleCase(C.Structure):
         ("bc_wave", (C.c_double * 3) * 6),
         ("t0", C.c_double),
         ("sigma", C.c_double),
+        ("contact_angle", C.c_double),
     ]
 
 
@@ -100,7 +101,7 @@ def lib():
         L.dbso_step.argtypes = ([C.POINTER(OracleCase)] + [_DP] * 11 +
                                 [C.c_int, C.POINTER(OracleInfo), C.POINTER(OracleTrace)])
         L.dbso_step.restype = C.c_int
-        L.dbso_curvature.argtypes = [C.POINTER(OracleCase)] + [_DP] * 5
+        L.dbso_curvature.argtypes = [C.POINTER(OracleCase)] + [_DP] * 6
         L.dbso_curvature.restype = C.c_int
         L.dbso_pressure_apply.argtypes = [C.POINTER(OracleCase), _DP, _DP, _DP]
         L.dbso_pressure_apply.restype = C.c_int
@@ -147,6 +148,7 @@ def make_case(cs) -> OracleCase:
             o.bc_wave[b][q] = wave[q]
     o.t0 = float(getattr(cs, "t0", 0.0))
     o.sigma = float(getattr(cs, "sigma", 0.0))
+    o.contact_angle = float(getattr(cs, "contact_angle", 0.0))
     o.dt = cs.dt
     o.n_corr = cs.n_corr
     o.mom_sweeps = cs.mom_sweeps
@@ -171,14 +173,16 @@ def closures(cs, alpha: float):
 
 def curvature(cs, alpha: np.ndarray, F=None) -> np.ndarray:
     """Interface curvature kappa = -div(grad(alpha)/|grad(alpha)|) per cell
-    (CSF, Sec. 2.2); F (face fluxes) only picks outlet backflow values."""
+    (CSF, Sec. 2.2), penalized at clear/porous faces when the case imposes a
+    contact angle; F (face fluxes) only picks outlet backflow values."""
     o = make_case(cs)
     a = np.ascontiguousarray(alpha, dtype=np.float64).reshape(-1)
     if F is None:
         F = [np.zeros(n) for n in nfaces(cs.shape)]
     F = [np.ascontiguousarray(f, dtype=np.float64) for f in F]
     k = np.zeros(a.size)
-    rc = lib().dbso_curvature(C.byref(o), _ptr(a), *[_ptr(f) for f in F], _ptr(k))
+    kv = np.ascontiguousarray(cs.kinv, dtype=np.float64).reshape(-1)
+    rc = lib().dbso_curvature(C.byref(o), _ptr(a), _ptr(kv), *[_ptr(f) for f in F], _ptr(k))
     if rc:
         raise ValueError(f"dbso_curvature failed ({rc})")
     return k

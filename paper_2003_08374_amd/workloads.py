@@ -85,6 +85,7 @@ class Case:
     steps: int = 1
     t0: float = 0.0
     sigma: float = 0.0
+    contact_angle: float = 0.0  # radians, at clear/porous faces; 0 = not imposed
 
     @property
     def ncells(self) -> int:
