@@ -78,7 +78,13 @@ typedef struct {
                            div(n_lg) = -div(grad(alpha)/|grad(alpha)|), positive
                            for a liquid drop; porous cells keep the App. B
                            capillary force.  0 switches it off (no extra work).
-                           The contact angle at porous walls is not modelled. */
+                           */
+  double contact_angle; /* penalized contact angle theta [rad] in [0, pi), measured
+                           through the alpha = 1 phase, imposed on every face between
+                           a clear and a porous cell (Sec. 2.3, locally modified
+                           normal): that face's normal flux in the curvature becomes
+                           -cos(theta) (n_w . e_axis) |n_f|, n_w pointing from the
+                           porous into the clear cell.  0 = not imposed. */
 } dbs_physics;
 
 typedef struct {

@@ -256,6 +256,7 @@ static int validate_shared(const dbs_physics *p, const dbs_controls *c, std::str
   if (p->pc_model == DBS_VAN_GENUCHTEN && !(p->pc_exp > 0.0 && p->pc_exp < 1.0)) { msg = "VG m"; return DBS_EINVAL; }
   if (!(p->rho_l > 0.0 && p->rho_g > 0.0 && p->mu_l > 0.0 && p->mu_g > 0.0)) { msg = "fluid properties"; return DBS_EINVAL; }
   if (!(p->sigma >= 0.0 && p->sigma < HUGE_VAL)) { msg = "sigma"; return DBS_EINVAL; }
+  if (!(p->contact_angle >= 0.0 && p->contact_angle < M_PI)) { msg = "contact_angle"; return DBS_EINVAL; }
   if (!(c->dt > 0.0) || c->n_corr < 1 || c->n_corr > 16 || c->mom_sweeps < 0 ||
       c->mules_iter < 1 || !(c->p_tol > 0.0) || c->p_maxit < 1 ||
       (c->precision != DBS_FP64 && c->precision != DBS_MIXED) || c->mg_pre < 0 || c->mg_post < 0) {
@@ -363,6 +364,8 @@ static Phys make_phys(const dbs_physics *phys) {
   P.inv_span_pc = 1.0 / (phys->a_pcmax - phys->a_pcirr);
   P.eps_pc = phys->eps_pc;
   P.sigma = phys->sigma;
+  P.ca_on = phys->contact_angle > 0.0 ? 1 : 0;
+  P.cos_ca = cos(phys->contact_angle);
   return P;
 }
 

@@ -26,6 +26,8 @@ struct Phys {
   int pc_model;
   double pc0, pc_exp, a_pcirr, inv_span_pc, eps_pc;
   double sigma;  // interfacial tension of the clear-fluid CSF force (0: off)
+  int ca_on;     // a contact angle is imposed on clear/porous faces
+  double cos_ca; // its cosine
 };
 
 // One sample (one mesh) of a batch.  Cell and face indices are absolute in

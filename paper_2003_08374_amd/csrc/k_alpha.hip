@@ -288,7 +288,11 @@ __global__ void __launch_bounds__(NTHREADS) k_alpha_update(Segs SG, Phys Ph, con
 // force): SK = sigma kappa / phi in clear cells, 0 in porous cells, with
 // kappa = div(n_lg) = -div(n_f), n_f = grad_f / (|grad_f| + dN) and grad_f
 // the mean of the two cells' Gauss gradients of alpha^{n+1} (the cell's own
-// on a domain face; empty axes carry no face).
+// on a domain face; empty axes carry no face).  With a contact angle, a
+// face between a clear and a porous cell carries the penalized normal of
+// Sec. 2.3 instead: only its component along the face axis enters the
+// divergence, -cos(theta) (n_w . e_axis) |n_f|, n_w from the porous into the
+// clear cell.
 __global__ void __launch_bounds__(NTHREADS) k_curvature(Segs SG, Phys Ph,
                                                         const double *__restrict__ gx,
                                                         const double *__restrict__ gy,
@@ -298,6 +302,7 @@ __global__ void __launch_bounds__(NTHREADS) k_curvature(Segs SG, Phys Ph,
                                                         double *__restrict__ SK) {
   FOR_CELLS(SG, G, P) {
   const double gP[3] = {gx[P.c], gy[P.c], gz[P.c]};
+  const bool pP = kinv[P.c] > 0.0;
   double div = 0.0;
 #pragma unroll
   for (int a = 0; a < 3; a++) {
@@ -307,8 +312,16 @@ __global__ void __launch_bounds__(NTHREADS) k_curvature(Segs SG, Phys Ph,
     const int cp = on_boundary(G, P, a, 1) ? P.c : P.c + st;
     const double fm[3] = {0.5 * (gP[0] + gx[cm]), 0.5 * (gP[1] + gy[cm]), 0.5 * (gP[2] + gz[cm])};
     const double fp[3] = {0.5 * (gP[0] + gx[cp]), 0.5 * (gP[1] + gy[cp]), 0.5 * (gP[2] + gz[cp])};
-    const double nm = fm[a] / (sqrt(fm[0] * fm[0] + fm[1] * fm[1] + fm[2] * fm[2]) + G.dN);
-    const double np = fp[a] / (sqrt(fp[0] * fp[0] + fp[1] * fp[1] + fp[2] * fp[2]) + G.dN);
+    const double mm = sqrt(fm[0] * fm[0] + fm[1] * fm[1] + fm[2] * fm[2]);
+    const double mp = sqrt(fp[0] * fp[0] + fp[1] * fp[1] + fp[2] * fp[2]);
+    double nm = fm[a] / (mm + G.dN);
+    double np = fp[a] / (mp + G.dN);
+    if (Ph.ca_on) {
+      // a domain face reads the cell itself: same porosity, no wall
+      const bool pm = kinv[cm] > 0.0, pp = kinv[cp] > 0.0;
+      if (pm != pP) nm = -Ph.cos_ca * (pm ? 1.0 : -1.0) * (mm / (mm + G.dN));
+      if (pp != pP) np = -Ph.cos_ca * (pP ? 1.0 : -1.0) * (mp / (mp + G.dN));
+    }
     div += (np - nm) * G.ih[a];
   }
   SK[P.c] = kinv[P.c] > 0.0 ? 0.0 : Ph.sigma * -div / phi[P.c];

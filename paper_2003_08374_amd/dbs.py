@@ -42,7 +42,8 @@ class Physics(C.Structure):
                 ("kr_model", C.c_int), ("kr_m", C.c_double), ("s_lirr", C.c_double),
                 ("s_girr", C.c_double), ("pc_model", C.c_int), ("pc0", C.c_double),
                 ("pc_exp", C.c_double), ("a_pcirr", C.c_double), ("a_pcmax", C.c_double),
-                ("eps_pc", C.c_double), ("sigma", C.c_double)]
+                ("eps_pc", C.c_double), ("sigma", C.c_double),
+                ("contact_angle", C.c_double)]
 
 
 class BC(C.Structure):
@@ -160,6 +161,7 @@ def make_structs(case, precision=None, p_tol=None, mg=None, max_courant=0.0, bou
     p.a_pcmax = case.pc.get("a_max", 1.0)
     p.eps_pc = case.pc.get("eps", 1e-3)
     p.sigma = float(getattr(case, "sigma", 0.0))
+    p.contact_angle = float(getattr(case, "contact_angle", 0.0))
     bcs = (BC * 6)()
     for b in range(6):
         d = case.bc[b]

@@ -227,14 +227,16 @@ def fractured_3d(n=128, h=1e-4, dt=1e-5, seed_k=1, seed_phi=2, fractures="slab",
 
 
 def droplet(shape=(64, 64, 1), h=1e-4, radius_cells=16.0, width_cells=1.0, centre=None,
-            sigma=0.07, dt=1e-5, porous_rows=0, gravity=False, steps=5, name=None):
+            sigma=0.07, dt=1e-5, porous_rows=0, gravity=False, steps=5, name=None,
+            contact_angle=0.0):
     """A water drop in air inside a closed box (walls; z empty when nz = 1).
 
     alpha = (1 - tanh((r - R) / w)) / 2 around ``centre`` (cell units, the
     box centre by default), R = radius_cells h, w = width_cells h;
     sigma = 0.07 N/m (water-air).  ``porous_rows`` > 0 puts a porous floor
     of that many cell rows (phi 0.5, k 1e-12 m^2, Brooks-Corey models as the
-    2D layered case) under the drop; gravity -y when ``gravity``.
+    2D layered case) under the drop; gravity -y when ``gravity``;
+    ``contact_angle`` (radians, 0 = none) is imposed on the floor.
     """
     shape = tuple(shape)
     nx, ny, nz = shape
@@ -258,6 +260,7 @@ def droplet(shape=(64, 64, 1), h=1e-4, radius_cells=16.0, width_cells=1.0, centr
     return Case(name=nm, shape=shape, h=hh, fluids=fluids(WATER, AIR),
                 g=(0.0, -GRAVITY if gravity else 0.0, 0.0), bc=bc, phi=phi, kinv=kinv,
                 alpha=alpha, U=U, p_rgh=prgh, dt=dt, steps=steps, sigma=sigma,
+                contact_angle=contact_angle,
                 kr={"model": "brooks_corey", "m": 2.0},
                 pc={"model": "brooks_corey", "pc0": 1e3, "exp": 0.5})
 

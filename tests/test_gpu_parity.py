@@ -198,12 +198,18 @@ CSF_DROPS = [
          porous_rows=6, gravity=True),
     # static 2D drop, no gravity, closed box
     dict(shape=(48, 48, 1), radius_cells=12, width_cells=1.5),
+    # penalized contact angles on the porous floor (Sec. 2.3)
+    dict(shape=(64, 64, 1), radius_cells=12, width_cells=1.5, centre=(32, 26, 0),
+         porous_rows=16, gravity=True, contact_angle=float(np.radians(60.0))),
+    dict(shape=(23, 24, 21), radius_cells=6, width_cells=1.5, centre=(11.5, 12, 10.5),
+         porous_rows=6, gravity=True, contact_angle=float(np.radians(120.0))),
 ]
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 @pytest.mark.parametrize("kw", CSF_DROPS, ids=["drop2d_porous_floor", "drop3d_porous_floor",
-                                               "drop2d_static"])
+                                               "drop2d_static", "drop2d_angle60",
+                                               "drop3d_angle120"])
 def test_csf_drops_match_oracle(kw, precision):
     """Clear-fluid CSF surface tension: drops against the oracle over 10
     steps, in FP64 and mixed precision.  The closed boxes' pressure solves
@@ -257,6 +263,9 @@ def test_error_paths():
     assert e.value.code == dbs.EINVAL
     with pytest.raises(dbs.DBSError) as e:
         dbs.Solver(case.replace(sigma=-0.07))
+    assert e.value.code == dbs.EINVAL
+    with pytest.raises(dbs.DBSError) as e:
+        dbs.Solver(case.replace(contact_angle=4.0))
     assert e.value.code == dbs.EINVAL
     with dbs.Solver(case.replace(p_maxit=1, p_tol=1e-15)) as s:
         assert s.step(2, check=False) == dbs.ENOCONV
