@@ -186,6 +186,19 @@ def test_gravity_drainage_plateau_on_gpu():
     assert abs(np.median(a[-40:-5]) - 0.467) < 0.01
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_buckley_leverett_on_gpu(precision):
+    """Sec. 4.1.1 water-into-oil Buckley-Leverett column (Brooks-Corey k_r,
+    m = 3), 400 steps of 20 s: the GPU profile equals the oracle's."""
+    n, L, U = 200, 0.4, 1e-5
+    c = PC.column_1d(n, L / n, axis=0, alpha0=0.0, U_in=U, kinv=1e11, phi=0.5,
+                     fl=W.fluids(W.WATER, W.OIL), kr={"model": "brooks_corey", "m": 3.0},
+                     pc={"model": "brooks_corey", "pc0": 0.0, "exp": 0.5}, dt=20.0,
+                     bc_lo=W.inlet((U, 0.0, 0.0), 1.0), bc_hi=W.outlet(0.0, 0.0))
+    out, ref, st, _ = _run_both(c, 400, gpu_tol=1e-12, precision=precision)
+    compare_states(out, ref, tol_alpha=1e-9, tol_l2=1e-9, label=f"buckley-leverett {precision}")
+
+
 # --------------------------------------------- clear-fluid surface tension
 
 CSF_DROPS = [
