@@ -103,7 +103,13 @@
  *       normals, |n_f| = |grad_f|/(|grad_f| + dN) (no interface, no term).
  *       theta is measured through the liquid (alpha = 1) phase; the wall
  *       being the face between the two cells, the same angle holds at every
- *       clear/porous face; 0 means not imposed.
+ *       clear/porous face; 0 means not imposed;
+ *   R19 CFL-adaptive time step (Sec. 3.2: the march follows an imposed
+ *       Courant number; no rule is printed): before every step
+ *       dt <- min(dt_max, 1.2 dt, Co_target dt / Co), Co = dt max over cells
+ *       of the outflow sum_f max(F_f, 0) / (phi V) of the current fluxes
+ *       (the growth factor 1.2 is a choice); the first step starts from the
+ *       given dt.
  *
  * Pins (tests/test_oracle_pins.py) tie each function to what the paper and
  * the mathematics fix.  Parity unpinned: the values the eps_pc clamp of R5
@@ -965,11 +971,16 @@ int dbso_step(const dbso_case *cs, const double *phi, const double *kinv,
               double *p_out, double *Fx, double *Fy, double *Fz, int nsteps,
               dbso_info *info, dbso_trace *trace) {
   mesh_t m;
-  int rc = build_mesh(cs, &m);
+  /* working copy: the adaptive time step (R19) changes dt between steps */
+  dbso_case cw = *cs;
+  int rc = build_mesh(&cw, &m);
   if (rc) { free_mesh(&m); return rc; }
+  cs = &cw;
+  if (cw.target_courant > 0.0 && !(cw.dt_max > 0.0)) { free_mesh(&m); return -1; }
   int nc = m.nc, nf = m.nf;
   for (int c = 0; c < nc; c++)
     if (!(phi[c] > 0.0 && phi[c] <= 1.0) || !(kinv[c] >= 0.0)) { free_mesh(&m); return -1; }
+  double tnow = cw.t0;
   double V = m.V;
   double *F = (double *)malloc(sizeof(double) * nf);
   double *U = (double *)malloc(sizeof(double) * 3 * nc);
@@ -1003,7 +1014,26 @@ int dbso_step(const dbso_case *cs, const double *phi, const double *kinv,
 
   for (int step = 0; step < nsteps && rc == 0; step++) {
     dbso_trace *tr = step == 0 ? trace : NULL;
-    m.t = cs->t0 + (step + 1) * cs->dt;  /* boundary values at t^{n+1} (R16) */
+    if (cw.target_courant > 0.0) {
+      /* R19: Courant number of the current fluxes at the current dt */
+      double rate = 0.0;
+      for (int c = 0; c < nc; c++) {
+        double out = 0.0;
+        for (int k = 0; k < 6; k++) {
+          const face_t *Fc = &m.f[m.cf[c * 6 + k]];
+          if (Fc->kind == DBSO_EMPTY) continue;
+          double fl = F[m.cf[c * 6 + k]];
+          out += (k & 1) ? maxd(fl, 0.0) : maxd(-fl, 0.0);
+        }
+        rate = maxd(rate, out / (phi[c] * V));
+      }
+      double co = cw.dt * rate;
+      double dtn = mind(cw.dt_max, 1.2 * cw.dt);
+      if (co > 0.0) dtn = mind(dtn, cw.target_courant * cw.dt / co);
+      cw.dt = dtn;
+    }
+    m.t = tnow + cw.dt;  /* boundary values at t^{n+1} (R16) */
+    tnow = m.t;
     /* 1. saturation */
     for (int c = 0; c < nc; c++) cell_props(cs, alpha[c], kinv[c], &po[c]);
     alpha_stage(&m, phi, kinv, alpha, F, p_rgh, an, aPhi, rPhi, tr);
@@ -1123,6 +1153,8 @@ int dbso_step(const dbso_case *cs, const double *phi, const double *kinv,
     info->alpha_max = -1e300;
     info->phase_volume = 0.0;
     info->max_div = 0.0;
+    info->dt_last = cw.dt;
+    info->t_end = tnow;
     for (int c = 0; c < nc; c++) {
       info->alpha_min = mind(info->alpha_min, alpha[c]);
       info->alpha_max = maxd(info->alpha_max, alpha[c]);

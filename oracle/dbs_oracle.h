@@ -57,6 +57,8 @@ typedef struct {
   double t0;                /* time at the start of the first step [s] */
   double sigma;             /* interfacial tension [N/m] (clear-fluid CSF) */
   double contact_angle;     /* at clear/porous faces [rad], 0 = not imposed */
+  double target_courant;    /* > 0: CFL-adaptive time step (R19), dt is the first */
+  double dt_max;            /* cap of the adaptive time step (> 0) */
 } dbso_case;
 
 typedef struct {
@@ -65,6 +67,8 @@ typedef struct {
   double alpha_min, alpha_max;
   double phase_volume;      /* sum phi*alpha*V after the last step */
   double max_div;           /* max |sum_out F| over cells after the last step */
+  double dt_last;           /* time step of the last step */
+  double t_end;             /* time reached */
 } dbso_info;
 
 /* Optional intermediate arrays of the first step (any pointer may be NULL).

@@ -48,6 +48,7 @@ class OracleCase(C.Structure):
         ("t0", C.c_double),
         ("sigma", C.c_double),
         ("contact_angle", C.c_double),
+        ("target_courant", C.c_double), ("dt_max", C.c_double),
     ]
 
 
@@ -57,6 +58,7 @@ class OracleInfo(C.Structure):
         ("p_relres", C.c_double * 16),
         ("alpha_min", C.c_double), ("alpha_max", C.c_double),
         ("phase_volume", C.c_double), ("max_div", C.c_double),
+        ("dt_last", C.c_double), ("t_end", C.c_double),
     ]
 
 
@@ -149,6 +151,8 @@ def make_case(cs) -> OracleCase:
     o.t0 = float(getattr(cs, "t0", 0.0))
     o.sigma = float(getattr(cs, "sigma", 0.0))
     o.contact_angle = float(getattr(cs, "contact_angle", 0.0))
+    o.target_courant = float(getattr(cs, "target_courant", 0.0))
+    o.dt_max = float(getattr(cs, "dt_max", 0.0))
     o.dt = cs.dt
     o.n_corr = cs.n_corr
     o.mom_sweeps = cs.mom_sweeps
@@ -261,12 +265,13 @@ def step(cs, state: dict, nsteps: int, trace: bool = False, check: bool = True):
     if check and rc:
         raise RuntimeError(f"dbso_step failed ({rc})")
     out = {"alpha": a, "U": np.stack(U), "p_rgh": prgh, "p": p, "F": tuple(F), "rc": rc,
-           "t": t0 + nsteps * cs.dt}
+           "t": info.t_end if nsteps > 0 else t0}
     inf = {
         "p_iters": list(info.p_iters)[: cs.n_corr],
         "p_relres": list(info.p_relres)[: cs.n_corr],
         "alpha_min": info.alpha_min, "alpha_max": info.alpha_max,
         "phase_volume": info.phase_volume, "max_div": info.max_div,
+        "dt_last": info.dt_last,
     }
     if trace:
         return out, inf, tarr

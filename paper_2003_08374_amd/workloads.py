@@ -86,6 +86,8 @@ class Case:
     t0: float = 0.0
     sigma: float = 0.0
     contact_angle: float = 0.0  # radians, at clear/porous faces; 0 = not imposed
+    target_courant: float = 0.0  # > 0: CFL-adaptive time step (dt is the first)
+    dt_max: float = 0.0          # cap of the adaptive time step
 
     @property
     def ncells(self) -> int:

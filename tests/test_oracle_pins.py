@@ -913,3 +913,22 @@ def test_contact_angle_is_off_at_zero_and_away_from_porous_cells():
                           O.curvature(cp, cp.alpha))
     assert not np.array_equal(O.curvature(cp.replace(contact_angle=1.0), cp.alpha),
                               O.curvature(cp, cp.alpha))
+
+
+@pytest.mark.parametrize("phi", [1.0, 0.5])
+def test_adaptive_time_step_reaches_the_target_courant(phi):
+    """CFL-adaptive time step (Sec. 3.2, reading R19): in a uniform plug flow
+    U through a column of porosity phi the Courant number is U dt/(phi h), so
+    from a small first step dt grows by 1.2 per step until it settles at
+    Co_target phi h/U, and the time reached is the sum of the steps."""
+    n, h, U, target = 40, 1e-3, 0.1, 0.5
+    kinv = 0.0 if phi == 1.0 else 1e6
+    c = PC.column_1d(n, h, axis=0, alpha0=1.0, U_in=U, kinv=kinv, phi=phi, dt=1e-4)
+    c = c.replace(target_courant=target, dt_max=1.0, p_tol=1e-12)
+    expect = target * phi * h / U
+    out, info = O.step(c, O.initial_state(c), 30)
+    assert info["dt_last"] == pytest.approx(expect, rel=1e-9)
+    dts = [min(1e-4 * 1.2 ** (k + 1), expect) for k in range(30)]
+    assert out["t"] == pytest.approx(sum(dts), rel=1e-9)
+    capped, _ = O.step(c.replace(dt_max=0.5 * expect), O.initial_state(c), 30)
+    assert capped["t"] == pytest.approx(sum(min(d, 0.5 * expect) for d in dts), rel=1e-9)
