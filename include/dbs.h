@@ -115,6 +115,13 @@ typedef struct {
   int mg_pre, mg_post;  /* red-black Gauss-Seidel sweeps per level (0: default 2) */
   double max_courant;   /* > 0: refuse a step whose Courant number exceeds it */
   double bounds_tol;    /* > 0: report DBS_EBOUNDS when alpha leaves the band */
+  double target_courant;/* > 0: CFL-adaptive time step (Sec. 3.2): before every step
+                           dt <- min(dt_max, 1.2 dt, target_courant dt / Co), Co = dt
+                           max over cells of sum_out max(F_f, 0) / (phi V) of the
+                           current fluxes; dt above is the first step.  A batch
+                           steps in lockstep with the smallest dt of its samples.
+                           Not available in graph mode (DBS_EINVAL). */
+  double dt_max;        /* cap of the adaptive time step (> 0 when adaptive) */
 } dbs_controls;
 
 typedef struct {
@@ -125,7 +132,8 @@ typedef struct {
   double alpha_min, alpha_max;
   double phase_volume;  /* sum phi alpha V */
   double max_courant;   /* at the start of the last step */
-  double time;          /* time reached (steps x dt from dbs_set_time's value) */
+  double time;          /* time reached (the sum of the steps from dbs_set_time's value) */
+  double dt;            /* time step of the last step */
 } dbs_stats;
 
 typedef struct dbs_handle dbs_handle;

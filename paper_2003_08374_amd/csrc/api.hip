@@ -157,6 +157,12 @@ __global__ void k_add_time(Geom *__restrict__ g, int ns, double dt) {
   if (s < ns) g[s].t += dt;
 }
 
+// the time step of every sample (adaptive stepping)
+__global__ void k_set_dt(Geom *__restrict__ g, int ns, double dt) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s < ns) g[s].dt = dt;
+}
+
 // Wave inlet values of every row at each sample's time (linear wave on
 // still water of depth d, surface d + A sin(w t)): below the surface
 // alpha = 1, u = A w cosh(k y)/sinh(k d) sin(w t) into the domain and
@@ -257,6 +263,7 @@ static int validate_shared(const dbs_physics *p, const dbs_controls *c, std::str
   if (!(p->rho_l > 0.0 && p->rho_g > 0.0 && p->mu_l > 0.0 && p->mu_g > 0.0)) { msg = "fluid properties"; return DBS_EINVAL; }
   if (!(p->sigma >= 0.0 && p->sigma < HUGE_VAL)) { msg = "sigma"; return DBS_EINVAL; }
   if (!(p->contact_angle >= 0.0 && p->contact_angle < M_PI)) { msg = "contact_angle"; return DBS_EINVAL; }
+  if (c->target_courant > 0.0 && !(c->dt_max > 0.0)) { msg = "dt_max"; return DBS_EINVAL; }
   if (!(c->dt > 0.0) || c->n_corr < 1 || c->n_corr > 16 || c->mom_sweeps < 0 ||
       c->mules_iter < 1 || !(c->p_tol > 0.0) || c->p_maxit < 1 ||
       (c->precision != DBS_FP64 && c->precision != DBS_MIXED) || c->mg_pre < 0 || c->mg_post < 0) {
@@ -579,6 +586,20 @@ static int copy_out3(Handle *h, double *dst, const double *src) {
   return rc;
 }
 
+// CFL-adaptive time step: dt <- min(dt_max, 1.2 dt, target dt / Co) from
+// the Courant numbers of the current fluxes (one dt for the whole batch)
+static void adapt_dt(Handle *h) {
+  if (!(h->ctl.target_courant > 0.0)) return;
+  cell_stats(h);
+  double co = 0.0;
+  for (int s = 0; s < h->ns; s++) co = std::max(co, h->hsstat[5 * s + 3]);
+  double dt = std::min(h->ctl.dt_max, 1.2 * h->ctl.dt);
+  if (co > 0.0) dt = std::min(dt, h->ctl.target_courant * h->ctl.dt / co);
+  h->ctl.dt = dt;
+  for (int s = 0; s < h->ns; s++) h->hG[s].dt = dt;
+  DBS_LAUNCH(h, KC_MISC, k_set_dt, dim3((h->ns + 255) / 256), dim3(256), h->dG, h->ns, dt);
+}
+
 static int courant_check(Handle *h) {
   if (!(h->ctl.max_courant > 0.0)) return DBS_OK;
   cell_stats(h);
@@ -637,6 +658,7 @@ static int step_body(Handle *h, TraceOut *tr, int budget, std::vector<int> *its_
 }
 
 static int eager_step(Handle *h, TraceOut *tr, std::vector<int> *its_out) {
+  adapt_dt(h);
   int rc = courant_check(h);
   if (rc) return rc;
   rc = step_body(h, tr, 0, its_out);
@@ -919,6 +941,10 @@ int dbs_batch_step(dbs_handle *H, int nsteps) { return dbs_step(H, nsteps); }
 int dbs_set_graph(dbs_handle *H, int on) {
   if (!H) return DBS_EINVAL;
   Handle *h = &H->h;
+  if (on && h->ctl.target_courant > 0.0) {
+    h->err = "graph mode replays a fixed time step; adaptive stepping is eager only";
+    return DBS_EINVAL;
+  }
   hipStreamSynchronize(h->stream);
   h->graph_mode = on ? 1 : 0;
   reset_graphs(h);
@@ -1030,6 +1056,7 @@ int dbs_batch_get_stats(dbs_handle *H, int i, dbs_stats *out) {
   if (int rc = check_sample(&H->h, i)) return rc;
   *out = H->h.st[i];
   out->time = H->h.tnow;
+  out->dt = H->h.ctl.dt;  // the step just taken (adaptive: chosen before it)
   return DBS_OK;
 }
 

@@ -55,7 +55,8 @@ class Controls(C.Structure):
     _fields_ = [("dt", C.c_double), ("n_corr", C.c_int), ("mom_sweeps", C.c_int),
                 ("transpose_visc", C.c_int), ("mules_iter", C.c_int), ("p_tol", C.c_double),
                 ("p_maxit", C.c_int), ("precision", C.c_int), ("mg_pre", C.c_int),
-                ("mg_post", C.c_int), ("max_courant", C.c_double), ("bounds_tol", C.c_double)]
+                ("mg_post", C.c_int), ("max_courant", C.c_double), ("bounds_tol", C.c_double),
+                ("target_courant", C.c_double), ("dt_max", C.c_double)]
 
 
 class Stats(C.Structure):
@@ -63,7 +64,7 @@ class Stats(C.Structure):
                 ("p_relres", C.c_double * 16), ("mg_levels", C.c_int),
                 ("alpha_min", C.c_double), ("alpha_max", C.c_double),
                 ("phase_volume", C.c_double), ("max_courant", C.c_double),
-                ("time", C.c_double)]
+                ("time", C.c_double), ("dt", C.c_double)]
 
 
 _DP = C.POINTER(C.c_double)
@@ -184,6 +185,8 @@ def make_structs(case, precision=None, p_tol=None, mg=None, max_courant=0.0, bou
     c.mg_pre, c.mg_post = mg if mg else (0, 0)
     c.max_courant = max_courant
     c.bounds_tol = bounds_tol
+    c.target_courant = float(getattr(case, "target_courant", 0.0))
+    c.dt_max = float(getattr(case, "dt_max", 0.0))
     return g, p, bcs, c
 
 
@@ -237,7 +240,7 @@ class _Handle:
                 "p_relres": list(s.p_relres)[:n], "mg_levels": s.mg_levels,
                 "alpha_min": s.alpha_min, "alpha_max": s.alpha_max,
                 "phase_volume": s.phase_volume, "max_courant": s.max_courant,
-                "time": s.time}
+                "time": s.time, "dt": s.dt}
 
     # -------------------------------------------------------------- profiling
     def set_profiling(self, mask):

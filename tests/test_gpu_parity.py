@@ -199,6 +199,26 @@ def test_buckley_leverett_on_gpu(precision):
     compare_states(out, ref, tol_alpha=1e-9, tol_l2=1e-9, label=f"buckley-leverett {precision}")
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_adaptive_time_step_matches_oracle(precision):
+    """CFL-adaptive stepping (Sec. 3.2, Courant target 0.3, first step
+    1e-4 s, cap 2e-3 s) on the limiter-stress case: the same time steps,
+    time reached and fields as the oracle over 15 steps."""
+    case = W.layered_2d_stress(n=32).replace(dt=1e-4, target_courant=0.3, dt_max=2e-3)
+    dbs = _dbs()
+    ref, rinfo = O.step(case.replace(p_tol=1e-14, p_maxit=200000), O.initial_state(case), 15)
+    with dbs.Solver(case.replace(p_tol=1e-13), precision=precision) as s:
+        s.step(15)
+        out, st = s.state(), s.stats()
+        with pytest.raises(dbs.DBSError) as e:
+            s.set_graph(True)
+        assert e.value.code == dbs.EINVAL
+    assert st["dt"] == pytest.approx(rinfo["dt_last"], rel=1e-10)
+    assert st["time"] == pytest.approx(ref["t"], rel=1e-10)
+    assert st["dt"] > 1e-4 * 1.2 ** 5
+    compare_states(out, ref, tol_alpha=1e-9, tol_l2=1e-9, label=f"adaptive dt {precision}")
+
+
 # --------------------------------------------- clear-fluid surface tension
 
 CSF_DROPS = [
