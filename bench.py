@@ -272,6 +272,19 @@ def csf_leg(args, case):
                                                 (ms_k * 1e-3) / 1e9, 1) if ms_k > 0 else None}}
 
 
+def reservoir_leg(args):
+    """The Darcy-scale heterogeneous reservoir at the paper's 2000 x 800
+    cells (block permeabilities 1e-13..4e-13 m^2, water into oil, dt 0.5 s),
+    mixed precision, eagerly: a 2D, Darcy-dominated pressure system."""
+    from paper_2003_08374_amd import workloads as W
+
+    cs = W.reservoir_2d(nx=2000, ny=800, dt=0.5).replace(p_tol=args.p_tol, p_maxit=500)
+    r = time_solver(cs, "mixed", args.steps, args.warmup)
+    return {"workload": cs.name, "cells": cs.ncells, "p_tol": args.p_tol,
+            "value": cs.ncells / (r["sec"] / args.steps),
+            "ms_per_step": r["sec"] / args.steps * 1e3, "p_iters_last": r["p_iters"][-1]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -287,6 +300,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched leg")
     ap.add_argument("--no-flume", action="store_true", help="skip the wave-flume batch leg")
     ap.add_argument("--no-csf", action="store_true", help="skip the surface-tension leg")
+    ap.add_argument("--no-reservoir", action="store_true",
+                    help="skip the heterogeneous-reservoir leg")
     ap.add_argument("--batch-samples", type=int, default=512)
     ap.add_argument("--coarse-sweeps", type=int, default=3)
     ap.add_argument("--fused", type=int, default=1,
@@ -363,6 +378,7 @@ def main():
     batched = None if args.no_batch else batch_leg(args)
     flume = None if args.no_flume else flume_leg(args)
     csf = None if args.no_csf else csf_leg(args, case)
+    reservoir = None if args.no_reservoir else reservoir_leg(args)
     cpu = None if args.no_cpu else cpu_baseline()
 
     line = {
@@ -389,6 +405,7 @@ def main():
         "batched": batched,
         "flume_batch": flume,
         "csf": csf,
+        "reservoir": reservoir,
     }
     if main_run["all"]:
         line["kernel_ms_one_step"] = {k: round(v[1], 3) for k, v in sorted(

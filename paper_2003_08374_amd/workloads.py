@@ -225,6 +225,34 @@ def fractured_3d(n=128, h=1e-4, dt=1e-5, seed_k=1, seed_phi=2, fractures="slab",
                 pc={"model": "brooks_corey", "pc0": 1e3, "exp": 0.5})
 
 
+# ------------------------------------------- Darcy-scale heterogeneous reservoir
+
+
+def reservoir_2d(nx=2000, ny=800, size=(1.0, 0.4), blocks=(4, 4), seed=8, U_in=1e-4,
+                 phi=0.5, dt=0.5, steps=10, name=None):
+    """2D heterogeneous oil reservoir flooded with water (shaped after the
+    paper's Darcy-scale drainage case, Sec. 4.1.4): 1 m x 0.4 m, a grid of
+    blocks x blocks of 0.25 m x 0.1 m with k0 ~ U[1e-13, 4e-13] m^2 per block
+    (seeded), phi = 0.5 (not given in the paper), Van Genuchten k_r (m = 0.5)
+    and no capillary pressure, inlet U_in at x-, fixed p = 0 at x+, walls
+    top and bottom, no gravity (a horizontal section)."""
+    shape = (nx, ny, 1)
+    h = (size[0] / nx, size[1] / ny, size[0] / nx)
+    rng = np.random.default_rng(seed)
+    k_block = rng.uniform(1e-13, 4e-13, size=(blocks[1], blocks[0]))
+    x, y, _ = _cell_centres(shape, h)
+    bi = np.minimum((x / (size[0] / blocks[0])).astype(int), blocks[0] - 1)
+    bj = np.minimum((y / (size[1] / blocks[1])).astype(int), blocks[1] - 1)
+    kinv = 1.0 / k_block[bj, bi]
+    alpha, U, prgh = _blank_state(shape)
+    bc = [inlet((U_in, 0, 0), 1.0), outlet(0.0, 0.0), wall(), wall(), empty(), empty()]
+    return Case(name=name or f"reservoir_2d_{nx}x{ny}", shape=shape, h=h,
+                fluids=fluids(WATER, OIL), g=(0.0, 0.0, 0.0), bc=bc,
+                phi=np.full((1, ny, nx), phi), kinv=kinv, alpha=alpha, U=U, p_rgh=prgh,
+                dt=dt, steps=steps, kr={"model": "van_genuchten", "m": 0.5},
+                pc={"model": "van_genuchten", "pc0": 0.0, "exp": 0.5})
+
+
 # ------------------------------------------------------------ clear-fluid drop
 
 
