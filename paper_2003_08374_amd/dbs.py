@@ -405,6 +405,10 @@ class BatchSolver(_Handle):
                 bcs[6 * i + b] = b6[b]
             if phys is None:
                 phys, ctl = p, c
+            elif bytes(p) != bytes(phys) or bytes(c) != bytes(ctl):
+                # one physics and one set of controls serve the whole batch
+                raise ValueError(f"sample {i} ({cs.name}) differs from sample 0 in its "
+                                 "fluids, models, constants or controls")
         h = C.c_void_p()
         self._check(lib().dbs_batch_create(n, grids, C.byref(phys), bcs, C.byref(ctl),
                                            C.byref(h)), None)

@@ -43,3 +43,13 @@ def test_product_package_does_not_reach_the_oracle():
             if f.endswith((".py", ".hip", ".h", ".cpp")):
                 txt = open(os.path.join(dp, f)).read()
                 assert "dbs_oracle" not in txt and "import oracle" not in txt, f
+
+
+def test_batch_rejects_mixed_physics_before_touching_the_device():
+    """A batch shares one set of physics and controls: a sample that differs
+    is refused by the binding (no device call is made for it)."""
+    from paper_2003_08374_amd import dbs, workloads as W
+    a = W.droplet(shape=(8, 8, 1), radius_cells=3)
+    b = a.replace(sigma=0.03)
+    with pytest.raises(ValueError):
+        dbs.BatchSolver([a, b])
