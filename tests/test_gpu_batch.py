@@ -78,6 +78,28 @@ def test_tiny_and_thin_samples_match_oracle(precision):
         compare_states(out, ref, label=f"edge {precision}:{cs.name} {cs.shape}")
 
 
+def test_adaptive_batch_steps_in_lockstep():
+    """CFL-adaptive stepping of a batch: one time step for all samples, the
+    smallest any sample asks for.  A batch of a sample and its copy with a
+    10x slower inlet equals the single run of the fast sample (same steps and
+    time), and the slow copy advances with the fast sample's steps."""
+    dbs = _dbs()
+    fast = W.layered_2d_stress(n=16).replace(dt=1e-4, target_courant=0.3, dt_max=2e-3,
+                                             p_tol=1e-13)
+    slow_bc = [dict(b) for b in fast.bc]
+    slow_bc[0]["U"] = (0.01, 0.0, 0.0)
+    slow = fast.replace(bc=slow_bc, name="slow")
+    with dbs.Solver(fast) as s:
+        s.step(8)
+        ref, rst = s.state(), s.stats()
+    with dbs.BatchSolver([slow, fast]) as B:
+        B.step(8)
+        out, st0, st1 = B.state(1), B.stats(0), B.stats(1)
+    assert st0["dt"] == st1["dt"] == rst["dt"]
+    assert st0["time"] == pytest.approx(rst["time"], rel=1e-14)
+    compare_states(out, ref, tol_alpha=1e-12, tol_l2=1e-12, label="adaptive batch")
+
+
 def test_batch_equals_single_runs():
     """A sample's result does not depend on the rest of the batch."""
     dbs = _dbs()
