@@ -135,6 +135,28 @@ def test_graph_replay_equals_eager(precision):
                 assert E.stats(i)["p_iters"] == G.stats(i)["p_iters"], (step, cs.name)
 
 
+def test_graph_replay_with_surface_tension_equals_eager():
+    """Captured steps carry the curvature launches and the contact angle:
+    every replay of a batch of drops (clear and porous floors, 60 degrees)
+    equals the eager step."""
+    dbs = _dbs()
+    ca = float(np.radians(60.0))
+    cases = [W.droplet(shape=(40, 36, 1), radius_cells=9, width_cells=1.5, porous_rows=8,
+                       gravity=True, contact_angle=ca, name="g0").replace(p_tol=1e-11),
+             W.droplet(shape=(17, 19, 15), radius_cells=5, width_cells=1.5, porous_rows=4,
+                       gravity=True, contact_angle=ca, name="g1").replace(p_tol=1e-11)]
+    with dbs.BatchSolver(cases) as E, dbs.BatchSolver(cases) as G:
+        G.set_graph(True)
+        for step in range(5):
+            E.step(1)
+            G.step(1)
+            for i, cs in enumerate(cases):
+                a, b = E.state(i), G.state(i)
+                assert max_abs(a["alpha"], b["alpha"]) <= 1e-14, (step, cs.name)
+                assert rel_l2(a["p_rgh"], b["p_rgh"]) <= 1e-13, (step, cs.name)
+                assert rel_l2(a["U"], b["U"]) <= 1e-13, (step, cs.name)
+
+
 def test_graph_budget_too_small_is_recovered():
     """A captured step whose PCG budget is too small is redone eagerly."""
     dbs = _dbs()
