@@ -116,7 +116,10 @@
  * gives in dry porous cells, which only the GPU path checks; pinned are the
  * clamp at the closure level, that it changes nothing while every porous
  * cell is inside the range, and that dry cells keep a step finite and
- * bounded.
+ * bounded.  Parity unpinned as well: the 1/phi factor of R17 (it acts only
+ * in clear cells with phi < 1, which no workload has) and the equilibrium
+ * angle a drop reaches under R18 (pinned: the imposed normal against a
+ * static cap's geometry).
  */
 #include "dbs_oracle.h"
 
