@@ -58,7 +58,12 @@
  *   R9  Van Leer ratio r = (a_U - a_UU)/(a_D - a_U); beyond a boundary a_UU = a_U;
  *   R10 momentum convection upwind; viscous term implicit mu_f grad(U) plus an
  *       explicit div(mu grad(U)^T) from U^n (switchable);
- *   R11 momentum predictor solved with a fixed number of Jacobi sweeps;
+ *   R11 momentum predictor: Sec. 3.2 obtains v* by solving the momentum
+ *       equation implicitly, Eq. (semi_discretised_bis), which leaves the
+ *       linear solver open; Jacobi sweeps from U^n until the residual
+ *       B + sum a_N U_N - a_P U of the iterate a sweep starts from is at
+ *       most mom_tol ||B||_2 over the three components (the sweep is still
+ *       applied), at most mom_maxit sweeps;
  *   R12 no Rhie-Chow / ddt flux correction; Cartesian reconstruct
  *       R(q)_x = (q_west + q_east)/(2 A_x); no body force on boundary faces;
  *       fixed-flux faces carry the p_rgh gradient that reproduces their
@@ -109,7 +114,15 @@
  *       dt <- min(dt_max, 1.2 dt, Co_target dt / Co), Co = dt max over cells
  *       of the outflow sum_f max(F_f, 0) / (phi V) of the current fluxes
  *       (the growth factor 1.2 is a choice); the first step starts from the
- *       given dt.
+ *       given dt;
+ *   R20 saturation sub-cycling (robustness for long runs; the paper marches
+ *       the explicit saturation equation at the imposed Courant number): a
+ *       step's transport may run in n sub-cycles of dt/n, each the whole
+ *       transport stage above applied to the current saturation with F and
+ *       p_rgh of the step start held fixed (closures follow the current
+ *       saturation); the momentum equation takes the mean of the n limited
+ *       fluxes, so that alpha^{n+1} - alpha^n = -dt/(phi V) sum_out of that
+ *       mean exactly as for one stage, and rho^n from the step start.
  *
  * Pins (tests/test_oracle_pins.py) tie each function to what the paper and
  * the mathematics fix.  Parity unpinned: the values the eps_pc clamp of R5
@@ -185,7 +198,8 @@ static int validate_case(const dbso_case *cs) {
   for (int b = 0; b < 2; b++)
     if (cs->bc_kind[b] == DBSO_WAVE &&
         !(cs->bc_wave[b][1] > 0.0 && cs->bc_wave[b][2] > 0.0)) return -1;
-  if (!(cs->dt > 0.0) || cs->n_corr < 1 || cs->n_corr > 16 || cs->mom_sweeps < 0)
+  if (!(cs->dt > 0.0) || cs->n_corr < 1 || cs->n_corr > 16 || cs->mom_maxit < 0 ||
+      !(cs->mom_tol >= 0.0) || cs->n_alpha_sub < 1)
     return -1;
   return 0;
 }
@@ -414,12 +428,11 @@ static void curvature(const mesh_t *m, const double *alpha, const double *kinv,
 }
 
 static void alpha_stage(const mesh_t *m, const double *phi, const double *kinv,
-                        const double *alpha, const double *F, const double *prgh,
-                        double *alpha_new, double *alphaPhi, double *rhoPhi,
-                        dbso_trace *tr) {
+                        const double *alpha, const double *F, const double *prgh, double dt,
+                        double *alpha_new, double *alphaPhi, dbso_trace *tr) {
   const dbso_case *cs = m->cs;
   int nc = m->nc, nf = m->nf;
-  double V = m->V, dt = cs->dt;
+  double V = m->V;
   props_t *pr = (props_t *)malloc(sizeof(props_t) * nc);
   double *p = (double *)malloc(sizeof(double) * nc);
   double *grad = (double *)calloc((size_t)nc * 3, sizeof(double));
@@ -549,9 +562,7 @@ static void alpha_stage(const mesh_t *m, const double *phi, const double *kinv,
   }
   for (int f = 0; f < nf; f++) {
     const face_t *Fc = &m->f[f];
-    if (Fc->kind == DBSO_EMPTY) { alphaPhi[f] = 0.0; rhoPhi[f] = 0.0; continue; }
-    alphaPhi[f] = FL[f] + lam[f] * A[f];
-    rhoPhi[f] = (cs->rho_l - cs->rho_g) * alphaPhi[f] + cs->rho_g * F[f];
+    alphaPhi[f] = Fc->kind == DBSO_EMPTY ? 0.0 : FL[f] + lam[f] * A[f];
   }
   free(Qp); free(Qm); free(Pin); free(Pout); free(lam);
   /* forward Euler on d(phi alpha)/dt with static phi */
@@ -568,10 +579,43 @@ static void alpha_stage(const mesh_t *m, const double *phi, const double *kinv,
     if (tr->A) memcpy(tr->A, A, sizeof(double) * nf);
     if (tr->Rp) memcpy(tr->Rp, Rp, sizeof(double) * nc);
     if (tr->Rm) memcpy(tr->Rm, Rm, sizeof(double) * nc);
+  }
+  free(pr); free(p); free(grad); free(FL); free(A); free(Rp); free(Rm);
+}
+
+/* The saturation stage of a step (R20): n_alpha_sub sub-cycles of dt/n, each
+   the transport stage applied to the current saturation with F and p_rgh
+   fixed.  alphaPhi receives the mean of the sub-cycles' limited fluxes and
+   rhoPhi the mass flux built from it.  The trace keeps the last sub-cycle's
+   A and R+-, the mean flux and the final saturation. */
+static void alpha_transport(const mesh_t *m, const double *phi, const double *kinv,
+                            const double *alpha, const double *F, const double *prgh,
+                            double *alpha_new, double *alphaPhi, double *rhoPhi,
+                            dbso_trace *tr) {
+  const dbso_case *cs = m->cs;
+  int nc = m->nc, nf = m->nf, n = cs->n_alpha_sub;
+  double dts = cs->dt / n;
+  double *cur = (double *)malloc(sizeof(double) * nc);
+  double *sub = (double *)malloc(sizeof(double) * nf);
+  memcpy(cur, alpha, sizeof(double) * nc);
+  for (int f = 0; f < nf; f++) alphaPhi[f] = 0.0;
+  for (int k = 0; k < n; k++) {
+    alpha_stage(m, phi, kinv, cur, F, prgh, dts, alpha_new, sub, k == n - 1 ? tr : NULL);
+    for (int f = 0; f < nf; f++) alphaPhi[f] += sub[f];
+    memcpy(cur, alpha_new, sizeof(double) * nc);
+  }
+  for (int f = 0; f < nf; f++) {
+    alphaPhi[f] /= n;
+    rhoPhi[f] = m->f[f].kind == DBSO_EMPTY
+                    ? 0.0
+                    : (cs->rho_l - cs->rho_g) * alphaPhi[f] + cs->rho_g * F[f];
+  }
+  if (tr) {
     if (tr->alphaPhi) memcpy(tr->alphaPhi, alphaPhi, sizeof(double) * nf);
     if (tr->alpha_new) memcpy(tr->alpha_new, alpha_new, sizeof(double) * nc);
   }
-  free(pr); free(p); free(grad); free(FL); free(A); free(Rp); free(Rm);
+  free(cur);
+  free(sub);
 }
 
 /* ------------------------------------------------------- 3.-4. momentum */
@@ -969,6 +1013,33 @@ int dbso_pressure_solve(const dbso_case *cs, const double *rAU, const double *b,
   return rc;
 }
 
+int dbso_alpha_advance(const dbso_case *cs, const double *phi, const double *kinv,
+                       double *alpha, const double *Fx, const double *Fy, const double *Fz,
+                       const double *p_rgh, int nsteps, double *alphaPhi) {
+  mesh_t m;
+  if (build_mesh(cs, &m)) { free_mesh(&m); return -1; }
+  int nc = m.nc, nf = m.nf;
+  for (int c = 0; c < nc; c++)
+    if (!(phi[c] > 0.0 && phi[c] <= 1.0) || !(kinv[c] >= 0.0) ||
+        (phi[c] == 1.0 && kinv[c] > 0.0)) { free_mesh(&m); return -1; }
+  double *F = (double *)malloc(sizeof(double) * nf);
+  double *an = (double *)malloc(sizeof(double) * nc);
+  double *aPhi = (double *)malloc(sizeof(double) * nf);
+  double *rPhi = (double *)malloc(sizeof(double) * nf);
+  memcpy(F, Fx, sizeof(double) * m.nfa[0]);
+  memcpy(F + m.nfa[0], Fy, sizeof(double) * m.nfa[1]);
+  memcpy(F + m.nfa[0] + m.nfa[1], Fz, sizeof(double) * m.nfa[2]);
+  for (int st = 0; st < nsteps; st++) {
+    m.t = cs->t0 + (st + 1) * cs->dt;
+    alpha_transport(&m, phi, kinv, alpha, F, p_rgh, an, aPhi, rPhi, NULL);
+    memcpy(alpha, an, sizeof(double) * nc);
+  }
+  if (alphaPhi && nsteps > 0) memcpy(alphaPhi, aPhi, sizeof(double) * nf);
+  free(F); free(an); free(aPhi); free(rPhi);
+  free_mesh(&m);
+  return 0;
+}
+
 int dbso_step(const dbso_case *cs, const double *phi, const double *kinv,
               double *alpha, double *Ux, double *Uy, double *Uz, double *p_rgh,
               double *p_out, double *Fx, double *Fy, double *Fz, int nsteps,
@@ -981,8 +1052,10 @@ int dbso_step(const dbso_case *cs, const double *phi, const double *kinv,
   cs = &cw;
   if (cw.target_courant > 0.0 && !(cw.dt_max > 0.0)) { free_mesh(&m); return -1; }
   int nc = m.nc, nf = m.nf;
+  /* porosity in (0, 1], k^-1 >= 0, and no drag in a solid-free cell */
   for (int c = 0; c < nc; c++)
-    if (!(phi[c] > 0.0 && phi[c] <= 1.0) || !(kinv[c] >= 0.0)) { free_mesh(&m); return -1; }
+    if (!(phi[c] > 0.0 && phi[c] <= 1.0) || !(kinv[c] >= 0.0) ||
+        (phi[c] == 1.0 && kinv[c] > 0.0)) { free_mesh(&m); return -1; }
   double tnow = cw.t0;
   double V = m.V;
   double *F = (double *)malloc(sizeof(double) * nf);
@@ -1039,7 +1112,7 @@ int dbso_step(const dbso_case *cs, const double *phi, const double *kinv,
     tnow = m.t;
     /* 1. saturation */
     for (int c = 0; c < nc; c++) cell_props(cs, alpha[c], kinv[c], &po[c]);
-    alpha_stage(&m, phi, kinv, alpha, F, p_rgh, an, aPhi, rPhi, tr);
+    alpha_transport(&m, phi, kinv, alpha, F, p_rgh, an, aPhi, rPhi, tr);
     /* 2. properties at alpha^{n+1}, with the clear-fluid CSF coefficient */
     for (int c = 0; c < nc; c++) cell_props(cs, an[c], kinv[c], &pn[c]);
     if (cs->sigma != 0.0) {
@@ -1053,11 +1126,35 @@ int dbso_step(const dbso_case *cs, const double *phi, const double *kinv,
     fixed_flux_forces(&m, NULL, NULL, q);
     reconstruct(&m, q, R);
     for (int i = 0; i < 3 * nc; i++) B[i] = eq.Sh[i] + R[i];
-    for (int s = 0; s < cs->mom_sweeps; s++) {
-      for (int d = 0; d < 3; d++)
-        for (int c = 0; c < nc; c++)
-          U2[d * nc + c] = (nb_sum(&m, &eq, U + d * nc, c) + B[d * nc + c]) / eq.aP[c];
-      memcpy(U, U2, sizeof(double) * 3 * nc);
+    if (tr) {
+      if (tr->aP) memcpy(tr->aP, eq.aP, sizeof(double) * nc);
+      if (tr->aON) memcpy(tr->aON, eq.aON, sizeof(double) * nf);
+      if (tr->aNO) memcpy(tr->aNO, eq.aNO, sizeof(double) * nf);
+      if (tr->B) memcpy(tr->B, B, sizeof(double) * 3 * nc);
+    }
+    /* the implicit predictor system a_P U - sum a_N U_N = B (R11): Jacobi
+       sweeps from U^n; each sweep also forms the residual of the iterate it
+       starts from, and the solve ends after the sweep whose starting
+       residual is at most mom_tol ||B|| */
+    {
+      double nB = sqrt(vdot(3 * nc, B, B));
+      int sw = 0;
+      double rel = 0.0;
+      while (sw < cs->mom_maxit) {
+        double r2 = 0.0;
+        for (int d = 0; d < 3; d++)
+          for (int c = 0; c < nc; c++) {
+            double acc = nb_sum(&m, &eq, U + d * nc, c) + B[d * nc + c];
+            double r = acc - eq.aP[c] * U[d * nc + c];
+            r2 += r * r;
+            U2[d * nc + c] = acc / eq.aP[c];
+          }
+        memcpy(U, U2, sizeof(double) * 3 * nc);
+        sw++;
+        rel = nB > 0.0 ? sqrt(r2) / nB : 0.0;
+        if (sqrt(r2) <= cs->mom_tol * nB) break;
+      }
+      if (info) { info->mom_sweeps = sw; info->mom_relres = rel; }
     }
     if (tr) {
       if (tr->Shat) memcpy(tr->Shat, eq.Sh, sizeof(double) * 3 * nc);
@@ -1111,7 +1208,18 @@ int dbso_step(const dbso_case *cs, const double *phi, const double *kinv,
       int its = 0;
       double rr = 0.0;
       int src = pcg(&m, T, b, p_rgh, cs->p_tol, cs->p_maxit, &its, &rr);
-      if (info && corr < 16) { info->p_iters[corr] = its; info->p_relres[corr] = rr; }
+      if (info && corr < 16) {
+        info->p_iters[corr] = its;
+        info->p_relres[corr] = rr;
+        /* the norm the solve is relative to (closed domains: projected b) */
+        double bb = 0.0, mb = 0.0;
+        if (!has_outlet(cs)) {
+          for (int c = 0; c < nc; c++) mb += b[c];
+          mb /= nc;
+        }
+        for (int c = 0; c < nc; c++) bb += (b[c] - mb) * (b[c] - mb);
+        info->p_bnorm[corr] = sqrt(bb);
+      }
       if (src) rc = src;
       /* flux and velocity correction */
       for (int f = 0; f < nf; f++) {

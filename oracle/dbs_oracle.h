@@ -46,7 +46,7 @@ typedef struct {
   double bc_p[6];           /* outlet static pressure p */
   double dt;
   int n_corr;               /* PISO correctors */
-  int mom_sweeps;           /* Jacobi sweeps of the momentum predictor */
+  int mom_maxit;            /* sweep cap of the momentum predictor solve */
   int transpose_visc;       /* include div(mu grad(U)^T) */
   int mules_iter;           /* MULES limiter iterations */
   double p_tol;             /* relative residual of the pressure solve */
@@ -59,6 +59,13 @@ typedef struct {
   double contact_angle;     /* at clear/porous faces [rad], 0 = not imposed */
   double target_courant;    /* > 0: CFL-adaptive time step (R19), dt is the first */
   double dt_max;            /* cap of the adaptive time step (> 0) */
+  double mom_tol;           /* momentum predictor: Jacobi sweeps until the residual
+                               of the iterate a sweep starts from is at most
+                               mom_tol ||B||_2 (0: always mom_maxit sweeps) */
+  int n_alpha_sub;          /* saturation sub-cycles per step (>= 1): the
+                               transport runs n times with dt/n, F and p_rgh
+                               frozen, and the momentum equation sees the mean
+                               limited flux */
 } dbso_case;
 
 typedef struct {
@@ -69,6 +76,9 @@ typedef struct {
   double max_div;           /* max |sum_out F| over cells after the last step */
   double dt_last;           /* time step of the last step */
   double t_end;             /* time reached */
+  int mom_sweeps;           /* predictor sweeps of the last step */
+  double mom_relres;        /* ||r|| / ||B|| of the iterate the last sweep started from */
+  double p_bnorm[16];       /* ||b||_2 of each corrector's pressure system (last step) */
 } dbso_info;
 
 /* Optional intermediate arrays of the first step (any pointer may be NULL).
@@ -84,6 +94,10 @@ typedef struct {
   double *HbyA;             /* first corrector, 3 x cells */
   double *phiHbyA;          /* first corrector, faces */
   double *b;                /* first corrector pressure right-hand side */
+  double *aP;               /* momentum diagonal per unit volume, cells */
+  double *aON, *aNO;        /* per face: coefficient of U_nbr in the owner's row and
+                               of U_own in the neighbour's row (0 on domain faces) */
+  double *B;                /* predictor right-hand side Shat + R(q), 3 x cells */
 } dbso_trace;
 
 /* Relative permeabilities, capillary pressure and dp_c/dalpha at one
@@ -109,6 +123,16 @@ int dbso_init_flux(const dbso_case *cs, const double *Ux, const double *Uy,
    (faces in the order of the side's face array).  Returns the face count, or
    -1 when b is not an inlet. */
 int dbso_inlet_values(const dbso_case *cs, int b, double t, double *out);
+
+/* Saturation transport alone (Eq. (phaseEq), the first stage of a step):
+   nsteps transport stages of cs->dt, each of cs->n_alpha_sub sub-cycles,
+   with the face fluxes F and p_rgh held fixed; alpha is advanced in place.
+   alphaPhi (faces, may be NULL) receives the last stage's mean limited flux
+   alpha_f F_f.  Boundary values are taken at t0 + (stage + 1) dt.  Returns 0
+   or -1 (bad input). */
+int dbso_alpha_advance(const dbso_case *cs, const double *phi, const double *kinv,
+                       double *alpha, const double *Fx, const double *Fy, const double *Fz,
+                       const double *p_rgh, int nsteps, double *alphaPhi);
 
 /* Advance nsteps PISO steps in place.  p (out) may be NULL.  Returns 0, or a
    negative code: -1 bad input, -4 pressure solve did not converge. */

@@ -5,9 +5,9 @@ and the CPU-baseline leg of ``bench.py``.  It never imports the HIP product
 package, and the product package never imports it.
 
 Cases are duck-typed objects with the attributes produced by the seeded input
-generators (shape, h, fluids, g, c_alpha, kr, pc, bc, dt, n_corr, mom_sweeps,
-transpose_visc, p_tol, p_maxit, phi, kinv).  State dicts hold flat float64
-arrays: alpha (nc), U (3, nc), p_rgh (nc), p (nc), F = (Fx, Fy, Fz).
+generators (shape, h, fluids, g, c_alpha, kr, pc, bc, dt, n_corr, mom_maxit,
+mom_tol, n_alpha_sub, transpose_visc, p_tol, p_maxit, phi, kinv).  State dicts
+hold flat float64 arrays: alpha (nc), U (3, nc), p_rgh (nc), p (nc), F = (Fx, Fy, Fz).
 """
 from __future__ import annotations
 
@@ -41,7 +41,7 @@ class OracleCase(C.Structure):
         ("bc_alpha", C.c_double * 6),
         ("bc_p", C.c_double * 6),
         ("dt", C.c_double),
-        ("n_corr", C.c_int), ("mom_sweeps", C.c_int), ("transpose_visc", C.c_int),
+        ("n_corr", C.c_int), ("mom_maxit", C.c_int), ("transpose_visc", C.c_int),
         ("mules_iter", C.c_int),
         ("p_tol", C.c_double), ("p_maxit", C.c_int),
         ("bc_wave", (C.c_double * 3) * 6),
@@ -49,6 +49,7 @@ class OracleCase(C.Structure):
         ("sigma", C.c_double),
         ("contact_angle", C.c_double),
         ("target_courant", C.c_double), ("dt_max", C.c_double),
+        ("mom_tol", C.c_double), ("n_alpha_sub", C.c_int),
     ]
 
 
@@ -59,6 +60,8 @@ class OracleInfo(C.Structure):
         ("alpha_min", C.c_double), ("alpha_max", C.c_double),
         ("phase_volume", C.c_double), ("max_div", C.c_double),
         ("dt_last", C.c_double), ("t_end", C.c_double),
+        ("mom_sweeps", C.c_int), ("mom_relres", C.c_double),
+        ("p_bnorm", C.c_double * 16),
     ]
 
 
@@ -68,7 +71,7 @@ _DP = C.POINTER(C.c_double)
 class OracleTrace(C.Structure):
     _fields_ = [(n, _DP) for n in (
         "A", "Rp", "Rm", "alphaPhi", "alpha_new", "rAU", "Shat", "Ustar",
-        "HbyA", "phiHbyA", "b")]
+        "HbyA", "phiHbyA", "b", "aP", "aON", "aNO", "B")]
 
 
 def build(force: bool = True) -> str:
@@ -103,6 +106,9 @@ def lib():
         L.dbso_step.argtypes = ([C.POINTER(OracleCase)] + [_DP] * 11 +
                                 [C.c_int, C.POINTER(OracleInfo), C.POINTER(OracleTrace)])
         L.dbso_step.restype = C.c_int
+        L.dbso_alpha_advance.argtypes = ([C.POINTER(OracleCase)] + [_DP] * 7 +
+                                         [C.c_int, _DP])
+        L.dbso_alpha_advance.restype = C.c_int
         L.dbso_curvature.argtypes = [C.POINTER(OracleCase)] + [_DP] * 6
         L.dbso_curvature.restype = C.c_int
         L.dbso_pressure_apply.argtypes = [C.POINTER(OracleCase), _DP, _DP, _DP]
@@ -155,7 +161,9 @@ def make_case(cs) -> OracleCase:
     o.dt_max = float(getattr(cs, "dt_max", 0.0))
     o.dt = cs.dt
     o.n_corr = cs.n_corr
-    o.mom_sweeps = cs.mom_sweeps
+    o.mom_maxit = int(cs.mom_maxit)
+    o.mom_tol = float(cs.mom_tol)
+    o.n_alpha_sub = int(getattr(cs, "n_alpha_sub", 1))
     o.transpose_visc = int(cs.transpose_visc)
     o.mules_iter = int(cs.mules_iter)
     o.p_tol = cs.p_tol
@@ -255,7 +263,8 @@ def step(cs, state: dict, nsteps: int, trace: bool = False, check: bool = True):
         tr = OracleTrace()
         sizes = {"A": sum(nf), "Rp": nc, "Rm": nc, "alphaPhi": sum(nf), "alpha_new": nc,
                  "rAU": nc, "Shat": 3 * nc, "Ustar": 3 * nc, "HbyA": 3 * nc,
-                 "phiHbyA": sum(nf), "b": nc}
+                 "phiHbyA": sum(nf), "b": nc, "aP": nc, "aON": sum(nf), "aNO": sum(nf),
+                 "B": 3 * nc}
         for k, n in sizes.items():
             tarr[k] = np.zeros(n)
             setattr(tr, k, _ptr(tarr[k]))
@@ -272,10 +281,33 @@ def step(cs, state: dict, nsteps: int, trace: bool = False, check: bool = True):
         "alpha_min": info.alpha_min, "alpha_max": info.alpha_max,
         "phase_volume": info.phase_volume, "max_div": info.max_div,
         "dt_last": info.dt_last,
+        "mom_sweeps": info.mom_sweeps, "mom_relres": info.mom_relres,
+        "p_bnorm": list(info.p_bnorm)[: cs.n_corr],
     }
     if trace:
         return out, inf, tarr
     return out, inf
+
+
+def alpha_advance(cs, alpha, F, p_rgh=None, nsteps=1, t0=None):
+    """Saturation transport alone: nsteps stages of cs.dt (each in
+    cs.n_alpha_sub sub-cycles) with F and p_rgh fixed.  Returns (alpha, mean
+    limited flux of the last stage as a concatenated x|y|z face array)."""
+    o = make_case(cs)
+    if t0 is not None:
+        o.t0 = float(t0)
+    nc = int(np.prod(cs.shape))
+    phi = np.ascontiguousarray(cs.phi, dtype=np.float64).reshape(nc)
+    kinv = np.ascontiguousarray(cs.kinv, dtype=np.float64).reshape(nc)
+    a = np.ascontiguousarray(alpha, dtype=np.float64).reshape(nc).copy()
+    F = [np.ascontiguousarray(f, dtype=np.float64) for f in F]
+    pr = np.zeros(nc) if p_rgh is None else np.ascontiguousarray(p_rgh, dtype=np.float64).reshape(nc)
+    aphi = np.zeros(sum(nfaces(cs.shape)))
+    rc = lib().dbso_alpha_advance(C.byref(o), _ptr(phi), _ptr(kinv), _ptr(a), *[_ptr(f) for f in F],
+                                  _ptr(pr), int(nsteps), _ptr(aphi))
+    if rc:
+        raise ValueError(f"dbso_alpha_advance failed ({rc})")
+    return a, aphi
 
 
 def pressure_apply(cs, rAU: np.ndarray, x: np.ndarray) -> np.ndarray:

@@ -76,7 +76,9 @@ class Case:
     pc: dict = field(default_factory=lambda: {"model": "brooks_corey", "pc0": 1e3, "exp": 0.5})
     dt: float = 1e-5
     n_corr: int = 2
-    mom_sweeps: int = 3
+    mom_maxit: int = 100        # sweep cap of the momentum predictor solve
+    mom_tol: float = 1e-14      # predictor: ||B + N U - D U|| <= mom_tol ||B||
+    n_alpha_sub: int = 1        # saturation sub-cycles per step
     transpose_visc: bool = True
     mules_iter: int = 3
     p_tol: float = 1e-13
