@@ -211,7 +211,7 @@ def batch_leg(args):
 
     log(f"generating {args.batch_samples} samples")
     cases = W.batch_cases(n_samples=args.batch_samples, seed=6, lo=32, hi=96, p_tol=args.p_tol)
-    cases = [c.replace(p_maxit=500) for c in cases]
+    cases = [c.replace(p_maxit=500, mom_tol=args.mom_tol) for c in cases]
     cells = sum(c.ncells for c in cases)
     out = {"workload": f"batch{len(cases)}_edges32to96", "samples": len(cases), "cells": cells,
            "p_tol": args.p_tol}
@@ -242,7 +242,8 @@ def flume_leg(args):
     from paper_2003_08374_amd import workloads as W
 
     log("generating the flume batch")
-    cases = [c.replace(p_maxit=500) for c in W.flume_batch(n=16, seed=7, p_tol=args.p_tol)]
+    cases = [c.replace(p_maxit=500, mom_tol=args.mom_tol)
+             for c in W.flume_batch(n=16, seed=7, p_tol=args.p_tol)]
     cells = sum(c.ncells for c in cases)
     rm = time_solver(cases, "mixed", args.steps, args.warmup, tune=True)
     rg = time_solver(cases, "mixed", args.steps, args.warmup, graph=True, tune=True)
@@ -278,7 +279,8 @@ def reservoir_leg(args):
     mixed precision, eagerly: a 2D, Darcy-dominated pressure system."""
     from paper_2003_08374_amd import workloads as W
 
-    cs = W.reservoir_2d(nx=2000, ny=800, dt=0.5).replace(p_tol=args.p_tol, p_maxit=500)
+    cs = W.reservoir_2d(nx=2000, ny=800, dt=0.5).replace(p_tol=args.p_tol, p_maxit=500,
+                                                          mom_tol=args.mom_tol)
     r = time_solver(cs, "mixed", args.steps, args.warmup)
     return {"workload": cs.name, "cells": cs.ncells, "p_tol": args.p_tol,
             "value": cs.ncells / (r["sec"] / args.steps),
@@ -293,6 +295,8 @@ def main():
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
     ap.add_argument("--p-tol", type=float, default=1e-8)
+    ap.add_argument("--mom-tol", type=float, default=1e-8,
+                    help="momentum predictor tolerance (relative residual)")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 leg")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--kernel", default=None, help="kernel class for the roofline")
@@ -334,7 +338,7 @@ def main():
 
     case = W.fractured_3d(n=args.n, seed_k=3, seed_phi=4, fractures="planes", frac_seed=5,
                           n_frac=3, name=f"fractured_3d_{args.n}_planes")
-    case = case.replace(p_tol=args.p_tol, p_maxit=500)
+    case = case.replace(p_tol=args.p_tol, p_maxit=500, mom_tol=args.mom_tol)
     cells = case.ncells
 
     knobs = {"kz": 0, "sweeps": 2, "coarse_sweeps": args.coarse_sweeps, "bottom_shift": 0,

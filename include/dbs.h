@@ -106,7 +106,7 @@ typedef struct {
 typedef struct {
   double dt;            /* time step [s] */
   int n_corr;           /* PISO correctors (>= 1, the paper uses >= 2) */
-  int mom_sweeps;       /* Jacobi sweeps of the momentum predictor */
+  int mom_maxit;        /* sweep cap of the momentum predictor solve (0: U* = U^n) */
   int transpose_visc;   /* 1: add div(mu grad(U)^T) explicitly */
   int mules_iter;       /* MULES limiter iterations (>= 1) */
   double p_tol;         /* pressure solve: ||b - A x||_2 <= p_tol ||b||_2 */
@@ -122,6 +122,16 @@ typedef struct {
                            steps in lockstep with the smallest dt of its samples.
                            Not available in graph mode (DBS_EINVAL). */
   double dt_max;        /* cap of the adaptive time step (> 0 when adaptive) */
+  double mom_tol;       /* momentum predictor (Sec. 3.2, Eq. (semi_discretised_bis), solved
+                           implicitly): Jacobi sweeps from U^n, each forming the residual
+                           B + sum a_N U_N - a_P U of the iterate it starts from; the solve
+                           ends after the first sweep whose starting residual is at most
+                           mom_tol ||B||_2 (three components), or after mom_maxit sweeps.
+                           0: always mom_maxit sweeps. */
+  int n_alpha_sub;      /* saturation sub-cycles per step (>= 1): the transport stage runs
+                           n times with dt/n, F and p_rgh of the step start held fixed and
+                           the closures following the current saturation; the momentum
+                           equation takes the mean of the n limited fluxes. */
 } dbs_controls;
 
 typedef struct {
@@ -134,6 +144,14 @@ typedef struct {
   double max_courant;   /* at the start of the last step */
   double time;          /* time reached (the sum of the steps from dbs_set_time's value) */
   double dt;            /* time step of the last step */
+  int mom_sweeps;       /* momentum predictor sweeps of the last step */
+  double mom_relres;    /* ||r|| / ||B|| of the iterate the last predictor sweep started from */
+  double p_bnorm[16];   /* ||b||_2 of each corrector's pressure system (closed domains:
+                           of the mean-free b) */
+  double p_res0[16];    /* relative residual of each corrector's initial guess */
+  double max_div;       /* max over cells of |sum_out F_f| after the last step (the
+                           discrete divergence; at most p_tol p_bnorm[n_corr - 1] when the
+                           last solve converged) */
 } dbs_stats;
 
 typedef struct dbs_handle dbs_handle;
@@ -227,15 +245,16 @@ int dbs_batch_get_stats(dbs_handle *h, int i, dbs_stats *out);
 int dbs_batch_step(dbs_handle *h, int nsteps);
 
 /* Graph mode (on != 0): each step is replayed from a captured HIP graph.
-   The first step after switching runs eagerly and sets a PCG iteration
-   budget per corrector (the largest count over the samples plus a margin);
-   the captured step runs exactly that many iterations with converged
-   samples masked and no host synchronisation inside.  If a sample has not
-   converged within the budget, the step is redone eagerly from a saved copy
-   of the state and the budget grows, so results equal eager stepping.  The
-   saved state costs 5 cell arrays and one face array of device memory.
-   on > 1 starts from a budget of on - 1 iterations instead of measuring it
-   (this exercises the recovery path when the budget is too small). */
+   The first step after switching runs eagerly and sets a budget of
+   momentum predictor sweeps and of PCG iterations per corrector (the
+   largest counts over the samples plus a margin); the captured step runs
+   exactly that many with converged samples masked and no host
+   synchronisation inside.  If a sample has not converged within a budget,
+   the step is redone eagerly from a saved copy of the state and the
+   budgets grow, so results equal eager stepping.  The saved state costs 5
+   cell arrays and one face array of device memory.  on > 1 starts from
+   budgets of on - 1 instead of measuring them (this exercises the recovery
+   path when a budget is too small). */
 int dbs_set_graph(dbs_handle *h, int on);
 
 /* Autotuner: times the pressure solve of the current state's first
@@ -249,9 +268,13 @@ int dbs_set_graph(dbs_handle *h, int on);
    may be NULL; *ms receives the best solve time in milliseconds. */
 int dbs_autotune(dbs_handle *h, int *kz, int *sweeps, int *coarse_sweeps, int *bottom_shift,
                  int *fused, double *ms);
-/* Set the same knobs by hand (kz = 0: the launch-size heuristic). */
-int dbs_set_tuning(dbs_handle *h, int kz, int sweeps, int coarse_sweeps, int bottom_shift,
-                   int fused);
+/* Set the same knobs by hand (kz = 0: the launch-size heuristic), and the
+   planes per coarse-level tile or thread column kz_coarse (0: the launch-size
+   heuristic, which keeps enough blocks to fill the chip; the autotuner leaves
+   it as set).  kz and kz_coarse in [0, 64], sweeps and coarse_sweeps in
+   [1, 8], bottom_shift in [0, 4]; else DBS_EINVAL. */
+int dbs_set_tuning(dbs_handle *h, int kz, int kz_coarse, int sweeps, int coarse_sweeps,
+                   int bottom_shift, int fused);
 
 /* Tests only (single-sample handles).  Solve the p_rgh pressure equation of
    this handle's mesh and boundary conditions, -div(rAU_f grad x) with outlet faces as Dirichlet
@@ -264,9 +287,13 @@ int dbs_debug_pressure_solve(dbs_handle *h, const double *rAU, const double *b, 
    (any pointer may be NULL): the MULES antidiffusive flux A (faces), 1/a_P
    (cells), momentum source Shat and predicted U (3 x cells), and from the
    first corrector HbyA (3 x cells), phiHbyA (faces) and the pressure
-   right-hand side b (cells). */
+   right-hand side b (cells); from the saturation stage (its last sub-cycle)
+   the Zalesak cell factors R+ and R- of the last limiter iteration (cells)
+   and the limited flux alpha_f F_f (faces; with sub-cycles the mean the
+   momentum equation receives). */
 int dbs_debug_step_trace(dbs_handle *h, double *A, double *rAU, double *Shat, double *Ustar,
-                         double *HbyA, double *phiHbyA, double *b);
+                         double *HbyA, double *phiHbyA, double *b, double *Rp, double *Rm,
+                         double *alphaPhi);
 
 #ifdef __cplusplus
 }

@@ -64,89 +64,82 @@ void prof_collect(Handle *h) {
 
 // ------------------------------------------------------------- statistics
 
-// per block: min alpha, max alpha, sum phi alpha V, max Courant, non-finite count
+// Per block: min alpha, max alpha, sum phi alpha V, max Courant number,
+// non-finite count and max |sum_out F| (the discrete divergence).  Slots
+// combine by min, max, sum, max, sum, max.
+__device__ __forceinline__ double stat_comb(int q, double a, double b) {
+  return q == 0 ? fmin(a, b) : (q == 2 || q == 4) ? a + b : fmax(a, b);
+}
+__device__ __forceinline__ double stat_wave(int q, double v) {
+  return q == 0 ? wave_min(v) : (q == 2 || q == 4) ? wave_sum(v) : wave_max(v);
+}
+
 __global__ void __launch_bounds__(NTHREADS) k_stats(Segs SG, const double *__restrict__ alpha,
                                                     const double *__restrict__ U,
                                                     const double *__restrict__ prgh,
                                                     const double *__restrict__ phi,
                                                     const double *__restrict__ F,
                                                     double *__restrict__ part, int nb) {
-  __shared__ double lds[5][NTHREADS / 64];
-  double amin = 1e300, amax = -1e300, vol = 0.0, co = 0.0, bad = 0.0;
+  __shared__ double lds[NSTAT][NTHREADS / 64];
+  double r[NSTAT] = {1e300, -1e300, 0.0, 0.0, 0.0, 0.0};
   FOR_CELLS(SG, G, P) {
     const double a = alpha[P.c];
-    amin = fmin(amin, a);
-    amax = fmax(amax, a);
-    vol += phi[P.c] * a * G.V;
-    double out = 0.0;
+    r[0] = fmin(r[0], a);
+    r[1] = fmax(r[1], a);
+    r[2] += phi[P.c] * a * G.V;
+    double out = 0.0, div = 0.0;
     for (int ax = 0; ax < 3; ax++) {
       const double fm = F[face_of(G, P, ax, 0)], fp = F[face_of(G, P, ax, 1)];
       out += fmax(fp, 0.0) + fmax(-fm, 0.0);
+      div += fp - fm;
     }
-    co = fmax(co, G.dt * out / (phi[P.c] * G.V));
+    r[3] = fmax(r[3], G.dt * out / (phi[P.c] * G.V));
     bool ok = isfinite(a) && isfinite(prgh[P.c]);
     for (int d = 0; d < 3; d++) ok = ok && isfinite(U[(size_t)d * G.vs + P.c]);
-    bad += ok ? 0.0 : 1.0;
+    r[4] += ok ? 0.0 : 1.0;
+    r[5] = fmax(r[5], fabs(div));
   }
-  amin = wave_min(amin);
-  amax = wave_max(amax);
-  vol = wave_sum(vol);
-  co = wave_max(co);
-  bad = wave_sum(bad);
   const int t = threadIdx.x + BX * threadIdx.y;
-  if ((t & 63) == 0) {
-    lds[0][t >> 6] = amin; lds[1][t >> 6] = amax; lds[2][t >> 6] = vol;
-    lds[3][t >> 6] = co;   lds[4][t >> 6] = bad;
+#pragma unroll
+  for (int q = 0; q < NSTAT; q++) {
+    const double v = stat_wave(q, r[q]);
+    if ((t & 63) == 0) lds[q][t >> 6] = v;
   }
   __syncthreads();
   if (t == 0) {
-    double r[5] = {1e300, -1e300, 0.0, 0.0, 0.0};
-    for (int w = 0; w < NTHREADS / 64; w++) {
-      r[0] = fmin(r[0], lds[0][w]); r[1] = fmax(r[1], lds[1][w]); r[2] += lds[2][w];
-      r[3] = fmax(r[3], lds[3][w]); r[4] += lds[4][w];
+#pragma unroll
+    for (int q = 0; q < NSTAT; q++) {
+      double v = lds[q][0];
+      for (int w = 1; w < NTHREADS / 64; w++) v = stat_comb(q, v, lds[q][w]);
+      part[q * nb + cell_gb] = v;
     }
-    for (int q = 0; q < 5; q++) part[q * nb + cell_gb] = r[q];
   }
 }
 
-// one block per sample: reduce the sample's block partials (four per
-// thread and loop trip, so that many loads are in flight)
+// one block per sample: reduce the sample's block partials into `out`
+// (host-mapped memory), NSTAT values per sample
 __global__ void __launch_bounds__(1024) k_stats_final(const double *__restrict__ part, int nb,
                                                       const int *__restrict__ bp,
                                                       double *__restrict__ out) {
-  __shared__ double lds[5][16];
+  __shared__ double lds[NSTAT][16];
   const int t = threadIdx.x, s = blockIdx.x;
-  double r[5] = {1e300, -1e300, 0.0, 0.0, 0.0};
-  const int b0 = bp[s], b1 = bp[s + 1];
-  int i = b0 + t;
-  for (; i + 3 * 1024 < b1; i += 4 * 1024) {
-    double v[4][5];
+  double r[NSTAT] = {1e300, -1e300, 0.0, 0.0, 0.0, 0.0};
+  for (int i = bp[s] + t; i < bp[s + 1]; i += 1024)
 #pragma unroll
-    for (int u = 0; u < 4; u++)
+    for (int q = 0; q < NSTAT; q++) r[q] = stat_comb(q, r[q], part[q * nb + i]);
 #pragma unroll
-      for (int q = 0; q < 5; q++) v[u][q] = part[q * nb + i + u * 1024];
-#pragma unroll
-    for (int u = 0; u < 4; u++) {
-      r[0] = fmin(r[0], v[u][0]); r[1] = fmax(r[1], v[u][1]); r[2] += v[u][2];
-      r[3] = fmax(r[3], v[u][3]); r[4] += v[u][4];
-    }
+  for (int q = 0; q < NSTAT; q++) {
+    const double v = stat_wave(q, r[q]);
+    if ((t & 63) == 0) lds[q][t >> 6] = v;
   }
-  for (; i < b1; i += 1024) {
-    r[0] = fmin(r[0], part[i]); r[1] = fmax(r[1], part[nb + i]); r[2] += part[2 * nb + i];
-    r[3] = fmax(r[3], part[3 * nb + i]); r[4] += part[4 * nb + i];
-  }
-  r[0] = wave_min(r[0]); r[1] = wave_max(r[1]); r[2] = wave_sum(r[2]);
-  r[3] = wave_max(r[3]); r[4] = wave_sum(r[4]);
-  if ((t & 63) == 0)
-    for (int q = 0; q < 5; q++) lds[q][t >> 6] = r[q];
   __syncthreads();
   if (t == 0) {
-    double v[5] = {1e300, -1e300, 0.0, 0.0, 0.0};
-    for (int w = 0; w < 16; w++) {
-      v[0] = fmin(v[0], lds[0][w]); v[1] = fmax(v[1], lds[1][w]); v[2] += lds[2][w];
-      v[3] = fmax(v[3], lds[3][w]); v[4] += lds[4][w];
+#pragma unroll
+    for (int q = 0; q < NSTAT; q++) {
+      double v = lds[q][0];
+      for (int w = 1; w < 16; w++) v = stat_comb(q, v, lds[q][w]);
+      out[s * NSTAT + q] = v;
     }
-    for (int q = 0; q < 5; q++) out[s * 5 + q] = v[q];
   }
 }
 
@@ -209,9 +202,7 @@ void cell_stats(Handle *h) {
              (const double *)h->U, (const double *)h->prgh, (const double *)h->phi,
              (const double *)h->F, h->partials, nb);
   DBS_LAUNCH(h, KC_STATS, k_stats_final, dim3(h->ns), dim3(1024), (const double *)h->partials,
-             nb, (const int *)h->cell.bp, h->sstat);
-  hipMemcpyAsync(h->hsstat, h->sstat, 5 * sizeof(double) * h->ns, hipMemcpyDeviceToHost,
-                 h->stream);
+             nb, (const int *)h->cell.bp, h->dsstat_h);
   hipStreamSynchronize(h->stream);
 }
 
@@ -245,6 +236,22 @@ static double *dmalloc(Handle *h, size_t n, int &rc) {
   return (double *)dmalloc_bytes(h, n * sizeof(double), rc);
 }
 
+// pinned host memory that kernels write directly (mapped, coherent): small
+// per-sample flags and records the host reads after an event or a sync
+static void *hmap(Handle *h, size_t bytes, void **dev, int &rc) {
+  void *p = nullptr;
+  if (rc) return nullptr;
+  if (hipHostMalloc(&p, bytes ? bytes : 8, hipHostMallocMapped | hipHostMallocCoherent) !=
+      hipSuccess) {
+    rc = DBS_ENOMEM;
+    return nullptr;
+  }
+  memset(p, 0, bytes ? bytes : 8);
+  h->hallocs.push_back(p);
+  if (hipHostGetDevicePointer(dev, p, 0) != hipSuccess) rc = DBS_EHIP;
+  return p;
+}
+
 static bool all_finite(const double *a, size_t n) {
   for (size_t i = 0; i < n; i++)
     if (!isfinite(a[i])) return false;
@@ -264,7 +271,8 @@ static int validate_shared(const dbs_physics *p, const dbs_controls *c, std::str
   if (!(p->sigma >= 0.0 && p->sigma < HUGE_VAL)) { msg = "sigma"; return DBS_EINVAL; }
   if (!(p->contact_angle >= 0.0 && p->contact_angle < M_PI)) { msg = "contact_angle"; return DBS_EINVAL; }
   if (c->target_courant > 0.0 && !(c->dt_max > 0.0)) { msg = "dt_max"; return DBS_EINVAL; }
-  if (!(c->dt > 0.0) || c->n_corr < 1 || c->n_corr > 16 || c->mom_sweeps < 0 ||
+  if (!(c->dt > 0.0) || c->n_corr < 1 || c->n_corr > 16 || c->mom_maxit < 0 ||
+      !(c->mom_tol >= 0.0) || c->n_alpha_sub < 1 || c->n_alpha_sub > 64 ||
       c->mules_iter < 1 || !(c->p_tol > 0.0) || c->p_maxit < 1 ||
       (c->precision != DBS_FP64 && c->precision != DBS_MIXED) || c->mg_pre < 0 || c->mg_post < 0) {
     msg = "bad controls";
@@ -475,6 +483,7 @@ static int create_impl(int n, const dbs_grid *grids, const dbs_physics *phys, co
   h->cgrid = dim3(h->cell.nblk);
   h->phi = dmalloc(h, NC, rc); h->kinv = dmalloc(h, NC, rc);
   h->alpha = dmalloc(h, NC, rc); h->alpha_old = dmalloc(h, NC, rc);
+  if (ctl->n_alpha_sub > 1) h->alpha3 = dmalloc(h, NC, rc);
   h->U = dmalloc(h, 3 * NC, rc); h->U2 = dmalloc(h, 3 * NC, rc);
   h->prgh = dmalloc(h, NC, rc); h->p = dmalloc(h, NC, rc);
   h->F = dmalloc(h, NF, rc);
@@ -490,13 +499,16 @@ static int create_impl(int n, const dbs_grid *grids, const dbs_physics *phys, co
   h->r = dmalloc(h, NC, rc); h->z = dmalloc(h, NC, rc); h->pv = dmalloc(h, NC, rc);
   h->q = dmalloc(h, NC, rc); h->pv2 = dmalloc(h, NC, rc);
   h->scal = dmalloc(h, (size_t)NSC * n, rc);
-  h->sstat = dmalloc(h, 5 * (size_t)n, rc);
-  h->rec = dmalloc(h, (size_t)n * 16 * 3, rc);
-  if (!rc && (hipHostMalloc((void **)&h->hscal, sizeof(double) * NSC * n, hipHostMallocDefault) != hipSuccess ||
-              hipHostMalloc((void **)&h->hflags, sizeof(int) * 2 * n, hipHostMallocDefault) != hipSuccess ||
-              hipHostMalloc((void **)&h->hsstat, sizeof(double) * 5 * n, hipHostMallocDefault) != hipSuccess ||
-              hipHostMalloc((void **)&h->hrec, sizeof(double) * 48 * n, hipHostMallocDefault) != hipSuccess))
-    rc = DBS_ENOMEM;
+  h->msc = dmalloc(h, (size_t)NMSC * n, rc);
+  h->mact = (int *)dmalloc_bytes(h, sizeof(int) * n, rc);
+  h->hscal = (double *)hmap(h, sizeof(double) * NSC * n, (void **)&h->dscal_h, rc);
+  h->hpub = (int *)hmap(h, sizeof(int) * 2 * n, (void **)&h->dpub, rc);
+  h->hmsc = (double *)hmap(h, sizeof(double) * NMSC * n, (void **)&h->dmsc, rc);
+  h->hmflag = (int *)hmap(h, sizeof(int) * 2 * n, (void **)&h->dmflag, rc);
+  h->hsstat = (double *)hmap(h, sizeof(double) * NSTAT * n, (void **)&h->dsstat_h, rc);
+  h->hrec = (double *)hmap(h, sizeof(double) * 16 * NREC * n, (void **)&h->rec, rc);
+  for (int e = 0; e < 2 && !rc; e++)
+    rc = hip_check(h, hipEventCreateWithFlags(&h->mom_ev[e], hipEventDisableTiming), "event");
   if (!rc) rc = pressure_setup(h);
   if (!rc) rc = hip_check(h, hipDeviceSynchronize(), "create");
   if (rc) {
@@ -521,6 +533,10 @@ static int set_static_impl(Handle *h, int i, const double *phi, const double *ki
   for (size_t c = 0; c < nc; c++) {
     if (!(phi[c] > 0.0 && phi[c] <= 1.0)) return fail(h, DBS_EINVAL, "porosity outside (0,1]");
     if (!(kinv[c] >= 0.0) || !isfinite(kinv[c])) return fail(h, DBS_EINVAL, "bad k^-1");
+    // a solid-free cell (phi = 1) has no Darcy drag: k^-1 > 0 there contradicts
+    // the porosity field (Sec. 2.2: k tends to infinity as phi tends to 1)
+    if (phi[c] == 1.0 && kinv[c] > 0.0)
+      return fail(h, DBS_EINVAL, "phi = 1 (solid-free) with k^-1 > 0");
   }
   int rc = hip_check(h, hipMemcpyAsync(h->phi + G.c0, phi, nc * 8, hipMemcpyHostToDevice, h->stream), "copy phi");
   if (!rc) rc = hip_check(h, hipMemcpyAsync(h->kinv + G.c0, kinv, nc * 8, hipMemcpyHostToDevice, h->stream), "copy kinv");
@@ -568,7 +584,7 @@ static int get_state_impl(Handle *h, int i, double *alpha, double *U, double *pr
 // ----------------------------------------------------------------- stepping
 
 struct TraceOut {
-  double *A, *rAU, *Shat, *Ustar, *HbyA, *phiHbyA, *b;
+  double *A, *rAU, *Shat, *Ustar, *HbyA, *phiHbyA, *b, *Rp, *Rm, *alphaPhi;
 };
 
 static int copy_out(Handle *h, double *dst, const double *src, size_t n) {
@@ -592,7 +608,7 @@ static void adapt_dt(Handle *h) {
   if (!(h->ctl.target_courant > 0.0)) return;
   cell_stats(h);
   double co = 0.0;
-  for (int s = 0; s < h->ns; s++) co = std::max(co, h->hsstat[5 * s + 3]);
+  for (int s = 0; s < h->ns; s++) co = std::max(co, h->hsstat[NSTAT * s + 3]);
   double dt = std::min(h->ctl.dt_max, 1.2 * h->ctl.dt);
   if (co > 0.0) dt = std::min(dt, h->ctl.target_courant * h->ctl.dt / co);
   h->ctl.dt = dt;
@@ -604,7 +620,7 @@ static int courant_check(Handle *h) {
   if (!(h->ctl.max_courant > 0.0)) return DBS_OK;
   cell_stats(h);
   for (int s = 0; s < h->ns; s++) {
-    const double co = h->hsstat[5 * s + 3];
+    const double co = h->hsstat[NSTAT * s + 3];
     h->st[s].max_courant = co;
     if (co > h->ctl.max_courant)
       return fail(h, DBS_ECOURANT, "Courant number " + std::to_string(co) +
@@ -613,16 +629,25 @@ static int courant_check(Handle *h) {
   return DBS_OK;
 }
 
-// The step body.  budget > 0: every pressure solve runs the per-corrector
-// iteration budget with no host synchronisation (graph capture) and its
-// per-sample results go to h->rec; else results go to the statistics and
-// the largest iteration count per corrector to its_out.
-static int step_body(Handle *h, TraceOut *tr, int budget, std::vector<int> *its_out) {
+// The step body.  budget > 0: the predictor runs h->mom_budget sweeps and
+// every pressure solve the per-corrector iteration budget, with no host
+// synchronisation (graph capture); per-sample results go to h->rec and the
+// host-mapped predictor records.  Else results go to the statistics, the
+// largest iteration count per corrector to its_out and the largest
+// predictor sweep count to *sweeps_out.
+static int step_body(Handle *h, TraceOut *tr, int budget, std::vector<int> *its_out,
+                     int *sweeps_out = nullptr) {
   int rc = DBS_OK;
   add_time(h, h->ctl.dt);  // boundary values of this step are taken at its end
-  alpha_stage(h);
-  if (tr) rc |= copy_out(h, tr->A, h->A, h->hG[0].nf);
-  momentum_predictor(h);
+  // the trace's limited flux borrows phiH, which the correctors fill later
+  alpha_stage(h, tr && tr->alphaPhi ? h->phiH : nullptr);
+  if (tr) {
+    rc |= copy_out(h, tr->A, h->A, h->hG[0].nf);
+    rc |= copy_out(h, tr->Rp, h->Rp, h->hG[0].nc);
+    rc |= copy_out(h, tr->Rm, h->Rm, h->hG[0].nc);
+    rc |= copy_out(h, tr->alphaPhi, h->phiH, h->hG[0].nf);
+  }
+  momentum_predictor(h, budget > 0 ? h->mom_budget : 0);
   if (tr) {
     rc |= copy_out(h, tr->rAU, h->rAU, h->hG[0].nc);
     rc |= copy_out3(h, tr->Shat, h->Sh);
@@ -643,14 +668,30 @@ static int step_body(Handle *h, TraceOut *tr, int budget, std::vector<int> *its_
     if (budget > 0) {
       pressure_record(h, h->rec, c);
     } else {
+      std::vector<double> bn(h->ns), r0(h->ns);
+      pressure_norms(h, bn.data(), r0.data());
       for (int s = 0; s < h->ns; s++) {
         h->st[s].p_iters[c] = its[s];
         h->st[s].p_relres[c] = rel[s];
+        h->st[s].p_bnorm[c] = bn[s];
+        h->st[s].p_res0[c] = r0[s];
         if (its_out) (*its_out)[c] = std::max((*its_out)[c], its[s]);
       }
     }
     if (src) solve_rc = src;
     corrector_update(h, c == h->ctl.n_corr - 1);
+  }
+  if (budget <= 0) {
+    // the pressure solves synchronised the stream: the predictor records
+    // in host-mapped memory are final
+    std::vector<int> sw(h->ns);
+    std::vector<double> mr(h->ns);
+    momentum_results(h, sw.data(), mr.data(), nullptr);
+    for (int s = 0; s < h->ns; s++) {
+      h->st[s].mom_sweeps = sw[s];
+      h->st[s].mom_relres = mr[s];
+      if (sweeps_out) *sweeps_out = std::max(*sweeps_out, sw[s]);
+    }
   }
   if (rc) return fail(h, DBS_EHIP, "trace copy failed");
   if (solve_rc) return fail(h, solve_rc, "pressure solve did not converge");
@@ -680,32 +721,57 @@ static void snapshot(Handle *h, bool save) {
   mv(h->F, S + 5 * NC, (size_t)h->NF);
 }
 
-// the host side of a step swaps buffer roles: alpha once, U once per sweep
-static void swap_roles(Handle *h) {
-  std::swap(h->alpha, h->alpha_old);
-  if (h->ctl.mom_sweeps & 1) std::swap(h->U, h->U2);
+// buffer roles of the state (the host side of a step permutes them)
+struct Roles {
+  double *alpha, *alpha_old, *alpha3, *U, *U2;
+};
+static Roles roles(const Handle *h) { return Roles{h->alpha, h->alpha_old, h->alpha3, h->U, h->U2}; }
+static void set_roles(Handle *h, const Roles &r) {
+  h->alpha = r.alpha;
+  h->alpha_old = r.alpha_old;
+  h->alpha3 = r.alpha3;
+  h->U = r.U;
+  h->U2 = r.U2;
+}
+
+// the roles a captured step leaves: the saturation stage's permutation, and
+// the predictor's result in buffer (budget % 2) of {U, U2}
+static void replay_roles(Handle *h) {
+  alpha_roles(h);
+  if (h->mom_budget & 1) std::swap(h->U, h->U2);
 }
 
 // One step in graph mode: the step is captured once per buffer-role
-// combination with a fixed PCG budget per corrector, then replayed.  A
-// sample that does not converge within the budget makes the step run again
-// eagerly from the saved state, and the budget grows.
+// combination with a fixed predictor sweep budget and a fixed PCG budget per
+// corrector, then replayed.  A sample that does not converge within a
+// budget makes the step run again eagerly from the saved state, and the
+// budgets grow.
 static int graph_step(Handle *h) {
   int rc = courant_check(h);
   if (rc) return rc;
   const int nc = h->ctl.n_corr;
+  auto set_budgets = [&](const std::vector<int> &its, int sweeps, bool grow) {
+    for (int c = 0; c < nc; c++) {
+      const int want = its[c] + std::max(2, its[c] / 4);
+      h->graph_budget[c] = grow ? std::max(h->graph_budget[c] + 2, want) : want;
+    }
+    const int mw = std::min(h->ctl.mom_maxit, sweeps + 1);
+    h->mom_budget = grow ? std::min(h->ctl.mom_maxit, std::max(h->mom_budget + 1, mw)) : mw;
+  };
   if (h->graph_budget[0] == 0) {
     std::vector<int> its(nc, 0);
-    rc = step_body(h, nullptr, 0, &its);
+    int sweeps = 0;
+    rc = step_body(h, nullptr, 0, &its, &sweeps);
     for (int s = 0; s < h->ns; s++) h->st[s].steps++;
     if (rc) return rc;
-    for (int c = 0; c < nc; c++) h->graph_budget[c] = its[c] + std::max(2, its[c] / 4);
+    set_budgets(its, sweeps, false);
     return DBS_OK;
   }
   if (!h->snap) {
     h->snap = dmalloc(h, 5 * (size_t)h->NC + (size_t)h->NF, rc);
     if (rc) return fail(h, rc, "snapshot allocation");
   }
+  const Roles before = roles(h);
   const GraphKey key{h->alpha, h->U};
   auto it = h->graphs.find(key);
   if (it == h->graphs.end()) {
@@ -725,40 +791,53 @@ static int graph_step(Handle *h) {
     hipGraphDestroy(g);
     if (rc) return rc;
     it = h->graphs.emplace(key, ex).first;
-    // capturing ran the host side of the step: the roles are already swapped
+    // capturing ran the host side of the step: the roles are already set
     // and the host time moved
   } else {
-    swap_roles(h);
+    replay_roles(h);
     h->tnow += h->ctl.dt;
   }
   rc = hip_check(h, hipGraphLaunch(it->second, h->stream), "graph launch");
-  if (rc) return rc;
-  rc = hip_check(h, hipMemcpyAsync(h->hrec, h->rec, sizeof(double) * 48 * h->ns,
-                                   hipMemcpyDeviceToHost, h->stream), "records");
   if (!rc) rc = hip_check(h, hipStreamSynchronize(h->stream), "graph step");
   if (rc) return rc;
+  // the records were written to host-mapped memory by the replayed kernels
   bool ok = true;
-  for (int s = 0; s < h->ns; s++)
+  const int ns = h->ns;
+  const int slot = (h->mom_budget - 1) & 1;
+  for (int s = 0; s < ns; s++) {
     for (int c = 0; c < nc; c++) {
-      const double *o = h->hrec + ((size_t)s * 16 + c) * 3;
+      const double *o = h->hrec + ((size_t)s * 16 + c) * NREC;
       h->st[s].p_iters[c] = (int)o[0];
       h->st[s].p_relres[c] = o[1];
+      h->st[s].p_bnorm[c] = o[3];
+      h->st[s].p_res0[c] = o[4];
       ok = ok && o[2] != 0.0;
     }
+    if (h->ctl.mom_maxit > 0) ok = ok && h->hmflag[slot * ns + s] == 0;
+  }
+  {
+    std::vector<int> sw(ns);
+    std::vector<double> mr(ns);
+    momentum_results(h, sw.data(), mr.data(), nullptr);
+    for (int s = 0; s < ns; s++) {
+      h->st[s].mom_sweeps = sw[s];
+      h->st[s].mom_relres = mr[s];
+    }
+  }
   if (ok) {
-    for (int s = 0; s < h->ns; s++) h->st[s].steps++;
+    for (int s = 0; s < ns; s++) h->st[s].steps++;
     return DBS_OK;
   }
-  // redo eagerly from the saved state with the budget raised
-  swap_roles(h);
+  // redo eagerly from the saved state with the budgets raised
+  set_roles(h, before);
   snapshot(h, false);
   add_time(h, -h->ctl.dt);
   update_closures(h);
   std::vector<int> its(nc, 0);
-  rc = step_body(h, nullptr, 0, &its);
-  for (int s = 0; s < h->ns; s++) h->st[s].steps++;
-  for (int c = 0; c < nc; c++)
-    h->graph_budget[c] = std::max(h->graph_budget[c] + 2, its[c] + std::max(2, its[c] / 4));
+  int sweeps = 0;
+  rc = step_body(h, nullptr, 0, &its, &sweeps);
+  for (int s = 0; s < ns; s++) h->st[s].steps++;
+  set_budgets(its, sweeps, true);
   clear_graphs(h);
   return rc;
 }
@@ -771,10 +850,11 @@ static int finish_steps(Handle *h, int rc) {
   cell_stats(h);
   bool bad = false, out = false;
   for (int s = 0; s < h->ns; s++) {
-    const double *v = h->hsstat + 5 * s;
+    const double *v = h->hsstat + NSTAT * s;
     h->st[s].alpha_min = v[0];
     h->st[s].alpha_max = v[1];
     h->st[s].phase_volume = v[2];
+    h->st[s].max_div = v[5];
     bad = bad || v[4] > 0.0;
     out = out || v[0] < -h->ctl.bounds_tol || v[1] > 1.0 + h->ctl.bounds_tol;
   }
@@ -808,6 +888,7 @@ static double time_solve(Handle *h, const double *x0, int *ok) {
 static void reset_graphs(Handle *h) {
   clear_graphs(h);
   for (int c = 0; c < 16; c++) h->graph_budget[c] = 0;
+  h->mom_budget = 0;
 }
 
 // ----------------------------------------------------------------- the ABI
@@ -838,12 +919,11 @@ void dbs_destroy(dbs_handle *H) {
   if (h->stream) hipStreamSynchronize(h->stream);
   clear_graphs(h);
   for (void *p : h->allocs) hipFree(p);
-  if (h->hscal) hipHostFree(h->hscal);
-  if (h->hflags) hipHostFree(h->hflags);
-  if (h->hsstat) hipHostFree(h->hsstat);
-  if (h->hrec) hipHostFree(h->hrec);
+  for (void *p : h->hallocs) hipHostFree(p);
   for (hipEvent_t e : h->tm.ev) hipEventDestroy(e);
   if (h->flag_ev) hipEventDestroy(h->flag_ev);
+  for (hipEvent_t e : h->mom_ev)
+    if (e) hipEventDestroy(e);
   pressure_free(h);
   if (h->own_stream) hipStreamDestroy(h->own_stream);
   delete H;
@@ -948,9 +1028,12 @@ int dbs_set_graph(dbs_handle *H, int on) {
   hipStreamSynchronize(h->stream);
   h->graph_mode = on ? 1 : 0;
   reset_graphs(h);
-  // on > 1: start from a budget of on - 1 iterations instead of measuring it
-  if (on > 1)
+  // on > 1: start from a budget of on - 1 iterations (and predictor sweeps)
+  // instead of measuring it
+  if (on > 1) {
     for (int c = 0; c < 16; c++) h->graph_budget[c] = on - 1;
+    h->mom_budget = std::min(h->ctl.mom_maxit, on - 1);
+  }
   return DBS_OK;
 }
 
@@ -968,6 +1051,7 @@ int dbs_autotune(dbs_handle *H, int *kz_out, int *sweeps_out, int *coarse_out, i
   h->prof_mask = 0;
   // the first corrector's system of the current state (p_rgh is untouched
   // until the solve)
+  const Roles before = roles(h);
   snapshot(h, true);
   alpha_stage(h);
   momentum_predictor(h);
@@ -1010,7 +1094,7 @@ int dbs_autotune(dbs_handle *H, int *kz_out, int *sweeps_out, int *coarse_out, i
   h->fused_sweep = best.fused;
   rc = pressure_retune(h);
   // restore the state as it was before tuning
-  swap_roles(h);
+  set_roles(h, before);
   snapshot(h, false);
   update_closures(h);
   h->prof_mask = pm;
@@ -1025,13 +1109,15 @@ int dbs_autotune(dbs_handle *H, int *kz_out, int *sweeps_out, int *coarse_out, i
   return rc;
 }
 
-int dbs_set_tuning(dbs_handle *H, int kz, int sweeps, int coarse_sweeps, int shift, int fused) {
-  if (!H || kz < 0 || kz > 64 || sweeps < 1 || sweeps > 8 || coarse_sweeps < 1 ||
-      coarse_sweeps > 8 || shift < 0 || shift > 4)
+int dbs_set_tuning(dbs_handle *H, int kz, int kz_coarse, int sweeps, int coarse_sweeps,
+                   int shift, int fused) {
+  if (!H || kz < 0 || kz > 64 || kz_coarse < 0 || kz_coarse > 64 || sweeps < 1 || sweeps > 8 ||
+      coarse_sweeps < 1 || coarse_sweeps > 8 || shift < 0 || shift > 4)
     return DBS_EINVAL;
   Handle *h = &H->h;
   hipStreamSynchronize(h->stream);
   h->kz_fine = kz;
+  h->kz_coarse = kz_coarse;
   h->mg_pre = h->mg_post = sweeps;
   h->mgc = coarse_sweeps;
   h->bottom_shift = shift;
@@ -1041,11 +1127,12 @@ int dbs_set_tuning(dbs_handle *H, int kz, int sweeps, int coarse_sweeps, int shi
 }
 
 int dbs_debug_step_trace(dbs_handle *H, double *A, double *rAU, double *Shat, double *Ustar,
-                         double *HbyA, double *phiHbyA, double *b) {
+                         double *HbyA, double *phiHbyA, double *b, double *Rp, double *Rm,
+                         double *alphaPhi) {
   if (!H) return DBS_EINVAL;
   Handle *h = &H->h;
   if (h->ns != 1) return fail(h, DBS_EINVAL, "trace needs a single-sample handle");
-  TraceOut tr{A, rAU, Shat, Ustar, HbyA, phiHbyA, b};
+  TraceOut tr{A, rAU, Shat, Ustar, HbyA, phiHbyA, b, Rp, Rm, alphaPhi};
   int rc = eager_step(h, &tr, nullptr);
   if (rc == DBS_ECOURANT) return rc;
   return finish_steps(h, rc);

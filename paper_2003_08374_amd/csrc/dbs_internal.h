@@ -29,6 +29,9 @@ enum KClass {
 constexpr int FLAT_T = 256;               // threads of a vector-kernel block
 constexpr int FLAT_CELLS = 4 * FLAT_T;    // cells of a vector-kernel block
 constexpr int NSC = 16;                   // device scalars per sample
+constexpr int NSTAT = 6;                  // cell statistics per sample
+constexpr int NREC = 5;                   // graph-mode solve record per corrector
+constexpr int NMSC = 4;                   // predictor record per sample
 
 // first cell, cell count and closed-domain flag of a sample's fine cells
 struct Rng {
@@ -109,8 +112,9 @@ struct Handle {
 
   // static fields
   double *phi = nullptr, *kinv = nullptr;
-  // state (alpha is double-buffered: alpha holds n+1 after the transport)
-  double *alpha = nullptr, *alpha_old = nullptr;
+  // state (alpha is double-buffered: alpha holds n+1 after the transport;
+  // with sub-cycles a third buffer keeps alpha^n while the cycles alternate)
+  double *alpha = nullptr, *alpha_old = nullptr, *alpha3 = nullptr;
   double *U = nullptr, *U2 = nullptr;  // 3 x NC each
   double *prgh = nullptr, *p = nullptr;
   double *F = nullptr;                 // faces
@@ -138,11 +142,22 @@ struct Handle {
   double *partials = nullptr;  // per-block partial sums
   size_t npartials = 0;
   double *scal = nullptr;      // NSC device scalars per sample
-  double *hscal = nullptr;     // pinned host mirror
+  double *hscal = nullptr, *dscal_h = nullptr;  // host-mapped mirror (host, device view)
   int *act = nullptr, *want = nullptr;  // per-sample CG flags
-  int *hflags = nullptr;       // pinned mirror: act | want
-  hipEvent_t flag_ev = nullptr;  // eager CG: the flags copy of an iteration has landed
-  double *sstat = nullptr, *hsstat = nullptr;  // per-sample statistics (5 each)
+  hipEvent_t flag_ev = nullptr;  // eager CG: the flags of an iteration have landed
+  // pinned host memory written by kernels (mapped): the active flags of the
+  // eager CG iteration, and the predictor's flags (two slots) and records
+  int *hpub = nullptr, *dpub = nullptr;
+  // momentum predictor solve: per sample an iterate flag and a record
+  // {||B||^2, sweeps, relative residual, converged}; host-mapped mirrors
+  int *mact = nullptr;
+  double *msc = nullptr, *hmsc = nullptr, *dmsc = nullptr;
+  int *hmflag = nullptr, *dmflag = nullptr;
+  hipEvent_t mom_ev[2] = {nullptr, nullptr};
+  int mom_budget = 0;          // graph mode: predictor sweeps in a captured step
+  int mom_last = 0;            // sweeps launched by the last predictor solve
+  // per-sample statistics (NSTAT each): host-mapped, written by the kernel
+  double *hsstat = nullptr, *dsstat_h = nullptr;
 
   std::vector<Level> lv;
   std::vector<int> nlev;     // levels per sample
@@ -155,6 +170,7 @@ struct Handle {
   // tuning knobs (autotuner): fine tile depth (0 = heuristic), bottom shift,
   // fused full sweeps on the fine level (else two half-sweep launches)
   int kz_fine = 0, bottom_shift = 0, fused_sweep = 1;
+  int kz_coarse = 0;  // planes per coarse-level tile or thread column (0 = heuristic)
 
   std::vector<dbs_stats> st;  // per sample
   double tnow = 0.0;          // time reached by the samples
@@ -165,14 +181,16 @@ struct Handle {
   int graph_budget[16] = {0};  // PCG iterations per corrector in a captured step
   std::map<GraphKey, hipGraphExec_t> graphs;
   double *snap = nullptr;      // state snapshot for a step redone eagerly
-  double *rec = nullptr, *hrec = nullptr;  // per-sample solve records (ns x 16 x 3)
+  // per-sample solve records (ns x 16 x NREC), host-mapped (host, device view)
+  double *hrec = nullptr, *rec = nullptr;
 
   // profiling
   unsigned long long prof_mask = 0;
   Timer tm;
   long long k_launches[KC_COUNT] = {0};
   double k_ms[KC_COUNT] = {0};
-  std::vector<void *> allocs;
+  std::vector<void *> allocs;   // device allocations
+  std::vector<void *> hallocs;  // host-mapped allocations
 };
 
 // launch-time event bracketing
@@ -189,11 +207,19 @@ void prof_collect(Handle *h);
   } while (0)
 
 // k_alpha.hip
-void alpha_stage(Handle *h);
+// the saturation stage (n_alpha_sub sub-cycles); aphi (faces, may be NULL)
+// receives the mean limited flux
+void alpha_stage(Handle *h, double *aphi = nullptr);
+// the buffer roles the stage leaves: alpha^{n+1} current, alpha^n kept
+void alpha_roles(Handle *h);
 void update_closures(Handle *h, int only = -1);  // pc/ml/mg/cf from the current alpha
 void init_flux(Handle *h, int only = -1);  // F from U (linear interpolation)
 // k_momentum.hip
-void momentum_predictor(Handle *h);
+// budget > 0: exactly that many sweeps (graph capture), samples that have
+// converged skipped; else sweeps until every sample has converged
+void momentum_predictor(Handle *h, int budget = 0);
+// after a budgeted predictor: per-sample sweeps and convergence (host-mapped)
+void momentum_results(Handle *h, int *sweeps, double *relres, int *converged);
 void corrector_assemble(Handle *h);
 void corrector_update(Handle *h, bool last);
 // k_pressure.hip
@@ -214,11 +240,17 @@ void pressure_results(Handle *h, int *iters, double *relres, int *converged);
 void arena_copy(Handle *h, const double *src, double *dst, int narrays);
 // copy n doubles with a kernel (safe under graph capture)
 void copy_n(Handle *h, const double *src, double *dst, size_t n);
-// store the last solve's per-sample iterations, relative residual and
-// convergence flag for corrector c in rec (ns x 16 x 3 doubles)
+// the same into host-mapped memory (its device address), no blit
+void host_copy(Handle *h, const double *src, double *dst_mapped, size_t n);
+// store the last solve's per-sample iterations, relative residual,
+// convergence flag, ||b|| and initial relative residual for corrector c in
+// rec (ns x 16 x NREC doubles)
 void pressure_record(Handle *h, double *rec, int c);
+// per sample of the last solve: ||b||_2 and the initial relative residual
+void pressure_norms(Handle *h, double *bnorm, double *res0);
 // api.hip
 void add_time(Handle *h, double dt);  // move the boundary-value time
-void cell_stats(Handle *h);  // per sample: min a, max a, sum phi a V, max Co, nonfinite
+// per sample: min a, max a, sum phi a V, max Co, nonfinite count, max |div F|
+void cell_stats(Handle *h);
 
 }  // namespace dbs

@@ -157,7 +157,7 @@ __device__ __forceinline__ double low_order_flux(const Geom &G, const double *__
 __global__ void __launch_bounds__(NTHREADS) k_alpha_bounds(Segs SG, const double *__restrict__ alpha, const double *__restrict__ F,
     const double *__restrict__ phi, const double *__restrict__ A, double *__restrict__ Qp,
     double *__restrict__ Qm, double *__restrict__ Pin, double *__restrict__ Pout,
-    double *__restrict__ Rp, double *__restrict__ Rm) {
+    double *__restrict__ Rp, double *__restrict__ Rm, int nsub) {
   FOR_CELLS(SG, G, P) {
   const double aP = alpha[P.c];
   double outL = 0.0, amax = aP, amin = aP, pin = 0.0, pout = 0.0;
@@ -184,7 +184,7 @@ __global__ void __launch_bounds__(NTHREADS) k_alpha_bounds(Segs SG, const double
   }
   amax = fmin(1.0, amax);
   amin = fmax(0.0, amin);
-  const double vol = phi[P.c] * G.V / G.dt;
+  const double vol = phi[P.c] * G.V / (G.dt / nsub);
   const double aL = aP - outL / vol;
   const double qp = vol * fmax(0.0, amax - aL), qm = vol * fmax(0.0, aL - amin);
   Qp[P.c] = qp;
@@ -241,21 +241,29 @@ __global__ void __launch_bounds__(NTHREADS) k_alpha_lambda(Segs SG, const double
 // The last limiter iteration's face factor is formed here for each of the
 // cell's faces (each interior face by both its cells, with the same
 // arithmetic) from R+- and the previous factors lam (first: none).
+// Sub-cycle `sub` of nsub (time step dt / nsub): the face's limited flux is
+// summed into rhoPhi (and aphi) over the sub-cycles, and the last turns the
+// sum into the mean and the mean into the mass flux.
 __global__ void __launch_bounds__(NTHREADS) k_alpha_update(Segs SG, Phys Ph, const double *__restrict__ alpha, const double *__restrict__ F,
     const double *__restrict__ phi, const double *__restrict__ kinv, const double *__restrict__ A,
     const double *__restrict__ Rp, const double *__restrict__ Rm,
     const double *__restrict__ lam, int first, double *__restrict__ alpha_new,
     double *__restrict__ rhoPhi, double *__restrict__ ml, double *__restrict__ mg,
-    double *__restrict__ pc, double *__restrict__ cf) {
+    double *__restrict__ pc, double *__restrict__ cf, int sub, int nsub,
+    double *__restrict__ aphi) {
   FOR_CELLS(SG, G, P) {
   double out = 0.0;
   const double drho = Ph.rho_l - Ph.rho_g;
+  const bool last = sub == nsub - 1;
   for (int a = 0; a < 3; a++) {
     const bool empty = G.n[a] == 1 && G.bck[2 * a] == BC_EMPTY;
     for (int s = 0; s < 2; s++) {
       const int f = face_of(G, P, a, s);
       if (empty) {
-        if (s == 0 || P.co[a] == G.n[a] - 1) rhoPhi[f] = 0.0;
+        if (s == 0 || P.co[a] == G.n[a] - 1) {
+          rhoPhi[f] = 0.0;
+          if (aphi) aphi[f] = 0.0;
+        }
         continue;
       }
       const bool bnd = on_boundary(G, P, a, s);
@@ -269,10 +277,18 @@ __global__ void __launch_bounds__(NTHREADS) k_alpha_update(Segs SG, Phys Ph, con
       const double lf = first ? l : fmin(lam[f], l);
       const double ap = bnd ? FL : fma(lf, Af, FL);
       out += s ? ap : -ap;
-      if (s == 0 || bnd) rhoPhi[f] = drho * ap + Ph.rho_g * F[f];
+      if (s == 0 || bnd) {
+        // the running sum of the sub-cycles' limited fluxes (one cycle: the flux)
+        const double sum = (sub == 0 ? 0.0 : rhoPhi[f]) + ap;
+        rhoPhi[f] = last ? drho * (sum / nsub) + Ph.rho_g * F[f] : sum;
+        if (aphi) {
+          const double sa = (sub == 0 ? 0.0 : aphi[f]) + ap;
+          aphi[f] = last ? sa / nsub : sa;
+        }
+      }
     }
   }
-  const double an = alpha[P.c] - G.dt * out / (phi[P.c] * G.V);
+  const double an = alpha[P.c] - (G.dt / nsub) * out / (phi[P.c] * G.V);
   alpha_new[P.c] = an;
   double l, g, p;
   closures(Ph, an, l, g, p);
@@ -376,16 +392,18 @@ __global__ void __launch_bounds__(NTHREADS) k_init_flux(Segs SG, const double *_
   }
 }
 
-void alpha_stage(Handle *h) {
+// One transport sub-cycle: alpha_in -> alpha_out with dt / nsub.
+static void alpha_cycle(Handle *h, const double *ain, double *aout, int sub, int nsub,
+                        double *aphi) {
   dim3 blk(BX, BY);
   // the cell gradients borrow Qp, Qm and Pin, which the bounds pass fills later
-  AlphaArgs X{h->alpha, h->F,  h->phi, h->kinv, h->prgh, h->ml,
-              h->mg,    h->pc, h->Qp,  h->Qm,   h->Pin};
+  AlphaArgs X{ain,   h->F,  h->phi, h->kinv, h->prgh, h->ml,
+              h->mg, h->pc, h->Qp,  h->Qm,   h->Pin};
   DBS_LAUNCH(h, KC_ALPHA_FACE, k_alpha_grad, h->cgrid, blk, h->seg, X, h->Qp, h->Qm, h->Pin);
   DBS_LAUNCH(h, KC_ALPHA_FACE, k_alpha_face, h->cgrid, blk, h->seg, h->P, X, h->A);
-  DBS_LAUNCH(h, KC_ALPHA_BOUNDS, k_alpha_bounds, h->cgrid, blk, h->seg, (const double *)h->alpha,
+  DBS_LAUNCH(h, KC_ALPHA_BOUNDS, k_alpha_bounds, h->cgrid, blk, h->seg, ain,
              (const double *)h->F, (const double *)h->phi, (const double *)h->A, h->Qp, h->Qm,
-             h->Pin, h->Pout, h->Rp, h->Rm);
+             h->Pin, h->Pout, h->Rp, h->Rm, nsub);
   // the last iteration's face factors are formed inside the update
   for (int it = 0; it < h->ctl.mules_iter - 1; it++) {
     int first = it == 0;
@@ -402,15 +420,37 @@ void alpha_stage(Handle *h) {
     DBS_LAUNCH(h, KC_ALPHA_LIMIT, k_alpha_R, h->cgrid, blk, h->seg, (const double *)h->A,
                (const double *)h->lam, 0, (const double *)h->Qp, (const double *)h->Qm,
                (const double *)h->Pin, (const double *)h->Pout, h->Rp, h->Rm);
-  // alpha^{n+1} goes to the spare buffer; the old one stays for rho^n
-  DBS_LAUNCH(h, KC_ALPHA_UPDATE, k_alpha_update, h->cgrid, blk, h->seg, h->P,
-             (const double *)h->alpha, (const double *)h->F, (const double *)h->phi,
-             (const double *)h->kinv, (const double *)h->A, (const double *)h->Rp,
-             (const double *)h->Rm, (const double *)h->lam, h->ctl.mules_iter == 1 ? 1 : 0,
-             h->alpha_old, h->rhoPhi, h->ml, h->mg, h->pc, h->cf);
-  double *t = h->alpha;
-  h->alpha = h->alpha_old;
-  h->alpha_old = t;
+  DBS_LAUNCH(h, KC_ALPHA_UPDATE, k_alpha_update, h->cgrid, blk, h->seg, h->P, ain,
+             (const double *)h->F, (const double *)h->phi, (const double *)h->kinv,
+             (const double *)h->A, (const double *)h->Rp, (const double *)h->Rm,
+             (const double *)h->lam, h->ctl.mules_iter == 1 ? 1 : 0, aout, h->rhoPhi, h->ml,
+             h->mg, h->pc, h->cf, sub, nsub, aphi);
+}
+
+// Buffer roles after the stage: the cycles alternate between alpha_old and
+// alpha3 starting with alpha_old, alpha^n stays where it was (for rho^n)
+void alpha_roles(Handle *h) {
+  const int n = h->ctl.n_alpha_sub;
+  double *src = h->alpha, *x = h->alpha_old, *y = h->alpha3;
+  double *fin = (n & 1) ? x : y;
+  h->alpha_old = src;
+  h->alpha = fin;
+  if (n > 1) h->alpha3 = fin == x ? y : x;
+}
+
+void alpha_stage(Handle *h, double *aphi) {
+  dim3 blk(BX, BY);
+  const int n = h->ctl.n_alpha_sub;
+  const double *cur = h->alpha;
+  for (int k = 0; k < n; k++) {
+    // alpha^{n+1} goes to the spare buffers; alpha^n stays for rho^n
+    double *dst = (k & 1) ? h->alpha3 : h->alpha_old;
+    alpha_cycle(h, cur, dst, k, n, aphi);
+    cur = dst;
+  }
+  alpha_roles(h);
+  AlphaArgs X{h->alpha, h->F,  h->phi, h->kinv, h->prgh, h->ml,
+              h->mg,    h->pc, h->Qp,  h->Qm,   h->Pin};
   if (h->SK) {
     // surface tension coefficient from alpha^{n+1}; the gradients borrow
     // Qp, Qm and Pin again (the limiter is done with them)

@@ -304,6 +304,152 @@ __global__ void __launch_bounds__(NTHREADS) k_mom_offdiag(Segs SG, Phys Ph, MomA
   }
 }
 
+// One Jacobi sweep of the implicit predictor system a_P U - sum a_N U_N = B
+// (Eq. (semi_discretised_bis)) for the samples still iterating (mact != 0;
+// the blocks of the others return at once): Uout = rAU (B + sum a_N Uin_N),
+// and per block the sum over the three components of the squared residual
+// B + sum a_N Uin_N - Uin / rAU of the iterate the sweep starts from (and of
+// B^2 in the first sweep) for the sample's convergence test.
+__global__ void __launch_bounds__(NTHREADS) k_mom_jacobi(Segs SG, MomArgs M,
+                                                         const double *__restrict__ AN,
+                                                         const double *__restrict__ Uin,
+                                                         const double *__restrict__ B,
+                                                         double *__restrict__ Uout,
+                                                         const int *__restrict__ mact,
+                                                         double *__restrict__ part, int nb,
+                                                         int first) {
+  __shared__ double lds[2][NTHREADS / 64];
+  const int cell_gb = xcd_remap(blockIdx.x, gridDim.x);
+  const int cell_sg = find_seg(SG.bp, SG.ns, cell_gb);
+  if (!mact[cell_sg]) return;  // uniform over the block: one sample per block
+  const Geom &G = SG.g[cell_sg];
+  Cell P;
+  double r2 = 0.0, b2 = 0.0;
+  if (cell_of_thread(G, cell_gb - SG.bp[cell_sg], P)) {
+    const int c = P.c;
+    const size_t vs = (size_t)G.vs;
+    double aN[6], un[6][3];
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+#pragma unroll
+      for (int s = 0; s < 2; s++) {
+        const int q = 2 * a + s;
+        const bool interior = !empty_axis(G, a) && !on_boundary(G, P, a, s);
+        const int nbc = interior ? nbr_of(G, P, a, s) : c;
+        aN[q] = AN[(size_t)q * vs + c];
+#pragma unroll
+        for (int d = 0; d < 3; d++) un[q][d] = Uin[(size_t)d * vs + nbc];
+      }
+    }
+    const double rau = M.rAU[c];
+#pragma unroll
+    for (int d = 0; d < 3; d++) {
+      const double bd = B[(size_t)d * vs + c];
+      double acc = bd;
+#pragma unroll
+      for (int q = 0; q < 6; q++) acc += aN[q] * un[q][d];
+      const double r = acc - Uin[(size_t)d * vs + c] / rau;
+      r2 += r * r;
+      b2 += bd * bd;
+      Uout[(size_t)d * vs + c] = rau * acc;
+    }
+  }
+  r2 = wave_sum(r2);
+  b2 = wave_sum(b2);
+  const int t = threadIdx.x + BX * threadIdx.y;
+  if ((t & 63) == 0) {
+    lds[0][t >> 6] = r2;
+    lds[1][t >> 6] = b2;
+  }
+  __syncthreads();
+  if (t == 0) {
+    double sr = 0.0, sb = 0.0;
+    for (int w = 0; w < NTHREADS / 64; w++) {
+      sr += lds[0][w];
+      sb += lds[1][w];
+    }
+    part[cell_gb] = sr;
+    if (first) part[nb + cell_gb] = sb;
+  }
+}
+
+// One block per sample after a predictor sweep: the sample's residual sum
+// (and ||B||^2 after the first sweep) decides whether it iterates on.  The
+// flags go to slot `slot` of host-mapped memory for the host's stopping test
+// and the record {||B||^2, sweeps, relative residual, converged} to the
+// device and host-mapped records.
+__global__ void __launch_bounds__(1024) k_mom_final(const double *__restrict__ part, int nb,
+                                                    const int *__restrict__ bp, int ns,
+                                                    int *__restrict__ mact,
+                                                    double *__restrict__ msc,
+                                                    double *__restrict__ hmsc,
+                                                    int *__restrict__ hflag, int slot,
+                                                    double tol2, int maxit, int first) {
+  __shared__ double lds[2][16];
+  const int s = blockIdx.x, t = threadIdx.x;
+  double *R = msc + (size_t)s * NMSC;
+  if (!mact[s]) {
+    if (t == 0) hflag[slot * ns + s] = 0;
+    return;
+  }
+  double vr = 0.0, vb = 0.0;
+  for (int i = bp[s] + t; i < bp[s + 1]; i += 1024) {
+    vr += part[i];
+    if (first) vb += part[nb + i];
+  }
+  vr = wave_sum(vr);
+  vb = wave_sum(vb);
+  if ((t & 63) == 0) {
+    lds[0][t >> 6] = vr;
+    lds[1][t >> 6] = vb;
+  }
+  __syncthreads();
+  if (t != 0) return;
+  double r2 = 0.0, b2 = 0.0;
+  for (int w = 0; w < 16; w++) {
+    r2 += lds[0][w];
+    b2 += lds[1][w];
+  }
+  if (first) R[0] = b2;
+  b2 = R[0];
+  const double sweeps = first ? 1.0 : R[1] + 1.0;
+  R[1] = sweeps;
+  R[2] = b2 > 0.0 ? sqrt(r2 / b2) : 0.0;
+  const bool conv = r2 <= tol2 * b2;
+  R[3] = conv ? 1.0 : 0.0;
+  const int on = (conv || sweeps >= (double)maxit) ? 0 : 1;
+  mact[s] = on;
+  hflag[slot * ns + s] = on;
+  for (int q = 0; q < NMSC; q++) hmsc[(size_t)s * NMSC + q] = R[q];
+}
+
+// before the sweeps: every sample iterates, its record is cleared
+__global__ void k_mom_init(int *__restrict__ mact, double *__restrict__ msc, int ns, int on) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= ns) return;
+  mact[s] = on;
+  for (int q = 0; q < NMSC; q++) msc[(size_t)s * NMSC + q] = 0.0;
+}
+
+// After the sweeps: sample s ended in buffer (sweeps % 2) of {U0, U1}; the
+// samples whose parity differs from `par` copy their cells there, so that
+// every sample's predicted velocity is in buffer par.
+__global__ void __launch_bounds__(NTHREADS) k_mom_gather(Segs SG, const double *__restrict__ msc,
+                                                         double *__restrict__ U0,
+                                                         double *__restrict__ U1, int par) {
+  const int cell_gb = xcd_remap(blockIdx.x, gridDim.x);
+  const int cell_sg = find_seg(SG.bp, SG.ns, cell_gb);
+  const int own = ((int)msc[(size_t)cell_sg * NMSC + 1]) & 1;
+  if (own == par) return;
+  const Geom &G = SG.g[cell_sg];
+  Cell P;
+  if (cell_of_thread(G, cell_gb - SG.bp[cell_sg], P)) {
+    const double *src = own ? U1 : U0;
+    double *dst = par ? U1 : U0;
+    for (int d = 0; d < 3; d++) dst[(size_t)d * G.vs + P.c] = src[(size_t)d * G.vs + P.c];
+  }
+}
+
 // phiHbyA on the cell's faces and the pressure right-hand side
 // b = -sum_out phiHbyA + sum_outlet T_b p_rgh_b
 __device__ inline double phi_hbya(const Geom &G, const Phys &Ph, const MomArgs &M,
@@ -412,18 +558,71 @@ __global__ void __launch_bounds__(NTHREADS) k_face_body(Segs SG, Phys Ph, MomArg
   }
 }
 
-void momentum_predictor(Handle *h) {
+// The predictor: assembly, then Jacobi sweeps until every sample's starting
+// residual is at most mom_tol ||B|| (or mom_maxit sweeps).  Sweep k reads
+// buffer k % 2 of {U, U2} and writes the other; a sample that has converged
+// skips the later sweeps, so its result sits in buffer (its sweeps) % 2, and
+// a last gather brings every sample into one buffer.  Eager: the flags of
+// sweep k are read by the host (host-mapped memory, one event per sweep)
+// while sweep k + 1 is already queued, so the device never drains; the
+// sweep launched past the last convergence finds no sample iterating.
+// Budgeted (graph capture): exactly `budget` sweeps, no host reads.
+void momentum_predictor(Handle *h, int budget) {
   dim3 blk(BX, BY);
   MomArgs M = mom_args(h);
   DBS_LAUNCH(h, KC_MOM_ASSEMBLE, k_face_body, h->cgrid, blk, h->seg, h->P, M, h->FB);
   DBS_LAUNCH(h, KC_MOM_ASSEMBLE, k_mom_assemble, h->cgrid, blk, h->seg, h->P, M,
              (const double *)h->U, h->ctl.transpose_visc, h->rAU, h->Sh, h->B, h->AN);
-  for (int s = 0; s < h->ctl.mom_sweeps; s++) {
-    DBS_LAUNCH(h, KC_MOM_OFFDIAG, k_mom_offdiag, h->cgrid, blk, h->seg, h->P, M,
-               (const double *)h->AN, (const double *)h->U, (const double *)h->B, h->U2);
-    double *t = h->U;
-    h->U = h->U2;
-    h->U2 = t;
+  const int maxit = h->ctl.mom_maxit;
+  const int ns = h->ns;
+  DBS_LAUNCH(h, KC_MISC, k_mom_init, dim3((ns + 255) / 256), dim3(256), h->mact, h->msc, ns,
+             maxit > 0 ? 1 : 0);
+  h->mom_last = 0;
+  if (maxit <= 0) return;
+  const double tol2 = h->ctl.mom_tol * h->ctl.mom_tol;
+  const int nb = h->cell.nblk;
+  double *buf[2] = {h->U, h->U2};
+  const bool graph = budget > 0;
+  const int kmax = graph ? budget : maxit;
+  int K = 0, par = -1;
+  for (int k = 0; k < kmax; k++) {
+    DBS_LAUNCH(h, KC_MOM_OFFDIAG, k_mom_jacobi, h->cgrid, blk, h->seg, M, (const double *)h->AN,
+               (const double *)buf[k & 1], (const double *)h->B, buf[(k + 1) & 1],
+               (const int *)h->mact, h->partials, nb, k == 0 ? 1 : 0);
+    DBS_LAUNCH(h, KC_MISC, k_mom_final, dim3(ns), dim3(1024), (const double *)h->partials, nb,
+               (const int *)h->cell.bp, ns, h->mact, h->msc, h->dmsc, h->dmflag, k & 1, tol2,
+               maxit, k == 0 ? 1 : 0);
+    K = k + 1;
+    if (graph) continue;
+    (void)hipEventRecord(h->mom_ev[k & 1], h->stream);
+    if (k >= 1) {
+      (void)hipEventSynchronize(h->mom_ev[(k - 1) & 1]);
+      int on = 0;
+      for (int s = 0; s < ns; s++) on += h->hmflag[((k - 1) & 1) * ns + s];
+      if (!on) {
+        // every sample stopped after sweep k - 1: the last one to stop made
+        // k sweeps, and sweep k was a no-op
+        par = k & 1;
+        break;
+      }
+    }
+  }
+  if (par < 0) par = K & 1;
+  h->mom_last = K;
+  // single sample stopped by the host test: it already sits in buffer par
+  if (!(ns == 1 && !graph && K < kmax))
+    DBS_LAUNCH(h, KC_MISC, k_mom_gather, h->cgrid, blk, h->seg, (const double *)h->msc, buf[0],
+               buf[1], par);
+  h->U = buf[par];
+  h->U2 = buf[1 - par];
+}
+
+void momentum_results(Handle *h, int *sweeps, double *relres, int *converged) {
+  for (int s = 0; s < h->ns; s++) {
+    const double *R = h->hmsc + (size_t)s * NMSC;
+    if (sweeps) sweeps[s] = (int)R[1];
+    if (relres) relres[s] = R[2];
+    if (converged) converged[s] = R[3] != 0.0 || h->ctl.mom_maxit <= 0;
   }
 }
 

@@ -43,8 +43,9 @@ namespace dbs {
 
 enum {
   S_RZ = 0, S_PQ, S_RR, S_ALPHA, S_BETA, S_RZNEW, S_RZOLD, S_BB, S_SUM, S_NRM2, S_ITS,
-  S_NOCONV, S_RRFIN, S_RESTART
+  S_NOCONV, S_RRFIN, S_RESTART, S_RR0
 };
+static_assert(S_RR0 < NSC, "device scalars per sample");
 
 constexpr int KZ = 8;               // planes per thread column (coarse levels)
 constexpr int BOTTOM_LDS = 144000;  // bytes of LDS for the single work-group bottom
@@ -435,6 +436,7 @@ __global__ void __launch_bounds__(FIN_T) k_finalize(FinArgs A, double *__restric
     case FIN_INIT: {
       const double n2 = S[S_BB] > 0.0 ? S[S_BB] : S[S_RR];
       S[S_NRM2] = n2;
+      S[S_RR0] = S[S_RR];
       S[S_ITS] = 0.0;
       S[S_NOCONV] = 0.0;
       S[S_RESTART] = 0.0;
@@ -2102,7 +2104,7 @@ static int pick_kz(int start, int kzmax, long long minblocks, F total_blocks) {
 }
 
 // launch shapes of every level and the bottom table; depends on the tuning
-// knobs kz_fine and bottom_shift
+// knobs kz_fine, kz_coarse and bottom_shift
 int pressure_retune(Handle *h) {
   int rc = DBS_OK;
   const int ns = h->ns;
@@ -2167,7 +2169,7 @@ int pressure_retune(Handle *h) {
           if (member(s)) t += column_blocks(L.hs[s].n0, L.hs[s].n1, L.hs[s].n2, kz, pair);
         return t;
       };
-      const int kz = pick_kz(1, KZ, MIN_BLOCKS, total);
+      const int kz = h->kz_coarse > 0 ? h->kz_coarse : pick_kz(1, KZ, MIN_BLOCKS, total);
       for (int s = 0; s < ns; s++)
         blocks[s] = member(s) ? column_blocks(L.hs[s].n0, L.hs[s].n1, L.hs[s].n2, kz, pair) : 0;
       set_shape(h, S, blocks, kz, rc);
@@ -2185,7 +2187,7 @@ int pressure_retune(Handle *h) {
           if (cyc(s)) t += tiles25(L.hs[s].n0, L.hs[s].n1, L.hs[s].n2, 128, kz);
         return t;
       };
-      const int kz = pick_kz(1, KZ2, MIN_BLOCKS_CSW, total);
+      const int kz = h->kz_coarse > 0 ? h->kz_coarse : pick_kz(1, KZ2, MIN_BLOCKS_CSW, total);
       for (int s = 0; s < ns; s++)
         blocks[s] = cyc(s) ? tiles25(L.hs[s].n0, L.hs[s].n1, L.hs[s].n2, 128, kz) : 0;
       set_shape(h, L.sw, blocks, kz, rc);
@@ -2329,7 +2331,7 @@ int pressure_setup(Handle *h) {
   for (int s = 0; s < ns; s++)
     t1 += (size_t)tiles25(h->hG[s].n[0], h->hG[s].n[1], h->hG[s].n[2], 64, 1);
   np = std::max(np, 2 * t1);
-  np = std::max(np, 5 * (size_t)h->cell.nblk);
+  np = std::max(np, (size_t)NSTAT * h->cell.nblk);
   h->partials = (double *)dalloc(h, np * 8, rc);
   h->npartials = np;
   if (rc) return rc;
@@ -2639,34 +2641,48 @@ static void true_residual(Handle *h, const double *rAU, const double *b, const d
   }
 }
 
+// the active flags into host-mapped memory (a kernel store, where a
+// device-to-host copy would launch a blit of about 25 us)
+__global__ void k_publish(const int *__restrict__ act, int *__restrict__ pub, int n) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s < n) pub[s] = act[s];
+}
+__global__ void k_publish2(const int *__restrict__ act, const int *__restrict__ want,
+                           int *__restrict__ pub, int n) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s < n) {
+    pub[s] = act[s];
+    pub[n + s] = want[s];
+  }
+}
+
 // copies the CG flags to the host; returns the number of active samples and
 // sets *nwant to the number asking for a true residual
 static int fetch_flags(Handle *h, int *nwant) {
-  (void)hipMemcpyAsync(h->hflags, h->act, sizeof(int) * h->ns, hipMemcpyDeviceToHost,
-                       h->stream);
-  (void)hipMemcpyAsync(h->hflags + h->ns, h->want, sizeof(int) * h->ns, hipMemcpyDeviceToHost,
-                       h->stream);
+  DBS_LAUNCH(h, KC_MISC, k_publish2, dim3((h->ns + 255) / 256), dim3(256), (const int *)h->act,
+             (const int *)h->want, h->dpub, h->ns);
   (void)hipStreamSynchronize(h->stream);
   int na = 0, nw = 0;
   for (int s = 0; s < h->ns; s++) {
-    na += h->hflags[s] != 0;
-    nw += h->hflags[h->ns + s] != 0;
+    na += h->hpub[s] != 0;
+    nw += h->hpub[h->ns + s] != 0;
   }
   if (nwant) *nwant = nw;
   return na;
 }
 
-// eager CG: the active flags are copied to the host and an event marks
-// their arrival; the host waits on the event while later work is queued
+// eager CG: the active flags are published to host-mapped memory and an
+// event marks their arrival; the host waits on the event while later work
+// is queued
 static void post_flags(Handle *h) {
-  (void)hipMemcpyAsync(h->hflags, h->act, sizeof(int) * h->ns, hipMemcpyDeviceToHost,
-                       h->stream);
+  DBS_LAUNCH(h, KC_MISC, k_publish, dim3((h->ns + 255) / 256), dim3(256), (const int *)h->act,
+             h->dpub, h->ns);
   (void)hipEventRecord(h->flag_ev, h->stream);
 }
 static int wait_flags(Handle *h) {
   (void)hipEventSynchronize(h->flag_ev);
   int na = 0;
-  for (int s = 0; s < h->ns; s++) na += h->hflags[s] != 0;
+  for (int s = 0; s < h->ns; s++) na += h->hpub[s] != 0;
   return na;
 }
 
@@ -2793,15 +2809,15 @@ static int pcg(Handle *h, const double *rAU, const double *b, double *x, int bud
 
 void pressure_results(Handle *h, int *iters, double *relres, int *converged) {
   const int ns = h->ns;
-  (void)hipMemcpyAsync(h->hscal, h->scal, sizeof(double) * NSC * ns, hipMemcpyDeviceToHost,
-                       h->stream);
-  (void)hipMemcpyAsync(h->hflags, h->act, sizeof(int) * ns, hipMemcpyDeviceToHost, h->stream);
+  host_copy(h, h->scal, h->dscal_h, (size_t)NSC * ns);
+  DBS_LAUNCH(h, KC_MISC, k_publish, dim3((ns + 255) / 256), dim3(256), (const int *)h->act,
+             h->dpub, ns);
   (void)hipStreamSynchronize(h->stream);
   for (int s = 0; s < ns; s++) {
     const double *S = h->hscal + (size_t)s * NSC;
     if (iters) iters[s] = (int)S[S_ITS];
     if (relres) relres[s] = S[S_NRM2] > 0.0 ? sqrt(S[S_RRFIN] / S[S_NRM2]) : 0.0;
-    if (converged) converged[s] = S[S_NOCONV] == 0.0 && h->hflags[s] == 0;
+    if (converged) converged[s] = S[S_NOCONV] == 0.0 && h->hpub[s] == 0;
   }
 }
 
@@ -2822,10 +2838,12 @@ __global__ void k_record(const double *__restrict__ scal, const int *__restrict_
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= ns) return;
   const double *S = scal + (size_t)s * NSC;
-  double *o = rec + ((size_t)s * 16 + c) * 3;
+  double *o = rec + ((size_t)s * 16 + c) * NREC;
   o[0] = S[S_ITS];
   o[1] = S[S_NRM2] > 0.0 ? sqrt(S[S_RRFIN] / S[S_NRM2]) : 0.0;
   o[2] = (S[S_NOCONV] == 0.0 && act[s] == 0) ? 1.0 : 0.0;
+  o[3] = sqrt(S[S_NRM2]);
+  o[4] = S[S_NRM2] > 0.0 ? sqrt(S[S_RR0] / S[S_NRM2]) : 0.0;
 }
 
 __global__ void __launch_bounds__(FLAT_T) k_copyn(const double *__restrict__ in,
@@ -2834,9 +2852,24 @@ __global__ void __launch_bounds__(FLAT_T) k_copyn(const double *__restrict__ in,
   if (c < n) out[c] = in[c];
 }
 
+void pressure_norms(Handle *h, double *bnorm, double *res0) {
+  // valid after pressure_results (which copies the scalars to the host)
+  for (int s = 0; s < h->ns; s++) {
+    const double *S = h->hscal + (size_t)s * NSC;
+    if (bnorm) bnorm[s] = sqrt(S[S_NRM2]);
+    if (res0) res0[s] = S[S_NRM2] > 0.0 ? sqrt(S[S_RR0] / S[S_NRM2]) : 0.0;
+  }
+}
+
 void pressure_record(Handle *h, double *rec, int c) {
   DBS_LAUNCH(h, KC_MISC, k_record, dim3((h->ns + 255) / 256), dim3(256),
              (const double *)h->scal, (const int *)h->act, h->ns, rec, c);
+}
+
+void host_copy(Handle *h, const double *src, double *dst_mapped, size_t n) {
+  if (!n) return;
+  DBS_LAUNCH(h, KC_MISC, k_copyn, dim3((unsigned)((n + FLAT_T - 1) / FLAT_T)), dim3(FLAT_T), src,
+             dst_mapped, n);
 }
 
 void copy_n(Handle *h, const double *src, double *dst, size_t n) {

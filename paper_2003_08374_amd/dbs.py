@@ -52,11 +52,12 @@ class BC(C.Structure):
 
 
 class Controls(C.Structure):
-    _fields_ = [("dt", C.c_double), ("n_corr", C.c_int), ("mom_sweeps", C.c_int),
+    _fields_ = [("dt", C.c_double), ("n_corr", C.c_int), ("mom_maxit", C.c_int),
                 ("transpose_visc", C.c_int), ("mules_iter", C.c_int), ("p_tol", C.c_double),
                 ("p_maxit", C.c_int), ("precision", C.c_int), ("mg_pre", C.c_int),
                 ("mg_post", C.c_int), ("max_courant", C.c_double), ("bounds_tol", C.c_double),
-                ("target_courant", C.c_double), ("dt_max", C.c_double)]
+                ("target_courant", C.c_double), ("dt_max", C.c_double),
+                ("mom_tol", C.c_double), ("n_alpha_sub", C.c_int)]
 
 
 class Stats(C.Structure):
@@ -64,7 +65,9 @@ class Stats(C.Structure):
                 ("p_relres", C.c_double * 16), ("mg_levels", C.c_int),
                 ("alpha_min", C.c_double), ("alpha_max", C.c_double),
                 ("phase_volume", C.c_double), ("max_courant", C.c_double),
-                ("time", C.c_double), ("dt", C.c_double)]
+                ("time", C.c_double), ("dt", C.c_double), ("mom_sweeps", C.c_int),
+                ("mom_relres", C.c_double), ("p_bnorm", C.c_double * 16),
+                ("p_res0", C.c_double * 16), ("max_div", C.c_double)]
 
 
 _DP = C.POINTER(C.c_double)
@@ -111,7 +114,7 @@ def lib():
         L.dbs_reset_profiling.argtypes = [H]
         L.dbs_reset_profiling.restype = None
         L.dbs_debug_pressure_solve.argtypes = [H, _DP, _DP, _DP, C.POINTER(C.c_int), _DP]
-        L.dbs_debug_step_trace.argtypes = [H] + [_DP] * 7
+        L.dbs_debug_step_trace.argtypes = [H] + [_DP] * 10
         L.dbs_batch_create.argtypes = [C.c_int, C.POINTER(Grid), C.POINTER(Physics),
                                        C.POINTER(BC), C.POINTER(Controls), C.POINTER(H)]
         L.dbs_batch_size.argtypes = [H]
@@ -123,7 +126,7 @@ def lib():
         L.dbs_batch_get_stats.argtypes = [H, C.c_int, C.POINTER(Stats)]
         L.dbs_set_graph.argtypes = [H, C.c_int]
         L.dbs_autotune.argtypes = [H] + [C.POINTER(C.c_int)] * 5 + [_DP]
-        L.dbs_set_tuning.argtypes = [H] + [C.c_int] * 5
+        L.dbs_set_tuning.argtypes = [H] + [C.c_int] * 6
         L.dbs_set_time.argtypes = [H, C.c_double]
         _lib = L
     return _lib
@@ -176,7 +179,9 @@ def make_structs(case, precision=None, p_tol=None, mg=None, max_courant=0.0, bou
     c = Controls()
     c.dt = case.dt
     c.n_corr = case.n_corr
-    c.mom_sweeps = case.mom_sweeps
+    c.mom_maxit = int(case.mom_maxit)
+    c.mom_tol = float(case.mom_tol)
+    c.n_alpha_sub = int(getattr(case, "n_alpha_sub", 1))
     c.transpose_visc = int(case.transpose_visc)
     c.mules_iter = int(case.mules_iter)
     c.p_tol = case.p_tol if p_tol is None else p_tol
@@ -230,9 +235,10 @@ class _Handle:
     def set_time(self, t):
         self._check(lib().dbs_set_time(self.h, float(t)))
 
-    def set_tuning(self, kz=0, sweeps=2, coarse_sweeps=2, bottom_shift=0, fused=1):
-        self._check(lib().dbs_set_tuning(self.h, int(kz), int(sweeps), int(coarse_sweeps),
-                                         int(bottom_shift), int(fused)))
+    def set_tuning(self, kz=0, sweeps=2, coarse_sweeps=2, bottom_shift=0, fused=1,
+                   kz_coarse=0):
+        self._check(lib().dbs_set_tuning(self.h, int(kz), int(kz_coarse), int(sweeps),
+                                         int(coarse_sweeps), int(bottom_shift), int(fused)))
 
     @staticmethod
     def _stats_dict(s, n):
@@ -240,7 +246,9 @@ class _Handle:
                 "p_relres": list(s.p_relres)[:n], "mg_levels": s.mg_levels,
                 "alpha_min": s.alpha_min, "alpha_max": s.alpha_max,
                 "phase_volume": s.phase_volume, "max_courant": s.max_courant,
-                "time": s.time, "dt": s.dt}
+                "time": s.time, "dt": s.dt, "mom_sweeps": s.mom_sweeps,
+                "mom_relres": s.mom_relres, "p_bnorm": list(s.p_bnorm)[:n],
+                "p_res0": list(s.p_res0)[:n], "max_div": s.max_div}
 
     # -------------------------------------------------------------- profiling
     def set_profiling(self, mask):
@@ -370,14 +378,14 @@ class Solver(_Handle):
                                                    C.byref(it), C.byref(rr)))
         return x, it.value, rr.value
 
+    TRACE = ("A", "rAU", "Shat", "Ustar", "HbyA", "phiHbyA", "b", "Rp", "Rm", "alphaPhi")
+
     def trace_step(self):
         nc, nf = self.nc, self.nf
-        out = {"A": np.zeros(nf), "rAU": np.zeros(nc), "Shat": np.zeros(3 * nc),
-               "Ustar": np.zeros(3 * nc), "HbyA": np.zeros(3 * nc), "phiHbyA": np.zeros(nf),
-               "b": np.zeros(nc)}
-        self._check(lib().dbs_debug_step_trace(
-            self.h, *[_ptr(out[k]) for k in ("A", "rAU", "Shat", "Ustar", "HbyA", "phiHbyA",
-                                              "b")]))
+        size = {"A": nf, "rAU": nc, "Shat": 3 * nc, "Ustar": 3 * nc, "HbyA": 3 * nc,
+                "phiHbyA": nf, "b": nc, "Rp": nc, "Rm": nc, "alphaPhi": nf}
+        out = {k: np.zeros(size[k]) for k in self.TRACE}
+        self._check(lib().dbs_debug_step_trace(self.h, *[_ptr(out[k]) for k in self.TRACE]))
         return out
 
 
