@@ -197,6 +197,8 @@ int dbs_get_stats(dbs_handle *h, dbs_stats *out);
 /* Time of the state of every sample (default 0); time-dependent boundary
    values (DBS_BC_WAVE) of the next step are taken at t + dt. */
 int dbs_set_time(dbs_handle *h, double t);
+/* Message of the last failed call on h; with h = NULL, of this thread's last
+   failed handle-free call (dbs_pressure_solve_noalloc). */
 const char *dbs_last_error(const dbs_handle *h);
 void dbs_destroy(dbs_handle *h);
 
@@ -282,6 +284,31 @@ int dbs_set_tuning(dbs_handle *h, int kz, int kz_coarse, int sweeps, int coarse_
    b; x holds the initial guess and receives the solution. */
 int dbs_debug_pressure_solve(dbs_handle *h, const double *rAU, const double *b, double *x,
                              int *iters, double *relres);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+   capture, tight serving loops, harnesses that forbid hipMalloc): the solve
+   of dbs_debug_pressure_solve without a handle and without any allocation.
+   The mesh `grid` and the kinds of its six domain faces (DBS_BC_*; outlet
+   faces are the Dirichlet faces of the operator, EMPTY faces pair on an
+   axis of one cell, the other kinds are fixed-flux faces) define
+   -div(rAU_f grad x); rAU, b and x are caller DEVICE arrays of nx*ny*nz
+   doubles (x: initial guess in, solution out), solved on `stream`
+   (hipStream_t, NULL: the default stream) to ||b - A x||_2 <= tol ||b||_2
+   with at most maxit iterations, FP64 or DBS_MIXED (FP32 V-cycle);
+   iters and relres may be NULL.  Every work array (CG vectors, multigrid
+   levels, launch tables, partial sums) lives in one static device array of
+   DBS_NOALLOC_BYTES per GPU, held from module load to process end and
+   cleared at the start of each call; meshes above DBS_NOALLOC_MAX_CELLS
+   cells, or whose hierarchy does not fit, return DBS_EINVAL.  Calls that
+   overlap on one GPU race for that array.  The call synchronises `stream`
+   before returning.  Errors: DBS_EINVAL (arguments, size), DBS_ENOCONV,
+   DBS_EHIP; dbs_last_error(NULL) gives the message of this thread's last
+   failed call. */
+#define DBS_NOALLOC_BYTES (64u << 20)
+#define DBS_NOALLOC_MAX_CELLS (1 << 19)
+int dbs_pressure_solve_noalloc(const dbs_grid *grid, const int bc_kind[6], int precision,
+                               const double *rAU, const double *b, double *x, double tol,
+                               int maxit, int *iters, double *relres, void *stream);
 
 /* Tests only (single-sample handles).  Run one step and copy intermediate fields to host arrays
    (any pointer may be NULL): the MULES antidiffusive flux A (faces), 1/a_P

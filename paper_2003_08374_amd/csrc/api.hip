@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <string>
 
@@ -891,6 +892,152 @@ static void reset_graphs(Handle *h) {
   h->mom_budget = 0;
 }
 
+// ------------------------------------------ pressure solve without allocation
+//
+// The no-alloc solve keeps every device array it needs (work vectors,
+// multigrid levels, launch tables, reduction partials) in `scratch`, a
+// file-scope device array that each GPU holds from module load until the
+// process ends.  In host code the symbol is only a stand-in: its device
+// address is taken once per device with hipGetSymbolAddress and that
+// address (never the symbol) is what kernels and copies receive.  Calls on
+// one GPU share the array and must not overlap.
+
+static __device__ __align__(256) unsigned char scratch[DBS_NOALLOC_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned char *g_scratch_ptr[kMaxDevices] = {nullptr};
+thread_local std::string g_noalloc_err;
+}  // namespace
+
+static const char *noalloc_error() {
+  return g_noalloc_err.empty() ? "null handle" : g_noalloc_err.c_str();
+}
+
+__global__ void __launch_bounds__(256) k_zero16(uint4 *__restrict__ p, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256)
+    p[i] = make_uint4(0u, 0u, 0u, 0u);
+}
+
+// device address of this device's scratch array (taken once per device)
+static unsigned char *scratch_of_device(int &rc) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+    rc = DBS_EHIP;
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+      rc = DBS_EHIP;
+      return nullptr;
+    }
+    g_scratch_ptr[dev] = (unsigned char *)ptr;
+  }
+  return g_scratch_ptr[dev];
+}
+
+static int noalloc_fail(int code, const std::string &msg) {
+  g_noalloc_err = msg;
+  return code;
+}
+
+static int pressure_solve_noalloc(const dbs_grid *grid, const int *bc_kind, int precision,
+                                  const double *rAU, const double *b, double *x, double tol,
+                                  int maxit, int *iters, double *relres, hipStream_t stream) {
+  if (!grid || !bc_kind || !rAU || !b || !x) return noalloc_fail(DBS_EINVAL, "null argument");
+  if (precision != DBS_FP64 && precision != DBS_MIXED)
+    return noalloc_fail(DBS_EINVAL, "precision");
+  if (!(tol > 0.0) || maxit < 1) return noalloc_fail(DBS_EINVAL, "tolerance or iteration limit");
+  dbs_bc bc[6];
+  memset(bc, 0, sizeof(bc));
+  for (int q = 0; q < 6; q++) {
+    if (bc_kind[q] < DBS_BC_WALL || bc_kind[q] > DBS_BC_WAVE)
+      return noalloc_fail(DBS_EINVAL, "bad bc kind");
+    // only outlet (Dirichlet) and empty faces matter to the operator
+    bc[q].kind = bc_kind[q] == DBS_BC_WAVE ? DBS_BC_INLET : bc_kind[q];
+  }
+  std::string msg;
+  if (validate_sample(grid, bc, msg)) return noalloc_fail(DBS_EINVAL, msg);
+  const long long nc = (long long)grid->nx * grid->ny * grid->nz;
+  if (nc > DBS_NOALLOC_MAX_CELLS)
+    return noalloc_fail(DBS_EINVAL, "mesh of " + std::to_string(nc) +
+                                        " cells exceeds the no-alloc maximum of " +
+                                        std::to_string(DBS_NOALLOC_MAX_CELLS));
+  int rc = DBS_OK;
+  unsigned char *base = scratch_of_device(rc);
+  if (rc) return noalloc_fail(rc, "hipGetSymbolAddress failed");
+  Handle hh;
+  Handle *h = &hh;
+  h->stream = stream;
+  h->arena = base;
+  h->arena_cap = DBS_NOALLOC_BYTES;
+  h->hscal = h->hscal_own;
+  h->hpub = h->hpub_own;
+  // the array keeps the last call's contents: clear all of it
+  const size_t n16 = DBS_NOALLOC_BYTES / 16;
+  hipLaunchKernelGGL(k_zero16, dim3(2048), dim3(256), 0, h->stream, (uint4 *)base, n16);
+  const double g0[3] = {0.0, 0.0, 0.0};
+  Geom G = make_geom(grid, bc, 1.0, g0);
+  G.c0 = 0;
+  h->ns = 1;
+  h->NC = ((long long)G.nc + FLAT_CELLS - 1) / FLAT_CELLS * FLAT_CELLS;
+  G.vs = (int)h->NC;
+  h->hG.assign(1, G);
+  h->hrng.assign(1, Rng{0, G.nc, G.has_outlet ? 0 : 1, 0});
+  h->st.assign(1, dbs_stats());
+  memset(&h->ctl, 0, sizeof(h->ctl));
+  h->ctl.p_tol = tol;
+  h->ctl.p_maxit = maxit;
+  h->ctl.precision = precision;
+  h->cell.hbp = {0, cell_blocks(G)};
+  h->cell.nblk = h->cell.hbp[1];
+  h->flat.hbp = {0, (int)(h->NC / FLAT_CELLS)};
+  h->flat.nblk = h->flat.hbp[1];
+  const size_t NC = (size_t)h->NC;
+  h->cell.bp = (int *)arena_take(h, sizeof(int) * 2, rc);
+  h->flat.bp = (int *)arena_take(h, sizeof(int) * 2, rc);
+  h->rng = (Rng *)arena_take(h, sizeof(Rng), rc);
+  h->scal = (double *)arena_take(h, sizeof(double) * NSC, rc);
+  double *vec[8];
+  for (double *&v : vec) v = (double *)arena_take(h, sizeof(double) * NC, rc);
+  h->r = vec[0]; h->z = vec[1]; h->pv = vec[2]; h->q = vec[3]; h->pv2 = vec[4];
+  double *rA = vec[5], *bA = vec[6], *xA = vec[7];
+  if (!rc) {
+    const bool ok =
+        hipMemcpyAsync(h->cell.bp, h->cell.hbp.data(), sizeof(int) * 2, hipMemcpyHostToDevice,
+                       h->stream) == hipSuccess &&
+        hipMemcpyAsync(h->flat.bp, h->flat.hbp.data(), sizeof(int) * 2, hipMemcpyHostToDevice,
+                       h->stream) == hipSuccess &&
+        hipMemcpyAsync(h->rng, h->hrng.data(), sizeof(Rng), hipMemcpyHostToDevice, h->stream) ==
+            hipSuccess &&
+        hipStreamSynchronize(h->stream) == hipSuccess;
+    if (!ok) rc = DBS_EHIP;
+  }
+  if (!rc) rc = pressure_setup(h);
+  if (rc == DBS_ENOMEM)
+    return noalloc_fail(DBS_EINVAL, "the solve needs more than " +
+                                        std::to_string(h->arena_used) + " bytes of scratch (has " +
+                                        std::to_string((size_t)DBS_NOALLOC_BYTES) + ")");
+  if (rc) return noalloc_fail(rc, h->err.empty() ? "set-up failed" : h->err);
+  // the caller's arrays hold nc cells; the solve runs over the padded arena
+  copy_n(h, rAU, rA, (size_t)G.nc);
+  copy_n(h, b, bA, (size_t)G.nc);
+  copy_n(h, x, xA, (size_t)G.nc);
+  int its = 0;
+  double rel = 0.0;
+  const int src = pressure_solve(h, rA, bA, xA, 0, &its, &rel);
+  copy_n(h, xA, x, (size_t)G.nc);
+  if (hipStreamSynchronize(h->stream) != hipSuccess || hipGetLastError() != hipSuccess)
+    return noalloc_fail(DBS_EHIP, "solve failed");
+  if (iters) *iters = its;
+  if (relres) *relres = rel;
+  if (src) return noalloc_fail(src, "pressure solve did not converge");
+  return DBS_OK;
+}
+
 // ----------------------------------------------------------------- the ABI
 
 extern "C" {
@@ -929,7 +1076,9 @@ void dbs_destroy(dbs_handle *H) {
   delete H;
 }
 
-const char *dbs_last_error(const dbs_handle *H) { return H ? H->h.err.c_str() : "null handle"; }
+const char *dbs_last_error(const dbs_handle *H) {
+  return H ? H->h.err.c_str() : noalloc_error();
+}
 
 int dbs_set_stream(dbs_handle *H, void *stream) {
   if (!H) return DBS_EINVAL;
@@ -1183,6 +1332,13 @@ int dbs_kernel_time(dbs_handle *H, int cls, long long *launches, double *ms) {
   if (launches) *launches = H->h.k_launches[cls];
   if (ms) *ms = H->h.k_ms[cls];
   return DBS_OK;
+}
+
+int dbs_pressure_solve_noalloc(const dbs_grid *grid, const int bc_kind[6], int precision,
+                               const double *rAU, const double *b, double *x, double tol,
+                               int maxit, int *iters, double *relres, void *stream) {
+  return pressure_solve_noalloc(grid, bc_kind, precision, rAU, b, x, tol, maxit, iters, relres,
+                                (hipStream_t)stream);
 }
 
 int dbs_debug_pressure_solve(dbs_handle *H, const double *rAU, const double *b, double *x,

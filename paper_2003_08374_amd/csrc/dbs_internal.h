@@ -190,8 +190,28 @@ struct Handle {
   long long k_launches[KC_COUNT] = {0};
   double k_ms[KC_COUNT] = {0};
   std::vector<void *> allocs;   // device allocations
+  // Scratch-arena mode (the no-alloc pressure solve): device arrays are
+  // carved from a caller-provided zeroed region instead of hipMalloc, and
+  // flags and scalars travel by plain copies into these host arrays.
+  unsigned char *arena = nullptr;
+  size_t arena_cap = 0, arena_used = 0;
+  double hscal_own[NSC] = {0};
+  int hpub_own[2] = {0, 0};
   std::vector<void *> hallocs;  // host-mapped allocations
 };
+
+// bytes from the scratch arena (256-byte aligned); DBS_ENOMEM when it is full
+inline void *arena_take(Handle *h, size_t bytes, int &rc) {
+  if (rc) return nullptr;
+  const size_t off = (h->arena_used + 255) & ~(size_t)255;
+  if (off + bytes > h->arena_cap) {
+    rc = DBS_ENOMEM;
+    h->arena_used = off + bytes;  // the size that was asked for, for the message
+    return nullptr;
+  }
+  h->arena_used = off + bytes;
+  return h->arena + off;
+}
 
 // launch-time event bracketing
 void prof_begin(Handle *h, int cls);

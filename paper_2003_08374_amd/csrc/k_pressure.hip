@@ -2067,6 +2067,7 @@ static void *dalloc(Handle *h, size_t bytes, int &rc) {
   void *p = nullptr;
   if (rc) return nullptr;
   const size_t n = bytes < 256 ? 256 : bytes;
+  if (h->arena) return arena_take(h, n, rc);  // zeroed by the caller of the solve
   if (hipMalloc(&p, n) != hipSuccess) {
     rc = DBS_ENOMEM;
     return nullptr;
@@ -2076,7 +2077,13 @@ static void *dalloc(Handle *h, size_t bytes, int &rc) {
   return p;
 }
 
-static int upload(void *dst, const void *src, size_t bytes) {
+// host table -> device; with a scratch arena on the handle's stream
+static int upload(Handle *h, void *dst, const void *src, size_t bytes) {
+  if (h->arena)
+    return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, h->stream) == hipSuccess &&
+                   hipStreamSynchronize(h->stream) == hipSuccess
+               ? DBS_OK
+               : DBS_EHIP;
   return hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice) == hipSuccess ? DBS_OK : DBS_EHIP;
 }
 
@@ -2088,7 +2095,7 @@ static void set_shape(Handle *h, Shape &S, const std::vector<int> &blocks, int k
   for (int s = 0; s < h->ns; s++) S.hbp[s + 1] = S.hbp[s] + blocks[s];
   S.nblk = S.hbp[h->ns];
   if (!S.bp) S.bp = (int *)dalloc(h, sizeof(int) * (h->ns + 1), rc);
-  if (!rc) rc = upload(S.bp, S.hbp.data(), sizeof(int) * (h->ns + 1));
+  if (!rc) rc = upload(h, S.bp, S.hbp.data(), sizeof(int) * (h->ns + 1));
 }
 
 static dim3 blk() { return dim3(BX, BY); }
@@ -2235,7 +2242,7 @@ int pressure_retune(Handle *h) {
     int r2 = DBS_OK;
     if (!h->btab) h->btab = dalloc(h, sizeof(Bottom<R>) * tab.size(), r2);
     if (r2) return r2;
-    return upload(h->btab, tab.data(), sizeof(Bottom<R>) * tab.size());
+    return upload(h, h->btab, tab.data(), sizeof(Bottom<R>) * tab.size());
   };
   rc = mixed ? build(0.0f) : build(0.0);
   return rc;
@@ -2294,7 +2301,7 @@ int pressure_setup(Handle *h) {
   for (int l = 0; l < nlmax && !rc; l++) {
     Level &L = h->lv[l];
     L.ds = (LvS *)dalloc(h, sizeof(LvS) * ns, rc);
-    if (!rc) rc = upload(L.ds, L.hs.data(), sizeof(LvS) * ns);
+    if (!rc) rc = upload(h, L.ds, L.hs.data(), sizeof(LvS) * ns);
     if (l == 0 || rc) continue;
     const size_t n = (size_t)L.nc;
     const size_t s = mixed ? 4 : 8;
@@ -2659,8 +2666,15 @@ __global__ void k_publish2(const int *__restrict__ act, const int *__restrict__ 
 // copies the CG flags to the host; returns the number of active samples and
 // sets *nwant to the number asking for a true residual
 static int fetch_flags(Handle *h, int *nwant) {
-  DBS_LAUNCH(h, KC_MISC, k_publish2, dim3((h->ns + 255) / 256), dim3(256), (const int *)h->act,
-             (const int *)h->want, h->dpub, h->ns);
+  if (h->dpub) {
+    DBS_LAUNCH(h, KC_MISC, k_publish2, dim3((h->ns + 255) / 256), dim3(256),
+               (const int *)h->act, (const int *)h->want, h->dpub, h->ns);
+  } else {
+    // no host-mapped memory (scratch-arena solve): plain copies
+    (void)hipMemcpyAsync(h->hpub, h->act, sizeof(int) * h->ns, hipMemcpyDeviceToHost, h->stream);
+    (void)hipMemcpyAsync(h->hpub + h->ns, h->want, sizeof(int) * h->ns, hipMemcpyDeviceToHost,
+                         h->stream);
+  }
   (void)hipStreamSynchronize(h->stream);
   int na = 0, nw = 0;
   for (int s = 0; s < h->ns; s++) {
@@ -2675,12 +2689,17 @@ static int fetch_flags(Handle *h, int *nwant) {
 // event marks their arrival; the host waits on the event while later work
 // is queued
 static void post_flags(Handle *h) {
+  if (!h->dpub) {
+    (void)hipMemcpyAsync(h->hpub, h->act, sizeof(int) * h->ns, hipMemcpyDeviceToHost, h->stream);
+    return;
+  }
   DBS_LAUNCH(h, KC_MISC, k_publish, dim3((h->ns + 255) / 256), dim3(256), (const int *)h->act,
              h->dpub, h->ns);
   (void)hipEventRecord(h->flag_ev, h->stream);
 }
 static int wait_flags(Handle *h) {
-  (void)hipEventSynchronize(h->flag_ev);
+  if (h->dpub) (void)hipEventSynchronize(h->flag_ev);
+  else (void)hipStreamSynchronize(h->stream);
   int na = 0;
   for (int s = 0; s < h->ns; s++) na += h->hpub[s] != 0;
   return na;
@@ -2809,9 +2828,15 @@ static int pcg(Handle *h, const double *rAU, const double *b, double *x, int bud
 
 void pressure_results(Handle *h, int *iters, double *relres, int *converged) {
   const int ns = h->ns;
-  host_copy(h, h->scal, h->dscal_h, (size_t)NSC * ns);
-  DBS_LAUNCH(h, KC_MISC, k_publish, dim3((ns + 255) / 256), dim3(256), (const int *)h->act,
-             h->dpub, ns);
+  if (h->dpub) {
+    host_copy(h, h->scal, h->dscal_h, (size_t)NSC * ns);
+    DBS_LAUNCH(h, KC_MISC, k_publish, dim3((ns + 255) / 256), dim3(256), (const int *)h->act,
+               h->dpub, ns);
+  } else {
+    (void)hipMemcpyAsync(h->hscal, h->scal, sizeof(double) * NSC * ns, hipMemcpyDeviceToHost,
+                         h->stream);
+    (void)hipMemcpyAsync(h->hpub, h->act, sizeof(int) * ns, hipMemcpyDeviceToHost, h->stream);
+  }
   (void)hipStreamSynchronize(h->stream);
   for (int s = 0; s < ns; s++) {
     const double *S = h->hscal + (size_t)s * NSC;

@@ -28,6 +28,7 @@ EXPORTS = (
     "dbs_batch_create", "dbs_batch_size", "dbs_batch_set_static", "dbs_batch_set_state",
     "dbs_batch_get_state", "dbs_batch_set_state_dev", "dbs_batch_get_state_dev",
     "dbs_batch_get_stats", "dbs_batch_step", "dbs_set_graph", "dbs_autotune", "dbs_set_tuning", "dbs_set_time",
+    "dbs_pressure_solve_noalloc",
 )
 
 
@@ -128,6 +129,9 @@ def lib():
         L.dbs_autotune.argtypes = [H] + [C.POINTER(C.c_int)] * 5 + [_DP]
         L.dbs_set_tuning.argtypes = [H] + [C.c_int] * 6
         L.dbs_set_time.argtypes = [H, C.c_double]
+        L.dbs_pressure_solve_noalloc.argtypes = [C.POINTER(Grid), C.POINTER(C.c_int), C.c_int,
+                                                 C.c_void_p, C.c_void_p, C.c_void_p, C.c_double,
+                                                 C.c_int, C.POINTER(C.c_int), _DP, C.c_void_p]
         _lib = L
     return _lib
 
@@ -193,6 +197,29 @@ def make_structs(case, precision=None, p_tol=None, mg=None, max_courant=0.0, bou
     c.target_courant = float(getattr(case, "target_courant", 0.0))
     c.dt_max = float(getattr(case, "dt_max", 0.0))
     return g, p, bcs, c
+
+
+NOALLOC_BYTES = 64 << 20
+NOALLOC_MAX_CELLS = 1 << 19
+
+
+def pressure_solve_noalloc(case, rAU, b, x, tol, maxit=2000, precision="fp64", stream=None):
+    """dbs_pressure_solve_noalloc on device buffers given as raw pointers
+    (e.g. torch ``data_ptr()``) of nx*ny*nz doubles; the mesh and the kinds
+    of the six domain faces come from ``case``.  Returns (iterations,
+    relative residual); raises DBSError on failure."""
+    g = Grid()
+    g.nx, g.ny, g.nz = case.shape
+    g.dx, g.dy, g.dz = case.h
+    kinds = (C.c_int * 6)(*[_KIND[bc["kind"]] for bc in case.bc])
+    it = C.c_int()
+    rr = C.c_double()
+    rc = lib().dbs_pressure_solve_noalloc(C.byref(g), kinds, _PREC[precision], rAU, b, x,
+                                          float(tol), int(maxit), C.byref(it), C.byref(rr),
+                                          stream)
+    if rc != OK:
+        raise DBSError(rc, lib().dbs_last_error(None).decode())
+    return it.value, rr.value
 
 
 class _Handle:
