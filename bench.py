@@ -28,6 +28,31 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, AMD public figure
 
+# Algorithmic bytes per cell of one PISO step, stage by stage (FP64 fields of
+# 8 B; the ideal traffic of each stage with the fusion the model states):
+# alpha face fluxes (alpha, 3 fluxes, phi, k^-1, p_rgh read; 3 antidiffusive
+# fluxes and R+- written), MULES limit and update (alpha, 3 A, R+-, 3 F, phi
+# read; alpha' and 3 limited fluxes written), momentum assembly (16 fields
+# read, a_P and 3 sources written), one Jacobi sweep (15 read, 3 written),
+# per corrector the p_rgh assembly (15 read, 8 written) and the flux and
+# velocity correction (10 read, 6 written), and per PCG iteration the SpMV,
+# the x/r update, the V-cycle (fine level with fused red-black sweeps, 8/7
+# for the coarse levels) and the direction update: 216 B in FP64, about 160 B
+# with the V-cycle in FP32.
+STEP_BYTES = {"alpha_face": 96, "alpha_limit_update": 112, "mom_assemble": 144,
+              "jacobi_sweep": 144, "p_assembly": 184, "correct": 128,
+              "pcg_iteration": {"fp64": 216, "mixed": 160}}
+
+
+def alg_step_bytes_per_cell(precision, p_iters, sweeps, n_sub=1):
+    """Algorithmic bytes per cell of one step with the measured PCG
+    iterations per corrector and predictor sweeps (n_sub saturation
+    sub-cycles repeat the transport stages)."""
+    B = STEP_BYTES
+    return (n_sub * (B["alpha_face"] + B["alpha_limit_update"]) + B["mom_assemble"] +
+            sweeps * B["jacobi_sweep"] + len(p_iters) * (B["p_assembly"] + B["correct"]) +
+            sum(p_iters) * B["pcg_iteration"][precision])
+
 
 def alg_bytes_per_cell(cls: str, rsize: int, fused: bool = False) -> float:
     """Algorithmic bytes per fine cell and launch of a kernel class.
@@ -88,13 +113,165 @@ def measured_traffic(kernel, precision, n):
         rec = json.loads(m.group(1))
         if (rec.get("kernel"), rec.get("precision"), rec.get("n")) != (kernel, precision, n):
             continue
-        src = os.path.join(ROOT, rec["source"])
-        if not os.path.exists(src):
-            continue
-        if hashlib.sha1(open(src, "rb").read()).hexdigest() != rec["source_sha1"]:
+        if "sources" not in rec or sources_sha1(rec["sources"]) != rec.get("sources_sha1"):
             continue
         return float(rec["traffic_bytes_per_launch"]), os.path.relpath(path, ROOT)
     return None, None
+
+
+CSRC = ["paper_2003_08374_amd/csrc/" + f for f in
+        ("api.hip", "k_alpha.hip", "k_momentum.hip", "k_pressure.hip", "dbs_device.h",
+         "dbs_internal.h")]
+
+
+def sources_sha1(files):
+    """One SHA-1 over the named source files (repository-relative)."""
+    import hashlib
+    h = hashlib.sha1()
+    for f in files:
+        path = os.path.join(ROOT, f)
+        if not os.path.exists(path):
+            return None
+        h.update(open(path, "rb").read())
+    return h.hexdigest()
+
+
+def summarize_counters(d, n, precision, cmd_trace, cmd_counters):
+    """Markdown summary of a whole-step rocprofv3 measurement of the 256^3
+    workload: a kernel trace (d/trace), FETCH_SIZE and WRITE_SIZE passes
+    (d/fetch, d/write) and the same passes over a plain 1 GiB copy
+    (d/cfetch, d/cwrite) for the calibration.  The last step of each run
+    (from the last k_add_time dispatch to the end) is the one summarised."""
+    import csv
+    import re
+
+    def rows(p):
+        with open(p) as f:
+            return list(csv.DictReader(f))
+
+    def name(x):
+        return re.sub(r"\(.*$", "", x["Kernel_Name"]).replace("void ", "").replace("dbs::", "")
+
+    def last_step(rs):
+        # from the last step start (k_add_time) to the end of that dbs_step
+        # call (k_stats_final)
+        key = "Dispatch_Id" if "Dispatch_Id" in rs[0] else "Start_Timestamp"
+        rs = sorted(rs, key=lambda x: int(x[key]))
+        idx = [i for i, x in enumerate(rs) if name(x) == "k_add_time"]
+        seg = rs[idx[-1]:] if idx else rs
+        end = [i for i, x in enumerate(seg) if name(x) == "k_stats_final"]
+        return seg[:end[0] + 1] if end else seg
+
+    def calib(kind):
+        v = [float(x["Counter_Value"]) for x in rows(f"{d}/c{kind}/run_counter_collection.csv")
+             if "copyBuffer" in x["Kernel_Name"]]
+        return (1 << 30) / 1024.0 / max(v)
+
+    cf, cw = calib("fetch"), calib("write")
+    cells = n ** 3
+    tr = last_step(rows(f"{d}/trace/run_kernel_trace.csv"))
+    fe = last_step(rows(f"{d}/fetch/run_counter_collection.csv"))
+    wr = last_step(rows(f"{d}/write/run_counter_collection.csv"))
+    agg = {}
+    def grid(x):  # threads in the launch (the two files name the field differently)
+        if "Grid_Size" in x:
+            return int(x["Grid_Size"])
+        return int(x["Grid_Size_X"]) * int(x["Grid_Size_Y"]) * int(x["Grid_Size_Z"])
+
+    for x in tr:
+        k = (name(x), grid(x))
+        a = agg.setdefault(k, {"n": 0, "us": 0.0, "f": 0.0, "w": 0.0, "nc": 0})
+        a["n"] += 1
+        a["us"] += (int(x["End_Timestamp"]) - int(x["Start_Timestamp"])) * 1e-3
+    for src, key, fac in ((fe, "f", cf), (wr, "w", cw)):
+        cnt = {}
+        for x in src:
+            k = (name(x), grid(x))
+            if k in agg:
+                agg[k][key] += float(x["Counter_Value"]) * 1024.0 * fac
+                cnt[k] = cnt.get(k, 0) + 1
+        for k, c in cnt.items():
+            agg[k][key] /= c  # bytes per launch
+    span = (max(int(x["End_Timestamp"]) for x in tr) - int(tr[0]["Start_Timestamp"])) * 1e-6
+    busy = sum(a["us"] for a in agg.values()) * 1e-3
+    step_bytes = sum((a["f"] + a["w"]) * a["n"] for a in agg.values())
+    lines = [f"# One PISO step, {n}^3 fractured workload, {precision}: kernel times and HBM "
+             "traffic", "",
+             "Commands (from /tmp, `export TMPDIR=/tmp`; `<out>` is the output folder):", "",
+             "```", cmd_trace, cmd_counters, "```", "",
+             f"Calibration: a plain 1 GiB device copy reads FETCH_SIZE x {cf:.4f} and "
+             f"WRITE_SIZE x {cw:.4f} of the bytes it moves.", "",
+             f"Last step of the trace run: {len(tr)} launches, kernel time {busy:.3f} ms over a "
+             f"span of {span:.3f} ms (the tracer adds a few us per launch).  Counted HBM "
+             f"traffic of the step: {step_bytes / 1e9:.2f} GB = "
+             f"{step_bytes / cells:.0f} B per cell.", "",
+             "| kernel | threads | launches | avg us | ms | MB per launch | "
+             "B per cell | GB/s |", "|---|---:|---:|---:|---:|---:|---:|---:|"]
+    for (k, g), a in sorted(agg.items(), key=lambda kv: -kv[1]["us"]):
+        if a["us"] < 1.0:
+            continue
+        avg = a["us"] / a["n"]
+        mb = (a["f"] + a["w"]) / 1e6
+        lines.append(f"| `{k}` | {g} | {a['n']} | {avg:.1f} | {a['us'] / 1e3:.3f} | {mb:.1f} | "
+                     f"{(a['f'] + a['w']) / cells:.1f} | {(a['f'] + a['w']) / (avg * 1e-6) / 1e9:.0f} |")
+    ax = [a for (k, g), a in agg.items() if k == "k_axpy_dot"]
+    recs = [{"kernel": "step", "precision": precision, "n": n,
+             "traffic_bytes_per_launch": step_bytes, "sources": CSRC,
+             "sources_sha1": sources_sha1(CSRC)}]
+    if ax:
+        recs.append({"kernel": "axpy", "precision": precision, "n": n,
+                     "traffic_bytes_per_launch": ax[0]["f"] + ax[0]["w"], "sources": CSRC,
+                     "sources_sha1": sources_sha1(CSRC)})
+    lines.append("")
+    for r in recs:
+        lines.append(f"<!-- bench-traffic {json.dumps(r)} -->")
+    return "\n".join(lines) + "\n"
+
+
+def step_roofline(run, cells, precision, ms, n):
+    """Whole-step figures: the algorithmic bytes of the stage model with the
+    last timed step's PCG iterations and predictor sweeps, over the measured
+    step time; and, when a committed counter summary of this workload and
+    source exists, the counted HBM bytes of one step over the same time."""
+    its, sw = run["p_iters"][-1], run["sweeps"][-1]
+    b_cell = alg_step_bytes_per_cell(precision, its, sw)
+    t = ms * 1e-3
+    out = {"alg_bytes_per_cell": b_cell, "p_iters": its, "predictor_sweeps": sw,
+           "alg_GBs": round(b_cell * cells / t / 1e9, 1),
+           "frac_alg": round(b_cell * cells / t / 1e9 / HBM_PEAK_GBS, 4)}
+    counted, src = measured_traffic("step", precision, n)
+    out["counter_bytes_per_step"] = counted
+    out["frac_counters"] = (round(counted / t / 1e9 / HBM_PEAK_GBS, 4) if counted else None)
+    if counted:
+        out["counter_source"] = src
+    return out
+
+
+def class_table(run, cells, precision, n, its, mgc):
+    """Per kernel class over one profiled step: milliseconds, and for the
+    classes with a byte model the algorithmic rate and fraction of peak.
+    The coarse multigrid sweeps (FP32, stored coefficients) read x, b, the
+    three face coefficients and the diagonal and write x (28 B per coarse
+    cell and sweep); at 256^3 the levels 128^3, 64^3 and 32^3 are cycled by
+    grid kernels, 2 mgc sweeps each per V-cycle, one V-cycle per PCG
+    iteration."""
+    allt = run.get("all") or {}
+    rs = 4 if precision == "mixed" else 8
+    out = {}
+    for k, (launches, kms) in sorted(allt.items(), key=lambda kv: -kv[1][1]):
+        e = {"ms": round(kms, 3), "launches": launches}
+        b = alg_bytes_per_cell(k, rs, True) * cells * launches
+        if k == "smooth_coarse" and precision == "mixed":
+            lv, cc = [], n // 2
+            while cc * cc * cc * 24 * 8 // 7 > 144000 and cc > 1:
+                lv.append(cc ** 3)
+                cc //= 2
+            b = 28.0 * 2 * mgc * sum(lv) * sum(its)
+        if b > 0 and kms > 0:
+            e["alg_GBs"] = round(b / (kms * 1e-3) / 1e9, 1)
+            e["frac"] = round(b / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+        out[k] = e
+    return out
 
 
 def copy_bandwidth():
@@ -161,13 +338,15 @@ def time_solver(case, precision, steps, warmup, prof_class=None, profile_all=Fal
     if dom and not graph:
         s.set_profiling(1 << dbs.Solver.kernel_class(dom))
     s.reset_profiling()
-    its = []
+    its, sweeps = [], []
     stats = (lambda: s.stats(0)) if batch else s.stats
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
         s.step(1)
-        its.append(stats()["p_iters"])
+        sts = stats()
+        its.append(sts["p_iters"])
+        sweeps.append(sts["mom_sweeps"])
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     log(f"  {steps} steps in {t1 - t0:.3f} s")
@@ -177,7 +356,8 @@ def time_solver(case, precision, steps, warmup, prof_class=None, profile_all=Fal
         its_all = [s.stats(i)["p_iters"] for i in range(len(case))]
         st["p_iters_max"] = [max(v[c] for v in its_all) for c in range(len(its_all[0]))]
     s.close()
-    return {"sec": t1 - t0, "p_iters": its, "kernel": dom, "ktimes": kt, "all": all_times,
+    return {"sec": t1 - t0, "p_iters": its, "sweeps": sweeps, "kernel": dom, "ktimes": kt,
+            "all": all_times,
             "stats": st, "tuning": tuning}
 
 
@@ -312,7 +492,24 @@ def main():
                     help="1: fused full sweeps on the fine level (else half sweeps)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration)")
+    ap.add_argument("--summarize-counters", metavar="DIR", default=None,
+                    help="print the markdown summary of a rocprofv3 step measurement in DIR "
+                         "(trace, fetch, write, cfetch, cwrite) and exit")
     args = ap.parse_args()
+    if args.summarize_counters:
+        d = args.summarize_counters
+        flags = ("--no-cpu --no-fp64 --no-graph --no-batch --no-flume --no-csf --no-reservoir "
+                 "--kernel axpy")
+        t = (f"rocprofv3 --kernel-trace --stats --output-format csv -d <out>/trace -o run -- "
+             f"python3 <repo>/bench.py {flags} --steps 3 --warmup 1")
+        c = "\n".join(f"rocprofv3 --pmc {p} --output-format csv -d <out>/{q} -o run -- python3 "
+                      f"<repo>/bench.py {flags} --steps 1 --warmup 0"
+                      for p, q in (("FETCH_SIZE", "fetch"), ("WRITE_SIZE", "write"))) + "\n" + \
+            "\n".join(f"rocprofv3 --pmc {p} --output-format csv -d <out>/{q} -o run -- python3 "
+                      f"<repo>/bench.py --copy-calibration"
+                      for p, q in (("FETCH_SIZE", "cfetch"), ("WRITE_SIZE", "cwrite")))
+        sys.stdout.write(summarize_counters(d, args.n, args.precision, t, c))
+        return
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -366,6 +563,10 @@ def main():
             roof["traffic_source"] = tsrc
         # context: the rate of torch's own device copy on the same box
         roof["torch_copy_GBs"] = round(copy_bandwidth(), 1)
+    if roof is not None:
+        roof["step"] = step_roofline(main_run, cells, args.precision, ms, args.n)
+        roof["classes"] = class_table(main_run, cells, args.precision, args.n,
+                                      main_run["p_iters"][-1], knobs["coarse_sweeps"])
 
     fp64 = None
     if not args.no_fp64 and args.precision == "mixed":

@@ -253,8 +253,9 @@ int dbs_batch_step(dbs_handle *h, int nsteps);
    exactly that many with converged samples masked and no host
    synchronisation inside.  If a sample has not converged within a budget,
    the step is redone eagerly from a saved copy of the state and the
-   budgets grow, so results equal eager stepping.  The saved state costs 5
-   cell arrays and one face array of device memory.  on > 1 starts from
+   budgets grow, so results equal eager stepping.  A step leaves the
+   buffers of alpha^n, U^n and F^n untouched (their roles move), so only
+   p_rgh is saved, one cell array of device memory.  on > 1 starts from
    budgets of on - 1 instead of measuring them (this exercises the recovery
    path when a budget is too small). */
 int dbs_set_graph(dbs_handle *h, int on);
@@ -266,17 +267,23 @@ int dbs_set_graph(dbs_handle *h, int on);
    bottom takes over (bottom_shift 0 or 1 levels coarser than the first that
    fits in LDS), then 1..4 sweeps on the coarse levels, fused full sweeps
    on the finest level or two half-sweep launches, then the planes per
-   fine-level tile (kz 2..16).  The state is unchanged afterwards.  Outputs
+   fine-level tile (kz 2..16); block-local coarse smoothing is left as set
+   (*coarse_block reports it).  The state is unchanged afterwards.  Outputs
    may be NULL; *ms receives the best solve time in milliseconds. */
 int dbs_autotune(dbs_handle *h, int *kz, int *sweeps, int *coarse_sweeps, int *bottom_shift,
-                 int *fused, double *ms);
+                 int *fused, int *coarse_block, double *ms);
 /* Set the same knobs by hand (kz = 0: the launch-size heuristic), and the
    planes per coarse-level tile or thread column kz_coarse (0: the launch-size
    heuristic, which keeps enough blocks to fill the chip; the autotuner leaves
-   it as set).  kz and kz_coarse in [0, 64], sweeps and coarse_sweeps in
-   [1, 8], bottom_shift in [0, 4]; else DBS_EINVAL. */
+   it as set).  coarse_block != 0 (FP32 V-cycle only): the coarse_sweeps
+   sweeps of each grid-cycled coarse level run in one launch, each block
+   smoothing a 16^3 tile in LDS with the cells around it held fixed (Jacobi
+   between tiles, Gauss-Seidel within; the post-sweeps transpose the
+   pre-sweeps, so the preconditioner stays symmetric).  kz and kz_coarse in
+   [0, 64], sweeps and coarse_sweeps in [1, 8], bottom_shift in [0, 4];
+   else DBS_EINVAL. */
 int dbs_set_tuning(dbs_handle *h, int kz, int kz_coarse, int sweeps, int coarse_sweeps,
-                   int bottom_shift, int fused);
+                   int bottom_shift, int fused, int coarse_block);
 
 /* Tests only (single-sample handles).  Solve the p_rgh pressure equation of
    this handle's mesh and boundary conditions, -div(rAU_f grad x) with outlet faces as Dirichlet

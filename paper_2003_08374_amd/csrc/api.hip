@@ -485,9 +485,9 @@ static int create_impl(int n, const dbs_grid *grids, const dbs_physics *phys, co
   h->phi = dmalloc(h, NC, rc); h->kinv = dmalloc(h, NC, rc);
   h->alpha = dmalloc(h, NC, rc); h->alpha_old = dmalloc(h, NC, rc);
   if (ctl->n_alpha_sub > 1) h->alpha3 = dmalloc(h, NC, rc);
-  h->U = dmalloc(h, 3 * NC, rc); h->U2 = dmalloc(h, 3 * NC, rc);
+  h->U = dmalloc(h, 3 * NC, rc); h->U2 = dmalloc(h, 3 * NC, rc); h->U3 = dmalloc(h, 3 * NC, rc);
   h->prgh = dmalloc(h, NC, rc); h->p = dmalloc(h, NC, rc);
-  h->F = dmalloc(h, NF, rc);
+  h->F = dmalloc(h, NF, rc); h->F2 = dmalloc(h, NF, rc);
   h->ml = dmalloc(h, NC, rc); h->mg = dmalloc(h, NC, rc); h->pc = dmalloc(h, NC, rc);
   h->cf = dmalloc(h, NC, rc);
   h->A = dmalloc(h, NF, rc); h->lam = dmalloc(h, NF, rc); h->rhoPhi = dmalloc(h, NF, rc);
@@ -682,6 +682,7 @@ static int step_body(Handle *h, TraceOut *tr, int budget, std::vector<int> *its_
     if (src) solve_rc = src;
     corrector_update(h, c == h->ctl.n_corr - 1);
   }
+  std::swap(h->F, h->F2);  // the corrected fluxes; F^n stays in F2
   if (budget <= 0) {
     // the pressure solves synchronised the stream: the predictor records
     // in host-mapped memory are final
@@ -708,38 +709,44 @@ static int eager_step(Handle *h, TraceOut *tr, std::vector<int> *its_out) {
   return rc;
 }
 
-// state arrays saved before a graph step: alpha | U (3) | p_rgh (cells), F (faces)
+// A step never overwrites the buffers of alpha^n, U^n and F^n (the roles
+// below move instead); p_rgh is solved in place, so a step that may be
+// redone saves it first.
 static void snapshot(Handle *h, bool save) {
-  const size_t NC = (size_t)h->NC;
-  double *S = h->snap;
-  auto mv = [&](double *live, double *saved, size_t n) {
-    if (save) copy_n(h, live, saved, n);
-    else copy_n(h, saved, live, n);
-  };
-  mv(h->alpha, S, NC);
-  mv(h->U, S + NC, 3 * NC);
-  mv(h->prgh, S + 4 * NC, NC);
-  mv(h->F, S + 5 * NC, (size_t)h->NF);
+  if (save) copy_n(h, h->prgh, h->snap, (size_t)h->NC);
+  else copy_n(h, h->snap, h->prgh, (size_t)h->NC);
 }
 
 // buffer roles of the state (the host side of a step permutes them)
 struct Roles {
-  double *alpha, *alpha_old, *alpha3, *U, *U2;
+  double *alpha, *alpha_old, *alpha3, *U, *U2, *U3, *F, *F2;
 };
-static Roles roles(const Handle *h) { return Roles{h->alpha, h->alpha_old, h->alpha3, h->U, h->U2}; }
+static Roles roles(const Handle *h) {
+  return Roles{h->alpha, h->alpha_old, h->alpha3, h->U, h->U2, h->U3, h->F, h->F2};
+}
 static void set_roles(Handle *h, const Roles &r) {
   h->alpha = r.alpha;
   h->alpha_old = r.alpha_old;
   h->alpha3 = r.alpha3;
   h->U = r.U;
   h->U2 = r.U2;
+  h->U3 = r.U3;
+  h->F = r.F;
+  h->F2 = r.F2;
 }
 
-// the roles a captured step leaves: the saturation stage's permutation, and
-// the predictor's result in buffer (budget % 2) of {U, U2}
+// the roles a captured step leaves: the saturation stage's permutation, the
+// predictor's result in U2 (odd budget) or U3 (even) with U^n moved to U3,
+// and the correctors' fluxes swapped into F
 static void replay_roles(Handle *h) {
   alpha_roles(h);
-  if (h->mom_budget & 1) std::swap(h->U, h->U2);
+  double *Un = h->U, *X = h->U2, *Y = h->U3;
+  double *to = (h->mom_budget & 1) ? X : Y;
+  if (h->ctl.mom_maxit <= 0) to = X;
+  h->U = to;
+  h->U2 = to == X ? Y : X;
+  h->U3 = Un;
+  std::swap(h->F, h->F2);
 }
 
 // One step in graph mode: the step is captured once per buffer-role
@@ -751,13 +758,16 @@ static int graph_step(Handle *h) {
   int rc = courant_check(h);
   if (rc) return rc;
   const int nc = h->ctl.n_corr;
+  // The predictor's budget keeps the parity of the sweeps it expects (two
+  // more), so a sample that converges on schedule needs no gather copy.
   auto set_budgets = [&](const std::vector<int> &its, int sweeps, bool grow) {
     for (int c = 0; c < nc; c++) {
       const int want = its[c] + std::max(2, its[c] / 4);
       h->graph_budget[c] = grow ? std::max(h->graph_budget[c] + 2, want) : want;
     }
-    const int mw = std::min(h->ctl.mom_maxit, sweeps + 1);
-    h->mom_budget = grow ? std::min(h->ctl.mom_maxit, std::max(h->mom_budget + 1, mw)) : mw;
+    const int mw = std::min(h->ctl.mom_maxit, sweeps + 2);
+    h->mom_budget = grow ? std::min(h->ctl.mom_maxit, std::max(h->mom_budget + 2, mw)) : mw;
+    h->slack_steps = 0;
   };
   if (h->graph_budget[0] == 0) {
     std::vector<int> its(nc, 0);
@@ -769,11 +779,11 @@ static int graph_step(Handle *h) {
     return DBS_OK;
   }
   if (!h->snap) {
-    h->snap = dmalloc(h, 5 * (size_t)h->NC + (size_t)h->NF, rc);
+    h->snap = dmalloc(h, (size_t)h->NC, rc);
     if (rc) return fail(h, rc, "snapshot allocation");
   }
   const Roles before = roles(h);
-  const GraphKey key{h->alpha, h->U};
+  const GraphKey key{h->alpha, h->U, h->F};
   auto it = h->graphs.find(key);
   if (it == h->graphs.end()) {
     hipGraph_t g = nullptr;
@@ -827,6 +837,23 @@ static int graph_step(Handle *h) {
   }
   if (ok) {
     for (int s = 0; s < ns; s++) h->st[s].steps++;
+    // Budgets only grow on a redo; when every corrector has kept a slack of
+    // two or more iterations for four replays in a row, they shrink to the
+    // largest count of those replays plus one (and the step is captured
+    // again), so masked iterations do not accumulate as the solves speed up.
+    bool slack = true;
+    for (int c = 0; c < nc; c++) {
+      int used = 0;
+      for (int s = 0; s < ns; s++) used = std::max(used, h->st[s].p_iters[c]);
+      h->used_max[c] = h->slack_steps == 0 ? used : std::max(h->used_max[c], used);
+      slack = slack && h->graph_budget[c] - used >= 2;
+    }
+    h->slack_steps = slack ? h->slack_steps + 1 : 0;
+    if (h->slack_steps >= 4) {
+      for (int c = 0; c < nc; c++) h->graph_budget[c] = h->used_max[c] + 1;
+      h->slack_steps = 0;
+      clear_graphs(h);
+    }
     return DBS_OK;
   }
   // redo eagerly from the saved state with the budgets raised
@@ -1187,12 +1214,12 @@ int dbs_set_graph(dbs_handle *H, int on) {
 }
 
 int dbs_autotune(dbs_handle *H, int *kz_out, int *sweeps_out, int *coarse_out, int *shift_out,
-                 int *fused_out, double *ms_out) {
+                 int *fused_out, int *cblock_out, double *ms_out) {
   if (!H) return DBS_EINVAL;
   Handle *h = &H->h;
   int rc = DBS_OK;
   if (!h->snap) {
-    h->snap = dmalloc(h, 5 * (size_t)h->NC + (size_t)h->NF, rc);
+    h->snap = dmalloc(h, (size_t)h->NC, rc);
     if (rc) return fail(h, rc, "snapshot allocation");
   }
   double *x0 = h->Rp;  // transport scratch, free once the transport is done
@@ -1207,9 +1234,9 @@ int dbs_autotune(dbs_handle *H, int *kz_out, int *sweeps_out, int *coarse_out, i
   corrector_assemble(h);
   copy_n(h, h->prgh, x0, (size_t)h->NC);
   struct Cand {
-    int kz, sweeps, coarse, shift, fused;
+    int kz, sweeps, coarse, shift, fused, cblock;
   };
-  Cand best{h->kz_fine, h->mg_pre, h->mgc, h->bottom_shift, h->fused_sweep};
+  Cand best{h->kz_fine, h->mg_pre, h->mgc, h->bottom_shift, h->fused_sweep, h->coarse_block};
   double best_ms = 1e300;
   auto trial = [&](const Cand &c) {
     h->kz_fine = c.kz;
@@ -1217,6 +1244,7 @@ int dbs_autotune(dbs_handle *H, int *kz_out, int *sweeps_out, int *coarse_out, i
     h->mgc = c.coarse;
     h->bottom_shift = c.shift;
     h->fused_sweep = c.fused;
+    h->coarse_block = c.cblock;
     if (pressure_retune(h)) return;
     int ok = 0;
     time_solve(h, x0, &ok);  // first run: caches and clocks
@@ -1227,20 +1255,22 @@ int dbs_autotune(dbs_handle *H, int *kz_out, int *sweeps_out, int *coarse_out, i
     }
   };
   for (int sw = 1; sw <= 3; sw++)
-    for (int shf = 0; shf <= 1; shf++) trial(Cand{0, sw, sw, shf, 1});
+    for (int shf = 0; shf <= 1; shf++) trial(Cand{0, sw, sw, shf, 1, 0});
   {
     const Cand b0 = best;
     for (int cs = 1; cs <= 4; cs++)
-      if (cs != b0.coarse) trial(Cand{0, b0.sweeps, cs, b0.shift, 1});
+      if (cs != b0.coarse) trial(Cand{0, b0.sweeps, cs, b0.shift, 1, 0});
   }
-  trial(Cand{0, best.sweeps, best.coarse, best.shift, 0});
+  trial(Cand{0, best.sweeps, best.coarse, best.shift, 0, best.cblock});
   const Cand mid = best;
-  for (int kz : {2, 4, 8, 16}) trial(Cand{kz, mid.sweeps, mid.coarse, mid.shift, mid.fused});
+  for (int kz : {2, 4, 8, 16})
+    trial(Cand{kz, mid.sweeps, mid.coarse, mid.shift, mid.fused, mid.cblock});
   h->kz_fine = best.kz;
   h->mg_pre = h->mg_post = best.sweeps;
   h->mgc = best.coarse;
   h->bottom_shift = best.shift;
   h->fused_sweep = best.fused;
+  h->coarse_block = best.cblock;
   rc = pressure_retune(h);
   // restore the state as it was before tuning
   set_roles(h, before);
@@ -1254,12 +1284,13 @@ int dbs_autotune(dbs_handle *H, int *kz_out, int *sweeps_out, int *coarse_out, i
   if (coarse_out) *coarse_out = best.coarse;
   if (shift_out) *shift_out = best.shift;
   if (fused_out) *fused_out = best.fused;
+  if (cblock_out) *cblock_out = best.cblock;
   if (ms_out) *ms_out = best_ms;
   return rc;
 }
 
 int dbs_set_tuning(dbs_handle *H, int kz, int kz_coarse, int sweeps, int coarse_sweeps,
-                   int shift, int fused) {
+                   int shift, int fused, int coarse_block) {
   if (!H || kz < 0 || kz > 64 || kz_coarse < 0 || kz_coarse > 64 || sweeps < 1 || sweeps > 8 ||
       coarse_sweeps < 1 || coarse_sweeps > 8 || shift < 0 || shift > 4)
     return DBS_EINVAL;
@@ -1267,6 +1298,7 @@ int dbs_set_tuning(dbs_handle *H, int kz, int kz_coarse, int sweeps, int coarse_
   hipStreamSynchronize(h->stream);
   h->kz_fine = kz;
   h->kz_coarse = kz_coarse;
+  h->coarse_block = coarse_block ? 1 : 0;
   h->mg_pre = h->mg_post = sweeps;
   h->mgc = coarse_sweeps;
   h->bottom_shift = shift;

@@ -75,6 +75,7 @@ struct Level {
   // grid kernels (pairs and single cells); samples restricted into it
   Shape one_all, pair_cyc, one_cyc, one_rc;
   Shape sw;  // coarse levels: 2.5-D tiles of the cycled samples (fused sweeps)
+  Shape cb;  // coarse levels: CB^3 tiles of the cycled samples (block-local smoothing)
   int sw_ok = 0;  // every cycled sample is deep enough in z for fused sweeps
 };
 
@@ -86,9 +87,11 @@ struct Timer {
 
 // one captured step (graph mode), keyed by the buffer roles it was captured with
 struct GraphKey {
-  const void *alpha, *U;
+  const void *alpha, *U, *F;
   bool operator<(const GraphKey &o) const {
-    return alpha != o.alpha ? alpha < o.alpha : U < o.U;
+    if (alpha != o.alpha) return alpha < o.alpha;
+    if (U != o.U) return U < o.U;
+    return F < o.F;
   }
 };
 
@@ -115,9 +118,12 @@ struct Handle {
   // state (alpha is double-buffered: alpha holds n+1 after the transport;
   // with sub-cycles a third buffer keeps alpha^n while the cycles alternate)
   double *alpha = nullptr, *alpha_old = nullptr, *alpha3 = nullptr;
-  double *U = nullptr, *U2 = nullptr;  // 3 x NC each
+  // U: the current velocity; U2, U3: the predictor's sweep buffers (the
+  // step leaves U^n in U3).  3 x NC each
+  double *U = nullptr, *U2 = nullptr, *U3 = nullptr;
   double *prgh = nullptr, *p = nullptr;
   double *F = nullptr;                 // faces
+  double *F2 = nullptr;                // the correctors' fluxes (swapped with F per step)
   // closures of the current alpha: k_rl/mu_l, k_rg/mu_g, p_c (0 in clear cells)
   double *ml = nullptr, *mg = nullptr, *pc = nullptr;
   double *cf = nullptr;  // f_l - alpha in porous cells, 0 in clear cells
@@ -171,6 +177,10 @@ struct Handle {
   // fused full sweeps on the fine level (else two half-sweep launches)
   int kz_fine = 0, bottom_shift = 0, fused_sweep = 1;
   int kz_coarse = 0;  // planes per coarse-level tile or thread column (0 = heuristic)
+  // FP32 V-cycle: the sweeps of a grid-cycled coarse level in one launch of
+  // block-local smoothing (Jacobi between CB^3 tiles) instead of global
+  // red-black sweeps
+  int coarse_block = 0;
 
   std::vector<dbs_stats> st;  // per sample
   double tnow = 0.0;          // time reached by the samples
@@ -179,8 +189,11 @@ struct Handle {
   // graph mode
   int graph_mode = 0;
   int graph_budget[16] = {0};  // PCG iterations per corrector in a captured step
+  int used_max[16] = {0};      // largest count per corrector over the slack run
+  int slack_steps = 0;         // replays in a row that left a slack of two or more
   std::map<GraphKey, hipGraphExec_t> graphs;
-  double *snap = nullptr;      // state snapshot for a step redone eagerly
+  double *snap = nullptr;      // p_rgh saved for a step redone eagerly (the other
+                               // fields keep their step-start buffers)
   // per-sample solve records (ns x 16 x NREC), host-mapped (host, device view)
   double *hrec = nullptr, *rec = nullptr;
 

@@ -431,23 +431,24 @@ __global__ void k_mom_init(int *__restrict__ mact, double *__restrict__ msc, int
   for (int q = 0; q < NMSC; q++) msc[(size_t)s * NMSC + q] = 0.0;
 }
 
-// After the sweeps: sample s ended in buffer (sweeps % 2) of {U0, U1}; the
-// samples whose parity differs from `par` copy their cells there, so that
-// every sample's predicted velocity is in buffer par.
+// After the sweeps: a sample that made n sweeps ended in X (n odd), Y (n
+// even) or, without sweeps, in Un; the samples whose buffer is not `to`
+// copy their cells there, so that every sample's predicted velocity is in
+// `to` (Un itself is never written).
 __global__ void __launch_bounds__(NTHREADS) k_mom_gather(Segs SG, const double *__restrict__ msc,
-                                                         double *__restrict__ U0,
-                                                         double *__restrict__ U1, int par) {
+                                                         const double *__restrict__ Un,
+                                                         const double *__restrict__ X,
+                                                         const double *__restrict__ Y,
+                                                         double *__restrict__ to) {
   const int cell_gb = xcd_remap(blockIdx.x, gridDim.x);
   const int cell_sg = find_seg(SG.bp, SG.ns, cell_gb);
-  const int own = ((int)msc[(size_t)cell_sg * NMSC + 1]) & 1;
-  if (own == par) return;
+  const int n = (int)msc[(size_t)cell_sg * NMSC + 1];
+  const double *src = n == 0 ? Un : ((n & 1) ? X : Y);
+  if (src == to) return;
   const Geom &G = SG.g[cell_sg];
   Cell P;
-  if (cell_of_thread(G, cell_gb - SG.bp[cell_sg], P)) {
-    const double *src = own ? U1 : U0;
-    double *dst = par ? U1 : U0;
-    for (int d = 0; d < 3; d++) dst[(size_t)d * G.vs + P.c] = src[(size_t)d * G.vs + P.c];
-  }
+  if (cell_of_thread(G, cell_gb - SG.bp[cell_sg], P))
+    for (int d = 0; d < 3; d++) to[(size_t)d * G.vs + P.c] = src[(size_t)d * G.vs + P.c];
 }
 
 // phiHbyA on the cell's faces and the pressure right-hand side
@@ -559,13 +560,15 @@ __global__ void __launch_bounds__(NTHREADS) k_face_body(Segs SG, Phys Ph, MomArg
 }
 
 // The predictor: assembly, then Jacobi sweeps until every sample's starting
-// residual is at most mom_tol ||B|| (or mom_maxit sweeps).  Sweep k reads
-// buffer k % 2 of {U, U2} and writes the other; a sample that has converged
-// skips the later sweeps, so its result sits in buffer (its sweeps) % 2, and
-// a last gather brings every sample into one buffer.  Eager: the flags of
-// sweep k are read by the host (host-mapped memory, one event per sweep)
-// while sweep k + 1 is already queued, so the device never drains; the
-// sweep launched past the last convergence finds no sample iterating.
+// residual is at most mom_tol ||B|| (or mom_maxit sweeps).  U^n stays
+// untouched (a graph step redone eagerly starts from it again): sweep 0
+// reads it and writes X = U2, later sweeps alternate between X and Y = U3.
+// A sample that has converged skips the later sweeps, so its result sits in
+// X or Y by the parity of its sweep count, and a last gather brings every
+// sample into one of them, which becomes U; U^n becomes U3.  Eager: the
+// flags of sweep k are read by the host (host-mapped memory, one event per
+// sweep) while sweep k + 1 is already queued, so the device never drains;
+// the sweep launched past the last convergence finds no sample iterating.
 // Budgeted (graph capture): exactly `budget` sweeps, no host reads.
 void momentum_predictor(Handle *h, int budget) {
   dim3 blk(BX, BY);
@@ -578,17 +581,28 @@ void momentum_predictor(Handle *h, int budget) {
   DBS_LAUNCH(h, KC_MISC, k_mom_init, dim3((ns + 255) / 256), dim3(256), h->mact, h->msc, ns,
              maxit > 0 ? 1 : 0);
   h->mom_last = 0;
-  if (maxit <= 0) return;
+  if (maxit <= 0) {
+    // U* = U^n, copied, so that U^n itself stays untouched
+    DBS_LAUNCH(h, KC_MISC, k_mom_gather, h->cgrid, blk, h->seg, (const double *)h->msc,
+               (const double *)h->U, (const double *)h->U2, (const double *)h->U3, h->U2);
+    double *Un = h->U;
+    h->U = h->U2;
+    h->U2 = h->U3;
+    h->U3 = Un;
+    return;
+  }
   const double tol2 = h->ctl.mom_tol * h->ctl.mom_tol;
   const int nb = h->cell.nblk;
-  double *buf[2] = {h->U, h->U2};
+  double *Un = h->U, *X = h->U2, *Y = h->U3;
   const bool graph = budget > 0;
   const int kmax = graph ? budget : maxit;
   int K = 0, par = -1;
   for (int k = 0; k < kmax; k++) {
+    const double *in = k == 0 ? Un : ((k & 1) ? X : Y);
+    double *out = (k & 1) ? Y : X;
     DBS_LAUNCH(h, KC_MOM_OFFDIAG, k_mom_jacobi, h->cgrid, blk, h->seg, M, (const double *)h->AN,
-               (const double *)buf[k & 1], (const double *)h->B, buf[(k + 1) & 1],
-               (const int *)h->mact, h->partials, nb, k == 0 ? 1 : 0);
+               in, (const double *)h->B, out, (const int *)h->mact, h->partials, nb,
+               k == 0 ? 1 : 0);
     DBS_LAUNCH(h, KC_MISC, k_mom_final, dim3(ns), dim3(1024), (const double *)h->partials, nb,
                (const int *)h->cell.bp, ns, h->mact, h->msc, h->dmsc, h->dmflag, k & 1, tol2,
                maxit, k == 0 ? 1 : 0);
@@ -609,12 +623,14 @@ void momentum_predictor(Handle *h, int budget) {
   }
   if (par < 0) par = K & 1;
   h->mom_last = K;
-  // single sample stopped by the host test: it already sits in buffer par
+  double *to = par ? X : Y;  // where a sample of K (resp. k) sweeps ended
+  // single sample stopped by the host test: it already sits in `to`
   if (!(ns == 1 && !graph && K < kmax))
-    DBS_LAUNCH(h, KC_MISC, k_mom_gather, h->cgrid, blk, h->seg, (const double *)h->msc, buf[0],
-               buf[1], par);
-  h->U = buf[par];
-  h->U2 = buf[1 - par];
+    DBS_LAUNCH(h, KC_MISC, k_mom_gather, h->cgrid, blk, h->seg, (const double *)h->msc,
+               (const double *)Un, (const double *)X, (const double *)Y, to);
+  h->U = to;
+  h->U2 = to == X ? Y : X;
+  h->U3 = Un;
 }
 
 void momentum_results(Handle *h, int *sweeps, double *relres, int *converged) {
@@ -635,11 +651,13 @@ void corrector_assemble(Handle *h) {
              h->phiH, h->rhs);
 }
 
+// the corrected fluxes go to F2 (F^n stays for a redone graph step); the
+// step swaps F and F2 after its last corrector
 void corrector_update(Handle *h, bool last) {
   dim3 blk(BX, BY);
   MomArgs M = mom_args(h);
   DBS_LAUNCH(h, KC_CORRECT, k_correct, h->cgrid, blk, h->seg, h->P, M, (const double *)h->HbyA,
-             (const double *)h->phiH, h->F, h->U, h->p, (int)last);
+             (const double *)h->phiH, h->F2, h->U, h->p, (int)last);
 }
 
 }  // namespace dbs

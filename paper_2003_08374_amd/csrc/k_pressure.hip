@@ -1916,6 +1916,102 @@ __global__ void __launch_bounds__(NT2) k_sweep25(OpB<R> LB, SH S, const B *__res
   }
 }
 
+// ------------------------------------------ block-local coarse smoothing
+//
+// All sweeps of a coarse level in one launch (FP32 V-cycle, stored
+// operator): a block owns a CB^3 tile and makes `sweeps` red-black
+// Gauss-Seidel sweeps over it in LDS, the cells around the tile held at
+// their values when the launch starts (Jacobi between tiles, Gauss-Seidel
+// within).  CB_ZERO (pre-smoothing): from x = 0, red then black.
+// CB_PROLONG (post-smoothing): from x = xin plus the parent's coarse
+// correction on the tile and its halo, black then red.  The post-smoother
+// is the transpose of the pre-smoother, so the V-cycle stays symmetric.
+// Each thread owns a column of 8 cells (4 of each colour) and keeps their
+// coefficients in registers; LDS holds the iterate with a one-cell halo.
+constexpr int CB = 16;                   // tile edge (cells)
+constexpr int CBT = 512;                 // threads per block
+constexpr int CBH = CB + 2;              // tile edge with the halo
+constexpr int CBQ = CB * CB * CB / CBT;  // cells per thread (a column in z)
+enum { CB_ZERO = 0, CB_PROLONG = 1 };
+
+__host__ __device__ inline int cb_tiles(int n0, int n1, int n2) {
+  return ((n0 + CB - 1) / CB) * ((n1 + CB - 1) / CB) * ((n2 + CB - 1) / CB);
+}
+
+template <int MODE>
+__global__ void __launch_bounds__(CBT) k_cblock(OpB<float> LB, SH S, const float *__restrict__ b,
+                                                const float *__restrict__ xin,
+                                                float *__restrict__ xout,
+                                                const float *__restrict__ xc, int sweeps,
+                                                const int *__restrict__ mask) {
+  static_assert(CB * CB * CB == CBT * CBQ && CBQ % 2 == 0, "tile columns");
+  __shared__ float sx[CBH * CBH * CBH];
+  int g, s, lb;
+  if (!locate(S, mask, g, s, lb)) return;
+  const Op<float> L = op_at(LB, s);
+  const LvS &Q = LB.ls[s];
+  const int n0 = L.n0, n1 = L.n1, n2 = L.n2;
+  b += Q.c0;
+  xout += Q.c0;
+  if (MODE == CB_PROLONG) xin += Q.c0;
+  const float *xcs = (MODE == CB_PROLONG && Q.cn0 > 0) ? xc + Q.cc0 : nullptr;
+  const int ntx = (n0 + CB - 1) / CB, nty = (n1 + CB - 1) / CB;
+  const int x0 = (lb % ntx) * CB, y0 = ((lb / ntx) % nty) * CB, z0 = (lb / (ntx * nty)) * CB;
+  const int t = threadIdx.x;
+  // the iterate on the tile and its halo (zero outside the mesh)
+  for (int e = t; e < CBH * CBH * CBH; e += CBT) {
+    const int i = x0 + e % CBH - 1, j = y0 + (e / CBH) % CBH - 1, k = z0 + e / (CBH * CBH) - 1;
+    float v = 0.f;
+    if (MODE == CB_PROLONG && i >= 0 && i < n0 && j >= 0 && j < n1 && k >= 0 && k < n2) {
+      v = xin[i + n0 * (j + n1 * k)];
+      if (xcs) v += xcs[(i >> 1) + Q.cn0 * ((j >> 1) + Q.cn1 * (k >> 1))];
+    }
+    sx[e] = v;
+  }
+  // own column: (i, j) and CBQ planes from kq
+  const int li = t % CB, lj = (t / CB) % CB, lk = (t / (CB * CB)) * CBQ;
+  const int i = x0 + li, j = y0 + lj;
+  float D[CBQ], Bv[CBQ], Txm[CBQ], Txp[CBQ], Tym[CBQ], Typ[CBQ], Tzm[CBQ], Tzp[CBQ];
+#pragma unroll
+  for (int q = 0; q < CBQ; q++) {
+    const int k = z0 + lk + q;
+    const bool in = i < n0 && j < n1 && k < n2;
+    const int c = in ? i + n0 * (j + n1 * k) : 0;
+    D[q] = in ? L.D[c] : 0.f;
+    Bv[q] = in ? b[c] : 0.f;
+    Txp[q] = in ? L.Tx[c] : 0.f;
+    Txm[q] = (in && i > 0) ? L.Tx[c - 1] : 0.f;
+    Typ[q] = in ? L.Ty[c] : 0.f;
+    Tym[q] = (in && j > 0) ? L.Ty[c - n0] : 0.f;
+    Tzp[q] = in ? L.Tz[c] : 0.f;
+    Tzm[q] = (in && k > 0) ? L.Tz[c - n0 * n1] : 0.f;
+  }
+  __syncthreads();
+  const int par0 = (i + j + z0 + lk) & 1;  // colour of the column's first cell
+  for (int sw = 0; sw < sweeps; sw++) {
+#pragma unroll
+    for (int hh = 0; hh < 2; hh++) {
+      const int color = MODE == CB_ZERO ? hh : 1 - hh;  // 0 = red (i + j + k even)
+#pragma unroll
+      for (int q = 0; q < CBQ; q++) {
+        if (((par0 + q) & 1) != color || !(D[q] > 0.f)) continue;
+        const int e = (li + 1) + CBH * ((lj + 1) + CBH * (lk + q + 1));
+        const float off = Txm[q] * sx[e - 1] + Txp[q] * sx[e + 1] + Tym[q] * sx[e - CBH] +
+                          Typ[q] * sx[e + CBH] + Tzm[q] * sx[e - CBH * CBH] +
+                          Tzp[q] * sx[e + CBH * CBH];
+        sx[e] = (Bv[q] + off) * sw_rcp(D[q]);
+      }
+      __syncthreads();
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < CBQ; q++) {
+    const int k = z0 + lk + q;
+    if (i < n0 && j < n1 && k < n2)
+      xout[i + n0 * (j + n1 * k)] = sx[(li + 1) + CBH * ((lj + 1) + CBH * (lk + q + 1))];
+  }
+}
+
 // Restriction after a pre-smoothing that ended with a black half sweep: the
 // black residual is zero, so the coarse right-hand side is the sum of the
 // red children's residuals.  Block tiles are 128 x 8 fine cells and walk
@@ -2203,6 +2299,10 @@ int pressure_retune(Handle *h) {
       L.sw_ok = 1;
       for (int s = 0; s < ns; s++)
         if (cyc(s) && L.hs[s].n2 < CSW_MIN_DEPTH) L.sw_ok = 0;
+      // block-local smoothing: one block per CB^3 tile
+      for (int s = 0; s < ns; s++)
+        blocks[s] = cyc(s) ? cb_tiles(L.hs[s].n0, L.hs[s].n1, L.hs[s].n2) : 0;
+      set_shape(h, L.cb, blocks, 1, rc);
     }
   }
   if (rc) return rc;
@@ -2497,6 +2597,7 @@ static R *vcycle(Handle *h, const R *rAUr, const B *b0, R *z0, R *z1, bool dot =
   // also leaves its result.  ccur[l] holds the pre-smoothed iterate.
   constexpr bool flexr = std::is_same<R, float>::value;
   const bool cfused = flexr && h->fused_sweep;
+  const bool cblock = flexr && h->coarse_block;
   std::vector<R *> ccur(h->lv.size(), nullptr), coth(h->lv.size(), nullptr);
   for (int l = 1; l < h->maxbottom; l++) {
     OpB<R> o = opb<R>(h, l, rAUr);
@@ -2505,7 +2606,13 @@ static R *vcycle(Handle *h, const R *rAUr, const B *b0, R *z0, R *z1, bool dot =
     ccur[l] = lx<R>(L);
     const bool lf = cfused && L.sw_ok;
     if constexpr (flexr) {
-      if (lf) {
+      if (cblock && L.cb.nblk) {
+        // all pre-sweeps of the level in one launch, into xf2
+        DBS_LAUNCH(h, KC_SMOOTHC, k_cblock<CB_ZERO>, dim3(L.cb.nblk), dim3(CBT), o,
+                   sh(h, L.cb), (const float *)lb<R>(L), (const float *)nullptr, (float *)L.xf2,
+                   (const float *)nullptr, h->mgc, act);
+        ccur[l] = (R *)L.xf2;
+      } else if (lf) {
         R *a = (R *)L.xf2, *b2 = lx<R>(L);
         sweep_coarse(h, l, o, (const R *)lb<R>(L), (const R *)nullptr, a, 0, SW_ZERO,
                      (const R *)nullptr);
@@ -2518,7 +2625,7 @@ static R *vcycle(Handle *h, const R *rAUr, const B *b0, R *z0, R *z1, bool dot =
         coth[l] = b2;
       }
     }
-    if (!lf) smooth_level<R, R>(h, l, o, (const R *)lb<R>(L), lx<R>(L), true);
+    if (!lf && !(cblock && L.cb.nblk)) smooth_level<R, R>(h, l, o, (const R *)lb<R>(L), lx<R>(L), true);
     if (C.one_rc.nblk)
       DBS_LAUNCH(h, KC_RESTRICTC, (k_restrict<R, R>), dim3(C.one_rc.nblk), blk(), o,
                  sh(h, C.one_rc), (const R *)lb<R>(L), (const R *)ccur[l], lb<R>(C), act,
@@ -2532,6 +2639,14 @@ static R *vcycle(Handle *h, const R *rAUr, const B *b0, R *z0, R *z1, bool dot =
     Level &L = h->lv[l];
     Level &C = h->lv[l + 1];
     if constexpr (flexr) {
+      if (cblock && L.cb.nblk) {
+        // the prolongation and all post-sweeps in one launch: xf2 -> xf,
+        // where the finer level's prolongation reads the correction
+        DBS_LAUNCH(h, KC_SMOOTHC, k_cblock<CB_PROLONG>, dim3(L.cb.nblk), dim3(CBT), o,
+                   sh(h, L.cb), (const float *)lb<R>(L), (const float *)L.xf2, (float *)lx<R>(L),
+                   (const float *)lx<R>(C), h->mgc, act);
+        continue;
+      }
       if (cfused && L.sw_ok) {
         // the prolongation rides on the first (black) sweep
         R *a = ccur[l], *b2 = coth[l];

@@ -126,8 +126,8 @@ def lib():
         L.dbs_batch_get_state_dev.argtypes = [H, C.c_int] + [C.c_void_p] * 6
         L.dbs_batch_get_stats.argtypes = [H, C.c_int, C.POINTER(Stats)]
         L.dbs_set_graph.argtypes = [H, C.c_int]
-        L.dbs_autotune.argtypes = [H] + [C.POINTER(C.c_int)] * 5 + [_DP]
-        L.dbs_set_tuning.argtypes = [H] + [C.c_int] * 6
+        L.dbs_autotune.argtypes = [H] + [C.POINTER(C.c_int)] * 6 + [_DP]
+        L.dbs_set_tuning.argtypes = [H] + [C.c_int] * 7
         L.dbs_set_time.argtypes = [H, C.c_double]
         L.dbs_pressure_solve_noalloc.argtypes = [C.POINTER(Grid), C.POINTER(C.c_int), C.c_int,
                                                  C.c_void_p, C.c_void_p, C.c_void_p, C.c_double,
@@ -253,19 +253,21 @@ class _Handle:
     def autotune(self):
         """Tune tile depth, sweeps, coarse sweeps, bottom depth and sweep
         fusion on the current state (which is left unchanged)."""
-        v = [C.c_int() for _ in range(5)]
+        v = [C.c_int() for _ in range(6)]
         ms = C.c_double()
         self._check(lib().dbs_autotune(self.h, *[C.byref(x) for x in v], C.byref(ms)))
         return {"kz": v[0].value, "sweeps": v[1].value, "coarse_sweeps": v[2].value,
-                "bottom_shift": v[3].value, "fused": v[4].value, "ms": ms.value}
+                "bottom_shift": v[3].value, "fused": v[4].value, "coarse_block": v[5].value,
+                "ms": ms.value}
 
     def set_time(self, t):
         self._check(lib().dbs_set_time(self.h, float(t)))
 
     def set_tuning(self, kz=0, sweeps=2, coarse_sweeps=2, bottom_shift=0, fused=1,
-                   kz_coarse=0):
+                   kz_coarse=0, coarse_block=0):
         self._check(lib().dbs_set_tuning(self.h, int(kz), int(kz_coarse), int(sweeps),
-                                         int(coarse_sweeps), int(bottom_shift), int(fused)))
+                                         int(coarse_sweeps), int(bottom_shift), int(fused),
+                                         int(coarse_block)))
 
     @staticmethod
     def _stats_dict(s, n):

@@ -186,6 +186,7 @@ def test_autotune_keeps_state_and_converges():
         assert knobs["sweeps"] in (1, 2, 3) and knobs["bottom_shift"] in (0, 1)
         assert knobs["coarse_sweeps"] in (1, 2, 3, 4) and knobs["fused"] in (0, 1)
         assert knobs["kz"] in (0, 2, 4, 8, 16) and knobs["ms"] > 0
+        assert knobs["coarse_block"] == 0  # FP64: block-local smoothing is FP32 only
         s.step(2)
         out = s.state()
         assert max(s.stats()["p_relres"]) <= 1e-13
