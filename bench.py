@@ -261,6 +261,11 @@ def class_table(run, cells, precision, n, its, mgc):
     for k, (launches, kms) in sorted(allt.items(), key=lambda kv: -kv[1][1]):
         e = {"ms": round(kms, 3), "launches": launches}
         b = alg_bytes_per_cell(k, rs, True) * cells * launches
+        if k == "residual":
+            # the true residual is launched every iteration but works only
+            # where it is wanted: the initial residual and the confirming
+            # check of each solve (the other launches exit at once)
+            b = alg_bytes_per_cell(k, rs, True) * cells * 2 * len(its)
         if k == "smooth_coarse" and precision == "mixed":
             lv, cc = [], n // 2
             while cc * cc * cc * 24 * 8 // 7 > 144000 and cc > 1:
