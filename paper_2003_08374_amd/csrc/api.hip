@@ -644,8 +644,10 @@ static int step_body(Handle *h, TraceOut *tr, int budget, std::vector<int> *its_
   alpha_stage(h, tr && tr->alphaPhi ? h->phiH : nullptr);
   if (tr) {
     rc |= copy_out(h, tr->A, h->A, h->hG[0].nf);
-    rc |= copy_out(h, tr->Rp, h->Rp, h->hG[0].nc);
-    rc |= copy_out(h, tr->Rm, h->Rm, h->hG[0].nc);
+    double *Rp, *Rm;
+    alpha_final_R(h, &Rp, &Rm);
+    rc |= copy_out(h, tr->Rp, Rp, h->hG[0].nc);
+    rc |= copy_out(h, tr->Rm, Rm, h->hG[0].nc);
     rc |= copy_out(h, tr->alphaPhi, h->phiH, h->hG[0].nf);
   }
   momentum_predictor(h, budget > 0 ? h->mom_budget : 0);

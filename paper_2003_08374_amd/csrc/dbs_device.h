@@ -203,29 +203,43 @@ __device__ __forceinline__ double clamp01(double x, double lo, double hi) {
   return fmin(fmax(x, lo), hi);
 }
 
+// x^e for x >= 0.  The exponents of the usual closures (1, 2, 3, 1/2,
+// -1/2) are taken by multiplication or the square root, whose results are
+// within an ulp or two of the correctly rounded power; any other exponent
+// goes to pow.  The exponent is the same for the whole launch, so the
+// choice does not diverge.
+__device__ __forceinline__ double powc(double x, double e) {
+  if (e == 2.0) return x * x;
+  if (e == 1.0) return x;
+  if (e == 0.5) return sqrt(x);
+  if (e == 3.0) return x * x * x;
+  if (e == -0.5) return 1.0 / sqrt(x);
+  return pow(x, e);
+}
+
 // App. A.1 relative permeabilities divided by the viscosities (mobility per
 // unit permeability) and App. A.2 capillary pressure of one cell.
 __device__ inline void closures(const Phys &Ph, double a, double &ml, double &mg, double &pc) {
   double ae = clamp01((a - Ph.s_lirr) * Ph.inv_span_kr, 0.0, 1.0);
   double krl, krg;
   if (Ph.kr_model == M_BROOKS_COREY) {
-    krl = pow(ae, Ph.kr_m);
-    krg = pow(1.0 - ae, Ph.kr_m);
+    krl = powc(ae, Ph.kr_m);
+    krg = powc(1.0 - ae, Ph.kr_m);
   } else {
-    double t = pow(ae, Ph.inv_kr_m);
-    double u = 1.0 - pow(1.0 - t, Ph.kr_m);
+    double t = powc(ae, Ph.inv_kr_m);
+    double u = 1.0 - powc(1.0 - t, Ph.kr_m);
     krl = sqrt(ae) * u * u;
-    krg = sqrt(1.0 - ae) * pow(1.0 - t, 2.0 * Ph.kr_m);
+    krg = sqrt(1.0 - ae) * powc(1.0 - t, 2.0 * Ph.kr_m);
   }
   ml = krl / Ph.mu_l;
   mg = krg / Ph.mu_g;
   double s = (a - Ph.a_pcirr) * Ph.inv_span_pc;
   if (Ph.pc_model == M_BROOKS_COREY) {
     s = clamp01(s, Ph.eps_pc, 1.0);
-    pc = Ph.pc0 * pow(s, -Ph.pc_exp);
+    pc = Ph.pc0 * powc(s, -Ph.pc_exp);
   } else {
     s = clamp01(s, Ph.eps_pc, 1.0 - Ph.eps_pc);
-    pc = Ph.pc0 * pow(pow(s, -1.0 / Ph.pc_exp) - 1.0, 1.0 - Ph.pc_exp);
+    pc = Ph.pc0 * powc(powc(s, -1.0 / Ph.pc_exp) - 1.0, 1.0 - Ph.pc_exp);
   }
 }
 

@@ -245,6 +245,8 @@ void prof_collect(Handle *h);
 void alpha_stage(Handle *h, double *aphi = nullptr);
 // the buffer roles the stage leaves: alpha^{n+1} current, alpha^n kept
 void alpha_roles(Handle *h);
+// R+- of the last limiter iteration of the last transport cycle
+void alpha_final_R(Handle *h, double **Rp, double **Rm);
 void update_closures(Handle *h, int only = -1);  // pc/ml/mg/cf from the current alpha
 void init_flux(Handle *h, int only = -1);  // F from U (linear interpolation)
 // k_momentum.hip

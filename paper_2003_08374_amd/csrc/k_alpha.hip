@@ -3,18 +3,23 @@
 // Sec. 2.3 summary (interface compression in clear regions, Eq. (vr_porous)
 // in porous regions) and the MULES flux limiter (Sec. 3.2).
 //
-// Four passes over the cells (plus two per extra limiter iteration):
+// One transport cycle is M + 3 passes over the cells for M limiter
+// iterations:
 //   alpha_grad     cell gradient of alpha (for the compression flux)
 //   alpha_face     antidiffusive face flux A = F*alpha_VL + G - F*alpha_upwind
-//   alpha_bounds   local extrema, low-order provisional alpha, Q+-, P+-, and
-//                  the first iteration's R+- (face limiters all 1)
-//   alpha_R        cell limiter factors R+- of a later iteration (counts
-//                  limited counter-fluxes)
-//   alpha_lambda   face limiter = min over the two cells, never increasing
+//   alpha_bounds   local extrema, low-order provisional alpha, Q+-, and the
+//                  first iteration's R+- (face limiters all 1)
+//   alpha_iter     (M - 1 times) face limiters of an iteration (min over the
+//                  two cells, never increasing) and the next R+- (limited
+//                  counter-fluxes counted)
 //   alpha_update   the last iteration's face limiter, limited flux,
 //                  alpha^{n+1}, mass flux rhoPhi, closures
-// Every face is owned by the cell on its plus side (plus the last face of
-// each row, owned by the last cell), so all writes are race-free.
+// The passes are bound by FP64 arithmetic and load latency more than by
+// bandwidth, and run one cell per thread at high occupancy: a tiled variant
+// that kept A in LDS and formed the bounds in the same launch (one barrier
+// per plane, half the occupancy) took 30% longer than the two passes.  Every face is owned by the cell on its plus side (plus
+// the last face of each row, owned by the last cell), so all writes are
+// race-free; R+- and the face limiters alternate between two buffers.
 #include "dbs_internal.h"
 
 namespace dbs {
@@ -55,9 +60,11 @@ __device__ inline void grad_alpha(const Geom &G, const AlphaArgs &X, const Cell 
 // Antidiffusive flux of the face on the minus side of cell N along a
 // (zero on a domain face).  Every load of the upwind stencil and of the
 // porous form is issued before any branch; a domain face reads the cell
-// itself and is discarded.
+// itself and is discarded.  The axis is a compile-time constant, so the
+// cell's coordinates are indexed statically.
+template <int a>
 __device__ inline double face_antidiffusive(const Geom &G, const Phys &Ph, const AlphaArgs &X,
-                                            const Cell &N, int a, int f) {
+                                            const Cell &N, int f) {
   const bool bnd = on_boundary(G, N, a, 0);
   const int sa = stride_of(G, a);
   const int o = bnd ? N.c : N.c - sa, n = N.c;
@@ -73,12 +80,11 @@ __device__ inline double face_antidiffusive(const Geom &G, const Phys &Ph, const
   const double aU = fwd ? ao : an, aD = fwd ? an : ao;
   const double aUU = auu;
   const double FL = Ff * aU;
-  double avl = aU;
-  if (aD != aU) {
-    double r = (aU - aUU) / (aD - aU);
-    double psi = (r + fabs(r)) / (1.0 + fabs(r));
-    avl = aU + 0.5 * psi * (aD - aU);
-  }
+  // Van Leer: aU + psi(r) (aD - aU) / 2 with psi(r) = (r + |r|) / (1 + |r|)
+  // and r = d0 / d1 (d0 = aU - aUU, d1 = aD - aU) is aU + d0 d1 / (d0 + d1)
+  // where d0 d1 > 0 and aU elsewhere: one division instead of two
+  const double d0 = aU - aUU, d1 = aD - aU;
+  const double avl = d0 * d1 > 0.0 ? aU + d0 * d1 / (d0 + d1) : aU;
   double Gr;
   Cell O = shifted(G, N, a, bnd ? 0 : -1);
   if (ko == 0.0 && kn == 0.0) {
@@ -126,18 +132,6 @@ __global__ void __launch_bounds__(NTHREADS) k_alpha_grad(Segs SG, AlphaArgs X,
   }
 }
 
-__global__ void __launch_bounds__(NTHREADS) k_alpha_face(Segs SG, Phys Ph, AlphaArgs X,
-                                                         double *__restrict__ A) {
-  FOR_CELLS(SG, G, P) {
-#pragma unroll
-  for (int a = 0; a < 3; a++) {
-    const int f = face_of(G, P, a, 0);
-    A[f] = face_antidiffusive(G, Ph, X, P, a, f);
-    if (P.co[a] == G.n[a] - 1) A[face_of(G, P, a, 1)] = 0.0;
-  }
-  }
-}
-
 // low-order (upwind) flux of side s of cell P along a, oriented along +axis
 // (both candidate upwind values are loaded with the flux, before any
 // branch; a domain face reads the cell itself)
@@ -152,17 +146,34 @@ __device__ __forceinline__ double low_order_flux(const Geom &G, const double *__
   return Ff * (Ff >= 0.0 ? aown : anbr);
 }
 
-// also the cell factors R+- of the first limiter iteration (all face limiters
-// 1, so the limited sums equal P-+)
-__global__ void __launch_bounds__(NTHREADS) k_alpha_bounds(Segs SG, const double *__restrict__ alpha, const double *__restrict__ F,
-    const double *__restrict__ phi, const double *__restrict__ A, double *__restrict__ Qp,
-    double *__restrict__ Qm, double *__restrict__ Pin, double *__restrict__ Pout,
-    double *__restrict__ Rp, double *__restrict__ Rm, int nsub) {
+__global__ void __launch_bounds__(NTHREADS) k_alpha_face(Segs SG, Phys Ph, AlphaArgs X,
+                                                         double *__restrict__ A) {
+  FOR_CELLS(SG, G, P) {
+  A[face_of(G, P, 0, 0)] = face_antidiffusive<0>(G, Ph, X, P, face_of(G, P, 0, 0));
+  A[face_of(G, P, 1, 0)] = face_antidiffusive<1>(G, Ph, X, P, face_of(G, P, 1, 0));
+  A[face_of(G, P, 2, 0)] = face_antidiffusive<2>(G, Ph, X, P, face_of(G, P, 2, 0));
+#pragma unroll
+  for (int a = 0; a < 3; a++)
+    if (P.co[a] == G.n[a] - 1) A[face_of(G, P, a, 1)] = 0.0;
+  }
+}
+
+
+// Local extrema, the low-order provisional alpha and Q+- of each cell, and
+// the cell factors R+- of the first limiter iteration (all face limiters 1,
+// so the limited sums equal P-+).  P+- are not kept: the later iterations
+// form them again from A.
+__global__ void __launch_bounds__(NTHREADS) k_alpha_bounds(Segs SG, const double *__restrict__ alpha,
+    const double *__restrict__ F, const double *__restrict__ phi, const double *__restrict__ A,
+    double *__restrict__ Qp, double *__restrict__ Qm, double *__restrict__ Rp,
+    double *__restrict__ Rm, int nsub) {
   FOR_CELLS(SG, G, P) {
   const double aP = alpha[P.c];
   double outL = 0.0, amax = aP, amin = aP, pin = 0.0, pout = 0.0;
+#pragma unroll
   for (int a = 0; a < 3; a++) {
     if (G.n[a] == 1 && G.bck[2 * a] == BC_EMPTY) continue;
+#pragma unroll
     for (int s = 0; s < 2; s++) {
       const double so = s ? 1.0 : -1.0;
       const int f = face_of(G, P, a, s);
@@ -189,52 +200,46 @@ __global__ void __launch_bounds__(NTHREADS) k_alpha_bounds(Segs SG, const double
   const double qp = vol * fmax(0.0, amax - aL), qm = vol * fmax(0.0, aL - amin);
   Qp[P.c] = qp;
   Qm[P.c] = qm;
-  Pin[P.c] = pin;
-  Pout[P.c] = pout;
   Rp[P.c] = pin > 0.0 ? clamp01((qp + pout) / pin, 0.0, 1.0) : 1.0;
   Rm[P.c] = pout > 0.0 ? clamp01((qm + pin) / pout, 0.0, 1.0) : 1.0;
   }
 }
 
-__global__ void __launch_bounds__(NTHREADS) k_alpha_R(Segs SG, const double *__restrict__ A, const double *__restrict__ lam, int first,
-    const double *__restrict__ Qp, const double *__restrict__ Qm, const double *__restrict__ Pin,
-    const double *__restrict__ Pout, double *__restrict__ Rp, double *__restrict__ Rm) {
+// One further limiter iteration: the face limiters lam_k = min(lam_{k-1},
+// the factor of R_k at the face's two cells) of the cell's six faces (each
+// interior face formed by both its cells with the same arithmetic; the
+// owned faces stored), and the cell's next R+- with the limited
+// counter-fluxes counted.  first: lam_{k-1} is 1 everywhere (k = 1).
+__global__ void __launch_bounds__(NTHREADS) k_alpha_iter(Segs SG, const double *__restrict__ A,
+    const double *__restrict__ Rp, const double *__restrict__ Rm,
+    const double *__restrict__ lam_in, int first, const double *__restrict__ Qp,
+    const double *__restrict__ Qm, double *__restrict__ lam_out, double *__restrict__ Rp_out,
+    double *__restrict__ Rm_out) {
   FOR_CELLS(SG, G, P) {
-  double lout = 0.0, lin = 0.0;
+  double lout = 0.0, lin = 0.0, pin = 0.0, pout = 0.0;
   for (int a = 0; a < 3; a++) {
-    if (G.n[a] == 1 && G.bck[2 * a] == BC_EMPTY) continue;
     for (int s = 0; s < 2; s++) {
-      if (on_boundary(G, P, a, s)) continue;  // A = 0 on boundary faces
-      const double so = s ? 1.0 : -1.0;
       const int f = face_of(G, P, a, s);
-      const double l = first ? 1.0 : lam[f];
+      if (on_boundary(G, P, a, s)) {
+        // A = 0 on domain faces (and on both faces of an empty axis)
+        lam_out[f] = 0.0;
+        continue;
+      }
+      const double so = s ? 1.0 : -1.0;
+      const int nb = P.c + (s ? 1 : -1) * stride_of(G, a);
+      const int o = s ? P.c : nb, n = s ? nb : P.c;
       const double Af = A[f];
-      lout += l * fmax(0.0, so * Af);
-      lin += l * fmax(0.0, -so * Af);
+      const double l = Af >= 0.0 ? fmin(Rm[o], Rp[n]) : fmin(Rp[o], Rm[n]);
+      const double lf = first ? l : fmin(lam_in[f], l);
+      if (s == 0) lam_out[f] = lf;
+      lout += lf * fmax(0.0, so * Af);
+      lin += lf * fmax(0.0, -so * Af);
+      pin += fmax(0.0, -so * Af);
+      pout += fmax(0.0, so * Af);
     }
   }
-  const double pin = Pin[P.c], pout = Pout[P.c];
-  Rp[P.c] = pin > 0.0 ? clamp01((Qp[P.c] + lout) / pin, 0.0, 1.0) : 1.0;
-  Rm[P.c] = pout > 0.0 ? clamp01((Qm[P.c] + lin) / pout, 0.0, 1.0) : 1.0;
-  }
-}
-
-__global__ void __launch_bounds__(NTHREADS) k_alpha_lambda(Segs SG, const double *__restrict__ A,
-                                                           const double *__restrict__ Rp,
-                                                           const double *__restrict__ Rm,
-                                                           int first, double *__restrict__ lam) {
-  FOR_CELLS(SG, G, P) {
-  for (int a = 0; a < 3; a++) {
-    const int f = face_of(G, P, a, 0);
-    if (on_boundary(G, P, a, 0)) {
-      lam[f] = 0.0;
-    } else {
-      const int o = P.c - stride_of(G, a), n = P.c;
-      const double l = A[f] >= 0.0 ? fmin(Rm[o], Rp[n]) : fmin(Rp[o], Rm[n]);
-      lam[f] = first ? l : fmin(lam[f], l);
-    }
-    if (P.co[a] == G.n[a] - 1) lam[face_of(G, P, a, 1)] = 0.0;
-  }
+  Rp_out[P.c] = pin > 0.0 ? clamp01((Qp[P.c] + lout) / pin, 0.0, 1.0) : 1.0;
+  Rm_out[P.c] = pout > 0.0 ? clamp01((Qm[P.c] + lin) / pout, 0.0, 1.0) : 1.0;
   }
 }
 
@@ -392,39 +397,43 @@ __global__ void __launch_bounds__(NTHREADS) k_init_flux(Segs SG, const double *_
   }
 }
 
+// R+- of limiter iteration k (k = 1..M) alternate between (Rp, Rm) and
+// (Pin, Pout); the face limiters of iteration k between lam and FB (which
+// the momentum stage fills later in the step)
+static double *R_buf(Handle *h, int k, int sign) {
+  return ((k - 1) & 1) ? (sign ? h->Pin : h->Pout) : (sign ? h->Rp : h->Rm);
+}
+static double *lam_buf(Handle *h, int k) { return ((k - 1) & 1) ? h->FB : h->lam; }
+
+void alpha_final_R(Handle *h, double **Rp, double **Rm) {
+  *Rp = R_buf(h, h->ctl.mules_iter, 1);
+  *Rm = R_buf(h, h->ctl.mules_iter, 0);
+}
+
 // One transport sub-cycle: alpha_in -> alpha_out with dt / nsub.
 static void alpha_cycle(Handle *h, const double *ain, double *aout, int sub, int nsub,
                         double *aphi) {
   dim3 blk(BX, BY);
-  // the cell gradients borrow Qp, Qm and Pin, which the bounds pass fills later
-  AlphaArgs X{ain,   h->F,  h->phi, h->kinv, h->prgh, h->ml,
-              h->mg, h->pc, h->Qp,  h->Qm,   h->Pin};
-  DBS_LAUNCH(h, KC_ALPHA_FACE, k_alpha_grad, h->cgrid, blk, h->seg, X, h->Qp, h->Qm, h->Pin);
+  const int M = h->ctl.mules_iter;
+  // the cell gradients borrow HbyA, which the correctors fill later
+  double *gx = h->HbyA, *gy = h->HbyA + h->NC, *gz = h->HbyA + 2 * h->NC;
+  AlphaArgs X{ain, h->F, h->phi, h->kinv, h->prgh, h->ml, h->mg, h->pc, gx, gy, gz};
+  DBS_LAUNCH(h, KC_ALPHA_FACE, k_alpha_grad, h->cgrid, blk, h->seg, X, gx, gy, gz);
   DBS_LAUNCH(h, KC_ALPHA_FACE, k_alpha_face, h->cgrid, blk, h->seg, h->P, X, h->A);
   DBS_LAUNCH(h, KC_ALPHA_BOUNDS, k_alpha_bounds, h->cgrid, blk, h->seg, ain,
              (const double *)h->F, (const double *)h->phi, (const double *)h->A, h->Qp, h->Qm,
-             h->Pin, h->Pout, h->Rp, h->Rm, nsub);
-  // the last iteration's face factors are formed inside the update
-  for (int it = 0; it < h->ctl.mules_iter - 1; it++) {
-    int first = it == 0;
-    // the first iteration's R+- come from the bounds pass
-    if (!first)
-      DBS_LAUNCH(h, KC_ALPHA_LIMIT, k_alpha_R, h->cgrid, blk, h->seg, (const double *)h->A,
-                 (const double *)h->lam, first, (const double *)h->Qp, (const double *)h->Qm,
-                 (const double *)h->Pin, (const double *)h->Pout, h->Rp, h->Rm);
-    DBS_LAUNCH(h, KC_ALPHA_LIMIT, k_alpha_lambda, h->cgrid, blk, h->seg, (const double *)h->A,
-               (const double *)h->Rp, (const double *)h->Rm, first, h->lam);
-  }
-  // R+- of the last iteration (unless it is the first)
-  if (h->ctl.mules_iter > 1)
-    DBS_LAUNCH(h, KC_ALPHA_LIMIT, k_alpha_R, h->cgrid, blk, h->seg, (const double *)h->A,
-               (const double *)h->lam, 0, (const double *)h->Qp, (const double *)h->Qm,
-               (const double *)h->Pin, (const double *)h->Pout, h->Rp, h->Rm);
+             R_buf(h, 1, 1), R_buf(h, 1, 0), nsub);
+  for (int k = 1; k < M; k++)
+    DBS_LAUNCH(h, KC_ALPHA_LIMIT, k_alpha_iter, h->cgrid, blk, h->seg, (const double *)h->A,
+               (const double *)R_buf(h, k, 1), (const double *)R_buf(h, k, 0),
+               (const double *)lam_buf(h, k - 1), k == 1 ? 1 : 0, (const double *)h->Qp,
+               (const double *)h->Qm, lam_buf(h, k), R_buf(h, k + 1, 1), R_buf(h, k + 1, 0));
+  // the last iteration's face limiters are formed inside the update
   DBS_LAUNCH(h, KC_ALPHA_UPDATE, k_alpha_update, h->cgrid, blk, h->seg, h->P, ain,
              (const double *)h->F, (const double *)h->phi, (const double *)h->kinv,
-             (const double *)h->A, (const double *)h->Rp, (const double *)h->Rm,
-             (const double *)h->lam, h->ctl.mules_iter == 1 ? 1 : 0, aout, h->rhoPhi, h->ml,
-             h->mg, h->pc, h->cf, sub, nsub, aphi);
+             (const double *)h->A, (const double *)R_buf(h, M, 1),
+             (const double *)R_buf(h, M, 0), (const double *)lam_buf(h, M - 1), M == 1 ? 1 : 0,
+             aout, h->rhoPhi, h->ml, h->mg, h->pc, h->cf, sub, nsub, aphi);
 }
 
 // Buffer roles after the stage: the cycles alternate between alpha_old and
@@ -449,11 +458,11 @@ void alpha_stage(Handle *h, double *aphi) {
     cur = dst;
   }
   alpha_roles(h);
-  AlphaArgs X{h->alpha, h->F,  h->phi, h->kinv, h->prgh, h->ml,
-              h->mg,    h->pc, h->Qp,  h->Qm,   h->Pin};
+  AlphaArgs X{h->alpha, h->F, h->phi, h->kinv, h->prgh, h->ml, h->mg, h->pc,
+              nullptr, nullptr, nullptr};
   if (h->SK) {
     // surface tension coefficient from alpha^{n+1}; the gradients borrow
-    // Qp, Qm and Pin again (the limiter is done with them)
+    // Qp, Qm and Pin (the limiter is done with them)
     AlphaArgs Xn = X;
     Xn.alpha = h->alpha;
     DBS_LAUNCH(h, KC_CURV, k_alpha_grad, h->cgrid, blk, h->seg, Xn, h->Qp, h->Qm, h->Pin);
