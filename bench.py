@@ -327,6 +327,10 @@ def time_solver(case, precision, steps, warmup, prof_class=None, profile_all=Fal
         tuning = s.autotune()
     if graph:
         s.set_graph(True)
+        # graph replays settle their iteration budgets over the first steps
+        # (one eager step, the capture, four replays with slack, the capture
+        # with the shrunk budgets and its first replay): time the steady state
+        warmup = max(warmup, 8)
     s.step(warmup)
     all_times = None
     if profile_all:

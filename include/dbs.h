@@ -275,12 +275,16 @@ int dbs_autotune(dbs_handle *h, int *kz, int *sweeps, int *coarse_sweeps, int *b
 /* Set the same knobs by hand (kz = 0: the launch-size heuristic), and the
    planes per coarse-level tile or thread column kz_coarse (0: the launch-size
    heuristic, which keeps enough blocks to fill the chip; the autotuner leaves
-   it as set).  coarse_block != 0 (FP32 V-cycle only): the coarse_sweeps
-   sweeps of each grid-cycled coarse level run in one launch, each block
-   smoothing a 16^3 tile in LDS with the cells around it held fixed (Jacobi
-   between tiles, Gauss-Seidel within; the post-sweeps transpose the
-   pre-sweeps, so the preconditioner stays symmetric).  kz and kz_coarse in
-   [0, 64], sweeps and coarse_sweeps in [1, 8], bottom_shift in [0, 4];
+   it as set).  coarse_block (FP32 V-cycle only) picks the coarse-level
+   smoother: 0 (the default) exact red-black sweeps, walking planes of 2.5-D
+   tiles on levels of more than 2^20 cycled cells and on 8 x 8 x 4 tiles in
+   one pass below; 2 the plane walk and 3 the small tiles on every level;
+   1 block-local smoothing, where the coarse_sweeps sweeps of each
+   grid-cycled coarse level run in one launch, each block smoothing a 16^3
+   tile in LDS with the cells around it held fixed (Jacobi between tiles,
+   Gauss-Seidel within; the post-sweeps transpose the pre-sweeps, so the
+   preconditioner stays symmetric).  kz and kz_coarse in [0, 64], sweeps and
+   coarse_sweeps in [1, 8], bottom_shift in [0, 4], coarse_block in [0, 3];
    else DBS_EINVAL. */
 int dbs_set_tuning(dbs_handle *h, int kz, int kz_coarse, int sweeps, int coarse_sweeps,
                    int bottom_shift, int fused, int coarse_block);

@@ -1294,13 +1294,14 @@ int dbs_autotune(dbs_handle *H, int *kz_out, int *sweeps_out, int *coarse_out, i
 int dbs_set_tuning(dbs_handle *H, int kz, int kz_coarse, int sweeps, int coarse_sweeps,
                    int shift, int fused, int coarse_block) {
   if (!H || kz < 0 || kz > 64 || kz_coarse < 0 || kz_coarse > 64 || sweeps < 1 || sweeps > 8 ||
-      coarse_sweeps < 1 || coarse_sweeps > 8 || shift < 0 || shift > 4)
+      coarse_sweeps < 1 || coarse_sweeps > 8 || shift < 0 || shift > 4 || coarse_block < 0 ||
+      coarse_block > 3)
     return DBS_EINVAL;
   Handle *h = &H->h;
   hipStreamSynchronize(h->stream);
   h->kz_fine = kz;
   h->kz_coarse = kz_coarse;
-  h->coarse_block = coarse_block ? 1 : 0;
+  h->coarse_block = coarse_block;
   h->mg_pre = h->mg_post = sweeps;
   h->mgc = coarse_sweeps;
   h->bottom_shift = shift;

@@ -76,6 +76,8 @@ struct Level {
   Shape one_all, pair_cyc, one_cyc, one_rc;
   Shape sw;  // coarse levels: 2.5-D tiles of the cycled samples (fused sweeps)
   Shape cb;  // coarse levels: CB^3 tiles of the cycled samples (block-local smoothing)
+  Shape cs;  // coarse levels: 8 x 8 x 4 tiles of the cycled samples (small-tile sweeps)
+  long long cyc_cells = 0;  // cells of the cycled samples on this level
   int sw_ok = 0;  // every cycled sample is deep enough in z for fused sweeps
 };
 

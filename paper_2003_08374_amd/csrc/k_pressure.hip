@@ -2012,6 +2012,124 @@ __global__ void __launch_bounds__(CBT) k_cblock(OpB<float> LB, SH S, const float
   }
 }
 
+// ------------------------------------------ small-tile coarse sweeps
+//
+// One fused red-black Gauss-Seidel sweep of a coarse level (FP32, stored
+// operator) on 8 x 8 x 4 tiles, one cell per thread, with no plane
+// pipeline: the smaller coarse levels are too small for the 2.5-D walk to
+// pay for its prologue, and their launches are latency-bound.  The sweep is
+// exact, with the plane-walking sweep's arithmetic (each update reads the
+// same neighbours in the same order): the block loads the old iterate on
+// the tile with a two-cell ring and the coefficients and b on a one-cell
+// ring, relaxes the colour colA on the tile and its ring (the values the
+// other colour's update of the tile reads), then the other colour on the
+// tile.  MODE as k_sweep25 (SW_ZERO: from zero;
+// SW_PROLONG: xin plus the parent's coarse correction).
+constexpr int CSX = 8, CSY = 8, CSZ = 4;           // tile
+constexpr int CST = CSX * CSY * CSZ;               // threads per block
+constexpr int CXW = CSX + 4, CXH = CSY + 4, CXD = CSZ + 4;  // iterate, 2-cell ring
+constexpr int CRW = CSX + 2, CRH = CSY + 2, CRD = CSZ + 2;  // coefficients, 1-cell ring
+constexpr int CXN = CXW * CXH * CXD, CRN = CRW * CRH * CRD;
+
+__host__ __device__ inline int cs_tiles(int n0, int n1, int n2) {
+  return ((n0 + CSX - 1) / CSX) * ((n1 + CSY - 1) / CSY) * ((n2 + CSZ - 1) / CSZ);
+}
+
+template <int MODE>
+__global__ void __launch_bounds__(CST) k_csweep(OpB<float> LB, SH S, const float *__restrict__ b,
+                                                const float *__restrict__ xin,
+                                                float *__restrict__ xout, int colA,
+                                                const float *__restrict__ xc,
+                                                const int *__restrict__ mask) {
+  __shared__ float sx[CXN];          // old iterate (0 outside the mesh)
+  __shared__ float sc[8][CRN];       // b, D, T[0..5] of the ring-1 region
+  __shared__ float sa[CRN];          // new colour-A values of the region
+  int g, s, lb;
+  if (!locate(S, mask, g, s, lb)) return;
+  const Op<float> L = op_at(LB, s);
+  const LvS &Q = LB.ls[s];
+  const int n0 = L.n0, n1 = L.n1, n2 = L.n2;
+  const int sy = n0, sz = n0 * n1;
+  b += Q.c0;
+  if (MODE != SW_ZERO) xin += Q.c0;
+  xout += Q.c0;
+  const float *xcs = (MODE == SW_PROLONG && Q.cn0 > 0) ? xc + Q.cc0 : nullptr;
+  const int nbx = (n0 + CSX - 1) / CSX, nby = (n1 + CSY - 1) / CSY;
+  const int i0 = (lb % nbx) * CSX, j0 = ((lb / nbx) % nby) * CSY, k0 = (lb / (nbx * nby)) * CSZ;
+  const int t = threadIdx.x;
+  // old iterate on the tile and its two-cell ring
+  if (MODE != SW_ZERO) {
+#pragma unroll
+    for (int e = t; e < CXN; e += CST) {
+      const int i = i0 - 2 + e % CXW, j = j0 - 2 + (e / CXW) % CXH, k = k0 - 2 + e / (CXW * CXH);
+      float v = 0.0f;
+      if (i >= 0 && i < n0 && j >= 0 && j < n1 && k >= 0 && k < n2) {
+        v = xin[i + sy * j + sz * k];
+        if (MODE == SW_PROLONG && xcs)
+          v += xcs[(i >> 1) + Q.cn0 * ((j >> 1) + Q.cn1 * (k >> 1))];
+      }
+      sx[e] = v;
+    }
+  }
+  // b, diagonal and the six neighbour coefficients (0 on domain faces and
+  // outside the mesh) on the tile and its one-cell ring
+#pragma unroll
+  for (int e = t; e < CRN; e += CST) {
+    const int i = i0 - 1 + e % CRW, j = j0 - 1 + (e / CRW) % CRH, k = k0 - 1 + e / (CRW * CRH);
+    float v[8] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+    if (i >= 0 && i < n0 && j >= 0 && j < n1 && k >= 0 && k < n2) {
+      const int c = i + sy * j + sz * k;
+      v[0] = b[c];
+      v[1] = L.D[c];
+      v[2] = i > 0 ? L.Tx[c - 1] : 0.0f;
+      v[3] = i + 1 < n0 ? L.Tx[c] : 0.0f;
+      v[4] = j > 0 ? L.Ty[c - sy] : 0.0f;
+      v[5] = j + 1 < n1 ? L.Ty[c] : 0.0f;
+      v[6] = k > 0 ? L.Tz[c - sz] : 0.0f;
+      v[7] = k + 1 < n2 ? L.Tz[c] : 0.0f;
+    }
+#pragma unroll
+    for (int q = 0; q < 8; q++) sc[q][e] = v[q];
+  }
+  __syncthreads();
+  // colour A on the tile and its ring, from the old iterate
+  for (int e = t; e < CRN; e += CST) {
+    const int li = e % CRW, lj = (e / CRW) % CRH, lk = e / (CRW * CRH);
+    const int i = i0 - 1 + li, j = j0 - 1 + lj, k = k0 - 1 + lk;
+    float v = 0.0f;
+    const float D = sc[1][e];
+    if (((i + j + k) & 1) == colA && i >= 0 && i < n0 && j >= 0 && j < n1 && k >= 0 &&
+        k < n2 && D > 0.0f) {
+      if (MODE == SW_ZERO) {
+        v = sc[0][e] * sw_rcp(D);
+      } else {
+        const int x = (li + 1) + CXW * ((lj + 1) + CXH * (lk + 1));
+        const float off = sc[2][e] * sx[x - 1] + sc[3][e] * sx[x + 1] +
+                          sc[4][e] * sx[x - CXW] + sc[5][e] * sx[x + CXW] +
+                          sc[6][e] * sx[x - CXW * CXH] + sc[7][e] * sx[x + CXW * CXH];
+        v = (sc[0][e] + off) * sw_rcp(D);
+      }
+    }
+    sa[e] = v;
+  }
+  __syncthreads();
+  // the tile: colour A as relaxed, the other colour from the new A values
+  const int li = t % CSX + 1, lj = (t / CSX) % CSY + 1, lk = t / (CSX * CSY) + 1;
+  const int i = i0 + li - 1, j = j0 + lj - 1, k = k0 + lk - 1;
+  if (i < n0 && j < n1 && k < n2) {
+    const int e = li + CRW * (lj + CRH * lk);
+    float v = sa[e];
+    if (((i + j + k) & 1) != colA) {
+      const float D = sc[1][e];
+      const float off = sc[2][e] * sa[e - 1] + sc[3][e] * sa[e + 1] + sc[4][e] * sa[e - CRW] +
+                        sc[5][e] * sa[e + CRW] + sc[6][e] * sa[e - CRW * CRH] +
+                        sc[7][e] * sa[e + CRW * CRH];
+      v = D > 0.0f ? (sc[0][e] + off) * sw_rcp(D) : 0.0f;
+    }
+    xout[i + sy * j + sz * k] = v;
+  }
+}
+
 // Restriction after a pre-smoothing that ended with a black half sweep: the
 // black residual is zero, so the coarse right-hand side is the sum of the
 // red children's residuals.  Block tiles are 128 x 8 fine cells and walk
@@ -2303,6 +2421,13 @@ int pressure_retune(Handle *h) {
       for (int s = 0; s < ns; s++)
         blocks[s] = cyc(s) ? cb_tiles(L.hs[s].n0, L.hs[s].n1, L.hs[s].n2) : 0;
       set_shape(h, L.cb, blocks, 1, rc);
+      // small-tile sweeps: one block per 8 x 8 x 4 tile
+      L.cyc_cells = 0;
+      for (int s = 0; s < ns; s++) {
+        blocks[s] = cyc(s) ? cs_tiles(L.hs[s].n0, L.hs[s].n1, L.hs[s].n2) : 0;
+        if (cyc(s)) L.cyc_cells += (long long)L.hs[s].n0 * L.hs[s].n1 * L.hs[s].n2;
+      }
+      set_shape(h, L.cs, blocks, 1, rc);
     }
   }
   if (rc) return rc;
@@ -2537,14 +2662,39 @@ static void sweep_fine_dot(Handle *h, const OpB<float> &o, const float *b, const
                b, xin, xout, colA, xc, m, zold, h->partials, (int)Z.nblk);
 }
 
+// Levels of at most CS_MAX_CELLS cycled cells take the small-tile sweeps
+// (coarse_block 0); coarse_block 2 keeps the plane walk on every level and
+// 3 the small tiles.
+constexpr long long CS_MAX_CELLS = 1LL << 20;
+static bool small_tiles(const Handle *h, const Level &L) {
+  if (h->coarse_block == 3) return true;
+  if (h->coarse_block == 2) return false;
+  return L.cyc_cells <= CS_MAX_CELLS;
+}
+
 // one fused sweep on coarse level l (FP32, stored coefficients), xin -> xout
 static void sweep_coarse(Handle *h, int l, const OpB<float> &o, const float *b,
                          const float *xin, float *xout, int colA, int mode, const float *xc) {
+  const int *m = h->act;
+  if (small_tiles(h, h->lv[l])) {
+    const Shape &C = h->lv[l].cs;
+    if (!C.nblk) return;
+    const dim3 g(C.nblk);
+    const SH S = sh(h, C);
+    if (mode == SW_ZERO)
+      DBS_LAUNCH(h, KC_SMOOTHC, k_csweep<SW_ZERO>, g, dim3(CST), o, S, b, xin, xout, colA, xc, m);
+    else if (mode == SW_PROLONG)
+      DBS_LAUNCH(h, KC_SMOOTHC, k_csweep<SW_PROLONG>, g, dim3(CST), o, S, b, xin, xout, colA, xc,
+                 m);
+    else
+      DBS_LAUNCH(h, KC_SMOOTHC, k_csweep<SW_NORMAL>, g, dim3(CST), o, S, b, xin, xout, colA, xc,
+                 m);
+    return;
+  }
   const Shape &Z = h->lv[l].sw;
   if (!Z.nblk) return;
   const dim3 g(Z.nblk);
   const SH S = sh(h, Z);
-  const int *m = h->act;
   const float *nz = nullptr;
   double *np = nullptr;
   if (mode == SW_ZERO)
@@ -2597,7 +2747,7 @@ static R *vcycle(Handle *h, const R *rAUr, const B *b0, R *z0, R *z1, bool dot =
   // also leaves its result.  ccur[l] holds the pre-smoothed iterate.
   constexpr bool flexr = std::is_same<R, float>::value;
   const bool cfused = flexr && h->fused_sweep;
-  const bool cblock = flexr && h->coarse_block;
+  const bool cblock = flexr && h->coarse_block == 1;
   std::vector<R *> ccur(h->lv.size(), nullptr), coth(h->lv.size(), nullptr);
   for (int l = 1; l < h->maxbottom; l++) {
     OpB<R> o = opb<R>(h, l, rAUr);

@@ -297,6 +297,43 @@ def droplet(shape=(64, 64, 1), h=1e-4, radius_cells=16.0, width_cells=1.0, centr
                 pc={"model": "brooks_corey", "pc0": 1e3, "exp": 0.5})
 
 
+def capillary_rise(n_tube=40, ny=400, width=1e-3, height=20e-3, wall_cells=2,
+                   theta_deg=45.0, h0=8e-3, sigma=0.07, dt=2e-6, steps=30000, wall_alpha=None,
+                   name=None):
+    """Water rising in an air-filled 2D tube (the pore-scale capillary rise
+    of Sec. 4.2): a ``width`` x ``height`` slit of n_tube x ny clear cells
+    between porous walls of ``wall_cells`` columns each (k^-1 = 1e20 m^-2,
+    phi 0.5: impermeable), contact angle ``theta_deg`` on the clear/porous
+    faces, gravity -y.  The bottom face is a water reservoir (fixed p_rgh =
+    0, inflow carries alpha = 1), the top face is open to the air (fixed
+    p_rgh = 0, inflow carries alpha = 0).  The meniscus starts flat at
+    ``h0`` (a tanh profile one cell wide) in the tube and, unless
+    ``wall_alpha`` gives their saturation, in the walls (whose saturation
+    cannot change).  The
+    Jurin height 2 sigma cos(theta) / (rho_l g width) is 10.1 mm for the
+    defaults."""
+    nx = n_tube + 2 * wall_cells
+    hh = (width / n_tube, height / ny, width / n_tube)
+    shape = (nx, ny, 1)
+    x, y, z = _cell_centres(shape, hh)
+    alpha = 0.5 * (1.0 - np.tanh((y - h0) / hh[1]))
+    phi = np.ones((1, ny, nx))
+    kinv = np.zeros((1, ny, nx))
+    phi[:, :, :wall_cells] = phi[:, :, nx - wall_cells:] = 0.5
+    kinv[:, :, :wall_cells] = kinv[:, :, nx - wall_cells:] = 1e20
+    if wall_alpha is not None:
+        alpha[:, :, :wall_cells] = alpha[:, :, nx - wall_cells:] = wall_alpha
+    U = np.zeros((3, 1, ny, nx))
+    bc = [wall(), wall(), outlet(0.0, 1.0), outlet(0.0, 0.0), empty(), empty()]
+    nm = name or f"capillary_rise_{n_tube}x{ny}"
+    return Case(name=nm, shape=shape, h=hh, fluids=fluids(WATER, AIR),
+                g=(0.0, -GRAVITY, 0.0), bc=bc, phi=phi, kinv=kinv, alpha=alpha, U=U,
+                p_rgh=_zeros(shape), dt=dt, steps=steps, sigma=sigma,
+                contact_angle=float(np.deg2rad(theta_deg)),
+                kr={"model": "brooks_corey", "m": 2.0},
+                pc={"model": "brooks_corey", "pc0": 1e3, "exp": 0.5})
+
+
 def fractured_128():
     """128^3, one slab fracture, k seed 1, phi seed 2, 100 steps."""
     return fractured_3d(n=128, seed_k=1, seed_phi=2, fractures="slab", steps=100,

@@ -355,6 +355,20 @@ def test_csf_batch_of_drops_matches_oracle():
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_capillary_tube_matches_oracle(precision):
+    """The pore-scale capillary rise of Sec. 4.2 (a 1 x 20 mm tube of
+    40 x 400 cells of aspect ratio 2 between impermeable porous walls,
+    contact angle 45 degrees on the walls, a water reservoir below and open
+    air above, gravity): 5 steps against the oracle.  Exercises the
+    contact-line forcing, the fixed-pressure faces with backflow of either
+    phase and anisotropic cells."""
+    case = W.capillary_rise()
+    out, ref, st, _ = _run_both(case, 5, precision=precision)
+    tol = 1e-10 if precision == "fp64" else 1e-9
+    compare_states(out, ref, tol_alpha=tol, tol_l2=tol, label=f"capillary {precision}")
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_pcg_below_its_rounding_floor_stalls_without_diverging(precision):
     """Asked for a residual below what rounding allows (a static drop in a
     closed box at 1e-13), PCG restarts after each residual replacement: the

@@ -60,23 +60,29 @@ TILES = [(0, 0, 0), (2, 2, 0), (4, 8, 1), (8, 4, 0), (16, 8, 1), (16, 3, 1)]
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-@pytest.mark.parametrize("fused", [1, 0])
+@pytest.mark.parametrize("fused,coarse", [(1, 0), (1, 2), (0, 0)])
 @pytest.mark.parametrize("kz,kzc,shift", TILES, ids=lambda t: str(t))
-def test_forced_tile_depths_match_oracle(ragged_ref, kz, kzc, shift, fused, precision):
+def test_forced_tile_depths_match_oracle(ragged_ref, kz, kzc, shift, fused, coarse, precision):
     """Fine tiles of kz planes (partial last chunk: 37 = 2 x 16 + 5) and
     coarse tiles or columns of kzc planes (0: the heuristic), fused full
-    sweeps or half sweeps, two steps against the oracle.  The GPU solves to
-    1e-12: at this size the true residual's rounding floor is near 1e-13."""
+    sweeps or half sweeps, two steps against the oracle.  In the mixed
+    V-cycle with fused sweeps the coarse levels (34 x 23 x 19, 17 x 12 x 10)
+    take the small-tile sweeps by default (coarse 0) or the plane walk on
+    kzc-plane tiles (coarse 2).  The GPU solves to 1e-12: at this size the
+    true residual's rounding floor is near 1e-13."""
+    if precision == "fp64" and coarse == 2:
+        pytest.skip("the FP64 V-cycle's coarse levels take half sweeps either way")
     dbs = _dbs()
     case, ref, info = ragged_ref
     with dbs.Solver(case.replace(p_tol=1e-12), precision=precision) as s:
         s.set_tuning(kz=kz, kz_coarse=kzc, sweeps=2, coarse_sweeps=3, bottom_shift=shift,
-                     fused=fused)
+                     fused=fused, coarse_block=coarse)
         s.step(NSTEPS)
         out, st = s.state(), s.stats()
     tol = 1e-10 if precision == "fp64" else 1e-9
     compare_states(out, ref, tol_alpha=tol, tol_l2=tol,
-                   label=f"tiles kz={kz} kzc={kzc} shift={shift} fused={fused} {precision}")
+                   label=f"tiles kz={kz} kzc={kzc} shift={shift} fused={fused} "
+                         f"coarse={coarse} {precision}")
     assert max(st["p_relres"]) <= 1e-12
     assert st["max_div"] <= 1e-12 * st["p_bnorm"][-1] * (1 + 1e-9)
 
@@ -98,6 +104,27 @@ def test_block_local_coarse_smoothing_matches_oracle(ragged_ref, coarse_sweeps):
     compare_states(out, ref, tol_alpha=1e-9, tol_l2=1e-9,
                    label=f"block-local coarse sweeps={coarse_sweeps}")
     assert max(st["p_relres"]) <= 1e-12
+
+
+def test_small_tile_and_plane_walk_coarse_sweeps_agree(ragged_ref):
+    """The two exact coarse smoothers of the mixed V-cycle (small tiles and
+    the plane walk) relax with the same arithmetic (FP32 contraction may
+    differ): iteration counts within one, and the two converged states
+    agree far inside the mixed bar."""
+    dbs = _dbs()
+    case, ref, info = ragged_ref
+    outs = {}
+    for coarse in (2, 3):
+        with dbs.Solver(case.replace(p_tol=1e-12), precision="mixed") as s:
+            s.set_tuning(kz=0, sweeps=2, coarse_sweeps=3, bottom_shift=1, fused=1,
+                         coarse_block=coarse)
+            s.step(NSTEPS)
+            outs[coarse] = (s.state(), s.stats())
+    (a, sa), (b, sb) = outs[2], outs[3]
+    print("coarse smoothers", sa["p_iters"], sb["p_iters"], flush=True)
+    assert all(abs(x - y) <= 1 for x, y in zip(sa["p_iters"], sb["p_iters"]))
+    assert rel_l2(a["p_rgh"], b["p_rgh"]) <= 1e-10
+    assert rel_l2(a["U"], b["U"]) <= 1e-10
 
 
 def _c2_case():
