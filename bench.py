@@ -389,7 +389,36 @@ def cpu_baseline(n=64, steps=2):
                    f"oracle's Jacobi-CG cost per cell grows with n, so this sample "
                    f"flatters the CPU"),
         "seconds": dt,
+        "parity": parity_sample(O, W),
     }
+
+
+def parity_sample(O, W, n=48, steps=2):
+    """Per-field errors of the HIP path against the oracle (untimed, in the
+    CPU leg): a 48^3 instance of the benchmark generator, 2 steps, the
+    oracle's pressure solves to 1e-14 and the GPU's to 1e-13, FP64 and
+    mixed.  Relative L2 on p_rgh, U and F, max-abs on alpha."""
+    import numpy as np
+    from paper_2003_08374_amd import dbs
+
+    c = W.fractured_3d(n=n, seed_k=3, seed_phi=4, fractures="planes", frac_seed=5, n_frac=3,
+                       name=f"fractured_3d_{n}_planes")
+    ref, _ = O.step(c.replace(p_tol=1e-14, p_maxit=200000), O.initial_state(c), steps)
+    rel = lambda a, b: float(np.linalg.norm(np.ravel(a) - np.ravel(b)) /
+                             max(np.linalg.norm(np.ravel(b)), 1e-300))
+    out = {"workload": c.name, "steps": steps, "oracle_p_tol": 1e-14, "gpu_p_tol": 1e-13,
+           "bar": {"fp64": 1e-10, "mixed": 1e-9}}
+    for prec in ("fp64", "mixed"):
+        with dbs.Solver(c.replace(p_tol=1e-13), precision=prec) as s:
+            s.step(steps)
+            g = s.state()
+        out[prec] = {
+            "alpha_maxabs": float(np.max(np.abs(g["alpha"] - ref["alpha"]))),
+            "U_relL2": rel(g["U"], ref["U"]),
+            "p_rgh_relL2": rel(g["p_rgh"], ref["p_rgh"]),
+            "F_relL2": rel(np.concatenate(g["F"]), np.concatenate(ref["F"])),
+        }
+    return out
 
 
 def batch_leg(args):
