@@ -538,10 +538,12 @@ def main():
         d = args.summarize_counters
         flags = ("--no-cpu --no-fp64 --no-graph --no-batch --no-flume --no-csf --no-reservoir "
                  "--kernel axpy")
+        # the 13th step from rest: the last timed step of the default run
+        # (2 warm-up steps, one profiled step, 10 timed ones)
         t = (f"rocprofv3 --kernel-trace --stats --output-format csv -d <out>/trace -o run -- "
-             f"python3 <repo>/bench.py {flags} --steps 3 --warmup 1")
+             f"python3 <repo>/bench.py {flags} --steps 1 --warmup 12")
         c = "\n".join(f"rocprofv3 --pmc {p} --output-format csv -d <out>/{q} -o run -- python3 "
-                      f"<repo>/bench.py {flags} --steps 1 --warmup 0"
+                      f"<repo>/bench.py {flags} --steps 1 --warmup 12"
                       for p, q in (("FETCH_SIZE", "fetch"), ("WRITE_SIZE", "write"))) + "\n" + \
             "\n".join(f"rocprofv3 --pmc {p} --output-format csv -d <out>/{q} -o run -- python3 "
                       f"<repo>/bench.py --copy-calibration"
