@@ -108,7 +108,13 @@
  *       normals, |n_f| = |grad_f|/(|grad_f| + dN) (no interface, no term).
  *       theta is measured through the liquid (alpha = 1) phase; the wall
  *       being the face between the two cells, the same angle holds at every
- *       clear/porous face; 0 means not imposed;
+ *       clear/porous face; 0 means not imposed.  The same angle fixes
+ *       the wall-normal derivative of alpha in the clear cell, as a wall
+ *       contact-angle condition does: the curvature's Gauss gradient of a
+ *       clear cell next to a porous cell along an axis takes, on that axis,
+ *       the component that makes its normal meet the wall at theta given
+ *       its other components (the solid's own saturation, frozen, would
+ *       otherwise pin the contact line);
  *   R19 CFL-adaptive time step (Sec. 3.2: the march follows an imposed
  *       Courant number; no rule is printed): before every step
  *       dt <- min(dt_max, 1.2 dt, Co_target dt / Co), Co = dt max over cells
@@ -404,6 +410,37 @@ static void curvature(const mesh_t *m, const double *alpha, const double *kinv,
   const double th = m->cs->contact_angle;
   double *grad = (double *)malloc(sizeof(double) * 3 * (size_t)m->nc);
   gauss_grad(m, alpha, F, grad);
+  if (th > 0.0 && kinv) {
+    /* the wall-normal component of a clear cell's gradient next to a porous
+       cell: the one that makes the cell's normal meet the wall at theta
+       (n.n_w = -cos(theta) for n = grad(alpha)/|grad(alpha)|), given the
+       components along the other axes; a cell with porous cells on both
+       sides of an axis keeps its Gauss value there */
+    int *wall = (int *)calloc((size_t)m->nc * 3, sizeof(int));
+    double *g0 = (double *)malloc(sizeof(double) * 3 * (size_t)m->nc);
+    memcpy(g0, grad, sizeof(double) * 3 * (size_t)m->nc);
+    for (int f = 0; f < m->nf; f++) {
+      const face_t *Fc = &m->f[f];
+      if (Fc->kind == DBSO_EMPTY || Fc->bnd >= 0) continue;
+      const int po = kinv[Fc->own] > 0.0, pn = kinv[Fc->nbr] > 0.0;
+      if (po == pn) continue;
+      /* n_w . e_axis: +1 with the porous cell on the minus side */
+      if (!po) wall[Fc->own * 3 + Fc->axis] -= 1;
+      else wall[Fc->nbr * 3 + Fc->axis] += 1;
+    }
+    const double cot = cos(th) / sin(th);
+    for (int c = 0; c < m->nc; c++)
+      for (int a = 0; a < 3; a++) {
+        const int w = wall[c * 3 + a];
+        if (w != 1 && w != -1) continue;
+        double t2 = 0.0;
+        for (int b = 0; b < 3; b++)
+          if (b != a) t2 += g0[c * 3 + b] * g0[c * 3 + b];
+        grad[c * 3 + a] = -cot * sqrt(t2) * (double)w;
+      }
+    free(g0);
+    free(wall);
+  }
   double dN = 1e-8 / cbrt(m->V);
   for (int c = 0; c < m->nc; c++) kappa[c] = 0.0;
   for (int f = 0; f < m->nf; f++) {

@@ -382,6 +382,7 @@ static Phys make_phys(const dbs_physics *phys) {
   P.sigma = phys->sigma;
   P.ca_on = phys->contact_angle > 0.0 ? 1 : 0;
   P.cos_ca = cos(phys->contact_angle);
+  P.cot_ca = P.ca_on ? cos(phys->contact_angle) / sin(phys->contact_angle) : 0.0;
   return P;
 }
 

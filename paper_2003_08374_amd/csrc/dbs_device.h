@@ -28,6 +28,7 @@ struct Phys {
   double sigma;  // interfacial tension of the clear-fluid CSF force (0: off)
   int ca_on;     // a contact angle is imposed on clear/porous faces
   double cos_ca; // its cosine
+  double cot_ca; // and cotangent
 };
 
 // One sample (one mesh) of a batch.  Cell and face indices are absolute in

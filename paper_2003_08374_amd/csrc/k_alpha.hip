@@ -119,13 +119,38 @@ __device__ inline double face_antidiffusive(const Geom &G, const Phys &Ph, const
 }
 
 // grad(alpha) of every cell, read by the compression flux of clear faces
+// and by the curvature.  ca (the curvature's gradient with a contact angle
+// imposed): a clear cell next to a porous cell along an axis takes, on that
+// axis, the component that makes its normal meet the wall at the angle
+// (n.n_w = -cos(theta) for n = grad(alpha)/|grad(alpha)|, n_w from the
+// porous into the clear cell) given its other Gauss components; with
+// porous cells on both sides of an axis it keeps the Gauss value.
 __global__ void __launch_bounds__(NTHREADS) k_alpha_grad(Segs SG, AlphaArgs X,
                                                          double *__restrict__ gx,
                                                          double *__restrict__ gy,
-                                                         double *__restrict__ gz) {
+                                                         double *__restrict__ gz, int ca,
+                                                         double cot) {
   FOR_CELLS(SG, G, P) {
   double g[3];
   grad_alpha(G, X, P, g);
+  if (ca && X.kinv[P.c] == 0.0) {
+    const double g0[3] = {g[0], g[1], g[2]};
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+      if (G.n[a] == 1 && G.bck[2 * a] == BC_EMPTY) continue;
+      const int st = stride_of(G, a);
+      // n_w . e_axis summed over the porous neighbours along a
+      int w = 0;
+      if (!on_boundary(G, P, a, 0) && X.kinv[P.c - st] > 0.0) w += 1;
+      if (!on_boundary(G, P, a, 1) && X.kinv[P.c + st] > 0.0) w -= 1;
+      if (w == 0) continue;
+      double t2 = 0.0;
+#pragma unroll
+      for (int b = 0; b < 3; b++)
+        if (b != a) t2 += g0[b] * g0[b];
+      g[a] = -cot * sqrt(t2) * (double)w;
+    }
+  }
   gx[P.c] = g[0];
   gy[P.c] = g[1];
   gz[P.c] = g[2];
@@ -418,7 +443,7 @@ static void alpha_cycle(Handle *h, const double *ain, double *aout, int sub, int
   // the cell gradients borrow HbyA, which the correctors fill later
   double *gx = h->HbyA, *gy = h->HbyA + h->NC, *gz = h->HbyA + 2 * h->NC;
   AlphaArgs X{ain, h->F, h->phi, h->kinv, h->prgh, h->ml, h->mg, h->pc, gx, gy, gz};
-  DBS_LAUNCH(h, KC_ALPHA_FACE, k_alpha_grad, h->cgrid, blk, h->seg, X, gx, gy, gz);
+  DBS_LAUNCH(h, KC_ALPHA_FACE, k_alpha_grad, h->cgrid, blk, h->seg, X, gx, gy, gz, 0, 0.0);
   DBS_LAUNCH(h, KC_ALPHA_FACE, k_alpha_face, h->cgrid, blk, h->seg, h->P, X, h->A);
   DBS_LAUNCH(h, KC_ALPHA_BOUNDS, k_alpha_bounds, h->cgrid, blk, h->seg, ain,
              (const double *)h->F, (const double *)h->phi, (const double *)h->A, h->Qp, h->Qm,
@@ -465,7 +490,8 @@ void alpha_stage(Handle *h, double *aphi) {
     // Qp, Qm and Pin (the limiter is done with them)
     AlphaArgs Xn = X;
     Xn.alpha = h->alpha;
-    DBS_LAUNCH(h, KC_CURV, k_alpha_grad, h->cgrid, blk, h->seg, Xn, h->Qp, h->Qm, h->Pin);
+    DBS_LAUNCH(h, KC_CURV, k_alpha_grad, h->cgrid, blk, h->seg, Xn, h->Qp, h->Qm, h->Pin,
+               h->P.ca_on, h->P.cot_ca);
     DBS_LAUNCH(h, KC_CURV, k_curvature, h->cgrid, blk, h->seg, h->P, (const double *)h->Qp,
                (const double *)h->Qm, (const double *)h->Pin, (const double *)h->phi,
                (const double *)h->kinv, h->SK);

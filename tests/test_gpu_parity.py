@@ -368,6 +368,37 @@ def test_capillary_tube_matches_oracle(precision):
     compare_states(out, ref, tol_alpha=tol, tol_l2=tol, label=f"capillary {precision}")
 
 
+def test_capillary_rise_settles_at_the_jurin_height():
+    """Capillary rise (Sec. 4.2, Eq. (capillaryHeight)) run to equilibrium
+    on the GPU: water in a 1 mm tube between impermeable porous walls at a
+    45 degree contact angle, started at 8 mm, rises to the Jurin height
+    2 sigma cos(theta)/(rho g w) = 10.1 mm and oscillates about it with a
+    period of about 0.23 s (10 x 100 cells, steps of 20 us, graph replay).
+    The midpoint of the highest and lowest heights over the last 0.25 s
+    (one period, sampled every 0.02 s) is within 5 % of the Jurin height
+    (the paper's own run reached 8.8 mm, 13 % below, for an imposed 45
+    degrees)."""
+    dbs = _dbs()
+    c = W.capillary_rise(n_tube=10, ny=100, dt=2e-5).replace(p_tol=1e-8, p_maxit=2000,
+                                                               mom_tol=1e-8)
+    jurin = 2 * c.sigma * np.cos(c.contact_angle) / (c.fluids["rho_l"] * W.GRAVITY * 1e-3)
+    hy = 20e-3 / 100
+    heights = []
+    with dbs.Solver(c, precision="mixed") as s:
+        s.set_graph(True)
+        for k in range(25):
+            s.step(1000)
+            a = s.state()["alpha"].reshape(100, 14)
+            col = a[:, 7]
+            i = np.where((col[:-1] >= 0.5) & (col[1:] < 0.5))[0][-1]
+            heights.append((i + 0.5 + (col[i] - 0.5) / (col[i] - col[i + 1])) * hy)
+    print("capillary rise heights (mm)", np.round(np.array(heights) * 1e3, 3), flush=True)
+    assert max(heights) > 10.0e-3
+    last = heights[12:]
+    mid = 0.5 * (max(last) + min(last))
+    assert abs(mid / jurin - 1.0) < 0.05, (mid, jurin)
+
+
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_pcg_below_its_rounding_floor_stalls_without_diverging(precision):
     """Asked for a residual below what rounding allows (a static drop in a
