@@ -334,6 +334,42 @@ def capillary_rise(n_tube=40, ny=400, width=1e-3, height=20e-3, wall_cells=2,
                 pc={"model": "brooks_corey", "pc0": 1e3, "exp": 0.5})
 
 
+ETHANOL = {"rho": 789.0, "mu": 1.2e-3}
+
+
+def taylor_film(nx=280, ny=116, length=800e-6, width=100e-6, wall_cells=2, U_in=0.4,
+                sigma=0.022, theta_deg=20.0, dt=2e-8, steps=30000, name=None):
+    """Air driving ethanol out of a 2D micro-channel (the Taylor-film case of
+    Sec. 4.2): a ``length`` x ``width`` channel of nx x ny clear cells
+    between impermeable porous walls of ``wall_cells`` rows (k^-1 =
+    1e20 m^-2, phi 0.5, saturated with ethanol), contact angle
+    ``theta_deg``, no gravity.  Air enters at x- with U_in (inlet alpha =
+    0), the outlet at x+ holds p = 0 (ethanol on backflow); the channel is
+    full of ethanol moving at U_in except an air plug over the first tenth
+    (a one-cell tanh).  sigma = 0.022 N/m (ethanol-air, not given in the
+    paper).  The film left on the walls is R 1.34 Ca^(2/3) / (1 + 3.35
+    Ca^(2/3)) with R the half-width and Ca = mu U / sigma: 4.15 um here."""
+    nyt = ny + 2 * wall_cells
+    hh = (length / nx, width / ny, length / nx)
+    shape = (nx, nyt, 1)
+    x, y, z = _cell_centres(shape, hh)
+    alpha = 0.5 * (1.0 + np.tanh((x - 0.1 * length) / hh[0]))
+    phi = np.ones((1, nyt, nx))
+    kinv = np.zeros((1, nyt, nx))
+    phi[:, :wall_cells, :] = phi[:, nyt - wall_cells:, :] = 0.5
+    kinv[:, :wall_cells, :] = kinv[:, nyt - wall_cells:, :] = 1e20
+    alpha[:, :wall_cells, :] = alpha[:, nyt - wall_cells:, :] = 1.0
+    U = np.zeros((3, 1, nyt, nx))
+    U[0, :, wall_cells:nyt - wall_cells, :] = U_in
+    bc = [inlet((U_in, 0.0, 0.0), 0.0), outlet(0.0, 1.0), wall(), wall(), empty(), empty()]
+    nm = name or f"taylor_film_{nx}x{ny}"
+    return Case(name=nm, shape=shape, h=hh, fluids=fluids(ETHANOL, AIR), g=(0.0, 0.0, 0.0),
+                bc=bc, phi=phi, kinv=kinv, alpha=alpha, U=U, p_rgh=_zeros(shape), dt=dt,
+                steps=steps, sigma=sigma, contact_angle=float(np.deg2rad(theta_deg)),
+                kr={"model": "brooks_corey", "m": 2.0},
+                pc={"model": "brooks_corey", "pc0": 1e3, "exp": 0.5})
+
+
 def fractured_128():
     """128^3, one slab fracture, k seed 1, phi seed 2, 100 steps."""
     return fractured_3d(n=128, seed_k=1, seed_phi=2, fractures="slab", steps=100,
