@@ -107,15 +107,13 @@ def measured_traffic(kernel, precision, n):
     import hashlib
     import re
     for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
-        m = re.search(r"<!-- bench-traffic (\{.*?\}) -->", open(path).read())
-        if not m:
-            continue
-        rec = json.loads(m.group(1))
-        if (rec.get("kernel"), rec.get("precision"), rec.get("n")) != (kernel, precision, n):
-            continue
-        if "sources" not in rec or sources_sha1(rec["sources"]) != rec.get("sources_sha1"):
-            continue
-        return float(rec["traffic_bytes_per_launch"]), os.path.relpath(path, ROOT)
+        for m in re.finditer(r"<!-- bench-traffic (\{.*?\}) -->", open(path).read()):
+            rec = json.loads(m.group(1))
+            if (rec.get("kernel"), rec.get("precision"), rec.get("n")) != (kernel, precision, n):
+                continue
+            if "sources" not in rec or sources_sha1(rec["sources"]) != rec.get("sources_sha1"):
+                continue
+            return float(rec["traffic_bytes_per_launch"]), os.path.relpath(path, ROOT)
     return None, None
 
 
