@@ -231,3 +231,38 @@ def test_fractured_256_benchmark_invariants():
     print("256^3 mixed vs fp64", e, flush=True)
     assert e["p_rgh_relL2"] <= 1e-6 and e["U_relL2"] <= 1e-6 and e["F_relL2"] <= 1e-6
     assert e["alpha_maxabs"] <= 1e-8
+
+
+def test_batch_of_512_at_full_size_sampled_against_oracle():
+    """The benchmark's 512-sample batch (edges U{32..96}, 1.7e8 cells) at
+    full size with the benchmark's tuned launch shapes (fine tiles of 16
+    planes, 2 fine and 3 coarse sweeps, fused), two steps, FP64 and mixed.
+    Every sample keeps alpha in [0, 1] and its divergence below the solver
+    tolerance times ||b||; the three smallest samples (32^3, which the
+    oracle solves in a second) match the oracle run alone: FP64 at p_tol
+    1e-12 to the FP64 bar, mixed at the benchmark's 1e-8 per field (p_rgh,
+    U, F relative L2 <= 1e-7, alpha max-abs <= 1e-8)."""
+    dbs = _dbs()
+    cases = W.batch_cases(n_samples=512, seed=6, lo=32, hi=96)
+    small = sorted(range(len(cases)), key=lambda i: (cases[i].ncells, i))[:3]
+    refs = {i: O.step(cases[i].replace(p_tol=1e-14, p_maxit=200000),
+                      O.initial_state(cases[i]), 2)[0] for i in small}
+    for precision, p_tol in (("fp64", 1e-12), ("mixed", 1e-8)):
+        batch = [c.replace(p_tol=p_tol, p_maxit=500, mom_tol=1e-14 if precision == "fp64"
+                           else 1e-8) for c in cases]
+        with dbs.BatchSolver(batch, precision=precision) as B:
+            B.set_tuning(kz=16, sweeps=2, coarse_sweeps=3, bottom_shift=0, fused=1)
+            B.step(2)
+            for i in range(len(cases)):
+                st = B.stats(i)
+                assert -1e-9 <= st["alpha_min"] and st["alpha_max"] <= 1 + 1e-9, (i, st)
+                assert st["max_div"] <= p_tol * st["p_bnorm"][-1] * (1 + 1e-9) + 1e-300, (i, st)
+                assert max(st["p_relres"]) <= p_tol, (i, st)
+            outs = {i: B.state(i) for i in small}
+        for i in small:
+            if precision == "fp64":
+                compare_states(outs[i], refs[i], label=f"batch512 sample {i} fp64")
+            else:
+                e = compare_states(outs[i], refs[i], tol_l2=1e-7, tol_alpha=1e-8,
+                                   label=f"batch512 sample {i} mixed")
+                assert e["F_relL2"] <= 1e-7
