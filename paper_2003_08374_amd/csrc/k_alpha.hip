@@ -487,13 +487,14 @@ void alpha_stage(Handle *h, double *aphi) {
               nullptr, nullptr, nullptr};
   if (h->SK) {
     // surface tension coefficient from alpha^{n+1}; the gradients borrow
-    // Qp, Qm and Pin (the limiter is done with them)
+    // HbyA again (R+- of the last limiter iteration stay for the trace)
     AlphaArgs Xn = X;
     Xn.alpha = h->alpha;
-    DBS_LAUNCH(h, KC_CURV, k_alpha_grad, h->cgrid, blk, h->seg, Xn, h->Qp, h->Qm, h->Pin,
-               h->P.ca_on, h->P.cot_ca);
-    DBS_LAUNCH(h, KC_CURV, k_curvature, h->cgrid, blk, h->seg, h->P, (const double *)h->Qp,
-               (const double *)h->Qm, (const double *)h->Pin, (const double *)h->phi,
+    double *gx = h->HbyA, *gy = h->HbyA + h->NC, *gz = h->HbyA + 2 * h->NC;
+    DBS_LAUNCH(h, KC_CURV, k_alpha_grad, h->cgrid, blk, h->seg, Xn, gx, gy, gz, h->P.ca_on,
+               h->P.cot_ca);
+    DBS_LAUNCH(h, KC_CURV, k_curvature, h->cgrid, blk, h->seg, h->P, (const double *)gx,
+               (const double *)gy, (const double *)gz, (const double *)h->phi,
                (const double *)h->kinv, h->SK);
   }
 }

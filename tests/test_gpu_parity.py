@@ -93,23 +93,30 @@ def test_pressure_solve_matches_oracle(shape, closed):
 TRACED = ("A", "Rp", "Rm", "alphaPhi", "rAU", "Shat", "Ustar", "HbyA", "phiHbyA", "b")
 
 
-@pytest.mark.parametrize("name", ["layered_2d", "stress_limited", "random_3d"])
+@pytest.mark.parametrize("name", ["layered_2d", "stress_limited", "random_3d",
+                                  "stress_two_iterations_csf"])
 def test_first_step_intermediates_match_oracle(name):
     """One step: antidiffusive fluxes, the Zalesak cell factors R+- of the
     last limiter iteration and the limited flux, momentum diagonal and
     source, predicted U, HbyA, phiHbyA and the pressure RHS.  The
     limiter-stress case at dt 3e-3 limits many faces (its R+- are far from
-    1); the random 3D case has every face type."""
+    1); the random 3D case has every face type; the stress case with two
+    limiter iterations keeps the last R+- in the other buffer pair, with
+    surface tension and a contact angle on (their gradients borrow a work
+    array of the step)."""
     dbs = _dbs()
     case = {"layered_2d": W.layered_2d(n=24),
             "stress_limited": W.layered_2d_stress(n=32).replace(dt=3e-3),
-            "random_3d": PC.random_3d((9, 7, 6), seed=4)}[name].replace(p_tol=1e-14)
+            "random_3d": PC.random_3d((9, 7, 6), seed=4),
+            "stress_two_iterations_csf": W.layered_2d_stress(n=32).replace(
+                dt=3e-3, mules_iter=2, sigma=0.07, contact_angle=float(np.radians(70.0)))
+            }[name].replace(p_tol=1e-14)
     # a state with motion everywhere: advance the oracle a few steps first
     st, _ = O.step(case, O.initial_state(case), 3)
     _, _, tr = O.step(case, st, 1, trace=True)
     with dbs.Solver(case.replace(p_tol=1e-13), state=st) as s:
         g = s.trace_step()
-    if name == "stress_limited":
+    if name.startswith("stress"):
         assert min(tr["Rp"].min(), tr["Rm"].min()) < 0.9  # the limiter is active
     for k in TRACED:
         e = rel_l2(g[k], tr[k])
