@@ -359,13 +359,27 @@ def time_solver(case, precision, steps, warmup, prof_class=None, profile_all=Fal
     log(f"  {steps} steps in {t1 - t0:.3f} s")
     kt = s.kernel_times()
     st = stats()
+    sts_all = [s.stats(i) for i in range(len(case))] if batch else [st]
     if batch:
-        its_all = [s.stats(i)["p_iters"] for i in range(len(case))]
+        its_all = [v["p_iters"] for v in sts_all]
         st["p_iters_max"] = [max(v[c] for v in its_all) for c in range(len(its_all[0]))]
     s.close()
     return {"sec": t1 - t0, "p_iters": its, "sweeps": sweeps, "kernel": dom, "ktimes": kt,
-            "all": all_times,
-            "stats": st, "tuning": tuning}
+            "all": all_times, "stats": st, "tuning": tuning,
+            "invariants": invariants(sts_all, (case[0] if batch else case).p_tol)}
+
+
+def invariants(sts, p_tol):
+    """State checks after the last timed step, over every sample: the
+    discrete divergence of the corrected fluxes against the bound the last
+    converged pressure solve guarantees (p_tol ||b||), and the range of
+    alpha."""
+    ratio = max(v["max_div"] / (p_tol * v["p_bnorm"][-1]) if v["p_bnorm"][-1] > 0 else 0.0
+                for v in sts)
+    amin = min(v["alpha_min"] for v in sts)
+    amax = max(v["alpha_max"] for v in sts)
+    return {"max_div_over_bound": ratio, "div_within_bound": ratio <= 1.0 + 1e-9,
+            "alpha_range": [amin, amax]}
 
 
 def cpu_baseline(n=64, steps=2):
@@ -435,16 +449,19 @@ def batch_leg(args):
     out["mixed_tuned"] = {"value": cells / (rm["sec"] / args.steps),
                           "ms_per_step": rm["sec"] / args.steps * 1e3,
                           "tuning": rm["tuning"],
-                          "p_iters_max_last": rm["stats"].get("p_iters_max")}
+                          "p_iters_max_last": rm["stats"].get("p_iters_max"),
+                          "invariants": rm["invariants"]}
     rg = time_solver(cases, "mixed", args.steps, args.warmup, graph=True, tune=True)
     out["mixed_graph_tuned"] = {"value": cells / (rg["sec"] / args.steps),
                                 "ms_per_step": rg["sec"] / args.steps * 1e3,
                                 "tuning": rg["tuning"],
-                                "p_iters_max_last": rg["stats"].get("p_iters_max")}
+                                "p_iters_max_last": rg["stats"].get("p_iters_max"),
+                                "invariants": rg["invariants"]}
     r64 = time_solver(cases, "fp64", args.steps, args.warmup)
     out["fp64_eager"] = {"value": cells / (r64["sec"] / args.steps),
                          "ms_per_step": r64["sec"] / args.steps * 1e3,
-                         "p_iters_max_last": r64["stats"].get("p_iters_max")}
+                         "p_iters_max_last": r64["stats"].get("p_iters_max"),
+                         "invariants": r64["invariants"]}
     out["speedup_mixed_batched_vs_fp64"] = (max(out["mixed_tuned"]["value"],
                                                 out["mixed_graph_tuned"]["value"]) /
                                             out["fp64_eager"]["value"])
@@ -467,7 +484,9 @@ def flume_leg(args):
             "p_tol": args.p_tol, "value": cells / (rm["sec"] / args.steps),
             "ms_per_step": rm["sec"] / args.steps * 1e3, "tuning": rm["tuning"],
             "p_iters_max_last": rm["stats"].get("p_iters_max"),
-            "graph_ms_per_step": rg["sec"] / args.steps * 1e3}
+            "invariants": rm["invariants"],
+            "graph_ms_per_step": rg["sec"] / args.steps * 1e3,
+            "graph_invariants": rg["invariants"]}
 
 
 def csf_leg(args, case):
@@ -482,7 +501,7 @@ def csf_leg(args, case):
     return {"workload": case.name + "_csf", "sigma": cs.sigma,
             "value": cells / (r["sec"] / args.steps),
             "ms_per_step": r["sec"] / args.steps * 1e3,
-            "p_iters_last": r["p_iters"][-1],
+            "p_iters_last": r["p_iters"][-1], "invariants": r["invariants"],
             "curvature": {"ms_per_step": round(ms_k, 4), "launches_per_step": launches / args.steps,
                           "alg_bytes_per_cell": alg_bytes_per_cell("curvature", 4),
                           "achieved_GBs": round(alg_bytes_per_cell("curvature", 4) * cells /
@@ -500,7 +519,8 @@ def reservoir_leg(args):
     r = time_solver(cs, "mixed", args.steps, args.warmup)
     return {"workload": cs.name, "cells": cs.ncells, "p_tol": args.p_tol,
             "value": cs.ncells / (r["sec"] / args.steps),
-            "ms_per_step": r["sec"] / args.steps * 1e3, "p_iters_last": r["p_iters"][-1]}
+            "ms_per_step": r["sec"] / args.steps * 1e3, "p_iters_last": r["p_iters"][-1],
+            "invariants": r["invariants"]}
 
 
 def main():
@@ -611,13 +631,13 @@ def main():
         r64 = time_solver(case, "fp64", args.steps, args.warmup, prof_class=kname)
         fp64 = {"value": cells / (r64["sec"] / args.steps),
                 "ms_per_step": r64["sec"] / args.steps * 1e3,
-                "p_iters_last": r64["p_iters"][-1]}
+                "p_iters_last": r64["p_iters"][-1], "invariants": r64["invariants"]}
     graph = None
     if not args.no_graph:
         rg = time_solver(case, args.precision, args.steps, args.warmup, graph=True)
         graph = {"value": cells / (rg["sec"] / args.steps),
                  "ms_per_step": rg["sec"] / args.steps * 1e3,
-                 "p_iters_last": rg["p_iters"][-1]}
+                 "p_iters_last": rg["p_iters"][-1], "invariants": rg["invariants"]}
     batched = None if args.no_batch else batch_leg(args)
     flume = None if args.no_flume else flume_leg(args)
     csf = None if args.no_csf else csf_leg(args, case)
@@ -640,6 +660,7 @@ def main():
         "config": {"workload": case.name, "cells": cells, "precision": args.precision,
                    "p_tol": args.p_tol, "n_corr": case.n_corr, "dt": case.dt,
                    "p_iters_last_step": main_run["p_iters"][-1]},
+        "invariants": main_run["invariants"],
         "roofline": roof,
         "cpu_baseline": cpu,
         "fp64_same_tol": fp64,

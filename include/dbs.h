@@ -277,8 +277,9 @@ int dbs_autotune(dbs_handle *h, int *kz, int *sweeps, int *coarse_sweeps, int *b
    heuristic, which keeps enough blocks to fill the chip; the autotuner leaves
    it as set).  coarse_block (FP32 V-cycle only) picks the coarse-level
    smoother: 0 (the default) exact red-black sweeps, walking planes of 2.5-D
-   tiles on levels of more than 2^20 cycled cells and on 8 x 8 x 4 tiles in
-   one pass below; 2 the plane walk and 3 the small tiles on every level;
+   tiles of 128 x 8 cells on levels of more than 2^20 cycled cells whose
+   rows fill at least half of those tiles, and on 8 x 8 x 4 tiles in one
+   pass on the others; 2 the plane walk and 3 the small tiles on every level;
    1 block-local smoothing, where the coarse_sweeps sweeps of each
    grid-cycled coarse level run in one launch, each block smoothing a 16^3
    tile in LDS with the cells around it held fixed (Jacobi between tiles,

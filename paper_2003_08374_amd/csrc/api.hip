@@ -31,9 +31,11 @@ static const char *kNames[KC_COUNT] = {
 void prof_begin(Handle *h, int cls) {
   Timer &t = h->tm;
   if (t.used + 2 > t.ev.size()) {
+    // timing only: no system-scope fence (cache write-back) at the
+    // records, which would add its own cost to every bracketed launch
     for (int i = 0; i < 256; i++) {
       hipEvent_t e;
-      hipEventCreate(&e);
+      hipEventCreateWithFlags(&e, hipEventDisableSystemFence);
       t.ev.push_back(e);
     }
     t.cls.resize(t.ev.size() / 2 + 1);

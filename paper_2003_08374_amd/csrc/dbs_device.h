@@ -110,8 +110,17 @@ struct Segs {
 // Per-cell kernels run one cell per thread on 64x4 blocks; blocks of one
 // sample walk its x-row segments, rows and planes.  (Walking several planes
 // per thread was tried: the heavy per-cell kernels then hold more registers
-// and lose occupancy.)
+// and lose occupancy.)  A sample whose rows would leave more than a ninth
+// of those lanes idle (x rows of a few dozen cells, as in a batch of small
+// samples) is instead walked in cell order, 256 consecutive cells a block.
+__host__ __device__ inline bool cell_linear(const Geom &G) {
+  const long long tiled =
+      (long long)((G.n[0] + BX - 1) / BX * BX) * ((G.n[1] + BY - 1) / BY * BY);
+  return 8 * tiled > 9 * (long long)G.n[0] * G.n[1];
+}
+
 __host__ __device__ inline int cell_blocks(const Geom &G) {
+  if (cell_linear(G)) return (G.nc + BX * BY - 1) / (BX * BY);
   return ((G.n[0] + BX - 1) / BX) * ((G.n[1] + BY - 1) / BY) * G.n[2];
 }
 
@@ -124,6 +133,17 @@ __host__ __device__ inline int cell_blocks(const Geom &G) {
 constexpr int CELL_BAND = 4;
 
 __device__ __forceinline__ bool cell_of_thread(const Geom &G, int lb, Cell &P) {
+  if (cell_linear(G)) {
+    const unsigned n0 = (unsigned)G.n[0], n01 = n0 * (unsigned)G.n[1];
+    const unsigned e = (unsigned)lb * (BX * BY) + threadIdx.x + BX * threadIdx.y;
+    const unsigned k = e / n01, r = e - k * n01, j = r / n0;
+    P.i = (int)(r - j * n0);
+    P.j = (int)j;
+    P.k = (int)k;
+    P.co[0] = P.i; P.co[1] = P.j; P.co[2] = P.k;
+    P.c = G.c0 + (int)e;
+    return e < (unsigned)G.nc;
+  }
   const int nbx = (G.n[0] + BX - 1) / BX, nby = (G.n[1] + BY - 1) / BY, n2 = G.n[2];
   const int full = nby / CELL_BAND;               // bands of CELL_BAND block rows
   const int full_blocks = full * nbx * CELL_BAND * n2;

@@ -78,6 +78,7 @@ struct Level {
   Shape cb;  // coarse levels: CB^3 tiles of the cycled samples (block-local smoothing)
   Shape cs;  // coarse levels: 8 x 8 x 4 tiles of the cycled samples (small-tile sweeps)
   long long cyc_cells = 0;  // cells of the cycled samples on this level
+  long long sw_lanes = 0;   // cells the 2.5-D tiles of `sw` span (idle lanes included)
   int sw_ok = 0;  // every cycled sample is deep enough in z for fused sweeps
 };
 

@@ -2409,8 +2409,13 @@ int pressure_retune(Handle *h) {
         return t;
       };
       const int kz = h->kz_coarse > 0 ? h->kz_coarse : pick_kz(1, KZ2, MIN_BLOCKS_CSW, total);
-      for (int s = 0; s < ns; s++)
+      L.sw_lanes = 0;
+      for (int s = 0; s < ns; s++) {
         blocks[s] = cyc(s) ? tiles25(L.hs[s].n0, L.hs[s].n1, L.hs[s].n2, 128, kz) : 0;
+        if (cyc(s))
+          L.sw_lanes += (long long)((L.hs[s].n0 + 127) / 128 * 128) *
+                        ((L.hs[s].n1 + TY2 - 1) / TY2 * TY2) * L.hs[s].n2;
+      }
       set_shape(h, L.sw, blocks, kz, rc);
       // the plane wavefront stages three planes beyond a tile's own: thin
       // (2D or nearly) levels keep the half-sweep kernels
@@ -2662,14 +2667,16 @@ static void sweep_fine_dot(Handle *h, const OpB<float> &o, const float *b, const
                b, xin, xout, colA, xc, m, zold, h->partials, (int)Z.nblk);
 }
 
-// Levels of at most CS_MAX_CELLS cycled cells take the small-tile sweeps
-// (coarse_block 0); coarse_block 2 keeps the plane walk on every level and
-// 3 the small tiles.
+// Levels of at most CS_MAX_CELLS cycled cells (launch- and latency-bound),
+// and levels on which the 128-wide plane-walk tiles would leave more than
+// half of their lanes idle (the samples' rows are short, as in a batch of
+// small samples), take the small-tile sweeps (coarse_block 0);
+// coarse_block 2 keeps the plane walk on every level and 3 the small tiles.
 constexpr long long CS_MAX_CELLS = 1LL << 20;
 static bool small_tiles(const Handle *h, const Level &L) {
   if (h->coarse_block == 3) return true;
   if (h->coarse_block == 2) return false;
-  return L.cyc_cells <= CS_MAX_CELLS;
+  return L.cyc_cells <= CS_MAX_CELLS || 2 * L.cyc_cells < L.sw_lanes;
 }
 
 // one fused sweep on coarse level l (FP32, stored coefficients), xin -> xout
