@@ -278,8 +278,11 @@ int dbs_autotune(dbs_handle *h, int *kz, int *sweeps, int *coarse_sweeps, int *b
    it as set).  coarse_block (FP32 V-cycle only) picks the coarse-level
    smoother: 0 (the default) exact red-black sweeps, walking planes of 2.5-D
    tiles of 128 x 8 cells on levels of more than 2^20 cycled cells whose
-   rows fill at least half of those tiles, and on 8 x 8 x 4 tiles in one
-   pass on the others; 2 the plane walk and 3 the small tiles on every level;
+   rows fill at least half of those tiles and that are at least 8 cells
+   deep, and on 8 x 8 x 4 tiles (16 x 16 x 1 where every sample is one cell
+   deep) in one pass on the others; 2 the plane walk on every level deep
+   enough for it and half sweeps on the others; 3 the small tiles on every
+   level;
    1 block-local smoothing, where the coarse_sweeps sweeps of each
    grid-cycled coarse level run in one launch, each block smoothing a 16^3
    tile in LDS with the cells around it held fixed (Jacobi between tiles,

@@ -80,6 +80,7 @@ struct Level {
   long long cyc_cells = 0;  // cells of the cycled samples on this level
   long long sw_lanes = 0;   // cells the 2.5-D tiles of `sw` span (idle lanes included)
   int sw_ok = 0;  // every cycled sample is deep enough in z for fused sweeps
+  int cs2d = 0;   // every cycled sample is one cell deep: small tiles are 16 x 16 x 1
 };
 
 struct Timer {

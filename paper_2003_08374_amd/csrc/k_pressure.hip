@@ -2015,35 +2015,48 @@ __global__ void __launch_bounds__(CBT) k_cblock(OpB<float> LB, SH S, const float
 // ------------------------------------------ small-tile coarse sweeps
 //
 // One fused red-black Gauss-Seidel sweep of a coarse level (FP32, stored
-// operator) on 8 x 8 x 4 tiles, one cell per thread, with no plane
-// pipeline: the smaller coarse levels are too small for the 2.5-D walk to
-// pay for its prologue, and their launches are latency-bound.  The sweep is
-// exact, with the plane-walking sweep's arithmetic (each update reads the
-// same neighbours in the same order): the block loads the old iterate on
-// the tile with a two-cell ring and the coefficients and b on a one-cell
-// ring, relaxes the colour colA on the tile and its ring (the values the
-// other colour's update of the tile reads), then the other colour on the
-// tile.  MODE as k_sweep25 (SW_ZERO: from zero;
+// operator) on small tiles, one cell per thread, with no plane pipeline:
+// the smaller coarse levels are too small for the 2.5-D walk to pay for its
+// prologue, their launches are latency-bound, and short rows would idle
+// most lanes of the 128-wide plane-walk tiles.  The sweep is exact, with
+// the plane-walking sweep's arithmetic (each update reads the same
+// neighbours in the same order): the block loads the old iterate on the
+// tile with a two-cell ring and the coefficients and b on a one-cell ring,
+// relaxes the colour colA on the tile and its ring (the values the other
+// colour's update of the tile reads), then the other colour on the tile.
+// Tiles are 8 x 8 x 4 cells, or 16 x 16 x 1 on levels whose samples are
+// all one cell deep (no z ring, no z terms: their z coefficients are the
+// zeros of domain faces).  MODE as k_sweep25 (SW_ZERO: from zero;
 // SW_PROLONG: xin plus the parent's coarse correction).
-constexpr int CSX = 8, CSY = 8, CSZ = 4;           // tile
-constexpr int CST = CSX * CSY * CSZ;               // threads per block
-constexpr int CXW = CSX + 4, CXH = CSY + 4, CXD = CSZ + 4;  // iterate, 2-cell ring
-constexpr int CRW = CSX + 2, CRH = CSY + 2, CRD = CSZ + 2;  // coefficients, 1-cell ring
-constexpr int CXN = CXW * CXH * CXD, CRN = CRW * CRH * CRD;
+template <int TX, int TY, int TZ>
+struct CsTile {
+  static constexpr int X = TX, Y = TY, Z = TZ, T = TX * TY * TZ;  // cells = threads
+  static constexpr int RZ2 = TZ > 1 ? 2 : 0, RZ1 = TZ > 1 ? 1 : 0;  // z rings
+  static constexpr int XW = TX + 4, XH = TY + 4, XD = TZ + 2 * RZ2;  // iterate, 2-cell ring
+  static constexpr int RW = TX + 2, RH = TY + 2, RD = TZ + 2 * RZ1;  // coefficients, 1-cell ring
+  static constexpr int XN = XW * XH * XD, RN = RW * RH * RD;
+};
+using Cs3 = CsTile<8, 8, 4>;
+using Cs2 = CsTile<16, 16, 1>;
+constexpr int CST = 256;  // threads per block
+static_assert(Cs3::T == CST && Cs2::T == CST, "one cell per thread");
 
+template <typename TL>
 __host__ __device__ inline int cs_tiles(int n0, int n1, int n2) {
-  return ((n0 + CSX - 1) / CSX) * ((n1 + CSY - 1) / CSY) * ((n2 + CSZ - 1) / CSZ);
+  return ((n0 + TL::X - 1) / TL::X) * ((n1 + TL::Y - 1) / TL::Y) * ((n2 + TL::Z - 1) / TL::Z);
 }
 
-template <int MODE>
+template <int MODE, typename TL>
 __global__ void __launch_bounds__(CST) k_csweep(OpB<float> LB, SH S, const float *__restrict__ b,
                                                 const float *__restrict__ xin,
                                                 float *__restrict__ xout, int colA,
                                                 const float *__restrict__ xc,
                                                 const int *__restrict__ mask) {
-  __shared__ float sx[CXN];          // old iterate (0 outside the mesh)
-  __shared__ float sc[8][CRN];       // b, D, T[0..5] of the ring-1 region
-  __shared__ float sa[CRN];          // new colour-A values of the region
+  constexpr bool Z3 = TL::Z > 1;
+  constexpr int XW = TL::XW, XH = TL::XH, RW = TL::RW, RH = TL::RH;
+  __shared__ float sx[TL::XN];          // old iterate (0 outside the mesh)
+  __shared__ float sc[8][TL::RN];       // b, D, T[0..5] of the ring-1 region
+  __shared__ float sa[TL::RN];          // new colour-A values of the region
   int g, s, lb;
   if (!locate(S, mask, g, s, lb)) return;
   const Op<float> L = op_at(LB, s);
@@ -2054,14 +2067,16 @@ __global__ void __launch_bounds__(CST) k_csweep(OpB<float> LB, SH S, const float
   if (MODE != SW_ZERO) xin += Q.c0;
   xout += Q.c0;
   const float *xcs = (MODE == SW_PROLONG && Q.cn0 > 0) ? xc + Q.cc0 : nullptr;
-  const int nbx = (n0 + CSX - 1) / CSX, nby = (n1 + CSY - 1) / CSY;
-  const int i0 = (lb % nbx) * CSX, j0 = ((lb / nbx) % nby) * CSY, k0 = (lb / (nbx * nby)) * CSZ;
+  const int nbx = (n0 + TL::X - 1) / TL::X, nby = (n1 + TL::Y - 1) / TL::Y;
+  const int i0 = (lb % nbx) * TL::X, j0 = ((lb / nbx) % nby) * TL::Y;
+  const int k0 = (lb / (nbx * nby)) * TL::Z;
   const int t = threadIdx.x;
   // old iterate on the tile and its two-cell ring
   if (MODE != SW_ZERO) {
 #pragma unroll
-    for (int e = t; e < CXN; e += CST) {
-      const int i = i0 - 2 + e % CXW, j = j0 - 2 + (e / CXW) % CXH, k = k0 - 2 + e / (CXW * CXH);
+    for (int e = t; e < TL::XN; e += CST) {
+      const int i = i0 - 2 + e % XW, j = j0 - 2 + (e / XW) % XH;
+      const int k = k0 - TL::RZ2 + e / (XW * XH);
       float v = 0.0f;
       if (i >= 0 && i < n0 && j >= 0 && j < n1 && k >= 0 && k < n2) {
         v = xin[i + sy * j + sz * k];
@@ -2074,8 +2089,9 @@ __global__ void __launch_bounds__(CST) k_csweep(OpB<float> LB, SH S, const float
   // b, diagonal and the six neighbour coefficients (0 on domain faces and
   // outside the mesh) on the tile and its one-cell ring
 #pragma unroll
-  for (int e = t; e < CRN; e += CST) {
-    const int i = i0 - 1 + e % CRW, j = j0 - 1 + (e / CRW) % CRH, k = k0 - 1 + e / (CRW * CRH);
+  for (int e = t; e < TL::RN; e += CST) {
+    const int i = i0 - 1 + e % RW, j = j0 - 1 + (e / RW) % RH;
+    const int k = k0 - TL::RZ1 + e / (RW * RH);
     float v[8] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
     if (i >= 0 && i < n0 && j >= 0 && j < n1 && k >= 0 && k < n2) {
       const int c = i + sy * j + sz * k;
@@ -2085,17 +2101,19 @@ __global__ void __launch_bounds__(CST) k_csweep(OpB<float> LB, SH S, const float
       v[3] = i + 1 < n0 ? L.Tx[c] : 0.0f;
       v[4] = j > 0 ? L.Ty[c - sy] : 0.0f;
       v[5] = j + 1 < n1 ? L.Ty[c] : 0.0f;
-      v[6] = k > 0 ? L.Tz[c - sz] : 0.0f;
-      v[7] = k + 1 < n2 ? L.Tz[c] : 0.0f;
+      if constexpr (Z3) {
+        v[6] = k > 0 ? L.Tz[c - sz] : 0.0f;
+        v[7] = k + 1 < n2 ? L.Tz[c] : 0.0f;
+      }
     }
 #pragma unroll
     for (int q = 0; q < 8; q++) sc[q][e] = v[q];
   }
   __syncthreads();
   // colour A on the tile and its ring, from the old iterate
-  for (int e = t; e < CRN; e += CST) {
-    const int li = e % CRW, lj = (e / CRW) % CRH, lk = e / (CRW * CRH);
-    const int i = i0 - 1 + li, j = j0 - 1 + lj, k = k0 - 1 + lk;
+  for (int e = t; e < TL::RN; e += CST) {
+    const int li = e % RW, lj = (e / RW) % RH, lk = e / (RW * RH);
+    const int i = i0 - 1 + li, j = j0 - 1 + lj, k = k0 - TL::RZ1 + lk;
     float v = 0.0f;
     const float D = sc[1][e];
     if (((i + j + k) & 1) == colA && i >= 0 && i < n0 && j >= 0 && j < n1 && k >= 0 &&
@@ -2103,10 +2121,14 @@ __global__ void __launch_bounds__(CST) k_csweep(OpB<float> LB, SH S, const float
       if (MODE == SW_ZERO) {
         v = sc[0][e] * sw_rcp(D);
       } else {
-        const int x = (li + 1) + CXW * ((lj + 1) + CXH * (lk + 1));
-        const float off = sc[2][e] * sx[x - 1] + sc[3][e] * sx[x + 1] +
-                          sc[4][e] * sx[x - CXW] + sc[5][e] * sx[x + CXW] +
-                          sc[6][e] * sx[x - CXW * CXH] + sc[7][e] * sx[x + CXW * CXH];
+        const int x = (li + 1) + XW * ((lj + 1) + XH * (lk + TL::RZ2 - TL::RZ1));
+        float off;
+        if constexpr (Z3)
+          off = sc[2][e] * sx[x - 1] + sc[3][e] * sx[x + 1] + sc[4][e] * sx[x - XW] +
+                sc[5][e] * sx[x + XW] + sc[6][e] * sx[x - XW * XH] + sc[7][e] * sx[x + XW * XH];
+        else
+          off = sc[2][e] * sx[x - 1] + sc[3][e] * sx[x + 1] + sc[4][e] * sx[x - XW] +
+                sc[5][e] * sx[x + XW];
         v = (sc[0][e] + off) * sw_rcp(D);
       }
     }
@@ -2114,16 +2136,20 @@ __global__ void __launch_bounds__(CST) k_csweep(OpB<float> LB, SH S, const float
   }
   __syncthreads();
   // the tile: colour A as relaxed, the other colour from the new A values
-  const int li = t % CSX + 1, lj = (t / CSX) % CSY + 1, lk = t / (CSX * CSY) + 1;
-  const int i = i0 + li - 1, j = j0 + lj - 1, k = k0 + lk - 1;
+  const int li = t % TL::X + 1, lj = (t / TL::X) % TL::Y + 1, lk = t / (TL::X * TL::Y) + TL::RZ1;
+  const int i = i0 + li - 1, j = j0 + lj - 1, k = k0 + lk - TL::RZ1;
   if (i < n0 && j < n1 && k < n2) {
-    const int e = li + CRW * (lj + CRH * lk);
+    const int e = li + RW * (lj + RH * lk);
     float v = sa[e];
     if (((i + j + k) & 1) != colA) {
       const float D = sc[1][e];
-      const float off = sc[2][e] * sa[e - 1] + sc[3][e] * sa[e + 1] + sc[4][e] * sa[e - CRW] +
-                        sc[5][e] * sa[e + CRW] + sc[6][e] * sa[e - CRW * CRH] +
-                        sc[7][e] * sa[e + CRW * CRH];
+      float off;
+      if constexpr (Z3)
+        off = sc[2][e] * sa[e - 1] + sc[3][e] * sa[e + 1] + sc[4][e] * sa[e - RW] +
+              sc[5][e] * sa[e + RW] + sc[6][e] * sa[e - RW * RH] + sc[7][e] * sa[e + RW * RH];
+      else
+        off = sc[2][e] * sa[e - 1] + sc[3][e] * sa[e + 1] + sc[4][e] * sa[e - RW] +
+              sc[5][e] * sa[e + RW];
       v = D > 0.0f ? (sc[0][e] + off) * sw_rcp(D) : 0.0f;
     }
     xout[i + sy * j + sz * k] = v;
@@ -2418,7 +2444,7 @@ int pressure_retune(Handle *h) {
       }
       set_shape(h, L.sw, blocks, kz, rc);
       // the plane wavefront stages three planes beyond a tile's own: thin
-      // (2D or nearly) levels keep the half-sweep kernels
+      // (2D or nearly) levels take the small tiles (or half sweeps)
       L.sw_ok = 1;
       for (int s = 0; s < ns; s++)
         if (cyc(s) && L.hs[s].n2 < CSW_MIN_DEPTH) L.sw_ok = 0;
@@ -2426,11 +2452,18 @@ int pressure_retune(Handle *h) {
       for (int s = 0; s < ns; s++)
         blocks[s] = cyc(s) ? cb_tiles(L.hs[s].n0, L.hs[s].n1, L.hs[s].n2) : 0;
       set_shape(h, L.cb, blocks, 1, rc);
-      // small-tile sweeps: one block per 8 x 8 x 4 tile
+      // small-tile sweeps: one block per 8 x 8 x 4 tile, or per 16 x 16 x 1
+      // tile where every cycled sample is one cell deep
       L.cyc_cells = 0;
+      L.cs2d = 1;
+      for (int s = 0; s < ns; s++)
+        if (cyc(s) && L.hs[s].n2 != 1) L.cs2d = 0;
       for (int s = 0; s < ns; s++) {
-        blocks[s] = cyc(s) ? cs_tiles(L.hs[s].n0, L.hs[s].n1, L.hs[s].n2) : 0;
-        if (cyc(s)) L.cyc_cells += (long long)L.hs[s].n0 * L.hs[s].n1 * L.hs[s].n2;
+        const LvS &Q = L.hs[s];
+        blocks[s] = !cyc(s) ? 0
+                    : L.cs2d ? cs_tiles<Cs2>(Q.n0, Q.n1, Q.n2)
+                             : cs_tiles<Cs3>(Q.n0, Q.n1, Q.n2);
+        if (cyc(s)) L.cyc_cells += (long long)Q.n0 * Q.n1 * Q.n2;
       }
       set_shape(h, L.cs, blocks, 1, rc);
     }
@@ -2668,15 +2701,22 @@ static void sweep_fine_dot(Handle *h, const OpB<float> &o, const float *b, const
 }
 
 // Levels of at most CS_MAX_CELLS cycled cells (launch- and latency-bound),
-// and levels on which the 128-wide plane-walk tiles would leave more than
-// half of their lanes idle (the samples' rows are short, as in a batch of
-// small samples), take the small-tile sweeps (coarse_block 0);
-// coarse_block 2 keeps the plane walk on every level and 3 the small tiles.
+// levels on which the 128-wide plane-walk tiles would leave more than half
+// of their lanes idle (the samples' rows are short, as in a batch of small
+// samples) and levels too thin for the plane walk take the small-tile
+// sweeps (coarse_block 0); coarse_block 2 keeps the plane walk on every
+// level (half sweeps on thin ones) and 3 the small tiles.
 constexpr long long CS_MAX_CELLS = 1LL << 20;
 static bool small_tiles(const Handle *h, const Level &L) {
   if (h->coarse_block == 3) return true;
   if (h->coarse_block == 2) return false;
-  return L.cyc_cells <= CS_MAX_CELLS || 2 * L.cyc_cells < L.sw_lanes;
+  return !L.sw_ok || L.cyc_cells <= CS_MAX_CELLS || 2 * L.cyc_cells < L.sw_lanes;
+}
+
+// the FP32 V-cycle smooths coarse level L with fused sweeps (plane walk or
+// small tiles) rather than half sweeps
+static bool fused_coarse(const Handle *h, const Level &L) {
+  return h->fused_sweep && (L.sw_ok || small_tiles(h, L));
 }
 
 // one fused sweep on coarse level l (FP32, stored coefficients), xin -> xout
@@ -2688,14 +2728,22 @@ static void sweep_coarse(Handle *h, int l, const OpB<float> &o, const float *b,
     if (!C.nblk) return;
     const dim3 g(C.nblk);
     const SH S = sh(h, C);
-    if (mode == SW_ZERO)
-      DBS_LAUNCH(h, KC_SMOOTHC, k_csweep<SW_ZERO>, g, dim3(CST), o, S, b, xin, xout, colA, xc, m);
-    else if (mode == SW_PROLONG)
-      DBS_LAUNCH(h, KC_SMOOTHC, k_csweep<SW_PROLONG>, g, dim3(CST), o, S, b, xin, xout, colA, xc,
-                 m);
+    auto go = [&](auto tile) {
+      using TL = decltype(tile);
+      if (mode == SW_ZERO)
+        DBS_LAUNCH(h, KC_SMOOTHC, (k_csweep<SW_ZERO, TL>), g, dim3(CST), o, S, b, xin, xout, colA,
+                   xc, m);
+      else if (mode == SW_PROLONG)
+        DBS_LAUNCH(h, KC_SMOOTHC, (k_csweep<SW_PROLONG, TL>), g, dim3(CST), o, S, b, xin, xout,
+                   colA, xc, m);
+      else
+        DBS_LAUNCH(h, KC_SMOOTHC, (k_csweep<SW_NORMAL, TL>), g, dim3(CST), o, S, b, xin, xout,
+                   colA, xc, m);
+    };
+    if (h->lv[l].cs2d)
+      go(Cs2{});
     else
-      DBS_LAUNCH(h, KC_SMOOTHC, k_csweep<SW_NORMAL>, g, dim3(CST), o, S, b, xin, xout, colA, xc,
-                 m);
+      go(Cs3{});
     return;
   }
   const Shape &Z = h->lv[l].sw;
@@ -2753,7 +2801,6 @@ static R *vcycle(Handle *h, const R *rAUr, const B *b0, R *z0, R *z1, bool dot =
   // writes xf2, so the 2 mgc sweeps of a cycle end in xf, where the bottom
   // also leaves its result.  ccur[l] holds the pre-smoothed iterate.
   constexpr bool flexr = std::is_same<R, float>::value;
-  const bool cfused = flexr && h->fused_sweep;
   const bool cblock = flexr && h->coarse_block == 1;
   std::vector<R *> ccur(h->lv.size(), nullptr), coth(h->lv.size(), nullptr);
   for (int l = 1; l < h->maxbottom; l++) {
@@ -2761,7 +2808,7 @@ static R *vcycle(Handle *h, const R *rAUr, const B *b0, R *z0, R *z1, bool dot =
     Level &L = h->lv[l];
     Level &C = h->lv[l + 1];
     ccur[l] = lx<R>(L);
-    const bool lf = cfused && L.sw_ok;
+    const bool lf = flexr && fused_coarse(h, L);
     if constexpr (flexr) {
       if (cblock && L.cb.nblk) {
         // all pre-sweeps of the level in one launch, into xf2
@@ -2804,7 +2851,7 @@ static R *vcycle(Handle *h, const R *rAUr, const B *b0, R *z0, R *z1, bool dot =
                    (const float *)lx<R>(C), h->mgc, act);
         continue;
       }
-      if (cfused && L.sw_ok) {
+      if (fused_coarse(h, L)) {
         // the prolongation rides on the first (black) sweep
         R *a = ccur[l], *b2 = coth[l];
         for (int s = 0; s < h->mgc; s++) {

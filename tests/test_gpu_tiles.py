@@ -127,6 +127,47 @@ def test_small_tile_and_plane_walk_coarse_sweeps_agree(ragged_ref):
     assert rel_l2(a["U"], b["U"]) <= 1e-10
 
 
+# 2D mesh with ragged tiles (260 = 2 x 128 + 4 columns, 100 = 12 x 8 + 4
+# rows): with bottom_shift 1 the one-cell-deep coarse levels 130 x 50 and
+# 65 x 25 are cycled by grid kernels, on 16 x 16 x 1 small tiles
+# (coarse_block 0) or with half sweeps (coarse_block 2)
+THIN_SHAPE = (260, 100)
+THIN_STEPS = 4
+
+
+@pytest.fixture(scope="module")
+def thin_ref():
+    case = W.reservoir_2d(nx=THIN_SHAPE[0], ny=THIN_SHAPE[1], dt=5.0)
+    ref, info = O.step(case.replace(p_tol=1e-14, p_maxit=200000), O.initial_state(case),
+                       THIN_STEPS)
+    return case, ref, info
+
+
+def test_thin_coarse_levels_on_small_tiles_match_oracle(thin_ref):
+    """The one-cell-deep coarse levels of a 2D mesh smoothed on 16 x 16 x 1
+    small tiles (the default) and with half sweeps: both match the oracle
+    at the mixed bar and agree with each other (iteration counts within
+    one)."""
+    dbs = _dbs()
+    case, ref, info = thin_ref
+    outs = {}
+    for coarse in (0, 2):
+        with dbs.Solver(case.replace(p_tol=1e-12), precision="mixed") as s:
+            s.set_tuning(kz=0, sweeps=2, coarse_sweeps=3, bottom_shift=1, fused=1,
+                         coarse_block=coarse)
+            s.step(THIN_STEPS)
+            out, st = s.state(), s.stats()
+        assert st["mg_levels"] >= 4, st
+        assert st["max_div"] <= 1e-12 * st["p_bnorm"][-1] * (1 + 1e-9)
+        compare_states(out, ref, tol_alpha=1e-9, tol_l2=1e-9, label=f"thin coarse {coarse}")
+        outs[coarse] = (out, st)
+    (a, sa), (b, sb) = outs[0], outs[2]
+    print("thin coarse smoothers", sa["p_iters"], sb["p_iters"], flush=True)
+    assert all(abs(x - y) <= 1 for x, y in zip(sa["p_iters"], sb["p_iters"]))
+    assert rel_l2(a["p_rgh"], b["p_rgh"]) <= 1e-10
+    assert rel_l2(a["U"], b["U"]) <= 1e-10
+
+
 def _c2_case():
     sys.path.insert(0, GOLD)
     import make_c2_reference as M
