@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
 #include <mutex>
 #include <new>
 #include <string>
@@ -389,7 +390,10 @@ static Phys make_phys(const dbs_physics *phys) {
 }
 
 static void clear_graphs(Handle *h) {
-  for (auto &kv : h->graphs) hipGraphExecDestroy(kv.second);
+  for (auto &kv : h->graphs) {
+    if (kv.second.front) hipGraphExecDestroy(kv.second.front);
+    if (kv.second.back) hipGraphExecDestroy(kv.second.back);
+  }
   h->graphs.clear();
 }
 
@@ -639,8 +643,9 @@ static int courant_check(Handle *h) {
 // host-mapped predictor records.  Else results go to the statistics, the
 // largest iteration count per corrector to its_out and the largest
 // predictor sweep count to *sweeps_out.
-static int step_body(Handle *h, TraceOut *tr, int budget, std::vector<int> *its_out,
-                     int *sweeps_out = nullptr) {
+// The step body runs in two parts (graph mode captures each on its own):
+// the saturation stage and the predictor, then the correctors.
+static int step_front(Handle *h, TraceOut *tr, int budget) {
   int rc = DBS_OK;
   add_time(h, h->ctl.dt);  // boundary values of this step are taken at its end
   // the trace's limited flux borrows phiH, which the correctors fill later
@@ -659,6 +664,12 @@ static int step_body(Handle *h, TraceOut *tr, int budget, std::vector<int> *its_
     rc |= copy_out3(h, tr->Shat, h->Sh);
     rc |= copy_out3(h, tr->Ustar, h->U);
   }
+  return rc;
+}
+
+// rc: the first part's trace copy status
+static int step_back(Handle *h, TraceOut *tr, int budget, std::vector<int> *its_out,
+                     int *sweeps_out, int rc) {
   int solve_rc = DBS_OK;
   std::vector<int> its(h->ns);
   std::vector<double> rel(h->ns);
@@ -703,6 +714,12 @@ static int step_body(Handle *h, TraceOut *tr, int budget, std::vector<int> *its_
   if (rc) return fail(h, DBS_EHIP, "trace copy failed");
   if (solve_rc) return fail(h, solve_rc, "pressure solve did not converge");
   return DBS_OK;
+}
+
+static int step_body(Handle *h, TraceOut *tr, int budget, std::vector<int> *its_out,
+                     int *sweeps_out = nullptr) {
+  const int rc = step_front(h, tr, budget);
+  return step_back(h, tr, budget, its_out, sweeps_out, rc);
 }
 
 static int eager_step(Handle *h, TraceOut *tr, std::vector<int> *its_out) {
@@ -791,34 +808,64 @@ static int graph_step(Handle *h) {
   const GraphKey key{h->alpha, h->U, h->F};
   auto it = h->graphs.find(key);
   if (it == h->graphs.end()) {
-    hipGraph_t g = nullptr;
-    rc = hip_check(h, hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal),
-                   "capture");
-    if (rc) return rc;
     const unsigned long long pm = h->prof_mask;
     h->prof_mask = 0;
-    snapshot(h, true);
-    step_body(h, nullptr, 1, nullptr);
+    StepGraphs sg;
+    for (int part = 0; part < 2 && !rc; part++) {
+      hipGraph_t g = nullptr;
+      rc = hip_check(h, hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal),
+                     "capture");
+      if (rc) break;
+      if (part == 0) {
+        snapshot(h, true);
+        step_front(h, nullptr, 1);
+      } else {
+        step_back(h, nullptr, 1, nullptr, nullptr, DBS_OK);
+      }
+      rc = hip_check(h, hipStreamEndCapture(h->stream, &g), "capture");
+      if (rc) break;
+      hipGraphExec_t &ex = part == 0 ? sg.front : sg.back;
+      rc = hip_check(h, hipGraphInstantiate(&ex, g, nullptr, nullptr, 0), "instantiate");
+      hipGraphDestroy(g);
+    }
     h->prof_mask = pm;
-    rc = hip_check(h, hipStreamEndCapture(h->stream, &g), "capture");
-    if (rc) return rc;
-    hipGraphExec_t ex = nullptr;
-    rc = hip_check(h, hipGraphInstantiate(&ex, g, nullptr, nullptr, 0), "instantiate");
-    hipGraphDestroy(g);
-    if (rc) return rc;
-    it = h->graphs.emplace(key, ex).first;
+    if (rc) {
+      if (sg.front) hipGraphExecDestroy(sg.front);
+      if (sg.back) hipGraphExecDestroy(sg.back);
+      return rc;
+    }
+    it = h->graphs.emplace(key, sg).first;
     // capturing ran the host side of the step: the roles are already set
     // and the host time moved
   } else {
     replay_roles(h);
     h->tnow += h->ctl.dt;
   }
-  rc = hip_check(h, hipGraphLaunch(it->second, h->stream), "graph launch");
-  if (!rc) rc = hip_check(h, hipStreamSynchronize(h->stream), "graph step");
+  // The host waits for the ready tags of the last corrector's records, not
+  // for the whole replay: the next step is then submitted while the last
+  // kernels of this one still run, and the device does not idle while the
+  // host wakes up and launches.  An event after the replay bounds the wait.
+  const int ns = h->ns;
+  volatile double *tag = h->hrec;
+  auto tag_of = [&](int s) -> volatile double & {
+    return tag[((size_t)s * 16 + (nc - 1)) * NREC + (NREC - 1)];
+  };
+  for (int s = 0; s < ns; s++) tag_of(s) = -1.0;
+  rc = hip_check(h, hipGraphLaunch(it->second.front, h->stream), "graph launch");
+  if (!rc) rc = hip_check(h, hipGraphLaunch(it->second.back, h->stream), "graph launch");
+  if (!rc) rc = hip_check(h, hipEventRecord(h->flag_ev, h->stream), "graph step");
   if (rc) return rc;
+  for (;;) {
+    bool ready = true;
+    for (int s = 0; s < ns && ready; s++) ready = tag_of(s) > 0.0;
+    if (ready) break;
+    const hipError_t q = hipEventQuery(h->flag_ev);
+    if (q == hipSuccess) break;  // the replay has ended: the records are final
+    if (q != hipErrorNotReady) return hip_check(h, q, "graph step");
+  }
+  std::atomic_thread_fence(std::memory_order_acquire);
   // the records were written to host-mapped memory by the replayed kernels
   bool ok = true;
-  const int ns = h->ns;
   const int slot = (h->mom_budget - 1) & 1;
   for (int s = 0; s < ns; s++) {
     for (int c = 0; c < nc; c++) {
@@ -857,11 +904,14 @@ static int graph_step(Handle *h) {
     if (h->slack_steps >= 4) {
       for (int c = 0; c < nc; c++) h->graph_budget[c] = h->used_max[c] + 1;
       h->slack_steps = 0;
+      rc = hip_check(h, hipStreamSynchronize(h->stream), "graph step");
       clear_graphs(h);
     }
-    return DBS_OK;
+    return rc;
   }
   // redo eagerly from the saved state with the budgets raised
+  rc = hip_check(h, hipStreamSynchronize(h->stream), "graph step");
+  if (rc) return rc;
   set_roles(h, before);
   snapshot(h, false);
   add_time(h, -h->ctl.dt);

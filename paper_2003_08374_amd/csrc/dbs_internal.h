@@ -30,7 +30,7 @@ constexpr int FLAT_T = 256;               // threads of a vector-kernel block
 constexpr int FLAT_CELLS = 4 * FLAT_T;    // cells of a vector-kernel block
 constexpr int NSC = 16;                   // device scalars per sample
 constexpr int NSTAT = 6;                  // cell statistics per sample
-constexpr int NREC = 5;                   // graph-mode solve record per corrector
+constexpr int NREC = 6;                   // graph-mode solve record per corrector (last: ready tag)
 constexpr int NMSC = 4;                   // predictor record per sample
 
 // first cell, cell count and closed-domain flag of a sample's fine cells
@@ -90,6 +90,13 @@ struct Timer {
 };
 
 // one captured step (graph mode), keyed by the buffer roles it was captured with
+// a captured step in two parts, launched back to back: the small first
+// part (saturation stage and momentum predictor) starts on the device while
+// the host is still submitting the second (the correctors' solves)
+struct StepGraphs {
+  hipGraphExec_t front = nullptr, back = nullptr;
+};
+
 struct GraphKey {
   const void *alpha, *U, *F;
   bool operator<(const GraphKey &o) const {
@@ -195,7 +202,7 @@ struct Handle {
   int graph_budget[16] = {0};  // PCG iterations per corrector in a captured step
   int used_max[16] = {0};      // largest count per corrector over the slack run
   int slack_steps = 0;         // replays in a row that left a slack of two or more
-  std::map<GraphKey, hipGraphExec_t> graphs;
+  std::map<GraphKey, StepGraphs> graphs;
   double *snap = nullptr;      // p_rgh saved for a step redone eagerly (the other
                                // fields keep their step-start buffers)
   // per-sample solve records (ns x 16 x NREC), host-mapped (host, device view)

@@ -3176,7 +3176,10 @@ int pressure_solve(Handle *h, const double *rAU, const double *b, double *x, int
 namespace dbs {
 
 // per-sample results of the last solve, stored for corrector c (graph mode:
-// read back once after the replayed step)
+// read back by the host after the replayed step, or as soon as the last
+// corrector's records are ready).  The ready tag o[5] = 1 is written after
+// the other fields are visible to the host (the host clears it to -1 before
+// each replay).
 __global__ void k_record(const double *__restrict__ scal, const int *__restrict__ act, int ns,
                          double *__restrict__ rec, int c) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
@@ -3188,6 +3191,8 @@ __global__ void k_record(const double *__restrict__ scal, const int *__restrict_
   o[2] = (S[S_NOCONV] == 0.0 && act[s] == 0) ? 1.0 : 0.0;
   o[3] = sqrt(S[S_NRM2]);
   o[4] = S[S_NRM2] > 0.0 ? sqrt(S[S_RR0] / S[S_NRM2]) : 0.0;
+  __threadfence_system();
+  o[5] = 1.0;
 }
 
 __global__ void __launch_bounds__(FLAT_T) k_copyn(const double *__restrict__ in,
