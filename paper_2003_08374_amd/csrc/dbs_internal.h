@@ -81,6 +81,7 @@ struct Level {
   long long sw_lanes = 0;   // cells the 2.5-D tiles of `sw` span (idle lanes included)
   int sw_ok = 0;  // every cycled sample is deep enough in z for fused sweeps
   int cs2d = 0;   // every cycled sample is one cell deep: small tiles are 16 x 16 x 1
+  int flat = 0;   // fine level: every sample is one cell deep (the 2D kernels)
 };
 
 struct Timer {

@@ -2265,6 +2265,279 @@ __global__ void __launch_bounds__(NT2) k_restrict25(OpB<R> LB, SH S, const B *__
   else run(std::false_type{});
 }
 
+// ------------------------------------------ fine level, one-cell-deep meshes
+//
+// On a 2D mesh (one cell deep) the plane walk of the 2.5-D kernels has one
+// plane per tile, and its prologue, staging and barriers cost more than the
+// plane itself (the SpMV, sweeps and restriction of a 2048 x 512 flume ran
+// 2.8 times slower per cell than at 256^3).  These kernels take the same
+// tiles and launch shapes, with no pipeline: a thread reads its cell's
+// neighbours straight from memory (the rows above and below are the tile's
+// own or its ring, cached), and the fused sweep keeps only the new values
+// of the first colour in LDS.  Same operator rows as the plane walk
+// (coef7 / row_diff, coefu with zero outside the mesh); the z terms vanish.
+
+template <typename R>
+__device__ __forceinline__ R at2(const R *__restrict__ a, int i, int j, int n0, int n1) {
+  return (i >= 0 && i < n0 && j >= 0 && j < n1) ? a[i + n0 * j] : (R)0;
+}
+
+// MODE 1: r = b - A p (and its FP32 copy), partials r.r and b.b.  MODE 2:
+// p_new = z + beta p (z when first) on the cell and its neighbours, written
+// for the cell (with the copy z_old = z when zold is given), q = A p_new and
+// the partial p_new.q.  Tiles of 64 x 8 cells, one cell per thread (the
+// SpMV shape of the 2.5-D kernel).
+template <int MODE, typename Z = double>
+__global__ void __launch_bounds__(NT2) k_stencil2d(OpB<double> LB, SH S,
+                                                   const double *__restrict__ p,
+                                                   const double *__restrict__ b,
+                                                   double *__restrict__ out,
+                                                   float *__restrict__ outf,
+                                                   double *__restrict__ partials, int off2,
+                                                   const int *__restrict__ mask,
+                                                   const Z *__restrict__ z = nullptr,
+                                                   double *__restrict__ pnew = nullptr,
+                                                   Z *__restrict__ zold = nullptr,
+                                                   const double *__restrict__ scal = nullptr,
+                                                   int first = 0) {
+  static_assert(MODE == 1 || MODE == 2, "residual or direction update + SpMV");
+  __shared__ double lred[NT2 / 64];
+  int g, s, lb;
+  if (!locate(S, mask, g, s, lb)) return;
+  const Op<double> L = op_at(LB, s);
+  const int c0 = LB.ls[s].c0;
+  p += c0;
+  if (MODE == 1) b += c0;
+  out += c0;
+  if (outf) outf += c0;
+  if (MODE == 2) {
+    z += c0;
+    pnew += c0;
+    if (zold) zold += c0;
+  }
+  const double beta = (MODE == 2 && !first) ? scal[s * NSC + S_BETA] : 0.0;
+  const int n0 = L.n0, n1 = L.n1;
+  int xb, y0, k0, k1;
+  tile_of(lb, n0, n1, 1, 64, S.kz, xb, y0, k0, k1);
+  const int i = xb * 64 + threadIdx.x, j = y0 + threadIdx.y;
+  const double *rA = L.rAU;
+  // the iterate the row multiplies: p itself, or the new direction
+  auto val = [&](int ii, int jj) -> double {
+    if (ii < 0 || ii >= n0 || jj < 0 || jj >= n1) return 0.0;
+    const int c = ii + n0 * jj;
+    if constexpr (MODE == 2) {
+      const double zc = (double)z[c];
+      return first ? zc : fma(beta, p[c], zc);
+    } else {
+      return p[c];
+    }
+  };
+  double v1 = 0.0, v2 = 0.0;
+  if (i < n0 && j < n1) {
+    const int c = i + n0 * j;
+    const double pc = val(i, j), pxm = val(i - 1, j), pxp = val(i + 1, j);
+    const double pym = val(i, j - 1), pyp = val(i, j + 1);
+    const double y = row_diff(L, i, j, 0, rA[c], at2(rA, i - 1, j, n0, n1),
+                              at2(rA, i + 1, j, n0, n1), at2(rA, i, j - 1, n0, n1),
+                              at2(rA, i, j + 1, n0, n1), 0.0, 0.0, pc, pxm, pxp, pym, pyp, 0.0,
+                              0.0);
+    if constexpr (MODE == 2) {
+      pnew[c] = pc;
+      if (zold) zold[c] = z[c];
+      out[c] = y;
+      v1 += pc * y;
+    } else {
+      const double bb = b[c];
+      const double res = bb - y;
+      out[c] = res;
+      if (outf) outf[c] = (float)res;
+      v1 += res * res;
+      v2 += bb * bb;
+    }
+  }
+  const double s1 = block_sum_n<NT2 / 64>(v1, lred);
+  if (threadIdx.x == 0 && threadIdx.y == 0) partials[g] = s1;
+  if (MODE == 1) {
+    const double s2 = block_sum_n<NT2 / 64>(v2, lred);
+    if (threadIdx.x == 0 && threadIdx.y == 0) partials[off2 + g] = s2;
+  }
+}
+
+// One fused red-black sweep of the fine level of a 2D mesh, colour colA
+// first, xin -> xout: tiles of 128 x 8 cells, one x-pair per thread (the
+// shape of the 2.5-D sweep).  Each thread relaxes the colA cell of its pair
+// from the old iterate, threads t < 2 (130 + 8) / 2 also one colA cell of
+// the one-cell ring; the new values go to LDS (zero outside the mesh), and
+// after one barrier each thread relaxes the other cell of its pair from
+// them and writes both.  MODE and DOT as k_sweep25.
+template <typename R, typename B, int MODE, int DOT = 0>
+__global__ void __launch_bounds__(NT2) k_sweep2d(OpB<R> LB, SH S, const B *__restrict__ b,
+                                                 const R *__restrict__ xin,
+                                                 R *__restrict__ xout, int colA,
+                                                 const R *__restrict__ xc,
+                                                 const int *__restrict__ mask,
+                                                 const R *__restrict__ zold,
+                                                 double *__restrict__ partials, int off2) {
+  static_assert(std::is_same<R, B>::value, "one precision per level");
+  constexpr int W = 128, AW = W + 2, AH = TY2 + 2;
+  __shared__ R sA[AW * AH];  // new colA values of the tile and its ring
+  __shared__ double lred[DOT ? NT2 / 64 : 1];
+  int g, s, lb;
+  if (!locate(S, mask, g, s, lb)) return;
+  const Op<R> L = op_at(LB, s);
+  const LvS &Q = LB.ls[s];
+  b += Q.c0;
+  if (MODE != SW_ZERO) xin += Q.c0;
+  xout += Q.c0;
+  const R *xcs = (MODE == SW_PROLONG && Q.cn0 > 0) ? xc + Q.cc0 : nullptr;
+  const int cn0 = Q.cn0;
+  const int n0 = L.n0, n1 = L.n1;
+  int xb, y0, k0, k1;
+  tile_of(lb, n0, n1, 1, W, S.kz, xb, y0, k0, k1);
+  const int x0 = xb * W;
+  const int tx = threadIdx.x, ty = threadIdx.y, t = tx + 64 * ty;
+  const int i0 = x0 + 2 * tx, j = y0 + ty;
+  const R *rA = L.rAU;
+  const RowK<R> K = rowk(L);
+  auto inside = [&](int ii, int jj) { return ii >= 0 && ii < n0 && jj >= 0 && jj < n1; };
+  // the old iterate (with the parent's coarse correction) at a cell
+  auto xold = [&](int ii, int jj) -> R {
+    if (MODE == SW_ZERO || !inside(ii, jj)) return (R)0;
+    R v = xin[ii + n0 * jj];
+    if (MODE == SW_PROLONG && xcs) v += xcs[(ii >> 1) + cn0 * (jj >> 1)];
+    return v;
+  };
+  // new value of the colA cell (ii, jj) from the old iterate
+  auto relax_a = [&](int ii, int jj) -> R {
+    if (!inside(ii, jj)) return (R)0;
+    const int c = ii + n0 * jj;
+    R T[6], D;
+    coefu(K, ii, jj, 0, n0, n1, 1, rA[c], at2(rA, ii - 1, jj, n0, n1),
+          at2(rA, ii + 1, jj, n0, n1), at2(rA, ii, jj - 1, n0, n1),
+          at2(rA, ii, jj + 1, n0, n1), (R)0, (R)0, T, D);
+    R v;
+    if (MODE == SW_ZERO) {
+      v = (R)b[c] * sw_rcp(D);
+    } else {
+      const R off = T[0] * xold(ii - 1, jj) + T[1] * xold(ii + 1, jj) +
+                    T[2] * xold(ii, jj - 1) + T[3] * xold(ii, jj + 1) + T[4] * (R)0 +
+                    T[5] * (R)0;
+      v = ((R)b[c] + off) * sw_rcp(D);
+    }
+    return D > (R)0 ? v : (R)0;
+  };
+  auto ai = [](int lx, int ly) { return (ly + 1) * AW + lx + 1; };
+  // own colA cell
+  const int offA = ((i0 + j) & 1) == colA ? 0 : 1;  // i0 is even
+  const R aOwn = relax_a(i0 + offA, j);
+  sA[ai(2 * tx + offA, ty)] = aOwn;
+  // colA cells of the ring: rows above and below (65 each), then the
+  // columns left and right (4 each)
+  constexpr int NR = 2 * (AW / 2) + TY2;
+  if (t < NR) {
+    int lx, ly;
+    if (t < 2 * (AW / 2)) {
+      ly = t < AW / 2 ? -1 : TY2;
+      const int q = t < AW / 2 ? t : t - AW / 2;
+      lx = 2 * q - 1 + ((colA - (x0 - 1 + y0 + ly)) & 1);
+    } else {
+      const int q = t - 2 * (AW / 2);
+      lx = q < TY2 / 2 ? -1 : W;
+      const int qq = q < TY2 / 2 ? q : q - TY2 / 2;
+      ly = 2 * qq + ((colA - (x0 + lx + y0)) & 1);
+    }
+    sA[ai(lx, ly)] = relax_a(x0 + lx, y0 + ly);
+  }
+  __syncthreads();
+  // the other cell of the pair, from the new colA values; both are written
+  double dz = 0.0, dzo = 0.0;
+  if (j < n1) {
+    const int lxB = 2 * tx + (1 - offA), iB = i0 + 1 - offA;
+    R vB = (R)0, bB = (R)0;
+    if (iB < n0) {
+      const int c = iB + n0 * j;
+      bB = (R)b[c];
+      R T[6], D;
+      coefu(K, iB, j, 0, n0, n1, 1, rA[c], at2(rA, iB - 1, j, n0, n1),
+            at2(rA, iB + 1, j, n0, n1), at2(rA, iB, j - 1, n0, n1),
+            at2(rA, iB, j + 1, n0, n1), (R)0, (R)0, T, D);
+      const R off = T[0] * sA[ai(lxB - 1, ty)] + T[1] * sA[ai(lxB + 1, ty)] +
+                    T[2] * sA[ai(lxB, ty - 1)] + T[3] * sA[ai(lxB, ty + 1)] + T[4] * (R)0 +
+                    T[5] * (R)0;
+      vB = D > (R)0 ? (bB + off) * sw_rcp(D) : (R)0;
+    }
+    const R v0 = offA == 0 ? aOwn : vB, v1 = offA == 0 ? vB : aOwn;
+    R *row = xout + n0 * j;
+    if (i0 < n0) row[i0] = v0;
+    if (i0 + 1 < n0) row[i0 + 1] = v1;
+    if constexpr (DOT) {
+      const R b0 = i0 < n0 ? (R)b[i0 + n0 * j] : (R)0;
+      const R b1 = i0 + 1 < n0 ? (R)b[i0 + 1 + n0 * j] : (R)0;
+      dz += (double)b0 * (double)(i0 < n0 ? v0 : (R)0) +
+            (double)b1 * (double)(i0 + 1 < n0 ? v1 : (R)0);
+      if (zold) {
+        const R z0 = i0 < n0 ? zold[Q.c0 + i0 + n0 * j] : (R)0;
+        const R z1 = i0 + 1 < n0 ? zold[Q.c0 + i0 + 1 + n0 * j] : (R)0;
+        dzo += (double)b0 * (double)z0 + (double)b1 * (double)z1;
+      }
+    }
+  }
+  if constexpr (DOT) {
+    const double s1 = block_sum_n<NT2 / 64>(dz, lred);
+    if (t == 0) partials[g] = s1;
+    if (zold) {
+      const double s2 = block_sum_n<NT2 / 64>(dzo, lred);
+      if (t == 0) partials[off2 + g] = s2;
+    }
+  }
+}
+
+// Restriction of a 2D fine level after a pre-smoothing that ended with a
+// black half sweep: the coarse right-hand side is the sum of the red
+// children's residuals.  Tiles of 128 x 8 fine cells (the shape of the
+// 2.5-D restriction), one x-pair (one red cell) per thread; rows 2J and
+// 2J+1 are combined through LDS.
+template <typename R, typename B>
+__global__ void __launch_bounds__(NT2) k_restrict2d(OpB<R> LB, SH S, const B *__restrict__ b,
+                                                    const R *__restrict__ x, R *__restrict__ bc,
+                                                    const int *__restrict__ mask) {
+  static_assert(std::is_same<R, B>::value, "one precision per level");
+  __shared__ R part[TY2 / 2][64];
+  int g, s, lb;
+  if (!locate(S, mask, g, s, lb)) return;
+  const Op<R> L = op_at(LB, s);
+  const LvS &Q = LB.ls[s];
+  b += Q.c0;
+  x += Q.c0;
+  bc += Q.cc0;
+  const int cn0 = Q.cn0;
+  const int n0 = L.n0, n1 = L.n1;
+  int xb, y0, k0, k1;
+  tile_of(lb, n0, n1, 1, 128, S.kz, xb, y0, k0, k1);
+  const int tx = threadIdx.x, ty = threadIdx.y;
+  const int i0 = xb * 128 + 2 * tx, j = y0 + ty;
+  const R *rA = L.rAU;
+  R acc = 0;
+  const int off = (j & 1) == 0 ? 0 : 1;  // the red cell of the pair
+  const int i = i0 + off;
+  if (j < n1 && i < n0) {
+    const int c = i + n0 * j;
+    R T[6], D;
+    coef7(L, i, j, 0, rA[c], at2(rA, i - 1, j, n0, n1), at2(rA, i + 1, j, n0, n1),
+          at2(rA, i, j - 1, n0, n1), at2(rA, i, j + 1, n0, n1), (R)0, (R)0, T, D);
+    const R sm = T[0] * at2(x, i - 1, j, n0, n1) + T[1] * at2(x, i + 1, j, n0, n1) +
+                 T[2] * at2(x, i, j - 1, n0, n1) + T[3] * at2(x, i, j + 1, n0, n1) +
+                 T[4] * (R)0 + T[5] * (R)0;
+    acc = (R)b[c] - (D * x[c] - sm);
+  }
+  if (ty & 1) part[ty >> 1][tx] = acc;
+  __syncthreads();
+  if (!(ty & 1) && i0 < n0 && j < n1) {
+    const R other = (j + 1 < n1) ? part[ty >> 1][tx] : (R)0;
+    bc[(i0 >> 1) + cn0 * (j >> 1)] = acc + other;
+  }
+}
+
 // ------------------------------------------------------------------ host
 
 template <typename R> static R *lx(Level &L);
@@ -2406,6 +2679,9 @@ int pressure_retune(Handle *h) {
   for (int s = 0; s < ns; s++)
     blocks[s] = nlev(s) > 1 ? tiles25(F.hs[s].n0, F.hs[s].n1, F.hs[s].n2, 128, krs) : 0;
   set_shape(h, F.rs, blocks, krs, rc);
+  F.flat = 1;
+  for (int s = 0; s < ns; s++)
+    if (F.hs[s].n2 != 1) F.flat = 0;
   // coarse levels
   for (int l = 1; l < (int)h->lv.size() && !rc; l++) {
     Level &L = h->lv[l];
@@ -2672,6 +2948,18 @@ static void sweep_fine(Handle *h, const OpB<R> &o, const B *b, const R *xin, R *
   const int *m = h->act;
   const R *nz = nullptr;
   double *np = nullptr;
+  if (h->lv[0].flat) {
+    if (mode == SW_ZERO)
+      DBS_LAUNCH(h, KC_SMOOTH0_ZERO, (k_sweep2d<R, B, SW_ZERO>), g, blk2(), o, S, b, xin, xout,
+                 colA, xc, m, nz, np, 0);
+    else if (mode == SW_PROLONG)
+      DBS_LAUNCH(h, KC_PROLONG0, (k_sweep2d<R, B, SW_PROLONG>), g, blk2(), o, S, b, xin, xout,
+                 colA, xc, m, nz, np, 0);
+    else
+      DBS_LAUNCH(h, KC_SMOOTH0, (k_sweep2d<R, B, SW_NORMAL>), g, blk2(), o, S, b, xin, xout,
+                 colA, xc, m, nz, np, 0);
+    return;
+  }
   if (mode == SW_ZERO)
     DBS_LAUNCH(h, KC_SMOOTH0_ZERO, (k_sweep25<R, B, SW_ZERO>), g, blk2(), o, S, b, xin, xout,
                colA, xc, m, nz, np, 0);
@@ -2692,6 +2980,15 @@ static void sweep_fine_dot(Handle *h, const OpB<float> &o, const float *b, const
   const dim3 g(Z.nblk);
   const SH S = sh(h, Z);
   const int *m = h->act;
+  if (h->lv[0].flat) {
+    if (mode == SW_PROLONG)
+      DBS_LAUNCH(h, KC_PROLONG0, (k_sweep2d<float, float, SW_PROLONG, 1>), g, blk2(), o, S, b,
+                 xin, xout, colA, xc, m, zold, h->partials, (int)Z.nblk);
+    else
+      DBS_LAUNCH(h, KC_SMOOTH0_DOT, (k_sweep2d<float, float, SW_NORMAL, 1>), g, blk2(), o, S,
+                 b, xin, xout, colA, xc, m, zold, h->partials, (int)Z.nblk);
+    return;
+  }
   if (mode == SW_PROLONG)
     DBS_LAUNCH(h, KC_PROLONG0, (k_sweep25<float, float, SW_PROLONG, 0, 1>), g, blk2(), o, S,
                b, xin, xout, colA, xc, m, zold, h->partials, (int)Z.nblk);
@@ -2793,8 +3090,12 @@ static R *vcycle(Handle *h, const R *rAUr, const B *b0, R *z0, R *z1, bool dot =
   }
   if (nl > 1 && h->lv[0].rs.nblk) {
     const Shape &Z = h->lv[0].rs;
-    DBS_LAUNCH(h, KC_RESTRICT0, (k_restrict25<R, B>), dim3(Z.nblk), blk2(), o0, sh(h, Z), b0,
-               (const R *)cur, lb<R>(h->lv[1]), act);
+    if (h->lv[0].flat)
+      DBS_LAUNCH(h, KC_RESTRICT0, (k_restrict2d<R, B>), dim3(Z.nblk), blk2(), o0, sh(h, Z), b0,
+                 (const R *)cur, lb<R>(h->lv[1]), act);
+    else
+      DBS_LAUNCH(h, KC_RESTRICT0, (k_restrict25<R, B>), dim3(Z.nblk), blk2(), o0, sh(h, Z), b0,
+                 (const R *)cur, lb<R>(h->lv[1]), act);
   }
   // Coarse levels.  In the FP32 V-cycle with fused sweeps, a level's sweeps
   // alternate between its two correction buffers; the first (zero guess)
@@ -2956,8 +3257,12 @@ static void true_residual(Handle *h, const double *rAU, const double *b, const d
                           float *rf, const int *mask, int then = FIN_STORE) {
   const Shape &Z = h->lv[0].st;
   OpB<double> o = opb<double>(h, 0, rAU);
-  DBS_LAUNCH(h, KC_RESIDUAL, k_stencil25<1>, dim3(Z.nblk), blk2(), o, sh(h, Z), x, b, h->r, rf,
-             h->partials, (int)Z.nblk, mask);
+  if (h->lv[0].flat)
+    DBS_LAUNCH(h, KC_RESIDUAL, k_stencil2d<1>, dim3(Z.nblk), blk2(), o, sh(h, Z), x, b, h->r, rf,
+               h->partials, (int)Z.nblk, mask);
+  else
+    DBS_LAUNCH(h, KC_RESIDUAL, k_stencil25<1>, dim3(Z.nblk), blk2(), o, sh(h, Z), x, b, h->r, rf,
+               h->partials, (int)Z.nblk, mask);
   const bool closed = any_closed(h);
   finalize(h, fin_args(h, &Z, 1, S_RR, S_BB, closed ? FIN_STORE : then, mask));
   if (closed) {
@@ -3097,10 +3402,16 @@ static int pcg(Handle *h, const double *rAU, const double *b, double *x, int bud
     const R *zc = zR;
     for (int it = 0;; it++) {
       if (graph && it >= budget) break;
-      DBS_LAUNCH(h, KC_SPMV, (k_stencil25<2, R>), dim3(ST.nblk), blk2(), o, sh(h, ST),
-                 (const double *)pc, (const double *)nullptr, h->q, (float *)nullptr,
-                 h->partials, 0, act, zc, pn, fdot ? (R *)nullptr : zold, (const double *)h->scal,
-                 it == 0 ? 1 : 0);
+      if (h->lv[0].flat)
+        DBS_LAUNCH(h, KC_SPMV, (k_stencil2d<2, R>), dim3(ST.nblk), blk2(), o, sh(h, ST),
+                   (const double *)pc, (const double *)nullptr, h->q, (float *)nullptr,
+                   h->partials, 0, act, zc, pn, fdot ? (R *)nullptr : zold,
+                   (const double *)h->scal, it == 0 ? 1 : 0);
+      else
+        DBS_LAUNCH(h, KC_SPMV, (k_stencil25<2, R>), dim3(ST.nblk), blk2(), o, sh(h, ST),
+                   (const double *)pc, (const double *)nullptr, h->q, (float *)nullptr,
+                   h->partials, 0, act, zc, pn, fdot ? (R *)nullptr : zold,
+                   (const double *)h->scal, it == 0 ? 1 : 0);
       std::swap(pc, pn);
       finalize(h, fin_args(h, &ST, 0, S_PQ, 0, FIN_ALPHA, act));
       DBS_LAUNCH(h, KC_AXPY, k_axpy_dot, fg, ft, F, (const double *)h->scal,
