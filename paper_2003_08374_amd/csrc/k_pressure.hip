@@ -2271,11 +2271,10 @@ __global__ void __launch_bounds__(NT2) k_restrict25(OpB<R> LB, SH S, const B *__
 // plane per tile, and its prologue, staging and barriers cost more than the
 // plane itself (the SpMV, sweeps and restriction of a 2048 x 512 flume ran
 // 2.8 times slower per cell than at 256^3).  These kernels take the same
-// tiles and launch shapes, with no pipeline: a thread reads its cell's
-// neighbours straight from memory (the rows above and below are the tile's
-// own or its ring, cached), and the fused sweep keeps only the new values
-// of the first colour in LDS.  Same operator rows as the plane walk
-// (coef7 / row_diff, coefu with zero outside the mesh); the z terms vanish.
+// tiles and launch shapes with no pipeline: the tile and its ring are
+// staged in LDS once (zero outside the mesh), one barrier, then the cells
+// are computed.  Same operator rows as the plane walk (coef7 / row_diff,
+// coefu with zero outside the mesh); the z terms vanish.
 
 template <typename R>
 __device__ __forceinline__ R at2(const R *__restrict__ a, int i, int j, int n0, int n1) {
@@ -2283,9 +2282,9 @@ __device__ __forceinline__ R at2(const R *__restrict__ a, int i, int j, int n0, 
 }
 
 // MODE 1: r = b - A p (and its FP32 copy), partials r.r and b.b.  MODE 2:
-// p_new = z + beta p (z when first) on the cell and its neighbours, written
-// for the cell (with the copy z_old = z when zold is given), q = A p_new and
-// the partial p_new.q.  Tiles of 64 x 8 cells, one cell per thread (the
+// p_new = z + beta p (z when first) on the tile and its ring, written for
+// the tile's cells (with the copy z_old = z when zold is given), q = A p_new
+// and the partial p_new.q.  Tiles of 64 x 8 cells, one cell per thread (the
 // SpMV shape of the 2.5-D kernel).
 template <int MODE, typename Z = double>
 __global__ void __launch_bounds__(NT2) k_stencil2d(OpB<double> LB, SH S,
@@ -2301,6 +2300,8 @@ __global__ void __launch_bounds__(NT2) k_stencil2d(OpB<double> LB, SH S,
                                                    const double *__restrict__ scal = nullptr,
                                                    int first = 0) {
   static_assert(MODE == 1 || MODE == 2, "residual or direction update + SpMV");
+  constexpr int W = 64, AW = W + 2, AH = TY2 + 2, AN = AW * AH;
+  __shared__ double sP[AN], sR[AN];  // iterate and rAU, tile and one-cell ring
   __shared__ double lred[NT2 / 64];
   int g, s, lb;
   if (!locate(S, mask, g, s, lb)) return;
@@ -2318,28 +2319,34 @@ __global__ void __launch_bounds__(NT2) k_stencil2d(OpB<double> LB, SH S,
   const double beta = (MODE == 2 && !first) ? scal[s * NSC + S_BETA] : 0.0;
   const int n0 = L.n0, n1 = L.n1;
   int xb, y0, k0, k1;
-  tile_of(lb, n0, n1, 1, 64, S.kz, xb, y0, k0, k1);
-  const int i = xb * 64 + threadIdx.x, j = y0 + threadIdx.y;
+  tile_of(lb, n0, n1, 1, W, S.kz, xb, y0, k0, k1);
+  const int x0 = xb * W;
+  const int tx = threadIdx.x, ty = threadIdx.y, t = tx + 64 * ty;
   const double *rA = L.rAU;
-  // the iterate the row multiplies: p itself, or the new direction
-  auto val = [&](int ii, int jj) -> double {
-    if (ii < 0 || ii >= n0 || jj < 0 || jj >= n1) return 0.0;
-    const int c = ii + n0 * jj;
-    if constexpr (MODE == 2) {
-      const double zc = (double)z[c];
-      return first ? zc : fma(beta, p[c], zc);
-    } else {
-      return p[c];
+  for (int e = t; e < AN; e += NT2) {
+    const int ii = x0 + e % AW - 1, jj = y0 + e / AW - 1;
+    double pv = 0.0, rv = 0.0;
+    if (ii >= 0 && ii < n0 && jj >= 0 && jj < n1) {
+      const int c = ii + n0 * jj;
+      rv = rA[c];
+      if constexpr (MODE == 2) {
+        const double zc = (double)z[c];
+        pv = first ? zc : fma(beta, p[c], zc);
+      } else {
+        pv = p[c];
+      }
     }
-  };
+    sP[e] = pv;
+    sR[e] = rv;
+  }
+  __syncthreads();
+  const int i = x0 + tx, j = y0 + ty;
   double v1 = 0.0, v2 = 0.0;
   if (i < n0 && j < n1) {
-    const int c = i + n0 * j;
-    const double pc = val(i, j), pxm = val(i - 1, j), pxp = val(i + 1, j);
-    const double pym = val(i, j - 1), pyp = val(i, j + 1);
-    const double y = row_diff(L, i, j, 0, rA[c], at2(rA, i - 1, j, n0, n1),
-                              at2(rA, i + 1, j, n0, n1), at2(rA, i, j - 1, n0, n1),
-                              at2(rA, i, j + 1, n0, n1), 0.0, 0.0, pc, pxm, pxp, pym, pyp, 0.0,
+    const int c = i + n0 * j, e = (ty + 1) * AW + tx + 1;
+    const double pc = sP[e];
+    const double y = row_diff(L, i, j, 0, sR[e], sR[e - 1], sR[e + 1], sR[e - AW], sR[e + AW],
+                              0.0, 0.0, pc, sP[e - 1], sP[e + 1], sP[e - AW], sP[e + AW], 0.0,
                               0.0);
     if constexpr (MODE == 2) {
       pnew[c] = pc;
@@ -2356,20 +2363,21 @@ __global__ void __launch_bounds__(NT2) k_stencil2d(OpB<double> LB, SH S,
     }
   }
   const double s1 = block_sum_n<NT2 / 64>(v1, lred);
-  if (threadIdx.x == 0 && threadIdx.y == 0) partials[g] = s1;
+  if (t == 0) partials[g] = s1;
   if (MODE == 1) {
     const double s2 = block_sum_n<NT2 / 64>(v2, lred);
-    if (threadIdx.x == 0 && threadIdx.y == 0) partials[off2 + g] = s2;
+    if (t == 0) partials[off2 + g] = s2;
   }
 }
 
 // One fused red-black sweep of the fine level of a 2D mesh, colour colA
 // first, xin -> xout: tiles of 128 x 8 cells, one x-pair per thread (the
-// shape of the 2.5-D sweep).  Each thread relaxes the colA cell of its pair
-// from the old iterate, threads t < 2 (130 + 8) / 2 also one colA cell of
-// the one-cell ring; the new values go to LDS (zero outside the mesh), and
-// after one barrier each thread relaxes the other cell of its pair from
-// them and writes both.  MODE and DOT as k_sweep25.
+// shape of the 2.5-D sweep).  The old iterate (with the parent's coarse
+// correction) and rAU are staged with a two-cell ring, b with a one-cell
+// ring; each thread relaxes the colA cell of its pair, threads t < 138 also
+// one colA cell of the one-cell ring, into LDS (zero outside the mesh), and
+// after a barrier the other cell of its pair from them, and writes both.
+// MODE and DOT as k_sweep25.
 template <typename R, typename B, int MODE, int DOT = 0>
 __global__ void __launch_bounds__(NT2) k_sweep2d(OpB<R> LB, SH S, const B *__restrict__ b,
                                                  const R *__restrict__ xin,
@@ -2379,8 +2387,11 @@ __global__ void __launch_bounds__(NT2) k_sweep2d(OpB<R> LB, SH S, const B *__res
                                                  const R *__restrict__ zold,
                                                  double *__restrict__ partials, int off2) {
   static_assert(std::is_same<R, B>::value, "one precision per level");
-  constexpr int W = 128, AW = W + 2, AH = TY2 + 2;
-  __shared__ R sA[AW * AH];  // new colA values of the tile and its ring
+  constexpr int W = 128;
+  constexpr int XW = W + 4, XH = TY2 + 4, XN = XW * XH;  // two-cell ring
+  constexpr int AW = W + 2, AH = TY2 + 2, AN = AW * AH;  // one-cell ring
+  __shared__ R sX[MODE == SW_ZERO ? 1 : XN], sR[XN], sB[AN];
+  __shared__ R sA[AN];  // new colA values of the tile and its ring
   __shared__ double lred[DOT ? NT2 / 64 : 1];
   int g, s, lb;
   if (!locate(S, mask, g, s, lb)) return;
@@ -2400,36 +2411,49 @@ __global__ void __launch_bounds__(NT2) k_sweep2d(OpB<R> LB, SH S, const B *__res
   const R *rA = L.rAU;
   const RowK<R> K = rowk(L);
   auto inside = [&](int ii, int jj) { return ii >= 0 && ii < n0 && jj >= 0 && jj < n1; };
-  // the old iterate (with the parent's coarse correction) at a cell
-  auto xold = [&](int ii, int jj) -> R {
-    if (MODE == SW_ZERO || !inside(ii, jj)) return (R)0;
-    R v = xin[ii + n0 * jj];
-    if (MODE == SW_PROLONG && xcs) v += xcs[(ii >> 1) + cn0 * (jj >> 1)];
-    return v;
-  };
-  // new value of the colA cell (ii, jj) from the old iterate
-  auto relax_a = [&](int ii, int jj) -> R {
+  for (int e = t; e < XN; e += NT2) {
+    const int ii = x0 + e % XW - 2, jj = y0 + e / XW - 2;
+    R xv = (R)0, rv = (R)0;
+    if (inside(ii, jj)) {
+      const int c = ii + n0 * jj;
+      rv = rA[c];
+      if (MODE != SW_ZERO) {
+        xv = xin[c];
+        if (MODE == SW_PROLONG && xcs) xv += xcs[(ii >> 1) + cn0 * (jj >> 1)];
+      }
+    }
+    if (MODE != SW_ZERO) sX[e] = xv;
+    sR[e] = rv;
+  }
+  for (int e = t; e < AN; e += NT2) {
+    const int ii = x0 + e % AW - 1, jj = y0 + e / AW - 1;
+    sB[e] = inside(ii, jj) ? (R)b[ii + n0 * jj] : (R)0;
+  }
+  __syncthreads();
+  auto xi = [](int lx, int ly) { return (ly + 2) * XW + lx + 2; };
+  auto ai = [](int lx, int ly) { return (ly + 1) * AW + lx + 1; };
+  // new value of the colA cell at (lx, ly) of the tile or its ring
+  auto relax_a = [&](int lx, int ly) -> R {
+    const int ii = x0 + lx, jj = y0 + ly;
     if (!inside(ii, jj)) return (R)0;
-    const int c = ii + n0 * jj;
+    const int q = xi(lx, ly);
     R T[6], D;
-    coefu(K, ii, jj, 0, n0, n1, 1, rA[c], at2(rA, ii - 1, jj, n0, n1),
-          at2(rA, ii + 1, jj, n0, n1), at2(rA, ii, jj - 1, n0, n1),
-          at2(rA, ii, jj + 1, n0, n1), (R)0, (R)0, T, D);
+    coefu(K, ii, jj, 0, n0, n1, 1, sR[q], sR[q - 1], sR[q + 1], sR[q - XW], sR[q + XW], (R)0,
+          (R)0, T, D);
+    const R bb = sB[ai(lx, ly)];
     R v;
     if (MODE == SW_ZERO) {
-      v = (R)b[c] * sw_rcp(D);
+      v = bb * sw_rcp(D);
     } else {
-      const R off = T[0] * xold(ii - 1, jj) + T[1] * xold(ii + 1, jj) +
-                    T[2] * xold(ii, jj - 1) + T[3] * xold(ii, jj + 1) + T[4] * (R)0 +
-                    T[5] * (R)0;
-      v = ((R)b[c] + off) * sw_rcp(D);
+      const R off = T[0] * sX[q - 1] + T[1] * sX[q + 1] + T[2] * sX[q - XW] +
+                    T[3] * sX[q + XW] + T[4] * (R)0 + T[5] * (R)0;
+      v = (bb + off) * sw_rcp(D);
     }
     return D > (R)0 ? v : (R)0;
   };
-  auto ai = [](int lx, int ly) { return (ly + 1) * AW + lx + 1; };
   // own colA cell
   const int offA = ((i0 + j) & 1) == colA ? 0 : 1;  // i0 is even
-  const R aOwn = relax_a(i0 + offA, j);
+  const R aOwn = relax_a(2 * tx + offA, ty);
   sA[ai(2 * tx + offA, ty)] = aOwn;
   // colA cells of the ring: rows above and below (65 each), then the
   // columns left and right (4 each)
@@ -2446,24 +2470,23 @@ __global__ void __launch_bounds__(NT2) k_sweep2d(OpB<R> LB, SH S, const B *__res
       const int qq = q < TY2 / 2 ? q : q - TY2 / 2;
       ly = 2 * qq + ((colA - (x0 + lx + y0)) & 1);
     }
-    sA[ai(lx, ly)] = relax_a(x0 + lx, y0 + ly);
+    sA[ai(lx, ly)] = relax_a(lx, ly);
   }
   __syncthreads();
   // the other cell of the pair, from the new colA values; both are written
   double dz = 0.0, dzo = 0.0;
   if (j < n1) {
     const int lxB = 2 * tx + (1 - offA), iB = i0 + 1 - offA;
-    R vB = (R)0, bB = (R)0;
+    const R bB = sB[ai(lxB, ty)];
+    R vB = (R)0;
     if (iB < n0) {
-      const int c = iB + n0 * j;
-      bB = (R)b[c];
+      const int q = xi(lxB, ty);
       R T[6], D;
-      coefu(K, iB, j, 0, n0, n1, 1, rA[c], at2(rA, iB - 1, j, n0, n1),
-            at2(rA, iB + 1, j, n0, n1), at2(rA, iB, j - 1, n0, n1),
-            at2(rA, iB, j + 1, n0, n1), (R)0, (R)0, T, D);
-      const R off = T[0] * sA[ai(lxB - 1, ty)] + T[1] * sA[ai(lxB + 1, ty)] +
-                    T[2] * sA[ai(lxB, ty - 1)] + T[3] * sA[ai(lxB, ty + 1)] + T[4] * (R)0 +
-                    T[5] * (R)0;
+      coefu(K, iB, j, 0, n0, n1, 1, sR[q], sR[q - 1], sR[q + 1], sR[q - XW], sR[q + XW], (R)0,
+            (R)0, T, D);
+      const int a = ai(lxB, ty);
+      const R off = T[0] * sA[a - 1] + T[1] * sA[a + 1] + T[2] * sA[a - AW] +
+                    T[3] * sA[a + AW] + T[4] * (R)0 + T[5] * (R)0;
       vB = D > (R)0 ? (bB + off) * sw_rcp(D) : (R)0;
     }
     const R v0 = offA == 0 ? aOwn : vB, v1 = offA == 0 ? vB : aOwn;
@@ -2471,10 +2494,9 @@ __global__ void __launch_bounds__(NT2) k_sweep2d(OpB<R> LB, SH S, const B *__res
     if (i0 < n0) row[i0] = v0;
     if (i0 + 1 < n0) row[i0 + 1] = v1;
     if constexpr (DOT) {
-      const R b0 = i0 < n0 ? (R)b[i0 + n0 * j] : (R)0;
-      const R b1 = i0 + 1 < n0 ? (R)b[i0 + 1 + n0 * j] : (R)0;
-      dz += (double)b0 * (double)(i0 < n0 ? v0 : (R)0) +
-            (double)b1 * (double)(i0 + 1 < n0 ? v1 : (R)0);
+      // b and the new x are zero outside the mesh
+      const R b0 = sB[ai(2 * tx, ty)], b1 = sB[ai(2 * tx + 1, ty)];
+      dz += (double)b0 * (double)v0 + (double)b1 * (double)v1;
       if (zold) {
         const R z0 = i0 < n0 ? zold[Q.c0 + i0 + n0 * j] : (R)0;
         const R z1 = i0 + 1 < n0 ? zold[Q.c0 + i0 + 1 + n0 * j] : (R)0;
