@@ -289,7 +289,7 @@ __global__ void __launch_bounds__(NTHREADS) k_mom_offdiag(Segs SG, Phys Ph, MomA
       const int q = 2 * a + s;
       const bool interior = !empty_axis(G, a) && !on_boundary(G, P, a, s);
       const int nb = interior ? nbr_of(G, P, a, s) : c;
-      aN[q] = AN[(size_t)q * vs + c];
+      aN[q] = empty_axis(G, a) ? 0.0 : AN[(size_t)q * vs + c];  // zero on an empty axis
 #pragma unroll
       for (int d = 0; d < 3; d++) un[q][d] = Uin[(size_t)d * vs + nb];
     }
@@ -336,7 +336,7 @@ __global__ void __launch_bounds__(NTHREADS) k_mom_jacobi(Segs SG, MomArgs M,
         const int q = 2 * a + s;
         const bool interior = !empty_axis(G, a) && !on_boundary(G, P, a, s);
         const int nbc = interior ? nbr_of(G, P, a, s) : c;
-        aN[q] = AN[(size_t)q * vs + c];
+        aN[q] = empty_axis(G, a) ? 0.0 : AN[(size_t)q * vs + c];  // zero on an empty axis
 #pragma unroll
         for (int d = 0; d < 3; d++) un[q][d] = Uin[(size_t)d * vs + nbc];
       }
