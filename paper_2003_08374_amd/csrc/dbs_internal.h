@@ -69,6 +69,7 @@ struct Level {
   double *x = nullptr, *b = nullptr;  // correction and right-hand side
   float *xf = nullptr, *bf = nullptr;
   float *xf2 = nullptr;  // second FP32 correction buffer (fused coarse sweeps)
+  double *x2 = nullptr;  // second FP64 correction buffer (small-tile coarse sweeps)
   // launch shapes: fine level
   Shape st, sm, rs;
   // coarse levels: every sample holding the level; samples cycled on it by

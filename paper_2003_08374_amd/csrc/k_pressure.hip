@@ -2046,27 +2046,27 @@ __host__ __device__ inline int cs_tiles(int n0, int n1, int n2) {
   return ((n0 + TL::X - 1) / TL::X) * ((n1 + TL::Y - 1) / TL::Y) * ((n2 + TL::Z - 1) / TL::Z);
 }
 
-template <int MODE, typename TL>
-__global__ void __launch_bounds__(CST) k_csweep(OpB<float> LB, SH S, const float *__restrict__ b,
-                                                const float *__restrict__ xin,
-                                                float *__restrict__ xout, int colA,
-                                                const float *__restrict__ xc,
+template <int MODE, typename TL, typename R = float>
+__global__ void __launch_bounds__(CST) k_csweep(OpB<R> LB, SH S, const R *__restrict__ b,
+                                                const R *__restrict__ xin,
+                                                R *__restrict__ xout, int colA,
+                                                const R *__restrict__ xc,
                                                 const int *__restrict__ mask) {
   constexpr bool Z3 = TL::Z > 1;
   constexpr int XW = TL::XW, XH = TL::XH, RW = TL::RW, RH = TL::RH;
-  __shared__ float sx[TL::XN];          // old iterate (0 outside the mesh)
-  __shared__ float sc[8][TL::RN];       // b, D, T[0..5] of the ring-1 region
-  __shared__ float sa[TL::RN];          // new colour-A values of the region
+  __shared__ R sx[TL::XN];          // old iterate (0 outside the mesh)
+  __shared__ R sc[8][TL::RN];       // b, D, T[0..5] of the ring-1 region
+  __shared__ R sa[TL::RN];          // new colour-A values of the region
   int g, s, lb;
   if (!locate(S, mask, g, s, lb)) return;
-  const Op<float> L = op_at(LB, s);
+  const Op<R> L = op_at(LB, s);
   const LvS &Q = LB.ls[s];
   const int n0 = L.n0, n1 = L.n1, n2 = L.n2;
   const int sy = n0, sz = n0 * n1;
   b += Q.c0;
   if (MODE != SW_ZERO) xin += Q.c0;
   xout += Q.c0;
-  const float *xcs = (MODE == SW_PROLONG && Q.cn0 > 0) ? xc + Q.cc0 : nullptr;
+  const R *xcs = (MODE == SW_PROLONG && Q.cn0 > 0) ? xc + Q.cc0 : nullptr;
   const int nbx = (n0 + TL::X - 1) / TL::X, nby = (n1 + TL::Y - 1) / TL::Y;
   const int i0 = (lb % nbx) * TL::X, j0 = ((lb / nbx) % nby) * TL::Y;
   const int k0 = (lb / (nbx * nby)) * TL::Z;
@@ -2077,7 +2077,7 @@ __global__ void __launch_bounds__(CST) k_csweep(OpB<float> LB, SH S, const float
     for (int e = t; e < TL::XN; e += CST) {
       const int i = i0 - 2 + e % XW, j = j0 - 2 + (e / XW) % XH;
       const int k = k0 - TL::RZ2 + e / (XW * XH);
-      float v = 0.0f;
+      R v = (R)0;
       if (i >= 0 && i < n0 && j >= 0 && j < n1 && k >= 0 && k < n2) {
         v = xin[i + sy * j + sz * k];
         if (MODE == SW_PROLONG && xcs)
@@ -2092,18 +2092,18 @@ __global__ void __launch_bounds__(CST) k_csweep(OpB<float> LB, SH S, const float
   for (int e = t; e < TL::RN; e += CST) {
     const int i = i0 - 1 + e % RW, j = j0 - 1 + (e / RW) % RH;
     const int k = k0 - TL::RZ1 + e / (RW * RH);
-    float v[8] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+    R v[8] = {(R)0, (R)0, (R)0, (R)0, (R)0, (R)0, (R)0, (R)0};
     if (i >= 0 && i < n0 && j >= 0 && j < n1 && k >= 0 && k < n2) {
       const int c = i + sy * j + sz * k;
       v[0] = b[c];
       v[1] = L.D[c];
-      v[2] = i > 0 ? L.Tx[c - 1] : 0.0f;
-      v[3] = i + 1 < n0 ? L.Tx[c] : 0.0f;
-      v[4] = j > 0 ? L.Ty[c - sy] : 0.0f;
-      v[5] = j + 1 < n1 ? L.Ty[c] : 0.0f;
+      v[2] = i > 0 ? L.Tx[c - 1] : (R)0;
+      v[3] = i + 1 < n0 ? L.Tx[c] : (R)0;
+      v[4] = j > 0 ? L.Ty[c - sy] : (R)0;
+      v[5] = j + 1 < n1 ? L.Ty[c] : (R)0;
       if constexpr (Z3) {
-        v[6] = k > 0 ? L.Tz[c - sz] : 0.0f;
-        v[7] = k + 1 < n2 ? L.Tz[c] : 0.0f;
+        v[6] = k > 0 ? L.Tz[c - sz] : (R)0;
+        v[7] = k + 1 < n2 ? L.Tz[c] : (R)0;
       }
     }
 #pragma unroll
@@ -2114,15 +2114,15 @@ __global__ void __launch_bounds__(CST) k_csweep(OpB<float> LB, SH S, const float
   for (int e = t; e < TL::RN; e += CST) {
     const int li = e % RW, lj = (e / RW) % RH, lk = e / (RW * RH);
     const int i = i0 - 1 + li, j = j0 - 1 + lj, k = k0 - TL::RZ1 + lk;
-    float v = 0.0f;
-    const float D = sc[1][e];
+    R v = (R)0;
+    const R D = sc[1][e];
     if (((i + j + k) & 1) == colA && i >= 0 && i < n0 && j >= 0 && j < n1 && k >= 0 &&
-        k < n2 && D > 0.0f) {
+        k < n2 && D > (R)0) {
       if (MODE == SW_ZERO) {
         v = sc[0][e] * sw_rcp(D);
       } else {
         const int x = (li + 1) + XW * ((lj + 1) + XH * (lk + TL::RZ2 - TL::RZ1));
-        float off;
+        R off;
         if constexpr (Z3)
           off = sc[2][e] * sx[x - 1] + sc[3][e] * sx[x + 1] + sc[4][e] * sx[x - XW] +
                 sc[5][e] * sx[x + XW] + sc[6][e] * sx[x - XW * XH] + sc[7][e] * sx[x + XW * XH];
@@ -2140,17 +2140,17 @@ __global__ void __launch_bounds__(CST) k_csweep(OpB<float> LB, SH S, const float
   const int i = i0 + li - 1, j = j0 + lj - 1, k = k0 + lk - TL::RZ1;
   if (i < n0 && j < n1 && k < n2) {
     const int e = li + RW * (lj + RH * lk);
-    float v = sa[e];
+    R v = sa[e];
     if (((i + j + k) & 1) != colA) {
-      const float D = sc[1][e];
-      float off;
+      const R D = sc[1][e];
+      R off;
       if constexpr (Z3)
         off = sc[2][e] * sa[e - 1] + sc[3][e] * sa[e + 1] + sc[4][e] * sa[e - RW] +
               sc[5][e] * sa[e + RW] + sc[6][e] * sa[e - RW * RH] + sc[7][e] * sa[e + RW * RH];
       else
         off = sc[2][e] * sa[e - 1] + sc[3][e] * sa[e + 1] + sc[4][e] * sa[e - RW] +
               sc[5][e] * sa[e + RW];
-      v = D > 0.0f ? (sc[0][e] + off) * sw_rcp(D) : 0.0f;
+      v = D > (R)0 ? (sc[0][e] + off) * sw_rcp(D) : (R)0;
     }
     xout[i + sy * j + sz * k] = v;
   }
@@ -2565,6 +2565,9 @@ __global__ void __launch_bounds__(NT2) k_restrict2d(OpB<R> LB, SH S, const B *__
 template <typename R> static R *lx(Level &L);
 template <> double *lx<double>(Level &L) { return L.x; }
 template <> float *lx<float>(Level &L) { return L.xf; }
+template <typename R> static R *lx2(Level &L);
+template <> double *lx2<double>(Level &L) { return L.x2; }
+template <> float *lx2<float>(Level &L) { return L.xf2; }
 template <typename R> static R *lb(Level &L);
 template <> double *lb<double>(Level &L) { return L.b; }
 template <> float *lb<float>(Level &L) { return L.bf; }
@@ -2877,6 +2880,7 @@ int pressure_setup(Handle *h) {
     } else {
       L.Tx = (double *)Tx; L.Ty = (double *)Ty; L.Tz = (double *)Tz; L.Db = (double *)Db;
       L.D = (double *)D; L.x = (double *)x; L.b = (double *)b;
+      L.x2 = (double *)dalloc(h, n * s, rc);
     }
   }
   if (rc) return rc;
@@ -3034,15 +3038,25 @@ static bool small_tiles(const Handle *h, const Level &L) {
 
 // the FP32 V-cycle smooths coarse level L with fused sweeps (plane walk or
 // small tiles) rather than half sweeps
+// The FP64 V-cycle has no plane walk on coarse levels (its planes would not
+// fit in LDS): it takes the small tiles on latency-bound and thin levels and
+// half sweeps elsewhere (on the larger levels of a batch of small samples
+// the FP64 small tiles, with a third of the blocks per CU, were slower).
+template <typename R>
 static bool fused_coarse(const Handle *h, const Level &L) {
-  return h->fused_sweep && (L.sw_ok || small_tiles(h, L));
+  if (!h->fused_sweep) return false;
+  if (std::is_same<R, float>::value) return L.sw_ok || small_tiles(h, L);
+  if (h->coarse_block == 3) return true;
+  if (h->coarse_block == 2) return false;
+  return !L.sw_ok || L.cyc_cells <= CS_MAX_CELLS;
 }
 
-// one fused sweep on coarse level l (FP32, stored coefficients), xin -> xout
-static void sweep_coarse(Handle *h, int l, const OpB<float> &o, const float *b,
-                         const float *xin, float *xout, int colA, int mode, const float *xc) {
+// one fused sweep on coarse level l (stored coefficients), xin -> xout
+template <typename R>
+static void sweep_coarse(Handle *h, int l, const OpB<R> &o, const R *b, const R *xin, R *xout,
+                         int colA, int mode, const R *xc) {
   const int *m = h->act;
-  if (small_tiles(h, h->lv[l])) {
+  if (!std::is_same<R, float>::value || small_tiles(h, h->lv[l])) {
     const Shape &C = h->lv[l].cs;
     if (!C.nblk) return;
     const dim3 g(C.nblk);
@@ -3050,14 +3064,14 @@ static void sweep_coarse(Handle *h, int l, const OpB<float> &o, const float *b,
     auto go = [&](auto tile) {
       using TL = decltype(tile);
       if (mode == SW_ZERO)
-        DBS_LAUNCH(h, KC_SMOOTHC, (k_csweep<SW_ZERO, TL>), g, dim3(CST), o, S, b, xin, xout, colA,
-                   xc, m);
+        DBS_LAUNCH(h, KC_SMOOTHC, (k_csweep<SW_ZERO, TL, R>), g, dim3(CST), o, S, b, xin, xout,
+                   colA, xc, m);
       else if (mode == SW_PROLONG)
-        DBS_LAUNCH(h, KC_SMOOTHC, (k_csweep<SW_PROLONG, TL>), g, dim3(CST), o, S, b, xin, xout,
-                   colA, xc, m);
+        DBS_LAUNCH(h, KC_SMOOTHC, (k_csweep<SW_PROLONG, TL, R>), g, dim3(CST), o, S, b, xin,
+                   xout, colA, xc, m);
       else
-        DBS_LAUNCH(h, KC_SMOOTHC, (k_csweep<SW_NORMAL, TL>), g, dim3(CST), o, S, b, xin, xout,
-                   colA, xc, m);
+        DBS_LAUNCH(h, KC_SMOOTHC, (k_csweep<SW_NORMAL, TL, R>), g, dim3(CST), o, S, b, xin,
+                   xout, colA, xc, m);
     };
     if (h->lv[l].cs2d)
       go(Cs2{});
@@ -3065,6 +3079,7 @@ static void sweep_coarse(Handle *h, int l, const OpB<float> &o, const float *b,
       go(Cs3{});
     return;
   }
+  if constexpr (std::is_same<R, float>::value) {
   const Shape &Z = h->lv[l].sw;
   if (!Z.nblk) return;
   const dim3 g(Z.nblk);
@@ -3080,6 +3095,7 @@ static void sweep_coarse(Handle *h, int l, const OpB<float> &o, const float *b,
   else
     DBS_LAUNCH(h, KC_SMOOTHC, (k_sweep25<float, float, SW_NORMAL, 1>), g, blk2(), o, S, b,
                xin, xout, colA, xc, m, nz, np, 0);
+  }
 }
 
 // z = M r: one V-cycle over the active samples.  b0 is the fine right-hand
@@ -3119,10 +3135,11 @@ static R *vcycle(Handle *h, const R *rAUr, const B *b0, R *z0, R *z1, bool dot =
       DBS_LAUNCH(h, KC_RESTRICT0, (k_restrict25<R, B>), dim3(Z.nblk), blk2(), o0, sh(h, Z), b0,
                  (const R *)cur, lb<R>(h->lv[1]), act);
   }
-  // Coarse levels.  In the FP32 V-cycle with fused sweeps, a level's sweeps
-  // alternate between its two correction buffers; the first (zero guess)
-  // writes xf2, so the 2 mgc sweeps of a cycle end in xf, where the bottom
-  // also leaves its result.  ccur[l] holds the pre-smoothed iterate.
+  // Coarse levels.  With fused sweeps, a level's sweeps alternate between
+  // its two correction buffers; the first (zero guess) writes the second
+  // buffer (xf2, x2), so the 2 mgc sweeps of a cycle end in the first (xf,
+  // x), where the bottom also leaves its result.  ccur[l] holds the
+  // pre-smoothed iterate.
   constexpr bool flexr = std::is_same<R, float>::value;
   const bool cblock = flexr && h->coarse_block == 1;
   std::vector<R *> ccur(h->lv.size(), nullptr), coth(h->lv.size(), nullptr);
@@ -3131,28 +3148,30 @@ static R *vcycle(Handle *h, const R *rAUr, const B *b0, R *z0, R *z1, bool dot =
     Level &L = h->lv[l];
     Level &C = h->lv[l + 1];
     ccur[l] = lx<R>(L);
-    const bool lf = flexr && fused_coarse(h, L);
+    const bool cbl = cblock && L.cb.nblk;
+    const bool lf = !cbl && fused_coarse<R>(h, L);
     if constexpr (flexr) {
-      if (cblock && L.cb.nblk) {
+      if (cbl) {
         // all pre-sweeps of the level in one launch, into xf2
         DBS_LAUNCH(h, KC_SMOOTHC, k_cblock<CB_ZERO>, dim3(L.cb.nblk), dim3(CBT), o,
                    sh(h, L.cb), (const float *)lb<R>(L), (const float *)nullptr, (float *)L.xf2,
                    (const float *)nullptr, h->mgc, act);
         ccur[l] = (R *)L.xf2;
-      } else if (lf) {
-        R *a = (R *)L.xf2, *b2 = lx<R>(L);
-        sweep_coarse(h, l, o, (const R *)lb<R>(L), (const R *)nullptr, a, 0, SW_ZERO,
-                     (const R *)nullptr);
-        for (int s = 1; s < h->mgc; s++) {
-          sweep_coarse(h, l, o, (const R *)lb<R>(L), (const R *)a, b2, 0, SW_NORMAL,
-                       (const R *)nullptr);
-          std::swap(a, b2);
-        }
-        ccur[l] = a;
-        coth[l] = b2;
       }
     }
-    if (!lf && !(cblock && L.cb.nblk)) smooth_level<R, R>(h, l, o, (const R *)lb<R>(L), lx<R>(L), true);
+    if (lf) {
+      R *a = lx2<R>(L), *b2 = lx<R>(L);
+      sweep_coarse<R>(h, l, o, (const R *)lb<R>(L), (const R *)nullptr, a, 0, SW_ZERO,
+                      (const R *)nullptr);
+      for (int s = 1; s < h->mgc; s++) {
+        sweep_coarse<R>(h, l, o, (const R *)lb<R>(L), (const R *)a, b2, 0, SW_NORMAL,
+                        (const R *)nullptr);
+        std::swap(a, b2);
+      }
+      ccur[l] = a;
+      coth[l] = b2;
+    }
+    if (!lf && !cbl) smooth_level<R, R>(h, l, o, (const R *)lb<R>(L), lx<R>(L), true);
     if (C.one_rc.nblk)
       DBS_LAUNCH(h, KC_RESTRICTC, (k_restrict<R, R>), dim3(C.one_rc.nblk), blk(), o,
                  sh(h, C.one_rc), (const R *)lb<R>(L), (const R *)ccur[l], lb<R>(C), act,
@@ -3174,16 +3193,16 @@ static R *vcycle(Handle *h, const R *rAUr, const B *b0, R *z0, R *z1, bool dot =
                    (const float *)lx<R>(C), h->mgc, act);
         continue;
       }
-      if (fused_coarse(h, L)) {
-        // the prolongation rides on the first (black) sweep
-        R *a = ccur[l], *b2 = coth[l];
-        for (int s = 0; s < h->mgc; s++) {
-          sweep_coarse(h, l, o, (const R *)lb<R>(L), (const R *)a, b2, 1,
-                       s == 0 ? SW_PROLONG : SW_NORMAL, (const R *)lx<R>(C));
-          std::swap(a, b2);
-        }
-        continue;
+    }
+    if (fused_coarse<R>(h, L)) {
+      // the prolongation rides on the first (black) sweep
+      R *a = ccur[l], *b2 = coth[l];
+      for (int s = 0; s < h->mgc; s++) {
+        sweep_coarse<R>(h, l, o, (const R *)lb<R>(L), (const R *)a, b2, 1,
+                        s == 0 ? SW_PROLONG : SW_NORMAL, (const R *)lx<R>(C));
+        std::swap(a, b2);
       }
+      continue;
     }
     if (L.one_cyc.nblk)
       DBS_LAUNCH(h, KC_PROLONGC, k_prolong<R>, dim3(L.one_cyc.nblk), blk(), (const LvS *)L.ds,
