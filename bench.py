@@ -619,7 +619,7 @@ def main():
         if traffic:
             roof["traffic_rate_GBs"] = round(traffic / avg_s / 1e9, 1)
             roof["traffic_source"] = tsrc
-        # context: the rate of torch's own device copy on the same box
+        # context: the rate of torch's own device copy in the same run
         roof["torch_copy_GBs"] = round(copy_bandwidth(), 1)
     if roof is not None:
         roof["step"] = step_roofline(main_run, cells, args.precision, ms, args.n)
