@@ -71,15 +71,45 @@ __device__ __forceinline__ bool locate(const SH &S, const int *__restrict__ mask
   return !mask || mask[s];
 }
 
-__host__ __device__ inline int column_blocks(int n0, int n1, int n2, int kz, bool pair) {
+// Column kernels give each thread a column of kz planes at one cell (or an
+// x-pair of cells) of a plane, on 64 x 4 blocks tiling the plane.  Levels
+// whose rows would leave more than a ninth of those lanes idle (rows of a
+// few dozen cells, as on the coarse levels of a batch of small samples)
+// take the plane's columns in order instead, 256 consecutive ones a block.
+__host__ __device__ inline bool column_linear(int n0, int n1, bool pair) {
   const int cx = pair ? 2 * BX : BX;
-  return ((n0 + cx - 1) / cx) * ((n1 + BY - 1) / BY) * ((n2 + kz - 1) / kz);
+  const long long units = pair ? (n0 + 1) / 2 : n0;  // columns per row
+  const long long tiled = (long long)((n0 + cx - 1) / cx) * BX * ((n1 + BY - 1) / BY) * BY;
+  return 8 * tiled > 9 * units * n1;
+}
+
+__host__ __device__ inline int column_blocks(int n0, int n1, int n2, int kz, bool pair) {
+  const int chunks = (n2 + kz - 1) / kz;
+  if (column_linear(n0, n1, pair)) {
+    const long long cols = (long long)(pair ? (n0 + 1) / 2 : n0) * n1;
+    return (int)((cols + BX * BY - 1) / (BX * BY)) * chunks;
+  }
+  const int cx = pair ? 2 * BX : BX;
+  return ((n0 + cx - 1) / cx) * ((n1 + BY - 1) / BY) * chunks;
 }
 
 // column owned by this thread in block lb of a level of n0 x n1 x n2 cells:
 // x index (first of the pair), y index, plane range
 __device__ __forceinline__ bool column(int n0, int n1, int n2, int lb, int kz, bool pair, int &i,
                                        int &j, int &k0, int &k1) {
+  if (column_linear(n0, n1, pair)) {
+    const unsigned units = pair ? (unsigned)(n0 + 1) / 2 : (unsigned)n0;
+    const unsigned cols = units * (unsigned)n1;
+    const unsigned per = (cols + BX * BY - 1) / (BX * BY);  // blocks per chunk of planes
+    const unsigned chunk = (unsigned)lb / per;
+    const unsigned q = ((unsigned)lb - chunk * per) * (BX * BY) + threadIdx.x + BX * threadIdx.y;
+    const unsigned jj = q / units;
+    i = (int)(q - jj * units) * (pair ? 2 : 1);
+    j = (int)jj;
+    k0 = (int)chunk * kz;
+    k1 = min(k0 + kz, n2);
+    return q < cols;
+  }
   const int cx = pair ? 2 * BX : BX;
   const int nbx = (n0 + cx - 1) / cx, nby = (n1 + BY - 1) / BY;
   const int bx = lb % nbx;
