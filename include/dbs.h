@@ -275,22 +275,22 @@ int dbs_autotune(dbs_handle *h, int *kz, int *sweeps, int *coarse_sweeps, int *b
 /* Set the same knobs by hand (kz = 0: the launch-size heuristic), and the
    planes per coarse-level tile or thread column kz_coarse (0: the launch-size
    heuristic, which keeps enough blocks to fill the chip; the autotuner leaves
-   it as set).  coarse_block picks the coarse-level smoother: 0 (the
-   default) exact red-black sweeps, in the FP32 V-cycle walking planes of
-   2.5-D tiles of 128 x 8 cells on levels of more than 2^20 cycled cells
-   whose rows fill at least half of those tiles and that are at least 8
-   cells deep, and on 8 x 8 x 4 tiles (16 x 16 x 1 where every sample is
-   one cell deep) in one pass on the others; in the FP64 V-cycle small
-   tiles on levels of at most 2^20 cycled cells and thin levels, half
-   sweeps on the others; 2 the plane walk (FP32) or half sweeps (FP64) on
-   every level deep enough for the plane walk and half sweeps on the
-   others; 3 the small tiles on every level; 1 (the FP64 V-cycle takes it
-   as 0) block-local smoothing, where the coarse_sweeps sweeps of each
+   it as set).  coarse_block picks the coarse-level smoother (with fused
+   sweeps; fused = 0 takes red-black half sweeps everywhere): 0 (the
+   default) exact red-black sweeps, on 8 x 8 x 4 tiles (16 x 16 x 1 where
+   every sample is one cell deep) in one pass on levels of at most 2^20
+   cycled cells and on levels less than 8 cells deep, as half sweeps on
+   the larger levels whose rows fill less than half of a 128-cell tile row,
+   and on the others walking planes of 2.5-D tiles of 128 x 8 cells (FP32)
+   or as half sweeps (FP64); 2 the plane walk (FP32) or half sweeps (FP64)
+   on every level deep enough for the plane walk and half sweeps on the
+   others; 3 the small tiles on every level; 4 half sweeps on every level;
+   1 (the FP64 V-cycle takes it as 0) block-local smoothing, where the coarse_sweeps sweeps of each
    grid-cycled coarse level run in one launch, each block smoothing a 16^3
    tile in LDS with the cells around it held fixed (Jacobi between tiles,
    Gauss-Seidel within; the post-sweeps transpose the pre-sweeps, so the
    preconditioner stays symmetric).  kz and kz_coarse in [0, 64], sweeps and
-   coarse_sweeps in [1, 8], bottom_shift in [0, 4], coarse_block in [0, 3];
+   coarse_sweeps in [1, 8], bottom_shift in [0, 4], coarse_block in [0, 4];
    else DBS_EINVAL. */
 int dbs_set_tuning(dbs_handle *h, int kz, int kz_coarse, int sweeps, int coarse_sweeps,
                    int bottom_shift, int fused, int coarse_block);

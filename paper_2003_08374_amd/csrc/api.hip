@@ -1348,7 +1348,7 @@ int dbs_set_tuning(dbs_handle *H, int kz, int kz_coarse, int sweeps, int coarse_
                    int shift, int fused, int coarse_block) {
   if (!H || kz < 0 || kz > 64 || kz_coarse < 0 || kz_coarse > 64 || sweeps < 1 || sweeps > 8 ||
       coarse_sweeps < 1 || coarse_sweeps > 8 || shift < 0 || shift > 4 || coarse_block < 0 ||
-      coarse_block > 3)
+      coarse_block > 4)
     return DBS_EINVAL;
   Handle *h = &H->h;
   hipStreamSynchronize(h->stream);

@@ -3053,32 +3053,36 @@ static void sweep_fine_dot(Handle *h, const OpB<float> &o, const float *b, const
                b, xin, xout, colA, xc, m, zold, h->partials, (int)Z.nblk);
 }
 
-// Levels of at most CS_MAX_CELLS cycled cells (launch- and latency-bound),
-// levels on which the 128-wide plane-walk tiles would leave more than half
-// of their lanes idle (the samples' rows are short, as in a batch of small
-// samples) and levels too thin for the plane walk take the small-tile
-// sweeps (coarse_block 0); coarse_block 2 keeps the plane walk on every
-// level (half sweeps on thin ones) and 3 the small tiles.
+// The coarse-level smoother of the V-cycle with fused sweeps (coarse_block
+// 0): small tiles on levels of at most CS_MAX_CELLS cycled cells (launch-
+// and latency-bound) and on levels too thin for the plane walk; half sweeps
+// on the larger levels whose rows would leave more than half of the
+// 128-wide plane-walk tiles' lanes idle (a batch of small samples: there the
+// half sweeps, walking the columns in order, beat the small tiles, 243
+// against 257 ms per step of the 512-sample batch); the plane walk on the
+// others.  The FP64 V-cycle has no plane walk (its planes would not fit in
+// LDS) and takes half sweeps there (its small tiles, with a third of the
+// blocks per CU, were slower).  coarse_block 2: the plane walk where deep
+// enough, else half sweeps; 3: small tiles everywhere; 4: half sweeps
+// everywhere.
 constexpr long long CS_MAX_CELLS = 1LL << 20;
-static bool small_tiles(const Handle *h, const Level &L) {
-  if (h->coarse_block == 3) return true;
-  if (h->coarse_block == 2) return false;
-  return !L.sw_ok || L.cyc_cells <= CS_MAX_CELLS || 2 * L.cyc_cells < L.sw_lanes;
+enum { CS_HALF = 0, CS_TILES = 1, CS_WALK = 2 };
+template <typename R>
+static int coarse_smoother(const Handle *h, const Level &L) {
+  constexpr bool fp32 = std::is_same<R, float>::value;
+  if (!h->fused_sweep || h->coarse_block == 4) return CS_HALF;
+  if (h->coarse_block == 3) return CS_TILES;
+  if (h->coarse_block == 2) return fp32 && L.sw_ok ? CS_WALK : CS_HALF;
+  if (!L.sw_ok || L.cyc_cells <= CS_MAX_CELLS) return CS_TILES;
+  if (!fp32 || 2 * L.cyc_cells < L.sw_lanes) return CS_HALF;
+  return CS_WALK;
 }
 
-// the FP32 V-cycle smooths coarse level L with fused sweeps (plane walk or
-// small tiles) rather than half sweeps
-// The FP64 V-cycle has no plane walk on coarse levels (its planes would not
-// fit in LDS): it takes the small tiles on latency-bound and thin levels and
-// half sweeps elsewhere (on the larger levels of a batch of small samples
-// the FP64 small tiles, with a third of the blocks per CU, were slower).
+// the V-cycle smooths coarse level L with fused sweeps (plane walk or small
+// tiles) rather than half sweeps
 template <typename R>
 static bool fused_coarse(const Handle *h, const Level &L) {
-  if (!h->fused_sweep) return false;
-  if (std::is_same<R, float>::value) return L.sw_ok || small_tiles(h, L);
-  if (h->coarse_block == 3) return true;
-  if (h->coarse_block == 2) return false;
-  return !L.sw_ok || L.cyc_cells <= CS_MAX_CELLS;
+  return coarse_smoother<R>(h, L) != CS_HALF;
 }
 
 // one fused sweep on coarse level l (stored coefficients), xin -> xout
@@ -3086,7 +3090,7 @@ template <typename R>
 static void sweep_coarse(Handle *h, int l, const OpB<R> &o, const R *b, const R *xin, R *xout,
                          int colA, int mode, const R *xc) {
   const int *m = h->act;
-  if (!std::is_same<R, float>::value || small_tiles(h, h->lv[l])) {
+  if (coarse_smoother<R>(h, h->lv[l]) == CS_TILES) {
     const Shape &C = h->lv[l].cs;
     if (!C.nblk) return;
     const dim3 g(C.nblk);

@@ -60,7 +60,7 @@ TILES = [(0, 0, 0), (2, 2, 0), (4, 8, 1), (8, 4, 0), (16, 8, 1), (16, 3, 1)]
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-@pytest.mark.parametrize("fused,coarse", [(1, 0), (1, 2), (0, 0)])
+@pytest.mark.parametrize("fused,coarse", [(1, 0), (1, 2), (1, 4), (0, 0)])
 @pytest.mark.parametrize("kz,kzc,shift", TILES, ids=lambda t: str(t))
 def test_forced_tile_depths_match_oracle(ragged_ref, kz, kzc, shift, fused, coarse, precision):
     """Fine tiles of kz planes (partial last chunk: 37 = 2 x 16 + 5) and
@@ -69,7 +69,7 @@ def test_forced_tile_depths_match_oracle(ragged_ref, kz, kzc, shift, fused, coar
     V-cycle with fused sweeps the coarse levels (34 x 23 x 19, 17 x 12 x 10)
     take the small-tile sweeps by default (coarse 0) or the plane walk on
     kzc-plane tiles (coarse 2); in the FP64 V-cycle the small tiles (coarse
-    0) or half sweeps (coarse 2).  The GPU solves to 1e-12: at this size the
+    0) or half sweeps (coarse 2); half sweeps in both (coarse 4).  The GPU solves to 1e-12: at this size the
     true residual's rounding floor is near 1e-13."""
     dbs = _dbs()
     case, ref, info = ragged_ref
