@@ -173,8 +173,11 @@ int dbs_set_static(dbs_handle *h, const double *phi, const double *kinv);
 int dbs_set_state(dbs_handle *h, const double *alpha, const double *U,
                   const double *p_rgh, const double *F);
 
-/* Advance nsteps time steps (Sec. 3.2 sequence).  Synchronises the
-   library stream before returning. */
+/* Advance nsteps time steps (Sec. 3.2 sequence).  The first corrector's
+   pressure solve starts from p_rgh extrapolated linearly in time from the
+   ends of the last two steps (from p_rgh itself on the first step after
+   creation or a state reset).  Synchronises the library stream before
+   returning. */
 int dbs_step(dbs_handle *h, int nsteps);
 
 /* Copy the state to host arrays; any pointer may be NULL.  p = p_rgh +

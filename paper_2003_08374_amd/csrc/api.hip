@@ -493,7 +493,7 @@ static int create_impl(int n, const dbs_grid *grids, const dbs_physics *phys, co
   h->alpha = dmalloc(h, NC, rc); h->alpha_old = dmalloc(h, NC, rc);
   if (ctl->n_alpha_sub > 1) h->alpha3 = dmalloc(h, NC, rc);
   h->U = dmalloc(h, 3 * NC, rc); h->U2 = dmalloc(h, 3 * NC, rc); h->U3 = dmalloc(h, 3 * NC, rc);
-  h->prgh = dmalloc(h, NC, rc); h->p = dmalloc(h, NC, rc);
+  h->prgh = dmalloc(h, NC, rc); h->p = dmalloc(h, NC, rc); h->pprev = dmalloc(h, NC, rc);
   h->F = dmalloc(h, NF, rc); h->F2 = dmalloc(h, NF, rc);
   h->ml = dmalloc(h, NC, rc); h->mg = dmalloc(h, NC, rc); h->pc = dmalloc(h, NC, rc);
   h->cf = dmalloc(h, NC, rc);
@@ -571,6 +571,7 @@ static int set_state_impl(Handle *h, int i, const double *alpha, const double *U
     init_flux(h, i);
   }
   update_closures(h, i);
+  h->pprev_ok = false;  // no previous step for the extrapolated guess
   return hip_check(h, hipStreamSynchronize(h->stream), "set_state");
 }
 
@@ -667,6 +668,35 @@ static int step_front(Handle *h, TraceOut *tr, int budget) {
   return rc;
 }
 
+// p_rgh <- p_rgh + r (p_rgh - p_prev) and p_prev <- p_rgh (r = 0: the guess
+// is p_rgh itself)
+__global__ void __launch_bounds__(FLAT_T) k_extrap(double *__restrict__ p,
+                                                   double *__restrict__ pp, double r, size_t n) {
+  const size_t c = (size_t)blockIdx.x * FLAT_T + threadIdx.x;
+  if (c >= n) return;
+  const double t = p[c];
+  if (r != 0.0) p[c] = fma(r, t - pp[c], t);
+  pp[c] = t;
+}
+
+// Initial guess of the first corrector's pressure solve: p_rgh extrapolated
+// linearly in time from the ends of the last two steps (time steps dt_prev
+// and dt), which at 256^3 starts the solve 5 times closer than p_rgh^n and
+// saves two of its ten iterations.  The terms of the step before the solve
+// (transport, predictor, assembly) read p_rgh^n.
+static double extrap_factor(const Handle *h) {
+  return h->pprev_ok && h->dt_prev > 0.0 ? h->ctl.dt / h->dt_prev : 0.0;
+}
+static void extrapolate_guess(Handle *h) {
+  const double r = extrap_factor(h);
+  const size_t n = (size_t)h->NC;
+  DBS_LAUNCH(h, KC_MISC, k_extrap, dim3((unsigned)((n + FLAT_T - 1) / FLAT_T)), dim3(FLAT_T),
+             h->prgh, h->pprev, r, n);
+  h->extrap_r = r;
+  h->pprev_ok = true;
+  h->dt_prev = h->ctl.dt;
+}
+
 // rc: the first part's trace copy status
 static int step_back(Handle *h, TraceOut *tr, int budget, std::vector<int> *its_out,
                      int *sweeps_out, int rc) {
@@ -680,6 +710,7 @@ static int step_back(Handle *h, TraceOut *tr, int budget, std::vector<int> *its_
       rc |= copy_out(h, tr->phiHbyA, h->phiH, h->hG[0].nf);
       rc |= copy_out(h, tr->b, h->rhs, h->hG[0].nc);
     }
+    if (c == 0) extrapolate_guess(h);
     const int b = budget > 0 ? h->graph_budget[c] : 0;
     const int src = pressure_solve(h, h->rAU, h->rhs, h->prgh, b, its.data(), rel.data());
     if (budget > 0) {
@@ -805,6 +836,13 @@ static int graph_step(Handle *h) {
     if (rc) return fail(h, rc, "snapshot allocation");
   }
   const Roles before = roles(h);
+  // the captured steps bake in the extrapolation factor of the first
+  // solve's guess: capture again when it changes (after a state reset)
+  if (extrap_factor(h) != h->graph_r) {
+    rc = hip_check(h, hipStreamSynchronize(h->stream), "graph step");  // a replay may run
+    if (rc) return rc;
+    clear_graphs(h);
+  }
   const GraphKey key{h->alpha, h->U, h->F};
   auto it = h->graphs.find(key);
   if (it == h->graphs.end()) {
@@ -835,6 +873,7 @@ static int graph_step(Handle *h) {
       return rc;
     }
     it = h->graphs.emplace(key, sg).first;
+    h->graph_r = h->extrap_r;
     // capturing ran the host side of the step: the roles are already set
     // and the host time moved
   } else {

@@ -135,6 +135,13 @@ struct Handle {
   // step leaves U^n in U3).  3 x NC each
   double *U = nullptr, *U2 = nullptr, *U3 = nullptr;
   double *prgh = nullptr, *p = nullptr;
+  // p_rgh of the previous step's end, for the extrapolated initial guess of
+  // the first corrector's solve; valid once a step has run since the state
+  // was last set.  extrap_r: the factor the last guess used (0: none);
+  // graph_r: the factor the captured steps use.
+  double *pprev = nullptr;
+  bool pprev_ok = false;
+  double dt_prev = 0.0, extrap_r = 0.0, graph_r = -1.0;
   double *F = nullptr;                 // faces
   double *F2 = nullptr;                // the correctors' fluxes (swapped with F per step)
   // closures of the current alpha: k_rl/mu_l, k_rg/mu_g, p_c (0 in clear cells)

@@ -63,7 +63,10 @@ def test_flume_batch_graph_matches_oracle():
 
 
 def test_flume_restart_time():
-    """Stepping 4 + 4 from a restart at t = 4 dt equals 8 steps in one go."""
+    """Stepping 4 + 4 from a restart at t = 4 dt equals 8 steps in one go,
+    to the solver tolerance: the restarted run's first pressure solve starts
+    from p_rgh itself, the continuous run's from the guess extrapolated from
+    the two steps before (a wrong boundary time would differ by far more)."""
     from paper_2003_08374_amd import dbs
     c = _small_flume()
     with dbs.Solver(c) as s:
@@ -76,4 +79,4 @@ def test_flume_restart_time():
         s.set_time(4 * c.dt)
         s.step(4)
         out = s.state()
-    compare_states(out, full, tol_l2=1e-12, tol_alpha=1e-13, label="flume restart")
+    compare_states(out, full, tol_l2=1e-10, tol_alpha=1e-10, label="flume restart")
