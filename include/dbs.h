@@ -175,9 +175,10 @@ int dbs_set_state(dbs_handle *h, const double *alpha, const double *U,
 
 /* Advance nsteps time steps (Sec. 3.2 sequence).  The first corrector's
    pressure solve starts from p_rgh extrapolated linearly in time from the
-   ends of the last two steps (from p_rgh itself on the first step after
-   creation or a state reset).  Synchronises the library stream before
-   returning. */
+   ends of the last two steps, each later corrector's from the previous
+   corrector's solution plus the change that corrector's solve made in the
+   previous step (plain p_rgh on the first step after creation or a state
+   reset).  Synchronises the library stream before returning. */
 int dbs_step(dbs_handle *h, int nsteps);
 
 /* Copy the state to host arrays; any pointer may be NULL.  p = p_rgh +

@@ -494,6 +494,10 @@ static int create_impl(int n, const dbs_grid *grids, const dbs_physics *phys, co
   if (ctl->n_alpha_sub > 1) h->alpha3 = dmalloc(h, NC, rc);
   h->U = dmalloc(h, 3 * NC, rc); h->U2 = dmalloc(h, 3 * NC, rc); h->U3 = dmalloc(h, 3 * NC, rc);
   h->prgh = dmalloc(h, NC, rc); h->p = dmalloc(h, NC, rc); h->pprev = dmalloc(h, NC, rc);
+  if (ctl->n_corr > 1) {
+    h->p1 = dmalloc(h, NC, rc);
+    h->dcorr = dmalloc(h, (size_t)(ctl->n_corr - 1) * NC, rc);
+  }
   h->F = dmalloc(h, NF, rc); h->F2 = dmalloc(h, NF, rc);
   h->ml = dmalloc(h, NC, rc); h->mg = dmalloc(h, NC, rc); h->pc = dmalloc(h, NC, rc);
   h->cf = dmalloc(h, NC, rc);
@@ -684,6 +688,27 @@ __global__ void __launch_bounds__(FLAT_T) k_extrap(double *__restrict__ p,
 // and dt), which at 256^3 starts the solve 5 times closer than p_rgh^n and
 // saves two of its ten iterations.  The terms of the step before the solve
 // (transport, predictor, assembly) read p_rgh^n.
+// Initial guess of a later corrector's solve: the previous corrector's
+// solution plus the change this corrector's solve made in the previous step
+// (warm: a previous step ran since the state was set); the solution it
+// starts from is kept (p1) to record the change of this step.
+__global__ void __launch_bounds__(FLAT_T) k_corr_guess(double *__restrict__ p,
+                                                       double *__restrict__ p1,
+                                                       const double *__restrict__ d, int warm,
+                                                       size_t n) {
+  const size_t c = (size_t)blockIdx.x * FLAT_T + threadIdx.x;
+  if (c >= n) return;
+  const double t = p[c];
+  p1[c] = t;
+  if (warm) p[c] = t + d[c];
+}
+__global__ void __launch_bounds__(FLAT_T) k_corr_record(const double *__restrict__ p,
+                                                        const double *__restrict__ p1,
+                                                        double *__restrict__ d, size_t n) {
+  const size_t c = (size_t)blockIdx.x * FLAT_T + threadIdx.x;
+  if (c < n) d[c] = p[c] - p1[c];
+}
+
 static double extrap_factor(const Handle *h) {
   return h->pprev_ok && h->dt_prev > 0.0 ? h->ctl.dt / h->dt_prev : 0.0;
 }
@@ -701,6 +726,9 @@ static void extrapolate_guess(Handle *h) {
 static int step_back(Handle *h, TraceOut *tr, int budget, std::vector<int> *its_out,
                      int *sweeps_out, int rc) {
   int solve_rc = DBS_OK;
+  const bool warm = h->pprev_ok;  // the changes of a previous step are recorded
+  const size_t NCs = (size_t)h->NC;
+  const dim3 fg((unsigned)((NCs + FLAT_T - 1) / FLAT_T)), ft(FLAT_T);
   std::vector<int> its(h->ns);
   std::vector<double> rel(h->ns);
   for (int c = 0; c < h->ctl.n_corr; c++) {
@@ -710,9 +738,17 @@ static int step_back(Handle *h, TraceOut *tr, int budget, std::vector<int> *its_
       rc |= copy_out(h, tr->phiHbyA, h->phiH, h->hG[0].nf);
       rc |= copy_out(h, tr->b, h->rhs, h->hG[0].nc);
     }
-    if (c == 0) extrapolate_guess(h);
+    double *dc = c > 0 ? h->dcorr + (size_t)(c - 1) * NCs : nullptr;
+    if (c == 0)
+      extrapolate_guess(h);
+    else
+      DBS_LAUNCH(h, KC_MISC, k_corr_guess, fg, ft, h->prgh, h->p1, (const double *)dc,
+                 warm ? 1 : 0, NCs);
     const int b = budget > 0 ? h->graph_budget[c] : 0;
     const int src = pressure_solve(h, h->rAU, h->rhs, h->prgh, b, its.data(), rel.data());
+    if (c > 0)
+      DBS_LAUNCH(h, KC_MISC, k_corr_record, fg, ft, (const double *)h->prgh,
+                 (const double *)h->p1, dc, NCs);
     if (budget > 0) {
       pressure_record(h, h->rec, c);
     } else {

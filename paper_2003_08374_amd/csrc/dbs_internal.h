@@ -140,6 +140,9 @@ struct Handle {
   // was last set.  extrap_r: the factor the last guess used (0: none);
   // graph_r: the factor the captured steps use.
   double *pprev = nullptr;
+  // the solution of the corrector before (p1) and, per later corrector, the
+  // change its solve made in the previous step (dcorr, (n_corr - 1) x NC)
+  double *p1 = nullptr, *dcorr = nullptr;
   bool pprev_ok = false;
   double dt_prev = 0.0, extrap_r = 0.0, graph_r = -1.0;
   double *F = nullptr;                 // faces
