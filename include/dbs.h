@@ -174,11 +174,15 @@ int dbs_set_state(dbs_handle *h, const double *alpha, const double *U,
                   const double *p_rgh, const double *F);
 
 /* Advance nsteps time steps (Sec. 3.2 sequence).  The first corrector's
-   pressure solve starts from p_rgh extrapolated linearly in time from the
-   ends of the last two steps, each later corrector's from the previous
-   corrector's solution plus the change that corrector's solve made in the
-   previous step (plain p_rgh on the first step after creation or a state
-   reset).  Synchronises the library stream before returning. */
+   pressure solve starts from p_rgh extrapolated in time from the ends of
+   the previous steps (per sample, the order among 0, 1 and 2 that best
+   predicted the last step) less the later correctors' predicted changes;
+   each later corrector's starts from the previous corrector's solution plus
+   its predicted change (the change its solve made in the previous step,
+   where that predicted the last change better than none).  The guesses
+   change only the iteration counts; the first step after creation or a
+   state reset starts from p_rgh itself.  Synchronises the library stream
+   before returning. */
 int dbs_step(dbs_handle *h, int nsteps);
 
 /* Copy the state to host arrays; any pointer may be NULL.  p = p_rgh +

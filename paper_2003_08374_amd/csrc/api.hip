@@ -493,10 +493,13 @@ static int create_impl(int n, const dbs_grid *grids, const dbs_physics *phys, co
   h->alpha = dmalloc(h, NC, rc); h->alpha_old = dmalloc(h, NC, rc);
   if (ctl->n_alpha_sub > 1) h->alpha3 = dmalloc(h, NC, rc);
   h->U = dmalloc(h, 3 * NC, rc); h->U2 = dmalloc(h, 3 * NC, rc); h->U3 = dmalloc(h, 3 * NC, rc);
-  h->prgh = dmalloc(h, NC, rc); h->p = dmalloc(h, NC, rc); h->pprev = dmalloc(h, NC, rc);
+  h->prgh = dmalloc(h, NC, rc); h->p = dmalloc(h, NC, rc);
+  h->pprev = dmalloc(h, NC, rc); h->pprev2 = dmalloc(h, NC, rc); h->pprev3 = dmalloc(h, NC, rc);
+  h->gord = (int *)dmalloc_bytes(h, sizeof(int) * n, rc);
   if (ctl->n_corr > 1) {
     h->p1 = dmalloc(h, NC, rc);
     h->dcorr = dmalloc(h, (size_t)(ctl->n_corr - 1) * NC, rc);
+    h->gwarm = (int *)dmalloc_bytes(h, sizeof(int) * n * (ctl->n_corr - 1), rc);
   }
   h->F = dmalloc(h, NF, rc); h->F2 = dmalloc(h, NF, rc);
   h->ml = dmalloc(h, NC, rc); h->mg = dmalloc(h, NC, rc); h->pc = dmalloc(h, NC, rc);
@@ -575,7 +578,7 @@ static int set_state_impl(Handle *h, int i, const double *alpha, const double *U
     init_flux(h, i);
   }
   update_closures(h, i);
-  h->pprev_ok = false;  // no previous step for the extrapolated guess
+  h->hist = 0;  // no previous step for the extrapolated guess
   return hip_check(h, hipStreamSynchronize(h->stream), "set_state");
 }
 
@@ -672,53 +675,204 @@ static int step_front(Handle *h, TraceOut *tr, int budget) {
   return rc;
 }
 
-// p_rgh <- p_rgh + r (p_rgh - p_prev) and p_prev <- p_rgh (r = 0: the guess
-// is p_rgh itself)
-__global__ void __launch_bounds__(FLAT_T) k_extrap(double *__restrict__ p,
-                                                   double *__restrict__ pp, double r, size_t n) {
-  const size_t c = (size_t)blockIdx.x * FLAT_T + threadIdx.x;
-  if (c >= n) return;
-  const double t = p[c];
-  if (r != 0.0) p[c] = fma(r, t - pp[c], t);
-  pp[c] = t;
+// ---------------------------------------------------- pressure initial guesses
+//
+// The first corrector's solve starts from p_rgh at the end of the coming
+// step extrapolated in time from the ends of the previous steps, less the
+// changes the later correctors' solves are predicted to make; each later
+// corrector's solve starts from the previous corrector's solution plus its
+// predicted change.  Every prediction is chosen per sample from how it would
+// have fared one step back: the extrapolation order (0: p_rgh^n itself, 1:
+// linear, 2: quadratic) whose prediction of p_rgh^n from the steps before
+// came closest in the L2 norm, and for each later corrector the change of
+// the previous step when it predicted this step's change better than no
+// change.  (At 256^3, mixed, steps 13 to 22 from rest, the quadratic order
+// wins and the first solve starts 8 times closer than with the linear one
+// alone; in the wave flume p_rgh alternates from step to step, so order 0
+// wins there and the previous step's change does not help.)
+
+// one block per sample: the NQ block partials of the sample summed in a
+// fixed order; the sums are valid in thread 0
+template <int NQ>
+__device__ __forceinline__ void sample_sums(const double *__restrict__ part, int nb,
+                                            const int *__restrict__ bp, double *r) {
+  __shared__ double lds[NQ][16];
+  const int t = threadIdx.x, s = blockIdx.x;
+  for (int q = 0; q < NQ; q++) r[q] = 0.0;
+  for (int i = bp[s] + t; i < bp[s + 1]; i += 1024)
+    for (int q = 0; q < NQ; q++) r[q] += part[(size_t)q * nb + i];
+  for (int q = 0; q < NQ; q++) {
+    const double v = wave_sum(r[q]);
+    if ((t & 63) == 0) lds[q][t >> 6] = v;
+  }
+  __syncthreads();
+  if (t == 0)
+    for (int q = 0; q < NQ; q++) {
+      double v = lds[q][0];
+      for (int w = 1; w < 16; w++) v += lds[q][w];
+      r[q] = v;
+    }
 }
 
-// Initial guess of the first corrector's pressure solve: p_rgh extrapolated
-// linearly in time from the ends of the last two steps (time steps dt_prev
-// and dt), which at 256^3 starts the solve 5 times closer than p_rgh^n and
-// saves two of its ten iterations.  The terms of the step before the solve
-// (transport, predictor, assembly) read p_rgh^n.
-// Initial guess of a later corrector's solve: the previous corrector's
-// solution plus the change this corrector's solve made in the previous step
-// (warm: a previous step ran since the state was set); the solution it
-// starts from is kept (p1) to record the change of this step.
-__global__ void __launch_bounds__(FLAT_T) k_corr_guess(double *__restrict__ p,
-                                                       double *__restrict__ p1,
-                                                       const double *__restrict__ d, int warm,
-                                                       size_t n) {
-  const size_t c = (size_t)blockIdx.x * FLAT_T + threadIdx.x;
-  if (c >= n) return;
-  const double t = p[c];
-  p1[c] = t;
-  if (warm) p[c] = t + d[c];
-}
-__global__ void __launch_bounds__(FLAT_T) k_corr_record(const double *__restrict__ p,
-                                                        const double *__restrict__ p1,
-                                                        double *__restrict__ d, size_t n) {
-  const size_t c = (size_t)blockIdx.x * FLAT_T + threadIdx.x;
-  if (c < n) d[c] = p[c] - p1[c];
+// NQ per-thread values summed over the block into part[q * nb + block]
+template <int NQ>
+__device__ __forceinline__ void block_partials(const double *v, int gb, double *part, int nb) {
+  __shared__ double lds[NQ][NTHREADS / 64];
+  const int t = threadIdx.x + BX * threadIdx.y;
+  for (int q = 0; q < NQ; q++) {
+    const double w = wave_sum(v[q]);
+    if ((t & 63) == 0) lds[q][t >> 6] = w;
+  }
+  __syncthreads();
+  if (t == 0)
+    for (int q = 0; q < NQ; q++) {
+      double w = lds[q][0];
+      for (int k = 1; k < NTHREADS / 64; k++) w += lds[q][k];
+      part[(size_t)q * nb + gb] = w;
+    }
 }
 
-static double extrap_factor(const Handle *h) {
-  return h->pprev_ok && h->dt_prev > 0.0 ? h->ctl.dt / h->dt_prev : 0.0;
+// The first corrector's guess in p (p_rgh^n on entry) with the sample's
+// order ord[s] (at most A.use) less the changes d of the later correctors
+// whose flag warm[s * nd + k] is set; the squared errors of the backtests
+// as block partials; the history shifts (pq <- pb <- pa <- p_rgh^n).
+__global__ void __launch_bounds__(NTHREADS) k_extrap(Segs SG, double *__restrict__ p,
+                                                     double *__restrict__ pa,
+                                                     double *__restrict__ pb,
+                                                     double *__restrict__ pq,
+                                                     const double *__restrict__ d, size_t nc,
+                                                     const int *__restrict__ ord,
+                                                     const int *__restrict__ warm, GuessArgs A,
+                                                     double *__restrict__ part, int nb) {
+  double e[3] = {0.0, 0.0, 0.0};
+  FOR_CELLS(SG, G, P) {
+    const size_t c = P.c;
+    const double t = p[c], a = pa[c], b = pb[c];
+    const int o = min(ord[cell_sg], A.use);
+    double g = t;
+    if (o == 1) g = fma(A.r, t - a, t);
+    else if (o == 2) g = fma(A.q2, t - b, fma(A.q1, t - a, t));
+    for (int k = 0; k < A.nd; k++)
+      if (warm[cell_sg * A.nd + k]) g -= d[(size_t)k * nc + c];
+    if (A.nbt >= 1) e[0] = (t - a) * (t - a);
+    if (A.nbt >= 2) {
+      const double x = t - fma(A.b1, a - b, a);
+      e[1] = x * x;
+    }
+    if (A.nbt >= 3) {
+      const double x = t - fma(A.c2, a - pq[c], fma(A.c1, a - b, a));
+      e[2] = x * x;
+    }
+    p[c] = g;
+    pq[c] = b;
+    pb[c] = a;
+    pa[c] = t;
+  }
+  block_partials<3>(e, cell_gb, part, nb);
 }
+
+// one block per sample: the order of the next step's guess, the one whose
+// backtest erred least (linear while fewer than two backtests exist)
+__global__ void __launch_bounds__(1024) k_extrap_final(const double *__restrict__ part, int nb,
+                                                       const int *__restrict__ bp, int nbt,
+                                                       int *__restrict__ ord) {
+  double r[3];
+  sample_sums<3>(part, nb, bp, r);
+  if (threadIdx.x != 0) return;
+  int o = 1;
+  if (nbt >= 2) {
+    o = 0;
+    for (int k = 1; k < nbt && k < 3; k++)
+      if (r[k] < r[o]) o = k;
+  }
+  ord[blockIdx.x] = o;
+}
+
+// A later corrector's guess: the previous corrector's solution (kept in
+// p1) plus the change d this corrector's solve made in the previous step,
+// where the sample's flag is set and a previous step has run.
+__global__ void __launch_bounds__(NTHREADS) k_corr_guess(Segs SG, double *__restrict__ p,
+                                                         double *__restrict__ p1,
+                                                         const double *__restrict__ d,
+                                                         const int *__restrict__ warm, int nd,
+                                                         int k, int ok) {
+  FOR_CELLS(SG, G, P) {
+    const size_t c = P.c;
+    const double t = p[c];
+    p1[c] = t;
+    if (ok && warm[cell_sg * nd + k]) p[c] = t + d[c];
+  }
+}
+
+// The change of this step's solve, d <- p - p1, and as block partials the
+// squared norms of its difference from the previous step's change (when
+// old: that change is stored) and of the change itself.
+__global__ void __launch_bounds__(NTHREADS) k_corr_record(Segs SG, const double *__restrict__ p,
+                                                          const double *__restrict__ p1,
+                                                          double *__restrict__ d, int old,
+                                                          double *__restrict__ part, int nb) {
+  double e[2] = {0.0, 0.0};
+  FOR_CELLS(SG, G, P) {
+    const size_t c = P.c;
+    const double x = p[c] - p1[c];
+    if (old) {
+      const double y = x - d[c];
+      e[0] = y * y;
+    }
+    e[1] = x * x;
+    d[c] = x;
+  }
+  block_partials<2>(e, cell_gb, part, nb);
+}
+
+// one block per sample: use the change as the next step's prediction when
+// it predicted this step's change better than no change (and by default)
+__global__ void __launch_bounds__(1024) k_record_final(const double *__restrict__ part, int nb,
+                                                       const int *__restrict__ bp, int old,
+                                                       int *__restrict__ warm, int nd, int k) {
+  double r[2];
+  sample_sums<2>(part, nb, bp, r);
+  if (threadIdx.x == 0) warm[blockIdx.x * nd + k] = old ? (r[0] < r[1] ? 1 : 0) : 1;
+}
+
+// Lagrange extrapolation to offset tau past node 0 from nodes 0, -h1 and
+// -(h1 + h2), in difference form: x0 + c1 (x0 - x1) + c2 (x0 - x2)
+static void quad_coef(double tau, double h1, double h2, double *c1, double *c2) {
+  *c1 = tau * (tau + h1 + h2) / (h1 * h2);
+  *c2 = -tau * (tau + h1) / ((h1 + h2) * h2);
+}
+
+// the coming step's GuessArgs from the stored steps and their time steps
+static GuessArgs guess_args(const Handle *h) {
+  GuessArgs A{};
+  const double tau = h->ctl.dt, h1 = h->dt_prev, h2 = h->dt_prev2, h3 = h->dt_prev3;
+  A.use = std::min(h->hist, 2);
+  A.nbt = std::min(h->hist, 3);
+  A.nd = h->hist >= 1 ? h->ctl.n_corr - 1 : 0;
+  if (A.use >= 1) A.r = tau / h1;
+  if (A.use >= 2) quad_coef(tau, h1, h2, &A.q1, &A.q2);
+  if (A.nbt >= 2) A.b1 = h1 / h2;
+  if (A.nbt >= 3) quad_coef(h1, h2, h3, &A.c1, &A.c2);
+  return A;
+}
+
+static bool same_args(const GuessArgs &x, const GuessArgs &y) {
+  return x.r == y.r && x.q1 == y.q1 && x.q2 == y.q2 && x.b1 == y.b1 && x.c1 == y.c1 &&
+         x.c2 == y.c2 && x.use == y.use && x.nbt == y.nbt && x.nd == y.nd;
+}
+
 static void extrapolate_guess(Handle *h) {
-  const double r = extrap_factor(h);
-  const size_t n = (size_t)h->NC;
-  DBS_LAUNCH(h, KC_MISC, k_extrap, dim3((unsigned)((n + FLAT_T - 1) / FLAT_T)), dim3(FLAT_T),
-             h->prgh, h->pprev, r, n);
-  h->extrap_r = r;
-  h->pprev_ok = true;
+  const GuessArgs A = guess_args(h);
+  const int nb = h->cell.nblk;
+  DBS_LAUNCH(h, KC_MISC, k_extrap, h->cgrid, dim3(BX, BY), h->seg, h->prgh, h->pprev,
+             h->pprev2, h->pprev3, (const double *)h->dcorr, (size_t)h->NC,
+             (const int *)h->gord, (const int *)h->gwarm, A, h->partials, nb);
+  DBS_LAUNCH(h, KC_MISC, k_extrap_final, dim3(h->ns), dim3(1024), (const double *)h->partials,
+             nb, (const int *)h->cell.bp, A.nbt, h->gord);
+  h->guess_used = A;
+  h->hist = std::min(h->hist + 1, 3);
+  h->dt_prev3 = h->dt_prev2;
+  h->dt_prev2 = h->dt_prev;
   h->dt_prev = h->ctl.dt;
 }
 
@@ -726,9 +880,10 @@ static void extrapolate_guess(Handle *h) {
 static int step_back(Handle *h, TraceOut *tr, int budget, std::vector<int> *its_out,
                      int *sweeps_out, int rc) {
   int solve_rc = DBS_OK;
-  const bool warm = h->pprev_ok;  // the changes of a previous step are recorded
+  const int warm = h->hist >= 1 ? 1 : 0;  // the changes of a previous step are recorded
   const size_t NCs = (size_t)h->NC;
-  const dim3 fg((unsigned)((NCs + FLAT_T - 1) / FLAT_T)), ft(FLAT_T);
+  const int nd = h->ctl.n_corr - 1, nb = h->cell.nblk;
+  const dim3 blk(BX, BY);
   std::vector<int> its(h->ns);
   std::vector<double> rel(h->ns);
   for (int c = 0; c < h->ctl.n_corr; c++) {
@@ -742,13 +897,17 @@ static int step_back(Handle *h, TraceOut *tr, int budget, std::vector<int> *its_
     if (c == 0)
       extrapolate_guess(h);
     else
-      DBS_LAUNCH(h, KC_MISC, k_corr_guess, fg, ft, h->prgh, h->p1, (const double *)dc,
-                 warm ? 1 : 0, NCs);
+      DBS_LAUNCH(h, KC_MISC, k_corr_guess, h->cgrid, blk, h->seg, h->prgh, h->p1,
+                 (const double *)dc, (const int *)h->gwarm, nd, c - 1, warm);
     const int b = budget > 0 ? h->graph_budget[c] : 0;
     const int src = pressure_solve(h, h->rAU, h->rhs, h->prgh, b, its.data(), rel.data());
-    if (c > 0)
-      DBS_LAUNCH(h, KC_MISC, k_corr_record, fg, ft, (const double *)h->prgh,
-                 (const double *)h->p1, dc, NCs);
+    if (c > 0) {
+      DBS_LAUNCH(h, KC_MISC, k_corr_record, h->cgrid, blk, h->seg, (const double *)h->prgh,
+                 (const double *)h->p1, dc, warm, h->partials, nb);
+      DBS_LAUNCH(h, KC_MISC, k_record_final, dim3(h->ns), dim3(1024),
+                 (const double *)h->partials, nb, (const int *)h->cell.bp, warm, h->gwarm, nd,
+                 c - 1);
+    }
     if (budget > 0) {
       pressure_record(h, h->rec, c);
     } else {
@@ -872,9 +1031,10 @@ static int graph_step(Handle *h) {
     if (rc) return fail(h, rc, "snapshot allocation");
   }
   const Roles before = roles(h);
-  // the captured steps bake in the extrapolation factor of the first
-  // solve's guess: capture again when it changes (after a state reset)
-  if (extrap_factor(h) != h->graph_r) {
+  // the captured steps bake in the coefficients of the first solve's guess:
+  // capture again when they change (the first steps after a state reset, a
+  // change of the time step)
+  if (!same_args(guess_args(h), h->graph_guess)) {
     rc = hip_check(h, hipStreamSynchronize(h->stream), "graph step");  // a replay may run
     if (rc) return rc;
     clear_graphs(h);
@@ -909,7 +1069,7 @@ static int graph_step(Handle *h) {
       return rc;
     }
     it = h->graphs.emplace(key, sg).first;
-    h->graph_r = h->extrap_r;
+    h->graph_guess = h->guess_used;
     // capturing ran the host side of the step: the roles are already set
     // and the host time moved
   } else {

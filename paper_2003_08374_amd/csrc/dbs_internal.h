@@ -108,6 +108,18 @@ struct GraphKey {
   }
 };
 
+// Coefficients of the first corrector's initial guess (k_extrap): the
+// guess is t + r (t - a) (order 1) or t + q1 (t - a) + q2 (t - b) (order 2),
+// where t, a, b are p_rgh at the ends of this step and the two before; the
+// backtests predict t from a, b and the step before those (q) in the same
+// forms with coefficients b1 and c1, c2.
+struct GuessArgs {
+  double r, q1, q2, b1, c1, c2;
+  int use;  // highest order the stored steps allow (0 to 2)
+  int nbt;  // orders whose backtest the stored steps allow (0 to 3)
+  int nd;   // later correctors' changes recorded (0 or n_corr - 1)
+};
+
 struct Handle {
   int ns = 1;
   std::vector<Geom> hG;   // per sample, absolute arena offsets
@@ -135,16 +147,23 @@ struct Handle {
   // step leaves U^n in U3).  3 x NC each
   double *U = nullptr, *U2 = nullptr, *U3 = nullptr;
   double *prgh = nullptr, *p = nullptr;
-  // p_rgh of the previous step's end, for the extrapolated initial guess of
-  // the first corrector's solve; valid once a step has run since the state
-  // was last set.  extrap_r: the factor the last guess used (0: none);
-  // graph_r: the factor the captured steps use.
-  double *pprev = nullptr;
+  // p_rgh at the ends of the previous three steps (pprev, pprev2, pprev3),
+  // for the extrapolated initial guess of the first corrector's solve; hist
+  // of them are valid (0 to 3: steps run since the state was last set), with
+  // time steps dt_prev, dt_prev2 and dt_prev3.
+  double *pprev = nullptr, *pprev2 = nullptr, *pprev3 = nullptr;
   // the solution of the corrector before (p1) and, per later corrector, the
   // change its solve made in the previous step (dcorr, (n_corr - 1) x NC)
   double *p1 = nullptr, *dcorr = nullptr;
-  bool pprev_ok = false;
-  double dt_prev = 0.0, extrap_r = 0.0, graph_r = -1.0;
+  // per sample: the extrapolation order of the next first guess (gord) and,
+  // per later corrector, whether the stored change predicts the next one
+  // (gwarm, ns x (n_corr - 1)); set on the device after every step
+  int *gord = nullptr, *gwarm = nullptr;
+  int hist = 0;
+  double dt_prev = 0.0, dt_prev2 = 0.0, dt_prev3 = 0.0;
+  // the first guess's coefficients as the last step used them and as the
+  // captured steps use them
+  GuessArgs guess_used{}, graph_guess{0, 0, 0, 0, 0, 0, -1, -1, -1};
   double *F = nullptr;                 // faces
   double *F2 = nullptr;                // the correctors' fluxes (swapped with F per step)
   // closures of the current alpha: k_rl/mu_l, k_rg/mu_g, p_c (0 in clear cells)
