@@ -152,6 +152,10 @@ typedef struct {
   double max_div;       /* max over cells of |sum_out F_f| after the last step (the
                            discrete divergence; at most p_tol p_bnorm[n_corr - 1] when the
                            last solve converged) */
+  int p_guess_order;    /* time-extrapolation order of the next step's first pressure
+                           guess (0: p_rgh itself, 1: linear, 2: quadratic) */
+  int p_guess_change;   /* bit c - 1 set: corrector c's next guess adds the change its
+                           solve made in the last step (c = 1 .. n_corr - 1) */
 } dbs_stats;
 
 typedef struct dbs_handle dbs_handle;

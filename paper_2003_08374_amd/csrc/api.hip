@@ -19,6 +19,8 @@ struct dbs_handle {
   Handle h;
 };
 
+static int hip_check(Handle *h, hipError_t e, const char *what);
+
 namespace dbs {
 
 static const char *kNames[KC_COUNT] = {
@@ -36,34 +38,41 @@ void prof_begin(Handle *h, int cls) {
     // records, which would add its own cost to every bracketed launch
     for (int i = 0; i < 256; i++) {
       hipEvent_t e;
-      hipEventCreateWithFlags(&e, hipEventDisableSystemFence);
+      if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) break;
       t.ev.push_back(e);
     }
     t.cls.resize(t.ev.size() / 2 + 1);
   }
+  // no events to be had: this launch goes untimed (profiling is
+  // instrumentation only; the launch itself reports its own errors)
+  t.skip = t.used + 2 > t.ev.size();
+  if (t.skip) return;
   t.cls[t.used / 2] = cls;
-  hipEventRecord(t.ev[t.used], h->stream);
+  t.ok = t.ok && hipEventRecord(t.ev[t.used], h->stream) == hipSuccess;
 }
 
 void prof_end(Handle *h, int cls) {
   (void)cls;
   Timer &t = h->tm;
-  hipEventRecord(t.ev[t.used + 1], h->stream);
+  if (t.skip) return;
+  t.ok = t.ok && hipEventRecord(t.ev[t.used + 1], h->stream) == hipSuccess;
   t.used += 2;
 }
 
+// called after the stream has been synchronised and checked: add the timed
+// launches to the per-class totals (none if an event failed)
 void prof_collect(Handle *h) {
   Timer &t = h->tm;
   if (t.used == 0) return;
-  hipStreamSynchronize(h->stream);
-  for (size_t i = 0; i < t.used; i += 2) {
+  for (size_t i = 0; i < t.used && t.ok; i += 2) {
     float ms = 0.f;
-    hipEventElapsedTime(&ms, t.ev[i], t.ev[i + 1]);
+    if (hipEventElapsedTime(&ms, t.ev[i], t.ev[i + 1]) != hipSuccess) continue;
     int c = t.cls[i / 2];
     h->k_launches[c]++;
     h->k_ms[c] += ms;
   }
   t.used = 0;
+  t.ok = true;
 }
 
 // ------------------------------------------------------------- statistics
@@ -199,7 +208,7 @@ void add_time(Handle *h, double dt) {
   wave_profile(h);
 }
 
-void cell_stats(Handle *h) {
+int cell_stats(Handle *h) {
   dim3 blk(BX, BY);
   const int nb = h->cell.nblk;
   DBS_LAUNCH(h, KC_STATS, k_stats, h->cgrid, blk, h->seg, (const double *)h->alpha,
@@ -207,7 +216,7 @@ void cell_stats(Handle *h) {
              (const double *)h->F, h->partials, nb);
   DBS_LAUNCH(h, KC_STATS, k_stats_final, dim3(h->ns), dim3(1024), (const double *)h->partials,
              nb, (const int *)h->cell.bp, h->dsstat_h);
-  hipStreamSynchronize(h->stream);
+  return hip_check(h, hipStreamSynchronize(h->stream), "cell statistics");
 }
 
 }  // namespace dbs
@@ -391,8 +400,8 @@ static Phys make_phys(const dbs_physics *phys) {
 
 static void clear_graphs(Handle *h) {
   for (auto &kv : h->graphs) {
-    if (kv.second.front) hipGraphExecDestroy(kv.second.front);
-    if (kv.second.back) hipGraphExecDestroy(kv.second.back);
+    if (kv.second.front) (void)hipGraphExecDestroy(kv.second.front);
+    if (kv.second.back) (void)hipGraphExecDestroy(kv.second.back);
   }
   h->graphs.clear();
 }
@@ -445,7 +454,7 @@ static int create_impl(int n, const dbs_grid *grids, const dbs_physics *phys, co
   h->stream = h->own_stream;
   if ((rc = hip_check(h, hipEventCreateWithFlags(&h->flag_ev, hipEventDisableTiming),
                       "hipEventCreateWithFlags"))) {
-    hipStreamDestroy(h->own_stream);
+    (void)hipStreamDestroy(h->own_stream);
     delete H;
     return rc;
   }
@@ -620,9 +629,10 @@ static int copy_out3(Handle *h, double *dst, const double *src) {
 
 // CFL-adaptive time step: dt <- min(dt_max, 1.2 dt, target dt / Co) from
 // the Courant numbers of the current fluxes (one dt for the whole batch)
-static void adapt_dt(Handle *h) {
-  if (!(h->ctl.target_courant > 0.0)) return;
-  cell_stats(h);
+static int adapt_dt(Handle *h) {
+  if (!(h->ctl.target_courant > 0.0)) return DBS_OK;
+  const int e = cell_stats(h);
+  if (e) return e;
   double co = 0.0;
   for (int s = 0; s < h->ns; s++) co = std::max(co, h->hsstat[NSTAT * s + 3]);
   double dt = std::min(h->ctl.dt_max, 1.2 * h->ctl.dt);
@@ -630,11 +640,13 @@ static void adapt_dt(Handle *h) {
   h->ctl.dt = dt;
   for (int s = 0; s < h->ns; s++) h->hG[s].dt = dt;
   DBS_LAUNCH(h, KC_MISC, k_set_dt, dim3((h->ns + 255) / 256), dim3(256), h->dG, h->ns, dt);
+  return DBS_OK;
 }
 
 static int courant_check(Handle *h) {
   if (!(h->ctl.max_courant > 0.0)) return DBS_OK;
-  cell_stats(h);
+  const int e = cell_stats(h);
+  if (e) return e;
   for (int s = 0; s < h->ns; s++) {
     const double co = h->hsstat[NSTAT * s + 3];
     h->st[s].max_courant = co;
@@ -949,8 +961,9 @@ static int step_body(Handle *h, TraceOut *tr, int budget, std::vector<int> *its_
 }
 
 static int eager_step(Handle *h, TraceOut *tr, std::vector<int> *its_out) {
-  adapt_dt(h);
-  int rc = courant_check(h);
+  int rc = adapt_dt(h);
+  if (rc) return rc;
+  rc = courant_check(h);
   if (rc) return rc;
   rc = step_body(h, tr, 0, its_out);
   for (int s = 0; s < h->ns; s++) h->st[s].steps++;
@@ -1060,12 +1073,12 @@ static int graph_step(Handle *h) {
       if (rc) break;
       hipGraphExec_t &ex = part == 0 ? sg.front : sg.back;
       rc = hip_check(h, hipGraphInstantiate(&ex, g, nullptr, nullptr, 0), "instantiate");
-      hipGraphDestroy(g);
+      (void)hipGraphDestroy(g);
     }
     h->prof_mask = pm;
     if (rc) {
-      if (sg.front) hipGraphExecDestroy(sg.front);
-      if (sg.back) hipGraphExecDestroy(sg.back);
+      if (sg.front) (void)hipGraphExecDestroy(sg.front);
+      if (sg.back) (void)hipGraphExecDestroy(sg.back);
       return rc;
     }
     it = h->graphs.emplace(key, sg).first;
@@ -1160,12 +1173,36 @@ static int graph_step(Handle *h) {
   return rc;
 }
 
+// the per-sample choices of the next step's pressure guesses
+static int guess_stats(Handle *h) {
+  const int ns = h->ns, nd = h->ctl.n_corr - 1;
+  std::vector<int> go(ns), gw((size_t)ns * std::max(nd, 0));
+  int e = hip_check(h, hipMemcpyAsync(go.data(), h->gord, sizeof(int) * ns,
+                                      hipMemcpyDeviceToHost, h->stream), "guess state");
+  if (!e && nd > 0)
+    e = hip_check(h, hipMemcpyAsync(gw.data(), h->gwarm, sizeof(int) * gw.size(),
+                                    hipMemcpyDeviceToHost, h->stream), "guess state");
+  if (!e) e = hip_check(h, hipStreamSynchronize(h->stream), "guess state");
+  if (e) return e;
+  for (int s = 0; s < ns; s++) {
+    h->st[s].p_guess_order = std::min(go[s], std::min(h->hist, 2));
+    int m = 0;
+    for (int k = 0; k < nd; k++)
+      if (h->hist >= 1 && gw[(size_t)s * nd + k]) m |= 1 << k;
+    h->st[s].p_guess_change = m;
+  }
+  return DBS_OK;
+}
+
 static int finish_steps(Handle *h, int rc) {
   int e = hip_check(h, hipStreamSynchronize(h->stream), "step");
   if (!e) e = hip_check(h, hipGetLastError(), "kernel launch");
   if (e) return e;
   prof_collect(h);
-  cell_stats(h);
+  e = cell_stats(h);
+  if (e) return e;
+  e = guess_stats(h);
+  if (e) return e;
   bool bad = false, out = false;
   for (int s = 0; s < h->ns; s++) {
     const double *v = h->hsstat + NSTAT * s;
@@ -1185,21 +1222,24 @@ static int finish_steps(Handle *h, int rc) {
 
 // time one pressure solve of the current system (from x0) under the present knobs
 static double time_solve(Handle *h, const double *x0, int *ok) {
-  hipEvent_t e0, e1;
-  hipEventCreate(&e0);
-  hipEventCreate(&e1);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  *ok = 0;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    return 0.0;
+  }
   copy_n(h, x0, h->prgh, (size_t)h->NC);
   std::vector<int> its(h->ns);
   std::vector<double> rel(h->ns);
-  hipEventRecord(e0, h->stream);
+  bool good = hipEventRecord(e0, h->stream) == hipSuccess;
   const int rc = pressure_solve(h, h->rAU, h->rhs, h->prgh, 0, its.data(), rel.data());
-  hipEventRecord(e1, h->stream);
-  hipEventSynchronize(e1);
+  good = good && hipEventRecord(e1, h->stream) == hipSuccess;
+  good = good && hipEventSynchronize(e1) == hipSuccess;
   float ms = 0.f;
-  hipEventElapsedTime(&ms, e0, e1);
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
-  *ok = rc == DBS_OK;
+  good = good && hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  *ok = good && rc == DBS_OK;
   return ms;
 }
 
@@ -1380,16 +1420,17 @@ int dbs_batch_size(const dbs_handle *H) { return H ? H->h.ns : 0; }
 void dbs_destroy(dbs_handle *H) {
   if (!H) return;
   Handle *h = &H->h;
-  if (h->stream) hipStreamSynchronize(h->stream);
+  // teardown: nothing is left to report an error to
+  if (h->stream) (void)hipStreamSynchronize(h->stream);
   clear_graphs(h);
-  for (void *p : h->allocs) hipFree(p);
-  for (void *p : h->hallocs) hipHostFree(p);
-  for (hipEvent_t e : h->tm.ev) hipEventDestroy(e);
-  if (h->flag_ev) hipEventDestroy(h->flag_ev);
+  for (void *p : h->allocs) (void)hipFree(p);
+  for (void *p : h->hallocs) (void)hipHostFree(p);
+  for (hipEvent_t e : h->tm.ev) (void)hipEventDestroy(e);
+  if (h->flag_ev) (void)hipEventDestroy(h->flag_ev);
   for (hipEvent_t e : h->mom_ev)
-    if (e) hipEventDestroy(e);
+    if (e) (void)hipEventDestroy(e);
   pressure_free(h);
-  if (h->own_stream) hipStreamDestroy(h->own_stream);
+  if (h->own_stream) (void)hipStreamDestroy(h->own_stream);
   delete H;
 }
 
@@ -1400,7 +1441,7 @@ const char *dbs_last_error(const dbs_handle *H) {
 int dbs_set_stream(dbs_handle *H, void *stream) {
   if (!H) return DBS_EINVAL;
   Handle *h = &H->h;
-  hipStreamSynchronize(h->stream);
+  if (int rc = hip_check(h, hipStreamSynchronize(h->stream), "set_stream")) return rc;
   h->stream = stream ? (hipStream_t)stream : h->own_stream;
   return DBS_OK;
 }
@@ -1437,7 +1478,7 @@ int dbs_batch_set_state_dev(dbs_handle *H, int i, const double *alpha, const dou
   Handle *h = &H->h;
   if (int rc = check_sample(h, i)) return rc;
   hipStream_t s = stream ? (hipStream_t)stream : h->stream;
-  hipStreamSynchronize(h->stream);
+  if (int rc = hip_check(h, hipStreamSynchronize(h->stream), "set_state")) return rc;
   return set_state_impl(h, i, alpha, U, prgh, F, hipMemcpyDeviceToDevice, s);
 }
 
@@ -1491,7 +1532,7 @@ int dbs_set_graph(dbs_handle *H, int on) {
     h->err = "graph mode replays a fixed time step; adaptive stepping is eager only";
     return DBS_EINVAL;
   }
-  hipStreamSynchronize(h->stream);
+  if (int rc = hip_check(h, hipStreamSynchronize(h->stream), "set_graph")) return rc;
   h->graph_mode = on ? 1 : 0;
   reset_graphs(h);
   // on > 1: start from a budget of on - 1 iterations (and predictor sweeps)
@@ -1586,7 +1627,7 @@ int dbs_set_tuning(dbs_handle *H, int kz, int kz_coarse, int sweeps, int coarse_
       coarse_block > 4)
     return DBS_EINVAL;
   Handle *h = &H->h;
-  hipStreamSynchronize(h->stream);
+  if (int rc = hip_check(h, hipStreamSynchronize(h->stream), "set_tuning")) return rc;
   h->kz_fine = kz;
   h->kz_coarse = kz_coarse;
   h->coarse_block = coarse_block;

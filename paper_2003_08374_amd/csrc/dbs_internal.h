@@ -89,6 +89,8 @@ struct Timer {
   std::vector<hipEvent_t> ev;  // pairs (start, stop)
   std::vector<int> cls;
   size_t used = 0;
+  bool skip = false;  // the current launch is untimed (no event to be had)
+  bool ok = true;     // every record since the last collection succeeded
 };
 
 // one captured step (graph mode), keyed by the buffer roles it was captured with
@@ -328,6 +330,6 @@ void pressure_norms(Handle *h, double *bnorm, double *res0);
 // api.hip
 void add_time(Handle *h, double dt);  // move the boundary-value time
 // per sample: min a, max a, sum phi a V, max Co, nonfinite count, max |div F|
-void cell_stats(Handle *h);
+int cell_stats(Handle *h);
 
 }  // namespace dbs

@@ -465,7 +465,6 @@ __device__ inline double phi_hbya(const Geom &G, const Phys &Ph, const MomArgs &
   const int own = s ? P.c : nb, nbr = s ? nb : P.c;
   const double *Ha = H + (size_t)a * G.vs;
   const double rAUf = 0.5 * (M.rAU[own] + M.rAU[nbr]);
-  const double gxf = gdotx_face(G, Ph, P, a, s);
   return 0.5 * (Ha[own] + Ha[nbr]) * G.area[a] +
          rAUf * M.FB[face_of(G, P, a, s)] * G.area[a];
 }

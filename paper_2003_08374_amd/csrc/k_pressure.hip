@@ -1605,7 +1605,6 @@ __global__ void __launch_bounds__(NT2) k_smooth25(OpB<R> LB, SH S, const B *__re
 // where two half sweeps read and write every cache line twice.
 
 constexpr int FW = 128;              // tile width (cells), one x-pair per thread
-constexpr int FY2 = TY2 + 4;         // rows of a plane with a 2-row ring
 constexpr int FX1 = FW + 2;          // row stride of planes with a 1-cell ring
 constexpr int FY1 = TY2 + 2;
 constexpr int NX1 = FX1 * FY1;
