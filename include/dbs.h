@@ -154,8 +154,10 @@ typedef struct {
                            last solve converged) */
   int p_guess_order;    /* time-extrapolation order of the next step's first pressure
                            guess (0: p_rgh itself, 1: linear, 2: quadratic) */
-  int p_guess_change;   /* bit c - 1 set: corrector c's next guess adds the change its
-                           solve made in the last step (c = 1 .. n_corr - 1) */
+  int p_guess_change[16]; /* per corrector c >= 1: the change its next guess adds to the
+                           previous corrector's solution (0: none, 1: the change its solve
+                           made in the last step, 2: the last two changes extrapolated
+                           linearly in time); [0] is 0 */
 } dbs_stats;
 
 typedef struct dbs_handle dbs_handle;
@@ -182,8 +184,9 @@ int dbs_set_state(dbs_handle *h, const double *alpha, const double *U,
    the previous steps (per sample, the order among 0, 1 and 2 that best
    predicted the last step) less the later correctors' predicted changes;
    each later corrector's starts from the previous corrector's solution plus
-   its predicted change (the change its solve made in the previous step,
-   where that predicted the last change better than none).  The guesses
+   its predicted change (none, the change its solve made in the previous
+   step, or the last two changes extrapolated, whichever predicted the last
+   change best).  The guesses
    change only the iteration counts; the first step after creation or a
    state reset starts from p_rgh itself.  Synchronises the library stream
    before returning. */

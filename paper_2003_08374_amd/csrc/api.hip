@@ -507,8 +507,8 @@ static int create_impl(int n, const dbs_grid *grids, const dbs_physics *phys, co
   h->gord = (int *)dmalloc_bytes(h, sizeof(int) * n, rc);
   if (ctl->n_corr > 1) {
     h->p1 = dmalloc(h, NC, rc);
-    h->dcorr = dmalloc(h, (size_t)(ctl->n_corr - 1) * NC, rc);
-    h->gwarm = (int *)dmalloc_bytes(h, sizeof(int) * n * (ctl->n_corr - 1), rc);
+    h->dcorr = dmalloc(h, (size_t)2 * (ctl->n_corr - 1) * NC, rc);
+    h->gchg = (int *)dmalloc_bytes(h, sizeof(int) * n * (ctl->n_corr - 1), rc);
   }
   h->F = dmalloc(h, NF, rc); h->F2 = dmalloc(h, NF, rc);
   h->ml = dmalloc(h, NC, rc); h->mg = dmalloc(h, NC, rc); h->pc = dmalloc(h, NC, rc);
@@ -694,14 +694,14 @@ static int step_front(Handle *h, TraceOut *tr, int budget) {
 // changes the later correctors' solves are predicted to make; each later
 // corrector's solve starts from the previous corrector's solution plus its
 // predicted change.  Every prediction is chosen per sample from how it would
-// have fared one step back: the extrapolation order (0: p_rgh^n itself, 1:
-// linear, 2: quadratic) whose prediction of p_rgh^n from the steps before
-// came closest in the L2 norm, and for each later corrector the change of
-// the previous step when it predicted this step's change better than no
-// change.  (At 256^3, mixed, steps 13 to 22 from rest, the quadratic order
-// wins and the first solve starts 8 times closer than with the linear one
-// alone; in the wave flume p_rgh alternates from step to step, so order 0
-// wins there and the previous step's change does not help.)
+// have fared one step back: the extrapolation order of p_rgh (0: p_rgh^n
+// itself, 1: linear, 2: quadratic) whose prediction of p_rgh^n from the
+// steps before came closest in the L2 norm, and for each later corrector
+// the prediction of its change (0: none, 1: the previous step's change, 2:
+// the last two changes extrapolated linearly) that came closest to this
+// step's change.  (At 256^3, mixed, steps 13 to 22 from rest, the quadratic
+// order and the linear change win; in the wave flume p_rgh and the changes
+// alternate from step to step, so order 0 and no change win there.)
 
 // one block per sample: the NQ block partials of the sample summed in a
 // fixed order; the sums are valid in thread 0
@@ -744,17 +744,24 @@ __device__ __forceinline__ void block_partials(const double *v, int gb, double *
     }
 }
 
+// predicted change of a later corrector's solve, kind 1 or 2, from its last
+// change d and the one before d1 (r: this step's dt over the last one's)
+__device__ __forceinline__ double predicted_change(int kind, double d, double d1, double r) {
+  return kind == 2 ? fma(r, d - d1, d) : d;
+}
+
 // The first corrector's guess in p (p_rgh^n on entry) with the sample's
-// order ord[s] (at most A.use) less the changes d of the later correctors
-// whose flag warm[s * nd + k] is set; the squared errors of the backtests
-// as block partials; the history shifts (pq <- pb <- pa <- p_rgh^n).
+// order ord[s] (at most A.use) less the later correctors' predicted changes
+// (kind chg[s * nd + k] at most A.use; slice k of d holds the last change
+// and slice k + nd the one before); the squared errors of the backtests as
+// block partials; the history shifts (pq <- pb <- pa <- p_rgh^n).
 __global__ void __launch_bounds__(NTHREADS) k_extrap(Segs SG, double *__restrict__ p,
                                                      double *__restrict__ pa,
                                                      double *__restrict__ pb,
                                                      double *__restrict__ pq,
                                                      const double *__restrict__ d, size_t nc,
                                                      const int *__restrict__ ord,
-                                                     const int *__restrict__ warm, GuessArgs A,
+                                                     const int *__restrict__ chg, GuessArgs A,
                                                      double *__restrict__ part, int nb) {
   double e[3] = {0.0, 0.0, 0.0};
   FOR_CELLS(SG, G, P) {
@@ -764,8 +771,12 @@ __global__ void __launch_bounds__(NTHREADS) k_extrap(Segs SG, double *__restrict
     double g = t;
     if (o == 1) g = fma(A.r, t - a, t);
     else if (o == 2) g = fma(A.q2, t - b, fma(A.q1, t - a, t));
-    for (int k = 0; k < A.nd; k++)
-      if (warm[cell_sg * A.nd + k]) g -= d[(size_t)k * nc + c];
+    for (int k = 0; k < A.nd; k++) {
+      const int kind = min(chg[cell_sg * A.nd + k], A.use);
+      if (kind >= 1)
+        g -= predicted_change(kind, d[(size_t)k * nc + c],
+                              kind == 2 ? d[(size_t)(k + A.nd) * nc + c] : 0.0, A.r);
+    }
     if (A.nbt >= 1) e[0] = (t - a) * (t - a);
     if (A.nbt >= 2) {
       const double x = t - fma(A.b1, a - b, a);
@@ -801,50 +812,67 @@ __global__ void __launch_bounds__(1024) k_extrap_final(const double *__restrict_
 }
 
 // A later corrector's guess: the previous corrector's solution (kept in
-// p1) plus the change d this corrector's solve made in the previous step,
-// where the sample's flag is set and a previous step has run.
+// p1) plus the change predicted with the sample's kind (at most use) from
+// the last change d and the one before d1.
 __global__ void __launch_bounds__(NTHREADS) k_corr_guess(Segs SG, double *__restrict__ p,
                                                          double *__restrict__ p1,
                                                          const double *__restrict__ d,
-                                                         const int *__restrict__ warm, int nd,
-                                                         int k, int ok) {
+                                                         const double *__restrict__ d1,
+                                                         const int *__restrict__ chg, int nd,
+                                                         int k, int use, double r) {
   FOR_CELLS(SG, G, P) {
     const size_t c = P.c;
     const double t = p[c];
     p1[c] = t;
-    if (ok && warm[cell_sg * nd + k]) p[c] = t + d[c];
+    const int kind = min(chg[cell_sg * nd + k], use);
+    if (kind >= 1) p[c] = t + predicted_change(kind, d[c], kind == 2 ? d1[c] : 0.0, r);
   }
 }
 
-// The change of this step's solve, d <- p - p1, and as block partials the
-// squared norms of its difference from the previous step's change (when
-// old: that change is stored) and of the change itself.
+// The change of this step's solve x = p - p1; as block partials the squared
+// errors of its predictions from the stored changes (none; the last change,
+// with hist >= 1 stored steps; the last two extrapolated, with hist >= 2);
+// the changes shift (d1 <- d <- x).
 __global__ void __launch_bounds__(NTHREADS) k_corr_record(Segs SG, const double *__restrict__ p,
                                                           const double *__restrict__ p1,
-                                                          double *__restrict__ d, int old,
-                                                          double *__restrict__ part, int nb) {
-  double e[2] = {0.0, 0.0};
+                                                          double *__restrict__ d,
+                                                          double *__restrict__ d1, int hist,
+                                                          double r, double *__restrict__ part,
+                                                          int nb) {
+  double e[3] = {0.0, 0.0, 0.0};
   FOR_CELLS(SG, G, P) {
     const size_t c = P.c;
     const double x = p[c] - p1[c];
-    if (old) {
-      const double y = x - d[c];
-      e[0] = y * y;
+    e[0] = x * x;
+    if (hist >= 1) {
+      const double dl = d[c];
+      const double y = x - dl;
+      e[1] = y * y;
+      if (hist >= 2) {
+        const double z = x - predicted_change(2, dl, d1[c], r);
+        e[2] = z * z;
+      }
+      d1[c] = dl;
     }
-    e[1] = x * x;
     d[c] = x;
   }
-  block_partials<2>(e, cell_gb, part, nb);
+  block_partials<3>(e, cell_gb, part, nb);
 }
 
-// one block per sample: use the change as the next step's prediction when
-// it predicted this step's change better than no change (and by default)
+// one block per sample: the kind of the next step's change prediction, the
+// one whose backtest erred least (the last change while none can be told)
 __global__ void __launch_bounds__(1024) k_record_final(const double *__restrict__ part, int nb,
-                                                       const int *__restrict__ bp, int old,
-                                                       int *__restrict__ warm, int nd, int k) {
-  double r[2];
-  sample_sums<2>(part, nb, bp, r);
-  if (threadIdx.x == 0) warm[blockIdx.x * nd + k] = old ? (r[0] < r[1] ? 1 : 0) : 1;
+                                                       const int *__restrict__ bp, int hist,
+                                                       int *__restrict__ chg, int nd, int k) {
+  double r[3];
+  sample_sums<3>(part, nb, bp, r);
+  if (threadIdx.x != 0) return;
+  int o = 1;
+  if (hist >= 1) {
+    o = r[1] < r[0] ? 1 : 0;
+    if (hist >= 2 && r[2] < r[o]) o = 2;
+  }
+  chg[blockIdx.x * nd + k] = o;
 }
 
 // Lagrange extrapolation to offset tau past node 0 from nodes 0, -h1 and
@@ -878,7 +906,7 @@ static void extrapolate_guess(Handle *h) {
   const int nb = h->cell.nblk;
   DBS_LAUNCH(h, KC_MISC, k_extrap, h->cgrid, dim3(BX, BY), h->seg, h->prgh, h->pprev,
              h->pprev2, h->pprev3, (const double *)h->dcorr, (size_t)h->NC,
-             (const int *)h->gord, (const int *)h->gwarm, A, h->partials, nb);
+             (const int *)h->gord, (const int *)h->gchg, A, h->partials, nb);
   DBS_LAUNCH(h, KC_MISC, k_extrap_final, dim3(h->ns), dim3(1024), (const double *)h->partials,
              nb, (const int *)h->cell.bp, A.nbt, h->gord);
   h->guess_used = A;
@@ -892,7 +920,7 @@ static void extrapolate_guess(Handle *h) {
 static int step_back(Handle *h, TraceOut *tr, int budget, std::vector<int> *its_out,
                      int *sweeps_out, int rc) {
   int solve_rc = DBS_OK;
-  const int warm = h->hist >= 1 ? 1 : 0;  // the changes of a previous step are recorded
+  const int hb = h->hist;  // steps stored before this one (changes recorded: hb >= 1)
   const size_t NCs = (size_t)h->NC;
   const int nd = h->ctl.n_corr - 1, nb = h->cell.nblk;
   const dim3 blk(BX, BY);
@@ -905,19 +933,22 @@ static int step_back(Handle *h, TraceOut *tr, int budget, std::vector<int> *its_
       rc |= copy_out(h, tr->phiHbyA, h->phiH, h->hG[0].nf);
       rc |= copy_out(h, tr->b, h->rhs, h->hG[0].nc);
     }
+    // this corrector's last change and the one before
     double *dc = c > 0 ? h->dcorr + (size_t)(c - 1) * NCs : nullptr;
+    double *dc1 = c > 0 ? h->dcorr + (size_t)(c - 1 + nd) * NCs : nullptr;
     if (c == 0)
-      extrapolate_guess(h);
+      extrapolate_guess(h);  // sets guess_used, this step's coefficients
     else
       DBS_LAUNCH(h, KC_MISC, k_corr_guess, h->cgrid, blk, h->seg, h->prgh, h->p1,
-                 (const double *)dc, (const int *)h->gwarm, nd, c - 1, warm);
+                 (const double *)dc, (const double *)dc1, (const int *)h->gchg, nd, c - 1,
+                 std::min(hb, 2), h->guess_used.r);
     const int b = budget > 0 ? h->graph_budget[c] : 0;
     const int src = pressure_solve(h, h->rAU, h->rhs, h->prgh, b, its.data(), rel.data());
     if (c > 0) {
       DBS_LAUNCH(h, KC_MISC, k_corr_record, h->cgrid, blk, h->seg, (const double *)h->prgh,
-                 (const double *)h->p1, dc, warm, h->partials, nb);
+                 (const double *)h->p1, dc, dc1, hb, h->guess_used.r, h->partials, nb);
       DBS_LAUNCH(h, KC_MISC, k_record_final, dim3(h->ns), dim3(1024),
-                 (const double *)h->partials, nb, (const int *)h->cell.bp, warm, h->gwarm, nd,
+                 (const double *)h->partials, nb, (const int *)h->cell.bp, hb, h->gchg, nd,
                  c - 1);
     }
     if (budget > 0) {
@@ -1176,20 +1207,20 @@ static int graph_step(Handle *h) {
 // the per-sample choices of the next step's pressure guesses
 static int guess_stats(Handle *h) {
   const int ns = h->ns, nd = h->ctl.n_corr - 1;
-  std::vector<int> go(ns), gw((size_t)ns * std::max(nd, 0));
+  std::vector<int> go(ns), gc((size_t)ns * std::max(nd, 0));
   int e = hip_check(h, hipMemcpyAsync(go.data(), h->gord, sizeof(int) * ns,
                                       hipMemcpyDeviceToHost, h->stream), "guess state");
   if (!e && nd > 0)
-    e = hip_check(h, hipMemcpyAsync(gw.data(), h->gwarm, sizeof(int) * gw.size(),
+    e = hip_check(h, hipMemcpyAsync(gc.data(), h->gchg, sizeof(int) * gc.size(),
                                     hipMemcpyDeviceToHost, h->stream), "guess state");
   if (!e) e = hip_check(h, hipStreamSynchronize(h->stream), "guess state");
   if (e) return e;
+  const int use = std::min(h->hist, 2);
   for (int s = 0; s < ns; s++) {
-    h->st[s].p_guess_order = std::min(go[s], std::min(h->hist, 2));
-    int m = 0;
-    for (int k = 0; k < nd; k++)
-      if (h->hist >= 1 && gw[(size_t)s * nd + k]) m |= 1 << k;
-    h->st[s].p_guess_change = m;
+    h->st[s].p_guess_order = std::min(go[s], use);
+    h->st[s].p_guess_change[0] = 0;
+    for (int k = 0; k < nd && k < 15; k++)
+      h->st[s].p_guess_change[k + 1] = std::min(gc[(size_t)s * nd + k], use);
   }
   return DBS_OK;
 }

@@ -155,12 +155,14 @@ struct Handle {
   // time steps dt_prev, dt_prev2 and dt_prev3.
   double *pprev = nullptr, *pprev2 = nullptr, *pprev3 = nullptr;
   // the solution of the corrector before (p1) and, per later corrector, the
-  // change its solve made in the previous step (dcorr, (n_corr - 1) x NC)
+  // changes its solve made in the previous two steps (dcorr: n_corr - 1
+  // slices of the last changes, then n_corr - 1 of the ones before, NC each)
   double *p1 = nullptr, *dcorr = nullptr;
   // per sample: the extrapolation order of the next first guess (gord) and,
-  // per later corrector, whether the stored change predicts the next one
-  // (gwarm, ns x (n_corr - 1)); set on the device after every step
-  int *gord = nullptr, *gwarm = nullptr;
+  // per later corrector, the kind of its change prediction (gchg, ns x
+  // (n_corr - 1): 0 none, 1 the last change, 2 linear in the last two); set
+  // on the device after every step
+  int *gord = nullptr, *gchg = nullptr;
   int hist = 0;
   double dt_prev = 0.0, dt_prev2 = 0.0, dt_prev3 = 0.0;
   // the first guess's coefficients as the last step used them and as the

@@ -69,7 +69,7 @@ class Stats(C.Structure):
                 ("time", C.c_double), ("dt", C.c_double), ("mom_sweeps", C.c_int),
                 ("mom_relres", C.c_double), ("p_bnorm", C.c_double * 16),
                 ("p_res0", C.c_double * 16), ("max_div", C.c_double),
-                ("p_guess_order", C.c_int), ("p_guess_change", C.c_int)]
+                ("p_guess_order", C.c_int), ("p_guess_change", C.c_int * 16)]
 
 
 _DP = C.POINTER(C.c_double)
@@ -279,7 +279,8 @@ class _Handle:
                 "time": s.time, "dt": s.dt, "mom_sweeps": s.mom_sweeps,
                 "mom_relres": s.mom_relres, "p_bnorm": list(s.p_bnorm)[:n],
                 "p_res0": list(s.p_res0)[:n], "max_div": s.max_div,
-                "p_guess_order": s.p_guess_order, "p_guess_change": s.p_guess_change}
+                "p_guess_order": s.p_guess_order,
+                "p_guess_change": list(s.p_guess_change)[:n]}
 
     # -------------------------------------------------------------- profiling
     def set_profiling(self, mask):

@@ -4,8 +4,9 @@ so these tests pin the choice itself on workloads where it is clear-cut.
 
 The first corrector's guess extrapolates p_rgh in time with the order (0, 1
 or 2) whose prediction of the last step's p_rgh from the steps before erred
-least; a later corrector adds the change its solve made in the previous step
-where that change predicted the last one better than no change."""
+least; a later corrector adds the change of its solve
+predicted with the kind (none, its last change, its last two changes
+extrapolated linearly) that best predicted its last change."""
 from __future__ import annotations
 
 import pytest
@@ -40,18 +41,18 @@ def _flume():
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_smooth_flow_takes_quadratic_and_change(precision):
     """Flow through the fractured block, smooth in time once the start-up
-    transient has passed: quadratic extrapolation and the previous step's
-    corrector change win from step 8 on (order 0 during the first steps,
-    when p_rgh jumps away from its initial field)."""
+    transient has passed: quadratic extrapolation of p_rgh and linear
+    extrapolation of the second corrector's change win by step 10 (order 0
+    during the first steps, when p_rgh jumps away from its initial field)."""
     from paper_2003_08374_amd import dbs
     with dbs.Solver(_fractured(), precision=precision) as s:
         s.step(1)
         st = s.stats()
-        # one stored step: linear at most, the change used by default
-        assert (st["p_guess_order"], st["p_guess_change"]) == (1, 1)
+        # one stored step: linear at most, the last change by default
+        assert (st["p_guess_order"], st["p_guess_change"]) == (1, [0, 1])
         s.step(9)
         st = s.stats()
-        assert (st["p_guess_order"], st["p_guess_change"]) == (2, 1)
+        assert (st["p_guess_order"], st["p_guess_change"]) == (2, [0, 2])
 
 
 def test_alternating_flume_takes_p_rgh_itself():
@@ -91,7 +92,7 @@ def test_batch_samples_choose_alone():
             for _ in range(n):
                 s.step(1)
                 st = s.stats()
-                seq.append((st["p_guess_order"], st["p_guess_change"]))
+                seq.append((st["p_guess_order"], tuple(st["p_guess_change"])))
         alone.append(seq)
     batch = [[] for _ in cases]
     with dbs.BatchSolver(cases, precision="mixed") as B:
@@ -99,6 +100,6 @@ def test_batch_samples_choose_alone():
             B.step(1)
             for i in range(len(cases)):
                 st = B.stats(i)
-                batch[i].append((st["p_guess_order"], st["p_guess_change"]))
+                batch[i].append((st["p_guess_order"], tuple(st["p_guess_change"])))
     assert batch == alone
     assert any(a != b for a, b in zip(*alone))
