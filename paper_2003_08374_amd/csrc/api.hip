@@ -943,7 +943,9 @@ static int step_back(Handle *h, TraceOut *tr, int budget, std::vector<int> *its_
                  (const double *)dc, (const double *)dc1, (const int *)h->gchg, nd, c - 1,
                  std::min(hb, 2), h->guess_used.r);
     const int b = budget > 0 ? h->graph_budget[c] : 0;
+    h->keep_hierarchy = c > 0;  // rAU is the predictor's for every corrector
     const int src = pressure_solve(h, h->rAU, h->rhs, h->prgh, b, its.data(), rel.data());
+    h->keep_hierarchy = false;
     if (c > 0) {
       DBS_LAUNCH(h, KC_MISC, k_corr_record, h->cgrid, blk, h->seg, (const double *)h->prgh,
                  (const double *)h->p1, dc, dc1, hb, h->guess_used.r, h->partials, nb);

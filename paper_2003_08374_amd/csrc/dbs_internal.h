@@ -227,6 +227,9 @@ struct Handle {
   // block-local smoothing (Jacobi between CB^3 tiles) instead of global
   // red-black sweeps
   int coarse_block = 0;
+  // the coming solve uses the rAU of the previous one (a later corrector of
+  // the same step): the FP32 coefficients and coarse operators are kept
+  bool keep_hierarchy = false;
 
   std::vector<dbs_stats> st;  // per sample
   double tnow = 0.0;          // time reached by the samples

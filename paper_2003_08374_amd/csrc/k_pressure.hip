@@ -3414,16 +3414,15 @@ static int pcg(Handle *h, const double *rAU, const double *b, double *x, int bud
                int *iters, double *relres) {
   const bool flex = std::is_same<R, float>::value;
   const bool graph = budget > 0;
-  const R *rAUr;
   float *rf = flex ? h->rf : nullptr;
-  if (flex) {
-    float *rAUf = h->lv[0].bf;
-    DBS_LAUNCH(h, KC_MISC, k_cast<float>, flat_grid(h), dim3(FLAT_T), rAU, rAUf);
-    rAUr = (const R *)rAUf;
-  } else {
-    rAUr = (const R *)rAU;
+  // the operator's FP32 coefficients and the coarse levels' operators; a
+  // later corrector of the same step solves with the same rAU and keeps them
+  const R *rAUr = flex ? (const R *)h->lv[0].bf : (const R *)rAU;
+  if (!h->keep_hierarchy) {
+    if (flex)
+      DBS_LAUNCH(h, KC_MISC, k_cast<float>, flat_grid(h), dim3(FLAT_T), rAU, h->lv[0].bf);
+    build_hierarchy<R>(h, rAUr);
   }
-  build_hierarchy<R>(h, rAUr);
   // initial residual and norms of every sample
   set_flags(h, 1, 1);
   true_residual(h, rAU, b, x, rf, h->want);
