@@ -711,8 +711,7 @@ __device__ __forceinline__ void sample_sums(const double *__restrict__ part, int
   __shared__ double lds[NQ][16];
   const int t = threadIdx.x, s = blockIdx.x;
   for (int q = 0; q < NQ; q++) r[q] = 0.0;
-  for (int i = bp[s] + t; i < bp[s + 1]; i += 1024)
-    for (int q = 0; q < NQ; q++) r[q] += part[(size_t)q * nb + i];
+  strided_sums<NQ>(part, (size_t)nb, bp[s], bp[s + 1], r);
   for (int q = 0; q < NQ; q++) {
     const double v = wave_sum(r[q]);
     if ((t & 63) == 0) lds[q][t >> 6] = v;
@@ -1197,6 +1196,7 @@ static int graph_step(Handle *h) {
   snapshot(h, false);
   add_time(h, -h->ctl.dt);
   update_closures(h);
+  h->hist = 0;  // the replay moved the guesses' histories on: start them again
   std::vector<int> its(nc, 0);
   int sweeps = 0;
   rc = step_body(h, nullptr, 0, &its, &sweeps);

@@ -307,6 +307,28 @@ __device__ __forceinline__ double wave_min(double v) {
   return v;
 }
 
+// Thread t of a 1024-thread block adds part[q * nb + i] for i = lo + t,
+// lo + t + 1024, ... below hi into r[q], in that order, with eight loads in
+// flight (the sums equal those of the plain strided loop bit for bit).
+template <int NQ>
+__device__ __forceinline__ void strided_sums(const double *__restrict__ part, size_t nb, int lo,
+                                             int hi, double *r) {
+  for (int i = lo + (int)threadIdx.x; i < hi; i += 8 * 1024) {
+    double v[NQ][8];
+#pragma unroll
+    for (int u = 0; u < 8; u++) {
+      const int j = i + u * 1024;
+#pragma unroll
+      for (int q = 0; q < NQ; q++) v[q][u] = j < hi ? part[(size_t)q * nb + j] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; u++)
+#pragma unroll
+      for (int q = 0; q < NQ; q++)
+        if (i + u * 1024 < hi) r[q] += v[q][u];
+  }
+}
+
 // block-wide sum over NTHREADS threads (4 wavefronts); result valid in thread 0
 __device__ __forceinline__ double block_sum(double v, double *lds) {
   v = wave_sum(v);

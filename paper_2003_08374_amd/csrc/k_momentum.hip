@@ -392,11 +392,10 @@ __global__ void __launch_bounds__(1024) k_mom_final(const double *__restrict__ p
     if (t == 0) hflag[slot * ns + s] = 0;
     return;
   }
-  double vr = 0.0, vb = 0.0;
-  for (int i = bp[s] + t; i < bp[s + 1]; i += 1024) {
-    vr += part[i];
-    if (first) vb += part[nb + i];
-  }
+  double v2[2] = {0.0, 0.0};
+  if (first) strided_sums<2>(part, (size_t)nb, bp[s], bp[s + 1], v2);
+  else strided_sums<1>(part, (size_t)nb, bp[s], bp[s + 1], v2);
+  double vr = v2[0], vb = v2[1];
   vr = wave_sum(vr);
   vb = wave_sum(vb);
   if ((t & 63) == 0) {
