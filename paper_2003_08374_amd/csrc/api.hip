@@ -1045,8 +1045,8 @@ static void replay_roles(Handle *h) {
 // One step in graph mode: the step is captured once per buffer-role
 // combination with a fixed predictor sweep budget and a fixed PCG budget per
 // corrector, then replayed.  A sample that does not converge within a
-// budget makes the step run again eagerly from the saved state, and the
-// budgets grow.
+// budget makes the step run again eagerly from the state before it, and
+// the budgets grow.
 static int graph_step(Handle *h) {
   int rc = courant_check(h);
   if (rc) return rc;
@@ -1071,10 +1071,6 @@ static int graph_step(Handle *h) {
     set_budgets(its, sweeps, false);
     return DBS_OK;
   }
-  if (!h->snap) {
-    h->snap = dmalloc(h, (size_t)h->NC, rc);
-    if (rc) return fail(h, rc, "snapshot allocation");
-  }
   const Roles before = roles(h);
   // the captured steps bake in the coefficients of the first solve's guess:
   // capture again when they change (the first steps after a state reset, a
@@ -1096,7 +1092,6 @@ static int graph_step(Handle *h) {
                      "capture");
       if (rc) break;
       if (part == 0) {
-        snapshot(h, true);
         step_front(h, nullptr, 1);
       } else {
         step_back(h, nullptr, 1, nullptr, nullptr, DBS_OK);
@@ -1189,11 +1184,13 @@ static int graph_step(Handle *h) {
     }
     return rc;
   }
-  // redo eagerly from the saved state with the budgets raised
+  // redo eagerly from the state before the step with the budgets raised: the
+  // other buffers of the roles still hold it, and the first guess's history
+  // holds p_rgh^n (the first corrector's guess stored it there)
   rc = hip_check(h, hipStreamSynchronize(h->stream), "graph step");
   if (rc) return rc;
   set_roles(h, before);
-  snapshot(h, false);
+  copy_n(h, h->pprev, h->prgh, (size_t)h->NC);
   add_time(h, -h->ctl.dt);
   update_closures(h);
   h->hist = 0;  // the replay moved the guesses' histories on: start them again
