@@ -145,8 +145,9 @@ def summarize_counters(d, n, precision, cmd_trace, cmd_counters):
     """Markdown summary of a whole-step rocprofv3 measurement of the 256^3
     workload: a kernel trace (d/trace), FETCH_SIZE and WRITE_SIZE passes
     (d/fetch, d/write) and the same passes over a plain 1 GiB copy
-    (d/cfetch, d/cwrite) for the calibration.  The last step of each run
-    (from the last k_add_time dispatch to the end) is the one summarised."""
+    (d/cfetch, d/cwrite) for the calibration.  The timed call of each run
+    (its last dbs_step call, several steps) is summarised per step, the same
+    steps whose time the benchmark reports."""
     import csv
     import re
 
@@ -157,15 +158,18 @@ def summarize_counters(d, n, precision, cmd_trace, cmd_counters):
     def name(x):
         return re.sub(r"\(.*$", "", x["Kernel_Name"]).replace("void ", "").replace("dbs::", "")
 
-    def last_step(rs):
-        # from the last step start (k_add_time) to the end of that dbs_step
-        # call (k_stats_final)
+    def timed_call(rs):
+        # the last dbs_step call: from the end of the call before it (its
+        # k_stats_final) to the end of this one; k_add_time marks each step
         key = "Dispatch_Id" if "Dispatch_Id" in rs[0] else "Start_Timestamp"
         rs = sorted(rs, key=lambda x: int(x[key]))
-        idx = [i for i, x in enumerate(rs) if name(x) == "k_add_time"]
-        seg = rs[idx[-1]:] if idx else rs
-        end = [i for i, x in enumerate(seg) if name(x) == "k_stats_final"]
-        return seg[:end[0] + 1] if end else seg
+        adds = [i for i, x in enumerate(rs) if name(x) == "k_add_time"]
+        fins = [i for i, x in enumerate(rs) if name(x) == "k_stats_final"]
+        last = adds[-1]
+        end = min([i for i in fins if i > last], default=len(rs) - 1)
+        start = max([i for i in fins if i < last], default=-1) + 1
+        seg = rs[start:end + 1]
+        return seg, sum(1 for x in seg if name(x) == "k_add_time")
 
     def calib(kind):
         v = [float(x["Counter_Value"]) for x in rows(f"{d}/c{kind}/run_counter_collection.csv")
@@ -174,9 +178,9 @@ def summarize_counters(d, n, precision, cmd_trace, cmd_counters):
 
     cf, cw = calib("fetch"), calib("write")
     cells = n ** 3
-    tr = last_step(rows(f"{d}/trace/run_kernel_trace.csv"))
-    fe = last_step(rows(f"{d}/fetch/run_counter_collection.csv"))
-    wr = last_step(rows(f"{d}/write/run_counter_collection.csv"))
+    tr, steps = timed_call(rows(f"{d}/trace/run_kernel_trace.csv"))
+    fe, _ = timed_call(rows(f"{d}/fetch/run_counter_collection.csv"))
+    wr, _ = timed_call(rows(f"{d}/write/run_counter_collection.csv"))
     agg = {}
     def grid(x):  # threads in the launch (the two files name the field differently)
         if "Grid_Size" in x:
@@ -197,7 +201,12 @@ def summarize_counters(d, n, precision, cmd_trace, cmd_counters):
                 cnt[k] = cnt.get(k, 0) + 1
         for k, c in cnt.items():
             agg[k][key] /= c  # bytes per launch
+    # per step of the timed call
+    for a in agg.values():
+        a["n"] /= steps
+        a["us"] /= steps
     span = (max(int(x["End_Timestamp"]) for x in tr) - int(tr[0]["Start_Timestamp"])) * 1e-6
+    span /= steps
     busy = sum(a["us"] for a in agg.values()) * 1e-3
     step_bytes = sum((a["f"] + a["w"]) * a["n"] for a in agg.values())
     lines = [f"# One PISO step, {n}^3 fractured workload, {precision}: kernel times and HBM "
@@ -206,18 +215,19 @@ def summarize_counters(d, n, precision, cmd_trace, cmd_counters):
              "```", cmd_trace, cmd_counters, "```", "",
              f"Calibration: a plain 1 GiB device copy reads FETCH_SIZE x {cf:.4f} and "
              f"WRITE_SIZE x {cw:.4f} of the bytes it moves.", "",
-             f"Last step of the trace run: {len(tr)} launches, kernel time {busy:.3f} ms over a "
-             f"span of {span:.3f} ms (the tracer adds a few us per launch).  Counted HBM "
-             f"traffic of the step: {step_bytes / 1e9:.2f} GB = "
+             f"Per step of the timed call of the trace run ({steps} steps, the ones the "
+             f"benchmark times): {len(tr) / steps:.1f} launches, kernel time {busy:.3f} ms over "
+             f"a span of {span:.3f} ms (the tracer adds a few us per launch).  Counted HBM "
+             f"traffic per step: {step_bytes / 1e9:.2f} GB = "
              f"{step_bytes / cells:.0f} B per cell.", "",
-             "| kernel | threads | launches | avg us | ms | MB per launch | "
+             "| kernel | threads | launches per step | avg us | ms per step | MB per launch | "
              "B per cell | GB/s |", "|---|---:|---:|---:|---:|---:|---:|---:|"]
     for (k, g), a in sorted(agg.items(), key=lambda kv: -kv[1]["us"]):
         if a["us"] < 1.0:
             continue
         avg = a["us"] / a["n"]
         mb = (a["f"] + a["w"]) / 1e6
-        lines.append(f"| `{k}` | {g} | {a['n']} | {avg:.1f} | {a['us'] / 1e3:.3f} | {mb:.1f} | "
+        lines.append(f"| `{k}` | {g} | {a['n']:.1f} | {avg:.1f} | {a['us'] / 1e3:.3f} | {mb:.1f} | "
                      f"{(a['f'] + a['w']) / cells:.1f} | {(a['f'] + a['w']) / (avg * 1e-6) / 1e9:.0f} |")
     ax = [a for (k, g), a in agg.items() if k == "k_axpy_dot"]
     recs = [{"kernel": "step", "precision": precision, "n": n,
@@ -352,17 +362,17 @@ def time_solver(case, precision, steps, warmup, prof_class=None, profile_all=Fal
     if dom and not graph:
         s.set_profiling(1 << dbs.Solver.kernel_class(dom))
     s.reset_profiling()
-    its, sweeps = [], []
     stats = (lambda: s.stats(0)) if batch else s.stats
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(steps):
-        s.step(1)
-        sts = stats()
-        its.append(sts["p_iters"])
-        sweeps.append(sts["mom_sweeps"])
+    # one call for all timed steps, as a time loop makes it (the library
+    # synchronises and gathers its statistics once per call)
+    s.step(steps)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    sts = stats()
+    # the last timed step's counts
+    its, sweeps = [sts["p_iters"]], [sts["mom_sweeps"]]
     log(f"  {steps} steps in {t1 - t0:.3f} s")
     kt = s.kernel_times()
     st = stats()
@@ -563,12 +573,11 @@ def main():
         d = args.summarize_counters
         flags = ("--no-cpu --no-fp64 --no-graph --no-batch --no-flume --no-csf --no-reservoir "
                  "--kernel axpy")
-        # the 13th step from rest: the last timed step of the default run
-        # (2 warm-up steps, one profiled step, 10 timed ones)
+        # the default run's warm-up and timed steps
         t = (f"rocprofv3 --kernel-trace --stats --output-format csv -d <out>/trace -o run -- "
-             f"python3 <repo>/bench.py {flags} --steps 1 --warmup 12")
+             f"python3 <repo>/bench.py {flags} --steps 10 --warmup 12")
         c = "\n".join(f"rocprofv3 --pmc {p} --output-format csv -d <out>/{q} -o run -- python3 "
-                      f"<repo>/bench.py {flags} --steps 1 --warmup 12"
+                      f"<repo>/bench.py {flags} --steps 10 --warmup 12"
                       for p, q in (("FETCH_SIZE", "fetch"), ("WRITE_SIZE", "write"))) + "\n" + \
             "\n".join(f"rocprofv3 --pmc {p} --output-format csv -d <out>/{q} -o run -- python3 "
                       f"<repo>/bench.py --copy-calibration"
