@@ -156,8 +156,8 @@ typedef struct {
                            guess (0: p_rgh itself, 1: linear, 2: quadratic) */
   int p_guess_change[16]; /* per corrector c >= 1: the change its next guess adds to the
                            previous corrector's solution (0: none, 1: the change its solve
-                           made in the last step, 2: the last two changes extrapolated
-                           linearly in time); [0] is 0 */
+                           made in the last step, 2 and 3: the last two or three changes
+                           extrapolated linearly or quadratically in time); [0] is 0 */
 } dbs_stats;
 
 typedef struct dbs_handle dbs_handle;
@@ -185,8 +185,8 @@ int dbs_set_state(dbs_handle *h, const double *alpha, const double *U,
    predicted the last step) less the later correctors' predicted changes;
    each later corrector's starts from the previous corrector's solution plus
    its predicted change (none, the change its solve made in the previous
-   step, or the last two changes extrapolated, whichever predicted the last
-   change best).  The guesses
+   step, or the last two or three changes extrapolated, whichever predicted
+   the last change best).  The guesses
    change only the iteration counts; the first step after creation or a
    state reset starts from p_rgh itself.  Synchronises the library stream
    before returning. */

@@ -507,7 +507,7 @@ static int create_impl(int n, const dbs_grid *grids, const dbs_physics *phys, co
   h->gord = (int *)dmalloc_bytes(h, sizeof(int) * n, rc);
   if (ctl->n_corr > 1) {
     h->p1 = dmalloc(h, NC, rc);
-    h->dcorr = dmalloc(h, (size_t)2 * (ctl->n_corr - 1) * NC, rc);
+    h->dcorr = dmalloc(h, (size_t)3 * (ctl->n_corr - 1) * NC, rc);
     h->gchg = (int *)dmalloc_bytes(h, sizeof(int) * n * (ctl->n_corr - 1), rc);
   }
   h->F = dmalloc(h, NF, rc); h->F2 = dmalloc(h, NF, rc);
@@ -697,9 +697,9 @@ static int step_front(Handle *h, TraceOut *tr, int budget) {
 // have fared one step back: the extrapolation order of p_rgh (0: p_rgh^n
 // itself, 1: linear, 2: quadratic) whose prediction of p_rgh^n from the
 // steps before came closest in the L2 norm, and for each later corrector
-// the prediction of its change (0: none, 1: the previous step's change, 2:
-// the last two changes extrapolated linearly) that came closest to this
-// step's change.  (At 256^3, mixed, steps 13 to 22 from rest, the quadratic
+// the prediction of its change (0: none, 1: the previous step's change, 2
+// and 3: the last two or three changes extrapolated linearly or
+// quadratically) that came closest to this step's change.  (At 256^3, mixed, steps 13 to 22 from rest, the quadratic
 // order and the linear change win; in the wave flume p_rgh and the changes
 // alternate from step to step, so order 0 and no change win there.)
 
@@ -743,16 +743,19 @@ __device__ __forceinline__ void block_partials(const double *v, int gb, double *
     }
 }
 
-// predicted change of a later corrector's solve, kind 1 or 2, from its last
-// change d and the one before d1 (r: this step's dt over the last one's)
-__device__ __forceinline__ double predicted_change(int kind, double d, double d1, double r) {
-  return kind == 2 ? fma(r, d - d1, d) : d;
+// predicted change of a later corrector's solve, kind 1 to 3, from its last
+// three changes d, d1, d2 (A: this step's coefficients, linear r and
+// quadratic q1, q2 as for p_rgh)
+__device__ __forceinline__ double predicted_change(int kind, double d, double d1, double d2,
+                                                   const GuessArgs &A) {
+  if (kind == 3) return fma(A.q2, d - d2, fma(A.q1, d - d1, d));
+  return kind == 2 ? fma(A.r, d - d1, d) : d;
 }
 
 // The first corrector's guess in p (p_rgh^n on entry) with the sample's
 // order ord[s] (at most A.use) less the later correctors' predicted changes
-// (kind chg[s * nd + k] at most A.use; slice k of d holds the last change
-// and slice k + nd the one before); the squared errors of the backtests as
+// (kind chg[s * nd + k] at most A.usec; slices k, k + nd and k + 2 nd of d
+// hold the last three changes); the squared errors of the backtests as
 // block partials; the history shifts (pq <- pb <- pa <- p_rgh^n).
 __global__ void __launch_bounds__(NTHREADS) k_extrap(Segs SG, double *__restrict__ p,
                                                      double *__restrict__ pa,
@@ -771,10 +774,11 @@ __global__ void __launch_bounds__(NTHREADS) k_extrap(Segs SG, double *__restrict
     if (o == 1) g = fma(A.r, t - a, t);
     else if (o == 2) g = fma(A.q2, t - b, fma(A.q1, t - a, t));
     for (int k = 0; k < A.nd; k++) {
-      const int kind = min(chg[cell_sg * A.nd + k], A.use);
+      const int kind = min(chg[cell_sg * A.nd + k], A.usec);
       if (kind >= 1)
         g -= predicted_change(kind, d[(size_t)k * nc + c],
-                              kind == 2 ? d[(size_t)(k + A.nd) * nc + c] : 0.0, A.r);
+                              kind >= 2 ? d[(size_t)(k + A.nd) * nc + c] : 0.0,
+                              kind == 3 ? d[(size_t)(k + 2 * A.nd) * nc + c] : 0.0, A);
     }
     if (A.nbt >= 1) e[0] = (t - a) * (t - a);
     if (A.nbt >= 2) {
@@ -811,65 +815,71 @@ __global__ void __launch_bounds__(1024) k_extrap_final(const double *__restrict_
 }
 
 // A later corrector's guess: the previous corrector's solution (kept in
-// p1) plus the change predicted with the sample's kind (at most use) from
-// the last change d and the one before d1.
+// p1) plus the change predicted with the sample's kind (at most A.usec)
+// from its last three changes d, d1, d2.
 __global__ void __launch_bounds__(NTHREADS) k_corr_guess(Segs SG, double *__restrict__ p,
                                                          double *__restrict__ p1,
                                                          const double *__restrict__ d,
                                                          const double *__restrict__ d1,
+                                                         const double *__restrict__ d2,
                                                          const int *__restrict__ chg, int nd,
-                                                         int k, int use, double r) {
+                                                         int k, GuessArgs A) {
   FOR_CELLS(SG, G, P) {
     const size_t c = P.c;
     const double t = p[c];
     p1[c] = t;
-    const int kind = min(chg[cell_sg * nd + k], use);
-    if (kind >= 1) p[c] = t + predicted_change(kind, d[c], kind == 2 ? d1[c] : 0.0, r);
+    const int kind = min(chg[cell_sg * nd + k], A.usec);
+    if (kind >= 1)
+      p[c] = t + predicted_change(kind, d[c], kind >= 2 ? d1[c] : 0.0, kind == 3 ? d2[c] : 0.0,
+                                  A);
   }
 }
 
 // The change of this step's solve x = p - p1; as block partials the squared
-// errors of its predictions from the stored changes (none; the last change,
-// with hist >= 1 stored steps; the last two extrapolated, with hist >= 2);
-// the changes shift (d1 <- d <- x).
+// errors of its predictions from the stored changes (kind 0, none; kind k
+// >= 1 with A.usec >= k, i.e. once k steps are stored); the changes shift
+// (d2 <- d1 <- d <- x).
 __global__ void __launch_bounds__(NTHREADS) k_corr_record(Segs SG, const double *__restrict__ p,
                                                           const double *__restrict__ p1,
                                                           double *__restrict__ d,
-                                                          double *__restrict__ d1, int hist,
-                                                          double r, double *__restrict__ part,
-                                                          int nb) {
-  double e[3] = {0.0, 0.0, 0.0};
+                                                          double *__restrict__ d1,
+                                                          double *__restrict__ d2, GuessArgs A,
+                                                          double *__restrict__ part, int nb) {
+  double e[4] = {0.0, 0.0, 0.0, 0.0};
   FOR_CELLS(SG, G, P) {
     const size_t c = P.c;
     const double x = p[c] - p1[c];
     e[0] = x * x;
-    if (hist >= 1) {
-      const double dl = d[c];
-      const double y = x - dl;
-      e[1] = y * y;
-      if (hist >= 2) {
-        const double z = x - predicted_change(2, dl, d1[c], r);
-        e[2] = z * z;
+    if (A.usec >= 1) {
+      const double v0 = d[c];
+      const double v1 = A.usec >= 2 ? d1[c] : 0.0;
+      const double v2 = A.usec >= 3 ? d2[c] : 0.0;
+      for (int kind = 1; kind <= A.usec; kind++) {
+        const double y = x - predicted_change(kind, v0, v1, v2, A);
+        e[kind] = y * y;
       }
-      d1[c] = dl;
+      if (A.usec >= 2) d2[c] = v1;
+      d1[c] = v0;
     }
     d[c] = x;
   }
-  block_partials<3>(e, cell_gb, part, nb);
+  block_partials<4>(e, cell_gb, part, nb);
 }
 
 // one block per sample: the kind of the next step's change prediction, the
-// one whose backtest erred least (the last change while none can be told)
+// one whose backtest erred least among the usec + 1 told (the last change
+// while none can be told)
 __global__ void __launch_bounds__(1024) k_record_final(const double *__restrict__ part, int nb,
-                                                       const int *__restrict__ bp, int hist,
+                                                       const int *__restrict__ bp, int usec,
                                                        int *__restrict__ chg, int nd, int k) {
-  double r[3];
-  sample_sums<3>(part, nb, bp, r);
+  double r[4];
+  sample_sums<4>(part, nb, bp, r);
   if (threadIdx.x != 0) return;
   int o = 1;
-  if (hist >= 1) {
-    o = r[1] < r[0] ? 1 : 0;
-    if (hist >= 2 && r[2] < r[o]) o = 2;
+  if (usec >= 1) {
+    o = 0;
+    for (int q = 1; q <= usec && q < 4; q++)
+      if (r[q] < r[o]) o = q;
   }
   chg[blockIdx.x * nd + k] = o;
 }
@@ -886,6 +896,7 @@ static GuessArgs guess_args(const Handle *h) {
   GuessArgs A{};
   const double tau = h->ctl.dt, h1 = h->dt_prev, h2 = h->dt_prev2, h3 = h->dt_prev3;
   A.use = std::min(h->hist, 2);
+  A.usec = std::min(h->hist, 3);
   A.nbt = std::min(h->hist, 3);
   A.nd = h->hist >= 1 ? h->ctl.n_corr - 1 : 0;
   if (A.use >= 1) A.r = tau / h1;
@@ -897,7 +908,7 @@ static GuessArgs guess_args(const Handle *h) {
 
 static bool same_args(const GuessArgs &x, const GuessArgs &y) {
   return x.r == y.r && x.q1 == y.q1 && x.q2 == y.q2 && x.b1 == y.b1 && x.c1 == y.c1 &&
-         x.c2 == y.c2 && x.use == y.use && x.nbt == y.nbt && x.nd == y.nd;
+         x.c2 == y.c2 && x.use == y.use && x.usec == y.usec && x.nbt == y.nbt && x.nd == y.nd;
 }
 
 static void extrapolate_guess(Handle *h) {
@@ -919,7 +930,6 @@ static void extrapolate_guess(Handle *h) {
 static int step_back(Handle *h, TraceOut *tr, int budget, std::vector<int> *its_out,
                      int *sweeps_out, int rc) {
   int solve_rc = DBS_OK;
-  const int hb = h->hist;  // steps stored before this one (changes recorded: hb >= 1)
   const size_t NCs = (size_t)h->NC;
   const int nd = h->ctl.n_corr - 1, nb = h->cell.nblk;
   const dim3 blk(BX, BY);
@@ -935,22 +945,23 @@ static int step_back(Handle *h, TraceOut *tr, int budget, std::vector<int> *its_
     // this corrector's last change and the one before
     double *dc = c > 0 ? h->dcorr + (size_t)(c - 1) * NCs : nullptr;
     double *dc1 = c > 0 ? h->dcorr + (size_t)(c - 1 + nd) * NCs : nullptr;
+    double *dc2 = c > 0 ? h->dcorr + (size_t)(c - 1 + 2 * nd) * NCs : nullptr;
     if (c == 0)
       extrapolate_guess(h);  // sets guess_used, this step's coefficients
     else
       DBS_LAUNCH(h, KC_MISC, k_corr_guess, h->cgrid, blk, h->seg, h->prgh, h->p1,
-                 (const double *)dc, (const double *)dc1, (const int *)h->gchg, nd, c - 1,
-                 std::min(hb, 2), h->guess_used.r);
+                 (const double *)dc, (const double *)dc1, (const double *)dc2,
+                 (const int *)h->gchg, nd, c - 1, h->guess_used);
     const int b = budget > 0 ? h->graph_budget[c] : 0;
     h->keep_hierarchy = c > 0;  // rAU is the predictor's for every corrector
     const int src = pressure_solve(h, h->rAU, h->rhs, h->prgh, b, its.data(), rel.data());
     h->keep_hierarchy = false;
     if (c > 0) {
       DBS_LAUNCH(h, KC_MISC, k_corr_record, h->cgrid, blk, h->seg, (const double *)h->prgh,
-                 (const double *)h->p1, dc, dc1, hb, h->guess_used.r, h->partials, nb);
+                 (const double *)h->p1, dc, dc1, dc2, h->guess_used, h->partials, nb);
       DBS_LAUNCH(h, KC_MISC, k_record_final, dim3(h->ns), dim3(1024),
-                 (const double *)h->partials, nb, (const int *)h->cell.bp, hb, h->gchg, nd,
-                 c - 1);
+                 (const double *)h->partials, nb, (const int *)h->cell.bp, h->guess_used.usec,
+                 h->gchg, nd, c - 1);
     }
     if (budget > 0) {
       pressure_record(h, h->rec, c);
@@ -1214,12 +1225,12 @@ static int guess_stats(Handle *h) {
                                     hipMemcpyDeviceToHost, h->stream), "guess state");
   if (!e) e = hip_check(h, hipStreamSynchronize(h->stream), "guess state");
   if (e) return e;
-  const int use = std::min(h->hist, 2);
+  const int use = std::min(h->hist, 2), usec = std::min(h->hist, 3);
   for (int s = 0; s < ns; s++) {
     h->st[s].p_guess_order = std::min(go[s], use);
     h->st[s].p_guess_change[0] = 0;
     for (int k = 0; k < nd && k < 15; k++)
-      h->st[s].p_guess_change[k + 1] = std::min(gc[(size_t)s * nd + k], use);
+      h->st[s].p_guess_change[k + 1] = std::min(gc[(size_t)s * nd + k], usec);
   }
   return DBS_OK;
 }

@@ -118,6 +118,7 @@ struct GraphKey {
 struct GuessArgs {
   double r, q1, q2, b1, c1, c2;
   int use;  // highest order the stored steps allow (0 to 2)
+  int usec; // highest kind of change prediction they allow (0 to 3)
   int nbt;  // orders whose backtest the stored steps allow (0 to 3)
   int nd;   // later correctors' changes recorded (0 or n_corr - 1)
 };
@@ -155,19 +156,21 @@ struct Handle {
   // time steps dt_prev, dt_prev2 and dt_prev3.
   double *pprev = nullptr, *pprev2 = nullptr, *pprev3 = nullptr;
   // the solution of the corrector before (p1) and, per later corrector, the
-  // changes its solve made in the previous two steps (dcorr: n_corr - 1
-  // slices of the last changes, then n_corr - 1 of the ones before, NC each)
+  // changes its solve made in the previous three steps (dcorr: n_corr - 1
+  // slices of the last changes, then of the ones before, then of the ones
+  // before those, NC each)
   double *p1 = nullptr, *dcorr = nullptr;
   // per sample: the extrapolation order of the next first guess (gord) and,
   // per later corrector, the kind of its change prediction (gchg, ns x
-  // (n_corr - 1): 0 none, 1 the last change, 2 linear in the last two); set
+  // (n_corr - 1): 0 none, 1 the last change, 2 linear in the last two, 3
+  // quadratic in the last three); set
   // on the device after every step
   int *gord = nullptr, *gchg = nullptr;
   int hist = 0;
   double dt_prev = 0.0, dt_prev2 = 0.0, dt_prev3 = 0.0;
   // the first guess's coefficients as the last step used them and as the
   // captured steps use them
-  GuessArgs guess_used{}, graph_guess{0, 0, 0, 0, 0, 0, -1, -1, -1};
+  GuessArgs guess_used{}, graph_guess{0, 0, 0, 0, 0, 0, -1, -1, -1, -1};
   double *F = nullptr;                 // faces
   double *F2 = nullptr;                // the correctors' fluxes (swapped with F per step)
   // closures of the current alpha: k_rl/mu_l, k_rg/mu_g, p_c (0 in clear cells)
