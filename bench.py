@@ -39,14 +39,14 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, AMD public figure
 # the x/r update, the V-cycle (fine level with fused red-black sweeps, 8/7
 # for the coarse levels) and the direction update: 216 B in FP64, about 160 B
 # with the V-cycle in FP32.  The pressure initial guesses: the first
-# corrector's extrapolation in time (p_rgh and its three previous values
+# corrector's extrapolation in time (p_rgh and its four previous values
 # read and written, and per later corrector its three stored changes read),
 # each later corrector's guess (p_rgh and the three stored changes read,
 # p_rgh and its copy written) and the record of its change (p_rgh, the copy
 # and the three stored changes read, the three changes written).
 STEP_BYTES = {"alpha_face": 96, "alpha_limit_update": 112, "mom_assemble": 144,
               "jacobi_sweep": 144, "p_assembly": 184, "correct": 128,
-              "guess_first": 64, "guess_later": 136,
+              "guess_first": 80, "guess_later": 136,
               "pcg_iteration": {"fp64": 216, "mixed": 160}}
 
 

@@ -153,7 +153,7 @@ typedef struct {
                            discrete divergence; at most p_tol p_bnorm[n_corr - 1] when the
                            last solve converged) */
   int p_guess_order;    /* time-extrapolation order of the next step's first pressure
-                           guess (0: p_rgh itself, 1: linear, 2: quadratic) */
+                           guess (0: p_rgh itself, 1: linear, 2: quadratic, 3: cubic) */
   int p_guess_change[16]; /* per corrector c >= 1: the change its next guess adds to the
                            previous corrector's solution (0: none, 1: the change its solve
                            made in the last step, 2 and 3: the last two or three changes
@@ -181,7 +181,7 @@ int dbs_set_state(dbs_handle *h, const double *alpha, const double *U,
 
 /* Advance nsteps time steps (Sec. 3.2 sequence).  The first corrector's
    pressure solve starts from p_rgh extrapolated in time from the ends of
-   the previous steps (per sample, the order among 0, 1 and 2 that best
+   the previous steps (per sample, the order from 0 to 3 that best
    predicted the last step) less the later correctors' predicted changes;
    each later corrector's starts from the previous corrector's solution plus
    its predicted change (none, the change its solve made in the previous

@@ -504,6 +504,7 @@ static int create_impl(int n, const dbs_grid *grids, const dbs_physics *phys, co
   h->U = dmalloc(h, 3 * NC, rc); h->U2 = dmalloc(h, 3 * NC, rc); h->U3 = dmalloc(h, 3 * NC, rc);
   h->prgh = dmalloc(h, NC, rc); h->p = dmalloc(h, NC, rc);
   h->pprev = dmalloc(h, NC, rc); h->pprev2 = dmalloc(h, NC, rc); h->pprev3 = dmalloc(h, NC, rc);
+  h->pprev4 = dmalloc(h, NC, rc);
   h->gord = (int *)dmalloc_bytes(h, sizeof(int) * n, rc);
   if (ctl->n_corr > 1) {
     h->p1 = dmalloc(h, NC, rc);
@@ -695,7 +696,7 @@ static int step_front(Handle *h, TraceOut *tr, int budget) {
 // corrector's solve starts from the previous corrector's solution plus its
 // predicted change.  Every prediction is chosen per sample from how it would
 // have fared one step back: the extrapolation order of p_rgh (0: p_rgh^n
-// itself, 1: linear, 2: quadratic) whose prediction of p_rgh^n from the
+// itself, 1 to 3: linear to cubic) whose prediction of p_rgh^n from the
 // steps before came closest in the L2 norm, and for each later corrector
 // the prediction of its change (0: none, 1: the previous step's change, 2
 // and 3: the last two or three changes extrapolated linearly or
@@ -756,23 +757,25 @@ __device__ __forceinline__ double predicted_change(int kind, double d, double d1
 // order ord[s] (at most A.use) less the later correctors' predicted changes
 // (kind chg[s * nd + k] at most A.usec; slices k, k + nd and k + 2 nd of d
 // hold the last three changes); the squared errors of the backtests as
-// block partials; the history shifts (pq <- pb <- pa <- p_rgh^n).
+// block partials; the history shifts (pr <- pq <- pb <- pa <- p_rgh^n).
 __global__ void __launch_bounds__(NTHREADS) k_extrap(Segs SG, double *__restrict__ p,
                                                      double *__restrict__ pa,
                                                      double *__restrict__ pb,
                                                      double *__restrict__ pq,
+                                                     double *__restrict__ pr,
                                                      const double *__restrict__ d, size_t nc,
                                                      const int *__restrict__ ord,
                                                      const int *__restrict__ chg, GuessArgs A,
                                                      double *__restrict__ part, int nb) {
-  double e[3] = {0.0, 0.0, 0.0};
+  double e[4] = {0.0, 0.0, 0.0, 0.0};
   FOR_CELLS(SG, G, P) {
     const size_t c = P.c;
-    const double t = p[c], a = pa[c], b = pb[c];
+    const double t = p[c], a = pa[c], b = pb[c], q = pq[c];
     const int o = min(ord[cell_sg], A.use);
     double g = t;
     if (o == 1) g = fma(A.r, t - a, t);
     else if (o == 2) g = fma(A.q2, t - b, fma(A.q1, t - a, t));
+    else if (o == 3) g = fma(A.k3, t - q, fma(A.k2, t - b, fma(A.k1, t - a, t)));
     for (int k = 0; k < A.nd; k++) {
       const int kind = min(chg[cell_sg * A.nd + k], A.usec);
       if (kind >= 1)
@@ -786,15 +789,20 @@ __global__ void __launch_bounds__(NTHREADS) k_extrap(Segs SG, double *__restrict
       e[1] = x * x;
     }
     if (A.nbt >= 3) {
-      const double x = t - fma(A.c2, a - pq[c], fma(A.c1, a - b, a));
+      const double x = t - fma(A.c2, a - q, fma(A.c1, a - b, a));
       e[2] = x * x;
     }
+    if (A.nbt >= 4) {
+      const double x = t - fma(A.m3, a - pr[c], fma(A.m2, a - q, fma(A.m1, a - b, a)));
+      e[3] = x * x;
+    }
     p[c] = g;
+    pr[c] = q;
     pq[c] = b;
     pb[c] = a;
     pa[c] = t;
   }
-  block_partials<3>(e, cell_gb, part, nb);
+  block_partials<4>(e, cell_gb, part, nb);
 }
 
 // one block per sample: the order of the next step's guess, the one whose
@@ -802,13 +810,13 @@ __global__ void __launch_bounds__(NTHREADS) k_extrap(Segs SG, double *__restrict
 __global__ void __launch_bounds__(1024) k_extrap_final(const double *__restrict__ part, int nb,
                                                        const int *__restrict__ bp, int nbt,
                                                        int *__restrict__ ord) {
-  double r[3];
-  sample_sums<3>(part, nb, bp, r);
+  double r[4];
+  sample_sums<4>(part, nb, bp, r);
   if (threadIdx.x != 0) return;
   int o = 1;
   if (nbt >= 2) {
     o = 0;
-    for (int k = 1; k < nbt && k < 3; k++)
+    for (int k = 1; k < nbt && k < 4; k++)
       if (r[k] < r[o]) o = k;
   }
   ord[blockIdx.x] = o;
@@ -884,43 +892,58 @@ __global__ void __launch_bounds__(1024) k_record_final(const double *__restrict_
   chg[blockIdx.x * nd + k] = o;
 }
 
-// Lagrange extrapolation to offset tau past node 0 from nodes 0, -h1 and
-// -(h1 + h2), in difference form: x0 + c1 (x0 - x1) + c2 (x0 - x2)
-static void quad_coef(double tau, double h1, double h2, double *c1, double *c2) {
-  *c1 = tau * (tau + h1 + h2) / (h1 * h2);
-  *c2 = -tau * (tau + h1) / ((h1 + h2) * h2);
+// Lagrange extrapolation to offset tau past node 0 from nodes 0, -h[0],
+// -(h[0] + h[1]), ... (m nodes before node 0), in the difference form
+// x0 + sum_k c[k - 1] (x0 - x_k): c[k - 1] = -w_k, with w_k the Lagrange
+// weight of node k (the weights sum to 1).
+static void lag_coef(double tau, const double *h, int m, double *c) {
+  double x[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int k = 1; k <= m; k++) x[k] = x[k - 1] - h[k - 1];
+  for (int k = 1; k <= m; k++) {
+    double w = 1.0;
+    for (int j = 0; j <= m; j++)
+      if (j != k) w *= (tau - x[j]) / (x[k] - x[j]);
+    c[k - 1] = -w;
+  }
 }
 
 // the coming step's GuessArgs from the stored steps and their time steps
 static GuessArgs guess_args(const Handle *h) {
   GuessArgs A{};
-  const double tau = h->ctl.dt, h1 = h->dt_prev, h2 = h->dt_prev2, h3 = h->dt_prev3;
-  A.use = std::min(h->hist, 2);
+  const double tau = h->ctl.dt;
+  const double hs[4] = {h->dt_prev, h->dt_prev2, h->dt_prev3, h->dt_prev4};
+  A.use = std::min(h->hist, 3);
   A.usec = std::min(h->hist, 3);
-  A.nbt = std::min(h->hist, 3);
+  A.nbt = std::min(h->hist, 4);
   A.nd = h->hist >= 1 ? h->ctl.n_corr - 1 : 0;
-  if (A.use >= 1) A.r = tau / h1;
-  if (A.use >= 2) quad_coef(tau, h1, h2, &A.q1, &A.q2);
-  if (A.nbt >= 2) A.b1 = h1 / h2;
-  if (A.nbt >= 3) quad_coef(h1, h2, h3, &A.c1, &A.c2);
+  double c[3];
+  if (A.use >= 1) { lag_coef(tau, hs, 1, c); A.r = c[0]; }
+  if (A.use >= 2) { lag_coef(tau, hs, 2, c); A.q1 = c[0]; A.q2 = c[1]; }
+  if (A.use >= 3) { lag_coef(tau, hs, 3, c); A.k1 = c[0]; A.k2 = c[1]; A.k3 = c[2]; }
+  if (A.nbt >= 2) { lag_coef(hs[0], hs + 1, 1, c); A.b1 = c[0]; }
+  if (A.nbt >= 3) { lag_coef(hs[0], hs + 1, 2, c); A.c1 = c[0]; A.c2 = c[1]; }
+  if (A.nbt >= 4) { lag_coef(hs[0], hs + 1, 3, c); A.m1 = c[0]; A.m2 = c[1]; A.m3 = c[2]; }
   return A;
 }
 
 static bool same_args(const GuessArgs &x, const GuessArgs &y) {
   return x.r == y.r && x.q1 == y.q1 && x.q2 == y.q2 && x.b1 == y.b1 && x.c1 == y.c1 &&
-         x.c2 == y.c2 && x.use == y.use && x.usec == y.usec && x.nbt == y.nbt && x.nd == y.nd;
+         x.c2 == y.c2 && x.k1 == y.k1 && x.k2 == y.k2 && x.k3 == y.k3 && x.m1 == y.m1 &&
+         x.m2 == y.m2 && x.m3 == y.m3 && x.use == y.use && x.usec == y.usec &&
+         x.nbt == y.nbt && x.nd == y.nd;
 }
 
 static void extrapolate_guess(Handle *h) {
   const GuessArgs A = guess_args(h);
   const int nb = h->cell.nblk;
   DBS_LAUNCH(h, KC_MISC, k_extrap, h->cgrid, dim3(BX, BY), h->seg, h->prgh, h->pprev,
-             h->pprev2, h->pprev3, (const double *)h->dcorr, (size_t)h->NC,
+             h->pprev2, h->pprev3, h->pprev4, (const double *)h->dcorr, (size_t)h->NC,
              (const int *)h->gord, (const int *)h->gchg, A, h->partials, nb);
   DBS_LAUNCH(h, KC_MISC, k_extrap_final, dim3(h->ns), dim3(1024), (const double *)h->partials,
              nb, (const int *)h->cell.bp, A.nbt, h->gord);
   h->guess_used = A;
-  h->hist = std::min(h->hist + 1, 3);
+  h->hist = std::min(h->hist + 1, 4);
+  h->dt_prev4 = h->dt_prev3;
   h->dt_prev3 = h->dt_prev2;
   h->dt_prev2 = h->dt_prev;
   h->dt_prev = h->ctl.dt;
@@ -1225,7 +1248,7 @@ static int guess_stats(Handle *h) {
                                     hipMemcpyDeviceToHost, h->stream), "guess state");
   if (!e) e = hip_check(h, hipStreamSynchronize(h->stream), "guess state");
   if (e) return e;
-  const int use = std::min(h->hist, 2), usec = std::min(h->hist, 3);
+  const int use = std::min(h->hist, 3), usec = std::min(h->hist, 3);
   for (int s = 0; s < ns; s++) {
     h->st[s].p_guess_order = std::min(go[s], use);
     h->st[s].p_guess_change[0] = 0;

@@ -110,16 +110,17 @@ struct GraphKey {
   }
 };
 
-// Coefficients of the first corrector's initial guess (k_extrap): the
-// guess is t + r (t - a) (order 1) or t + q1 (t - a) + q2 (t - b) (order 2),
-// where t, a, b are p_rgh at the ends of this step and the two before; the
-// backtests predict t from a, b and the step before those (q) in the same
-// forms with coefficients b1 and c1, c2.
+// Coefficients of the first corrector's initial guess (k_extrap), in the
+// difference form t + sum_k c_k (t - x_k) of Lagrange extrapolation in time
+// from p_rgh at the ends of this step (t) and the steps before (x_1 = a,
+// x_2 = b, x_3 = q): order 1 r; order 2 q1, q2; order 3 k1, k2, k3.  The
+// backtests predict t from a and the steps before in the same forms: b1;
+// c1, c2; m1, m2, m3.
 struct GuessArgs {
-  double r, q1, q2, b1, c1, c2;
-  int use;  // highest order the stored steps allow (0 to 2)
+  double r, q1, q2, b1, c1, c2, k1, k2, k3, m1, m2, m3;
+  int use;  // highest order the stored steps allow (0 to 3)
   int usec; // highest kind of change prediction they allow (0 to 3)
-  int nbt;  // orders whose backtest the stored steps allow (0 to 3)
+  int nbt;  // orders whose backtest the stored steps allow (0 to 4)
   int nd;   // later correctors' changes recorded (0 or n_corr - 1)
 };
 
@@ -150,11 +151,11 @@ struct Handle {
   // step leaves U^n in U3).  3 x NC each
   double *U = nullptr, *U2 = nullptr, *U3 = nullptr;
   double *prgh = nullptr, *p = nullptr;
-  // p_rgh at the ends of the previous three steps (pprev, pprev2, pprev3),
+  // p_rgh at the ends of the previous four steps (pprev .. pprev4),
   // for the extrapolated initial guess of the first corrector's solve; hist
-  // of them are valid (0 to 3: steps run since the state was last set), with
-  // time steps dt_prev, dt_prev2 and dt_prev3.
-  double *pprev = nullptr, *pprev2 = nullptr, *pprev3 = nullptr;
+  // of them are valid (0 to 4: steps run since the state was last set), with
+  // time steps dt_prev .. dt_prev4.
+  double *pprev = nullptr, *pprev2 = nullptr, *pprev3 = nullptr, *pprev4 = nullptr;
   // the solution of the corrector before (p1) and, per later corrector, the
   // changes its solve made in the previous three steps (dcorr: n_corr - 1
   // slices of the last changes, then of the ones before, then of the ones
@@ -167,10 +168,10 @@ struct Handle {
   // on the device after every step
   int *gord = nullptr, *gchg = nullptr;
   int hist = 0;
-  double dt_prev = 0.0, dt_prev2 = 0.0, dt_prev3 = 0.0;
+  double dt_prev = 0.0, dt_prev2 = 0.0, dt_prev3 = 0.0, dt_prev4 = 0.0;
   // the first guess's coefficients as the last step used them and as the
   // captured steps use them
-  GuessArgs guess_used{}, graph_guess{0, 0, 0, 0, 0, 0, -1, -1, -1, -1};
+  GuessArgs guess_used{}, graph_guess{0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, -1, -1, -1, -1};
   double *F = nullptr;                 // faces
   double *F2 = nullptr;                // the correctors' fluxes (swapped with F per step)
   // closures of the current alpha: k_rl/mu_l, k_rg/mu_g, p_c (0 in clear cells)

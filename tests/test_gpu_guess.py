@@ -2,8 +2,8 @@
 dbs_stats): a guess changes only the iteration counts, never the solution,
 so these tests pin the choice itself on workloads where it is clear-cut.
 
-The first corrector's guess extrapolates p_rgh in time with the order (0, 1
-or 2) whose prediction of the last step's p_rgh from the steps before erred
+The first corrector's guess extrapolates p_rgh in time with the order (0 to
+3) whose prediction of the last step's p_rgh from the steps before erred
 least; a later corrector adds the change of its solve
 predicted with the kind (none, its last change, its last two or three
 changes extrapolated linearly or quadratically) that best predicted its last
@@ -40,11 +40,11 @@ def _flume():
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_smooth_flow_takes_quadratic_and_change(precision):
+def test_smooth_flow_takes_cubic_and_quadratic_change(precision):
     """Flow through the fractured block, smooth in time once the start-up
-    transient has passed: quadratic extrapolation of p_rgh and of the second
-    corrector's change win by step 10 (order 0 during the first steps, when
-    p_rgh jumps away from its initial field)."""
+    transient has passed: cubic extrapolation of p_rgh and quadratic
+    extrapolation of the second corrector's change win by step 10 (order 0
+    during the first steps, when p_rgh jumps away from its initial field)."""
     from paper_2003_08374_amd import dbs
     with dbs.Solver(_fractured(), precision=precision) as s:
         s.step(1)
@@ -53,7 +53,7 @@ def test_smooth_flow_takes_quadratic_and_change(precision):
         assert (st["p_guess_order"], st["p_guess_change"]) == (1, [0, 1])
         s.step(9)
         st = s.stats()
-        assert (st["p_guess_order"], st["p_guess_change"]) == (2, [0, 3])
+        assert (st["p_guess_order"], st["p_guess_change"]) == (3, [0, 3])
 
 
 def test_alternating_flume_takes_p_rgh_itself():
@@ -74,7 +74,7 @@ def test_reset_restarts_history():
     from paper_2003_08374_amd import dbs
     with dbs.Solver(_fractured(), precision="mixed") as s:
         s.step(10)
-        assert s.stats()["p_guess_order"] == 2
+        assert s.stats()["p_guess_order"] == 3
         s.set_state(s.state())
         s.step(1)
         assert s.stats()["p_guess_order"] == 1
