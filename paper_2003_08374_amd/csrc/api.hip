@@ -1199,7 +1199,7 @@ static int graph_step(Handle *h) {
   if (ok) {
     for (int s = 0; s < ns; s++) h->st[s].steps++;
     // Budgets only grow on a redo; when every corrector has kept a slack of
-    // two or more iterations for four replays in a row, they shrink to the
+    // two or more iterations for two replays in a row, they shrink to the
     // largest count of those replays plus one (and the step is captured
     // again), so masked iterations do not accumulate as the solves speed up.
     bool slack = true;
@@ -1210,7 +1210,7 @@ static int graph_step(Handle *h) {
       slack = slack && h->graph_budget[c] - used >= 2;
     }
     h->slack_steps = slack ? h->slack_steps + 1 : 0;
-    if (h->slack_steps >= 4) {
+    if (h->slack_steps >= 2) {
       for (int c = 0; c < nc; c++) h->graph_budget[c] = h->used_max[c] + 1;
       h->slack_steps = 0;
       rc = hip_check(h, hipStreamSynchronize(h->stream), "graph step");
